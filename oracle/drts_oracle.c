@@ -1,0 +1,664 @@
+/*
+ * FP64 CPU oracle for the Dynamic Radiative Transfer System (DRTS).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark load this file's library.  The product
+ * library never includes, links or calls it, and it shares no code with it.
+ *
+ * What it computes (plain definitions, written out slowly):
+ *   - the system matrix A of Eq. (21)/(23): every state (voxel X_i, direction
+ *     S_n) sends, in one step dt, the fraction a_{jm,in} of its photons to the
+ *     state (X_j, S_m).  Single-scatter split of Eq. (9)-(10), scattering
+ *     kernel g(S_n,S_m) of Eq. (19), forward scatter added on the diagonal of
+ *     the direction block as in Eq. (21).  Space is a cubic voxel lattice and
+ *     directions are the 26 lattice neighbours (Sec. 3 allows any partition);
+ *     both the ballistic and the scattered population arrive at the
+ *     neighbour voxel one lattice vector away, i.e. the arrival segment AB of
+ *     Sec. 2 is collapsed to its end A.
+ *   - escape rows L: photons leaving through a vacuum face are collected in
+ *     extra rows (one per (voxel, direction) pair that leaves the grid), so
+ *     the rectangular [A; L] has columns summing to exp(-mu_a c dt)
+ *     (column-stochastic A_S of Eq. (24)).
+ *   - interfaces between media of different refractive index (Sec. 4.2):
+ *     the unpolarised Fresnel reflectance R splits the crossing population
+ *     into a reflected part that stays in the voxel with the lattice
+ *     direction closest to the specular direction, and a transmitted part
+ *     that enters the next voxel with the lattice direction closest to the
+ *     Snell direction.
+ *   - the evolution J(t+dt) = A J(t) + B P(t) of Eq. (26) and the detector
+ *     sums M(t) of Eq. (27) with a one-step window, in FP64, with a tracked
+ *     power-of-two exponent so that long runs never underflow (scaling by a
+ *     power of two is exact, so the values are the unscaled ones).
+ *
+ * Summation orders are fixed and sequential: a matrix entry that receives
+ * several contributions from one column sums them in ascending order of the
+ * collision direction m; an SpMV row sums its entries in ascending column
+ * order.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NDIR 26
+
+/* ---- lattice directions ------------------------------------------------ */
+
+/* Direction d -> lattice vector.  k = 9(dz+1) + 3(dy+1) + (dx+1) runs over
+ * the 27 offsets of the 3x3x3 block; k = 13 (the zero vector) is skipped. */
+static void or_dir_vec(int d, int e[3])
+{
+    int k = d < 13 ? d : d + 1;
+    e[0] = k % 3 - 1;
+    e[1] = (k / 3) % 3 - 1;
+    e[2] = k / 9 - 1;
+}
+
+static int or_dir_index(int dx, int dy, int dz)
+{
+    int k = 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1);
+    return k < 13 ? k : k - 1;
+}
+
+/* unit vector of direction d: each component of e_d divided by |e_d| */
+static void or_dir_unit(int d, double s[3])
+{
+    int e[3];
+    or_dir_vec(d, e);
+    double len = sqrt((double)(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]));
+    s[0] = (double)e[0] / len;
+    s[1] = (double)e[1] / len;
+    s[2] = (double)e[2] / len;
+}
+
+static double or_dot3(const double a[3], const double b[3])
+{
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+/* ---- coefficients of one material --------------------------------------- */
+
+/* Henyey-Greenstein phase value for cosine cs (the constant 1/(4 pi) cancels
+ * in the normalisation below). */
+static double or_hg(double g, double cs)
+{
+    double q = 1.0 + g * g - 2.0 * g * cs;
+    return (1.0 - g * g) / (q * sqrt(q));
+}
+
+/*
+ * Direction block C[m][n] of one material: the fraction of the population of
+ * direction n in a voxel that leaves it in direction m during one step.
+ *   P0 = exp(-mu_s h)        unscattered, Eq. (9) without absorption
+ *   Ps = 1 - P0              scattered once, Eq. (7)
+ *   alpha = exp(-mu_a h)     survival against absorption, Eq. (8)
+ *   G[m][n] = p(cos_mn) / sum_k p(cos_kn)     discrete g(S_n, S_m)
+ *   C[m][n] = alpha (Ps G[m][n])              m != n      (w1 of Eq. (19))
+ *   C[n][n] = alpha (P0 + Ps G[n][n])                     (w0 + w1, Eq. (21))
+ * Here h = c dt is the voxel edge.
+ */
+void or_collision_block(double mu_s, double mu_a, double g, double h,
+                        double *C /* [26*26], row m, column n */)
+{
+    double P0 = exp(-mu_s * h);
+    double Ps = 1.0 - P0;
+    double alpha = exp(-mu_a * h);
+    double p[NDIR][NDIR];
+    for (int m = 0; m < NDIR; ++m) {
+        int em[3];
+        or_dir_vec(m, em);
+        for (int n = 0; n < NDIR; ++n) {
+            int en[3];
+            or_dir_vec(n, en);
+            int dot = em[0] * en[0] + em[1] * en[1] + em[2] * en[2];
+            int nm = em[0] * em[0] + em[1] * em[1] + em[2] * em[2];
+            int nn = en[0] * en[0] + en[1] * en[1] + en[2] * en[2];
+            double cs = (double)dot / sqrt((double)(nm * nn));
+            p[m][n] = or_hg(g, cs);
+        }
+    }
+    for (int n = 0; n < NDIR; ++n) {
+        double Z = 0.0;
+        for (int k = 0; k < NDIR; ++k)
+            Z += p[k][n];
+        for (int m = 0; m < NDIR; ++m) {
+            double G = p[m][n] / Z;
+            C[m * NDIR + n] = (m != n) ? alpha * (Ps * G) : alpha * (P0 + Ps * G);
+        }
+    }
+}
+
+/* ---- interfaces ---------------------------------------------------------- */
+
+/* argmax of s_d . target over directions d whose side test (s_d . N) has the
+ * requested sign; a later direction must beat the best by more than 1e-12 */
+static int or_snap(const double target[3], const double N[3], int side)
+{
+    int best_d = -1;
+    double best = -INFINITY;
+    for (int d = 0; d < NDIR; ++d) {
+        double s[3];
+        or_dir_unit(d, s);
+        double sn = or_dot3(s, N);
+        if ((side < 0 && sn < 0.0) || (side > 0 && sn > 0.0)) {
+            double v = or_dot3(s, target);
+            if (best_d < 0 || v > best + 1e-12) {
+                best = v;
+                best_d = d;
+            }
+        }
+    }
+    return best_d;
+}
+
+/*
+ * Fresnel split of a population with lattice direction m crossing from index
+ * n1 into index n2 through a surface with unit normal N (oriented so that
+ * s_m . N > 0).  Outputs the reflectance R (1 on total internal reflection),
+ * T = 1 - R, and the snapped reflected / transmitted directions.
+ */
+void or_fresnel(int m, double n1, double n2, const double N[3],
+                double *R_out, double *T_out, int *mr_out, int *mt_out)
+{
+    double s[3];
+    or_dir_unit(m, s);
+    double cos_i = or_dot3(s, N);
+    double eta = n1 / n2;
+    double sin2t = eta * eta * (1.0 - cos_i * cos_i);
+    double R, T, cos_t;
+    if (sin2t >= 1.0) {
+        R = 1.0;
+        T = 0.0;
+        cos_t = 0.0;
+    } else {
+        cos_t = sqrt(1.0 - sin2t);
+        double rs = (n1 * cos_i - n2 * cos_t) / (n1 * cos_i + n2 * cos_t);
+        double rp = (n2 * cos_i - n1 * cos_t) / (n2 * cos_i + n1 * cos_t);
+        R = 0.5 * (rs * rs + rp * rp);
+        T = 1.0 - R;
+    }
+    double r[3], t[3];
+    for (int i = 0; i < 3; ++i) {
+        r[i] = s[i] - (2.0 * cos_i) * N[i];
+        t[i] = eta * s[i] + (cos_t - eta * cos_i) * N[i];
+    }
+    *R_out = R;
+    *T_out = T;
+    *mr_out = or_snap(r, N, -1);
+    *mt_out = (T > 0.0) ? or_snap(t, N, +1) : -1;
+}
+
+/* ---- medium ---------------------------------------------------------------- */
+
+enum { OR_GEOM_VOXELS = 0, OR_GEOM_LAYERS_Z = 1, OR_GEOM_SPHERE = 2 };
+enum { OR_BC_VACUUM = 0, OR_BC_REFLECT = 1 };
+
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t n_mat;
+    double h_mm;
+    const double *mat;           /* [n_mat][4] = mu_s (1/mm), mu_a (1/mm), g, n */
+    const uint8_t *mat_of_voxel; /* [nx*ny*nz], voxel v = x + nx (y + ny z) */
+    int32_t geom;                /* normal rule at interfaces */
+    int32_t bc;                  /* outer faces */
+    double sphere_c[3];          /* voxel units; voxel centres at index + 0.5 */
+    double sphere_r;
+} or_medium_t;
+
+/* unit normal at the crossing of voxel (x,y,z) along lattice vector e,
+ * oriented so that it points from the first voxel to the second */
+static void or_normal(const or_medium_t *M, int x, int y, int z, const int e[3],
+                      const double s[3], double N[3])
+{
+    if (M->geom == OR_GEOM_LAYERS_Z && e[2] != 0) {
+        N[0] = 0.0;
+        N[1] = 0.0;
+        N[2] = e[2] > 0 ? 1.0 : -1.0;
+        return;
+    }
+    if (M->geom == OR_GEOM_SPHERE) {
+        double P[3] = {(double)x + 0.5 + 0.5 * (double)e[0],
+                       (double)y + 0.5 + 0.5 * (double)e[1],
+                       (double)z + 0.5 + 0.5 * (double)e[2]};
+        double w[3] = {P[0] - M->sphere_c[0], P[1] - M->sphere_c[1], P[2] - M->sphere_c[2]};
+        double len = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+        if (len > 0.0) {
+            N[0] = w[0] / len;
+            N[1] = w[1] / len;
+            N[2] = w[2] / len;
+            if (or_dot3(s, N) < 0.0) {
+                N[0] = -N[0];
+                N[1] = -N[1];
+                N[2] = -N[2];
+            }
+            return;
+        }
+    }
+    /* voxel maps without a surface description: normal incidence along s */
+    N[0] = s[0];
+    N[1] = s[1];
+    N[2] = s[2];
+}
+
+/* ---- assembled matrix ------------------------------------------------------ */
+
+typedef struct {
+    int64_t n_vox, n_states, n_escape, n_rows, nnz;
+    int64_t *row_ptr;        /* [n_rows+1] */
+    int32_t *col;            /* [nnz] */
+    double *val;             /* [nnz] */
+    int32_t *escape_of_state; /* [n_states], -1 when (v,m) does not leave */
+    double *absorb_of_voxel; /* [n_vox] = 1 - exp(-mu_a h) */
+} or_csr_t;
+
+typedef struct {
+    int count;
+    int64_t row[2];
+    double f[2];
+} or_targets_t;
+
+/* where the population that leaves voxel v=(x,y,z) with direction m goes */
+static void or_move(const or_medium_t *M, const or_csr_t *A, int64_t v, int x, int y, int z,
+                    int m, or_targets_t *T)
+{
+    int e[3];
+    or_dir_vec(m, e);
+    int ux = x + e[0], uy = y + e[1], uz = z + e[2];
+    int inside = ux >= 0 && ux < M->nx && uy >= 0 && uy < M->ny && uz >= 0 && uz < M->nz;
+    if (!inside) {
+        if (M->bc == OR_BC_VACUUM) {
+            T->count = 1;
+            T->row[0] = A->n_states + A->escape_of_state[NDIR * v + m];
+            T->f[0] = 1.0;
+        } else {
+            /* specular wall: every component that leaves is reversed, the
+             * population stays in v */
+            int r[3] = {e[0], e[1], e[2]};
+            if (ux < 0 || ux >= M->nx) r[0] = -r[0];
+            if (uy < 0 || uy >= M->ny) r[1] = -r[1];
+            if (uz < 0 || uz >= M->nz) r[2] = -r[2];
+            T->count = 1;
+            T->row[0] = NDIR * v + or_dir_index(r[0], r[1], r[2]);
+            T->f[0] = 1.0;
+        }
+        return;
+    }
+    int64_t u = (int64_t)ux + (int64_t)M->nx * ((int64_t)uy + (int64_t)M->ny * uz);
+    double n1 = M->mat[4 * M->mat_of_voxel[v] + 3];
+    double n2 = M->mat[4 * M->mat_of_voxel[u] + 3];
+    if (n1 == n2) {
+        T->count = 1;
+        T->row[0] = NDIR * u + m;
+        T->f[0] = 1.0;
+        return;
+    }
+    double s[3], N[3];
+    or_dir_unit(m, s);
+    or_normal(M, x, y, z, e, s, N);
+    double R, Tr;
+    int mr, mt;
+    or_fresnel(m, n1, n2, N, &R, &Tr, &mr, &mt);
+    T->count = 1;
+    T->row[0] = NDIR * v + mr;
+    T->f[0] = R;
+    if (Tr > 0.0) {
+        T->count = 2;
+        T->row[1] = NDIR * u + mt;
+        T->f[1] = Tr;
+    }
+}
+
+void or_free(or_csr_t *A)
+{
+    if (!A) return;
+    free(A->row_ptr);
+    free(A->col);
+    free(A->val);
+    free(A->escape_of_state);
+    free(A->absorb_of_voxel);
+    free(A);
+}
+
+/*
+ * Push-style assembly.  For every column (v, n) in ascending order and every
+ * collision direction m in ascending order, the value C_q(v)[m][n] (times the
+ * Fresnel factor where the move crosses an interface) is appended to each
+ * target row.  Appends to a row therefore arrive in ascending column order,
+ * and several contributions of one column to one row are adjacent; they are
+ * summed in m order.  Exact zeros are not stored.
+ */
+or_csr_t *or_build(const or_medium_t *M)
+{
+    or_csr_t *A = (or_csr_t *)calloc(1, sizeof(or_csr_t));
+    if (!A) return NULL;
+    int64_t V = (int64_t)M->nx * M->ny * M->nz;
+    A->n_vox = V;
+    A->n_states = NDIR * V;
+    A->escape_of_state = (int32_t *)malloc(sizeof(int32_t) * A->n_states);
+    A->absorb_of_voxel = (double *)malloc(sizeof(double) * V);
+    double *Cq = (double *)malloc(sizeof(double) * NDIR * NDIR * M->n_mat);
+    if (!A->escape_of_state || !A->absorb_of_voxel || !Cq) goto fail;
+
+    for (int q = 0; q < M->n_mat; ++q)
+        or_collision_block(M->mat[4 * q], M->mat[4 * q + 1], M->mat[4 * q + 2], M->h_mm,
+                           Cq + (int64_t)q * NDIR * NDIR);
+
+    /* escape rows: (v, m) pairs leaving the grid, ascending state order */
+    int64_t ne = 0;
+    for (int64_t v = 0; v < V; ++v) {
+        int x = (int)(v % M->nx), y = (int)((v / M->nx) % M->ny), z = (int)(v / ((int64_t)M->nx * M->ny));
+        A->absorb_of_voxel[v] = -expm1(-M->mat[4 * M->mat_of_voxel[v] + 1] * M->h_mm);
+        for (int m = 0; m < NDIR; ++m) {
+            int e[3];
+            or_dir_vec(m, e);
+            int ux = x + e[0], uy = y + e[1], uz = z + e[2];
+            int inside = ux >= 0 && ux < M->nx && uy >= 0 && uy < M->ny && uz >= 0 && uz < M->nz;
+            A->escape_of_state[NDIR * v + m] = (!inside && M->bc == OR_BC_VACUUM) ? (int32_t)(ne++) : -1;
+        }
+    }
+    A->n_escape = ne;
+    A->n_rows = A->n_states + ne;
+
+    /* pass 1: upper bound of entries per row (before merging) */
+    int64_t *cnt = (int64_t *)calloc((size_t)A->n_rows + 1, sizeof(int64_t));
+    if (!cnt) goto fail;
+    for (int64_t v = 0; v < V; ++v) {
+        int x = (int)(v % M->nx), y = (int)((v / M->nx) % M->ny), z = (int)(v / ((int64_t)M->nx * M->ny));
+        const double *C = Cq + (int64_t)M->mat_of_voxel[v] * NDIR * NDIR;
+        for (int m = 0; m < NDIR; ++m) {
+            or_targets_t T;
+            or_move(M, A, v, x, y, z, m, &T);
+            int nz_in_row = 0;
+            for (int n = 0; n < NDIR; ++n)
+                nz_in_row += C[m * NDIR + n] != 0.0;
+            for (int i = 0; i < T.count; ++i)
+                cnt[T.row[i]] += nz_in_row;
+        }
+    }
+    int64_t *start = (int64_t *)malloc(sizeof(int64_t) * ((size_t)A->n_rows + 1));
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)A->n_rows);
+    if (!start || !fill) {
+        free(cnt);
+        free(start);
+        free(fill);
+        goto fail;
+    }
+    start[0] = 0;
+    for (int64_t r = 0; r < A->n_rows; ++r)
+        start[r + 1] = start[r] + cnt[r];
+    free(cnt);
+    int64_t cap = start[A->n_rows];
+    A->col = (int32_t *)malloc(sizeof(int32_t) * (size_t)(cap > 0 ? cap : 1));
+    A->val = (double *)malloc(sizeof(double) * (size_t)(cap > 0 ? cap : 1));
+    if (!A->col || !A->val) {
+        free(start);
+        free(fill);
+        goto fail;
+    }
+    for (int64_t r = 0; r < A->n_rows; ++r)
+        fill[r] = start[r];
+
+    /* pass 2: push every column, merging adjacent equal columns */
+    for (int64_t v = 0; v < V; ++v) {
+        int x = (int)(v % M->nx), y = (int)((v / M->nx) % M->ny), z = (int)(v / ((int64_t)M->nx * M->ny));
+        const double *C = Cq + (int64_t)M->mat_of_voxel[v] * NDIR * NDIR;
+        or_targets_t T[NDIR];
+        for (int m = 0; m < NDIR; ++m)
+            or_move(M, A, v, x, y, z, m, &T[m]);
+        for (int n = 0; n < NDIR; ++n) {
+            int32_t c = (int32_t)(NDIR * v + n);
+            for (int m = 0; m < NDIR; ++m) {
+                double w = C[m * NDIR + n];
+                if (w == 0.0) continue;
+                for (int i = 0; i < T[m].count; ++i) {
+                    int64_t r = T[m].row[i];
+                    double a = T[m].f[i] * w;
+                    if (fill[r] > start[r] && A->col[fill[r] - 1] == c) {
+                        A->val[fill[r] - 1] += a;
+                    } else {
+                        A->col[fill[r]] = c;
+                        A->val[fill[r]] = a;
+                        fill[r]++;
+                    }
+                }
+            }
+        }
+    }
+
+    /* compact rows (merging may have left gaps) */
+    A->row_ptr = (int64_t *)malloc(sizeof(int64_t) * ((size_t)A->n_rows + 1));
+    if (!A->row_ptr) {
+        free(start);
+        free(fill);
+        goto fail;
+    }
+    int64_t w = 0;
+    A->row_ptr[0] = 0;
+    for (int64_t r = 0; r < A->n_rows; ++r) {
+        for (int64_t j = start[r]; j < fill[r]; ++j) {
+            if (A->val[j] == 0.0) continue;
+            A->col[w] = A->col[j];
+            A->val[w] = A->val[j];
+            ++w;
+        }
+        A->row_ptr[r + 1] = w;
+    }
+    A->nnz = w;
+    free(start);
+    free(fill);
+    free(Cq);
+    return A;
+fail:
+    free(Cq);
+    or_free(A);
+    return NULL;
+}
+
+int64_t or_n_vox(const or_csr_t *A) { return A->n_vox; }
+int64_t or_n_states(const or_csr_t *A) { return A->n_states; }
+int64_t or_n_escape(const or_csr_t *A) { return A->n_escape; }
+int64_t or_n_rows(const or_csr_t *A) { return A->n_rows; }
+int64_t or_nnz(const or_csr_t *A) { return A->nnz; }
+const int64_t *or_row_ptr(const or_csr_t *A) { return A->row_ptr; }
+const int32_t *or_col(const or_csr_t *A) { return A->col; }
+const double *or_val(const or_csr_t *A) { return A->val; }
+const double *or_absorb_of_voxel(const or_csr_t *A) { return A->absorb_of_voxel; }
+
+/* row index of state s = 26 v + m (escape = 0) or of its escape row (escape = 1);
+ * -1 when the state does not leave the grid */
+int64_t or_row_of(const or_csr_t *A, int64_t s, int escape)
+{
+    if (!escape) return s;
+    int32_t e = A->escape_of_state[s];
+    return e < 0 ? -1 : A->n_states + e;
+}
+
+/* ---- FP32 values ----------------------------------------------------------- */
+
+static uint64_t or_splitmix64(uint64_t x)
+{
+    uint64_t z = x + 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+/*
+ * FP64 -> FP32 value rounding.  mode 0: round to nearest even.  mode 1:
+ * unbiased deterministic rounding: with r the nearest float and r' the other
+ * float neighbour of a, r' is taken with probability p = |r - a| / |r' - r|,
+ * the uniform variate being splitmix64((row << 32) ^ col) >> 11 scaled by
+ * 2^-53.  The expected stored value is a, so the rounding of A is unbiased.
+ */
+void or_round_f32(const or_csr_t *A, int mode, float *out)
+{
+    for (int64_t r = 0; r < A->n_rows; ++r) {
+        for (int64_t j = A->row_ptr[r]; j < A->row_ptr[r + 1]; ++j) {
+            double a = A->val[j];
+            float f = (float)a;
+            if (mode == 1 && (double)f != a) {
+                float f2 = nextafterf(f, (double)f < a ? INFINITY : -INFINITY);
+                double p = fabs((double)f - a) / fabs((double)f2 - (double)f);
+                uint64_t key = ((uint64_t)r << 32) ^ (uint64_t)(uint32_t)A->col[j];
+                double u = (double)(or_splitmix64(key) >> 11) * 0x1p-53;
+                if (u < p) f = f2;
+            }
+            out[j] = f;
+        }
+    }
+}
+
+/* ---- time stepping ----------------------------------------------------------- */
+
+/* y = A x over all rows (state rows then escape rows), each row summed in
+ * ascending column order; vals32 replaces the FP64 values when not NULL */
+void or_spmv(const or_csr_t *A, const float *vals32, const double *x, double *y)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < A->n_rows; ++r) {
+        double acc = 0.0;
+        for (int64_t j = A->row_ptr[r]; j < A->row_ptr[r + 1]; ++j) {
+            double a = vals32 ? (double)vals32[j] : A->val[j];
+            acc += a * x[A->col[j]];
+        }
+        y[r] = acc;
+    }
+}
+
+static int or_exponent(double m)
+{
+    int e = 0;
+    if (m > 0.0) frexp(m, &e);
+    return e;
+}
+
+/*
+ * Runs n_steps of J(t+1) = A J(t) + s(t) (Eq. (26)).  The state is kept as
+ * 2^E x with max |x| in [0.5, 1) after every step (exact rescaling).
+ *
+ * Sources: entry i adds src_w[i] * amp[t * n_src + src_id[i]] to row
+ * src_row[i] after the product of step t.
+ * Detectors: M_d(t) = sum over entries with det_id d of det_F * J_row(t+1).
+ * Outputs per step t (value, exponent pairs; physical = value * 2^exponent):
+ *   tot[3t+0] = total of the state after the step, N(t+1)
+ *   tot[3t+1] = escaped during the step (sum of the escape rows)
+ *   tot[3t+2] = absorbed during the step, sum_v (1 - alpha_v) sum_n J(t)
+ *   det[n_det t + d] = M_d(t)
+ * x0 (may be NULL = zero state) is the initial state times 2^-e0; on return
+ * x_out holds the final state times 2^-(*e_out).
+ */
+int or_run(const or_csr_t *A, const float *vals32, int64_t n_steps,
+           const double *x0, int32_t e0,
+           int64_t n_src_e, const int64_t *src_row, const int32_t *src_id, const double *src_w,
+           int32_t n_src, const double *amp,
+           int64_t n_det_e, const int64_t *det_row, const int32_t *det_id, const double *det_F,
+           int32_t n_det,
+           double *tot, int32_t *tot_exp, double *det, int32_t *det_exp,
+           double *x_out, int32_t *e_out)
+{
+    int64_t R = A->n_rows, D = A->n_states;
+    double *x = (double *)calloc((size_t)R, sizeof(double));
+    double *y = (double *)calloc((size_t)R, sizeof(double));
+    double *s = (double *)calloc((size_t)R, sizeof(double));
+    if (!x || !y || !s) {
+        free(x);
+        free(y);
+        free(s);
+        return -1;
+    }
+    int E = 0;
+    if (x0) {
+        memcpy(x, x0, sizeof(double) * (size_t)D);
+        E = e0;
+    }
+    for (int64_t t = 0; t < n_steps; ++t) {
+        /* absorbed during this step, from the state entering it */
+        double absorbed = 0.0;
+        for (int64_t v = 0; v < A->n_vox; ++v) {
+            double sv = 0.0;
+            for (int n = 0; n < NDIR; ++n)
+                sv += x[NDIR * v + n];
+            absorbed += A->absorb_of_voxel[v] * sv;
+        }
+        tot[3 * t + 2] = absorbed;
+        tot_exp[3 * t + 2] = E;
+
+        or_spmv(A, vals32, x, y);
+
+        /* source vector of this step (physical scale) */
+        double smax = 0.0;
+        for (int64_t i = 0; i < n_src_e; ++i)
+            s[src_row[i]] += src_w[i] * amp[t * n_src + src_id[i]];
+        for (int64_t i = 0; i < n_src_e; ++i)
+            if (fabs(s[src_row[i]]) > smax) smax = fabs(s[src_row[i]]);
+        double ymax = 0.0;
+        for (int64_t r = 0; r < D; ++r)
+            if (fabs(y[r]) > ymax) ymax = fabs(y[r]);
+        int En = E;
+        if (ymax > 0.0) En = E + or_exponent(ymax);
+        if (smax > 0.0 && (ymax == 0.0 || or_exponent(smax) > En)) En = or_exponent(smax);
+        for (int64_t r = 0; r < R; ++r)
+            y[r] = ldexp(y[r], E - En);
+        for (int64_t i = 0; i < n_src_e; ++i) {
+            int64_t r = src_row[i];
+            if (s[r] != 0.0) {
+                y[r] += ldexp(s[r], -En);
+                s[r] = 0.0;
+            }
+        }
+        E = En;
+
+        double N = 0.0, esc = 0.0;
+        for (int64_t r = 0; r < D; ++r)
+            N += y[r];
+        for (int64_t r = D; r < R; ++r)
+            esc += y[r];
+        tot[3 * t + 0] = N;
+        tot_exp[3 * t + 0] = E;
+        tot[3 * t + 1] = esc;
+        tot_exp[3 * t + 1] = E;
+        for (int d = 0; d < n_det; ++d) {
+            det[n_det * t + d] = 0.0;
+            det_exp[n_det * t + d] = E;
+        }
+        for (int64_t i = 0; i < n_det_e; ++i)
+            det[n_det * t + det_id[i]] += det_F[i] * y[det_row[i]];
+
+        for (int64_t r = 0; r < D; ++r)
+            x[r] = y[r];
+    }
+    if (x_out) memcpy(x_out, x, sizeof(double) * (size_t)D);
+    if (e_out) *e_out = E;
+    free(x);
+    free(y);
+    free(s);
+    return 0;
+}
+
+/* ---- sources -------------------------------------------------------------- */
+
+/* time step of the lattice: the voxel edge h (mm) crossed at c0 / n_ref */
+double or_dt_seconds(double h_mm, double n_ref)
+{
+    return h_mm * 1e-3 * n_ref / 299792458.0;
+}
+
+/*
+ * Photons a normalised Gaussian pulse of full width at half maximum fwhm
+ * (centred at 3 sigma) emits during step t, [t dt, (t+1) dt), with the lower
+ * limit of step 0 taken to -infinity so the steps sum to one (the source
+ * integrated over the step, Sec. 4.1).
+ */
+double or_gaussian_step(double fwhm_s, double dt_s, int64_t t)
+{
+    double sigma = fwhm_s / (2.0 * sqrt(2.0 * log(2.0)));
+    double tc = 3.0 * sigma;
+    double k = sigma * sqrt(2.0);
+    double lo = (t == 0) ? 2.0 : erfc(((double)t * dt_s - tc) / k);
+    double hi = erfc(((double)(t + 1) * dt_s - tc) / k);
+    return 0.5 * (lo - hi);
+}
+
+/* the splitmix64 finaliser, exposed so that it can be checked against its
+ * published output sequence */
+uint64_t or_splitmix64_value(uint64_t x) { return or_splitmix64(x); }
