@@ -1,0 +1,285 @@
+/*
+ * drts.h -- C ABI of the MI355X (gfx950) implementation of the Dynamic
+ * Radiative Transfer System (DRTS) time step.
+ *
+ * The method (Georgakopoulos, Politopoulos, Georgiou, arXiv 1611.08536):
+ * photons in a scattering and absorbing medium are counted per state
+ * (voxel X_i, direction S_n).  One time step dt maps the state vector J to
+ *     J(t + dt) = A J(t) + B P(t)                                   (Eq. 26)
+ * where A (Eq. 21/23) is a time-independent sparse matrix built once from the
+ * medium, and B P(t) injects the photons that sources emit during the step
+ * (Sec. 4.1).  Detectors read weighted sums of J (Eq. 27, one-step window).
+ *
+ * Discretisation implemented here (Sec. 3 allows any space and direction
+ * partition):
+ *   - cubic voxels of edge h, voxel index v = x + nx (y + ny z);
+ *   - the 26 lattice directions e = (dx,dy,dz) in {-1,0,1}^3 \ {0}, indexed
+ *     d = k - (k > 13) with k = 9(dz+1) + 3(dy+1) + (dx+1);
+ *   - state index s = 26 v + d (the 26 directions of a voxel are contiguous);
+ *   - dt = h n_ref / c0, so light crosses one voxel per step;
+ *   - in one step the population of (v, n) leaves v with direction m with
+ *     probability C_q(v)[m][n] (single-scatter split Eq. (9)-(10),
+ *     Henyey-Greenstein kernel Eq. (19), forward scatter on the diagonal
+ *     Eq. (21)) and arrives at (v + e_m, m);
+ *   - crossing into a voxel of different refractive index splits the
+ *     population by the unpolarised Fresnel reflectance (Sec. 4.2): the
+ *     reflected part stays in v with the lattice direction nearest the
+ *     specular direction, the transmitted part enters v + e_m with the
+ *     lattice direction nearest the Snell direction;
+ *   - at vacuum faces the population leaving the grid is collected in escape
+ *     rows (row index >= n_states), so the matrix is [A; L] with
+ *     n_rows = n_states + n_escape rows; at reflecting faces every leaving
+ *     component of e_m is reversed and the population stays in v.
+ *
+ * Numbers: coefficients are computed in FP64 on the host.  The matrix values
+ * are stored in FP64 or FP32 (round to nearest, or the unbiased "dither"
+ * rounding DRTS_ROUND_DITHER).  FP32 states are kept as 2^E * x with a
+ * per-right-hand-side power-of-two exponent E chosen every step (exact
+ * scaling), so femtosecond-pulse runs spanning 1e20 and more never underflow.
+ * Totals and detector sums are accumulated in FP64 in a fixed order (results
+ * are bitwise reproducible run to run).
+ *
+ * Conventions of every call:
+ *   - return 0 on success, a negative DRTS_E_* code on failure; the message
+ *     of the last failure of the calling thread is drts_last_error();
+ *   - no C++ exception crosses this interface;
+ *   - handles are opaque, owned by the library, freed by their *_destroy;
+ *   - host arrays passed in are read during the call only (copied);
+ *   - device memory is allocated through the caller's drts_device_t hooks
+ *     (or hipMalloc when the hooks are NULL) and all work is enqueued on the
+ *     hook's stream (or the null stream); calls that return host data
+ *     synchronise that stream.
+ */
+#ifndef DRTS_H
+#define DRTS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define DRTS_OK 0
+#define DRTS_E_INVALID (-1) /* malformed argument or medium */
+#define DRTS_E_NOMEM (-2)   /* an allocation (device or host) failed */
+#define DRTS_E_HIP (-3)     /* a HIP runtime call failed */
+#define DRTS_E_RANGE (-4)   /* an index or step count exceeds what was sized */
+#define DRTS_E_STATE (-5)   /* call not valid in the handle's current state */
+
+/* ---- enumerations -------------------------------------------------------- */
+#define DRTS_GEOM_VOXELS 0   /* interfaces use normal incidence along e_m */
+#define DRTS_GEOM_LAYERS_Z 1 /* planar layers stacked along z, normal +-z */
+#define DRTS_GEOM_SPHERE 2   /* sphere: normal radial at the step midpoint */
+
+#define DRTS_BC_VACUUM 0  /* leaving photons go to escape rows */
+#define DRTS_BC_REFLECT 1 /* specular walls, nothing leaves */
+
+#define DRTS_F64 0
+#define DRTS_F32 1
+
+#define DRTS_ROUND_NEAREST 0 /* FP64 -> FP32 values: IEEE round to nearest */
+#define DRTS_ROUND_DITHER 1  /* unbiased: the other float neighbour r' of a is
+                                taken iff u < |r - a| / |r' - r|, where
+                                u = (splitmix64((row << 32) ^ col) >> 11) 2^-53 */
+
+/* ---- medium ---------------------------------------------------------------- */
+typedef struct {
+    int32_t nx, ny, nz; /* voxels per axis, each >= 1 */
+    double h_mm;        /* voxel edge = c dt, in mm */
+} drts_grid_t;
+
+typedef struct {
+    double mu_s; /* scattering coefficient, 1/mm (Eq. 2) */
+    double mu_a; /* absorption coefficient, 1/mm (Eq. 8) */
+    double g;    /* Henyey-Greenstein anisotropy, -1 < g < 1 */
+    double n;    /* refractive index (Sec. 4.2) */
+} drts_material_t;
+
+typedef struct {
+    int32_t kind;            /* DRTS_GEOM_* : rule for interface normals */
+    double sphere_c[3];      /* DRTS_GEOM_SPHERE: centre, voxel units, voxel
+                                (x,y,z) has its centre at (x+.5, y+.5, z+.5) */
+    double sphere_r;         /* DRTS_GEOM_SPHERE: radius, voxel units */
+    int32_t n_layers;        /* DRTS_GEOM_LAYERS_Z: number of layers */
+    const int32_t *layer_z0; /* DRTS_GEOM_LAYERS_Z: first z of each layer,
+                                ascending, layer_z0[0] == 0; layer i uses
+                                material i */
+} drts_geometry_t;
+
+typedef struct {
+    drts_grid_t grid;
+    int32_t n_mat;               /* 1..255 */
+    const drts_material_t *mat;  /* host [n_mat] */
+    const uint8_t *mat_of_voxel; /* host [nx*ny*nz] material id per voxel, or
+                                    NULL: derived from geom (LAYERS_Z: layer of
+                                    z; SPHERE: material 1 where the voxel centre
+                                    lies within the sphere, else 0) */
+    drts_geometry_t geom;
+    int32_t bc;         /* DRTS_BC_* */
+    int32_t value_type; /* DRTS_F64 | DRTS_F32 */
+    int32_t rounding;   /* DRTS_ROUND_* (DRTS_F32 only) */
+    double n_ref;       /* refractive index that sets dt = h n_ref / c0 */
+} drts_medium_t;
+
+/* ---- device hooks ---------------------------------------------------------- */
+typedef struct {
+    void *ctx;
+    void *(*alloc)(void *ctx, size_t bytes, void *stream); /* NULL on failure */
+    void (*free)(void *ctx, void *ptr, void *stream);
+    void *stream; /* hipStream_t every kernel and copy is enqueued on */
+} drts_device_t;
+
+/* ---- sources: s(t) = B P(t) (Eq. 26) ------------------------------------------ */
+typedef struct {
+    void *ctx;
+    int32_t n_src; /* number of source functions */
+    /* Spatial/directional support of source src: writes up to cap (state,
+     * weight) pairs and returns how many it has (the library calls again with a
+     * larger buffer when the return value exceeds cap).  States index
+     * 26 v + d (< n_states). */
+    int64_t (*support)(void *ctx, int32_t src, int64_t *state, double *w, int64_t cap);
+    /* Photons source src emits during step `step` (between step dt and
+     * (step+1) dt); t0_s = step * dt_s.  Called on the host. */
+    double (*amplitude)(void *ctx, int32_t src, int64_t step, double t0_s, double dt_s);
+    /* Right-hand side (column of the multi-source state) that src feeds;
+     * may be NULL when the solver has one right-hand side. */
+    int32_t (*rhs_of)(void *ctx, int32_t src);
+} drts_source_table_t;
+
+/* ---- detectors: M_d(t) = sum F J (Eq. 27 with a one-step window) --------------- */
+typedef struct {
+    int32_t n_det;
+    const int64_t *det_ptr; /* host [n_det+1]: entries of detector d are
+                               det_ptr[d] .. det_ptr[d+1]-1 */
+    const int64_t *state;   /* host: state index 26 v + d */
+    const uint8_t *escape;  /* host: 1 = the escape row of that state (the
+                               photons leaving the grid from it during the
+                               step), 0 = the state itself after the step */
+    const double *F;        /* host: weight */
+} drts_detectors_t;
+
+typedef struct drts_matrix drts_matrix_t;
+typedef struct drts_solver drts_solver_t;
+typedef struct drts_batch drts_batch_t;
+
+/* ---- matrix ------------------------------------------------------------------- */
+
+/* Assembles [A; L] (Eq. 21/23 plus escape rows) on the device, once per
+ * medium (Fig. 3: "build A").  Coefficient tables are computed on the host in
+ * FP64; the CSR is filled on the device (int32 columns, int32 or int64 row
+ * pointers, FP64 or FP32 values).  Errors: DRTS_E_INVALID (bad sizes,
+ * materials or geometry), DRTS_E_RANGE (more than 2^31 - 1 states),
+ * DRTS_E_NOMEM, DRTS_E_HIP. */
+int drts_build_matrix(const drts_medium_t *medium, const drts_device_t *dev, drts_matrix_t **out);
+
+/* Sizes of an assembled matrix; any output pointer may be NULL.  bytes = device
+ * bytes of the CSR (row pointers, columns, values); dt_s in seconds. */
+int drts_matrix_info(const drts_matrix_t *A, int64_t *n_states, int64_t *n_escape, int64_t *nnz,
+                     int64_t *bytes, double *dt_s);
+
+/* Row index of state s (escape = 0 -> s itself; escape = 1 -> its escape row,
+ * or -1 when the state does not leave the grid or faces reflect). */
+int64_t drts_matrix_row_of(const drts_matrix_t *A, int64_t state, int32_t escape);
+
+/* Host copy of rows [row0, row0 + n_rows): row_ptr[n_rows+1] (absolute entry
+ * offsets), col[row_ptr[n_rows]-row_ptr[0]], val (double or float as stored).
+ * Pass col = val = NULL to fetch row_ptr only.  Synchronises the stream. */
+int drts_matrix_export_rows(const drts_matrix_t *A, int64_t row0, int64_t n_rows, int64_t *row_ptr,
+                            int32_t *col, void *val);
+
+void drts_matrix_destroy(drts_matrix_t *A);
+
+/* ---- solver ------------------------------------------------------------------- */
+
+#define DRTS_KERNEL_CSR 0        /* CSR SpMV / SpMM over the stored [A; L] */
+#define DRTS_KERNEL_STRUCTURED 1 /* matrix-free: per-voxel direction block */
+
+typedef struct {
+    int32_t kernel;       /* DRTS_KERNEL_* */
+    int32_t rows_per_tile; /* rows a workgroup reduces per tile (64..256) */
+    int32_t tiles_per_chunk; /* tiles whose sums form one FP64 partial */
+    int32_t grid;         /* persistent workgroups (0 = from the device) */
+    int32_t xcd_remap;    /* 1 = give each XCD a contiguous range of chunks */
+    int32_t graph_steps;  /* steps captured per hipGraph replay (0 = eager) */
+    int32_t rescale;      /* 1 = power-of-two rescale every step (default) */
+} drts_options_t;
+
+/* Creates the time-stepping state for n_rhs right-hand sides sharing A: the
+ * state (zero), detectors, series buffers for max_steps steps.  n_rhs > 1
+ * selects the SpMM kernels (FP32 matrices only).  det may be NULL. */
+int drts_solver_create(const drts_matrix_t *A, int32_t n_rhs, const drts_detectors_t *det,
+                       int64_t max_steps, const drts_device_t *dev, drts_solver_t **out);
+
+int drts_solver_get_options(const drts_solver_t *S, drts_options_t *opt);
+int drts_solver_set_options(drts_solver_t *S, const drts_options_t *opt);
+
+/* One step J <- A J + B P(t) (Eq. 26), t += 1.  Calls src->amplitude for the
+ * current step only.  Asynchronous. */
+int drts_step(drts_solver_t *S, const drts_source_table_t *src);
+
+/* n_steps steps.  Calls src->amplitude for all of them up front, then
+ * replays hipGraphs of graph_steps steps (no host synchronisation inside).
+ * DRTS_E_RANGE when t + n_steps exceeds max_steps.  Asynchronous. */
+int drts_run(drts_solver_t *S, const drts_source_table_t *src, int64_t n_steps);
+
+/* Current step count (synchronises). */
+int drts_solver_time(const drts_solver_t *S, int64_t *t);
+
+/* FP64 series of steps [first, first + count): for step t and right-hand side
+ * k the physical values are value * 2^exp2[t][k]:
+ *   series[t][d][k]  detector d (Eq. 27)             may be NULL
+ *   totals[t][0][k]  photons in the grid after the step      may be NULL
+ *   totals[t][1][k]  photons that left during the step
+ *   totals[t][2][k]  photons absorbed during the step
+ *   exp2[t][k]                                       may be NULL
+ * Synchronises the stream. */
+int drts_detector_readout(const drts_solver_t *S, int64_t first, int64_t count, double *series,
+                          int32_t *exp2, double *totals);
+
+/* State transfer for checkpoint/resume (bit-exact): host_x is
+ * [n_rows][n_rhs] in the value type (state rows, then the escape rows of the
+ * last step), exp2[n_rhs], t.  state_write zeroes nothing else and keeps the
+ * series recorded so far. */
+int drts_state_read(const drts_solver_t *S, void *host_x, int32_t *exp2, int64_t *t);
+int drts_state_write(drts_solver_t *S, const void *host_x, const int32_t *exp2, int64_t t);
+
+/* Kernel timing with HIP events around every launch of the step kernel
+ * (enable = 1 also disables graph replay); stats return the launch count and
+ * the summed milliseconds since the last enable. */
+int drts_solver_profile(drts_solver_t *S, int32_t enable);
+int drts_solver_profile_stats(drts_solver_t *S, int64_t *launches, double *total_ms);
+
+void drts_solver_destroy(drts_solver_t *S);
+
+/* ---- uneven batch: independent solvers in one persistent launch --------------- */
+
+/* Groups n single-rhs FP32 solvers (different matrices and sizes) so that one
+ * launch per step advances all of them.  Each solver keeps its own state,
+ * exponent and series; results equal those of the solver run alone, bit for
+ * bit.  The solvers must outlive the batch. */
+int drts_batch_create(drts_solver_t *const *solvers, int32_t n, const drts_device_t *dev,
+                      drts_batch_t **out);
+
+/* Advances solver i by n_steps[i] steps (0 = idle) with source table src[i];
+ * solvers that finish drop out of later launches. */
+int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const int64_t *n_steps);
+
+void drts_batch_destroy(drts_batch_t *B);
+
+/* ---- autotuning ------------------------------------------------------------------- */
+
+/* Times the candidate launch shapes on the solver's own matrix (a few steps
+ * each, state restored afterwards) and keeps the fastest as its options.
+ * cache_path (may be NULL) is a text file of "key options" lines read before
+ * and appended after tuning; the key is the size class of the problem. */
+int drts_autotune(drts_solver_t *S, const char *cache_path, drts_options_t *chosen);
+
+const char *drts_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DRTS_H */

@@ -1,0 +1,1074 @@
+// C ABI of the DRTS library: handles, device memory hooks, sources and
+// detectors, the step loop (eager or hipGraph replay), readout, state
+// transfer, kernel timing, uneven batches and the autotuner.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "drts_internal.h"
+#include "drts_step.h"
+
+namespace drts {
+
+static thread_local std::string g_error;
+
+int set_error(int code, const char *fmt, ...)
+{
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+const char *hip_name(hipError_t e) { return hipGetErrorString(e); }
+
+void *Device::alloc(size_t bytes)
+{
+    void *p = nullptr;
+    if (hooks.alloc) {
+        p = hooks.alloc(hooks.ctx, bytes, hooks.stream);
+        if (!p) set_error(DRTS_E_NOMEM, "device allocation of %zu bytes failed (caller hook)", bytes);
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            set_error(DRTS_E_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+            p = nullptr;
+        }
+    }
+    return p;
+}
+
+void Device::free(void *p)
+{
+    if (!p) return;
+    if (hooks.free) hooks.free(hooks.ctx, p, hooks.stream);
+    else (void)hipFree(p);
+}
+
+int Buffer::allocate(Device *d, size_t n)
+{
+    reset();
+    dev = d;
+    ptr = d->alloc(n ? n : 16);
+    if (!ptr) return DRTS_E_NOMEM;
+    bytes = n;
+    return DRTS_OK;
+}
+
+void Buffer::reset()
+{
+    if (ptr && dev) dev->free(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+int64_t Matrix::bytes() const { return (int64_t)(row_ptr.bytes + col.bytes + val.bytes); }
+
+static Device make_device(const drts_device_t *d)
+{
+    Device dev;
+    if (d) {
+        dev.hooks = *d;
+        dev.stream = (hipStream_t)d->stream;
+    }
+    return dev;
+}
+
+static int device_cu_count()
+{
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
+}  // namespace drts
+
+using namespace drts;
+
+struct drts_matrix {
+    Matrix m;
+};
+
+// ---- solver --------------------------------------------------------------------
+
+struct SourceEntry {
+    int64_t row;
+    int32_t rhs, id;
+    double w;
+};
+struct DetEntry {
+    int64_t row;
+    int32_t id;
+    double F;
+};
+
+struct drts_solver {
+    Device dev;
+    const drts_matrix *A = nullptr;
+    int n_rhs = 1;
+    int64_t max_steps = 0;
+    drts_options_t opt{};
+    int grid = 0;
+    int64_t n_tiles = 0, n_chunks = 0;
+    int64_t t_host = 0;
+
+    Buffer buf0, buf1, ctl_t, ctl_E, ctl_M, ctl_abs, t_end, partials;
+    Buffer ser_tot, ser_det, ser_exp, ser_abs_exp, amp, smax;
+    Buffer src_tile, src_row, src_id, src_rhs, src_w;
+    Buffer det_tile, det_row, det_id, det_F;
+    Buffer inst_dev, work_dev;
+
+    // host copies
+    std::vector<DetEntry> dets;
+    int n_det = 0;
+    std::vector<SourceEntry> srcs;
+    const drts_source_table_t *src_key = nullptr;
+    void *src_ctx_key = nullptr;
+    int n_src = 0;
+    std::vector<double> amp_h, smax_h;
+    StepInst inst_h{};
+    std::vector<WorkItem> work_h;
+
+    // graph replay
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph = nullptr;
+    int graph_steps = 0;
+
+    // profiling
+    bool profile = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    int64_t prof_launches = 0;
+    double prof_ms = 0.0;
+};
+
+struct drts_batch {
+    Device dev;
+    std::vector<drts_solver *> solvers;
+    Buffer inst_dev, work_dev;
+};
+
+namespace {
+
+int upload_bytes(Device &dev, Buffer &b, const void *h, size_t bytes)
+{
+    int rc = b.allocate(&dev, std::max<size_t>(bytes, 16));
+    if (rc) return rc;
+    if (bytes) DRTS_HIP(hipMemcpyAsync(b.ptr, h, bytes, hipMemcpyHostToDevice, dev.stream));
+    return DRTS_OK;
+}
+template <typename T> int upload_vec(Device &dev, Buffer &b, const std::vector<T> &v)
+{
+    return upload_bytes(dev, b, v.data(), v.size() * sizeof(T));
+}
+
+void drop_graph(drts_solver *S)
+{
+    if (S->graph) {
+        (void)hipGraphExecDestroy(S->graph);
+        S->graph = nullptr;
+    }
+    S->graph_steps = 0;
+}
+
+// per-tile offsets of entries sorted by row
+template <typename E> std::vector<int32_t> tile_offsets(const std::vector<E> &v, int64_t n_tiles, int rows_per_tile)
+{
+    std::vector<int32_t> off((size_t)n_tiles + 1, 0);
+    size_t e = 0;
+    for (int64_t k = 0; k <= n_tiles; ++k) {
+        const int64_t r0 = k * (int64_t)rows_per_tile;
+        while (e < v.size() && v[e].row < r0) ++e;
+        off[(size_t)k] = (int32_t)e;
+    }
+    return off;
+}
+
+bool spmm_of(const drts_solver *S) { return S->n_rhs > 1; }
+
+// (Re)builds every structure that depends on the options and the sources.
+int prepare(drts_solver *S)
+{
+    const Matrix &A = S->A->m;
+    Device &dev = S->dev;
+    const drts_options_t &o = S->opt;
+    int rc;
+    S->n_tiles = (A.model.n_rows + o.rows_per_tile - 1) / o.rows_per_tile;
+    S->n_chunks = (S->n_tiles + o.tiles_per_chunk - 1) / o.tiles_per_chunk;
+    S->grid = o.grid > 0 ? o.grid : device_cu_count() * (spmm_of(S) ? 4 : 8);
+    if (S->n_chunks > INT32_MAX) return set_error(DRTS_E_RANGE, "too many chunks");
+
+    // sources and detectors per tile
+    if ((rc = upload_vec(dev, S->src_tile, tile_offsets(S->srcs, S->n_tiles, o.rows_per_tile)))) return rc;
+    if ((rc = upload_vec(dev, S->det_tile, tile_offsets(S->dets, S->n_tiles, o.rows_per_tile)))) return rc;
+    const size_t slots = (size_t)(kSlotDet + S->n_det) * S->n_rhs;
+    if ((rc = S->partials.allocate(&dev, slots * (size_t)S->n_chunks * sizeof(double)))) return rc;
+
+    StepInst &I = S->inst_h;
+    memset(&I, 0, sizeof I);
+    I.row_ptr = A.row_ptr.ptr;
+    I.col = A.col.as<int32_t>();
+    I.val = A.val.ptr;
+    I.n_rows = A.model.n_rows;
+    I.n_states = A.model.n_states;
+    I.rp64 = A.rp64 ? 1 : 0;
+    I.rows_per_tile = o.rows_per_tile;
+    I.n_tiles = S->n_tiles;
+    I.tiles_per_chunk = o.tiles_per_chunk;
+    I.n_rhs = S->n_rhs;
+    I.buf0 = S->buf0.ptr;
+    I.buf1 = S->buf1.ptr;
+    I.mat = A.mat_of_voxel.as<uint8_t>();
+    I.absorb = A.absorb.as<double>();
+    I.src_tile = S->src_tile.as<int32_t>();
+    I.src_row = S->src_row.as<int64_t>();
+    I.src_id = S->src_id.as<int32_t>();
+    I.src_rhs = S->src_rhs.as<int32_t>();
+    I.src_w = S->src_w.as<double>();
+    I.amp = S->amp.as<double>();
+    I.smax = S->smax.as<double>();
+    I.n_src = S->n_src;
+    I.n_det = S->n_det;
+    I.det_tile = S->det_tile.as<int32_t>();
+    I.det_row = S->det_row.as<int64_t>();
+    I.det_id = S->det_id.as<int32_t>();
+    I.det_F = S->det_F.as<double>();
+    I.t = S->ctl_t.as<int64_t>();
+    I.E = S->ctl_E.as<int32_t>();
+    I.M = S->ctl_M.as<double>();
+    I.abs_cur = S->ctl_abs.as<double>();
+    I.t_end = S->t_end.as<int64_t>();
+    I.rescale = o.rescale;
+    I.max_steps = S->max_steps;
+    I.partials = S->partials.as<double>();
+    I.n_chunks = S->n_chunks;
+    I.ser_tot = S->ser_tot.as<double>();
+    I.ser_det = S->ser_det.as<double>();
+    I.ser_exp = S->ser_exp.as<int32_t>();
+    I.ser_abs_exp = S->ser_abs_exp.as<int32_t>();
+    if ((rc = upload_bytes(dev, S->inst_dev, &I, sizeof I))) return rc;
+
+    S->work_h.resize((size_t)S->n_chunks);
+    for (int64_t c = 0; c < S->n_chunks; ++c) S->work_h[(size_t)c] = {0, (int32_t)c};
+    if ((rc = upload_vec(dev, S->work_dev, S->work_h))) return rc;
+    drop_graph(S);
+    DRTS_HIP(hipStreamSynchronize(dev.stream));
+    return DRTS_OK;
+}
+
+int set_sources(drts_solver *S, const drts_source_table_t *src)
+{
+    if (!src || src->n_src <= 0) {
+        if (S->n_src == 0 && S->src_key == nullptr) return DRTS_OK;
+        S->srcs.clear();
+        S->n_src = 0;
+        S->src_key = nullptr;
+        S->src_ctx_key = nullptr;
+    } else {
+        if (src == S->src_key && src->ctx == S->src_ctx_key && src->n_src == S->n_src) return DRTS_OK;
+        if (!src->support || !src->amplitude) return set_error(DRTS_E_INVALID, "source table lacks callbacks");
+        if (S->n_rhs > 1 && !src->rhs_of) return set_error(DRTS_E_INVALID, "rhs_of is required with n_rhs > 1");
+        std::vector<SourceEntry> e;
+        std::vector<int64_t> st(64);
+        std::vector<double> w(64);
+        const int64_t D = S->A->m.model.n_states;
+        for (int32_t k = 0; k < src->n_src; ++k) {
+            int64_t n = src->support(src->ctx, k, st.data(), w.data(), (int64_t)st.size());
+            if (n > (int64_t)st.size()) {
+                st.resize((size_t)n);
+                w.resize((size_t)n);
+                n = src->support(src->ctx, k, st.data(), w.data(), (int64_t)st.size());
+            }
+            if (n < 0 || n > (int64_t)st.size()) return set_error(DRTS_E_INVALID, "source %d: bad support size", k);
+            const int32_t rhs = src->rhs_of ? src->rhs_of(src->ctx, k) : 0;
+            if (rhs < 0 || rhs >= S->n_rhs) return set_error(DRTS_E_INVALID, "source %d feeds rhs %d", k, rhs);
+            for (int64_t i = 0; i < n; ++i) {
+                if (st[(size_t)i] < 0 || st[(size_t)i] >= D)
+                    return set_error(DRTS_E_INVALID, "source %d: state %lld out of range", k, (long long)st[(size_t)i]);
+                e.push_back({st[(size_t)i], rhs, k, w[(size_t)i]});
+            }
+        }
+        std::stable_sort(e.begin(), e.end(), [](const SourceEntry &a, const SourceEntry &b) {
+            return a.row != b.row ? a.row < b.row : a.rhs < b.rhs;
+        });
+        S->srcs.swap(e);
+        S->n_src = src->n_src;
+        S->src_key = src;
+        S->src_ctx_key = src->ctx;
+    }
+    Device &dev = S->dev;
+    std::vector<int64_t> row(S->srcs.size());
+    std::vector<int32_t> id(S->srcs.size()), rhs(S->srcs.size());
+    std::vector<double> w(S->srcs.size());
+    for (size_t i = 0; i < S->srcs.size(); ++i) {
+        row[i] = S->srcs[i].row;
+        id[i] = S->srcs[i].id;
+        rhs[i] = S->srcs[i].rhs;
+        w[i] = S->srcs[i].w;
+    }
+    int rc;
+    if ((rc = upload_vec(dev, S->src_row, row))) return rc;
+    if ((rc = upload_vec(dev, S->src_id, id))) return rc;
+    if ((rc = upload_vec(dev, S->src_rhs, rhs))) return rc;
+    if ((rc = upload_vec(dev, S->src_w, w))) return rc;
+    if ((rc = S->amp.allocate(&dev, (size_t)S->max_steps * std::max(S->n_src, 1) * sizeof(double)))) return rc;
+    DRTS_HIP(hipMemsetAsync(S->amp.ptr, 0, S->amp.bytes, dev.stream));
+    return prepare(S);
+}
+
+// Host amplitudes and per-rhs source bounds for steps [t0, t0 + n), uploaded.
+int upload_amplitudes(drts_solver *S, const drts_source_table_t *src, int64_t t0, int64_t n)
+{
+    const int ns = S->n_src, nr = S->n_rhs;
+    S->smax_h.assign((size_t)n * nr, 0.0);
+    if (ns > 0) {
+        const double dt = S->A->m.model.dt_s;
+        S->amp_h.resize((size_t)n * ns);
+        for (int64_t s = 0; s < n; ++s)
+            for (int k = 0; k < ns; ++k)
+                S->amp_h[(size_t)(s * ns + k)] = src->amplitude(src->ctx, k, t0 + s, (double)(t0 + s) * dt, dt);
+        // bound of |s_t| per rhs: the largest |row sum| over source rows
+        for (int64_t s = 0; s < n; ++s) {
+            size_t i = 0;
+            while (i < S->srcs.size()) {
+                size_t j = i;
+                double acc = 0.0;
+                while (j < S->srcs.size() && S->srcs[j].row == S->srcs[i].row && S->srcs[j].rhs == S->srcs[i].rhs) {
+                    acc += S->srcs[j].w * S->amp_h[(size_t)(s * ns + S->srcs[j].id)];
+                    ++j;
+                }
+                double &m = S->smax_h[(size_t)(s * nr + S->srcs[i].rhs)];
+                m = std::max(m, std::fabs(acc));
+                i = j;
+            }
+        }
+        DRTS_HIP(hipMemcpyAsync(S->amp.as<double>() + t0 * ns, S->amp_h.data(), (size_t)n * ns * sizeof(double),
+                                hipMemcpyHostToDevice, S->dev.stream));
+    }
+    DRTS_HIP(hipMemcpyAsync(S->smax.as<double>() + t0 * nr, S->smax_h.data(), (size_t)n * nr * sizeof(double),
+                            hipMemcpyHostToDevice, S->dev.stream));
+    // the copies read host vectors that the next call may overwrite
+    DRTS_HIP(hipStreamSynchronize(S->dev.stream));
+    return DRTS_OK;
+}
+
+hipEvent_t next_event(drts_solver *S)
+{
+    if (S->ev_used == S->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        S->ev_pool.push_back(e);
+    }
+    return S->ev_pool[S->ev_used++];
+}
+
+int launch_one(drts_solver *S, hipStream_t stream)
+{
+    const Matrix &A = S->A->m;
+    const bool spmm = spmm_of(S);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (S->profile && stream == S->dev.stream) {
+        e0 = next_event(S);
+        e1 = next_event(S);
+        if (!e0 || !e1) return set_error(DRTS_E_HIP, "hipEventCreate failed");
+        DRTS_HIP(hipEventRecord(e0, stream));
+    }
+    hipError_t e = launch_step(S->inst_dev.as<StepInst>(), S->work_dev.as<WorkItem>(), S->n_chunks, 1, S->n_rhs,
+                               A.model.value_type == DRTS_F64, A.rp64 ? 1 : 0, spmm ? 1 : 0, S->grid,
+                               S->opt.xcd_remap, S->opt.rows_per_tile, S->n_det, stream);
+    if (e != hipSuccess) return set_error(DRTS_E_HIP, "step launch failed: %s", hipGetErrorString(e));
+    if (e1) DRTS_HIP(hipEventRecord(e1, stream));
+    e = launch_finalize(S->inst_dev.as<StepInst>(), 1, S->n_rhs, S->n_det, stream);
+    if (e != hipSuccess) return set_error(DRTS_E_HIP, "finalize launch failed: %s", hipGetErrorString(e));
+    return DRTS_OK;
+}
+
+int collect_profile(drts_solver *S)
+{
+    if (S->ev_used == 0) return DRTS_OK;
+    DRTS_HIP(hipStreamSynchronize(S->dev.stream));
+    for (size_t i = 0; i + 1 < S->ev_used; i += 2) {
+        float ms = 0.f;
+        DRTS_HIP(hipEventElapsedTime(&ms, S->ev_pool[i], S->ev_pool[i + 1]));
+        S->prof_ms += ms;
+        S->prof_launches += 1;
+    }
+    S->ev_used = 0;
+    return DRTS_OK;
+}
+
+int ensure_graph(drts_solver *S, int K)
+{
+    if (S->graph && S->graph_steps == K) return DRTS_OK;
+    drop_graph(S);
+    if (!S->cap_stream) DRTS_HIP(hipStreamCreateWithFlags(&S->cap_stream, hipStreamNonBlocking));
+    DRTS_HIP(hipStreamBeginCapture(S->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = DRTS_OK;
+    for (int k = 0; k < K && rc == DRTS_OK; ++k) rc = launch_one(S, S->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(S->cap_stream, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return set_error(DRTS_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&S->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        S->graph = nullptr;
+        return set_error(DRTS_E_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
+    }
+    S->graph_steps = K;
+    return DRTS_OK;
+}
+
+drts_options_t default_options(const drts_solver *S)
+{
+    drts_options_t o{};
+    o.kernel = DRTS_KERNEL_CSR;
+    o.rows_per_tile = spmm_of(S) ? 64 : 256;
+    o.tiles_per_chunk = spmm_of(S) ? 128 : 16;
+    o.grid = 0;
+    o.xcd_remap = 1;
+    o.graph_steps = 0;
+    o.rescale = 1;
+    return o;
+}
+
+int check_options(const drts_solver *S, const drts_options_t *o)
+{
+    if (o->kernel != DRTS_KERNEL_CSR && o->kernel != DRTS_KERNEL_STRUCTURED)
+        return set_error(DRTS_E_INVALID, "unknown kernel %d", o->kernel);
+    if (o->kernel == DRTS_KERNEL_STRUCTURED)
+        return set_error(DRTS_E_INVALID, "the structured kernel is not available in this build");
+    if (o->rows_per_tile < 16 || o->rows_per_tile > 256) return set_error(DRTS_E_INVALID, "rows_per_tile in 16..256");
+    if (o->tiles_per_chunk < 1 || o->tiles_per_chunk > (1 << 20))
+        return set_error(DRTS_E_INVALID, "tiles_per_chunk in 1..2^20");
+    if (o->grid < 0 || o->graph_steps < 0 || o->graph_steps > 4096)
+        return set_error(DRTS_E_INVALID, "bad grid or graph_steps");
+    (void)S;
+    return DRTS_OK;
+}
+
+}  // namespace
+
+// ---- C ABI ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char *drts_last_error(void) { return g_error.c_str(); }
+
+int drts_build_matrix(const drts_medium_t *medium, const drts_device_t *dev, drts_matrix_t **out)
+{
+    if (!out) return set_error(DRTS_E_INVALID, "out is NULL");
+    *out = nullptr;
+    drts_matrix *A = new (std::nothrow) drts_matrix;
+    if (!A) return set_error(DRTS_E_NOMEM, "host allocation failed");
+    A->m.dev = make_device(dev);
+    int rc;
+    try {
+        rc = build_model(medium, &A->m.model);
+        if (!rc) rc = assemble_on_device(&A->m);
+    } catch (const std::bad_alloc &) {
+        rc = set_error(DRTS_E_NOMEM, "host allocation failed during assembly");
+    } catch (...) {
+        rc = set_error(DRTS_E_INVALID, "unexpected failure during assembly");
+    }
+    if (rc) {
+        delete A;
+        return rc;
+    }
+    *out = A;
+    return DRTS_OK;
+}
+
+int drts_matrix_info(const drts_matrix_t *A, int64_t *n_states, int64_t *n_escape, int64_t *nnz, int64_t *bytes,
+                     double *dt_s)
+{
+    if (!A) return set_error(DRTS_E_INVALID, "matrix is NULL");
+    if (n_states) *n_states = A->m.model.n_states;
+    if (n_escape) *n_escape = A->m.model.n_escape;
+    if (nnz) *nnz = A->m.nnz;
+    if (bytes) *bytes = A->m.bytes();
+    if (dt_s) *dt_s = A->m.model.dt_s;
+    return DRTS_OK;
+}
+
+int64_t drts_matrix_row_of(const drts_matrix_t *A, int64_t state, int32_t escape)
+{
+    if (!A || state < 0 || state >= A->m.model.n_states) return -1;
+    if (!escape) return state;
+    const auto &es = A->m.model.escape_state;
+    auto it = std::lower_bound(es.begin(), es.end(), state);
+    if (it == es.end() || *it != state) return -1;
+    return A->m.model.n_states + (int64_t)(it - es.begin());
+}
+
+int drts_matrix_export_rows(const drts_matrix_t *A, int64_t row0, int64_t n_rows, int64_t *row_ptr, int32_t *col,
+                            void *val)
+{
+    if (!A || !row_ptr) return set_error(DRTS_E_INVALID, "matrix or row_ptr is NULL");
+    const Matrix &M = A->m;
+    if (row0 < 0 || n_rows < 0 || row0 + n_rows > M.model.n_rows) return set_error(DRTS_E_RANGE, "rows out of range");
+    hipStream_t s = M.dev.stream;
+    if (M.rp64) {
+        DRTS_HIP(hipMemcpyAsync(row_ptr, M.row_ptr.as<int64_t>() + row0, (size_t)(n_rows + 1) * sizeof(int64_t),
+                                hipMemcpyDeviceToHost, s));
+        DRTS_HIP(hipStreamSynchronize(s));
+    } else {
+        std::vector<int32_t> tmp((size_t)n_rows + 1);
+        DRTS_HIP(hipMemcpyAsync(tmp.data(), M.row_ptr.as<int32_t>() + row0, (size_t)(n_rows + 1) * sizeof(int32_t),
+                                hipMemcpyDeviceToHost, s));
+        DRTS_HIP(hipStreamSynchronize(s));
+        for (size_t i = 0; i < tmp.size(); ++i) row_ptr[i] = tmp[i];
+    }
+    const int64_t b = row_ptr[0], n = row_ptr[n_rows] - row_ptr[0];
+    const size_t vs = M.model.value_type == DRTS_F64 ? 8 : 4;
+    if (col && n) DRTS_HIP(hipMemcpyAsync(col, M.col.as<int32_t>() + b, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+    if (val && n)
+        DRTS_HIP(hipMemcpyAsync(val, (const char *)M.val.ptr + (size_t)b * vs, (size_t)n * vs, hipMemcpyDeviceToHost, s));
+    DRTS_HIP(hipStreamSynchronize(s));
+    return DRTS_OK;
+}
+
+void drts_matrix_destroy(drts_matrix_t *A) { delete A; }
+
+int drts_solver_create(const drts_matrix_t *A, int32_t n_rhs, const drts_detectors_t *det, int64_t max_steps,
+                       const drts_device_t *dev, drts_solver_t **out)
+{
+    if (!out || !A) return set_error(DRTS_E_INVALID, "NULL argument");
+    *out = nullptr;
+    if (n_rhs < 1 || n_rhs > 64) return set_error(DRTS_E_INVALID, "n_rhs must be in 1..64");
+    if (n_rhs > 1 && A->m.model.value_type != DRTS_F32)
+        return set_error(DRTS_E_INVALID, "several right-hand sides need an FP32 matrix");
+    if (max_steps < 1) return set_error(DRTS_E_INVALID, "max_steps must be >= 1");
+    drts_solver *S = new (std::nothrow) drts_solver;
+    if (!S) return set_error(DRTS_E_NOMEM, "host allocation failed");
+    S->dev = make_device(dev);
+    S->A = A;
+    S->n_rhs = n_rhs;
+    S->max_steps = max_steps;
+    S->opt = default_options(S);
+    const Model &M = A->m.model;
+    int rc = DRTS_OK;
+    try {
+        if (det && det->n_det > 0) {
+            const int nd_max = n_rhs > 1 ? 32 : 256;
+            if (det->n_det > nd_max) rc = set_error(DRTS_E_INVALID, "at most %d detectors", nd_max);
+            if (!rc && (!det->det_ptr || !det->state || !det->F)) rc = set_error(DRTS_E_INVALID, "detector arrays");
+            for (int d = 0; !rc && d < det->n_det; ++d) {
+                for (int64_t i = det->det_ptr[d]; i < det->det_ptr[d + 1]; ++i) {
+                    const bool esc = det->escape && det->escape[i];
+                    const int64_t r = drts_matrix_row_of(A, det->state[i], esc ? 1 : 0);
+                    if (r < 0) {
+                        rc = set_error(DRTS_E_INVALID, "detector %d entry %lld: state %lld has no %s row", d,
+                                       (long long)i, (long long)det->state[i], esc ? "escape" : "state");
+                        break;
+                    }
+                    S->dets.push_back({r, d, det->F[i]});
+                }
+            }
+            S->n_det = det->n_det;
+            std::stable_sort(S->dets.begin(), S->dets.end(),
+                             [](const DetEntry &a, const DetEntry &b) { return a.row < b.row; });
+        }
+        const size_t st = (size_t)M.n_rows * n_rhs * (M.value_type == DRTS_F64 ? 8 : 4);
+        Device &dv = S->dev;
+        if (!rc) rc = S->buf0.allocate(&dv, st);
+        if (!rc) rc = S->buf1.allocate(&dv, st);
+        if (!rc) rc = S->ctl_t.allocate(&dv, n_rhs * sizeof(int64_t));
+        if (!rc) rc = S->ctl_E.allocate(&dv, n_rhs * sizeof(int32_t));
+        if (!rc) rc = S->ctl_M.allocate(&dv, n_rhs * sizeof(double));
+        if (!rc) rc = S->ctl_abs.allocate(&dv, n_rhs * sizeof(double));
+        if (!rc) rc = S->t_end.allocate(&dv, sizeof(int64_t));
+        if (!rc) rc = S->ser_tot.allocate(&dv, (size_t)max_steps * 3 * n_rhs * sizeof(double));
+        if (!rc) rc = S->ser_det.allocate(&dv, (size_t)max_steps * std::max(S->n_det, 1) * n_rhs * sizeof(double));
+        if (!rc) rc = S->ser_exp.allocate(&dv, (size_t)max_steps * n_rhs * sizeof(int32_t));
+        if (!rc) rc = S->ser_abs_exp.allocate(&dv, (size_t)max_steps * n_rhs * sizeof(int32_t));
+        if (!rc) rc = S->smax.allocate(&dv, (size_t)max_steps * n_rhs * sizeof(double));
+        if (!rc) rc = S->amp.allocate(&dv, 16);
+        if (!rc) {
+            std::vector<int64_t> r(S->dets.size());
+            std::vector<int32_t> id(S->dets.size());
+            std::vector<double> F(S->dets.size());
+            for (size_t i = 0; i < S->dets.size(); ++i) {
+                r[i] = S->dets[i].row;
+                id[i] = S->dets[i].id;
+                F[i] = S->dets[i].F;
+            }
+            rc = upload_vec(dv, S->det_row, r);
+            if (!rc) rc = upload_vec(dv, S->det_id, id);
+            if (!rc) rc = upload_vec(dv, S->det_F, F);
+            std::vector<int64_t> none;
+            if (!rc) rc = upload_vec(dv, S->src_row, none);
+            std::vector<int32_t> none32;
+            if (!rc) rc = upload_vec(dv, S->src_id, none32);
+            if (!rc) rc = upload_vec(dv, S->src_rhs, none32);
+            std::vector<double> noned;
+            if (!rc) rc = upload_vec(dv, S->src_w, noned);
+        }
+        if (!rc) {
+            hipStream_t s = dv.stream;
+            if (hipMemsetAsync(S->buf0.ptr, 0, st, s) != hipSuccess || hipMemsetAsync(S->buf1.ptr, 0, st, s) != hipSuccess ||
+                hipMemsetAsync(S->ctl_t.ptr, 0, n_rhs * sizeof(int64_t), s) != hipSuccess ||
+                hipMemsetAsync(S->ctl_E.ptr, 0, n_rhs * sizeof(int32_t), s) != hipSuccess ||
+                hipMemsetAsync(S->ctl_M.ptr, 0, n_rhs * sizeof(double), s) != hipSuccess ||
+                hipMemsetAsync(S->ctl_abs.ptr, 0, n_rhs * sizeof(double), s) != hipSuccess ||
+                hipMemsetAsync(S->smax.ptr, 0, S->smax.bytes, s) != hipSuccess ||
+                hipMemsetAsync(S->ser_tot.ptr, 0, S->ser_tot.bytes, s) != hipSuccess ||
+                hipMemsetAsync(S->ser_det.ptr, 0, S->ser_det.bytes, s) != hipSuccess ||
+                hipMemcpyAsync(S->t_end.ptr, &S->max_steps, sizeof(int64_t), hipMemcpyHostToDevice, s) != hipSuccess)
+                rc = set_error(DRTS_E_HIP, "initialising solver buffers failed");
+        }
+        if (!rc) rc = prepare(S);
+    } catch (const std::bad_alloc &) {
+        rc = set_error(DRTS_E_NOMEM, "host allocation failed");
+    }
+    if (rc) {
+        drts_solver_destroy(S);
+        return rc;
+    }
+    *out = S;
+    return DRTS_OK;
+}
+
+int drts_solver_get_options(const drts_solver_t *S, drts_options_t *opt)
+{
+    if (!S || !opt) return set_error(DRTS_E_INVALID, "NULL argument");
+    *opt = S->opt;
+    return DRTS_OK;
+}
+
+int drts_solver_set_options(drts_solver_t *S, const drts_options_t *opt)
+{
+    if (!S || !opt) return set_error(DRTS_E_INVALID, "NULL argument");
+    int rc = check_options(S, opt);
+    if (rc) return rc;
+    S->opt = *opt;
+    return prepare(S);
+}
+
+int drts_step(drts_solver_t *S, const drts_source_table_t *src)
+{
+    if (!S) return set_error(DRTS_E_INVALID, "solver is NULL");
+    if (S->t_host + 1 > S->max_steps) return set_error(DRTS_E_RANGE, "step %lld beyond max_steps", (long long)S->t_host);
+    int rc = set_sources(S, src);
+    if (!rc) rc = upload_amplitudes(S, src, S->t_host, 1);
+    if (!rc) rc = launch_one(S, S->dev.stream);
+    if (rc) return rc;
+    S->t_host += 1;
+    return DRTS_OK;
+}
+
+int drts_run(drts_solver_t *S, const drts_source_table_t *src, int64_t n_steps)
+{
+    if (!S) return set_error(DRTS_E_INVALID, "solver is NULL");
+    if (n_steps < 0 || S->t_host + n_steps > S->max_steps)
+        return set_error(DRTS_E_RANGE, "steps %lld..%lld beyond max_steps %lld", (long long)S->t_host,
+                         (long long)(S->t_host + n_steps), (long long)S->max_steps);
+    if (n_steps == 0) return DRTS_OK;
+    int rc = set_sources(S, src);
+    if (!rc) rc = upload_amplitudes(S, src, S->t_host, n_steps);
+    if (rc) return rc;
+    const int K = S->opt.graph_steps;
+    int64_t done = 0;
+    if (K > 0 && !S->profile && n_steps >= K) {
+        if ((rc = ensure_graph(S, K))) return rc;
+        for (; done + K <= n_steps; done += K) DRTS_HIP(hipGraphLaunch(S->graph, S->dev.stream));
+    }
+    for (; done < n_steps; ++done)
+        if ((rc = launch_one(S, S->dev.stream))) return rc;
+    S->t_host += n_steps;
+    return DRTS_OK;
+}
+
+int drts_solver_time(const drts_solver_t *S, int64_t *t)
+{
+    if (!S || !t) return set_error(DRTS_E_INVALID, "NULL argument");
+    DRTS_HIP(hipMemcpyAsync(t, S->ctl_t.ptr, sizeof(int64_t), hipMemcpyDeviceToHost, S->dev.stream));
+    DRTS_HIP(hipStreamSynchronize(S->dev.stream));
+    return DRTS_OK;
+}
+
+int drts_detector_readout(const drts_solver_t *S, int64_t first, int64_t count, double *series, int32_t *exp2,
+                          double *totals)
+{
+    if (!S) return set_error(DRTS_E_INVALID, "solver is NULL");
+    if (first < 0 || count < 0 || first + count > S->max_steps) return set_error(DRTS_E_RANGE, "steps out of range");
+    if (count == 0) return DRTS_OK;
+    const int nr = S->n_rhs;
+    hipStream_t s = S->dev.stream;
+    std::vector<int32_t> e((size_t)count * nr), ea((size_t)count * nr);
+    DRTS_HIP(hipMemcpyAsync(e.data(), S->ser_exp.as<int32_t>() + first * nr, e.size() * 4, hipMemcpyDeviceToHost, s));
+    DRTS_HIP(hipMemcpyAsync(ea.data(), S->ser_abs_exp.as<int32_t>() + first * nr, ea.size() * 4, hipMemcpyDeviceToHost, s));
+    if (series && S->n_det > 0)
+        DRTS_HIP(hipMemcpyAsync(series, S->ser_det.as<double>() + first * S->n_det * nr,
+                                (size_t)count * S->n_det * nr * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (totals)
+        DRTS_HIP(hipMemcpyAsync(totals, S->ser_tot.as<double>() + first * 3 * nr, (size_t)count * 3 * nr * sizeof(double),
+                                hipMemcpyDeviceToHost, s));
+    DRTS_HIP(hipStreamSynchronize(s));
+    if (totals) {
+        // absorbed(t) was summed from x_t (exponent E_t); express it in E_{t+1}
+        for (int64_t i = 0; i < count; ++i)
+            for (int k = 0; k < nr; ++k) {
+                double &a = totals[(i * 3 + 2) * nr + k];
+                a = std::ldexp(a, ea[(size_t)(i * nr + k)] - e[(size_t)(i * nr + k)]);
+            }
+    }
+    if (exp2) memcpy(exp2, e.data(), e.size() * 4);
+    return DRTS_OK;
+}
+
+int drts_state_read(const drts_solver_t *S, void *host_x, int32_t *exp2, int64_t *t)
+{
+    if (!S) return set_error(DRTS_E_INVALID, "solver is NULL");
+    hipStream_t s = S->dev.stream;
+    int64_t tt = 0;
+    DRTS_HIP(hipMemcpyAsync(&tt, S->ctl_t.ptr, sizeof tt, hipMemcpyDeviceToHost, s));
+    DRTS_HIP(hipStreamSynchronize(s));
+    const Matrix &A = S->A->m;
+    const size_t st = (size_t)A.model.n_rows * S->n_rhs * (A.model.value_type == DRTS_F64 ? 8 : 4);
+    if (host_x)
+        DRTS_HIP(hipMemcpyAsync(host_x, (tt & 1) ? S->buf1.ptr : S->buf0.ptr, st, hipMemcpyDeviceToHost, s));
+    if (exp2) DRTS_HIP(hipMemcpyAsync(exp2, S->ctl_E.ptr, S->n_rhs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    DRTS_HIP(hipStreamSynchronize(s));
+    if (t) *t = tt;
+    return DRTS_OK;
+}
+
+int drts_state_write(drts_solver_t *S, const void *host_x, const int32_t *exp2, int64_t t)
+{
+    if (!S || !host_x || !exp2) return set_error(DRTS_E_INVALID, "NULL argument");
+    if (t < 0 || t > S->max_steps) return set_error(DRTS_E_RANGE, "t out of range");
+    const Matrix &A = S->A->m;
+    const Model &M = A.model;
+    const int nr = S->n_rhs;
+    const bool f64 = M.value_type == DRTS_F64;
+    std::vector<double> mx((size_t)nr, 0.0), ab((size_t)nr, 0.0);
+    for (int64_t r = 0; r < M.n_states; ++r) {
+        const double a = M.absorb[M.mat_of_voxel[(size_t)(r / kDirs)]];
+        for (int k = 0; k < nr; ++k) {
+            const double v = f64 ? ((const double *)host_x)[r * nr + k] : (double)((const float *)host_x)[r * nr + k];
+            mx[(size_t)k] = std::max(mx[(size_t)k], v);
+            ab[(size_t)k] += a * v;
+        }
+    }
+    std::vector<int64_t> tv((size_t)nr, t);
+    hipStream_t s = S->dev.stream;
+    const size_t st = (size_t)M.n_rows * nr * (f64 ? 8 : 4);
+    DRTS_HIP(hipMemcpyAsync((t & 1) ? S->buf1.ptr : S->buf0.ptr, host_x, st, hipMemcpyHostToDevice, s));
+    DRTS_HIP(hipMemcpyAsync(S->ctl_t.ptr, tv.data(), nr * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    DRTS_HIP(hipMemcpyAsync(S->ctl_E.ptr, exp2, nr * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    DRTS_HIP(hipMemcpyAsync(S->ctl_M.ptr, mx.data(), nr * sizeof(double), hipMemcpyHostToDevice, s));
+    DRTS_HIP(hipMemcpyAsync(S->ctl_abs.ptr, ab.data(), nr * sizeof(double), hipMemcpyHostToDevice, s));
+    DRTS_HIP(hipStreamSynchronize(s));
+    S->t_host = t;
+    return DRTS_OK;
+}
+
+int drts_solver_profile(drts_solver_t *S, int32_t enable)
+{
+    if (!S) return set_error(DRTS_E_INVALID, "solver is NULL");
+    int rc = collect_profile(S);
+    if (rc) return rc;
+    S->profile = enable != 0;
+    S->prof_launches = 0;
+    S->prof_ms = 0.0;
+    return DRTS_OK;
+}
+
+int drts_solver_profile_stats(drts_solver_t *S, int64_t *launches, double *total_ms)
+{
+    if (!S) return set_error(DRTS_E_INVALID, "solver is NULL");
+    int rc = collect_profile(S);
+    if (rc) return rc;
+    if (launches) *launches = S->prof_launches;
+    if (total_ms) *total_ms = S->prof_ms;
+    return DRTS_OK;
+}
+
+void drts_solver_destroy(drts_solver_t *S)
+{
+    if (!S) return;
+    if (S->dev.stream) (void)hipStreamSynchronize(S->dev.stream);
+    drop_graph(S);
+    if (S->cap_stream) (void)hipStreamDestroy(S->cap_stream);
+    for (hipEvent_t e : S->ev_pool) (void)hipEventDestroy(e);
+    delete S;
+}
+
+}  // extern "C"
+
+// ---- uneven batch ------------------------------------------------------------------
+
+namespace {
+
+int batch_launch(drts_batch *B, int64_t n_work, int n_inst, hipStream_t stream)
+{
+    const drts_solver *S0 = B->solvers[0];
+    const int grid = device_cu_count() * 8;
+    hipError_t e = launch_step(B->inst_dev.as<StepInst>(), B->work_dev.as<WorkItem>(), n_work, n_inst, 1, 0,
+                               S0->A->m.rp64 ? 1 : 0, 0, grid, 1, 256, 0, stream);
+    if (e != hipSuccess) return set_error(DRTS_E_HIP, "batch step launch failed: %s", hipGetErrorString(e));
+    e = launch_finalize(B->inst_dev.as<StepInst>(), n_inst, 1, 0, stream);
+    if (e != hipSuccess) return set_error(DRTS_E_HIP, "batch finalize launch failed: %s", hipGetErrorString(e));
+    return DRTS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int drts_batch_create(drts_solver_t *const *solvers, int32_t n, const drts_device_t *dev, drts_batch_t **out)
+{
+    if (!out || !solvers || n < 1) return set_error(DRTS_E_INVALID, "need at least one solver");
+    *out = nullptr;
+    const bool rp64 = solvers[0] && solvers[0]->A->m.rp64;
+    for (int i = 0; i < n; ++i) {
+        const drts_solver *S = solvers[i];
+        if (!S) return set_error(DRTS_E_INVALID, "solver %d is NULL", i);
+        if (S->n_rhs != 1 || S->A->m.model.value_type != DRTS_F32)
+            return set_error(DRTS_E_INVALID, "solver %d: batches take single-rhs FP32 solvers", i);
+        if (S->A->m.rp64 != rp64) return set_error(DRTS_E_INVALID, "solver %d: mixed row-pointer widths", i);
+        for (int j = 0; j < i; ++j)
+            if (solvers[j] == S) return set_error(DRTS_E_INVALID, "solver %d appears twice", i);
+    }
+    drts_batch *B = new (std::nothrow) drts_batch;
+    if (!B) return set_error(DRTS_E_NOMEM, "host allocation failed");
+    B->dev = make_device(dev);
+    B->solvers.assign(solvers, solvers + n);
+    *out = B;
+    return DRTS_OK;
+}
+
+int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const int64_t *n_steps)
+{
+    if (!B || !n_steps) return set_error(DRTS_E_INVALID, "NULL argument");
+    const int n = (int)B->solvers.size();
+    std::vector<int> order;
+    int rc;
+    for (int i = 0; i < n; ++i) {
+        drts_solver *S = B->solvers[i];
+        if (n_steps[i] < 0 || S->t_host + n_steps[i] > S->max_steps)
+            return set_error(DRTS_E_RANGE, "solver %d: steps beyond max_steps", i);
+        if (n_steps[i] == 0) continue;
+        if ((rc = set_sources(S, src ? src[i] : nullptr))) return rc;
+        if ((rc = upload_amplitudes(S, src ? src[i] : nullptr, S->t_host, n_steps[i]))) return rc;
+        order.push_back(i);
+    }
+    if (order.empty()) return DRTS_OK;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n_steps[a] > n_steps[b]; });
+    const int P = (int)order.size();
+    std::vector<StepInst> insts((size_t)P);
+    std::vector<WorkItem> work;
+    std::vector<int64_t> prefix((size_t)P), tend((size_t)P);
+    for (int j = 0; j < P; ++j) {
+        drts_solver *S = B->solvers[(size_t)order[(size_t)j]];
+        insts[(size_t)j] = S->inst_h;
+        for (int64_t c = 0; c < S->n_chunks; ++c) work.push_back({j, (int32_t)c});
+        prefix[(size_t)j] = (int64_t)work.size();
+        tend[(size_t)j] = S->t_host + n_steps[order[(size_t)j]];
+    }
+    Device &dev = B->dev;
+    hipStream_t s = dev.stream;
+    for (int j = 0; j < P; ++j) {
+        drts_solver *S = B->solvers[(size_t)order[(size_t)j]];
+        // every solver's own stream work (uploads) must be done before the batch stream uses it
+        DRTS_HIP(hipStreamSynchronize(S->dev.stream));
+        DRTS_HIP(hipMemcpyAsync(S->t_end.ptr, &tend[(size_t)j], sizeof(int64_t), hipMemcpyHostToDevice, s));
+    }
+    if ((rc = upload_vec(dev, B->inst_dev, insts))) return rc;
+    if ((rc = upload_vec(dev, B->work_dev, work))) return rc;
+    DRTS_HIP(hipStreamSynchronize(s));
+
+    // launches: while step < n of the j-th longest, the first j+1 solvers are active
+    const int K = 25;
+    hipStream_t cap = nullptr;
+    int64_t step = 0;
+    const int64_t n_max = n_steps[order[0]];
+    while (step < n_max) {
+        int active = 0;
+        while (active < P && n_steps[order[(size_t)active]] > step) ++active;
+        const int64_t seg_end = n_steps[order[(size_t)active - 1]];   // active set constant until here
+        const int64_t n_work = prefix[(size_t)active - 1];
+        int64_t len = seg_end - step;
+        if (len >= 2 * K) {
+            if (!cap) DRTS_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+            hipGraph_t g = nullptr;
+            hipGraphExec_t ge = nullptr;
+            DRTS_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+            for (int k = 0; k < K && rc == DRTS_OK; ++k) rc = batch_launch(B, n_work, active, cap);
+            hipError_t e = hipStreamEndCapture(cap, &g);
+            if (rc == DRTS_OK && e != hipSuccess) rc = set_error(DRTS_E_HIP, "capture: %s", hipGetErrorString(e));
+            if (rc == DRTS_OK && hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess)
+                rc = set_error(DRTS_E_HIP, "graph instantiate failed");
+            if (g) (void)hipGraphDestroy(g);
+            for (; rc == DRTS_OK && len >= K; len -= K, step += K)
+                if (hipGraphLaunch(ge, s) != hipSuccess) rc = set_error(DRTS_E_HIP, "graph launch failed");
+            if (ge) {
+                (void)hipStreamSynchronize(s);
+                (void)hipGraphExecDestroy(ge);
+            }
+            if (rc) break;
+        }
+        for (; len > 0; --len, ++step)
+            if ((rc = batch_launch(B, n_work, active, s))) break;
+        if (rc) break;
+    }
+    if (cap) (void)hipStreamDestroy(cap);
+    if (rc) return rc;
+    for (int j = 0; j < P; ++j) {
+        drts_solver *S = B->solvers[(size_t)order[(size_t)j]];
+        S->t_host += n_steps[order[(size_t)j]];
+    }
+    // restore the solvers' own step limit once the batch's work is done
+    DRTS_HIP(hipStreamSynchronize(s));
+    for (int j = 0; j < P; ++j) {
+        drts_solver *S = B->solvers[(size_t)order[(size_t)j]];
+        DRTS_HIP(hipMemcpyAsync(S->t_end.ptr, &S->max_steps, sizeof(int64_t), hipMemcpyHostToDevice, s));
+    }
+    DRTS_HIP(hipStreamSynchronize(s));
+    return DRTS_OK;
+}
+
+void drts_batch_destroy(drts_batch_t *B)
+{
+    if (!B) return;
+    if (B->dev.stream) (void)hipStreamSynchronize(B->dev.stream);
+    delete B;
+}
+
+// ---- autotuning ----------------------------------------------------------------------
+
+static std::string tune_key(const drts_solver *S)
+{
+    const Matrix &A = S->A->m;
+    const int rows_cls = (int)std::lround(std::log2((double)std::max<int64_t>(A.model.n_rows, 1)));
+    const int nnz_row = (int)std::lround((double)A.nnz / std::max<int64_t>(A.model.n_rows, 1));
+    char buf[128];
+    snprintf(buf, sizeof buf, "drts1:rhs%d:f%d:rows2^%d:nnzrow%d:cu%d", S->n_rhs,
+             A.model.value_type == DRTS_F64 ? 64 : 32, rows_cls, nnz_row, device_cu_count());
+    return buf;
+}
+
+int drts_autotune(drts_solver_t *S, const char *cache_path, drts_options_t *chosen)
+{
+    if (!S) return set_error(DRTS_E_INVALID, "solver is NULL");
+    if (S->t_host != 0) return set_error(DRTS_E_STATE, "autotune before the first step");
+    const std::string key = tune_key(S);
+    drts_options_t best = S->opt;
+    if (cache_path) {
+        if (FILE *f = fopen(cache_path, "r")) {
+            char k[128];
+            int r, c, g, x;
+            bool hit = false;
+            while (fscanf(f, "%127s %d %d %d %d", k, &r, &c, &g, &x) == 5) {
+                if (key == k) {
+                    best.rows_per_tile = r;
+                    best.tiles_per_chunk = c;
+                    best.grid = g;
+                    best.xcd_remap = x;
+                    hit = true;
+                }
+            }
+            fclose(f);
+            if (hit && check_options(S, &best) == DRTS_OK) {
+                S->opt = best;
+                int rc = prepare(S);
+                if (!rc && chosen) *chosen = best;
+                return rc;
+            }
+        }
+    }
+    const Matrix &A = S->A->m;
+    hipStream_t s = S->dev.stream;
+    const size_t st = (size_t)A.model.n_rows * S->n_rhs * (A.model.value_type == DRTS_F64 ? 8 : 4);
+    Buffer save;
+    int rc = save.allocate(&S->dev, st);
+    if (rc) return rc;
+    DRTS_HIP(hipMemcpyAsync(save.ptr, S->buf0.ptr, st, hipMemcpyDeviceToDevice, s));
+    const int cus = device_cu_count();
+    std::vector<drts_options_t> cands;
+    const bool spmm = spmm_of(S);
+    const int rows_opts[] = {64, 128, 256};
+    const int chunk_opts[] = {4, 16, 64};
+    const int grid_mult[] = {4, 8, 16};
+    for (int r : rows_opts)
+        for (int c : chunk_opts)
+            for (int g : grid_mult)
+                for (int x = 0; x < 2; ++x) {
+                    drts_options_t o = S->opt;
+                    o.rows_per_tile = r;
+                    o.tiles_per_chunk = spmm ? c * 8 : c;
+                    o.grid = cus * (spmm ? g / 2 : g);
+                    o.xcd_remap = x;
+                    cands.push_back(o);
+                }
+    const int steps = (int)std::min<int64_t>(4, S->max_steps);
+    hipEvent_t e0, e1;
+    DRTS_HIP(hipEventCreate(&e0));
+    DRTS_HIP(hipEventCreate(&e1));
+    const bool prof = S->profile;
+    S->profile = false;
+    float best_ms = INFINITY;
+    const int64_t zero_t[64] = {0};
+    for (const drts_options_t &o : cands) {
+        S->opt = o;
+        if ((rc = prepare(S))) break;
+        DRTS_HIP(hipMemcpyAsync(S->ctl_t.ptr, zero_t, S->n_rhs * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        if ((rc = launch_one(S, s))) break;   // warm-up
+        DRTS_HIP(hipMemcpyAsync(S->ctl_t.ptr, zero_t, S->n_rhs * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        DRTS_HIP(hipEventRecord(e0, s));
+        for (int k = 0; k < steps && !rc; ++k) rc = launch_one(S, s);
+        DRTS_HIP(hipEventRecord(e1, s));
+        DRTS_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        DRTS_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = o;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    S->profile = prof;
+    // restore the state and control words
+    DRTS_HIP(hipMemcpyAsync(S->buf0.ptr, save.ptr, st, hipMemcpyDeviceToDevice, s));
+    {
+        std::vector<int32_t> z32((size_t)S->n_rhs, 0);
+        std::vector<double> zd((size_t)S->n_rhs, 0.0);
+        DRTS_HIP(hipMemcpyAsync(S->ctl_t.ptr, zero_t, S->n_rhs * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        DRTS_HIP(hipMemcpyAsync(S->ctl_E.ptr, z32.data(), S->n_rhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        DRTS_HIP(hipMemcpyAsync(S->ctl_M.ptr, zd.data(), S->n_rhs * sizeof(double), hipMemcpyHostToDevice, s));
+        DRTS_HIP(hipMemcpyAsync(S->ctl_abs.ptr, zd.data(), S->n_rhs * sizeof(double), hipMemcpyHostToDevice, s));
+        DRTS_HIP(hipStreamSynchronize(s));
+    }
+    if (rc) return rc;
+    S->opt = best;
+    if ((rc = prepare(S))) return rc;
+    if (cache_path) {
+        if (FILE *f = fopen(cache_path, "a")) {
+            fprintf(f, "%s %d %d %d %d\n", key.c_str(), best.rows_per_tile, best.tiles_per_chunk, best.grid,
+                    best.xcd_remap);
+            fclose(f);
+        }
+    }
+    if (chosen) *chosen = best;
+    return DRTS_OK;
+}
+
+}  // extern "C"

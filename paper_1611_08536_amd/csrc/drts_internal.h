@@ -1,0 +1,98 @@
+// Internal declarations of the DRTS library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "drts.h"
+
+namespace drts {
+
+constexpr int kDirs = 26;
+
+// ---- lattice ---------------------------------------------------------------
+// Direction d <-> lattice vector: k = 9(dz+1) + 3(dy+1) + (dx+1), d = k - (k>13).
+__host__ __device__ inline int dir_dx(int d) { int k = d + (d >= 13); return k % 3 - 1; }
+__host__ __device__ inline int dir_dy(int d) { int k = d + (d >= 13); return (k / 3) % 3 - 1; }
+__host__ __device__ inline int dir_dz(int d) { int k = d + (d >= 13); return k / 9 - 1; }
+__host__ __device__ inline int dir_of(int dx, int dy, int dz)
+{
+    int k = 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1);
+    return k - (k > 13);
+}
+
+// ---- errors ----------------------------------------------------------------
+int set_error(int code, const char *fmt, ...);
+const char *hip_name(hipError_t e);
+
+#define DRTS_HIP(call)                                                                      \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return ::drts::set_error(DRTS_E_HIP, "%s failed: %s (%s:%d)", #call,            \
+                                     ::drts::hip_name(e_), __FILE__, __LINE__);             \
+    } while (0)
+
+// ---- device memory through the caller's hooks --------------------------------
+struct Device {
+    drts_device_t hooks{};
+    hipStream_t stream = nullptr;
+    void *alloc(size_t bytes);  // nullptr on failure (error message set)
+    void free(void *p);
+};
+
+// Typed device buffer that releases itself through the hooks.
+struct Buffer {
+    Device *dev = nullptr;
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    Buffer() = default;
+    Buffer(const Buffer &) = delete;
+    Buffer &operator=(const Buffer &) = delete;
+    ~Buffer() { reset(); }
+    int allocate(Device *d, size_t n);  // DRTS_OK or DRTS_E_NOMEM
+    void reset();
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+// ---- host model of a medium (coefficient tables, escape and interface lists) ----
+struct Model {
+    int nx = 0, ny = 0, nz = 0;
+    int64_t n_vox = 0, n_states = 0, n_escape = 0, n_rows = 0;
+    double h_mm = 0, dt_s = 0;
+    int bc = DRTS_BC_VACUUM;
+    int value_type = DRTS_F32, rounding = DRTS_ROUND_DITHER;
+    std::vector<drts_material_t> mats;
+    std::vector<uint8_t> mat_of_voxel;      // [n_vox]
+    std::vector<double> blocks;             // [n_mat][26][26] C_q[m][n]
+    std::vector<double> absorb;             // [n_mat] 1 - exp(-mu_a h)
+    std::vector<double> index;              // [n_mat] refractive index
+    std::vector<int64_t> escape_state;      // [n_escape] ascending states (v, m) leaving the grid
+    // moves whose targets are not the plain neighbour: wall reflections and
+    // interface splits, as (target row, source voxel, direction, factor),
+    // sorted by (row, voxel, direction)
+    std::vector<int64_t> irr_row, irr_vox;
+    std::vector<int32_t> irr_dir;
+    std::vector<double> irr_f;
+};
+
+int build_model(const drts_medium_t *m, Model *out);
+
+// ---- assembled matrix ----------------------------------------------------------
+struct Matrix {
+    Device dev;
+    Model model;
+    int64_t nnz = 0;
+    bool rp64 = false;       // int64 row pointers (nnz >= 2^31)
+    Buffer row_ptr, col, val;
+    Buffer mat_of_voxel, absorb, index, blocks64, blocks32;
+    Buffer irr_row, irr_vox, irr_dir, irr_f, irr_bits, escape_state;
+    int64_t bytes() const;
+};
+
+int assemble_on_device(Matrix *A);
+
+}  // namespace drts

@@ -1,0 +1,318 @@
+// Host-side coefficient model of a DRTS medium: per-material direction blocks
+// (FP64), the Fresnel split of every move that crosses an interface, the list
+// of (voxel, direction) pairs leaving through vacuum faces, and the list of
+// moves whose target is not the plain neighbour state.
+//
+// Arithmetic is FP64 with the evaluation order written out in each formula;
+// the device assembly only copies, multiplies by split factors and sums in a
+// fixed order, so the assembled values are reproducible bit for bit.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "drts_internal.h"
+
+namespace drts {
+namespace {
+
+constexpr double kC0 = 299792458.0;  // speed of light in vacuum, m/s
+
+struct Unit {
+    double s[kDirs][3];  // unit vector of every lattice direction
+    Unit()
+    {
+        for (int d = 0; d < kDirs; ++d) {
+            int e0 = dir_dx(d), e1 = dir_dy(d), e2 = dir_dz(d);
+            double len = std::sqrt((double)(e0 * e0 + e1 * e1 + e2 * e2));
+            s[d][0] = (double)e0 / len;
+            s[d][1] = (double)e1 / len;
+            s[d][2] = (double)e2 / len;
+        }
+    }
+};
+const Unit &units()
+{
+    static const Unit u;
+    return u;
+}
+
+inline double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+// Henyey-Greenstein phase value without its 1/(4 pi) (it cancels when normalised).
+inline double phase_hg(double g, double cs)
+{
+    double q = 1.0 + g * g - 2.0 * g * cs;
+    return (1.0 - g * g) / (q * std::sqrt(q));
+}
+
+// C[m][n] = alpha (Ps G[m][n]) off the diagonal, alpha (P0 + Ps G[n][n]) on it,
+// with P0 = exp(-mu_s h), Ps = 1 - P0, alpha = exp(-mu_a h) and
+// G[m][n] = p(cos_mn) / sum_k p(cos_kn) (Eq. (9)-(10), (19), (21)).
+void direction_block(const drts_material_t &q, double h, double *C)
+{
+    const double P0 = std::exp(-q.mu_s * h);
+    const double Ps = 1.0 - P0;
+    const double alpha = std::exp(-q.mu_a * h);
+    double phase[kDirs][kDirs];
+    for (int a = 0; a < kDirs; ++a) {
+        const int ax = dir_dx(a), ay = dir_dy(a), az = dir_dz(a);
+        for (int b = 0; b < kDirs; ++b) {
+            const int bx = dir_dx(b), by = dir_dy(b), bz = dir_dz(b);
+            const int ip = ax * bx + ay * by + az * bz;
+            const int la = ax * ax + ay * ay + az * az, lb = bx * bx + by * by + bz * bz;
+            phase[a][b] = phase_hg(q.g, (double)ip / std::sqrt((double)(la * lb)));
+        }
+    }
+    for (int n = 0; n < kDirs; ++n) {
+        double Z = 0.0;
+        for (int k = 0; k < kDirs; ++k) Z += phase[k][n];
+        for (int m = 0; m < kDirs; ++m) {
+            const double G = phase[m][n] / Z;
+            C[m * kDirs + n] = (m == n) ? alpha * (P0 + Ps * G) : alpha * (Ps * G);
+        }
+    }
+}
+
+// Lattice direction on side `side` of the surface (sign of s_d . N) whose unit
+// vector is closest to `want`; a later candidate must win by more than 1e-12.
+int nearest_direction(const double *want, const double *N, int side)
+{
+    const Unit &U = units();
+    int arg = -1;
+    double best = -INFINITY;
+    for (int d = 0; d < kDirs; ++d) {
+        const double sn = dot3(U.s[d], N);
+        const bool ok = side < 0 ? sn < 0.0 : sn > 0.0;
+        if (!ok) continue;
+        const double v = dot3(U.s[d], want);
+        if (arg < 0 || v > best + 1e-12) {
+            best = v;
+            arg = d;
+        }
+    }
+    return arg;
+}
+
+struct Split {
+    double R, T;
+    int m_refl, m_trans;
+};
+
+// Unpolarised Fresnel split (Sec. 4.2) of direction m going from index n1 to n2
+// through a surface of unit normal N (s_m . N > 0).
+Split fresnel_split(int m, double n1, double n2, const double *N)
+{
+    const double *s = units().s[m];
+    const double ci = dot3(s, N);
+    const double eta = n1 / n2;
+    const double s2t = eta * eta * (1.0 - ci * ci);
+    Split out;
+    double ct;
+    if (s2t >= 1.0) {  // total internal reflection
+        out.R = 1.0;
+        out.T = 0.0;
+        ct = 0.0;
+    } else {
+        ct = std::sqrt(1.0 - s2t);
+        const double rs = (n1 * ci - n2 * ct) / (n1 * ci + n2 * ct);
+        const double rp = (n2 * ci - n1 * ct) / (n2 * ci + n1 * ct);
+        out.R = 0.5 * (rs * rs + rp * rp);
+        out.T = 1.0 - out.R;
+    }
+    double r[3], t[3];
+    for (int i = 0; i < 3; ++i) {
+        r[i] = s[i] - (2.0 * ci) * N[i];
+        t[i] = eta * s[i] + (ct - eta * ci) * N[i];
+    }
+    out.m_refl = nearest_direction(r, N, -1);
+    out.m_trans = out.T > 0.0 ? nearest_direction(t, N, +1) : -1;
+    return out;
+}
+
+// Unit normal of the crossing from voxel (x,y,z) along direction d, pointing
+// from the first voxel into the second.
+void crossing_normal(const drts_geometry_t &g, int x, int y, int z, int d, double *N)
+{
+    const double *s = units().s[d];
+    const int ex = dir_dx(d), ey = dir_dy(d), ez = dir_dz(d);
+    if (g.kind == DRTS_GEOM_LAYERS_Z && ez != 0) {
+        N[0] = 0.0;
+        N[1] = 0.0;
+        N[2] = ez > 0 ? 1.0 : -1.0;
+        return;
+    }
+    if (g.kind == DRTS_GEOM_SPHERE) {
+        // radial direction at the midpoint of the two voxel centres
+        const double px = (double)x + 0.5 + 0.5 * (double)ex;
+        const double py = (double)y + 0.5 + 0.5 * (double)ey;
+        const double pz = (double)z + 0.5 + 0.5 * (double)ez;
+        const double w[3] = {px - g.sphere_c[0], py - g.sphere_c[1], pz - g.sphere_c[2]};
+        const double len = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+        if (len > 0.0) {
+            N[0] = w[0] / len;
+            N[1] = w[1] / len;
+            N[2] = w[2] / len;
+            if (dot3(s, N) < 0.0) {
+                N[0] = -N[0];
+                N[1] = -N[1];
+                N[2] = -N[2];
+            }
+            return;
+        }
+    }
+    N[0] = s[0];
+    N[1] = s[1];
+    N[2] = s[2];
+}
+
+struct IrrMove {
+    int64_t row, vox;
+    int32_t dir;
+    double f;
+    bool operator<(const IrrMove &o) const
+    {
+        if (row != o.row) return row < o.row;
+        if (vox != o.vox) return vox < o.vox;
+        return dir < o.dir;
+    }
+};
+
+}  // namespace
+
+int build_model(const drts_medium_t *m, Model *M)
+{
+    if (!m) return set_error(DRTS_E_INVALID, "medium is NULL");
+    const drts_grid_t &g = m->grid;
+    if (g.nx < 1 || g.ny < 1 || g.nz < 1) return set_error(DRTS_E_INVALID, "grid must be at least 1x1x1");
+    if (!(g.h_mm > 0.0) || !std::isfinite(g.h_mm)) return set_error(DRTS_E_INVALID, "h_mm must be positive");
+    if (m->n_mat < 1 || m->n_mat > 255 || !m->mat)
+        return set_error(DRTS_E_INVALID, "need 1..255 materials");
+    if (m->bc != DRTS_BC_VACUUM && m->bc != DRTS_BC_REFLECT) return set_error(DRTS_E_INVALID, "bad bc %d", m->bc);
+    if (m->value_type != DRTS_F64 && m->value_type != DRTS_F32)
+        return set_error(DRTS_E_INVALID, "bad value_type %d", m->value_type);
+    if (m->rounding != DRTS_ROUND_NEAREST && m->rounding != DRTS_ROUND_DITHER)
+        return set_error(DRTS_E_INVALID, "bad rounding %d", m->rounding);
+    if (m->geom.kind < DRTS_GEOM_VOXELS || m->geom.kind > DRTS_GEOM_SPHERE)
+        return set_error(DRTS_E_INVALID, "bad geometry kind %d", m->geom.kind);
+    if (!(m->n_ref > 0.0)) return set_error(DRTS_E_INVALID, "n_ref must be positive");
+    for (int q = 0; q < m->n_mat; ++q) {
+        const drts_material_t &mt = m->mat[q];
+        if (!(mt.mu_s >= 0.0) || !(mt.mu_a >= 0.0) || !(mt.g > -1.0 && mt.g < 1.0) || !(mt.n > 0.0) ||
+            !std::isfinite(mt.mu_s) || !std::isfinite(mt.mu_a))
+            return set_error(DRTS_E_INVALID, "material %d out of range", q);
+    }
+    const int64_t V = (int64_t)g.nx * g.ny * g.nz;
+    if (V * kDirs > (int64_t)INT32_MAX - 1)
+        return set_error(DRTS_E_RANGE, "%lld states exceed the int32 column range", (long long)(V * kDirs));
+
+    M->nx = g.nx;
+    M->ny = g.ny;
+    M->nz = g.nz;
+    M->n_vox = V;
+    M->n_states = V * kDirs;
+    M->h_mm = g.h_mm;
+    M->dt_s = g.h_mm * 1e-3 * m->n_ref / kC0;
+    M->bc = m->bc;
+    M->value_type = m->value_type;
+    M->rounding = m->rounding;
+    M->mats.assign(m->mat, m->mat + m->n_mat);
+
+    // material map
+    M->mat_of_voxel.resize(V);
+    if (m->mat_of_voxel) {
+        for (int64_t v = 0; v < V; ++v) {
+            if (m->mat_of_voxel[v] >= m->n_mat)
+                return set_error(DRTS_E_INVALID, "voxel %lld uses material %d of %d", (long long)v,
+                                 (int)m->mat_of_voxel[v], m->n_mat);
+            M->mat_of_voxel[v] = m->mat_of_voxel[v];
+        }
+    } else if (m->geom.kind == DRTS_GEOM_LAYERS_Z) {
+        if (m->geom.n_layers < 1 || !m->geom.layer_z0 || m->geom.layer_z0[0] != 0 ||
+            m->geom.n_layers > m->n_mat)
+            return set_error(DRTS_E_INVALID, "layers need layer_z0[0] == 0 and n_layers <= n_mat");
+        for (int i = 1; i < m->geom.n_layers; ++i)
+            if (m->geom.layer_z0[i] <= m->geom.layer_z0[i - 1])
+                return set_error(DRTS_E_INVALID, "layer_z0 must ascend");
+        for (int z = 0; z < g.nz; ++z) {
+            int layer = 0;
+            while (layer + 1 < m->geom.n_layers && z >= m->geom.layer_z0[layer + 1]) ++layer;
+            std::fill(M->mat_of_voxel.begin() + (int64_t)z * g.nx * g.ny,
+                      M->mat_of_voxel.begin() + (int64_t)(z + 1) * g.nx * g.ny, (uint8_t)layer);
+        }
+    } else if (m->geom.kind == DRTS_GEOM_SPHERE) {
+        if (m->n_mat < 2) return set_error(DRTS_E_INVALID, "a sphere needs materials 0 and 1");
+        const double r2 = m->geom.sphere_r * m->geom.sphere_r;
+        for (int64_t v = 0; v < V; ++v) {
+            const double x = (double)(v % g.nx) + 0.5 - m->geom.sphere_c[0];
+            const double y = (double)((v / g.nx) % g.ny) + 0.5 - m->geom.sphere_c[1];
+            const double z = (double)(v / ((int64_t)g.nx * g.ny)) + 0.5 - m->geom.sphere_c[2];
+            M->mat_of_voxel[v] = (x * x + y * y + z * z <= r2) ? 1 : 0;
+        }
+    } else {
+        std::fill(M->mat_of_voxel.begin(), M->mat_of_voxel.end(), (uint8_t)0);
+    }
+
+    // per-material tables
+    M->blocks.resize((size_t)m->n_mat * kDirs * kDirs);
+    M->absorb.resize(m->n_mat);
+    M->index.resize(m->n_mat);
+    for (int q = 0; q < m->n_mat; ++q) {
+        direction_block(m->mat[q], g.h_mm, &M->blocks[(size_t)q * kDirs * kDirs]);
+        M->absorb[q] = -std::expm1(-m->mat[q].mu_a * g.h_mm);
+        M->index[q] = m->mat[q].n;
+    }
+
+    // escape list and irregular moves
+    M->escape_state.clear();
+    std::vector<IrrMove> irr;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const int64_t v = x + (int64_t)nx * (y + (int64_t)ny * z);
+                const bool face = x == 0 || y == 0 || z == 0 || x == nx - 1 || y == ny - 1 || z == nz - 1;
+                const double n1 = M->index[M->mat_of_voxel[v]];
+                for (int d = 0; d < kDirs; ++d) {
+                    const int tx = x + dir_dx(d), ty = y + dir_dy(d), tz = z + dir_dz(d);
+                    const bool in = tx >= 0 && tx < nx && ty >= 0 && ty < ny && tz >= 0 && tz < nz;
+                    if (!in) {
+                        if (!face) continue;
+                        if (m->bc == DRTS_BC_VACUUM) {
+                            M->escape_state.push_back(kDirs * v + d);
+                        } else {
+                            const int rx = (tx < 0 || tx >= nx) ? -dir_dx(d) : dir_dx(d);
+                            const int ry = (ty < 0 || ty >= ny) ? -dir_dy(d) : dir_dy(d);
+                            const int rz = (tz < 0 || tz >= nz) ? -dir_dz(d) : dir_dz(d);
+                            irr.push_back({kDirs * v + dir_of(rx, ry, rz), v, d, 1.0});
+                        }
+                        continue;
+                    }
+                    const int64_t u = tx + (int64_t)nx * (ty + (int64_t)ny * tz);
+                    const double n2 = M->index[M->mat_of_voxel[u]];
+                    if (n1 == n2) continue;
+                    double N[3];
+                    crossing_normal(m->geom, x, y, z, d, N);
+                    const Split sp = fresnel_split(d, n1, n2, N);
+                    irr.push_back({kDirs * v + sp.m_refl, v, d, sp.R});
+                    if (sp.T > 0.0) irr.push_back({kDirs * u + sp.m_trans, v, d, sp.T});
+                }
+            }
+    M->n_escape = (int64_t)M->escape_state.size();
+    M->n_rows = M->n_states + M->n_escape;
+    std::sort(irr.begin(), irr.end());
+    const size_t ni = irr.size();
+    M->irr_row.resize(ni);
+    M->irr_vox.resize(ni);
+    M->irr_dir.resize(ni);
+    M->irr_f.resize(ni);
+    for (size_t i = 0; i < ni; ++i) {
+        M->irr_row[i] = irr[i].row;
+        M->irr_vox[i] = irr[i].vox;
+        M->irr_dir[i] = irr[i].dir;
+        M->irr_f[i] = irr[i].f;
+    }
+    return DRTS_OK;
+}
+
+}  // namespace drts

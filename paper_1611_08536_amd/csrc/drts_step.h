@@ -1,0 +1,97 @@
+// Device-side descriptors of the DRTS time step (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace drts {
+
+// Slots of the per-chunk FP64 partials, each [n_rhs] wide.
+enum : int { kSlotN = 0, kSlotEsc = 1, kSlotAbs = 2, kSlotMax = 3, kSlotDet = 4 };
+
+// Everything the step and finalize kernels need of one solver.  Lives in
+// device memory; the kernels read it with uniform (scalar) loads.
+struct StepInst {
+    // matrix [A; L]
+    const void *row_ptr;
+    const int32_t *col;
+    const void *val;
+    int64_t n_rows, n_states;
+    int32_t rp64;
+    int32_t rows_per_tile;
+    int64_t n_tiles;
+    int32_t tiles_per_chunk;
+    int32_t n_rhs;
+    // state: x_t lives in buf[t & 1], the step writes buf[(t + 1) & 1];
+    // layout [n_rows][n_rhs]
+    void *buf0, *buf1;
+    const uint8_t *mat;     // material of every voxel
+    const double *absorb;   // per material: 1 - exp(-mu_a h)
+    // sources, entries sorted by row then rhs; src_tile[k] = first entry of tile k
+    const int32_t *src_tile;
+    const int64_t *src_row;
+    const int32_t *src_id;
+    const int32_t *src_rhs;
+    const double *src_w;
+    const double *amp;      // [max_steps][n_src]
+    const double *smax;     // [max_steps][n_rhs] bound of |s_t| per rhs
+    int32_t n_src;
+    // detectors, entries sorted by tile then row; det_tile[k] = first entry of tile k
+    int32_t n_det;
+    const int32_t *det_tile;
+    const int64_t *det_row;
+    const int32_t *det_id;
+    const double *det_F;
+    // control, one per rhs
+    int64_t *t;             // [n_rhs] steps done
+    int32_t *E;             // [n_rhs] exponent of x_t
+    double *M;              // [n_rhs] max of the scaled state x_t
+    double *abs_cur;        // [n_rhs] absorbed during step t (from x_t), scaled by 2^-E
+    const int64_t *t_end;   // steps are skipped once t >= *t_end
+    int32_t rescale;
+    int32_t pad0;
+    int64_t max_steps;
+    // partials [slot * n_rhs + rhs][n_chunks]
+    double *partials;
+    int64_t n_chunks;
+    // series
+    double *ser_tot;        // [max_steps][3][n_rhs]: N(t+1), escaped(t), absorbed(t)
+    double *ser_det;        // [max_steps][n_det][n_rhs]
+    int32_t *ser_exp;       // [max_steps][n_rhs]: exponent E_{t+1} of the above
+    int32_t *ser_abs_exp;   // [max_steps][n_rhs]: exponent E_t of absorbed(t)
+};
+
+// One unit of work of a launch: chunk `chunk` of instance `inst`.
+struct WorkItem {
+    int32_t inst;
+    int32_t chunk;
+};
+
+// Launches the SpMV (n_rhs == 1) or SpMM step over a work list, followed by
+// the finalize kernel.  Returns a hipError_t.
+hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int64_t n_work, int n_inst,
+                       int n_rhs_max, int value_f64, int rp64, int spmm, int grid, int xcd_remap,
+                       int rows_per_tile, int n_det_max, hipStream_t stream);
+hipError_t launch_finalize(const StepInst *insts_dev, int n_inst, int n_rhs_max, int n_det_max,
+                           hipStream_t stream);
+
+// Matrix-free step over the per-voxel direction blocks (single rhs, FP32).
+struct StructArgs {
+    int nx, ny, nz;
+    int64_t n_states, n_rows;
+    const uint8_t *mat;
+    const double *index;
+    const float *blocks;       // [q][m][n]
+    int32_t n_mat;
+    const int64_t *irr_row, *irr_vox;
+    const int32_t *irr_dir;
+    const double *irr_f;
+    const uint32_t *irr_bits;
+    int64_t n_irr;
+    const int64_t *escape_state;
+};
+hipError_t launch_structured(const StructArgs &sa, const StepInst *insts_dev, const WorkItem *work_dev,
+                             int64_t n_work, int grid, int xcd_remap, int rows_per_tile, hipStream_t stream);
+
+}  // namespace drts

@@ -1,0 +1,424 @@
+"""ctypes binding of libdrts.so (the C ABI in include/drts.h).
+
+Argument marshalling only: every step of the hot path runs in the library's
+HIP kernels.  PyTorch provides device memory (its caching allocator, through
+the drts_device_t hooks) and the stream (torch's current stream).  The module
+raises ImportError when the built library is missing: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libdrts.so")
+
+F64, F32 = 0, 1
+ROUND_NEAREST, ROUND_DITHER = 0, 1
+GEOM = {"voxels": 0, "homog": 0, "layers_z": 1, "sphere": 2}
+BC = {"vacuum": 0, "reflect": 1}
+KERNEL_CSR, KERNEL_STRUCTURED = 0, 1
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libdrts.so is not built (run paper_1611_08536_amd._build.build())")
+_lib = C.CDLL(LIB_PATH)
+
+P = C.c_void_p
+i32, i64, dbl = C.c_int32, C.c_int64, C.c_double
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", i32), ("ny", i32), ("nz", i32), ("h_mm", dbl)]
+
+
+class MaterialT(C.Structure):
+    _fields_ = [("mu_s", dbl), ("mu_a", dbl), ("g", dbl), ("n", dbl)]
+
+
+class Geometry(C.Structure):
+    _fields_ = [("kind", i32), ("sphere_c", dbl * 3), ("sphere_r", dbl), ("n_layers", i32),
+                ("layer_z0", C.POINTER(i32))]
+
+
+class MediumT(C.Structure):
+    _fields_ = [("grid", Grid), ("n_mat", i32), ("mat", C.POINTER(MaterialT)),
+                ("mat_of_voxel", C.POINTER(C.c_uint8)), ("geom", Geometry), ("bc", i32),
+                ("value_type", i32), ("rounding", i32), ("n_ref", dbl)]
+
+
+ALLOC_FN = C.CFUNCTYPE(P, P, C.c_size_t, P)
+FREE_FN = C.CFUNCTYPE(None, P, P, P)
+
+
+class DeviceT(C.Structure):
+    _fields_ = [("ctx", P), ("alloc", ALLOC_FN), ("free", FREE_FN), ("stream", P)]
+
+
+SUPPORT_FN = C.CFUNCTYPE(i64, P, i32, C.POINTER(i64), C.POINTER(dbl), i64)
+AMP_FN = C.CFUNCTYPE(dbl, P, i32, i64, dbl, dbl)
+RHS_FN = C.CFUNCTYPE(i32, P, i32)
+
+
+class SourceTableT(C.Structure):
+    _fields_ = [("ctx", P), ("n_src", i32), ("support", SUPPORT_FN), ("amplitude", AMP_FN),
+                ("rhs_of", RHS_FN)]
+
+
+class DetectorsT(C.Structure):
+    _fields_ = [("n_det", i32), ("det_ptr", C.POINTER(i64)), ("state", C.POINTER(i64)),
+                ("escape", C.POINTER(C.c_uint8)), ("F", C.POINTER(dbl))]
+
+
+class OptionsT(C.Structure):
+    _fields_ = [("kernel", i32), ("rows_per_tile", i32), ("tiles_per_chunk", i32), ("grid", i32),
+                ("xcd_remap", i32), ("graph_steps", i32), ("rescale", i32)]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_sig("drts_last_error", C.c_char_p, [])
+_sig("drts_build_matrix", C.c_int, [C.POINTER(MediumT), C.POINTER(DeviceT), C.POINTER(P)])
+_sig("drts_matrix_info", C.c_int, [P, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64),
+                                   C.POINTER(dbl)])
+_sig("drts_matrix_row_of", i64, [P, i64, i32])
+_sig("drts_matrix_export_rows", C.c_int, [P, i64, i64, P, P, P])
+_sig("drts_matrix_destroy", None, [P])
+_sig("drts_solver_create", C.c_int, [P, i32, C.POINTER(DetectorsT), i64, C.POINTER(DeviceT), C.POINTER(P)])
+_sig("drts_solver_get_options", C.c_int, [P, C.POINTER(OptionsT)])
+_sig("drts_solver_set_options", C.c_int, [P, C.POINTER(OptionsT)])
+_sig("drts_step", C.c_int, [P, C.POINTER(SourceTableT)])
+_sig("drts_run", C.c_int, [P, C.POINTER(SourceTableT), i64])
+_sig("drts_solver_time", C.c_int, [P, C.POINTER(i64)])
+_sig("drts_detector_readout", C.c_int, [P, i64, i64, P, P, P])
+_sig("drts_state_read", C.c_int, [P, P, P, C.POINTER(i64)])
+_sig("drts_state_write", C.c_int, [P, P, P, i64])
+_sig("drts_solver_profile", C.c_int, [P, i32])
+_sig("drts_solver_profile_stats", C.c_int, [P, C.POINTER(i64), C.POINTER(dbl)])
+_sig("drts_solver_destroy", None, [P])
+_sig("drts_batch_create", C.c_int, [C.POINTER(P), i32, C.POINTER(DeviceT), C.POINTER(P)])
+_sig("drts_batch_run", C.c_int, [P, C.POINTER(C.POINTER(SourceTableT)), C.POINTER(i64)])
+_sig("drts_batch_destroy", None, [P])
+_sig("drts_autotune", C.c_int, [P, C.c_char_p, C.POINTER(OptionsT)])
+
+EXPORTED = [
+    "drts_build_matrix", "drts_matrix_info", "drts_matrix_row_of", "drts_matrix_export_rows",
+    "drts_matrix_destroy", "drts_solver_create", "drts_solver_get_options", "drts_solver_set_options",
+    "drts_step", "drts_run", "drts_solver_time", "drts_detector_readout", "drts_state_read",
+    "drts_state_write", "drts_solver_profile", "drts_solver_profile_stats", "drts_solver_destroy",
+    "drts_batch_create", "drts_batch_run", "drts_batch_destroy", "drts_autotune", "drts_last_error",
+]
+
+
+class DrtsError(RuntimeError):
+    def __init__(self, rc, where):
+        msg = _lib.drts_last_error().decode(errors="replace")
+        super().__init__("%s failed (%d): %s" % (where, rc, msg))
+        self.rc = rc
+
+
+def _check(rc, where):
+    if rc != 0:
+        raise DrtsError(rc, where)
+
+
+# ---- device hooks over torch ------------------------------------------------
+
+class TorchDevice:
+    """drts_device_t backed by torch's caching allocator and current stream."""
+
+    def __init__(self, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the DRTS library needs an MI355X")
+        self._torch = torch
+        self.device = torch.cuda.current_device()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        sp = self.stream.cuda_stream
+
+        def _alloc(ctx, size, stream):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(size), self.device, sp)
+            except Exception:
+                return None
+
+        def _free(ctx, ptr, stream):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self._alloc = ALLOC_FN(_alloc)
+        self._free = FREE_FN(_free)
+        self.c = DeviceT(None, self._alloc, self._free, sp)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+
+_default_device = None
+
+
+def default_device() -> TorchDevice:
+    global _default_device
+    if _default_device is None:
+        _default_device = TorchDevice()
+    return _default_device
+
+
+# ---- state layout of the library ---------------------------------------------
+
+def state_index(medium, vox, dirs) -> np.ndarray:
+    """State 26 v + d of voxels (x, y, z) and lattice vectors (dx, dy, dz), with
+    v = x + nx (y + ny z) and d = k - (k > 13), k = 9(dz+1) + 3(dy+1) + (dx+1)."""
+    vox = np.asarray(vox, dtype=np.int64).reshape(-1, 3)
+    dirs = np.asarray(dirs, dtype=np.int64).reshape(-1, 3)
+    k = 9 * (dirs[:, 2] + 1) + 3 * (dirs[:, 1] + 1) + (dirs[:, 0] + 1)
+    d = k - (k > 13)
+    v = vox[:, 0] + medium.nx * (vox[:, 1] + medium.ny * vox[:, 2])
+    return 26 * v + d
+
+
+# ---- matrix ---------------------------------------------------------------------
+
+class Matrix:
+    """[A; L] of one medium, assembled on the device (drts_build_matrix)."""
+
+    def __init__(self, medium, value_type: str = "f32", rounding: str = "dither",
+                 n_ref: Optional[float] = None, device: Optional[TorchDevice] = None,
+                 use_map: bool = True):
+        self.device = device or default_device()
+        self.medium = medium
+        mats = (MaterialT * len(medium.materials))(
+            *[MaterialT(m.mu_s, m.mu_a, m.g, m.n) for m in medium.materials])
+        self._map = np.ascontiguousarray(medium.mat_of_voxel, dtype=np.uint8).reshape(-1)
+        z0 = np.ascontiguousarray(medium.layer_z0 or (0,), dtype=np.int32)
+        geom = Geometry()
+        geom.kind = GEOM[medium.geom]
+        geom.sphere_c = (dbl * 3)(*(medium.sphere_c or (0.0, 0.0, 0.0)))
+        geom.sphere_r = medium.sphere_r or 0.0
+        geom.n_layers = len(medium.layer_z0)
+        geom.layer_z0 = z0.ctypes.data_as(C.POINTER(i32))
+        m = MediumT()
+        m.grid = Grid(medium.nx, medium.ny, medium.nz, medium.h_mm)
+        m.n_mat = len(medium.materials)
+        m.mat = mats
+        m.mat_of_voxel = self._map.ctypes.data_as(C.POINTER(C.c_uint8)) if use_map else None
+        m.geom = geom
+        m.bc = BC[medium.bc]
+        m.value_type = F64 if value_type == "f64" else F32
+        m.rounding = ROUND_DITHER if rounding == "dither" else ROUND_NEAREST
+        m.n_ref = n_ref if n_ref is not None else medium.materials[0].n
+        self.value_type = value_type
+        h = P()
+        _check(_lib.drts_build_matrix(C.byref(m), C.byref(self.device.c), C.byref(h)), "drts_build_matrix")
+        self._h = h
+        a, b, c, d = i64(), i64(), i64(), i64()
+        dt = dbl()
+        _check(_lib.drts_matrix_info(h, C.byref(a), C.byref(b), C.byref(c), C.byref(d), C.byref(dt)),
+               "drts_matrix_info")
+        self.n_states, self.n_escape, self.nnz, self.bytes, self.dt = a.value, b.value, c.value, d.value, dt.value
+        self.n_rows = self.n_states + self.n_escape
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.drts_matrix_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def row_of(self, state: int, escape: bool) -> int:
+        return _lib.drts_matrix_row_of(self._h, int(state), 1 if escape else 0)
+
+    def export_rows(self, row0: int = 0, n_rows: Optional[int] = None):
+        n_rows = self.n_rows - row0 if n_rows is None else n_rows
+        rp = np.empty(n_rows + 1, dtype=np.int64)
+        _check(_lib.drts_matrix_export_rows(self._h, row0, n_rows, rp.ctypes.data, None, None), "export_rows")
+        n = int(rp[-1] - rp[0])
+        col = np.empty(n, dtype=np.int32)
+        val = np.empty(n, dtype=np.float64 if self.value_type == "f64" else np.float32)
+        _check(_lib.drts_matrix_export_rows(self._h, row0, n_rows, rp.ctypes.data, col.ctypes.data,
+                                            val.ctypes.data), "export_rows")
+        return rp, col, val
+
+
+# ---- sources --------------------------------------------------------------------
+
+class SourceTable:
+    """drts_source_table_t over a list of workloads.Source (support and pulse shape)."""
+
+    def __init__(self, medium, sources, amplitude_fn):
+        self.medium = medium
+        self.sources = list(sources)
+        self._support = [(state_index(medium, s.vox, s.dirs), np.asarray(s.w, dtype=np.float64))
+                         for s in self.sources]
+        self._amp = amplitude_fn
+
+        def support(ctx, src, state, w, cap):
+            st, ww = self._support[src]
+            n = st.size
+            if n <= cap:
+                C.memmove(state, st.ctypes.data, n * 8)
+                C.memmove(w, ww.ctypes.data, n * 8)
+            return n
+
+        def amplitude(ctx, src, step, t0, dt):
+            return float(self._amp(self.sources[src], int(step), dt))
+
+        def rhs_of(ctx, src):
+            return int(self.sources[src].rhs)
+
+        self._cb = (SUPPORT_FN(support), AMP_FN(amplitude), RHS_FN(rhs_of))
+        self.c = SourceTableT(None, len(self.sources), *self._cb)
+
+
+# ---- solver ---------------------------------------------------------------------
+
+class Solver:
+    """Time stepping of one matrix for n_rhs right-hand sides (drts_solver_*)."""
+
+    def __init__(self, matrix: Matrix, n_rhs: int = 1, detectors: Sequence = (), max_steps: int = 1000,
+                 device: Optional[TorchDevice] = None):
+        self.A = matrix
+        self.device = device or matrix.device
+        self.n_rhs = n_rhs
+        self.max_steps = max_steps
+        self.n_det = len(detectors)
+        dt = None
+        if detectors:
+            ptr, st, esc, F = [0], [], [], []
+            for d in detectors:
+                s = state_index(matrix.medium, d.vox, d.dirs)
+                st.append(s)
+                esc.append(np.asarray(d.escape, dtype=np.uint8).reshape(-1))
+                F.append(np.asarray(d.F, dtype=np.float64).reshape(-1))
+                ptr.append(ptr[-1] + s.size)
+            self._det = (np.asarray(ptr, dtype=np.int64), np.concatenate(st), np.concatenate(esc),
+                         np.concatenate(F))
+            dt = DetectorsT(len(detectors), self._det[0].ctypes.data_as(C.POINTER(i64)),
+                            self._det[1].ctypes.data_as(C.POINTER(i64)),
+                            self._det[2].ctypes.data_as(C.POINTER(C.c_uint8)),
+                            self._det[3].ctypes.data_as(C.POINTER(dbl)))
+        h = P()
+        _check(_lib.drts_solver_create(matrix._h, n_rhs, C.byref(dt) if dt is not None else None, max_steps,
+                                       C.byref(self.device.c), C.byref(h)), "drts_solver_create")
+        self._h = h
+        self._tables = []
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.drts_solver_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def options(self) -> dict:
+        o = OptionsT()
+        _check(_lib.drts_solver_get_options(self._h, C.byref(o)), "get_options")
+        return {k: getattr(o, k) for k, _ in OptionsT._fields_}
+
+    def set_options(self, **kw):
+        cur = self.options
+        cur.update(kw)
+        o = OptionsT(**cur)
+        _check(_lib.drts_solver_set_options(self._h, C.byref(o)), "set_options")
+
+    def _table(self, sources: Optional[SourceTable]):
+        if sources is None:
+            return None
+        if sources not in self._tables:
+            self._tables.append(sources)
+        return C.byref(sources.c)
+
+    def step(self, sources: Optional[SourceTable] = None):
+        _check(_lib.drts_step(self._h, self._table(sources)), "drts_step")
+
+    def run(self, sources: Optional[SourceTable], n_steps: int):
+        _check(_lib.drts_run(self._h, self._table(sources), int(n_steps)), "drts_run")
+
+    def time(self) -> int:
+        t = i64()
+        _check(_lib.drts_solver_time(self._h, C.byref(t)), "drts_solver_time")
+        return t.value
+
+    def readout(self, first: int = 0, count: Optional[int] = None) -> dict:
+        count = self.time() - first if count is None else count
+        nr, nd = self.n_rhs, self.n_det
+        ser = np.zeros((count, max(nd, 1), nr))
+        e = np.zeros((count, nr), dtype=np.int32)
+        tot = np.zeros((count, 3, nr))
+        _check(_lib.drts_detector_readout(self._h, first, count, ser.ctypes.data, e.ctypes.data, tot.ctypes.data),
+               "drts_detector_readout")
+        return {"det": ser[:, :nd, :], "exp2": e, "tot": tot}
+
+    def state(self):
+        dtype = np.float64 if self.A.value_type == "f64" else np.float32
+        x = np.empty((self.A.n_rows, self.n_rhs), dtype=dtype)
+        e = np.zeros(self.n_rhs, dtype=np.int32)
+        t = i64()
+        _check(_lib.drts_state_read(self._h, x.ctypes.data, e.ctypes.data, C.byref(t)), "drts_state_read")
+        return x, e, t.value
+
+    def set_state(self, x, exp2, t: int):
+        dtype = np.float64 if self.A.value_type == "f64" else np.float32
+        x = np.ascontiguousarray(x, dtype=dtype).reshape(self.A.n_rows, self.n_rhs)
+        e = np.ascontiguousarray(exp2, dtype=np.int32).reshape(self.n_rhs)
+        _check(_lib.drts_state_write(self._h, x.ctypes.data, e.ctypes.data, int(t)), "drts_state_write")
+
+    def profile(self, enable: bool = True):
+        _check(_lib.drts_solver_profile(self._h, 1 if enable else 0), "drts_solver_profile")
+
+    def profile_stats(self):
+        n, ms = i64(), dbl()
+        _check(_lib.drts_solver_profile_stats(self._h, C.byref(n), C.byref(ms)), "profile_stats")
+        return n.value, ms.value
+
+    def autotune(self, cache_path: Optional[str] = None) -> dict:
+        o = OptionsT()
+        _check(_lib.drts_autotune(self._h, cache_path.encode() if cache_path else None, C.byref(o)),
+               "drts_autotune")
+        return {k: getattr(o, k) for k, _ in OptionsT._fields_}
+
+
+class Batch:
+    """Uneven batch of single-rhs FP32 solvers advanced by one launch per step."""
+
+    def __init__(self, solvers: List[Solver], device: Optional[TorchDevice] = None):
+        self.solvers = list(solvers)
+        self.device = device or solvers[0].device
+        arr = (P * len(solvers))(*[s._h for s in solvers])
+        h = P()
+        _check(_lib.drts_batch_create(arr, len(solvers), C.byref(self.device.c), C.byref(h)), "drts_batch_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.drts_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, tables: Sequence[Optional[SourceTable]], n_steps: Sequence[int]):
+        n = len(self.solvers)
+        ptrs = (C.POINTER(SourceTableT) * n)(
+            *[C.pointer(t.c) if t is not None else C.POINTER(SourceTableT)() for t in tables])
+        self._keep = tables
+        steps = np.ascontiguousarray(n_steps, dtype=np.int64)
+        _check(_lib.drts_batch_run(self._h, ptrs, steps.ctypes.data_as(C.POINTER(i64))), "drts_batch_run")
