@@ -23,6 +23,20 @@ FLAGS = [
 ]
 
 
+def torch_hip_lib_dir() -> str:
+    """Directory of the HIP runtime that PyTorch loads.  The library links that
+    same runtime so that torch's allocator, streams and events and the DRTS
+    kernels live in one HIP runtime instance."""
+    import importlib.util
+    spec = importlib.util.find_spec("torch")
+    if spec is None or not spec.origin:
+        raise RuntimeError("PyTorch (ROCm) is required to build libdrts.so")
+    d = os.path.join(os.path.dirname(spec.origin), "lib")
+    if not os.path.exists(os.path.join(d, "libamdhip64.so")):
+        raise RuntimeError("no libamdhip64.so next to torch in %s" % d)
+    return d
+
+
 def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
@@ -44,7 +58,12 @@ def build(force: bool = True, jobs: int = 4) -> str:
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp%d" % os.getpid()
-    subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs])
+    tlib = torch_hip_lib_dir()
+    clang = os.path.join(os.path.dirname(os.path.realpath(HIPCC)), "..", "lib", "llvm", "bin", "clang++")
+    if not os.path.exists(clang):
+        clang = "/opt/rocm/lib/llvm/bin/clang++"
+    subprocess.check_call([clang, "-shared", "-fPIC", "-o", tmp, *objs, "-L" + tlib, "-l:libamdhip64.so",
+                           "-Wl,-rpath," + tlib, "-Wl,--no-undefined", "-Wl,--as-needed"])
     os.replace(tmp, LIB)
     return LIB
 

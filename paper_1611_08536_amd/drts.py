@@ -24,7 +24,30 @@ KERNEL_CSR, KERNEL_STRUCTURED = 0, 1
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libdrts.so is not built (run paper_1611_08536_amd._build.build())")
+
+# torch's HIP runtime must be the one libdrts.so binds to: torch ships it as
+# libamdhip64.so with the soname libamdhip64.so.7, so once torch is loaded the
+# library's dependency resolves to that same copy.  Loading libdrts.so first
+# would map a second HIP runtime from /opt/rocm, and torch's streams, events
+# and allocations would then belong to a different runtime than the kernels.
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
+
+
+def _hip_runtimes():
+    paths = set()
+    with open("/proc/self/maps") as f:
+        for line in f:
+            p = line.split()[-1] if line.strip() else ""
+            if "libamdhip64" in p:
+                paths.add(os.path.realpath(p))
+    return sorted(paths)
+
+
+if len(_hip_runtimes()) > 1:
+    raise ImportError("two HIP runtimes are mapped (%s); import torch before loading libdrts.so"
+                      % ", ".join(_hip_runtimes()))
 
 P = C.c_void_p
 i32, i64, dbl = C.c_int32, C.c_int64, C.c_double

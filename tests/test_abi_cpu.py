@@ -21,6 +21,7 @@ def declared_functions():
 
 @pytest.fixture(scope="module")
 def lib():
+    import torch  # noqa: F401  (the library binds to torch's HIP runtime)
     if not os.path.exists(LIB):
         from paper_1611_08536_amd import _build
         _build.build()
@@ -66,3 +67,9 @@ def test_invalid_arguments_fail_without_a_gpu(lib):
     assert drts._lib.drts_solver_create(None, 1, None, 10, None, ctypes.byref(h)) == -1
     assert drts._lib.drts_step(None, None) == -1
     assert drts._lib.drts_matrix_row_of(None, 0, 0) == -1
+
+
+def test_one_hip_runtime_is_mapped(lib):
+    """torch's HIP runtime and the library's are the same mapped file."""
+    from paper_1611_08536_amd import drts
+    assert len(drts._hip_runtimes()) == 1
