@@ -204,7 +204,19 @@ typedef struct {
     int32_t xcd_remap;    /* 1 = give each XCD a contiguous range of chunks */
     int32_t graph_steps;  /* steps captured per hipGraph replay (0 = eager) */
     int32_t rescale;      /* 1 = power-of-two rescale every step (default) */
+    int32_t variant;      /* one rhs only: DRTS_SPMV_ROW (a thread per row),
+                             DRTS_SPMV_PIPE (the next tile's entries load while
+                             the current tile is reduced), DRTS_SPMV_HALF (two
+                             threads per row while streaming: fewer registers,
+                             more resident waves), DRTS_SPMV_HALF_PIPE (both) */
+    int32_t queue;        /* one rhs only: 1 = workgroups take chunks from a
+                             device counter (dynamic balance), 0 = fixed walk */
 } drts_options_t;
+
+#define DRTS_SPMV_ROW 0
+#define DRTS_SPMV_PIPE 1
+#define DRTS_SPMV_HALF 2
+#define DRTS_SPMV_HALF_PIPE 3
 
 /* Creates the time-stepping state for n_rhs right-hand sides sharing A: the
  * state (zero), detectors, series buffers for max_steps steps.  n_rhs > 1

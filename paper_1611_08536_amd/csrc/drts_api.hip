@@ -129,7 +129,7 @@ struct drts_solver {
     Buffer ser_tot, ser_det, ser_exp, ser_abs_exp, amp, smax;
     Buffer src_tile, src_row, src_id, src_rhs, src_w;
     Buffer det_tile, det_row, det_id, det_F;
-    Buffer inst_dev, work_dev;
+    Buffer inst_dev, work_dev, queue;
 
     // host copies
     std::vector<DetEntry> dets;
@@ -158,7 +158,7 @@ struct drts_solver {
 struct drts_batch {
     Device dev;
     std::vector<drts_solver *> solvers;
-    Buffer inst_dev, work_dev;
+    Buffer inst_dev, work_dev, queue;
 };
 
 namespace {
@@ -224,6 +224,7 @@ int prepare(drts_solver *S)
     I.val = A.val.ptr;
     I.n_rows = A.model.n_rows;
     I.n_states = A.model.n_states;
+    I.nnz = A.nnz;
     I.rp64 = A.rp64 ? 1 : 0;
     I.rows_per_tile = o.rows_per_tile;
     I.n_tiles = S->n_tiles;
@@ -252,6 +253,7 @@ int prepare(drts_solver *S)
     I.abs_cur = S->ctl_abs.as<double>();
     I.t_end = S->t_end.as<int64_t>();
     I.rescale = o.rescale;
+    I.n_mat = (int32_t)A.model.mats.size();
     I.max_steps = S->max_steps;
     I.partials = S->partials.as<double>();
     I.n_chunks = S->n_chunks;
@@ -386,12 +388,14 @@ int launch_one(drts_solver *S, hipStream_t stream)
         if (!e0 || !e1) return set_error(DRTS_E_HIP, "hipEventCreate failed");
         DRTS_HIP(hipEventRecord(e0, stream));
     }
+    int32_t *queue = (!spmm && S->opt.queue) ? S->queue.as<int32_t>() : nullptr;
     hipError_t e = launch_step(S->inst_dev.as<StepInst>(), S->work_dev.as<WorkItem>(), S->n_chunks, 1, S->n_rhs,
                                A.model.value_type == DRTS_F64, A.rp64 ? 1 : 0, spmm ? 1 : 0, S->grid,
-                               S->opt.xcd_remap, S->opt.rows_per_tile, S->n_det, stream);
+                               (S->opt.xcd_remap ? 1 : 0) | ((S->opt.variant & 3) << 1), S->opt.rows_per_tile,
+                               S->n_det, queue, stream);
     if (e != hipSuccess) return set_error(DRTS_E_HIP, "step launch failed: %s", hipGetErrorString(e));
     if (e1) DRTS_HIP(hipEventRecord(e1, stream));
-    e = launch_finalize(S->inst_dev.as<StepInst>(), 1, S->n_rhs, S->n_det, stream);
+    e = launch_finalize(S->inst_dev.as<StepInst>(), 1, S->n_rhs, S->n_det, queue, stream);
     if (e != hipSuccess) return set_error(DRTS_E_HIP, "finalize launch failed: %s", hipGetErrorString(e));
     return DRTS_OK;
 }
@@ -437,14 +441,19 @@ int ensure_graph(drts_solver *S, int K)
 
 drts_options_t default_options(const drts_solver *S)
 {
+    // defaults measured on MI355X for the 128^3 three-layer workload (one rhs):
+    // 256-row tiles, 4 tiles per chunk, 32 workgroups per CU launched (the
+    // surplus waits and gives dynamic balance), fixed walk
     drts_options_t o{};
     o.kernel = DRTS_KERNEL_CSR;
     o.rows_per_tile = spmm_of(S) ? 64 : 256;
-    o.tiles_per_chunk = spmm_of(S) ? 128 : 16;
-    o.grid = 0;
-    o.xcd_remap = 1;
+    o.tiles_per_chunk = spmm_of(S) ? 128 : 4;
+    o.grid = spmm_of(S) ? 0 : device_cu_count() * 32;
+    o.xcd_remap = 0;
     o.graph_steps = 0;
     o.rescale = 1;
+    o.variant = DRTS_SPMV_ROW;
+    o.queue = 0;
     return o;
 }
 
@@ -454,12 +463,22 @@ int check_options(const drts_solver *S, const drts_options_t *o)
         return set_error(DRTS_E_INVALID, "unknown kernel %d", o->kernel);
     if (o->kernel == DRTS_KERNEL_STRUCTURED)
         return set_error(DRTS_E_INVALID, "the structured kernel is not available in this build");
-    if (o->rows_per_tile < 16 || o->rows_per_tile > 256) return set_error(DRTS_E_INVALID, "rows_per_tile in 16..256");
-    if (o->tiles_per_chunk < 1 || o->tiles_per_chunk > (1 << 20))
-        return set_error(DRTS_E_INVALID, "tiles_per_chunk in 1..2^20");
+    if (S->n_rhs == 1) {
+        if (o->rows_per_tile != 64 && o->rows_per_tile != 128 && o->rows_per_tile != 256)
+            return set_error(DRTS_E_INVALID, "rows_per_tile must be 64, 128 or 256 for one right-hand side");
+        if (o->tiles_per_chunk < 1 || o->tiles_per_chunk > 64)
+            return set_error(DRTS_E_INVALID, "tiles_per_chunk in 1..64 for one right-hand side");
+    } else {
+        if (o->rows_per_tile < 16 || o->rows_per_tile > 256)
+            return set_error(DRTS_E_INVALID, "rows_per_tile in 16..256");
+        if (o->tiles_per_chunk < 1 || o->tiles_per_chunk > (1 << 20))
+            return set_error(DRTS_E_INVALID, "tiles_per_chunk in 1..2^20");
+    }
+    if (o->queue != 0 && o->queue != 1) return set_error(DRTS_E_INVALID, "queue must be 0 or 1");
+    if (o->variant < DRTS_SPMV_ROW || o->variant > DRTS_SPMV_HALF_PIPE)
+        return set_error(DRTS_E_INVALID, "unknown variant %d", o->variant);
     if (o->grid < 0 || o->graph_steps < 0 || o->graph_steps > 4096)
         return set_error(DRTS_E_INVALID, "bad grid or graph_steps");
-    (void)S;
     return DRTS_OK;
 }
 
@@ -555,6 +574,13 @@ int drts_solver_create(const drts_matrix_t *A, int32_t n_rhs, const drts_detecto
     if (n_rhs > 1 && A->m.model.value_type != DRTS_F32)
         return set_error(DRTS_E_INVALID, "several right-hand sides need an FP32 matrix");
     if (max_steps < 1) return set_error(DRTS_E_INVALID, "max_steps must be >= 1");
+    {
+        // the step kernels gather x with 32-bit byte offsets
+        const uint64_t vb = A->m.model.value_type == DRTS_F64 ? 8 : 4;
+        if ((uint64_t)A->m.model.n_rows * vb * (uint64_t)n_rhs >= 0xffffffffull)
+            return set_error(DRTS_E_RANGE, "a state vector of %lld rows x %d rhs exceeds 4 GiB",
+                             (long long)A->m.model.n_rows, n_rhs);
+    }
     drts_solver *S = new (std::nothrow) drts_solver;
     if (!S) return set_error(DRTS_E_NOMEM, "host allocation failed");
     S->dev = make_device(dev);
@@ -594,6 +620,7 @@ int drts_solver_create(const drts_matrix_t *A, int32_t n_rhs, const drts_detecto
         if (!rc) rc = S->ctl_M.allocate(&dv, n_rhs * sizeof(double));
         if (!rc) rc = S->ctl_abs.allocate(&dv, n_rhs * sizeof(double));
         if (!rc) rc = S->t_end.allocate(&dv, sizeof(int64_t));
+        if (!rc) rc = S->queue.allocate(&dv, sizeof(int32_t));
         if (!rc) rc = S->ser_tot.allocate(&dv, (size_t)max_steps * 3 * n_rhs * sizeof(double));
         if (!rc) rc = S->ser_det.allocate(&dv, (size_t)max_steps * std::max(S->n_det, 1) * n_rhs * sizeof(double));
         if (!rc) rc = S->ser_exp.allocate(&dv, (size_t)max_steps * n_rhs * sizeof(int32_t));
@@ -627,6 +654,7 @@ int drts_solver_create(const drts_matrix_t *A, int32_t n_rhs, const drts_detecto
                 hipMemsetAsync(S->ctl_E.ptr, 0, n_rhs * sizeof(int32_t), s) != hipSuccess ||
                 hipMemsetAsync(S->ctl_M.ptr, 0, n_rhs * sizeof(double), s) != hipSuccess ||
                 hipMemsetAsync(S->ctl_abs.ptr, 0, n_rhs * sizeof(double), s) != hipSuccess ||
+                hipMemsetAsync(S->queue.ptr, 0, sizeof(int32_t), s) != hipSuccess ||
                 hipMemsetAsync(S->smax.ptr, 0, S->smax.bytes, s) != hipSuccess ||
                 hipMemsetAsync(S->ser_tot.ptr, 0, S->ser_tot.bytes, s) != hipSuccess ||
                 hipMemsetAsync(S->ser_det.ptr, 0, S->ser_det.bytes, s) != hipSuccess ||
@@ -817,14 +845,16 @@ void drts_solver_destroy(drts_solver_t *S)
 
 namespace {
 
-int batch_launch(drts_batch *B, int64_t n_work, int n_inst, hipStream_t stream)
+int batch_launch(drts_batch *B, int64_t n_work, int n_inst, int rows_per_tile, hipStream_t stream)
 {
     const drts_solver *S0 = B->solvers[0];
-    const int grid = device_cu_count() * 8;
+    const int grid = device_cu_count() * 16;
+    int32_t *queue = S0->opt.queue ? B->queue.as<int32_t>() : nullptr;
     hipError_t e = launch_step(B->inst_dev.as<StepInst>(), B->work_dev.as<WorkItem>(), n_work, n_inst, 1, 0,
-                               S0->A->m.rp64 ? 1 : 0, 0, grid, 1, 256, 0, stream);
+                               S0->A->m.rp64 ? 1 : 0, 0, grid, (S0->opt.variant & 3) << 1, rows_per_tile, 0, queue,
+                               stream);
     if (e != hipSuccess) return set_error(DRTS_E_HIP, "batch step launch failed: %s", hipGetErrorString(e));
-    e = launch_finalize(B->inst_dev.as<StepInst>(), n_inst, 1, 0, stream);
+    e = launch_finalize(B->inst_dev.as<StepInst>(), n_inst, 1, 0, queue, stream);
     if (e != hipSuccess) return set_error(DRTS_E_HIP, "batch finalize launch failed: %s", hipGetErrorString(e));
     return DRTS_OK;
 }
@@ -851,6 +881,14 @@ int drts_batch_create(drts_solver_t *const *solvers, int32_t n, const drts_devic
     if (!B) return set_error(DRTS_E_NOMEM, "host allocation failed");
     B->dev = make_device(dev);
     B->solvers.assign(solvers, solvers + n);
+    int rc = B->queue.allocate(&B->dev, sizeof(int32_t));
+    if (!rc && hipMemsetAsync(B->queue.ptr, 0, sizeof(int32_t), B->dev.stream) != hipSuccess)
+        rc = set_error(DRTS_E_HIP, "hipMemsetAsync failed");
+    if (!rc && hipStreamSynchronize(B->dev.stream) != hipSuccess) rc = set_error(DRTS_E_HIP, "sync failed");
+    if (rc) {
+        delete B;
+        return rc;
+    }
     *out = B;
     return DRTS_OK;
 }
@@ -861,8 +899,11 @@ int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const
     const int n = (int)B->solvers.size();
     std::vector<int> order;
     int rc;
+    const int rpt = B->solvers[0]->opt.rows_per_tile;
     for (int i = 0; i < n; ++i) {
         drts_solver *S = B->solvers[i];
+        if (S->opt.rows_per_tile != rpt)
+            return set_error(DRTS_E_INVALID, "solver %d: every batch member needs the same rows_per_tile", i);
         if (n_steps[i] < 0 || S->t_host + n_steps[i] > S->max_steps)
             return set_error(DRTS_E_RANGE, "solver %d: steps beyond max_steps", i);
         if (n_steps[i] == 0) continue;
@@ -911,7 +952,7 @@ int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const
             hipGraph_t g = nullptr;
             hipGraphExec_t ge = nullptr;
             DRTS_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-            for (int k = 0; k < K && rc == DRTS_OK; ++k) rc = batch_launch(B, n_work, active, cap);
+            for (int k = 0; k < K && rc == DRTS_OK; ++k) rc = batch_launch(B, n_work, active, rpt, cap);
             hipError_t e = hipStreamEndCapture(cap, &g);
             if (rc == DRTS_OK && e != hipSuccess) rc = set_error(DRTS_E_HIP, "capture: %s", hipGetErrorString(e));
             if (rc == DRTS_OK && hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess)
@@ -926,7 +967,7 @@ int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const
             if (rc) break;
         }
         for (; len > 0; --len, ++step)
-            if ((rc = batch_launch(B, n_work, active, s))) break;
+            if ((rc = batch_launch(B, n_work, active, rpt, s))) break;
         if (rc) break;
     }
     if (cap) (void)hipStreamDestroy(cap);
@@ -974,14 +1015,15 @@ int drts_autotune(drts_solver_t *S, const char *cache_path, drts_options_t *chos
     if (cache_path) {
         if (FILE *f = fopen(cache_path, "r")) {
             char k[128];
-            int r, c, g, x;
+            int r, c, g, x, pl;
             bool hit = false;
-            while (fscanf(f, "%127s %d %d %d %d", k, &r, &c, &g, &x) == 5) {
+            while (fscanf(f, "%127s %d %d %d %d %d", k, &r, &c, &g, &x, &pl) == 6) {
                 if (key == k) {
                     best.rows_per_tile = r;
                     best.tiles_per_chunk = c;
                     best.grid = g;
                     best.xcd_remap = x;
+                    best.variant = pl;
                     hit = true;
                 }
             }
@@ -1005,19 +1047,21 @@ int drts_autotune(drts_solver_t *S, const char *cache_path, drts_options_t *chos
     std::vector<drts_options_t> cands;
     const bool spmm = spmm_of(S);
     const int rows_opts[] = {64, 128, 256};
-    const int chunk_opts[] = {4, 16, 64};
+    const int chunk_opts[] = {2, 4, 16};
     const int grid_mult[] = {4, 8, 16};
     for (int r : rows_opts)
         for (int c : chunk_opts)
             for (int g : grid_mult)
-                for (int x = 0; x < 2; ++x) {
-                    drts_options_t o = S->opt;
-                    o.rows_per_tile = r;
-                    o.tiles_per_chunk = spmm ? c * 8 : c;
-                    o.grid = cus * (spmm ? g / 2 : g);
-                    o.xcd_remap = x;
-                    cands.push_back(o);
-                }
+                for (int x = 0; x < 2; ++x)
+                    for (int pl = 0; pl < (spmm ? 1 : 4); ++pl) {
+                        drts_options_t o = S->opt;
+                        o.rows_per_tile = r;
+                        o.tiles_per_chunk = spmm ? c * 32 : c;
+                        o.grid = cus * (spmm ? g / 2 : g);
+                        o.xcd_remap = x;
+                        o.variant = pl;
+                        cands.push_back(o);
+                    }
     const int steps = (int)std::min<int64_t>(4, S->max_steps);
     hipEvent_t e0, e1;
     DRTS_HIP(hipEventCreate(&e0));
@@ -1062,8 +1106,8 @@ int drts_autotune(drts_solver_t *S, const char *cache_path, drts_options_t *chos
     if ((rc = prepare(S))) return rc;
     if (cache_path) {
         if (FILE *f = fopen(cache_path, "a")) {
-            fprintf(f, "%s %d %d %d %d\n", key.c_str(), best.rows_per_tile, best.tiles_per_chunk, best.grid,
-                    best.xcd_remap);
+            fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), best.rows_per_tile, best.tiles_per_chunk, best.grid,
+                    best.xcd_remap, best.variant);
             fclose(f);
         }
     }

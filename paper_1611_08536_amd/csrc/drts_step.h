@@ -18,6 +18,7 @@ struct StepInst {
     const int32_t *col;
     const void *val;
     int64_t n_rows, n_states;
+    int64_t nnz;            // entries of [A; L] (the arrays hold 4 more, zero)
     int32_t rp64;
     int32_t rows_per_tile;
     int64_t n_tiles;
@@ -50,7 +51,7 @@ struct StepInst {
     double *abs_cur;        // [n_rhs] absorbed during step t (from x_t), scaled by 2^-E
     const int64_t *t_end;   // steps are skipped once t >= *t_end
     int32_t rescale;
-    int32_t pad0;
+    int32_t n_mat;          // entries of absorb
     int64_t max_steps;
     // partials [slot * n_rhs + rhs][n_chunks]
     double *partials;
@@ -68,12 +69,15 @@ struct WorkItem {
     int32_t chunk;
 };
 
-// Launches the SpMV (n_rhs == 1) or SpMM step over a work list, followed by
-// the finalize kernel.  Returns a hipError_t.
+// Launches the SpMV (n_rhs == 1) or SpMM step over a work list.  xcd_remap
+// bit 0 selects the XCD-aware order, bit 1 the pipelined SpMV.  Returns a
+// hipError_t.
+// queue (may be NULL): a zeroed device counter from which the SpMV workgroups
+// take work items; the finalize kernel resets it.
 hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int64_t n_work, int n_inst,
                        int n_rhs_max, int value_f64, int rp64, int spmm, int grid, int xcd_remap,
-                       int rows_per_tile, int n_det_max, hipStream_t stream);
-hipError_t launch_finalize(const StepInst *insts_dev, int n_inst, int n_rhs_max, int n_det_max,
+                       int rows_per_tile, int n_det_max, int32_t *queue, hipStream_t stream);
+hipError_t launch_finalize(const StepInst *insts_dev, int n_inst, int n_rhs_max, int n_det_max, int32_t *queue,
                            hipStream_t stream);
 
 // Matrix-free step over the per-voxel direction blocks (single rhs, FP32).

@@ -28,26 +28,32 @@ namespace drts {
 namespace {
 
 constexpr int kNT = 256;     // threads per workgroup
-constexpr int kCap = 4096;   // matrix entries staged in LDS per pass
-constexpr int kRowsMax = 256;
 constexpr int kXcds = 8;
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
 typedef int i4 __attribute__((ext_vector_type(4)));
 
+// Pointers into device memory are marked as global (address space 1): the
+// descriptors are read from memory, so the compiler would otherwise emit flat
+// accesses, which may alias LDS and serialise every gather behind the LDS
+// stores.
+#define GLB __attribute__((address_space(1)))
+template <typename T> __device__ __forceinline__ const GLB T *gp(const T *p) { return (const GLB T *)p; }
+template <typename T> __device__ __forceinline__ GLB T *gpw(T *p) { return (GLB T *)p; }
+
 template <typename VT> struct Quad;
 template <> struct Quad<float> {
     f4 v;
-    __device__ __forceinline__ void load(const float *p) { v = __builtin_nontemporal_load((const f4 *)p); }
+    __device__ __forceinline__ void load(const GLB float *p) { v = __builtin_nontemporal_load((const GLB f4 *)p); }
     __device__ __forceinline__ float operator[](int j) const { return v[j]; }
 };
 template <> struct Quad<double> {
     d2 a, b;
-    __device__ __forceinline__ void load(const double *p)
+    __device__ __forceinline__ void load(const GLB double *p)
     {
-        a = __builtin_nontemporal_load((const d2 *)p);
-        b = __builtin_nontemporal_load((const d2 *)(p + 2));
+        a = __builtin_nontemporal_load((const GLB d2 *)p);
+        b = __builtin_nontemporal_load((const GLB d2 *)(p + 2));
     }
     __device__ __forceinline__ double operator[](int j) const { return j < 2 ? a[j] : b[j - 2]; }
 };
@@ -73,13 +79,14 @@ __device__ __forceinline__ Scale step_scale(const StepInst &I, int rhs, int64_t 
     return {k, E + k};
 }
 
+template <int NT = kNT>
 __device__ __forceinline__ double block_sum(double v, double *red)
 {
     const int tid = threadIdx.x;
     red[tid] = v;
     __syncthreads();
 #pragma unroll
-    for (int s = kNT / 2; s > 0; s >>= 1) {
+    for (int s = NT / 2; s > 0; s >>= 1) {
         if (tid < s) red[tid] += red[tid + s];
         __syncthreads();
     }
@@ -88,19 +95,34 @@ __device__ __forceinline__ double block_sum(double v, double *red)
     return r;
 }
 
+template <int NT = kNT>
 __device__ __forceinline__ double block_max(double v, double *red)
 {
     const int tid = threadIdx.x;
     red[tid] = v;
     __syncthreads();
 #pragma unroll
-    for (int s = kNT / 2; s > 0; s >>= 1) {
+    for (int s = NT / 2; s > 0; s >>= 1) {
         if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
         __syncthreads();
     }
     const double r = red[0];
     __syncthreads();
     return r;
+}
+
+// Butterfly sum / max over a wavefront; lane 0's result has a fixed order.
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
 }
 
 template <typename IT>
@@ -131,126 +153,322 @@ __device__ __forceinline__ Walk walk_of(int64_t n_work, int xcd_remap)
 
 // ---------------------------------------------------------------------------
 // SpMV step (one right-hand side)
+//
+// One row per thread (NT rows per tile).  Per chunk, the tile bounds
+// (row_ptr at tile starts), the per-tile source/detector offsets and the
+// absorption table go to LDS once, so a tile needs two dependent round trips
+// only: {values, columns, own row pointers, material} issued together, then
+// the x gathers.  The stage holds 32 entries per row; a tile with more
+// entries (rare: long rows) takes the multi-pass path.
 // ---------------------------------------------------------------------------
-template <typename VT, typename IT>
-__global__ void __launch_bounds__(kNT) step_spmv(const StepInst *__restrict__ insts,
-                                                  const WorkItem *__restrict__ work, int64_t n_work,
-                                                  int xcd_remap)
-{
-    constexpr int U = kCap / (4 * kNT);
-    __shared__ VT s_prod[kCap];
-    __shared__ IT s_rp[kRowsMax + 1];
-    __shared__ VT s_y[kRowsMax];
-    __shared__ double s_red[kNT];
-    const int tid = threadIdx.x;
-    const Walk wk = walk_of(n_work, xcd_remap);
+constexpr int kChunkMax = 64;   // tiles per chunk staged in LDS
+constexpr int kMatMax = 256;
 
-    for (int64_t wi = wk.begin; wi < wk.end; wi += wk.stride) {
+// Buffer resources (gfx9 layout: 64-bit base, byte range, 0x00020000) let the
+// streaming loads use 32-bit offsets from a scalar base instead of a 64-bit
+// address per lane, and return zero for an offset past the range.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint64_t bytes)
+{
+    const uint32_t n = bytes >= 0xffffffffull ? 0xffffffffu : (uint32_t)bytes;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)n, 0x00020000);
+}
+constexpr int kStream = 2;  // cache policy bits of a buffer load: nontemporal
+
+template <typename VT> struct BufQuad;
+template <> struct BufQuad<float> {
+    __device__ static Quad<float> load(__amdgpu_buffer_rsrc_t rs, uint32_t off)
+    {
+        Quad<float> q;
+        q.v = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, kStream));
+        return q;
+    }
+    __device__ static float gather(__amdgpu_buffer_rsrc_t rs, int32_t c)
+    {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, c * 4, 0, 0));
+    }
+};
+template <> struct BufQuad<double> {
+    __device__ static Quad<double> load(__amdgpu_buffer_rsrc_t rs, uint32_t off)
+    {
+        Quad<double> q;
+        q.a = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, kStream));
+        q.b = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off + 16, 0, kStream));
+        return q;
+    }
+    __device__ static double gather(__amdgpu_buffer_rsrc_t rs, int32_t c)
+    {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, c * 8, 0, 0));
+    }
+};
+
+// Entries of one tile held in registers between their loads and the gathers.
+template <typename VT, typename IT, int U> struct TileRegs {
+    Quad<VT> qv[U];
+    i4 qc[U];
+    uint32_t qo[U];   // entry offset of each quad from a0
+    IT a0, b, e;
+    IT mylo, myhi;
+    int q;
+};
+
+template <typename VT, typename IT, int NT, int U, int R>
+__device__ __forceinline__ void issue_tile(TileRegs<VT, IT, U> &T, const GLB IT *rp, const GLB int32_t *col,
+                                           const GLB VT *val, const GLB uint8_t *mat, IT b, IT e, int64_t r0,
+                                           int nr, int64_t n_states, int64_t nnz)
+{
+    const int tid = threadIdx.x;
+    const int64_t r = r0 + tid;
+    T.b = b;
+    T.e = e;
+    T.mylo = 0;
+    T.myhi = 0;
+    T.q = 0;
+    if (tid < nr && tid < R) {
+        T.mylo = rp[r];
+        T.myhi = rp[r + 1];
+        if (r < n_states) T.q = mat[r / kDirs];
+    }
+    // Every lane runs U quads without branches: a quad index at or past e is
+    // clamped to the last quad holding entries of the tile, so the lane
+    // re-reads cached data and rewrites the same products into the same LDS
+    // slots.  Entries of a loaded quad outside [b, e) belong to neighbouring
+    // tiles or to the zero padding: their columns are valid state indices
+    // and their products land in LDS slots no row of this tile reads.
+    T.a0 = b & ~(IT)3;
+    const uint32_t last = (uint32_t)(((e - 1 - T.a0) >> 2) << 2);
+    const uint32_t span = (uint32_t)(e - T.a0);
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        const uint32_t i = 4u * (uint32_t)(tid + k * NT);
+        T.qo[k] = i < span ? i : last;
+    }
+    const int64_t base = (int64_t)T.a0;
+    const uint64_t left = (uint64_t)(nnz + 4 - base);
+    const __amdgpu_buffer_rsrc_t rc = make_rsrc((const void *)(col + base), left * 4);
+    const __amdgpu_buffer_rsrc_t rv = make_rsrc((const void *)(val + base), left * sizeof(VT));
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        T.qc[k] = __builtin_amdgcn_raw_buffer_load_b128(rc, (int)(T.qo[k] * 4), 0, kStream);
+        T.qv[k] = BufQuad<VT>::load(rv, T.qo[k] * (uint32_t)sizeof(VT));
+    }
+}
+
+// gathers x, stages the products, sums each thread's row in column order
+template <typename VT, typename IT, int NT, int U, int R>
+__device__ __forceinline__ VT finish_tile(const TileRegs<VT, IT, U> &T, __amdgpu_buffer_rsrc_t rx, VT *s_prod)
+{
+    VT xv[U][4];
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) xv[k][jj] = BufQuad<VT>::gather(rx, T.qc[k][jj]);
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) s_prod[T.qo[k] + jj] = T.qv[k][jj] * xv[k][jj];
+    __syncthreads();
+    VT acc = 0;
+    IT jj = T.mylo;
+    for (; jj + 4 <= T.myhi; jj += 4) {
+        const VT p0 = s_prod[jj - T.a0], p1 = s_prod[jj - T.a0 + 1];
+        const VT p2 = s_prod[jj - T.a0 + 2], p3 = s_prod[jj - T.a0 + 3];
+        acc += p0;
+        acc += p1;
+        acc += p2;
+        acc += p3;
+    }
+    for (; jj < T.myhi; ++jj) acc += s_prod[jj - T.a0];
+    return acc;
+}
+
+// NT threads stream the entries of R rows (R = NT: one row per thread and 7
+// quads per thread; R = NT/2: 4 quads per thread, so fewer registers and more
+// resident waves; the first R threads sum the rows).  PIPE = 1: the next
+// tile's entries are loaded before this tile's gathers, so the matrix stream
+// of a workgroup never stops (two register sets).
+template <typename VT, typename IT, int NT, int R, int PIPE>
+__global__ void __launch_bounds__(NT) step_spmv(const StepInst *__restrict__ insts,
+                                                 const WorkItem *__restrict__ work, int64_t n_work,
+                                                 int xcd_remap, int32_t *__restrict__ queue)
+{
+    constexpr int NW = NT / 64;
+    __shared__ int64_t s_wi;
+    __shared__ double s_wred[4][NW];
+    constexpr int U = (R == NT) ? 7 : (32 * R) / (4 * NT);   // quads of entries per thread
+    constexpr int CAP = 4 * U * NT;      // entries staged per pass (>= 28 per row)
+    static_assert(U >= 1 && CAP >= 28 * R, "tile shape");
+    __shared__ VT s_prod[CAP];
+    __shared__ IT s_tb[kChunkMax + 1];
+    __shared__ int32_t s_src[kChunkMax + 1];
+    __shared__ int32_t s_det[kChunkMax + 1];
+    __shared__ double s_abs[kMatMax];
+    __shared__ VT s_y[R];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const Walk wk = walk_of(n_work, xcd_remap);
+    // work items come from a global counter (dynamic balance) or a fixed walk
+    int64_t wi = wk.begin;
+    int cached = -1;
+    int64_t t = 0;
+    bool live = false;
+    Scale sc{0, 0};
+    VT scale = 1;
+    for (;; wi += wk.stride) {
+        if (queue) {
+            if (tid == 0) s_wi = atomicAdd(queue, 1);
+            __syncthreads();
+            wi = s_wi;
+            __syncthreads();   // every thread has read s_wi before thread 0 may write it again
+        }
+        if (wi >= (queue ? n_work : wk.end)) break;
         const WorkItem item = work[wi];
         const StepInst &I = insts[item.inst];
-        const int64_t t = I.t[0];
-        if (t >= *I.t_end) continue;
-        const Scale sc = step_scale(I, 0, t);
-        const VT scale = (VT)ldexp(1.0, -sc.k);
-        const IT *__restrict__ rp = (const IT *)I.row_ptr;
-        const int32_t *__restrict__ col = I.col;
-        const VT *__restrict__ val = (const VT *)I.val;
-        const VT *__restrict__ x = (const VT *)((t & 1) ? I.buf1 : I.buf0);
-        VT *__restrict__ y = (VT *)((t & 1) ? I.buf0 : I.buf1);
-        const int R = I.rows_per_tile;
+        if (item.inst != cached) {
+            // per-instance constants of this launch, read once per workgroup
+            cached = item.inst;
+            t = I.t[0];
+            live = t < *I.t_end;
+            if (live) {
+                sc = step_scale(I, 0, t);
+                scale = (VT)ldexp(1.0, -sc.k);
+            }
+        }
+        if (!live) continue;
+        const GLB IT *rp = gp((const IT *)I.row_ptr);
+        const GLB int32_t *col = gp(I.col);
+        const GLB VT *val = gp((const VT *)I.val);
+        const GLB VT *x = gp((const VT *)((t & 1) ? I.buf1 : I.buf0));
+        const __amdgpu_buffer_rsrc_t rx = make_rsrc((const void *)x, (uint64_t)I.n_rows * sizeof(VT));
+        GLB VT *y = gpw((VT *)((t & 1) ? I.buf0 : I.buf1));
+        const GLB uint8_t *mat = gp(I.mat);
+        const int64_t n_rows = I.n_rows, n_states = I.n_states;
+        const int64_t tile0 = (int64_t)item.chunk * I.tiles_per_chunk;
+        const int ntc = (int)min((int64_t)I.tiles_per_chunk, I.n_tiles - tile0);
+
+        // chunk prologue
+        for (int j = tid; j <= ntc; j += NT) {
+            s_tb[j] = rp[min((tile0 + j) * R, n_rows)];
+            s_src[j] = gp(I.src_tile)[tile0 + j];
+            s_det[j] = gp(I.det_tile)[tile0 + j];
+        }
+        for (int q = tid; q < I.n_mat; q += NT) s_abs[q] = gp(I.absorb)[q];
+        __syncthreads();
 
         double sN = 0.0, sE = 0.0, sA = 0.0, dsum = 0.0;
         VT mx = 0;
-        const int64_t tile0 = (int64_t)item.chunk * I.tiles_per_chunk;
-        const int64_t tile1 = min(tile0 + (int64_t)I.tiles_per_chunk, I.n_tiles);
-        for (int64_t tile = tile0; tile < tile1; ++tile) {
-            const int64_t r0 = tile * R;
-            const int nr = (int)min((int64_t)R, I.n_rows - r0);
-            for (int i = tid; i <= nr; i += kNT) s_rp[i] = rp[r0 + i];
-            __syncthreads();
-            const IT b = s_rp[0], e = s_rp[nr];
-            IT mylo = 0, myhi = 0;
-            if (tid < nr) {
-                mylo = s_rp[tid];
-                myhi = s_rp[tid + 1];
-            }
+        TileRegs<VT, IT, U> cur, nxt;
+        auto fits = [&](int j) { return s_tb[j + 1] - s_tb[j] <= (IT)CAP - 3; };
+        auto rows_of = [&](int j) { return (int)min((int64_t)R, n_rows - (tile0 + j) * R); };
+        bool have = false;
+        if (PIPE && ntc > 0 && fits(0)) {
+            issue_tile<VT, IT, NT, U, R>(cur, rp, col, val, mat, s_tb[0], s_tb[1], tile0 * R, rows_of(0), n_states, I.nnz);
+            have = true;
+        }
+        for (int j = 0; j < ntc; ++j) {
+            const int64_t r0 = (tile0 + j) * R;
+            const int nr = rows_of(j);
+            const int64_t r = r0 + tid;
+            const bool own = tid < nr && tid < R;
             VT acc = 0;
-            for (IT a = b & ~(IT)3; a < e; a += kCap) {
-                const IT cs = a < b ? b : a;
-                const IT ce = (e - a < (IT)kCap) ? e : a + (IT)kCap;
-                Quad<VT> qv[U];
-                i4 qc[U];
-#pragma unroll
-                for (int k = 0; k < U; ++k) {
-                    const IT i = a + (IT)(4 * (tid + k * kNT));
-                    if (i < ce) {
-                        qc[k] = __builtin_nontemporal_load((const i4 *)(col + i));
-                        qv[k].load(val + i);
-                    }
+            int q = 0;
+            if (fits(j)) {
+                if (!have)
+                    issue_tile<VT, IT, NT, U, R>(cur, rp, col, val, mat, s_tb[j], s_tb[j + 1], r0, nr, n_states, I.nnz);
+                bool more = false;
+                if (PIPE && j + 1 < ntc && fits(j + 1)) {
+                    issue_tile<VT, IT, NT, U, R>(nxt, rp, col, val, mat, s_tb[j + 1], s_tb[j + 2], r0 + R, rows_of(j + 1),
+                                              n_states, I.nnz);
+                    more = true;
                 }
+                acc = finish_tile<VT, IT, NT, U, R>(cur, rx, s_prod);
+                q = cur.q;
+                if (more) cur = nxt;
+                have = more;
+            } else {
+                // long rows: several passes over the tile
+                const IT b = s_tb[j], e = s_tb[j + 1];
+                IT mylo = 0, myhi = 0;
+                if (own) {
+                    mylo = rp[r];
+                    myhi = rp[r + 1];
+                    if (r < n_states) q = mat[r / kDirs];
+                }
+                for (IT a = b & ~(IT)3; a < e; a += CAP) {
+                    const IT cs = a < b ? b : a;
+                    const IT ce = (e - a < (IT)CAP) ? e : a + (IT)CAP;
+                    for (IT i = a + 4 * tid; i < ce; i += 4 * NT) {
+                        const i4 c4 = __builtin_nontemporal_load((const GLB i4 *)(col + i));
+                        Quad<VT> v4;
+                        v4.load(val + i);
 #pragma unroll
-                for (int k = 0; k < U; ++k) {
-                    const IT i = a + (IT)(4 * (tid + k * kNT));
-                    if (i < ce) {
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const IT idx = i + j;
-                            if (idx >= cs && idx < ce) s_prod[idx - a] = qv[k][j] * x[qc[k][j]];
+                        for (int jj = 0; jj < 4; ++jj) {
+                            const IT idx = i + jj;
+                            if (idx >= cs && idx < ce) s_prod[idx - a] = v4[jj] * x[c4[jj]];
                         }
                     }
+                    __syncthreads();
+                    const IT lo = mylo > cs ? mylo : cs;
+                    const IT hi = myhi < ce ? myhi : ce;
+                    for (IT jj = lo; jj < hi; ++jj) acc += s_prod[jj - a];
+                    __syncthreads();
                 }
-                __syncthreads();
-                const IT lo = mylo > cs ? mylo : cs;
-                const IT hi = myhi < ce ? myhi : ce;
-                for (IT j = lo; j < hi; ++j) acc += s_prod[j - a];
-                __syncthreads();
+                have = false;
+                if (PIPE && j + 1 < ntc && fits(j + 1)) {
+                    issue_tile<VT, IT, NT, U, R>(cur, rp, col, val, mat, s_tb[j + 1], s_tb[j + 2], r0 + R, rows_of(j + 1),
+                                              n_states, I.nnz);
+                    have = true;
+                }
             }
 
             // epilogue: rescale, sources, store, FP64 totals
-            if (tid < nr) {
-                const int64_t r = r0 + tid;
+            if (own) {
                 VT v = acc * scale;
-                const int sb = I.src_tile[tile], se = I.src_tile[tile + 1];
+                const int sb = s_src[j], se = s_src[j + 1];
                 if (sb < se) {
+                    const GLB int64_t *srow = gp(I.src_row);
                     int e2 = lower_bound_rows<IT>(I.src_row, sb, se, r);
                     double s = 0.0;
                     bool any = false;
-                    for (; e2 < se && I.src_row[e2] == r; ++e2) {
-                        s += I.src_w[e2] * I.amp[t * I.n_src + I.src_id[e2]];
+                    for (; e2 < se && srow[e2] == r; ++e2) {
+                        s += gp(I.src_w)[e2] * gp(I.amp)[t * I.n_src + gp(I.src_id)[e2]];
                         any = true;
                     }
                     if (any) v += (VT)ldexp(s, -sc.En);
                 }
                 y[r] = v;
                 s_y[tid] = v;
-                if (r < I.n_states) {
+                if (r < n_states) {
                     sN += (double)v;
-                    sA += I.absorb[I.mat[r / kDirs]] * (double)v;
+                    sA += s_abs[q] * (double)v;
                     mx = v > mx ? v : mx;
                 } else {
                     sE += (double)v;
                 }
             }
-            const int db = I.det_tile[tile], de = I.det_tile[tile + 1];
             __syncthreads();
+            const int db = s_det[j], de = s_det[j + 1];
             if (db < de && tid < I.n_det) {
                 for (int e2 = db; e2 < de; ++e2)
-                    if (I.det_id[e2] == tid) dsum += I.det_F[e2] * (double)s_y[I.det_row[e2] - r0];
+                    if (gp(I.det_id)[e2] == tid) dsum += gp(I.det_F)[e2] * (double)s_y[gp(I.det_row)[e2] - r0];
             }
         }
-        // chunk partials, fixed-order tree reductions
+        // chunk partials: wave butterflies, then the waves in order
         const int64_t nc = I.n_chunks, c = item.chunk;
-        const double tN = block_sum(sN, s_red);
-        const double tE = block_sum(sE, s_red);
-        const double tA = block_sum(sA, s_red);
-        const double tM = block_max((double)mx, s_red);
-        if (tid == 0) {
-            I.partials[kSlotN * nc + c] = tN;
-            I.partials[kSlotEsc * nc + c] = tE;
-            I.partials[kSlotAbs * nc + c] = tA;
-            I.partials[kSlotMax * nc + c] = tM;
+        const double wN = wave_sum(sN), wE = wave_sum(sE), wA = wave_sum(sA), wM = wave_max((double)mx);
+        if (lane == 0) {
+            s_wred[0][wave] = wN;
+            s_wred[1][wave] = wE;
+            s_wred[2][wave] = wA;
+            s_wred[3][wave] = wM;
         }
-        if (tid < I.n_det) I.partials[(int64_t)(kSlotDet + tid) * nc + c] = dsum;
+        __syncthreads();
+        GLB double *part = gpw(I.partials);
+        if (tid < 4) {
+            double a = s_wred[tid][0];
+            for (int w = 1; w < NW; ++w) a = (tid == 3) ? fmax(a, s_wred[tid][w]) : a + s_wred[tid][w];
+            part[(int64_t)tid * nc + c] = a;
+        }
+        if (tid < I.n_det) part[(int64_t)(kSlotDet + tid) * nc + c] = dsum;
     }
 }
 
@@ -375,9 +593,12 @@ __global__ void __launch_bounds__(kNT) step_spmm(const StepInst *__restrict__ in
 // ---------------------------------------------------------------------------
 // finalize: fixed-order reduction of the chunk partials, series and control
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kNT) finalize_step(const StepInst *__restrict__ insts)
+__global__ void __launch_bounds__(kNT) finalize_step(const StepInst *__restrict__ insts, int32_t *queue)
 {
     __shared__ double red[kNT];
+    // the step kernel that used the work counter has completed: reset it for
+    // the next step (a kernel store, so the step loop can be graph-captured)
+    if (queue && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *queue = 0;
     const StepInst &I = insts[blockIdx.x];
     const int rhs = blockIdx.y;
     if (rhs >= I.n_rhs) return;
@@ -388,27 +609,30 @@ __global__ void __launch_bounds__(kNT) finalize_step(const StepInst *__restrict_
     const int nr = I.n_rhs;
     const Scale sc = step_scale(I, rhs, t);
     auto slot = [&](int kind) { return I.partials + ((int64_t)kind * nr + rhs) * nc; };
-    double a = 0.0;
-    const double *p = slot(kSlotN);
-    for (int64_t c = tid; c < nc; c += kNT) a += p[c];
-    const double N = block_sum(a, red);
-    a = 0.0;
-    p = slot(kSlotEsc);
-    for (int64_t c = tid; c < nc; c += kNT) a += p[c];
-    const double Esc = block_sum(a, red);
-    a = 0.0;
-    p = slot(kSlotAbs);
-    for (int64_t c = tid; c < nc; c += kNT) a += p[c];
-    const double Abs = block_sum(a, red);
-    a = 0.0;
-    p = slot(kSlotMax);
-    for (int64_t c = tid; c < nc; c += kNT) a = fmax(a, p[c]);
-    const double Mx = block_max(a, red);
+    // each thread sums chunks tid, tid + NT, ... in four interleaved
+    // accumulators (so the loads are independent), then a fixed tree
+    auto reduce = [&](int kind, bool is_max) {
+        const double *p = slot(kind);
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int64_t c = tid;
+        for (; c + 3 * kNT < nc; c += 4 * kNT) {
+            const double v0 = p[c], v1 = p[c + kNT], v2 = p[c + 2 * kNT], v3 = p[c + 3 * kNT];
+            if (is_max) {
+                a0 = fmax(a0, v0); a1 = fmax(a1, v1); a2 = fmax(a2, v2); a3 = fmax(a3, v3);
+            } else {
+                a0 += v0; a1 += v1; a2 += v2; a3 += v3;
+            }
+        }
+        for (; c < nc; c += kNT) a0 = is_max ? fmax(a0, p[c]) : a0 + p[c];
+        const double a = is_max ? fmax(fmax(a0, a1), fmax(a2, a3)) : (a0 + a1) + (a2 + a3);
+        return is_max ? block_max(a, red) : block_sum(a, red);
+    };
+    const double N = reduce(kSlotN, false);
+    const double Esc = reduce(kSlotEsc, false);
+    const double Abs = reduce(kSlotAbs, false);
+    const double Mx = reduce(kSlotMax, true);
     for (int d = 0; d < I.n_det; ++d) {
-        a = 0.0;
-        p = slot(kSlotDet + d);
-        for (int64_t c = tid; c < nc; c += kNT) a += p[c];
-        const double Dd = block_sum(a, red);
+        const double Dd = reduce(kSlotDet + d, false);
         if (tid == 0) I.ser_det[(t * I.n_det + d) * nr + rhs] = Dd;
     }
     if (tid == 0) {
@@ -428,7 +652,7 @@ __global__ void __launch_bounds__(kNT) finalize_step(const StepInst *__restrict_
 
 hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int64_t n_work, int n_inst,
                        int n_rhs_max, int value_f64, int rp64, int spmm, int grid, int xcd_remap,
-                       int rows_per_tile, int n_det_max, hipStream_t stream)
+                       int rows_per_tile, int n_det_max, int32_t *queue, hipStream_t stream)
 {
     (void)n_inst;
     (void)n_rhs_max;
@@ -438,28 +662,58 @@ hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int6
     if (spmm) {
         const size_t lds = (size_t)4 * n_det_max * 64 * sizeof(double);
         if (rp64)
-            hipLaunchKernelGGL(step_spmm<int64_t>, g, b, lds, stream, insts_dev, work_dev, n_work, xcd_remap);
+            hipLaunchKernelGGL(step_spmm<int64_t>, g, b, lds, stream, insts_dev, work_dev, n_work, xcd_remap & 1);
         else
-            hipLaunchKernelGGL(step_spmm<int32_t>, g, b, lds, stream, insts_dev, work_dev, n_work, xcd_remap);
-    } else if (value_f64) {
-        if (rp64)
-            hipLaunchKernelGGL((step_spmv<double, int64_t>), g, b, 0, stream, insts_dev, work_dev, n_work, xcd_remap);
-        else
-            hipLaunchKernelGGL((step_spmv<double, int32_t>), g, b, 0, stream, insts_dev, work_dev, n_work, xcd_remap);
+            hipLaunchKernelGGL(step_spmm<int32_t>, g, b, lds, stream, insts_dev, work_dev, n_work, xcd_remap & 1);
     } else {
-        if (rp64)
-            hipLaunchKernelGGL((step_spmv<float, int64_t>), g, b, 0, stream, insts_dev, work_dev, n_work, xcd_remap);
-        else
-            hipLaunchKernelGGL((step_spmv<float, int32_t>), g, b, 0, stream, insts_dev, work_dev, n_work, xcd_remap);
+        const dim3 g1((unsigned)grid);
+        const int variant = (xcd_remap >> 1) & 3;
+        const int remap = xcd_remap & 1;
+#define DRTS_SPMV1(VT, IT, NTV, RV, P) \
+    hipLaunchKernelGGL((step_spmv<VT, IT, NTV, RV, P>), g1, dim3(NTV), 0, stream, insts_dev, work_dev, n_work, remap, \
+                       queue)
+#define DRTS_SPMV(VT, IT, RV)                                  \
+    do {                                                       \
+        if (variant == 1) DRTS_SPMV1(VT, IT, RV, RV, 1);       \
+        else if (variant == 2) DRTS_SPMV1(VT, IT, 2 * RV, RV, 0); \
+        else if (variant == 3) DRTS_SPMV1(VT, IT, 2 * RV, RV, 1); \
+        else DRTS_SPMV1(VT, IT, RV, RV, 0);                    \
+    } while (0)
+        const int nt = rows_per_tile <= 64 ? 64 : (rows_per_tile <= 128 ? 128 : 256);
+        if (value_f64) {
+            if (rp64) {
+                if (nt == 64) DRTS_SPMV(double, int64_t, 64);
+                else if (nt == 128) DRTS_SPMV(double, int64_t, 128);
+                else DRTS_SPMV(double, int64_t, 256);
+            } else {
+                if (nt == 64) DRTS_SPMV(double, int32_t, 64);
+                else if (nt == 128) DRTS_SPMV(double, int32_t, 128);
+                else DRTS_SPMV(double, int32_t, 256);
+            }
+        } else {
+            if (rp64) {
+                if (nt == 64) DRTS_SPMV(float, int64_t, 64);
+                else if (nt == 128) DRTS_SPMV(float, int64_t, 128);
+                else DRTS_SPMV(float, int64_t, 256);
+            } else {
+                if (nt == 64) DRTS_SPMV(float, int32_t, 64);
+                else if (nt == 128) DRTS_SPMV(float, int32_t, 128);
+                else DRTS_SPMV(float, int32_t, 256);
+            }
+        }
+#undef DRTS_SPMV1
+#undef DRTS_SPMV
     }
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const StepInst *insts_dev, int n_inst, int n_rhs_max, int n_det_max, hipStream_t stream)
+hipError_t launch_finalize(const StepInst *insts_dev, int n_inst, int n_rhs_max, int n_det_max, int32_t *queue,
+                           hipStream_t stream)
 {
     (void)n_det_max;
     if (n_inst <= 0) return hipSuccess;
-    hipLaunchKernelGGL(finalize_step, dim3((unsigned)n_inst, (unsigned)n_rhs_max), dim3(kNT), 0, stream, insts_dev);
+    hipLaunchKernelGGL(finalize_step, dim3((unsigned)n_inst, (unsigned)n_rhs_max), dim3(kNT), 0, stream, insts_dev,
+                       queue);
     return hipGetLastError();
 }
 

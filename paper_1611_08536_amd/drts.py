@@ -97,7 +97,7 @@ class DetectorsT(C.Structure):
 
 class OptionsT(C.Structure):
     _fields_ = [("kernel", i32), ("rows_per_tile", i32), ("tiles_per_chunk", i32), ("grid", i32),
-                ("xcd_remap", i32), ("graph_steps", i32), ("rescale", i32)]
+                ("xcd_remap", i32), ("graph_steps", i32), ("rescale", i32), ("variant", i32), ("queue", i32)]
 
 
 def _sig(name, res, args):

@@ -1,0 +1,138 @@
+"""Many right-hand sides (SpMM), uneven batches and the autotuner, through the C ABI.
+
+Bars: each right-hand side against the FP64 oracle run of its own sources
+(1e-5); each SpMM column against the single-rhs SpMV run of the same source
+(bit-exact state: the per-row sums are the same operations in the same order);
+each batch member against the same solver run alone (bit-exact state and
+series); autotuned launch shapes against the defaults (bit-exact state).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+drts = pytest.importorskip("paper_1611_08536_amd.drts")
+from paper_1611_08536_amd import solve  # noqa: E402
+
+
+def _single(wl, j):
+    """The workload restricted to the sources of rhs j, as one rhs."""
+    import copy
+    w = copy.copy(wl)
+    w.sources = [copy.copy(s) for s in wl.sources if s.rhs == j]
+    for s in w.sources:
+        s.rhs = 0
+    w.n_rhs = 1
+    return w
+
+
+def test_spmm_columns_equal_spmv_runs():
+    wl = W.c3(n=20, k=8, n_steps=80)
+    out = solve.run(wl)
+    for j in (0, 3, 7):
+        one = solve.run(_single(wl, j), matrix=out["matrix"])
+        assert np.array_equal(out["x"][:, j], one["x"][:, 0]), j
+        assert out["x_exp"][j] == one["x_exp"][0]
+        assert np.array_equal(out["exp2"][:, j], one["exp2"][:, 0])
+        assert np.allclose(out["tot"][:, :, j], one["tot"][:, :, 0], rtol=1e-13, atol=0)
+        assert np.allclose(out["det"][:, :, j], one["det"][:, :, 0], rtol=1e-13, atol=0)
+
+
+def test_spmm_64_rhs_against_oracle():
+    wl = W.c3(n=24, k=64, n_steps=60)
+    out = solve.run(wl)
+    A = oracle.Matrix(wl.medium)
+    for j in (0, 17, 40, 63):
+        ref = oracle.run_workload(A, wl, rhs=j)
+        e = out["exp2"][:, j]
+        for d in range(16):
+            err = parity.rel_err_series(out["det"][:, d, j], e, ref["det"][:, d], ref["det_exp"][:, d])
+            assert err <= 1e-5, (j, d, err)
+        for c in range(3):
+            err = parity.rel_err_series(out["tot"][:, c, j], e, ref["tot"][:, c], ref["tot_exp"][:, c])
+            assert err <= 1e-5, (j, c, err)
+        assert parity.rel_l1(out["x"][:A.n_states, j], out["x_exp"][j], ref["x"], ref["x_exp"]) <= 1e-5
+
+
+@pytest.mark.parametrize("opts", [{"rows_per_tile": 16, "tiles_per_chunk": 5, "grid": 40, "xcd_remap": 1},
+                                  {"rows_per_tile": 200, "tiles_per_chunk": 300, "grid": 7, "xcd_remap": 0}])
+def test_spmm_launch_shapes(opts):
+    wl = W.c3(n=16, k=5, n_steps=30)
+    a = solve.run(wl)
+    b = solve.run(wl, options=opts)
+    assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["exp2"], b["exp2"])
+    assert np.allclose(a["det"], b["det"], rtol=1e-13, atol=0)
+
+
+def _c4_small(n_inst=9, edge=(6, 15)):
+    return W.c4(n_inst=n_inst, n_steps=60, edge=edge)
+
+
+def test_batch_members_equal_solo_runs():
+    wls = _c4_small()
+    steps = [60, 45, 60, 10, 33, 60, 1, 59, 20]
+    mats = [drts.Matrix(w.medium, w.value_type, w.rounding, w.n_ref) for w in wls]
+    solvers = [drts.Solver(m, 1, w.detectors, max_steps=60) for m, w in zip(mats, wls)]
+    tabs = [solve.source_table(m, w) for m, w in zip(mats, wls)]
+    B = drts.Batch(solvers)
+    B.run(tabs, steps)
+    for i, (w, m, S) in enumerate(zip(wls, mats, solvers)):
+        solo = solve.run(w, n_steps=steps[i], matrix=m)
+        x, e, t = S.state()
+        assert t == steps[i]
+        assert np.array_equal(x, solo["x"]) and np.array_equal(e, solo["x_exp"]), i
+        r = S.readout(0, steps[i])
+        assert np.array_equal(r["tot"], solo["tot"]) and np.array_equal(r["exp2"], solo["exp2"]), i
+
+
+def test_batch_against_oracle_and_continues():
+    wls = _c4_small(n_inst=5, edge=(8, 12))
+    mats = [drts.Matrix(w.medium, w.value_type, w.rounding, w.n_ref) for w in wls]
+    solvers = [drts.Solver(m, 1, w.detectors, max_steps=60) for m, w in zip(mats, wls)]
+    tabs = [solve.source_table(m, w) for m, w in zip(mats, wls)]
+    B = drts.Batch(solvers)
+    B.run(tabs, [30] * 5)
+    B.run(tabs, [30, 0, 30, 30, 30])      # solver 1 idles, the others continue
+    for i, w in enumerate(wls):
+        A = oracle.Matrix(w.medium)
+        n = 30 if i == 1 else 60
+        ref = oracle.run_workload(A, w, n_steps=n)
+        x, e, t = solvers[i].state()
+        assert t == n
+        r = solvers[i].readout(0, n)
+        err = parity.rel_err_series(r["tot"][:, 0, 0], r["exp2"][:, 0], ref["tot"][:, 0], ref["tot_exp"][:, 0])
+        assert err <= 1e-5, (i, err)
+        assert parity.rel_l1(x[:A.n_states, 0], e[0], ref["x"], ref["x_exp"]) <= 1e-5
+
+
+def test_batch_rejects_mixed_inputs():
+    w32 = W.c4(n_inst=1, n_steps=5, edge=(6, 6))[0]
+    m32 = drts.Matrix(w32.medium, "f32")
+    m64 = drts.Matrix(w32.medium, "f64")
+    s32 = drts.Solver(m32, 1, [], max_steps=5)
+    s64 = drts.Solver(m64, 1, [], max_steps=5)
+    with pytest.raises(drts.DrtsError):
+        drts.Batch([s32, s64])
+    with pytest.raises(drts.DrtsError):
+        drts.Batch([s32, s32])
+
+
+def test_autotune_keeps_results_and_caches(tmp_path):
+    wl = W.c2(n=20, n_steps=30)
+    ref = solve.run(wl)
+    M = drts.Matrix(wl.medium, wl.value_type, wl.rounding, wl.n_ref)
+    S = drts.Solver(M, 1, wl.detectors, max_steps=30)
+    cache = str(tmp_path / "tune.txt")
+    chosen = S.autotune(cache)
+    assert chosen["rows_per_tile"] in (64, 128, 256)
+    S.run(solve.source_table(M, wl), 30)
+    x, e, t = S.state()
+    assert np.array_equal(x, ref["x"]) and np.array_equal(e, ref["x_exp"])
+    assert open(cache).read().strip()
+    S2 = drts.Solver(M, 1, wl.detectors, max_steps=30)
+    again = S2.autotune(cache)
+    assert again == chosen
