@@ -194,7 +194,15 @@ void drts_matrix_destroy(drts_matrix_t *A);
 /* ---- solver ------------------------------------------------------------------- */
 
 #define DRTS_KERNEL_CSR 0        /* CSR SpMV / SpMM over the stored [A; L] */
-#define DRTS_KERNEL_STRUCTURED 1 /* matrix-free: per-voxel direction block */
+#define DRTS_KERNEL_STRUCTURED 1 /* matrix-free: every entry re-derived from the
+                                    per-voxel direction block and rounded as
+                                    stored, so the result equals the CSR step's
+                                    bit for bit (one rhs) */
+#define DRTS_KERNEL_STRUCTURED_SPLIT 2 /* matrix-free with each FP32 value carried
+                                    as a hi + lo pair (about 48-bit values):
+                                    more accurate than either stored rounding,
+                                    equal to the CSR step within rounding (one
+                                    rhs, FP32) */
 
 typedef struct {
     int32_t kernel;       /* DRTS_KERNEL_* */

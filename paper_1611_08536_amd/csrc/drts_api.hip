@@ -140,6 +140,7 @@ struct drts_solver {
     int n_src = 0;
     std::vector<double> amp_h, smax_h;
     StepInst inst_h{};
+    StructArgs sa{};
     std::vector<WorkItem> work_h;
 
     // graph replay
@@ -197,7 +198,39 @@ template <typename E> std::vector<int32_t> tile_offsets(const std::vector<E> &v,
     return off;
 }
 
+// per-tile offsets for explicit tile row boundaries
+template <typename E> std::vector<int32_t> tile_offsets_bounds(const std::vector<E> &v, const std::vector<int64_t> &b)
+{
+    std::vector<int32_t> off(b.size(), 0);
+    size_t e = 0;
+    for (size_t k = 0; k < b.size(); ++k) {
+        while (e < v.size() && v[e].row < b[k]) ++e;
+        off[k] = (int32_t)e;
+    }
+    return off;
+}
+
 bool spmm_of(const drts_solver *S) { return S->n_rhs > 1; }
+bool structured_of(const drts_solver *S) { return S->opt.kernel != DRTS_KERNEL_CSR; }
+
+// Tile row boundaries of the structured kernels: segments of kStructSegLen
+// voxels of every x-line, then the escape rows in tiles of kEscTileRows.
+std::vector<int64_t> structured_bounds(const Model &M, StructArgs *sa)
+{
+    const int L = kStructSegLen;
+    const int segs = (M.nx + L - 1) / L;
+    const int64_t lines = (int64_t)M.ny * M.nz;
+    std::vector<int64_t> b;
+    b.reserve((size_t)(lines * segs + M.n_escape / kEscTileRows + 2));
+    for (int64_t line = 0; line < lines; ++line)
+        for (int sg = 0; sg < segs; ++sg) b.push_back((int64_t)kDirs * (sg * L + (int64_t)M.nx * line));
+    for (int64_t r = M.n_states; r < M.n_rows; r += kEscTileRows) b.push_back(r);
+    b.push_back(M.n_rows);
+    sa->seg_len = L;
+    sa->segs_per_line = segs;
+    sa->n_vox_tiles = lines * segs;
+    return b;
+}
 
 // (Re)builds every structure that depends on the options and the sources.
 int prepare(drts_solver *S)
@@ -206,14 +239,45 @@ int prepare(drts_solver *S)
     Device &dev = S->dev;
     const drts_options_t &o = S->opt;
     int rc;
-    S->n_tiles = (A.model.n_rows + o.rows_per_tile - 1) / o.rows_per_tile;
+    std::vector<int64_t> bounds;
+    if (structured_of(S)) {
+        StructArgs &sa = S->sa;
+        sa.nx = A.model.nx;
+        sa.ny = A.model.ny;
+        sa.nz = A.model.nz;
+        sa.rounding = A.model.rounding;
+        sa.n_states = A.model.n_states;
+        sa.n_rows = A.model.n_rows;
+        sa.mat = A.mat_of_voxel.as<uint8_t>();
+        sa.index = A.index.as<double>();
+        sa.blocks32 = A.blocks32.as<float>();
+        sa.blocks32lo = A.blocks32lo.as<float>();
+        sa.blocks64 = A.blocks64.as<double>();
+        sa.n_mat = (int32_t)A.model.mats.size();
+        sa.irr_row = A.irr_row.as<int64_t>();
+        sa.irr_vox = A.irr_vox.as<int64_t>();
+        sa.irr_dir = A.irr_dir.as<int32_t>();
+        sa.irr_f = A.irr_f.as<double>();
+        sa.irr_bits = A.irr_bits.as<uint32_t>();
+        sa.n_irr = (int64_t)A.model.irr_row.size();
+        sa.escape_state = A.escape_state.as<int64_t>();
+        bounds = structured_bounds(A.model, &sa);
+        S->n_tiles = (int64_t)bounds.size() - 1;
+    } else {
+        S->n_tiles = (A.model.n_rows + o.rows_per_tile - 1) / o.rows_per_tile;
+    }
     S->n_chunks = (S->n_tiles + o.tiles_per_chunk - 1) / o.tiles_per_chunk;
     S->grid = o.grid > 0 ? o.grid : device_cu_count() * (spmm_of(S) ? 4 : 8);
     if (S->n_chunks > INT32_MAX) return set_error(DRTS_E_RANGE, "too many chunks");
 
     // sources and detectors per tile
-    if ((rc = upload_vec(dev, S->src_tile, tile_offsets(S->srcs, S->n_tiles, o.rows_per_tile)))) return rc;
-    if ((rc = upload_vec(dev, S->det_tile, tile_offsets(S->dets, S->n_tiles, o.rows_per_tile)))) return rc;
+    if (structured_of(S)) {
+        if ((rc = upload_vec(dev, S->src_tile, tile_offsets_bounds(S->srcs, bounds)))) return rc;
+        if ((rc = upload_vec(dev, S->det_tile, tile_offsets_bounds(S->dets, bounds)))) return rc;
+    } else {
+        if ((rc = upload_vec(dev, S->src_tile, tile_offsets(S->srcs, S->n_tiles, o.rows_per_tile)))) return rc;
+        if ((rc = upload_vec(dev, S->det_tile, tile_offsets(S->dets, S->n_tiles, o.rows_per_tile)))) return rc;
+    }
     const size_t slots = (size_t)(kSlotDet + S->n_det) * S->n_rhs;
     if ((rc = S->partials.allocate(&dev, slots * (size_t)S->n_chunks * sizeof(double)))) return rc;
 
@@ -388,11 +452,20 @@ int launch_one(drts_solver *S, hipStream_t stream)
         if (!e0 || !e1) return set_error(DRTS_E_HIP, "hipEventCreate failed");
         DRTS_HIP(hipEventRecord(e0, stream));
     }
-    int32_t *queue = (!spmm && S->opt.queue) ? S->queue.as<int32_t>() : nullptr;
-    hipError_t e = launch_step(S->inst_dev.as<StepInst>(), S->work_dev.as<WorkItem>(), S->n_chunks, 1, S->n_rhs,
+    int32_t *queue = (!spmm && S->opt.queue && S->opt.kernel == DRTS_KERNEL_CSR) ? S->queue.as<int32_t>() : nullptr;
+    hipError_t e;
+    if (structured_of(S)) {
+        const bool f64 = A.model.value_type == DRTS_F64;
+        int mode = 2;
+        if (S->opt.kernel == DRTS_KERNEL_STRUCTURED) mode = (f64 || A.model.rounding == DRTS_ROUND_DITHER) ? 0 : 1;
+        e = launch_structured(S->sa, S->inst_dev.as<StepInst>(), S->work_dev.as<WorkItem>(), S->n_chunks, f64, mode,
+                              S->grid, S->opt.xcd_remap, stream);
+    } else {
+    e = launch_step(S->inst_dev.as<StepInst>(), S->work_dev.as<WorkItem>(), S->n_chunks, 1, S->n_rhs,
                                A.model.value_type == DRTS_F64, A.rp64 ? 1 : 0, spmm ? 1 : 0, S->grid,
                                (S->opt.xcd_remap ? 1 : 0) | ((S->opt.variant & 3) << 1), S->opt.rows_per_tile,
                                S->n_det, queue, stream);
+    }
     if (e != hipSuccess) return set_error(DRTS_E_HIP, "step launch failed: %s", hipGetErrorString(e));
     if (e1) DRTS_HIP(hipEventRecord(e1, stream));
     e = launch_finalize(S->inst_dev.as<StepInst>(), 1, S->n_rhs, S->n_det, queue, stream);
@@ -459,10 +532,10 @@ drts_options_t default_options(const drts_solver *S)
 
 int check_options(const drts_solver *S, const drts_options_t *o)
 {
-    if (o->kernel != DRTS_KERNEL_CSR && o->kernel != DRTS_KERNEL_STRUCTURED)
+    if (o->kernel < DRTS_KERNEL_CSR || o->kernel > DRTS_KERNEL_STRUCTURED_SPLIT)
         return set_error(DRTS_E_INVALID, "unknown kernel %d", o->kernel);
-    if (o->kernel == DRTS_KERNEL_STRUCTURED)
-        return set_error(DRTS_E_INVALID, "the structured kernel is not available in this build");
+    if (o->kernel != DRTS_KERNEL_CSR && S->n_rhs != 1)
+        return set_error(DRTS_E_INVALID, "the structured kernel takes one right-hand side");
     if (S->n_rhs == 1) {
         if (o->rows_per_tile != 64 && o->rows_per_tile != 128 && o->rows_per_tile != 256)
             return set_error(DRTS_E_INVALID, "rows_per_tile must be 64, 128 or 256 for one right-hand side");

@@ -80,13 +80,19 @@ hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int6
 hipError_t launch_finalize(const StepInst *insts_dev, int n_inst, int n_rhs_max, int n_det_max, int32_t *queue,
                            hipStream_t stream);
 
-// Matrix-free step over the per-voxel direction blocks (single rhs, FP32).
+// Matrix-free step (single rhs): every row's entries are re-derived from the
+// per-material direction blocks, the irregular-move list and the escape list
+// (the rule the device assembly applies), rounded as the stored values are,
+// and multiplied by x in column order -- the same result as the CSR step.
 struct StructArgs {
     int nx, ny, nz;
+    int rounding;              // DRTS_ROUND_* of the FP32 values
     int64_t n_states, n_rows;
     const uint8_t *mat;
-    const double *index;
-    const float *blocks;       // [q][m][n]
+    const double *index;       // refractive index per material
+    const float *blocks32;     // [q][m][n], nearest-rounded
+    const float *blocks32lo;   // [q][m][n], FP32 of (block - blocks32)
+    const double *blocks64;    // [q][m][n]
     int32_t n_mat;
     const int64_t *irr_row, *irr_vox;
     const int32_t *irr_dir;
@@ -94,8 +100,16 @@ struct StructArgs {
     const uint32_t *irr_bits;
     int64_t n_irr;
     const int64_t *escape_state;
+    // tiling: first the voxel tiles (segments of seg_len voxels of one x-line,
+    // segs_per_line of them per line), then escape tiles of kEscTileRows rows
+    int32_t seg_len, segs_per_line;
+    int64_t n_vox_tiles;
 };
+constexpr int kEscTileRows = 256;
+constexpr int kStructSegLen = 16;
+// mode: 0 = exact values with global gathers, 1 = exact nearest values with
+// the LDS halo, 2 = hi + lo values with the LDS halo
 hipError_t launch_structured(const StructArgs &sa, const StepInst *insts_dev, const WorkItem *work_dev,
-                             int64_t n_work, int grid, int xcd_remap, int rows_per_tile, hipStream_t stream);
+                             int64_t n_work, int value_f64, int mode, int grid, int xcd_remap, hipStream_t stream);
 
 }  // namespace drts

@@ -648,6 +648,337 @@ __global__ void __launch_bounds__(kNT) finalize_step(const StepInst *__restrict_
     }
 }
 
+// ---------------------------------------------------------------------------
+// Matrix-free (structured) step, one right-hand side
+//
+// Row (w, m') of a state takes the plain move of its upstream voxel
+// u = w - e_m' (when u is inside and has w's refractive index) and the
+// irregular moves listed for it; an escape row takes its one leaving move.
+// A move (u, m, f) contributes f C_q(u)[m][n] to column 26 u + n; groups of
+// moves of one voxel are merged per column in FP64 and in ascending m, and
+// each entry is rounded exactly as the assembly stores it, then multiplied
+// by x in ascending column order: the row value equals the CSR row value bit
+// for bit, while the matrix itself never leaves the chip (per row only the
+// upstream voxel's 26 states of x are read, from L2).
+// ---------------------------------------------------------------------------
+constexpr int kStructMatLds = 8;   // direction blocks (hi, lo) kept in LDS up to this many materials
+
+__device__ __forceinline__ uint64_t mix64_dev(uint64_t x)
+{
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// FP64 -> FP32 of a nonnegative value as the assembly stores it
+__device__ __forceinline__ float round_entry(double a, int rounding, int64_t row, int64_t col)
+{
+    float f = (float)a;
+    if (rounding == DRTS_ROUND_DITHER && (double)f != a) {
+        const uint32_t bits = __float_as_uint(f);
+        const float g = __uint_as_float((double)f < a ? bits + 1u : bits - 1u);
+        // |g - f| is a power of two: scaling by its exponent is the exact quotient
+        const double p = ldexp(fabs((double)f - a), -ilogb(fabs((double)g - (double)f)));
+        const uint64_t key = ((uint64_t)row << 32) ^ (uint64_t)(uint32_t)col;
+        const double u = (double)(mix64_dev(key) >> 11) * 0x1p-53;
+        if (u < p) f = g;
+    }
+    return f;
+}
+
+template <typename VT> struct StructVals;
+template <> struct StructVals<float> {
+    // entry of a plain move (factor 1): the block value rounded like the CSR
+    __device__ static float plain(float cf, double cd, int rounding, int64_t row, int64_t col)
+    {
+        return rounding == DRTS_ROUND_DITHER ? round_entry(cd, rounding, row, col) : cf;
+    }
+    __device__ static float merged(double a, int rounding, int64_t row, int64_t col)
+    {
+        return round_entry(a, rounding, row, col);
+    }
+};
+template <> struct StructVals<double> {
+    __device__ static double plain(float, double cd, int, int64_t, int64_t) { return cd; }
+    __device__ static double merged(double a, int, int64_t, int64_t) { return a; }
+};
+
+// Row value from the blocks and move lists, x read from global memory.
+// MODE 2 carries every FP32 value as hi + lo and forms each term as
+// fma(hi, x, lo x): one rounding of the (almost exact) product, so the value
+// rounding error disappears.  Otherwise values are rounded as stored.
+template <typename VT, int MODE>
+__device__ __forceinline__ VT struct_row(const StructArgs &sa, int64_t r, const GLB VT *x)
+{
+    const GLB float *Chi = gp(sa.blocks32);
+    const GLB float *Clo = gp(sa.blocks32lo);
+    const GLB double *Cd = gp(sa.blocks64);
+    const GLB uint8_t *mat = gp(sa.mat);
+    const GLB double *index = gp(sa.index);
+    VT acc = 0;
+    auto plain_group = [&](int64_t u, int m) {
+        const int q = mat[u];
+        const int off = (q * kDirs + m) * kDirs;
+        const GLB VT *xu = x + kDirs * u;
+        VT xv[kDirs];
+#pragma unroll
+        for (int n = 0; n < kDirs; ++n) xv[n] = xu[n];
+#pragma unroll
+        for (int n = 0; n < kDirs; ++n) {
+            if (MODE == 2) {
+                acc += (VT)__builtin_fmaf(Chi[off + n], (float)xv[n], Clo[off + n] * (float)xv[n]);
+            } else {
+                const VT c = StructVals<VT>::plain(Chi[off + n], Cd[off + n], sa.rounding, r, kDirs * u + n);
+                acc += c * xv[n];
+            }
+        }
+    };
+    if (r >= sa.n_states) {
+        const int64_t s = gp(sa.escape_state)[r - sa.n_states];
+        plain_group(s / kDirs, (int)(s % kDirs));
+        return acc;
+    }
+    const int64_t w = r / kDirs;
+    const int mp = (int)(r % kDirs);
+    const int x0 = (int)(w % sa.nx), y0 = (int)((w / sa.nx) % sa.ny), z0 = (int)(w / ((int64_t)sa.nx * sa.ny));
+    const int ux = x0 - dir_dx(mp), uy = y0 - dir_dy(mp), uz = z0 - dir_dz(mp);
+    int64_t ureg = -1;
+    if (ux >= 0 && ux < sa.nx && uy >= 0 && uy < sa.ny && uz >= 0 && uz < sa.nz) {
+        const int64_t u = ux + (int64_t)sa.nx * (uy + (int64_t)sa.ny * uz);
+        if (index[mat[u]] == index[mat[w]]) ureg = u;
+    }
+    int64_t k = 0, kend = 0;
+    const GLB int64_t *irr_row = gp(sa.irr_row), *irr_vox = gp(sa.irr_vox);
+    const GLB int32_t *irr_dir = gp(sa.irr_dir);
+    const GLB double *irr_f = gp(sa.irr_f);
+    if (sa.n_irr > 0 && ((gp(sa.irr_bits)[r >> 5] >> (r & 31)) & 1u)) {
+        int64_t lo = 0, hi = sa.n_irr;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (irr_row[mid] < r) lo = mid + 1;
+            else hi = mid;
+        }
+        k = lo;
+        kend = k;
+        while (kend < sa.n_irr && irr_row[kend] == r) ++kend;
+    }
+    while (k < kend || ureg >= 0) {
+        const int64_t ug = k < kend ? irr_vox[k] : INT64_MAX;
+        if (ureg >= 0 && ureg < ug) {
+            plain_group(ureg, mp);
+            ureg = -1;
+            continue;
+        }
+        int64_t k1 = k;
+        while (k1 < kend && irr_vox[k1] == ug) ++k1;
+        const int q = mat[ug];
+        for (int n = 0; n < kDirs; ++n) {
+            double a = 0.0;
+            for (int64_t kk = k; kk < k1; ++kk) {
+                const double c = Cd[(q * kDirs + irr_dir[kk]) * kDirs + n];
+                if (c != 0.0) a = a + irr_f[kk] * c;
+            }
+            if (a != 0.0) {
+                const VT xv = x[kDirs * ug + n];
+                if (MODE == 2) {
+                    const float h = (float)a, l = (float)(a - (double)h);
+                    acc += (VT)__builtin_fmaf(h, (float)xv, l * (float)xv);
+                } else {
+                    acc += StructVals<VT>::merged(a, sa.rounding, r, kDirs * ug + n) * xv;
+                }
+            }
+        }
+        k = k1;
+    }
+    return acc;
+}
+
+struct StructTile {
+    int64_t row0;
+    int nrows;
+    bool vox;
+    int x0, len;
+    int64_t line;   // y + ny z of a voxel tile
+};
+
+__device__ __forceinline__ StructTile struct_tile(const StructArgs &sa, int64_t k)
+{
+    StructTile T;
+    if (k < sa.n_vox_tiles) {
+        T.line = k / sa.segs_per_line;
+        T.x0 = (int)(k % sa.segs_per_line) * sa.seg_len;
+        T.len = min(sa.seg_len, sa.nx - T.x0);
+        T.row0 = (int64_t)kDirs * (T.x0 + (int64_t)sa.nx * T.line);
+        T.nrows = kDirs * T.len;
+        T.vox = true;
+    } else {
+        T.line = 0;
+        T.x0 = 0;
+        T.len = 0;
+        T.row0 = sa.n_states + (k - sa.n_vox_tiles) * kEscTileRows;
+        T.nrows = (int)min((int64_t)kEscTileRows, sa.n_rows - T.row0);
+        T.vox = false;
+    }
+    return T;
+}
+
+// MODE 0: exact values, x gathered from global memory (FP64, dither).
+// MODE 1: exact nearest values, regular rows read x from an LDS halo.
+// MODE 2: hi + lo values, regular rows read x from an LDS halo.
+// MODE 3: hi + lo values, x gathered from global memory (many materials).
+// A voxel tile is a segment of L voxels of one x-line; the halo holds the x
+// blocks of the 3 x 3 neighbouring line segments (L + 2 voxels each), loaded
+// with contiguous reads, since a regular row's upstream voxel is one of them.
+template <typename VT, int MODE>
+__global__ void __launch_bounds__(256) step_struct(StructArgs sa, const StepInst *__restrict__ insts,
+                                                    const WorkItem *__restrict__ work, int64_t n_work,
+                                                    int xcd_remap)
+{
+    constexpr int NT = 256, NW = NT / 64, L = kStructSegLen;
+    constexpr int HV = L + 2;                       // voxels per halo line segment
+    constexpr int ROWS = kDirs * L > kEscTileRows ? kDirs * L : kEscTileRows;
+    extern __shared__ double s_dyn[];
+    __shared__ uint8_t s_q[9 * HV];
+    __shared__ int32_t s_src[kChunkMax + 1];
+    __shared__ int32_t s_det[kChunkMax + 1];
+    __shared__ double s_abs[kMatMax];
+    __shared__ double s_idx[kMatMax];
+    __shared__ VT s_y[ROWS];
+    __shared__ double s_wred[4][NW];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr bool HALO = MODE == 1 || MODE == 2;
+    const int nblk = sa.n_mat * kDirs * kDirs;
+    // halo modes: the blocks (hi, lo) and the halo in dynamic LDS
+    float *s_Chi = (float *)s_dyn;
+    float *s_Clo = s_Chi + nblk;
+    float *s_x = s_Clo + nblk;
+    if (HALO) {
+        for (int i = tid; i < nblk; i += NT) {
+            s_Chi[i] = gp(sa.blocks32)[i];
+            s_Clo[i] = gp(sa.blocks32lo)[i];
+        }
+    }
+    for (int q = tid; q < sa.n_mat; q += NT) s_idx[q] = gp(sa.index)[q];
+    __syncthreads();
+    const Walk wk = walk_of(n_work, xcd_remap);
+    for (int64_t wi = wk.begin; wi < wk.end; wi += wk.stride) {
+        const WorkItem item = work[wi];
+        const StepInst &I = insts[item.inst];
+        const int64_t t = I.t[0];
+        if (t >= *I.t_end) continue;
+        const Scale sc = step_scale(I, 0, t);
+        const VT scale = (VT)ldexp(1.0, -sc.k);
+        const GLB VT *x = gp((const VT *)((t & 1) ? I.buf1 : I.buf0));
+        GLB VT *y = gpw((VT *)((t & 1) ? I.buf0 : I.buf1));
+        const int64_t n_states = I.n_states;
+        const int64_t tile0 = (int64_t)item.chunk * I.tiles_per_chunk;
+        const int ntc = (int)min((int64_t)I.tiles_per_chunk, I.n_tiles - tile0);
+        for (int j = tid; j <= ntc; j += NT) {
+            s_src[j] = gp(I.src_tile)[tile0 + j];
+            s_det[j] = gp(I.det_tile)[tile0 + j];
+        }
+        for (int q = tid; q < I.n_mat; q += NT) s_abs[q] = gp(I.absorb)[q];
+        __syncthreads();
+        double sN = 0.0, sE = 0.0, sA = 0.0, dsum = 0.0;
+        VT mx = 0;
+        for (int j = 0; j < ntc; ++j) {
+            const StructTile T = struct_tile(sa, tile0 + j);
+            const bool halo = HALO && T.vox;
+            if (halo) {
+                const int yv0 = (int)(T.line % sa.ny), zv0 = (int)(T.line / sa.ny);
+                const int segw = (T.len + 2) * kDirs;
+                for (int idx = tid; idx < 9 * segw; idx += NT) {
+                    const int sg = idx / segw, rem = idx - sg * segw;
+                    const int iv = rem / kDirs, n = rem - iv * kDirs;
+                    const int xv = T.x0 - 1 + iv, yv = yv0 + sg % 3 - 1, zv = zv0 + sg / 3 - 1;
+                    float v = 0.f;
+                    if (xv >= 0 && xv < sa.nx && yv >= 0 && yv < sa.ny && zv >= 0 && zv < sa.nz)
+                        v = (float)x[(int64_t)kDirs * (xv + (int64_t)sa.nx * (yv + (int64_t)sa.ny * zv)) + n];
+                    s_x[(sg * HV + iv) * kDirs + n] = v;
+                }
+                for (int idx = tid; idx < 9 * (T.len + 2); idx += NT) {
+                    const int sg = idx / (T.len + 2), iv = idx - sg * (T.len + 2);
+                    const int xv = T.x0 - 1 + iv, yv = yv0 + sg % 3 - 1, zv = zv0 + sg / 3 - 1;
+                    uint8_t q = 255;
+                    if (xv >= 0 && xv < sa.nx && yv >= 0 && yv < sa.ny && zv >= 0 && zv < sa.nz)
+                        q = gp(sa.mat)[xv + (int64_t)sa.nx * (yv + (int64_t)sa.ny * zv)];
+                    s_q[sg * HV + iv] = q;
+                }
+                __syncthreads();
+            }
+            for (int lr = tid; lr < T.nrows; lr += NT) {
+                const int64_t r = T.row0 + lr;
+                VT acc;
+                const bool irr = T.vox && sa.n_irr > 0 && ((gp(sa.irr_bits)[r >> 5] >> (r & 31)) & 1u);
+                if (halo && !irr) {
+                    const int i = lr / kDirs, mp = lr - i * kDirs;
+                    const int sg = (1 - dir_dz(mp)) * 3 + (1 - dir_dy(mp));
+                    const int ix = i - dir_dx(mp) + 1;
+                    const int qu = s_q[sg * HV + ix], qw = s_q[4 * HV + i + 1];
+                    acc = 0;
+                    if (qu != 255 && s_idx[qu] == s_idx[qw]) {
+                        const float *xs = s_x + (sg * HV + ix) * kDirs;
+                        const int off = (qu * kDirs + mp) * kDirs;
+#pragma unroll
+                        for (int n = 0; n < kDirs; ++n) {
+                            if (MODE == 2) acc += (VT)__builtin_fmaf(s_Chi[off + n], xs[n], s_Clo[off + n] * xs[n]);
+                            else acc += (VT)(s_Chi[off + n] * xs[n]);
+                        }
+                    }
+                } else {
+                    acc = struct_row<VT, (MODE == 2 || MODE == 3) ? 2 : 0>(sa, r, x);
+                }
+                VT v = acc * scale;
+                const int sb = s_src[j], se = s_src[j + 1];
+                if (sb < se) {
+                    int e2 = lower_bound_rows<int32_t>(I.src_row, sb, se, r);
+                    double s = 0.0;
+                    bool any = false;
+                    for (; e2 < se && gp(I.src_row)[e2] == r; ++e2) {
+                        s += gp(I.src_w)[e2] * gp(I.amp)[t * I.n_src + gp(I.src_id)[e2]];
+                        any = true;
+                    }
+                    if (any) v += (VT)ldexp(s, -sc.En);
+                }
+                y[r] = v;
+                s_y[lr] = v;
+                if (r < n_states) {
+                    sN += (double)v;
+                    sA += s_abs[gp(sa.mat)[r / kDirs]] * (double)v;
+                    mx = v > mx ? v : mx;
+                } else {
+                    sE += (double)v;
+                }
+            }
+            __syncthreads();
+            const int db = s_det[j], de = s_det[j + 1];
+            if (db < de && tid < I.n_det) {
+                for (int e2 = db; e2 < de; ++e2)
+                    if (gp(I.det_id)[e2] == tid) dsum += gp(I.det_F)[e2] * (double)s_y[gp(I.det_row)[e2] - T.row0];
+            }
+            __syncthreads();
+        }
+        const int64_t nc = I.n_chunks, c = item.chunk;
+        const double wN = wave_sum(sN), wE = wave_sum(sE), wA = wave_sum(sA), wM = wave_max((double)mx);
+        if (lane == 0) {
+            s_wred[0][wave] = wN;
+            s_wred[1][wave] = wE;
+            s_wred[2][wave] = wA;
+            s_wred[3][wave] = wM;
+        }
+        __syncthreads();
+        GLB double *part = gpw(I.partials);
+        if (tid < 4) {
+            double a = s_wred[tid][0];
+            for (int w = 1; w < NW; ++w) a = (tid == 3) ? fmax(a, s_wred[tid][w]) : a + s_wred[tid][w];
+            part[(int64_t)tid * nc + c] = a;
+        }
+        if (tid < I.n_det) part[(int64_t)(kSlotDet + tid) * nc + c] = dsum;
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int64_t n_work, int n_inst,
@@ -703,6 +1034,31 @@ hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int6
         }
 #undef DRTS_SPMV1
 #undef DRTS_SPMV
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_structured(const StructArgs &sa, const StepInst *insts_dev, const WorkItem *work_dev,
+                             int64_t n_work, int value_f64, int mode, int grid, int xcd_remap, hipStream_t stream)
+{
+    if (n_work <= 0) return hipSuccess;
+    // the halo modes keep every direction block in LDS
+    if (sa.n_mat > kStructMatLds) mode = (mode == 2) ? 3 : 0;
+    const size_t blk = (size_t)sa.n_mat * kDirs * kDirs * 2 * sizeof(float);
+    const size_t halo = (size_t)9 * (kStructSegLen + 2) * kDirs * sizeof(float);
+    const dim3 g((unsigned)grid), b(256);
+    if (value_f64) {
+        hipLaunchKernelGGL((step_struct<double, 0>), g, b, 0, stream, sa, insts_dev, work_dev, n_work, xcd_remap & 1);
+    } else if (mode == 0) {
+        hipLaunchKernelGGL((step_struct<float, 0>), g, b, 0, stream, sa, insts_dev, work_dev, n_work, xcd_remap & 1);
+    } else if (mode == 1) {
+        hipLaunchKernelGGL((step_struct<float, 1>), g, b, blk + halo, stream, sa, insts_dev, work_dev, n_work,
+                           xcd_remap & 1);
+    } else if (mode == 2) {
+        hipLaunchKernelGGL((step_struct<float, 2>), g, b, blk + halo, stream, sa, insts_dev, work_dev, n_work,
+                           xcd_remap & 1);
+    } else {
+        hipLaunchKernelGGL((step_struct<float, 3>), g, b, 0, stream, sa, insts_dev, work_dev, n_work, xcd_remap & 1);
     }
     return hipGetLastError();
 }

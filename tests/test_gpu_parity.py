@@ -258,3 +258,63 @@ def test_errors_are_reported():
     with pytest.raises(drts.DrtsError) as ei:
         drts.Matrix(bad)
     assert ei.value.rc == -1
+
+
+# ---- structured (matrix-free) step -------------------------------------------------
+
+def _struct_workload(name):
+    if name == "c2_dither":
+        return W.c2(n=20)
+    if name == "c2_nearest":
+        return W.c2(n=18, rounding="nearest")
+    if name.startswith("c5_sphere"):
+        wl = W.c5(n_req=1, edge=(21, 21))[0].workload
+        if name.endswith("nearest"):
+            wl.rounding = "nearest"
+        return wl
+    if name == "c1_f64":
+        return W.c1(n=12)
+    med = W.layered(9, [W.Material(5, 0.1, 0.8, 1.33), W.Material(15, 0.2, 0.9, 1.45),
+                        W.Material(10, 0.1, 0.3, 1.4)], bc="reflect")
+    rnd = "nearest" if name.endswith("nearest") else "dither"
+    return W.Workload("reflect", med, [W.point_source(4, 4, 0)], [], 150, 1, "f32", rnd, 1.33)
+
+
+@pytest.mark.parametrize("wl_name", ["c2_dither", "c2_nearest", "c5_sphere", "c5_sphere_nearest", "c1_f64",
+                                     "reflect", "reflect_nearest"])
+def test_structured_equals_csr(wl_name):
+    """The matrix-free kernel re-derives every entry exactly as assembled:
+    states and step exponents equal the CSR run bit for bit (nearest values go
+    through the LDS halo path, FP64 and dithered values through the gather
+    path)."""
+    wl = _struct_workload(wl_name)
+    n = 45
+    a = solve.run(wl, n_steps=n)
+    b = solve.run(wl, n_steps=n, options={"kernel": 1, "tiles_per_chunk": 3}, matrix=a["matrix"])
+    assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["x_exp"], b["x_exp"])
+    assert np.array_equal(a["exp2"], b["exp2"])
+    assert np.allclose(a["tot"], b["tot"], rtol=1e-13, atol=0)
+    assert np.allclose(a["det"], b["det"], rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("wl_name", ["c2_dither", "c5_sphere", "reflect"])
+def test_structured_split_against_oracle(wl_name):
+    """hi + lo values: against the FP64 oracle at the FP32 tolerance, and closer
+    to it than the stored-value (dithered) CSR run."""
+    wl = _struct_workload(wl_name)
+    n = 150
+    A = oracle.Matrix(wl.medium)
+    ref = oracle.run_workload(A, wl, n_steps=n)
+    csr = solve.run(wl, n_steps=n)
+    spl = solve.run(wl, n_steps=n, options={"kernel": 2}, matrix=csr["matrix"])
+    D = A.n_states
+    e_csr = parity.rel_l1(csr["x"][:D, 0], csr["x_exp"][0], ref["x"], ref["x_exp"])
+    e_spl = parity.rel_l1(spl["x"][:D, 0], spl["x_exp"][0], ref["x"], ref["x_exp"])
+    print(wl_name, "state rel L1: csr", e_csr, "split", e_spl)
+    assert e_spl <= 1e-5 and e_spl <= e_csr * 1.5
+    for j in range(3):
+        err = parity.rel_err_series(spl["tot"][:, j, 0], spl["exp2"][:, 0], ref["tot"][:, j], ref["tot_exp"][:, j])
+        assert err <= 1e-5, (j, err)
+    for d in range(len(wl.detectors)):
+        err = parity.rel_err_series(spl["det"][:, d, 0], spl["exp2"][:, 0], ref["det"][:, d], ref["det_exp"][:, d])
+        assert err <= 1e-5, (d, err)
