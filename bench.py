@@ -23,6 +23,70 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+STEP_SOURCES = ("paper_1611_08536_amd/csrc/drts_step.hip", "paper_1611_08536_amd/csrc/drts_step.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_spmv_c2_traffic.txt")
+SPMV_KERNEL = "step_spmv<float, int, 256, 256, 0>"
+CALIB_KERNEL = "vectorized_elementwise_kernel"
+CALIB_BYTES = 2 ** 30          # the calibration kernel reads and writes 1 GiB
+
+
+def step_source_hash():
+    """sha256 of the step kernel sources: counters taken on other sources are stale."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in STEP_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _counter_means(path, counter):
+    """Mean per-dispatch value of one counter, by kernel name, from a rocprofv3
+    counter_collection.csv (values in KiB for FETCH_SIZE and WRITE_SIZE)."""
+    import csv
+    sums = {}
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        k = r["Kernel_Name"]
+        a = sums.setdefault(k, [0.0, 0])
+        a[0] += float(r["Counter_Value"])
+        a[1] += 1
+    return {k: v[0] / v[1] for k, v in sums.items()}
+
+
+def traffic_from_counters(fetch_csv, write_csv):
+    """HBM bytes per launch of the SpMV step from the FETCH_SIZE and WRITE_SIZE
+    passes, each scaled by what the same counter reads for a plain elementwise
+    kernel that reads and writes CALIB_BYTES."""
+    out = {}
+    for name, path in (("fetch", fetch_csv), ("write", write_csv)):
+        m = _counter_means(path, "FETCH_SIZE" if name == "fetch" else "WRITE_SIZE")
+        spmv = [v for k, v in m.items() if SPMV_KERNEL in k]
+        calib = [v for k, v in m.items() if CALIB_KERNEL in k]
+        if len(spmv) != 1 or not calib:
+            raise SystemExit("counter file %s lacks the step or the calibration kernel" % path)
+        factor = CALIB_BYTES / (max(calib) * 1024.0)
+        out[name + "_kib"] = spmv[0]
+        out[name + "_factor"] = round(factor, 4)
+        out[name + "_bytes"] = spmv[0] * 1024.0 * factor
+    out["bytes_per_launch"] = out["fetch_bytes"] + out["write_bytes"]
+    out["kernel"] = SPMV_KERNEL
+    out["source_sha256"] = step_source_hash()
+    return out
+
+
+def load_traffic():
+    """Traffic of the committed counter summary, or None when it is missing or
+    was taken on other kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    line = [ln for ln in open(TRAFFIC_FILE).read().splitlines() if ln.startswith("{")]
+    if not line:
+        return None
+    d = json.loads(line[-1])
+    if d.get("source_sha256") != step_source_hash():
+        return None
+    return d["bytes_per_launch"]
 
 
 def spmv_bytes(nnz, n_rows, n_states, val_bytes=4):
@@ -54,11 +118,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--n", type=int, default=128, help="grid edge (128 = the headline workload)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--traffic", type=str, default=None, help="JSON file with rocprof FETCH/WRITE bytes")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the run, launch an elementwise kernel that reads and writes 1 GiB (counter scale)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
+                    help="print the traffic JSON line from two rocprofv3 --pmc counter files and exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        print(json.dumps(traffic_from_counters(*args.traffic_from)))
+        return
     if args.gpus != 1:
-        print("this build runs on one GPU only (see DESIGN.md: how the step would shard); "
-              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        print("the step runs on one GPU: --gpus %d is not supported (a multi-GPU run would give "
+              "each GPU its own slab of voxels and exchange halo planes)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -95,9 +165,14 @@ def main():
 
     nbytes = spmv_bytes(A.nnz, A.n_rows, A.n_states)
     achieved = nbytes / (avg_kernel_ms * 1e-3) / 1e9
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        traffic = json.load(open(args.traffic)).get("bytes_per_launch")
+    traffic = load_traffic()
+    if args.copy_calibration:
+        a = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.add(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
     line = {
         "metric": "DRTS step GNNZ/s & % HBM peak; batched solves/s + p99 latency vs plain",
         "value": round(A.nnz * args.steps / (ms_total * 1e-3) / 1e9, 3),
@@ -115,9 +190,9 @@ def main():
                                "Gaussian 100 fs top-face source, 2 detectors" % args.n,
                    "n_states": A.n_states, "n_rows": A.n_rows, "nnz": A.nnz, "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None if traffic is None else round(traffic / 1e9, 3),
                      "kernel": "step_spmv<float,int32>", "kernel_ms": round(avg_kernel_ms, 4),
-                     "algorithmic_bytes": nbytes},
+                     "algorithmic_bytes": nbytes, "traffic_unit": "GB per launch"},
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()

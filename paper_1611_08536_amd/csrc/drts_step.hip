@@ -886,24 +886,37 @@ __global__ void __launch_bounds__(256) step_struct(StructArgs sa, const StepInst
             const StructTile T = struct_tile(sa, tile0 + j);
             const bool halo = HALO && T.vox;
             if (halo) {
+                // every load is issued before the first LDS store: coordinates
+                // are clamped into the grid and voxels outside it stored as zero
+                constexpr int SEGW = HV * kDirs;              // floats per halo line segment
+                constexpr int TOT = 9 * SEGW;
+                constexpr int PER = (TOT + NT - 1) / NT;
                 const int yv0 = (int)(T.line % sa.ny), zv0 = (int)(T.line / sa.ny);
-                const int segw = (T.len + 2) * kDirs;
-                for (int idx = tid; idx < 9 * segw; idx += NT) {
-                    const int sg = idx / segw, rem = idx - sg * segw;
+                float hv[PER];
+#pragma unroll
+                for (int k = 0; k < PER; ++k) {
+                    const int idx = min(tid + k * NT, TOT - 1);
+                    const int sg = idx / SEGW, rem = idx - sg * SEGW;
                     const int iv = rem / kDirs, n = rem - iv * kDirs;
                     const int xv = T.x0 - 1 + iv, yv = yv0 + sg % 3 - 1, zv = zv0 + sg / 3 - 1;
-                    float v = 0.f;
-                    if (xv >= 0 && xv < sa.nx && yv >= 0 && yv < sa.ny && zv >= 0 && zv < sa.nz)
-                        v = (float)x[(int64_t)kDirs * (xv + (int64_t)sa.nx * (yv + (int64_t)sa.ny * zv)) + n];
-                    s_x[(sg * HV + iv) * kDirs + n] = v;
+                    const bool in = xv >= 0 && xv < sa.nx && yv >= 0 && yv < sa.ny && zv >= 0 && zv < sa.nz;
+                    const int xc = min(max(xv, 0), sa.nx - 1), yc = min(max(yv, 0), sa.ny - 1);
+                    const int zc = min(max(zv, 0), sa.nz - 1);
+                    const float v = (float)x[(int64_t)kDirs * (xc + (int64_t)sa.nx * (yc + (int64_t)sa.ny * zc)) + n];
+                    hv[k] = in ? v : 0.f;
                 }
-                for (int idx = tid; idx < 9 * (T.len + 2); idx += NT) {
-                    const int sg = idx / (T.len + 2), iv = idx - sg * (T.len + 2);
+#pragma unroll
+                for (int k = 0; k < PER; ++k) {
+                    const int idx = tid + k * NT;
+                    if (idx < TOT) s_x[idx] = hv[k];
+                }
+                if (tid < 9 * HV) {
+                    const int sg = tid / HV, iv = tid - sg * HV;
                     const int xv = T.x0 - 1 + iv, yv = yv0 + sg % 3 - 1, zv = zv0 + sg / 3 - 1;
                     uint8_t q = 255;
                     if (xv >= 0 && xv < sa.nx && yv >= 0 && yv < sa.ny && zv >= 0 && zv < sa.nz)
                         q = gp(sa.mat)[xv + (int64_t)sa.nx * (yv + (int64_t)sa.ny * zv)];
-                    s_q[sg * HV + iv] = q;
+                    s_q[tid] = q;
                 }
                 __syncthreads();
             }
