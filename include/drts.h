@@ -163,6 +163,7 @@ typedef struct {
 typedef struct drts_matrix drts_matrix_t;
 typedef struct drts_solver drts_solver_t;
 typedef struct drts_batch drts_batch_t;
+typedef struct drts_server drts_server_t;
 
 /* ---- matrix ------------------------------------------------------------------- */
 
@@ -209,7 +210,11 @@ typedef struct {
     int32_t rows_per_tile; /* rows a workgroup reduces per tile (64..256) */
     int32_t tiles_per_chunk; /* tiles whose sums form one FP64 partial */
     int32_t grid;         /* persistent workgroups (0 = from the device) */
-    int32_t xcd_remap;    /* 1 = give each XCD a contiguous range of chunks */
+    int32_t xcd_remap;    /* 0 = workgroups walk the chunks round robin;
+                             1 = each XCD takes a contiguous range of chunks
+                             in row order; 2 = as 1, with the chunks ordered
+                             so that each XCD's range is one slab of y lines
+                             swept in z (its x gathers stay in its L2) */
     int32_t graph_steps;  /* steps captured per hipGraph replay (0 = eager) */
     int32_t rescale;      /* 1 = power-of-two rescale every step (default) */
     int32_t variant;      /* one rhs only: DRTS_SPMV_ROW (a thread per row),
@@ -287,6 +292,65 @@ int drts_batch_create(drts_solver_t *const *solvers, int32_t n, const drts_devic
 int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const int64_t *n_steps);
 
 void drts_batch_destroy(drts_batch_t *B);
+
+/* ---- serving: continuous batching of independent solves ----------------------- */
+
+/* A request loop over the uneven batch, for many media solved at once.
+ * Submitted requests wait in arrival order.  Each tick
+ *   1. admits waiting requests whose HBM footprint fits the budget beside the
+ *      requests already admitted, first-fit in arrival order (a request that
+ *      has been passed over max_skips times stops later ones from being
+ *      admitted ahead of it), and assembles their matrices on the device;
+ *   2. advances every admitted request by up to `quantum` steps in batched
+ *      launches: one launch per step covers all of them, so their work
+ *      overlaps on the device;
+ *   3. retires the requests that have finished: their series go to host
+ *      memory and their device memory is freed, which lets the next tick
+ *      admit more.
+ * The footprint of a request is its matrix [A; L] (an upper bound from the
+ * medium before assembly, the exact size after), two state buffers, its
+ * series and its source table.  Results equal those of the same solve run
+ * alone (drts_run), bit for bit.  budget_bytes > 0; 1 <= quantum <= 100000;
+ * 1 <= max_active <= 4096; max_skips >= 0.  Calls on one server must not
+ * overlap. */
+int drts_serve_create(const drts_device_t *dev, int64_t budget_bytes, int32_t quantum, int32_t max_active,
+                      int32_t max_skips, drts_server_t **out);
+
+/* Queues one solve of n_steps steps: an FP32 medium (its host arrays are
+ * copied), its sources (the table must stay valid until the request has
+ * finished) and detectors (copied; NULL for none).  DRTS_E_NOMEM when the
+ * request's footprint exceeds the whole budget; DRTS_E_INVALID for an FP64
+ * medium or a malformed argument. */
+int drts_serve_submit(drts_server_t *Q, const drts_medium_t *medium, const drts_source_table_t *src,
+                      const drts_detectors_t *det, int64_t n_steps, int64_t *request_id);
+
+/* The footprint bound drts_serve_submit admits a request by, without
+ * queueing it (host work only: no device memory is touched). */
+int drts_serve_footprint(const drts_medium_t *medium, const drts_source_table_t *src, const drts_detectors_t *det,
+                         int64_t n_steps, int64_t *bytes);
+
+/* One tick (admit, run one quantum, retire); returns once the quantum's
+ * launches have completed.  Outputs (each may be NULL): requests admitted
+ * and waiting after the tick, requests finished during it, and the device
+ * bytes the admitted requests hold. */
+int drts_serve_tick(drts_server_t *Q, int32_t *n_active, int32_t *n_waiting, int32_t *n_finished,
+                    int64_t *bytes_in_use);
+
+/* Ids of finished requests not reported before, in the order they finished;
+ * at most cap of them, *n_out receives the count. */
+int drts_serve_poll(drts_server_t *Q, int64_t *ids, int32_t cap, int32_t *n_out);
+
+/* Series of a finished request over all its steps, laid out as in
+ * drts_detector_readout (series [n_steps][n_det], exp2 [n_steps], totals
+ * [n_steps][3]); any output may be NULL.  DRTS_E_STATE before it finishes,
+ * DRTS_E_INVALID for an unknown or released id. */
+int drts_serve_result(const drts_server_t *Q, int64_t request_id, double *series, int32_t *exp2,
+                      double *totals);
+
+/* Forgets a finished request (its host copy of the results). */
+int drts_serve_release(drts_server_t *Q, int64_t request_id);
+
+void drts_serve_destroy(drts_server_t *Q);
 
 /* ---- autotuning ------------------------------------------------------------------- */
 

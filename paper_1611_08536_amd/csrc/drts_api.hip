@@ -125,7 +125,7 @@ struct drts_solver {
     int64_t n_tiles = 0, n_chunks = 0;
     int64_t t_host = 0;
 
-    Buffer buf0, buf1, ctl_t, ctl_E, ctl_M, ctl_abs, t_end, partials;
+    Buffer buf0, buf1, ctl_t, ctl_E, ctl_M, ctl_abs, t_end, partials, fin_ticket;
     Buffer ser_tot, ser_det, ser_exp, ser_abs_exp, amp, smax;
     Buffer src_tile, src_row, src_id, src_rhs, src_w;
     Buffer det_tile, det_row, det_id, det_F;
@@ -232,6 +232,35 @@ std::vector<int64_t> structured_bounds(const Model &M, StructArgs *sa)
     return b;
 }
 
+// XCD-aware order of a solver's chunks.  With the remapped walk, XCD i takes
+// the i-th eighth of the work list; this order makes that eighth one slab of
+// y lines (ny / 8 of them) swept in z, so the x values a chunk gathers (the
+// 26 neighbours of its voxels) come from a few planes of its own slab and stay
+// in that XCD's L2 while the neighbouring chunks use them.  Escape chunks sit
+// beside the voxels they leave from.  Only the order of the list changes:
+// every chunk keeps its own partials, so results are the same bit for bit.
+constexpr int kXcdCount = 8;
+void order_by_slabs(drts_solver *S, const std::vector<int64_t> &bounds)
+{
+    const Model &M = S->A->m.model;
+    const int64_t tpc = S->opt.tiles_per_chunk, rpt = S->opt.rows_per_tile;
+    std::vector<std::pair<uint64_t, int32_t>> key((size_t)S->n_chunks);
+    for (int64_t c = 0; c < S->n_chunks; ++c) {
+        const int64_t r0 = bounds.empty() ? c * tpc * rpt : bounds[(size_t)(c * tpc)];
+        const bool esc = r0 >= M.n_states;
+        const int64_t v = (esc ? M.escape_state[(size_t)(r0 - M.n_states)] : r0) / kDirs;
+        const int64_t x = v % M.nx, y = (v / M.nx) % M.ny, z = v / ((int64_t)M.nx * M.ny);
+        const int64_t slab = y * kXcdCount / M.ny;
+        const uint64_t k = ((((uint64_t)slab * M.nz + z) * M.ny + y) * M.nx + x) * 2 + (esc ? 1 : 0);
+        key[(size_t)c] = {k, (int32_t)c};
+    }
+    std::stable_sort(key.begin(), key.end(),
+                     [](const std::pair<uint64_t, int32_t> &a, const std::pair<uint64_t, int32_t> &b) {
+                         return a.first < b.first;
+                     });
+    for (size_t i = 0; i < key.size(); ++i) S->work_h[i] = {0, key[i].second};
+}
+
 // (Re)builds every structure that depends on the options and the sources.
 int prepare(drts_solver *S)
 {
@@ -279,7 +308,9 @@ int prepare(drts_solver *S)
         if ((rc = upload_vec(dev, S->det_tile, tile_offsets(S->dets, S->n_tiles, o.rows_per_tile)))) return rc;
     }
     const size_t slots = (size_t)(kSlotDet + S->n_det) * S->n_rhs;
-    if ((rc = S->partials.allocate(&dev, slots * (size_t)S->n_chunks * sizeof(double)))) return rc;
+    if ((rc = S->partials.allocate(&dev, slots * (size_t)(S->n_chunks + kFinSeg) * sizeof(double)))) return rc;
+    if ((rc = S->fin_ticket.allocate(&dev, (size_t)S->n_rhs * sizeof(int32_t)))) return rc;
+    DRTS_HIP(hipMemsetAsync(S->fin_ticket.ptr, 0, (size_t)S->n_rhs * sizeof(int32_t), dev.stream));
 
     StepInst &I = S->inst_h;
     memset(&I, 0, sizeof I);
@@ -321,6 +352,7 @@ int prepare(drts_solver *S)
     I.max_steps = S->max_steps;
     I.partials = S->partials.as<double>();
     I.n_chunks = S->n_chunks;
+    I.fin_ticket = S->fin_ticket.as<int32_t>();
     I.ser_tot = S->ser_tot.as<double>();
     I.ser_det = S->ser_det.as<double>();
     I.ser_exp = S->ser_exp.as<int32_t>();
@@ -329,6 +361,7 @@ int prepare(drts_solver *S)
 
     S->work_h.resize((size_t)S->n_chunks);
     for (int64_t c = 0; c < S->n_chunks; ++c) S->work_h[(size_t)c] = {0, (int32_t)c};
+    if (o.xcd_remap == 2) order_by_slabs(S, bounds);
     if ((rc = upload_vec(dev, S->work_dev, S->work_h))) return rc;
     drop_graph(S);
     DRTS_HIP(hipStreamSynchronize(dev.stream));
@@ -459,7 +492,7 @@ int launch_one(drts_solver *S, hipStream_t stream)
         int mode = 2;
         if (S->opt.kernel == DRTS_KERNEL_STRUCTURED) mode = (f64 || A.model.rounding == DRTS_ROUND_DITHER) ? 0 : 1;
         e = launch_structured(S->sa, S->inst_dev.as<StepInst>(), S->work_dev.as<WorkItem>(), S->n_chunks, f64, mode,
-                              S->grid, S->opt.xcd_remap, stream);
+                              S->grid, S->opt.xcd_remap ? 1 : 0, stream);
     } else {
     e = launch_step(S->inst_dev.as<StepInst>(), S->work_dev.as<WorkItem>(), S->n_chunks, 1, S->n_rhs,
                                A.model.value_type == DRTS_F64, A.rp64 ? 1 : 0, spmm ? 1 : 0, S->grid,
@@ -548,6 +581,7 @@ int check_options(const drts_solver *S, const drts_options_t *o)
             return set_error(DRTS_E_INVALID, "tiles_per_chunk in 1..2^20");
     }
     if (o->queue != 0 && o->queue != 1) return set_error(DRTS_E_INVALID, "queue must be 0 or 1");
+    if (o->xcd_remap < 0 || o->xcd_remap > 2) return set_error(DRTS_E_INVALID, "xcd_remap must be 0, 1 or 2");
     if (o->variant < DRTS_SPMV_ROW || o->variant > DRTS_SPMV_HALF_PIPE)
         return set_error(DRTS_E_INVALID, "unknown variant %d", o->variant);
     if (o->grid < 0 || o->graph_steps < 0 || o->graph_steps > 4096)
@@ -1125,7 +1159,7 @@ int drts_autotune(drts_solver_t *S, const char *cache_path, drts_options_t *chos
     for (int r : rows_opts)
         for (int c : chunk_opts)
             for (int g : grid_mult)
-                for (int x = 0; x < 2; ++x)
+                for (int x = 0; x < 3; ++x)
                     for (int pl = 0; pl < (spmm ? 1 : 4); ++pl) {
                         drts_options_t o = S->opt;
                         o.rows_per_tile = r;

@@ -1,0 +1,352 @@
+// Serving loop: continuous batching of independent DRTS solves.
+//
+// A client of the library's own C ABI: each admitted request owns a matrix
+// and a single-rhs solver; a tick groups every admitted solver into one
+// uneven batch (one launch per step for all of them) and runs a quantum of
+// steps.  Admission is by device footprint against a budget; retirement
+// copies the series to host memory and frees the request's device memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <new>
+#include <vector>
+
+#include "drts.h"
+#include "drts_internal.h"
+
+using namespace drts;
+
+namespace {
+
+struct Request {
+    int64_t id = 0;
+    int64_t n_steps = 0, done = 0;
+    int skips = 0;
+    // deep copy of the medium
+    drts_medium_t med{};
+    std::vector<drts_material_t> mats;
+    std::vector<uint8_t> map;
+    std::vector<int32_t> layer_z0;
+    // detectors
+    int32_t n_det = 0;
+    std::vector<int64_t> det_ptr, det_state;
+    std::vector<uint8_t> det_esc;
+    std::vector<double> det_F;
+    const drts_source_table_t *src = nullptr;
+    int64_t est_bytes = 0;   // footprint bound before assembly
+    int64_t bytes = 0;       // footprint held while admitted
+    drts_matrix_t *A = nullptr;
+    drts_solver_t *S = nullptr;
+    bool finished = false;
+    // results, copied at retirement
+    std::vector<double> series, totals;
+    std::vector<int32_t> exp2;
+
+    void free_device()
+    {
+        if (S) drts_solver_destroy(S);
+        if (A) drts_matrix_destroy(A);
+        S = nullptr;
+        A = nullptr;
+    }
+    ~Request() { free_device(); }
+};
+
+// Device bytes of a solver besides its matrix: two state buffers, the series,
+// the amplitude table and the per-chunk partials (bounded by the rows).
+int64_t solver_bytes(int64_t n_rows, int64_t n_steps, int32_t n_det, int32_t n_src)
+{
+    const int64_t series = n_steps * (8 * (3 + std::max(n_det, 1)) + 8);
+    const int64_t amp = n_steps * 8 * (std::max(n_src, 1) + 1);
+    const int64_t partials = (n_rows / 64 + 256 + 64) * 8 * (4 + n_det);
+    return 2 * 4 * n_rows + series + amp + partials + (1 << 20);
+}
+
+}  // namespace
+
+struct drts_server {
+    drts_device_t dev{};
+    int64_t budget = 0, used = 0;
+    int32_t quantum = 0, max_active = 0, max_skips = 0;
+    int64_t next_id = 1;
+    std::deque<Request *> waiting;
+    std::vector<Request *> active;
+    std::map<int64_t, std::unique_ptr<Request>> all;
+    std::deque<int64_t> unreported;
+    drts_batch_t *batch = nullptr;
+    bool batch_dirty = true;
+
+    ~drts_server()
+    {
+        if (batch) drts_batch_destroy(batch);
+    }
+};
+
+namespace {
+
+int copy_request(Request &q, const drts_medium_t *m, const drts_detectors_t *det)
+{
+    q.med = *m;
+    if (m->n_mat < 1 || m->n_mat > 255 || !m->mat) return set_error(DRTS_E_INVALID, "medium materials");
+    if (m->grid.nx < 1 || m->grid.ny < 1 || m->grid.nz < 1) return set_error(DRTS_E_INVALID, "grid size");
+    q.mats.assign(m->mat, m->mat + m->n_mat);
+    q.med.mat = q.mats.data();
+    if (m->mat_of_voxel) {
+        const size_t nv = (size_t)m->grid.nx * m->grid.ny * m->grid.nz;
+        q.map.assign(m->mat_of_voxel, m->mat_of_voxel + nv);
+        q.med.mat_of_voxel = q.map.data();
+    }
+    if (m->geom.kind == DRTS_GEOM_LAYERS_Z && m->geom.n_layers > 0) {
+        if (!m->geom.layer_z0) return set_error(DRTS_E_INVALID, "layer_z0 is NULL");
+        q.layer_z0.assign(m->geom.layer_z0, m->geom.layer_z0 + m->geom.n_layers);
+        q.med.geom.layer_z0 = q.layer_z0.data();
+    }
+    if (det && det->n_det > 0) {
+        if (!det->det_ptr || !det->state || !det->F) return set_error(DRTS_E_INVALID, "detector arrays");
+        q.n_det = det->n_det;
+        q.det_ptr.assign(det->det_ptr, det->det_ptr + det->n_det + 1);
+        const int64_t ne = q.det_ptr.back();
+        if (ne < 0) return set_error(DRTS_E_INVALID, "detector entries");
+        q.det_state.assign(det->state, det->state + ne);
+        q.det_F.assign(det->F, det->F + ne);
+        if (det->escape) q.det_esc.assign(det->escape, det->escape + ne);
+        else q.det_esc.assign((size_t)ne, 0);
+    }
+    return DRTS_OK;
+}
+
+// Upper bound of the request's device footprint, from the medium alone: a row
+// holds at most 26 entries per move group (the plain move and each irregular
+// move), every entry 8 bytes (FP32 value, int32 column).
+int estimate_bytes(Request &q)
+{
+    Model M;
+    int rc = build_model(&q.med, &M);
+    if (rc) return rc;
+    const int64_t nnz_ub = (int64_t)kDirs * (M.n_rows + (int64_t)M.irr_row.size());
+    const int64_t mat = 8 * (nnz_ub + 4) + 8 * (M.n_rows + 1) + M.n_vox + (1 << 20);
+    const int32_t n_src = q.src ? q.src->n_src : 0;
+    q.est_bytes = mat + solver_bytes(M.n_rows, q.n_steps, q.n_det, n_src);
+    return DRTS_OK;
+}
+
+int admit(drts_server *Q, Request &q)
+{
+    int rc = drts_build_matrix(&q.med, &Q->dev, &q.A);
+    if (rc) return rc;
+    drts_detectors_t det{};
+    det.n_det = q.n_det;
+    det.det_ptr = q.det_ptr.data();
+    det.state = q.det_state.data();
+    det.escape = q.det_esc.data();
+    det.F = q.det_F.data();
+    rc = drts_solver_create(q.A, 1, q.n_det > 0 ? &det : nullptr, q.n_steps, &Q->dev, &q.S);
+    if (rc) {
+        q.free_device();
+        return rc;
+    }
+    int64_t n_states = 0, n_escape = 0, nnz = 0, mbytes = 0;
+    double dt = 0;
+    drts_matrix_info(q.A, &n_states, &n_escape, &nnz, &mbytes, &dt);
+    const int32_t n_src = q.src ? q.src->n_src : 0;
+    q.bytes = mbytes + (n_states + n_escape) + (1 << 20) +
+              solver_bytes(n_states + n_escape, q.n_steps, q.n_det, n_src);
+    return DRTS_OK;
+}
+
+int retire(drts_server *Q, Request &q)
+{
+    const int64_t T = q.n_steps;
+    q.series.assign((size_t)T * std::max(q.n_det, 1), 0.0);
+    q.totals.assign((size_t)T * 3, 0.0);
+    q.exp2.assign((size_t)T, 0);
+    int rc = drts_detector_readout(q.S, 0, T, q.series.data(), q.exp2.data(), q.totals.data());
+    if (rc) return rc;
+    q.free_device();
+    Q->used -= q.bytes;
+    q.bytes = 0;
+    q.finished = true;
+    Q->unreported.push_back(q.id);
+    return DRTS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int drts_serve_create(const drts_device_t *dev, int64_t budget_bytes, int32_t quantum, int32_t max_active,
+                      int32_t max_skips, drts_server_t **out)
+{
+    if (!out) return set_error(DRTS_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (budget_bytes <= 0) return set_error(DRTS_E_INVALID, "budget_bytes must be positive");
+    if (quantum < 1 || quantum > 100000) return set_error(DRTS_E_INVALID, "quantum in 1..100000");
+    if (max_active < 1 || max_active > 4096) return set_error(DRTS_E_INVALID, "max_active in 1..4096");
+    if (max_skips < 0) return set_error(DRTS_E_INVALID, "max_skips must be >= 0");
+    drts_server *Q = new (std::nothrow) drts_server;
+    if (!Q) return set_error(DRTS_E_NOMEM, "host allocation failed");
+    if (dev) Q->dev = *dev;
+    Q->budget = budget_bytes;
+    Q->quantum = quantum;
+    Q->max_active = max_active;
+    Q->max_skips = max_skips;
+    *out = Q;
+    return DRTS_OK;
+}
+
+int drts_serve_submit(drts_server_t *Q, const drts_medium_t *medium, const drts_source_table_t *src,
+                      const drts_detectors_t *det, int64_t n_steps, int64_t *request_id)
+{
+    if (!Q || !medium || !request_id) return set_error(DRTS_E_INVALID, "NULL argument");
+    if (medium->value_type != DRTS_F32) return set_error(DRTS_E_INVALID, "served solves take FP32 media");
+    if (n_steps < 1) return set_error(DRTS_E_INVALID, "n_steps must be >= 1");
+    std::unique_ptr<Request> q;
+    int rc;
+    try {
+        q.reset(new Request);
+        q->n_steps = n_steps;
+        q->src = src;
+        rc = copy_request(*q, medium, det);
+        if (!rc) rc = estimate_bytes(*q);
+    } catch (const std::bad_alloc &) {
+        return set_error(DRTS_E_NOMEM, "host allocation failed");
+    }
+    if (rc) return rc;
+    if (q->est_bytes > Q->budget)
+        return set_error(DRTS_E_NOMEM, "request needs about %lld bytes, beyond the budget of %lld",
+                         (long long)q->est_bytes, (long long)Q->budget);
+    q->id = Q->next_id++;
+    *request_id = q->id;
+    Q->waiting.push_back(q.get());
+    Q->all[q->id] = std::move(q);
+    return DRTS_OK;
+}
+
+int drts_serve_footprint(const drts_medium_t *medium, const drts_source_table_t *src, const drts_detectors_t *det,
+                         int64_t n_steps, int64_t *bytes)
+{
+    if (!medium || !bytes) return set_error(DRTS_E_INVALID, "NULL argument");
+    if (n_steps < 1) return set_error(DRTS_E_INVALID, "n_steps must be >= 1");
+    int rc;
+    try {
+        Request q;
+        q.n_steps = n_steps;
+        q.src = src;
+        rc = copy_request(q, medium, det);
+        if (!rc) rc = estimate_bytes(q);
+        if (!rc) *bytes = q.est_bytes;
+    } catch (const std::bad_alloc &) {
+        return set_error(DRTS_E_NOMEM, "host allocation failed");
+    }
+    return rc;
+}
+
+int drts_serve_tick(drts_server_t *Q, int32_t *n_active, int32_t *n_waiting, int32_t *n_finished,
+                    int64_t *bytes_in_use)
+{
+    if (!Q) return set_error(DRTS_E_INVALID, "server is NULL");
+    int rc = DRTS_OK;
+    int32_t finished = 0;
+    // 1. admission: first fit in arrival order; a request passed over
+    //    max_skips times blocks the ones behind it
+    std::vector<Request *> passed;   // earlier requests that did not fit this tick
+    for (auto it = Q->waiting.begin(); it != Q->waiting.end() && (int)Q->active.size() < Q->max_active;) {
+        Request &q = **it;
+        if (Q->used + q.est_bytes <= Q->budget) {
+            if ((rc = admit(Q, q))) return rc;
+            Q->used += q.bytes;
+            Q->active.push_back(&q);
+            Q->batch_dirty = true;
+            for (Request *p : passed) ++p->skips;
+            it = Q->waiting.erase(it);
+            continue;
+        }
+        if (q.skips >= Q->max_skips) break;
+        passed.push_back(&q);
+        ++it;
+    }
+    // 2. one quantum for every admitted request, one launch per step
+    if (!Q->active.empty()) {
+        if (Q->batch_dirty) {
+            if (Q->batch) drts_batch_destroy(Q->batch);
+            Q->batch = nullptr;
+            std::vector<drts_solver_t *> ss;
+            for (Request *q : Q->active) ss.push_back(q->S);
+            if ((rc = drts_batch_create(ss.data(), (int32_t)ss.size(), &Q->dev, &Q->batch))) return rc;
+            Q->batch_dirty = false;
+        }
+        std::vector<const drts_source_table_t *> tabs;
+        std::vector<int64_t> steps;
+        for (Request *q : Q->active) {
+            tabs.push_back(q->src);
+            steps.push_back(std::min<int64_t>(Q->quantum, q->n_steps - q->done));
+        }
+        if ((rc = drts_batch_run(Q->batch, tabs.data(), steps.data()))) return rc;
+        for (size_t i = 0; i < Q->active.size(); ++i) Q->active[i]->done += steps[i];
+        // 3. retirement
+        std::vector<Request *> keep;
+        for (Request *q : Q->active) {
+            if (q->done >= q->n_steps) {
+                if ((rc = retire(Q, *q))) return rc;
+                ++finished;
+                Q->batch_dirty = true;
+            } else {
+                keep.push_back(q);
+            }
+        }
+        Q->active.swap(keep);
+        if (Q->batch_dirty && Q->batch) {
+            // the batch refers to retired solvers: drop it before anything else runs
+            drts_batch_destroy(Q->batch);
+            Q->batch = nullptr;
+        }
+    }
+    if (n_active) *n_active = (int32_t)Q->active.size();
+    if (n_waiting) *n_waiting = (int32_t)Q->waiting.size();
+    if (n_finished) *n_finished = finished;
+    if (bytes_in_use) *bytes_in_use = Q->used;
+    return DRTS_OK;
+}
+
+int drts_serve_poll(drts_server_t *Q, int64_t *ids, int32_t cap, int32_t *n_out)
+{
+    if (!Q || !n_out || (cap > 0 && !ids)) return set_error(DRTS_E_INVALID, "NULL argument");
+    int32_t n = 0;
+    while (n < cap && !Q->unreported.empty()) {
+        ids[n++] = Q->unreported.front();
+        Q->unreported.pop_front();
+    }
+    *n_out = n;
+    return DRTS_OK;
+}
+
+int drts_serve_result(const drts_server_t *Q, int64_t request_id, double *series, int32_t *exp2, double *totals)
+{
+    if (!Q) return set_error(DRTS_E_INVALID, "server is NULL");
+    auto it = Q->all.find(request_id);
+    if (it == Q->all.end()) return set_error(DRTS_E_INVALID, "unknown request %lld", (long long)request_id);
+    const Request &q = *it->second;
+    if (!q.finished) return set_error(DRTS_E_STATE, "request %lld has not finished", (long long)request_id);
+    if (series && q.n_det > 0) memcpy(series, q.series.data(), (size_t)q.n_steps * q.n_det * sizeof(double));
+    if (exp2) memcpy(exp2, q.exp2.data(), (size_t)q.n_steps * sizeof(int32_t));
+    if (totals) memcpy(totals, q.totals.data(), (size_t)q.n_steps * 3 * sizeof(double));
+    return DRTS_OK;
+}
+
+int drts_serve_release(drts_server_t *Q, int64_t request_id)
+{
+    if (!Q) return set_error(DRTS_E_INVALID, "server is NULL");
+    auto it = Q->all.find(request_id);
+    if (it == Q->all.end()) return set_error(DRTS_E_INVALID, "unknown request %lld", (long long)request_id);
+    if (!it->second->finished) return set_error(DRTS_E_STATE, "request %lld has not finished", (long long)request_id);
+    Q->all.erase(it);
+    return DRTS_OK;
+}
+
+void drts_serve_destroy(drts_server_t *Q) { delete Q; }
+
+}  // extern "C"

@@ -9,6 +9,10 @@ namespace drts {
 
 // Slots of the per-chunk FP64 partials, each [n_rhs] wide.
 enum : int { kSlotN = 0, kSlotEsc = 1, kSlotAbs = 2, kSlotMax = 3, kSlotDet = 4 };
+// Segments of the first reduction level of the finalize kernel; the partials
+// buffer holds [slots][n_chunks] chunk values followed by [slots][kFinSeg].
+constexpr int kFinSeg = 256;
+constexpr int kFinDetMax = 256;   // detectors per solver
 
 // Everything the step and finalize kernels need of one solver.  Lives in
 // device memory; the kernels read it with uniform (scalar) loads.
@@ -53,9 +57,10 @@ struct StepInst {
     int32_t rescale;
     int32_t n_mat;          // entries of absorb
     int64_t max_steps;
-    // partials [slot * n_rhs + rhs][n_chunks]
+    // partials [slot * n_rhs + rhs][n_chunks], then [slot * n_rhs + rhs][kFinSeg]
     double *partials;
     int64_t n_chunks;
+    int32_t *fin_ticket;    // [n_rhs] finalize blocks done this step (zero between steps)
     // series
     double *ser_tot;        // [max_steps][3][n_rhs]: N(t+1), escaped(t), absorbed(t)
     double *ser_det;        // [max_steps][n_det][n_rhs]

@@ -593,56 +593,94 @@ __global__ void __launch_bounds__(kNT) step_spmm(const StepInst *__restrict__ in
 // ---------------------------------------------------------------------------
 // finalize: fixed-order reduction of the chunk partials, series and control
 // ---------------------------------------------------------------------------
+// Two-level reduction of the per-chunk partials in a fixed order.  Block
+// (seg, inst, rhs) sums the chunks of segment seg (contiguous, kFinSeg of them
+// per instance) for every slot and stores one value per slot; the block that
+// takes the last ticket sums the segments in ascending order, records the
+// series and advances the control words.  The order of every addition depends
+// only on the number of chunks, never on which block finishes first.
 __global__ void __launch_bounds__(kNT) finalize_step(const StepInst *__restrict__ insts, int32_t *queue)
 {
-    __shared__ double red[kNT];
+    constexpr int NW = kNT / 64;
+    __shared__ double s_w[4][NW];
+    __shared__ double s_fin[kSlotDet + kFinDetMax];
+    __shared__ int s_last;
     // the step kernel that used the work counter has completed: reset it for
     // the next step (a kernel store, so the step loop can be graph-captured)
-    if (queue && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *queue = 0;
-    const StepInst &I = insts[blockIdx.x];
-    const int rhs = blockIdx.y;
+    if (queue && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) *queue = 0;
+    const StepInst &I = insts[blockIdx.y];
+    const int rhs = blockIdx.z;
     if (rhs >= I.n_rhs) return;
     const int64_t t = I.t[rhs];
     if (t >= *I.t_end) return;
-    const int tid = threadIdx.x;
     const int64_t nc = I.n_chunks;
-    const int nr = I.n_rhs;
-    const Scale sc = step_scale(I, rhs, t);
-    auto slot = [&](int kind) { return I.partials + ((int64_t)kind * nr + rhs) * nc; };
-    // each thread sums chunks tid, tid + NT, ... in four interleaved
-    // accumulators (so the loads are independent), then a fixed tree
-    auto reduce = [&](int kind, bool is_max) {
-        const double *p = slot(kind);
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        int64_t c = tid;
-        for (; c + 3 * kNT < nc; c += 4 * kNT) {
-            const double v0 = p[c], v1 = p[c + kNT], v2 = p[c + 2 * kNT], v3 = p[c + 3 * kNT];
-            if (is_max) {
-                a0 = fmax(a0, v0); a1 = fmax(a1, v1); a2 = fmax(a2, v2); a3 = fmax(a3, v3);
-            } else {
-                a0 += v0; a1 += v1; a2 += v2; a3 += v3;
+    const int nseg = (int)min((int64_t)kFinSeg, nc);
+    const int seg = blockIdx.x;
+    if (seg >= nseg) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nr = I.n_rhs, nslot = kSlotDet + I.n_det;
+    const int64_t c0 = seg * nc / nseg, c1 = (seg + 1) * nc / nseg;
+    const GLB double *part = gp(I.partials);
+    double *segp = I.partials + (int64_t)nslot * nr * nc;   // [slot * n_rhs + rhs][kFinSeg]
+    // up to four slots per pass, so their loads are in flight together
+    for (int k0 = 0; k0 < nslot; k0 += 4) {
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t c = c0 + tid; c < c1; c += kNT) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = k0 + j;
+                if (k < nslot) {
+                    const double v = part[((int64_t)k * nr + rhs) * nc + c];
+                    a[j] = (k == kSlotMax) ? fmax(a[j], v) : a[j] + v;
+                }
             }
         }
-        for (; c < nc; c += kNT) a0 = is_max ? fmax(a0, p[c]) : a0 + p[c];
-        const double a = is_max ? fmax(fmax(a0, a1), fmax(a2, a3)) : (a0 + a1) + (a2 + a3);
-        return is_max ? block_max(a, red) : block_sum(a, red);
-    };
-    const double N = reduce(kSlotN, false);
-    const double Esc = reduce(kSlotEsc, false);
-    const double Abs = reduce(kSlotAbs, false);
-    const double Mx = reduce(kSlotMax, true);
-    for (int d = 0; d < I.n_det; ++d) {
-        const double Dd = reduce(kSlotDet + d, false);
-        if (tid == 0) I.ser_det[(t * I.n_det + d) * nr + rhs] = Dd;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double w = (k0 + j == kSlotMax) ? wave_max(a[j]) : wave_sum(a[j]);
+            if (lane == 0) s_w[j][wave] = w;
+        }
+        __syncthreads();
+        if (tid < 4 && k0 + tid < nslot) {
+            const int k = k0 + tid;
+            double r = s_w[tid][0];
+            for (int w = 1; w < NW; ++w) r = (k == kSlotMax) ? fmax(r, s_w[tid][w]) : r + s_w[tid][w];
+            segp[((int64_t)k * nr + rhs) * kFinSeg + seg] = r;
+            __threadfence();   // release this block's segment values before its ticket
+        }
+        __syncthreads();
     }
+    if (tid == 0) s_last = atomicAdd(&I.fin_ticket[rhs], 1) == nseg - 1;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();   // acquire the other blocks' segment values
+    // lane l combines segments l, l + 64, ... in ascending order, then the wave
+    for (int k = wave; k < nslot; k += NW) {
+        const double *sp = segp + ((int64_t)k * nr + rhs) * kFinSeg;
+        double v = 0.0;
+#pragma unroll
+        for (int j = 0; j < kFinSeg / 64; ++j) {
+            const int sg = lane + 64 * j;
+            if (sg < nseg) {
+                const double u = __hip_atomic_load(sp + sg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                v = (k == kSlotMax) ? fmax(v, u) : v + u;
+            }
+        }
+        v = (k == kSlotMax) ? wave_max(v) : wave_sum(v);
+        if (lane == 0) s_fin[k] = v;
+    }
+    __syncthreads();
+    const Scale sc = step_scale(I, rhs, t);
+    for (int d = tid; d < I.n_det; d += kNT) I.ser_det[(t * I.n_det + d) * nr + rhs] = s_fin[kSlotDet + d];
     if (tid == 0) {
-        I.ser_tot[(t * 3 + 0) * nr + rhs] = N;
-        I.ser_tot[(t * 3 + 1) * nr + rhs] = Esc;
+        I.fin_ticket[rhs] = 0;
+        I.ser_tot[(t * 3 + 0) * nr + rhs] = s_fin[kSlotN];
+        I.ser_tot[(t * 3 + 1) * nr + rhs] = s_fin[kSlotEsc];
         I.ser_tot[(t * 3 + 2) * nr + rhs] = I.abs_cur[rhs];
         I.ser_abs_exp[t * nr + rhs] = I.E[rhs];
         I.ser_exp[t * nr + rhs] = sc.En;
-        I.abs_cur[rhs] = Abs;
-        I.M[rhs] = Mx;
+        I.abs_cur[rhs] = s_fin[kSlotAbs];
+        I.M[rhs] = s_fin[kSlotMax];
         I.E[rhs] = sc.En;
         I.t[rhs] = t + 1;
     }
@@ -1081,7 +1119,8 @@ hipError_t launch_finalize(const StepInst *insts_dev, int n_inst, int n_rhs_max,
 {
     (void)n_det_max;
     if (n_inst <= 0) return hipSuccess;
-    hipLaunchKernelGGL(finalize_step, dim3((unsigned)n_inst, (unsigned)n_rhs_max), dim3(kNT), 0, stream, insts_dev,
+    hipLaunchKernelGGL(finalize_step, dim3((unsigned)kFinSeg, (unsigned)n_inst, (unsigned)n_rhs_max), dim3(kNT), 0,
+                       stream, insts_dev,
                        queue);
     return hipGetLastError();
 }

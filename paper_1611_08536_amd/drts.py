@@ -130,6 +130,16 @@ _sig("drts_batch_create", C.c_int, [C.POINTER(P), i32, C.POINTER(DeviceT), C.POI
 _sig("drts_batch_run", C.c_int, [P, C.POINTER(C.POINTER(SourceTableT)), C.POINTER(i64)])
 _sig("drts_batch_destroy", None, [P])
 _sig("drts_autotune", C.c_int, [P, C.c_char_p, C.POINTER(OptionsT)])
+_sig("drts_serve_create", C.c_int, [C.POINTER(DeviceT), i64, i32, i32, i32, C.POINTER(P)])
+_sig("drts_serve_submit", C.c_int, [P, C.POINTER(MediumT), C.POINTER(SourceTableT), C.POINTER(DetectorsT), i64,
+                                    C.POINTER(i64)])
+_sig("drts_serve_footprint", C.c_int, [C.POINTER(MediumT), C.POINTER(SourceTableT), C.POINTER(DetectorsT), i64,
+                                       C.POINTER(i64)])
+_sig("drts_serve_tick", C.c_int, [P, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i64)])
+_sig("drts_serve_poll", C.c_int, [P, C.POINTER(i64), i32, C.POINTER(i32)])
+_sig("drts_serve_result", C.c_int, [P, i64, P, P, P])
+_sig("drts_serve_release", C.c_int, [P, i64])
+_sig("drts_serve_destroy", None, [P])
 
 EXPORTED = [
     "drts_build_matrix", "drts_matrix_info", "drts_matrix_row_of", "drts_matrix_export_rows",
@@ -137,6 +147,8 @@ EXPORTED = [
     "drts_step", "drts_run", "drts_solver_time", "drts_detector_readout", "drts_state_read",
     "drts_state_write", "drts_solver_profile", "drts_solver_profile_stats", "drts_solver_destroy",
     "drts_batch_create", "drts_batch_run", "drts_batch_destroy", "drts_autotune", "drts_last_error",
+    "drts_serve_create", "drts_serve_submit", "drts_serve_footprint", "drts_serve_tick", "drts_serve_poll", "drts_serve_result",
+    "drts_serve_release", "drts_serve_destroy",
 ]
 
 
@@ -208,6 +220,48 @@ def state_index(medium, vox, dirs) -> np.ndarray:
 
 # ---- matrix ---------------------------------------------------------------------
 
+def _medium_struct(medium, value_type="f32", rounding="dither", n_ref=None, use_map=True):
+    """drts_medium_t of a workloads.Medium plus the host arrays it points to."""
+    mats = (MaterialT * len(medium.materials))(
+        *[MaterialT(m.mu_s, m.mu_a, m.g, m.n) for m in medium.materials])
+    vmap = np.ascontiguousarray(medium.mat_of_voxel, dtype=np.uint8).reshape(-1)
+    z0 = np.ascontiguousarray(medium.layer_z0 or (0,), dtype=np.int32)
+    geom = Geometry()
+    geom.kind = GEOM[medium.geom]
+    geom.sphere_c = (dbl * 3)(*(medium.sphere_c or (0.0, 0.0, 0.0)))
+    geom.sphere_r = medium.sphere_r or 0.0
+    geom.n_layers = len(medium.layer_z0)
+    geom.layer_z0 = z0.ctypes.data_as(C.POINTER(i32))
+    m = MediumT()
+    m.grid = Grid(medium.nx, medium.ny, medium.nz, medium.h_mm)
+    m.n_mat = len(medium.materials)
+    m.mat = mats
+    m.mat_of_voxel = vmap.ctypes.data_as(C.POINTER(C.c_uint8)) if use_map else None
+    m.geom = geom
+    m.bc = BC[medium.bc]
+    m.value_type = F64 if value_type == "f64" else F32
+    m.rounding = ROUND_DITHER if rounding == "dither" else ROUND_NEAREST
+    m.n_ref = n_ref if n_ref is not None else medium.materials[0].n
+    return m, (mats, vmap, z0)
+
+
+def _detectors_struct(medium, detectors):
+    """drts_detectors_t of a list of workloads.Detector (None when empty) plus its arrays."""
+    if not detectors:
+        return None, None
+    ptr, st, esc, F = [0], [], [], []
+    for d in detectors:
+        s = state_index(medium, d.vox, d.dirs)
+        st.append(s)
+        esc.append(np.asarray(d.escape, dtype=np.uint8).reshape(-1))
+        F.append(np.asarray(d.F, dtype=np.float64).reshape(-1))
+        ptr.append(ptr[-1] + s.size)
+    arrs = (np.asarray(ptr, dtype=np.int64), np.concatenate(st), np.concatenate(esc), np.concatenate(F))
+    dt = DetectorsT(len(detectors), arrs[0].ctypes.data_as(C.POINTER(i64)), arrs[1].ctypes.data_as(C.POINTER(i64)),
+                    arrs[2].ctypes.data_as(C.POINTER(C.c_uint8)), arrs[3].ctypes.data_as(C.POINTER(dbl)))
+    return dt, arrs
+
+
 class Matrix:
     """[A; L] of one medium, assembled on the device (drts_build_matrix)."""
 
@@ -216,26 +270,7 @@ class Matrix:
                  use_map: bool = True):
         self.device = device or default_device()
         self.medium = medium
-        mats = (MaterialT * len(medium.materials))(
-            *[MaterialT(m.mu_s, m.mu_a, m.g, m.n) for m in medium.materials])
-        self._map = np.ascontiguousarray(medium.mat_of_voxel, dtype=np.uint8).reshape(-1)
-        z0 = np.ascontiguousarray(medium.layer_z0 or (0,), dtype=np.int32)
-        geom = Geometry()
-        geom.kind = GEOM[medium.geom]
-        geom.sphere_c = (dbl * 3)(*(medium.sphere_c or (0.0, 0.0, 0.0)))
-        geom.sphere_r = medium.sphere_r or 0.0
-        geom.n_layers = len(medium.layer_z0)
-        geom.layer_z0 = z0.ctypes.data_as(C.POINTER(i32))
-        m = MediumT()
-        m.grid = Grid(medium.nx, medium.ny, medium.nz, medium.h_mm)
-        m.n_mat = len(medium.materials)
-        m.mat = mats
-        m.mat_of_voxel = self._map.ctypes.data_as(C.POINTER(C.c_uint8)) if use_map else None
-        m.geom = geom
-        m.bc = BC[medium.bc]
-        m.value_type = F64 if value_type == "f64" else F32
-        m.rounding = ROUND_DITHER if rounding == "dither" else ROUND_NEAREST
-        m.n_ref = n_ref if n_ref is not None else medium.materials[0].n
+        m, self._keep = _medium_struct(medium, value_type, rounding, n_ref, use_map)
         self.value_type = value_type
         h = P()
         _check(_lib.drts_build_matrix(C.byref(m), C.byref(self.device.c), C.byref(h)), "drts_build_matrix")
@@ -315,21 +350,7 @@ class Solver:
         self.n_rhs = n_rhs
         self.max_steps = max_steps
         self.n_det = len(detectors)
-        dt = None
-        if detectors:
-            ptr, st, esc, F = [0], [], [], []
-            for d in detectors:
-                s = state_index(matrix.medium, d.vox, d.dirs)
-                st.append(s)
-                esc.append(np.asarray(d.escape, dtype=np.uint8).reshape(-1))
-                F.append(np.asarray(d.F, dtype=np.float64).reshape(-1))
-                ptr.append(ptr[-1] + s.size)
-            self._det = (np.asarray(ptr, dtype=np.int64), np.concatenate(st), np.concatenate(esc),
-                         np.concatenate(F))
-            dt = DetectorsT(len(detectors), self._det[0].ctypes.data_as(C.POINTER(i64)),
-                            self._det[1].ctypes.data_as(C.POINTER(i64)),
-                            self._det[2].ctypes.data_as(C.POINTER(C.c_uint8)),
-                            self._det[3].ctypes.data_as(C.POINTER(dbl)))
+        dt, self._det = _detectors_struct(matrix.medium, detectors)
         h = P()
         _check(_lib.drts_solver_create(matrix._h, n_rhs, C.byref(dt) if dt is not None else None, max_steps,
                                        C.byref(self.device.c), C.byref(h)), "drts_solver_create")
@@ -445,3 +466,77 @@ class Batch:
         self._keep = tables
         steps = np.ascontiguousarray(n_steps, dtype=np.int64)
         _check(_lib.drts_batch_run(self._h, ptrs, steps.ctypes.data_as(C.POINTER(i64))), "drts_batch_run")
+
+
+class Server:
+    """Continuous batching of independent FP32 solves (drts_serve_*)."""
+
+    def __init__(self, budget_bytes: int, quantum: int = 50, max_active: int = 256, max_skips: int = 8,
+                 device: Optional[TorchDevice] = None):
+        self.device = device or default_device()
+        h = P()
+        _check(_lib.drts_serve_create(C.byref(self.device.c), int(budget_bytes), int(quantum), int(max_active),
+                                      int(max_skips), C.byref(h)), "drts_serve_create")
+        self._h = h
+        self._req = {}     # id -> (n_steps, n_det, source table kept alive)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.drts_serve_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, medium, sources: Optional[SourceTable], detectors: Sequence, n_steps: int,
+               rounding: str = "dither", n_ref: Optional[float] = None) -> int:
+        m, keep = _medium_struct(medium, "f32", rounding, n_ref)
+        dt, _ = _detectors_struct(medium, detectors)
+        rid = i64()
+        _check(_lib.drts_serve_submit(self._h, C.byref(m), C.byref(sources.c) if sources is not None else None,
+                                      C.byref(dt) if dt is not None else None, int(n_steps), C.byref(rid)),
+               "drts_serve_submit")
+        self._req[rid.value] = (int(n_steps), len(detectors), sources)
+        return rid.value
+
+    @staticmethod
+    def footprint(medium, sources: Optional[SourceTable], detectors: Sequence, n_steps: int,
+                  rounding: str = "dither", n_ref: Optional[float] = None) -> int:
+        m, keep = _medium_struct(medium, "f32", rounding, n_ref)
+        dt, _ = _detectors_struct(medium, detectors)
+        b = i64()
+        _check(_lib.drts_serve_footprint(C.byref(m), C.byref(sources.c) if sources is not None else None,
+                                         C.byref(dt) if dt is not None else None, int(n_steps), C.byref(b)),
+               "drts_serve_footprint")
+        return b.value
+
+    def tick(self) -> dict:
+        a, w, f, b = i32(), i32(), i32(), i64()
+        _check(_lib.drts_serve_tick(self._h, C.byref(a), C.byref(w), C.byref(f), C.byref(b)), "drts_serve_tick")
+        return {"active": a.value, "waiting": w.value, "finished": f.value, "bytes": b.value}
+
+    def poll(self) -> List[int]:
+        out = []
+        buf = (i64 * 256)()
+        n = i32()
+        while True:
+            _check(_lib.drts_serve_poll(self._h, buf, 256, C.byref(n)), "drts_serve_poll")
+            out.extend(buf[:n.value])
+            if n.value < 256:
+                return out
+
+    def result(self, rid: int) -> dict:
+        n_steps, n_det, _ = self._req[rid]
+        ser = np.zeros((n_steps, max(n_det, 1)))
+        e = np.zeros(n_steps, dtype=np.int32)
+        tot = np.zeros((n_steps, 3))
+        _check(_lib.drts_serve_result(self._h, int(rid), ser.ctypes.data, e.ctypes.data, tot.ctypes.data),
+               "drts_serve_result")
+        return {"det": ser[:, :n_det], "exp2": e, "tot": tot}
+
+    def release(self, rid: int):
+        _check(_lib.drts_serve_release(self._h, int(rid)), "drts_serve_release")
+        self._req.pop(rid, None)

@@ -54,8 +54,11 @@ def test_library_is_built_for_gfx950():
 
 
 def test_last_error_is_empty_string_initially(lib):
-    lib.drts_last_error.restype = ctypes.c_char_p
-    assert lib.drts_last_error() == b""
+    """In a fresh process no call has failed yet (other tests here set it)."""
+    code = ("import torch, ctypes; l = ctypes.CDLL(%r); l.drts_last_error.restype = ctypes.c_char_p; "
+            "print(repr(l.drts_last_error()))" % LIB)
+    out = subprocess.check_output(["python", "-c", code], text=True, cwd=ROOT)
+    assert out.strip() == "b''"
 
 
 def test_invalid_arguments_fail_without_a_gpu(lib):

@@ -147,6 +147,8 @@ def test_step_run_and_graph_replay_identical():
     {"rows_per_tile": 128, "tiles_per_chunk": 7, "grid": 24, "xcd_remap": 1},
     {"rows_per_tile": 256, "tiles_per_chunk": 64, "grid": 2048, "xcd_remap": 1},
     {"rows_per_tile": 64, "tiles_per_chunk": 3, "grid": 9, "xcd_remap": 1},
+    {"rows_per_tile": 256, "tiles_per_chunk": 2, "grid": 64, "xcd_remap": 2},
+    {"rows_per_tile": 128, "tiles_per_chunk": 5, "grid": 13, "xcd_remap": 2},
 ])
 def test_launch_shapes_give_identical_states(opts):
     """Row sums do not depend on tiling (bit-exact); FP64 totals only change order."""
@@ -157,6 +159,19 @@ def test_launch_shapes_give_identical_states(opts):
     assert np.array_equal(ref[3], got[3])
     assert np.allclose(ref[2], got[2], rtol=1e-13, atol=0)
     assert np.allclose(ref[4], got[4], rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("kernel", [0, 1, 2], ids=["csr", "struct", "struct_split"])
+def test_work_order_changes_nothing(kernel):
+    """The XCD walk and the slab order of the chunks only move work between
+    workgroups: state and FP64 series are identical bit for bit."""
+    wl = W.c2(n=20)
+    base = {"kernel": kernel, "rows_per_tile": 256, "tiles_per_chunk": 2, "grid": 256}
+    ref = _state_and_series(wl, 30, options=dict(base, xcd_remap=0))
+    for x in (1, 2):
+        got = _state_and_series(wl, 30, options=dict(base, xcd_remap=x))
+        for a, b in zip(ref, got):
+            assert np.array_equal(a, b), x
 
 
 def test_runs_are_deterministic():

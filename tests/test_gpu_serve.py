@@ -1,0 +1,72 @@
+"""The serving loop on the GPU: continuous batching of independent solves
+(sphere-inclusion media with Fresnel interfaces, edges 10..16, through the
+C ABI).
+
+Bars:
+  - every served result (detector series, exponents, totals) equals the same
+    solve run alone with drts_run, bit for bit: the batched launch performs
+    the same per-row operations and the same per-chunk FP64 partial sums;
+  - served results against the FP64 oracle: relative error <= 1e-5;
+  - admission keeps the admitted footprint within the budget: with a budget
+    of about three requests, several requests run at once and the rest wait
+    until earlier ones retire.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+drts = pytest.importorskip("paper_1611_08536_amd.drts")
+from paper_1611_08536_amd import serve  # noqa: E402
+
+
+def _requests(n, steps=(30, 120)):
+    return W.c5(n_req=n, rate=1e6, edge=(10, 16), steps=steps)
+
+
+def _footprints(reqs):
+    return [drts.Server.footprint(q.workload.medium, serve._table(q.workload), q.workload.detectors,
+                                  q.workload.n_steps) for q in reqs]
+
+
+def _same(a, b):
+    return (np.array_equal(a["exp2"], b["exp2"]) and np.array_equal(a["tot"], b["tot"])
+            and np.array_equal(a["det"], b["det"]))
+
+
+def test_served_results_equal_solo_runs():
+    reqs = _requests(8)
+    fps = sorted(_footprints(reqs))
+    budget = sum(fps[-3:])
+    out = serve.serve(reqs, budget, quantum=16, max_active=6, max_skips=2, keep_results=True)
+    assert 2 <= out["peak_active"] < len(reqs), out["peak_active"]
+    solo = serve.fifo_plain(reqs, keep_results=True)
+    for i in range(len(reqs)):
+        assert _same(out["results"][i], solo["results"][i]), i
+
+
+def test_strict_fifo_and_single_slot_give_the_same_results():
+    reqs = _requests(5, steps=(20, 60))
+    a = serve.serve(reqs, 1 << 34, quantum=7, max_active=1, max_skips=0, keep_results=True)
+    b = serve.serve(reqs, 1 << 34, quantum=64, max_active=64, max_skips=0, keep_results=True)
+    assert a["peak_active"] == 1 and b["peak_active"] == len(reqs)
+    for i in range(len(reqs)):
+        assert _same(a["results"][i], b["results"][i]), i
+
+
+def test_served_results_against_oracle():
+    reqs = _requests(4)
+    out = serve.serve(reqs, 1 << 34, quantum=25, keep_results=True)
+    for i in (0, 3):
+        wl = reqs[i].workload
+        ref = oracle.run_workload(oracle.Matrix(wl.medium), wl)
+        r = out["results"][i]
+        for c in range(3):
+            err = parity.rel_err_series(r["tot"][:, c], r["exp2"], ref["tot"][:, c], ref["tot_exp"][:, c])
+            assert err <= 1e-5, (i, c, err)
+        err = parity.rel_err_series(r["det"][:, 0], r["exp2"], ref["det"][:, 0], ref["det_exp"][:, 0])
+        assert err <= 1e-5, (i, "det", err)
