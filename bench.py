@@ -95,9 +95,10 @@ def spmv_bytes(nnz, n_rows, n_states, val_bytes=4):
     return val_bytes * nnz + 4 * nnz + 4 * (n_rows + 1) + val_bytes * n_states + val_bytes * n_rows
 
 
-def cpu_baseline(n=64, steps=40):
-    """The FP64 oracle (as it stands) on the host cores: one bounded sample of
-    the same layered workload at a smaller edge, timed per step."""
+def cpu_baseline(n=128, steps=50):
+    """The FP64 oracle (as it stands) on the host cores: a bounded sample of the
+    same workload (the first `steps` steps of the 128^3 layered medium), timed
+    after its assembly."""
     import oracle
     import workloads as W
     wl = W.c2(n=n, n_steps=steps)
@@ -108,7 +109,132 @@ def cpu_baseline(n=64, steps=40):
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": round(A.nnz * steps / dt / 1e9, 4), "unit": "GNNZ/s", "cores": threads,
             "kind": "oracle",
-            "sample": "C2 layered medium at %d^3 (%d nnz), %d FP64 steps, %.1f s" % (n, A.nnz, steps, dt)}
+            "sample": "first %d of the 2000 FP64 steps of the %d^3 layered workload (%d nnz), %.1f s" %
+                      (steps, n, A.nnz, dt)}
+
+
+def _log(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
+def _timed(fn, torch):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def spmm_vs_plain(torch, steps=20):
+    """C3: 96^3 homogeneous slab, 64 right-hand sides (one source voxel each),
+    16 FP64 detectors.  SpMM steps of all 64 against plain single-rhs steps of
+    the same matrix (64 plain runs take 64 times the single run's time)."""
+    import copy
+    import workloads as W
+    from paper_1611_08536_amd import drts, solve
+    wl = W.c3(n_steps=steps + 4)
+    A = drts.Matrix(wl.medium, wl.value_type, wl.rounding, wl.n_ref)
+    S = drts.Solver(A, wl.n_rhs, wl.detectors, max_steps=steps + 4)
+    tab = solve.source_table(A, wl)
+    S.run(tab, 2)
+    S.profile(True)
+    t_mm = _timed(lambda: S.run(tab, steps), torch)
+    n_l, k_ms = S.profile_stats()
+    S.close()
+    w1 = copy.copy(wl)
+    w1.sources = [copy.copy(x) for x in wl.sources if x.rhs == 0]
+    for x in w1.sources:
+        x.rhs = 0
+    w1.n_rhs = 1
+    S1 = drts.Solver(A, 1, wl.detectors, max_steps=steps + 4)
+    tab1 = solve.source_table(A, w1)
+    S1.run(tab1, 2)
+    t_1 = _timed(lambda: S1.run(tab1, steps), torch)
+    S1.close()
+    k = wl.n_rhs
+    nbytes = 8 * A.nnz + 4 * (A.n_rows + 1) + 4 * k * A.n_states + 4 * k * A.n_rows
+    kern_s = k_ms / max(n_l, 1) * 1e-3
+    out = {"workload": "C3: 96^3 homogeneous, %d rhs, %d nnz, %d steps timed" % (k, A.nnz, steps),
+           "solve_steps_per_s": round(k * steps / t_mm, 1),
+           "plain_solve_steps_per_s": round(steps / t_1, 1),
+           "speedup_vs_plain": round((k * steps / t_mm) / (steps / t_1), 2),
+           "ms_per_step": round(t_mm / steps * 1e3, 3), "plain_ms_per_step": round(t_1 / steps * 1e3, 3),
+           "kernel": "step_spmm<int32>", "kernel_ms": round(kern_s * 1e3, 3),
+           "achieved_GBs": round(nbytes / kern_s / 1e9, 1), "frac": round(nbytes / kern_s / 1e9 / PEAK_HBM_GBS, 4)}
+    A.close()
+    return out
+
+
+def batch_vs_sequential(torch, steps=40):
+    """C4: 256 independent homogeneous cubes (edges 16..64), advanced together
+    by one launch per step, against the same solvers stepped one after another."""
+    import workloads as W
+    from paper_1611_08536_amd import drts, solve
+    wls = W.c4(n_steps=500)
+    _log("C4: assembling %d media" % len(wls))
+    mats = [drts.Matrix(w.medium, w.value_type, w.rounding, w.n_ref) for w in wls]
+    solvers = [drts.Solver(m, 1, [], max_steps=2 * steps + 4) for m in mats]
+    tabs = [solve.source_table(m, w) for m, w in zip(mats, wls)]
+    B = drts.Batch(solvers)
+    B.run(tabs, [2] * len(solvers))
+    t_b = _timed(lambda: B.run(tabs, [steps] * len(solvers)), torch)
+    B.close()
+
+    def seq():
+        for S, t in zip(solvers, tabs):
+            S.run(t, steps)
+    t_s = _timed(seq, torch)
+    nnz = sum(m.nnz for m in mats)
+    for S in solvers:
+        S.close()
+    for m in mats:
+        m.close()
+    n = len(wls)
+    return {"workload": "C4: %d media, %d nnz in all, %d of the 500 steps timed" % (n, nnz, steps),
+            "instance_steps_per_s": round(n * steps / t_b, 1),
+            "sequential_instance_steps_per_s": round(n * steps / t_s, 1),
+            "speedup_vs_sequential": round(t_s / t_b, 2),
+            "solves_per_s": round(n * steps / t_b / 500, 3),
+            "sequential_solves_per_s": round(n * steps / t_s / 500, 3),
+            "GNNZ_per_s": round(nnz * steps / t_b / 1e9, 1)}
+
+
+def serving_vs_fifo(torch, n_req=32, step_scale=0.1):
+    """C5 sample: the first n_req requests of the Poisson (200/s) stream of
+    sphere-inclusion media (edges 32..128), step counts scaled by step_scale,
+    through the serving loop and through sequential FIFO plain runs."""
+    import workloads as W
+    from paper_1611_08536_amd import serve
+    lo, hi = int(500 * step_scale), int(5000 * step_scale)
+    reqs = W.c5(n_req=n_req, steps=(lo, hi))
+    torch.cuda.empty_cache()
+    budget = serve.footprint_budget(0.7)
+    _log("C5: serving %d requests (budget %.1f GB)" % (n_req, budget / 1e9))
+    s = serve.serve(reqs, budget, quantum=50)
+    _log("C5: FIFO plain")
+    f = serve.fifo_plain(reqs)
+    r = lambda d: {k: round(v, 4) if isinstance(v, float) else v for k, v in d.items()}
+    return {"workload": "C5 sample: first %d requests, 200/s Poisson arrivals, edges 32..128, steps %d..%d" %
+                        (n_req, lo, hi),
+            "served": r(s), "fifo_plain": r(f),
+            "speedup_solves_per_s": round(s["solves_per_s"] / f["solves_per_s"], 2)}
+
+
+def structured_step(torch, A, wl, tab, steps=50):
+    """The matrix-free step (hi + lo values) on the same 128^3 workload."""
+    from paper_1611_08536_amd import drts
+    S = drts.Solver(A, 1, wl.detectors, max_steps=steps + 4)
+    S.set_options(kernel=drts.KERNEL_STRUCTURED_SPLIT, tiles_per_chunk=4)
+    S.run(tab, 2)
+    S.profile(True)
+    t = _timed(lambda: S.run(tab, steps), torch)
+    n_l, k_ms = S.profile_stats()
+    S.close()
+    kern_s = k_ms / max(n_l, 1) * 1e-3
+    nbytes = 4 * A.n_states + 4 * A.n_rows + A.n_states // 26
+    return {"kernel": "step_struct<float,2> (matrix-free, hi+lo values)", "ms_per_step": round(t / steps * 1e3, 4),
+            "kernel_ms": round(kern_s * 1e3, 4), "GNNZ_equiv_per_s": round(A.nnz / kern_s / 1e9, 1),
+            "algorithmic_bytes": nbytes, "achieved_GBs": round(nbytes / kern_s / 1e9, 1)}
 
 
 def main():
@@ -118,6 +244,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--n", type=int, default=128, help="grid edge (128 = the headline workload)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the SpMM, batch, serving and matrix-free measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, launch an elementwise kernel that reads and writes 1 GiB (counter scale)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
@@ -138,14 +266,14 @@ def main():
     torch.cuda.set_device(0)
     total = args.warmup + args.steps
     wl = W.c2(n=args.n, n_steps=total)
-    print("bench: assembling %d^3 layered medium" % args.n, file=sys.stderr, flush=True)
+    _log("assembling %d^3 layered medium" % args.n)
     A = drts.Matrix(wl.medium, wl.value_type, wl.rounding, wl.n_ref)
     S = drts.Solver(A, 1, wl.detectors, max_steps=total)
     tab = solve.source_table(A, wl)
     S.run(tab, args.warmup)
     torch.cuda.synchronize()
 
-    print("bench: timing %d steps" % args.steps, file=sys.stderr, flush=True)
+    _log("timing %d steps" % args.steps)
     S.profile(True)
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -194,7 +322,19 @@ def main():
                      "kernel": "step_spmv<float,int32>", "kernel_ms": round(avg_kernel_ms, 4),
                      "algorithmic_bytes": nbytes, "traffic_unit": "GB per launch"},
     }
+    if not args.no_extras and args.n == 128:
+        _log("structured step")
+        line["structured"] = structured_step(torch, A, wl, tab)
+    S.close()
+    A.close()
+    if not args.no_extras:
+        _log("C3 SpMM")
+        line["spmm"] = spmm_vs_plain(torch)
+        _log("C4 batch")
+        line["batch"] = batch_vs_sequential(torch)
+        line["serving"] = serving_vs_fifo(torch)
     if not args.no_cpu:
+        _log("CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
 

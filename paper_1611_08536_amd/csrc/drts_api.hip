@@ -681,12 +681,13 @@ int drts_solver_create(const drts_matrix_t *A, int32_t n_rhs, const drts_detecto
     if (n_rhs > 1 && A->m.model.value_type != DRTS_F32)
         return set_error(DRTS_E_INVALID, "several right-hand sides need an FP32 matrix");
     if (max_steps < 1) return set_error(DRTS_E_INVALID, "max_steps must be >= 1");
-    {
-        // the step kernels gather x with 32-bit byte offsets
+    if (n_rhs == 1) {
+        // the single-rhs step kernels gather x with 32-bit byte offsets (the
+        // SpMM kernel addresses X with 64-bit offsets)
         const uint64_t vb = A->m.model.value_type == DRTS_F64 ? 8 : 4;
-        if ((uint64_t)A->m.model.n_rows * vb * (uint64_t)n_rhs >= 0xffffffffull)
-            return set_error(DRTS_E_RANGE, "a state vector of %lld rows x %d rhs exceeds 4 GiB",
-                             (long long)A->m.model.n_rows, n_rhs);
+        if ((uint64_t)A->m.model.n_rows * vb >= 0xffffffffull)
+            return set_error(DRTS_E_RANGE, "a state vector of %lld rows exceeds 4 GiB",
+                             (long long)A->m.model.n_rows);
     }
     drts_solver *S = new (std::nothrow) drts_solver;
     if (!S) return set_error(DRTS_E_NOMEM, "host allocation failed");
