@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 STEP_SOURCES = ("paper_1611_08536_amd/csrc/drts_step.hip", "paper_1611_08536_amd/csrc/drts_step.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_spmv_c2_traffic.txt")
-SPMV_KERNEL = "step_spmv<float, int, 256, 256, 0>"
+SPMV_KERNEL = "step_spmv<float, int, 256, 256, 0, 0>"
 CALIB_KERNEL = "vectorized_elementwise_kernel"
 CALIB_BYTES = 2 ** 30          # the calibration kernel reads and writes 1 GiB
 
@@ -319,7 +319,7 @@ def main():
                    "n_states": A.n_states, "n_rows": A.n_rows, "nnz": A.nnz, "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None if traffic is None else round(traffic / 1e9, 3),
-                     "kernel": "step_spmv<float,int32>", "kernel_ms": round(avg_kernel_ms, 4),
+                     "kernel": "step_spmv<float, int, 256, 256, 0, 0>", "kernel_ms": round(avg_kernel_ms, 4),
                      "algorithmic_bytes": nbytes, "traffic_unit": "GB per launch"},
     }
     if not args.no_extras and args.n == 128:

@@ -217,11 +217,20 @@ typedef struct {
                              swept in z (its x gathers stay in its L2) */
     int32_t graph_steps;  /* steps captured per hipGraph replay (0 = eager) */
     int32_t rescale;      /* 1 = power-of-two rescale every step (default) */
-    int32_t variant;      /* one rhs only: DRTS_SPMV_ROW (a thread per row),
-                             DRTS_SPMV_PIPE (the next tile's entries load while
-                             the current tile is reduced), DRTS_SPMV_HALF (two
-                             threads per row while streaming: fewer registers,
-                             more resident waves), DRTS_SPMV_HALF_PIPE (both) */
+    int32_t variant;      /* one rhs only: DRTS_SPMV_ROW (a thread per row,
+                             four consecutive entries per lane), DRTS_SPMV_PIPE
+                             (the next tile's entries load while the current
+                             tile is reduced), DRTS_SPMV_HALF (two threads per
+                             row while streaming: fewer registers, more
+                             resident waves), DRTS_SPMV_HALF_PIPE (both),
+                             DRTS_SPMV_STRIDED (a thread per row, entries in
+                             strided order: consecutive lanes load and gather
+                             consecutive entries), DRTS_SPMV_WAVE (each wave
+                             carries its own 64-row tile through every phase,
+                             no workgroup barrier per tile; rows_per_tile 64),
+                             DRTS_SPMV_WAVE_PIPE (as DRTS_SPMV_WAVE, the next
+                             tile's entries load before the current tile's
+                             gathers) */
     int32_t queue;        /* one rhs only: 1 = workgroups take chunks from a
                              device counter (dynamic balance), 0 = fixed walk */
 } drts_options_t;
@@ -230,6 +239,9 @@ typedef struct {
 #define DRTS_SPMV_PIPE 1
 #define DRTS_SPMV_HALF 2
 #define DRTS_SPMV_HALF_PIPE 3
+#define DRTS_SPMV_STRIDED 4
+#define DRTS_SPMV_WAVE 5
+#define DRTS_SPMV_WAVE_PIPE 6
 
 /* Creates the time-stepping state for n_rhs right-hand sides sharing A: the
  * state (zero), detectors, series buffers for max_steps steps.  n_rhs > 1

@@ -125,7 +125,7 @@ struct drts_solver {
     int64_t n_tiles = 0, n_chunks = 0;
     int64_t t_host = 0;
 
-    Buffer buf0, buf1, ctl_t, ctl_E, ctl_M, ctl_abs, t_end, partials, fin_ticket;
+    Buffer buf0, buf1, ctl_t, ctl_E, ctl_M, ctl_abs, t_end, partials, fin_ticket, xcd_bounds;
     Buffer ser_tot, ser_det, ser_exp, ser_abs_exp, amp, smax;
     Buffer src_tile, src_row, src_id, src_rhs, src_w;
     Buffer det_tile, det_row, det_id, det_F;
@@ -261,6 +261,47 @@ void order_by_slabs(drts_solver *S, const std::vector<int64_t> &bounds)
     for (size_t i = 0; i < key.size(); ++i) S->work_h[i] = {0, key[i].second};
 }
 
+// Boundaries of the XCDs' ranges of the work list with about equal work in
+// each: entries of [A; L] for the CSR kernels (read from the device row
+// pointers at the chunk starts), rows for the matrix-free kernel.
+int balanced_xcd_bounds(drts_solver *S, const std::vector<int64_t> &bounds, std::vector<int64_t> *out)
+{
+    const Matrix &A = S->A->m;
+    const int64_t nc = S->n_chunks, tpc = S->opt.tiles_per_chunk, rpt = S->opt.rows_per_tile;
+    std::vector<int64_t> w((size_t)nc, 0);
+    if (!bounds.empty()) {
+        for (int64_t c = 0; c < nc; ++c) {
+            const int64_t a = bounds[(size_t)std::min(c * tpc, (int64_t)bounds.size() - 1)];
+            const int64_t b = bounds[(size_t)std::min((c + 1) * tpc, (int64_t)bounds.size() - 1)];
+            w[(size_t)c] = b - a;
+        }
+    } else {
+        const int64_t step = tpc * rpt;   // rows per chunk
+        const size_t es = A.rp64 ? 8 : 4;
+        std::vector<int64_t> rp((size_t)nc + 1);
+        std::vector<char> raw(((size_t)nc + 1) * es);
+        DRTS_HIP(hipMemcpy2DAsync(raw.data(), es, A.row_ptr.ptr, (size_t)step * es, es, (size_t)nc, hipMemcpyDeviceToHost,
+                                  S->dev.stream));
+        DRTS_HIP(hipMemcpyAsync(raw.data() + (size_t)nc * es, (const char *)A.row_ptr.ptr + (size_t)A.model.n_rows * es,
+                                es, hipMemcpyDeviceToHost, S->dev.stream));
+        DRTS_HIP(hipStreamSynchronize(S->dev.stream));
+        for (size_t i = 0; i <= (size_t)nc; ++i)
+            rp[i] = A.rp64 ? ((const int64_t *)raw.data())[i] : (int64_t)((const int32_t *)raw.data())[i];
+        for (int64_t c = 0; c < nc; ++c) w[(size_t)c] = rp[(size_t)c + 1] - rp[(size_t)c];
+    }
+    int64_t total = 0;
+    for (const WorkItem &it : S->work_h) total += w[(size_t)it.chunk];
+    out->assign(kXcdBounds, nc);
+    (*out)[0] = 0;
+    int64_t acc = 0;
+    int x = 1;
+    for (int64_t i = 0; i < nc && x < kXcdBounds - 1; ++i) {
+        acc += w[(size_t)S->work_h[(size_t)i].chunk];
+        while (x < kXcdBounds - 1 && acc * (kXcdBounds - 1) >= total * x) (*out)[(size_t)x++] = i + 1;
+    }
+    return DRTS_OK;
+}
+
 // (Re)builds every structure that depends on the options and the sources.
 int prepare(drts_solver *S)
 {
@@ -363,6 +404,12 @@ int prepare(drts_solver *S)
     for (int64_t c = 0; c < S->n_chunks; ++c) S->work_h[(size_t)c] = {0, (int32_t)c};
     if (o.xcd_remap == 2) order_by_slabs(S, bounds);
     if ((rc = upload_vec(dev, S->work_dev, S->work_h))) return rc;
+    S->xcd_bounds.reset();
+    if (o.xcd_remap) {
+        std::vector<int64_t> xb;
+        if ((rc = balanced_xcd_bounds(S, bounds, &xb))) return rc;
+        if ((rc = upload_vec(dev, S->xcd_bounds, xb))) return rc;
+    }
     drop_graph(S);
     DRTS_HIP(hipStreamSynchronize(dev.stream));
     return DRTS_OK;
@@ -492,12 +539,12 @@ int launch_one(drts_solver *S, hipStream_t stream)
         int mode = 2;
         if (S->opt.kernel == DRTS_KERNEL_STRUCTURED) mode = (f64 || A.model.rounding == DRTS_ROUND_DITHER) ? 0 : 1;
         e = launch_structured(S->sa, S->inst_dev.as<StepInst>(), S->work_dev.as<WorkItem>(), S->n_chunks, f64, mode,
-                              S->grid, S->opt.xcd_remap ? 1 : 0, stream);
+                              S->grid, S->opt.xcd_remap ? 1 : 0, S->xcd_bounds.as<int64_t>(), stream);
     } else {
     e = launch_step(S->inst_dev.as<StepInst>(), S->work_dev.as<WorkItem>(), S->n_chunks, 1, S->n_rhs,
                                A.model.value_type == DRTS_F64, A.rp64 ? 1 : 0, spmm ? 1 : 0, S->grid,
-                               (S->opt.xcd_remap ? 1 : 0) | ((S->opt.variant & 3) << 1), S->opt.rows_per_tile,
-                               S->n_det, queue, stream);
+                               (S->opt.xcd_remap ? 1 : 0) | ((S->opt.variant & 7) << 1), S->xcd_bounds.as<int64_t>(),
+                               S->opt.rows_per_tile, S->n_det, queue, stream);
     }
     if (e != hipSuccess) return set_error(DRTS_E_HIP, "step launch failed: %s", hipGetErrorString(e));
     if (e1) DRTS_HIP(hipEventRecord(e1, stream));
@@ -582,8 +629,11 @@ int check_options(const drts_solver *S, const drts_options_t *o)
     }
     if (o->queue != 0 && o->queue != 1) return set_error(DRTS_E_INVALID, "queue must be 0 or 1");
     if (o->xcd_remap < 0 || o->xcd_remap > 2) return set_error(DRTS_E_INVALID, "xcd_remap must be 0, 1 or 2");
-    if (o->variant < DRTS_SPMV_ROW || o->variant > DRTS_SPMV_HALF_PIPE)
+    if (o->variant < DRTS_SPMV_ROW || o->variant > DRTS_SPMV_WAVE_PIPE)
         return set_error(DRTS_E_INVALID, "unknown variant %d", o->variant);
+    if ((o->variant == DRTS_SPMV_WAVE || o->variant == DRTS_SPMV_WAVE_PIPE) && S->n_rhs == 1 &&
+        o->kernel == DRTS_KERNEL_CSR && o->rows_per_tile != 64)
+        return set_error(DRTS_E_INVALID, "the wave variant takes rows_per_tile = 64");
     if (o->grid < 0 || o->graph_steps < 0 || o->graph_steps > 4096)
         return set_error(DRTS_E_INVALID, "bad grid or graph_steps");
     return DRTS_OK;
@@ -959,8 +1009,8 @@ int batch_launch(drts_batch *B, int64_t n_work, int n_inst, int rows_per_tile, h
     const int grid = device_cu_count() * 16;
     int32_t *queue = S0->opt.queue ? B->queue.as<int32_t>() : nullptr;
     hipError_t e = launch_step(B->inst_dev.as<StepInst>(), B->work_dev.as<WorkItem>(), n_work, n_inst, 1, 0,
-                               S0->A->m.rp64 ? 1 : 0, 0, grid, (S0->opt.variant & 3) << 1, rows_per_tile, 0, queue,
-                               stream);
+                               S0->A->m.rp64 ? 1 : 0, 0, grid, (S0->opt.variant & 7) << 1, nullptr, rows_per_tile, 0,
+                               queue, stream);
     if (e != hipSuccess) return set_error(DRTS_E_HIP, "batch step launch failed: %s", hipGetErrorString(e));
     e = launch_finalize(B->inst_dev.as<StepInst>(), n_inst, 1, 0, queue, stream);
     if (e != hipSuccess) return set_error(DRTS_E_HIP, "batch finalize launch failed: %s", hipGetErrorString(e));
@@ -1161,7 +1211,8 @@ int drts_autotune(drts_solver_t *S, const char *cache_path, drts_options_t *chos
         for (int c : chunk_opts)
             for (int g : grid_mult)
                 for (int x = 0; x < 3; ++x)
-                    for (int pl = 0; pl < (spmm ? 1 : 4); ++pl) {
+                    for (int pl = 0; pl < (spmm ? 1 : 7); ++pl) {
+                        if ((pl == DRTS_SPMV_WAVE || pl == DRTS_SPMV_WAVE_PIPE) && r != 64) continue;
                         drts_options_t o = S->opt;
                         o.rows_per_tile = r;
                         o.tiles_per_chunk = spmm ? c * 32 : c;

@@ -13,6 +13,7 @@ enum : int { kSlotN = 0, kSlotEsc = 1, kSlotAbs = 2, kSlotMax = 3, kSlotDet = 4 
 // buffer holds [slots][n_chunks] chunk values followed by [slots][kFinSeg].
 constexpr int kFinSeg = 256;
 constexpr int kFinDetMax = 256;   // detectors per solver
+constexpr int kXcdBounds = 9;     // XCDs + 1
 
 // Everything the step and finalize kernels need of one solver.  Lives in
 // device memory; the kernels read it with uniform (scalar) loads.
@@ -79,9 +80,12 @@ struct WorkItem {
 // hipError_t.
 // queue (may be NULL): a zeroed device counter from which the SpMV workgroups
 // take work items; the finalize kernel resets it.
+// xcd_bounds (may be NULL): with the XCD-aware walk, XCD i takes work items
+// xcd_bounds[i] .. xcd_bounds[i+1]-1 (kXcdBounds entries), else equal counts.
 hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int64_t n_work, int n_inst,
                        int n_rhs_max, int value_f64, int rp64, int spmm, int grid, int xcd_remap,
-                       int rows_per_tile, int n_det_max, int32_t *queue, hipStream_t stream);
+                       const int64_t *xcd_bounds, int rows_per_tile, int n_det_max, int32_t *queue,
+                       hipStream_t stream);
 hipError_t launch_finalize(const StepInst *insts_dev, int n_inst, int n_rhs_max, int n_det_max, int32_t *queue,
                            hipStream_t stream);
 
@@ -115,6 +119,7 @@ constexpr int kStructSegLen = 16;
 // mode: 0 = exact values with global gathers, 1 = exact nearest values with
 // the LDS halo, 2 = hi + lo values with the LDS halo
 hipError_t launch_structured(const StructArgs &sa, const StepInst *insts_dev, const WorkItem *work_dev,
-                             int64_t n_work, int value_f64, int mode, int grid, int xcd_remap, hipStream_t stream);
+                             int64_t n_work, int value_f64, int mode, int grid, int xcd_remap,
+                             const int64_t *xcd_bounds, hipStream_t stream);
 
 }  // namespace drts

@@ -140,12 +140,14 @@ __device__ __forceinline__ int lower_bound_rows(const int64_t *rows, int lo, int
 struct Walk {
     int64_t begin, end, stride;
 };
-__device__ __forceinline__ Walk walk_of(int64_t n_work, int xcd_remap)
+__device__ __forceinline__ Walk walk_of(int64_t n_work, int xcd_remap, const int64_t *xcd_bounds)
 {
     const int64_t G = gridDim.x, b = blockIdx.x;
     if (xcd_remap && G % kXcds == 0 && G >= kXcds) {
+        // workgroups are dispatched to the XCDs round robin: b % kXcds is b's XCD
         const int64_t x = b % kXcds, local = b / kXcds, per = G / kXcds;
-        const int64_t lo = x * n_work / kXcds, hi = (x + 1) * n_work / kXcds;
+        const int64_t lo = xcd_bounds ? xcd_bounds[x] : x * n_work / kXcds;
+        const int64_t hi = xcd_bounds ? xcd_bounds[x + 1] : (x + 1) * n_work / kXcds;
         return {lo + local, hi, per};
     }
     return {b, n_work, G};
@@ -281,15 +283,94 @@ __device__ __forceinline__ VT finish_tile(const TileRegs<VT, IT, U> &T, __amdgpu
     return acc;
 }
 
+// Entries of one tile in strided order: thread t holds entries b + t + k NT,
+// so consecutive lanes hold consecutive entries.  Loads of columns and values
+// are then coalesced 4-byte loads, and so is most of the x gather: a row's
+// columns are runs of consecutive states (one voxel's 26 directions), so one
+// wave instruction gathers from the x blocks of two or three rows instead of
+// from a dozen (the address unit, not HBM, limits the quad layout).
+template <typename VT, typename IT, int S> struct TileRegsS {
+    VT v[S];
+    int32_t c[S];
+    IT b, e;
+    IT mylo, myhi;
+    int q;
+};
+
+template <typename VT, typename IT, int NT, int S, int R>
+__device__ __forceinline__ void issue_tile_s(TileRegsS<VT, IT, S> &T, const GLB IT *rp, const GLB int32_t *col,
+                                             const GLB VT *val, const GLB uint8_t *mat, IT b, IT e, int64_t r0,
+                                             int nr, int64_t n_states, int64_t nnz)
+{
+    const int tid = threadIdx.x;
+    const int64_t r = r0 + tid;
+    T.b = b;
+    T.e = e;
+    T.mylo = 0;
+    T.myhi = 0;
+    T.q = 0;
+    if (tid < nr && tid < R) {
+        T.mylo = rp[r];
+        T.myhi = rp[r + 1];
+        if (r < n_states) T.q = mat[r / kDirs];
+    }
+    // indices past the tile are clamped to its last entry (an empty tile reads
+    // entry b, at worst the zero padding): no branches, every load in bounds;
+    // such duplicates are not staged
+    const uint32_t last = e > b ? (uint32_t)(e - b - 1) : 0u;
+    const int64_t base = (int64_t)b;
+    const uint64_t left = (uint64_t)(nnz + 4 - base);
+    const __amdgpu_buffer_rsrc_t rc = make_rsrc((const void *)(col + base), left * 4);
+    const __amdgpu_buffer_rsrc_t rv = make_rsrc((const void *)(val + base), left * sizeof(VT));
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        const uint32_t i = min((uint32_t)(tid + k * NT), last);
+        T.c[k] = __builtin_amdgcn_raw_buffer_load_b32(rc, (int)(i * 4), 0, kStream);
+        if constexpr (sizeof(VT) == 4)
+            T.v[k] = __builtin_bit_cast(VT, __builtin_amdgcn_raw_buffer_load_b32(rv, (int)(i * 4), 0, kStream));
+        else
+            T.v[k] = __builtin_bit_cast(VT, __builtin_amdgcn_raw_buffer_load_b64(rv, (int)(i * 8), 0, kStream));
+    }
+}
+
+template <typename VT, typename IT, int NT, int S, int R>
+__device__ __forceinline__ VT finish_tile_s(const TileRegsS<VT, IT, S> &T, __amdgpu_buffer_rsrc_t rx, VT *s_prod)
+{
+    VT xv[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) xv[k] = BufQuad<VT>::gather(rx, T.c[k]);
+    const int span = (int)(T.e - T.b);
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        const int i = threadIdx.x + k * NT;
+        if (i < span) s_prod[i] = T.v[k] * xv[k];
+    }
+    __syncthreads();
+    VT acc = 0;
+    IT jj = T.mylo;
+    for (; jj + 4 <= T.myhi; jj += 4) {
+        const VT p0 = s_prod[jj - T.b], p1 = s_prod[jj - T.b + 1];
+        const VT p2 = s_prod[jj - T.b + 2], p3 = s_prod[jj - T.b + 3];
+        acc += p0;
+        acc += p1;
+        acc += p2;
+        acc += p3;
+    }
+    for (; jj < T.myhi; ++jj) acc += s_prod[jj - T.b];
+    return acc;
+}
+
 // NT threads stream the entries of R rows (R = NT: one row per thread and 7
 // quads per thread; R = NT/2: 4 quads per thread, so fewer registers and more
 // resident waves; the first R threads sum the rows).  PIPE = 1: the next
 // tile's entries are loaded before this tile's gathers, so the matrix stream
-// of a workgroup never stops (two register sets).
-template <typename VT, typename IT, int NT, int R, int PIPE>
+// of a workgroup never stops (two register sets).  LAY = 1: the strided tile
+// layout (one row per thread, no pipelining); LAY = 0: quads.
+template <typename VT, typename IT, int NT, int R, int PIPE, int LAY>
 __global__ void __launch_bounds__(NT) step_spmv(const StepInst *__restrict__ insts,
                                                  const WorkItem *__restrict__ work, int64_t n_work,
-                                                 int xcd_remap, int32_t *__restrict__ queue)
+                                                 int xcd_remap, const int64_t *__restrict__ xcd_bounds,
+                                                 int32_t *__restrict__ queue)
 {
     constexpr int NW = NT / 64;
     __shared__ int64_t s_wi;
@@ -305,7 +386,7 @@ __global__ void __launch_bounds__(NT) step_spmv(const StepInst *__restrict__ ins
     __shared__ VT s_y[R];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const Walk wk = walk_of(n_work, xcd_remap);
+    const Walk wk = walk_of(n_work, xcd_remap, xcd_bounds);
     // work items come from a global counter (dynamic balance) or a fixed walk
     int64_t wi = wk.begin;
     int cached = -1;
@@ -371,7 +452,13 @@ __global__ void __launch_bounds__(NT) step_spmv(const StepInst *__restrict__ ins
             const bool own = tid < nr && tid < R;
             VT acc = 0;
             int q = 0;
-            if (fits(j)) {
+            if (LAY == 1 && fits(j)) {
+                TileRegsS<VT, IT, CAP / NT> ts;
+                issue_tile_s<VT, IT, NT, CAP / NT, R>(ts, rp, col, val, mat, s_tb[j], s_tb[j + 1], r0, nr, n_states,
+                                                      I.nnz);
+                acc = finish_tile_s<VT, IT, NT, CAP / NT, R>(ts, rx, s_prod);
+                q = ts.q;
+            } else if (fits(j)) {
                 if (!have)
                     issue_tile<VT, IT, NT, U, R>(cur, rp, col, val, mat, s_tb[j], s_tb[j + 1], r0, nr, n_states, I.nnz);
                 bool more = false;
@@ -472,19 +559,301 @@ __global__ void __launch_bounds__(NT) step_spmv(const StepInst *__restrict__ ins
     }
 }
 
+// value of lane l (uniform l) of a 64-bit per-lane value
+__device__ __forceinline__ int64_t lane_i64(int64_t v, int l)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// ---------------------------------------------------------------------------
+// SpMV step, one wave per tile of 64 rows
+//
+// Each wave of a workgroup takes every fourth tile of the chunk and carries it
+// through on its own: the row bounds (a lane per row), the tile's columns and
+// values as quads (lane l holds entries 4 (l + 64 k) .. + 3 of the tile), the
+// x gathers, the products staged in the wave's own LDS slice, and the row sums
+// (each lane its row, in column order).  No workgroup barrier separates these
+// phases, so every wave keeps its loads in flight independently; the waves
+// meet once per chunk to combine their FP64 partials in a fixed order.
+// ---------------------------------------------------------------------------
+constexpr int kWaveTileRows = 64;
+
+template <typename VT, typename IT, int PIPEW>
+__global__ void __launch_bounds__(256) step_spmv_wave(const StepInst *__restrict__ insts,
+                                                       const WorkItem *__restrict__ work, int64_t n_work,
+                                                       int xcd_remap, const int64_t *__restrict__ xcd_bounds)
+{
+    constexpr int NW = 4, U = 7;
+    constexpr int CAPW = 4 * U * 64;     // entries one pass of a wave stages (28 per row)
+    __shared__ VT s_prod[NW][CAPW];
+    __shared__ VT s_yw[NW][64];
+    __shared__ double s_abs[kMatMax];
+    __shared__ double s_wred[4][NW];
+    __shared__ double s_wdet[NW][kFinDetMax];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    VT *my_prod = s_prod[wave];
+    const Walk wk = walk_of(n_work, xcd_remap, xcd_bounds);
+    for (int64_t wi = wk.begin; wi < wk.end; wi += wk.stride) {
+        const WorkItem item = work[wi];
+        const StepInst &I = insts[item.inst];
+        const int64_t t = I.t[0];
+        if (t >= *I.t_end) continue;
+        const Scale sc = step_scale(I, 0, t);
+        const VT scale = (VT)ldexp(1.0, -sc.k);
+        const GLB IT *rp = gp((const IT *)I.row_ptr);
+        const GLB int32_t *col = gp(I.col);
+        const GLB VT *val = gp((const VT *)I.val);
+        const GLB VT *x = gp((const VT *)((t & 1) ? I.buf1 : I.buf0));
+        const __amdgpu_buffer_rsrc_t rx = make_rsrc((const void *)x, (uint64_t)I.n_rows * sizeof(VT));
+        GLB VT *y = gpw((VT *)((t & 1) ? I.buf0 : I.buf1));
+        const GLB uint8_t *mat = gp(I.mat);
+        const int64_t n_rows = I.n_rows, n_states = I.n_states;
+        const int nd = I.n_det;
+        const int64_t tile0 = (int64_t)item.chunk * I.tiles_per_chunk;
+        const int64_t tile1 = min(tile0 + (int64_t)I.tiles_per_chunk, I.n_tiles);
+        for (int q = threadIdx.x; q < I.n_mat; q += 256) s_abs[q] = gp(I.absorb)[q];
+        __syncthreads();
+        double sN = 0.0, sE = 0.0, sA = 0.0;
+        double dsum[kFinDetMax / 64] = {0.0, 0.0, 0.0, 0.0};
+        VT mx = 0;
+        // one tile's stream: bounds, then the quads of columns and values
+        struct WTile {
+            IT mylo, myhi, b, e, a0;
+            int nr;
+            uint32_t span;
+            uint32_t qo[U];
+            i4 qc[U];
+            Quad<VT> qv[U];
+        };
+        auto bounds_of = [&](WTile &T, int64_t tile) {
+            const int64_t r0 = tile * kWaveTileRows;
+            T.nr = (int)min((int64_t)kWaveTileRows, n_rows - r0);
+            const int64_t rl = r0 + min(lane, T.nr - 1);
+            T.mylo = rp[rl];
+            T.myhi = rp[rl + 1];
+            T.b = (IT)lane_i64((int64_t)T.mylo, 0);
+            T.e = (IT)lane_i64((int64_t)T.myhi, T.nr - 1);
+        };
+        auto stream_of = [&](WTile &T) {
+            T.a0 = T.b & ~(IT)3;
+            const uint32_t last = T.e > T.a0 ? (uint32_t)(((T.e - 1 - T.a0) >> 2) << 2) : 0u;
+            T.span = (uint32_t)(T.e - T.a0);
+            const int64_t base = (int64_t)T.a0;
+            const uint64_t left = (uint64_t)(I.nnz + 4 - base);
+            const __amdgpu_buffer_rsrc_t rc = make_rsrc((const void *)(col + base), left * 4);
+            const __amdgpu_buffer_rsrc_t rv = make_rsrc((const void *)(val + base), left * sizeof(VT));
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const uint32_t i = 4u * (uint32_t)(lane + 64 * k);
+                T.qo[k] = i < T.span ? i : last;
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                T.qc[k] = __builtin_amdgcn_raw_buffer_load_b128(rc, (int)(T.qo[k] * 4), 0, kStream);
+                T.qv[k] = BufQuad<VT>::load(rv, T.qo[k] * (uint32_t)sizeof(VT));
+            }
+        };
+        auto fits_w = [&](const WTile &T) { return T.e - T.b <= (IT)CAPW - 3; };
+        WTile cur, nxt;
+        bool have = false;
+        if (PIPEW && tile0 + wave < tile1) {
+            bounds_of(cur, tile0 + wave);
+            if (fits_w(cur)) {
+                stream_of(cur);
+                have = true;
+            }
+        }
+        for (int64_t tile = tile0 + wave; tile < tile1; tile += NW) {
+            const int64_t r0 = tile * kWaveTileRows;
+            if (!have) bounds_of(cur, tile);
+            const int nr = cur.nr;
+            const int64_t r = r0 + lane;
+            const bool own = lane < nr;
+            const IT mylo = cur.mylo, myhi = cur.myhi, b = cur.b, e = cur.e;
+            int q = 0;
+            if (own && r < n_states) q = mat[r / kDirs];
+            VT acc = 0;
+            if (fits_w(cur)) {
+                if (!have) stream_of(cur);
+                // the next tile's stream goes out before this tile's gathers
+                bool more = false;
+                if (PIPEW && tile + NW < tile1) {
+                    bounds_of(nxt, tile + NW);
+                    if (fits_w(nxt)) {
+                        stream_of(nxt);
+                        more = true;
+                    }
+                }
+                const IT a0 = cur.a0;
+                VT xv[U][4];
+#pragma unroll
+                for (int k = 0; k < U; ++k)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) xv[k][jj] = BufQuad<VT>::gather(rx, cur.qc[k][jj]);
+#pragma unroll
+                for (int k = 0; k < U; ++k)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) my_prod[cur.qo[k] + jj] = cur.qv[k][jj] * xv[k][jj];
+                // the wave's own LDS writes, then its reads: in order within the wave
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (own) {
+                    IT jj = mylo;
+                    for (; jj + 4 <= myhi; jj += 4) {
+                        const VT p0 = my_prod[jj - a0], p1 = my_prod[jj - a0 + 1];
+                        const VT p2 = my_prod[jj - a0 + 2], p3 = my_prod[jj - a0 + 3];
+                        acc += p0;
+                        acc += p1;
+                        acc += p2;
+                        acc += p3;
+                    }
+                    for (; jj < myhi; ++jj) acc += my_prod[jj - a0];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (more) cur = nxt;
+                have = more;
+            } else {
+                // long rows: passes of CAPW entries
+                for (IT a = b & ~(IT)3; a < e; a += CAPW) {
+                    const IT cs = a < b ? b : a;
+                    const IT ce = (e - a < (IT)CAPW) ? e : a + (IT)CAPW;
+                    for (IT i = a + 4 * lane; i < ce; i += 4 * 64) {
+                        const i4 c4 = __builtin_nontemporal_load((const GLB i4 *)(col + i));
+                        Quad<VT> v4;
+                        v4.load(val + i);
+#pragma unroll
+                        for (int jj = 0; jj < 4; ++jj) {
+                            const IT idx = i + jj;
+                            if (idx >= cs && idx < ce) my_prod[idx - a] = v4[jj] * x[c4[jj]];
+                        }
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    if (own) {
+                        const IT lo = mylo > cs ? mylo : cs;
+                        const IT hi = myhi < ce ? myhi : ce;
+                        for (IT jj = lo; jj < hi; ++jj) acc += my_prod[jj - a];
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                }
+                have = false;
+                if (PIPEW && tile + NW < tile1) {
+                    bounds_of(cur, tile + NW);
+                    if (fits_w(cur)) {
+                        stream_of(cur);
+                        have = true;
+                    }
+                }
+            }
+            // epilogue: rescale, sources, store, FP64 totals
+            VT v = acc * scale;
+            const int sb = gp(I.src_tile)[tile], se = gp(I.src_tile)[tile + 1];
+            if (own && sb < se) {
+                const GLB int64_t *srow = gp(I.src_row);
+                int e2 = lower_bound_rows<IT>(I.src_row, sb, se, r);
+                double s = 0.0;
+                bool any = false;
+                for (; e2 < se && srow[e2] == r; ++e2) {
+                    s += gp(I.src_w)[e2] * gp(I.amp)[t * I.n_src + gp(I.src_id)[e2]];
+                    any = true;
+                }
+                if (any) v += (VT)ldexp(s, -sc.En);
+            }
+            if (own) {
+                y[r] = v;
+                if (r < n_states) {
+                    sN += (double)v;
+                    sA += s_abs[q] * (double)v;
+                    mx = v > mx ? v : mx;
+                } else {
+                    sE += (double)v;
+                }
+            }
+            const int db = gp(I.det_tile)[tile], de = gp(I.det_tile)[tile + 1];
+            if (db < de) {
+                s_yw[wave][lane] = v;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                // detector d is summed by lane d % 64 in register d / 64
+                for (int e2 = db; e2 < de; ++e2) {
+                    const int d = gp(I.det_id)[e2];
+                    if ((d & 63) == lane) {
+                        const double f = gp(I.det_F)[e2] * (double)s_yw[wave][gp(I.det_row)[e2] - r0];
+#pragma unroll
+                        for (int h = 0; h < kFinDetMax / 64; ++h)
+                            if ((d >> 6) == h) dsum[h] += f;
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+        }
+        // chunk partials: wave butterflies, then the waves in order
+        const int64_t nc = I.n_chunks, c = item.chunk;
+        const double wN = wave_sum(sN), wE = wave_sum(sE), wA = wave_sum(sA), wM = wave_max((double)mx);
+        if (lane == 0) {
+            s_wred[0][wave] = wN;
+            s_wred[1][wave] = wE;
+            s_wred[2][wave] = wA;
+            s_wred[3][wave] = wM;
+        }
+#pragma unroll
+        for (int h = 0; h < kFinDetMax / 64; ++h)
+            if (h * 64 + lane < nd) s_wdet[wave][h * 64 + lane] = dsum[h];
+        __syncthreads();
+        GLB double *part = gpw(I.partials);
+        const int tid = threadIdx.x;
+        if (tid < 4) {
+            double a = s_wred[tid][0];
+            for (int w = 1; w < NW; ++w) a = (tid == 3) ? fmax(a, s_wred[tid][w]) : a + s_wred[tid][w];
+            part[(int64_t)tid * nc + c] = a;
+        }
+        for (int d = tid; d < nd; d += 256) {
+            const double a = ((s_wdet[0][d] + s_wdet[1][d]) + s_wdet[2][d]) + s_wdet[3][d];
+            part[(int64_t)(kSlotDet + d) * nc + c] = a;
+        }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------
 // SpMM step (n_rhs right-hand sides, FP32), lanes = right-hand sides
+//
+// X is [rows][n_rhs]: one column index gives n_rhs contiguous values, so the
+// gather of one entry is a single coalesced load of the whole wave.  A wave
+// takes every fourth row of its chunk.  The row pointers of 64 of its rows
+// come with one load (lane l holds row l's bounds); per row, lanes 0..n-1 load
+// the row's columns and values with one coalesced load each, every lane reads
+// entry k's column and value back by readlane, and all gathers of the row are
+// issued before the first product.  The next row's columns and values are
+// requested before the current row's gathers, so both round trips overlap.
+// Products are added in column order, one rounding each, as the single-rhs
+// step adds them: every column of the result equals that step's bit for bit.
 // ---------------------------------------------------------------------------
+constexpr int kSpmmUnroll = 26;   // entries of a plain row, gathered fully unrolled
+
 template <typename IT>
 __global__ void __launch_bounds__(kNT) step_spmm(const StepInst *__restrict__ insts,
                                                   const WorkItem *__restrict__ work, int64_t n_work,
-                                                  int xcd_remap)
+                                                  int xcd_remap, const int64_t *__restrict__ xcd_bounds)
 {
     extern __shared__ double s_det[];   // [4 waves][n_det][64]
     __shared__ double s_w[4][4][64];     // per-wave totals for the fixed-order combine
+    __shared__ double s_abs[kMatMax];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const Walk wk = walk_of(n_work, xcd_remap);
+    const Walk wk = walk_of(n_work, xcd_remap, xcd_bounds);
 
     for (int64_t wi = wk.begin; wi < wk.end; wi += wk.stride) {
         const WorkItem item = work[wi];
@@ -493,75 +862,147 @@ __global__ void __launch_bounds__(kNT) step_spmm(const StepInst *__restrict__ in
         if (t >= *I.t_end) continue;
         const int nrhs = I.n_rhs, nd = I.n_det;
         const bool active = lane < nrhs;
+        const int xl = min(lane, nrhs - 1);   // lanes past n_rhs gather a valid element, then drop it
         Scale sc{0, 0};
         if (active) sc = step_scale(I, lane, t);
         const float scale = ldexpf(1.0f, -sc.k);
-        const IT *__restrict__ rp = (const IT *)I.row_ptr;
-        const int32_t *__restrict__ col = I.col;
-        const float *__restrict__ val = (const float *)I.val;
-        const float *__restrict__ X = (const float *)((t & 1) ? I.buf1 : I.buf0);
-        float *__restrict__ Y = (float *)((t & 1) ? I.buf0 : I.buf1);
+        const GLB IT *rp = gp((const IT *)I.row_ptr);
+        const GLB int32_t *col = gp(I.col);
+        const GLB float *val = gp((const float *)I.val);
+        const GLB float *X = gp((const float *)((t & 1) ? I.buf1 : I.buf0));
+        GLB float *Y = gpw((float *)((t & 1) ? I.buf0 : I.buf1));
+        const GLB uint8_t *mat = gp(I.mat);
         double *my_det = s_det + (int64_t)wave * nd * 64;
         for (int d = 0; d < nd; ++d) my_det[d * 64 + lane] = 0.0;
+        for (int q = threadIdx.x; q < I.n_mat; q += kNT) s_abs[q] = gp(I.absorb)[q];
+        __syncthreads();
 
         double sN = 0.0, sE = 0.0, sA = 0.0;
         float mx = 0.0f;
         const int R = I.rows_per_tile;
         const int64_t tile0 = (int64_t)item.chunk * I.tiles_per_chunk;
         const int64_t tile1 = min(tile0 + (int64_t)I.tiles_per_chunk, I.n_tiles);
-        for (int64_t tile = tile0; tile < tile1; ++tile) {
-            const int64_t r0 = tile * R;
-            const int nr = (int)min((int64_t)R, I.n_rows - r0);
-            const int sb = I.src_tile[tile], se = I.src_tile[tile + 1];
-            const int db = I.det_tile[tile], de = I.det_tile[tile + 1];
-            for (int i = wave; i < nr; i += 4) {
-                const int64_t r = r0 + i;
-                const IT lo = rp[r], hi = rp[r + 1];
+        const int64_t row_b = tile0 * R, row_e = min(tile1 * R, I.n_rows);
+        // sources and detectors are rare: look them up only in chunks that have them
+        const bool any_src = gp(I.src_tile)[tile1] > gp(I.src_tile)[tile0];
+        const bool any_det = nd > 0 && gp(I.det_tile)[tile1] > gp(I.det_tile)[tile0];
+
+        for (int64_t rb = row_b + wave; rb < row_e; rb += 4 * 64) {
+            // bounds of this wave's next 64 rows rb, rb + 4, ...
+            const int nb = (int)min((int64_t)64, (row_e - rb + 3) / 4);
+            const int64_t my_r = rb + 4 * (int64_t)min(lane, nb - 1);
+            const int64_t v_lo = (int64_t)rp[my_r], v_hi = (int64_t)rp[my_r + 1];
+            // columns and values of row 0 (lanes 0 .. n-1)
+            int64_t lo = lane_i64(v_lo, 0), hi = lane_i64(v_hi, 0);
+            const int64_t j0 = lo + min((int64_t)lane, max(hi - lo - 1, (int64_t)0));
+            int32_t c_cur = col[j0];
+            float v_cur = val[j0];
+            for (int i = 0; i < nb; ++i) {
+                const int64_t r = rb + 4 * (int64_t)i;
+                const int n = (int)(hi - lo);
+                // the next row's entries are requested right after this row's
+                // gathers: loads return in order, so the gathers are waited
+                // for without waiting for them, and they arrive meanwhile
+                int64_t lo_n = 0, hi_n = 0;
+                int32_t c_nxt = 0;
+                float v_nxt = 0.0f;
+                auto prefetch = [&]() {
+                    // unconditional, at an index clamped into the row (an empty
+                    // row reads the padding after the last entry): the wait
+                    // counts stay exact; lanes past the row's length are unused
+                    const int inx = min(i + 1, nb - 1);
+                    lo_n = lane_i64(v_lo, inx);
+                    hi_n = lane_i64(v_hi, inx);
+                    const int64_t j = lo_n + min((int64_t)lane, max(hi_n - lo_n - 1, (int64_t)0));
+                    c_nxt = col[j];
+                    v_nxt = val[j];
+                };
                 float acc = 0.0f;
-                IT j = lo;
-                if (active) {
-                    for (; j + 4 <= hi; j += 4) {
-                        const int32_t c0 = col[j], c1 = col[j + 1], c2 = col[j + 2], c3 = col[j + 3];
-                        const float v0 = val[j], v1 = val[j + 1], v2 = val[j + 2], v3 = val[j + 3];
-                        const float x0 = X[(int64_t)c0 * nrhs + lane];
-                        const float x1 = X[(int64_t)c1 * nrhs + lane];
-                        const float x2 = X[(int64_t)c2 * nrhs + lane];
-                        const float x3 = X[(int64_t)c3 * nrhs + lane];
-                        acc += v0 * x0;
-                        acc += v1 * x1;
-                        acc += v2 * x2;
-                        acc += v3 * x3;
+                if (n == kSpmmUnroll) {
+                    float xv[kSpmmUnroll];
+#pragma unroll
+                    for (int k = 0; k < kSpmmUnroll; ++k) {
+                        const int ck = __builtin_amdgcn_readlane(c_cur, k);
+                        xv[k] = X[(int64_t)ck * nrhs + xl];
                     }
-                    for (; j < hi; ++j) acc += val[j] * X[(int64_t)col[j] * nrhs + lane];
-                }
-                float v = acc * scale;
-                if (sb < se) {
-                    int e2 = lower_bound_rows<IT>(I.src_row, sb, se, r);
-                    double s = 0.0;
-                    bool any = false;
-                    for (; e2 < se && I.src_row[e2] == r; ++e2) {
-                        if (I.src_rhs[e2] == lane) {
-                            s += I.src_w[e2] * I.amp[t * I.n_src + I.src_id[e2]];
-                            any = true;
+                    prefetch();
+#pragma unroll
+                    for (int k = 0; k < kSpmmUnroll; ++k)
+                        acc += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v_cur), k)) * xv[k];
+                } else {
+                    prefetch();
+                    // any length, in windows of 64 entries
+                    for (int64_t wb = lo; wb < hi; wb += 64) {
+                        int32_t cw = c_cur;
+                        float vw = v_cur;
+                        if (wb != lo) {
+                            cw = 0;
+                            vw = 0.0f;
+                            if (wb + lane < hi) {
+                                cw = col[wb + lane];
+                                vw = val[wb + lane];
+                            }
+                        }
+                        const int m = (int)min((int64_t)64, hi - wb);
+                        int k = 0;
+                        for (; k + 8 <= m; k += 8) {
+                            float xv[8];
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) {
+                                const int ck = __builtin_amdgcn_readlane(cw, k + u);
+                                xv[u] = X[(int64_t)ck * nrhs + xl];
+                            }
+#pragma unroll
+                            for (int u = 0; u < 8; ++u)
+                                acc += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vw), k + u)) * xv[u];
+                        }
+                        for (; k < m; ++k) {
+                            const int ck = __builtin_amdgcn_readlane(cw, k);
+                            const float xk = X[(int64_t)ck * nrhs + xl];
+                            acc += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vw), k)) * xk;
                         }
                     }
-                    if (any) v += (float)ldexp(s, -sc.En);
+                }
+                float v = acc * scale;
+                if (any_src) {
+                    const int64_t tile = r / R;
+                    const int sb = gp(I.src_tile)[tile], se = gp(I.src_tile)[tile + 1];
+                    if (sb < se) {
+                        int e2 = lower_bound_rows<IT>(I.src_row, sb, se, r);
+                        double s = 0.0;
+                        bool any = false;
+                        for (; e2 < se && I.src_row[e2] == r; ++e2) {
+                            if (I.src_rhs[e2] == lane) {
+                                s += I.src_w[e2] * I.amp[t * I.n_src + I.src_id[e2]];
+                                any = true;
+                            }
+                        }
+                        if (any) v += (float)ldexp(s, -sc.En);
+                    }
                 }
                 if (active) {
                     Y[r * nrhs + lane] = v;
                     if (r < I.n_states) {
                         sN += (double)v;
-                        sA += I.absorb[I.mat[r / kDirs]] * (double)v;
+                        sA += s_abs[mat[r / kDirs]] * (double)v;
                         mx = fmaxf(mx, v);
                     } else {
                         sE += (double)v;
                     }
-                    if (db < de) {
-                        int e2 = lower_bound_rows<IT>(I.det_row, db, de, r);
-                        for (; e2 < de && I.det_row[e2] == r; ++e2)
-                            my_det[I.det_id[e2] * 64 + lane] += I.det_F[e2] * (double)v;
+                    if (any_det) {
+                        const int64_t tile = r / R;
+                        const int db = gp(I.det_tile)[tile], de = gp(I.det_tile)[tile + 1];
+                        if (db < de) {
+                            int e2 = lower_bound_rows<IT>(I.det_row, db, de, r);
+                            for (; e2 < de && I.det_row[e2] == r; ++e2)
+                                my_det[I.det_id[e2] * 64 + lane] += I.det_F[e2] * (double)v;
+                        }
                     }
                 }
+                lo = lo_n;
+                hi = hi_n;
+                c_cur = c_nxt;
+                v_cur = v_nxt;
             }
         }
         s_w[0][wave][lane] = sN;
@@ -871,7 +1312,7 @@ __device__ __forceinline__ StructTile struct_tile(const StructArgs &sa, int64_t 
 template <typename VT, int MODE>
 __global__ void __launch_bounds__(256) step_struct(StructArgs sa, const StepInst *__restrict__ insts,
                                                     const WorkItem *__restrict__ work, int64_t n_work,
-                                                    int xcd_remap)
+                                                    int xcd_remap, const int64_t *__restrict__ xcd_bounds)
 {
     constexpr int NT = 256, NW = NT / 64, L = kStructSegLen;
     constexpr int HV = L + 2;                       // voxels per halo line segment
@@ -899,7 +1340,7 @@ __global__ void __launch_bounds__(256) step_struct(StructArgs sa, const StepInst
     }
     for (int q = tid; q < sa.n_mat; q += NT) s_idx[q] = gp(sa.index)[q];
     __syncthreads();
-    const Walk wk = walk_of(n_work, xcd_remap);
+    const Walk wk = walk_of(n_work, xcd_remap, xcd_bounds);
     for (int64_t wi = wk.begin; wi < wk.end; wi += wk.stride) {
         const WorkItem item = work[wi];
         const StepInst &I = insts[item.inst];
@@ -1034,7 +1475,8 @@ __global__ void __launch_bounds__(256) step_struct(StructArgs sa, const StepInst
 
 hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int64_t n_work, int n_inst,
                        int n_rhs_max, int value_f64, int rp64, int spmm, int grid, int xcd_remap,
-                       int rows_per_tile, int n_det_max, int32_t *queue, hipStream_t stream)
+                       const int64_t *xcd_bounds, int rows_per_tile, int n_det_max, int32_t *queue,
+                       hipStream_t stream)
 {
     (void)n_inst;
     (void)n_rhs_max;
@@ -1044,24 +1486,48 @@ hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int6
     if (spmm) {
         const size_t lds = (size_t)4 * n_det_max * 64 * sizeof(double);
         if (rp64)
-            hipLaunchKernelGGL(step_spmm<int64_t>, g, b, lds, stream, insts_dev, work_dev, n_work, xcd_remap & 1);
+            hipLaunchKernelGGL(step_spmm<int64_t>, g, b, lds, stream, insts_dev, work_dev, n_work, xcd_remap & 1,
+                               xcd_bounds);
         else
-            hipLaunchKernelGGL(step_spmm<int32_t>, g, b, lds, stream, insts_dev, work_dev, n_work, xcd_remap & 1);
+            hipLaunchKernelGGL(step_spmm<int32_t>, g, b, lds, stream, insts_dev, work_dev, n_work, xcd_remap & 1,
+                               xcd_bounds);
     } else {
         const dim3 g1((unsigned)grid);
-        const int variant = (xcd_remap >> 1) & 3;
+        const int variant = (xcd_remap >> 1) & 7;
         const int remap = xcd_remap & 1;
-#define DRTS_SPMV1(VT, IT, NTV, RV, P) \
-    hipLaunchKernelGGL((step_spmv<VT, IT, NTV, RV, P>), g1, dim3(NTV), 0, stream, insts_dev, work_dev, n_work, remap, \
-                       queue)
-#define DRTS_SPMV(VT, IT, RV)                                  \
-    do {                                                       \
-        if (variant == 1) DRTS_SPMV1(VT, IT, RV, RV, 1);       \
-        else if (variant == 2) DRTS_SPMV1(VT, IT, 2 * RV, RV, 0); \
-        else if (variant == 3) DRTS_SPMV1(VT, IT, 2 * RV, RV, 1); \
-        else DRTS_SPMV1(VT, IT, RV, RV, 0);                    \
+#define DRTS_SPMV1(VT, IT, NTV, RV, P, L) \
+    hipLaunchKernelGGL((step_spmv<VT, IT, NTV, RV, P, L>), g1, dim3(NTV), 0, stream, insts_dev, work_dev, n_work, \
+                       remap, xcd_bounds, queue)
+#define DRTS_SPMV(VT, IT, RV)                                        \
+    do {                                                             \
+        if (variant == 1) DRTS_SPMV1(VT, IT, RV, RV, 1, 0);          \
+        else if (variant == 2) DRTS_SPMV1(VT, IT, 2 * RV, RV, 0, 0); \
+        else if (variant == 3) DRTS_SPMV1(VT, IT, 2 * RV, RV, 1, 0); \
+        else if (variant == 4) DRTS_SPMV1(VT, IT, RV, RV, 0, 1);     \
+        else DRTS_SPMV1(VT, IT, RV, RV, 0, 0);                       \
     } while (0)
         const int nt = rows_per_tile <= 64 ? 64 : (rows_per_tile <= 128 ? 128 : 256);
+        if (variant == 5 || variant == 6) {
+            // tiles of kWaveTileRows rows, one wave each
+#define DRTS_WAVE(VT, IT)                                                                                          \
+    do {                                                                                                           \
+        if (variant == 6)                                                                                          \
+            hipLaunchKernelGGL((step_spmv_wave<VT, IT, 1>), g1, dim3(256), 0, stream, insts_dev, work_dev, n_work, \
+                               remap, xcd_bounds);                                                                 \
+        else                                                                                                       \
+            hipLaunchKernelGGL((step_spmv_wave<VT, IT, 0>), g1, dim3(256), 0, stream, insts_dev, work_dev, n_work, \
+                               remap, xcd_bounds);                                                                 \
+    } while (0)
+            if (value_f64) {
+                if (rp64) DRTS_WAVE(double, int64_t);
+                else DRTS_WAVE(double, int32_t);
+            } else {
+                if (rp64) DRTS_WAVE(float, int64_t);
+                else DRTS_WAVE(float, int32_t);
+            }
+#undef DRTS_WAVE
+            return hipGetLastError();
+        }
         if (value_f64) {
             if (rp64) {
                 if (nt == 64) DRTS_SPMV(double, int64_t, 64);
@@ -1090,7 +1556,8 @@ hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int6
 }
 
 hipError_t launch_structured(const StructArgs &sa, const StepInst *insts_dev, const WorkItem *work_dev,
-                             int64_t n_work, int value_f64, int mode, int grid, int xcd_remap, hipStream_t stream)
+                             int64_t n_work, int value_f64, int mode, int grid, int xcd_remap,
+                             const int64_t *xcd_bounds, hipStream_t stream)
 {
     if (n_work <= 0) return hipSuccess;
     // the halo modes keep every direction block in LDS
@@ -1099,17 +1566,17 @@ hipError_t launch_structured(const StructArgs &sa, const StepInst *insts_dev, co
     const size_t halo = (size_t)9 * (kStructSegLen + 2) * kDirs * sizeof(float);
     const dim3 g((unsigned)grid), b(256);
     if (value_f64) {
-        hipLaunchKernelGGL((step_struct<double, 0>), g, b, 0, stream, sa, insts_dev, work_dev, n_work, xcd_remap & 1);
+        hipLaunchKernelGGL((step_struct<double, 0>), g, b, 0, stream, sa, insts_dev, work_dev, n_work, xcd_remap & 1, xcd_bounds);
     } else if (mode == 0) {
-        hipLaunchKernelGGL((step_struct<float, 0>), g, b, 0, stream, sa, insts_dev, work_dev, n_work, xcd_remap & 1);
+        hipLaunchKernelGGL((step_struct<float, 0>), g, b, 0, stream, sa, insts_dev, work_dev, n_work, xcd_remap & 1, xcd_bounds);
     } else if (mode == 1) {
         hipLaunchKernelGGL((step_struct<float, 1>), g, b, blk + halo, stream, sa, insts_dev, work_dev, n_work,
-                           xcd_remap & 1);
+                           xcd_remap & 1, xcd_bounds);
     } else if (mode == 2) {
         hipLaunchKernelGGL((step_struct<float, 2>), g, b, blk + halo, stream, sa, insts_dev, work_dev, n_work,
-                           xcd_remap & 1);
+                           xcd_remap & 1, xcd_bounds);
     } else {
-        hipLaunchKernelGGL((step_struct<float, 3>), g, b, 0, stream, sa, insts_dev, work_dev, n_work, xcd_remap & 1);
+        hipLaunchKernelGGL((step_struct<float, 3>), g, b, 0, stream, sa, insts_dev, work_dev, n_work, xcd_remap & 1, xcd_bounds);
     }
     return hipGetLastError();
 }

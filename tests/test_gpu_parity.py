@@ -161,6 +161,23 @@ def test_launch_shapes_give_identical_states(opts):
     assert np.allclose(ref[4], got[4], rtol=1e-13, atol=0)
 
 
+@pytest.mark.parametrize("rpt", [64, 256])
+def test_spmv_variants_give_identical_states(rpt):
+    """Every SpMV variant forms the same products and adds them per row in
+    column order: states bit for bit; FP64 totals differ at most in the order
+    of the per-wave partial sums."""
+    wl = W.c2(n=18)
+    ref = _state_and_series(wl, 30, options={"rows_per_tile": rpt, "variant": 0})
+    for v in (1, 2, 3, 4, 5, 6):
+        if v in (5, 6) and rpt != 64:
+            continue
+        got = _state_and_series(wl, 30, options={"rows_per_tile": rpt, "variant": v})
+        assert np.array_equal(ref[0], got[0]) and np.array_equal(ref[1], got[1]), v
+        assert np.array_equal(ref[3], got[3]), v
+        assert np.allclose(ref[2], got[2], rtol=1e-13, atol=0), v
+        assert np.allclose(ref[4], got[4], rtol=1e-13, atol=0), v
+
+
 @pytest.mark.parametrize("kernel", [0, 1, 2], ids=["csr", "struct", "struct_split"])
 def test_work_order_changes_nothing(kernel):
     """The XCD walk and the slab order of the chunks only move work between
