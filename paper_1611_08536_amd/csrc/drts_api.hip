@@ -122,10 +122,11 @@ struct drts_solver {
     int64_t max_steps = 0;
     drts_options_t opt{};
     int grid = 0;
-    int64_t n_tiles = 0, n_chunks = 0;
+    int64_t n_tiles = 0, n_chunks = 0, n_xchunks = 0;
     int64_t t_host = 0;
 
-    Buffer buf0, buf1, ctl_t, ctl_E, ctl_M, ctl_abs, t_end, partials, fin_ticket, xcd_bounds;
+    Buffer buf0, buf1, ctl_t, ctl_E, ctl_M, ctl_abs, t_end, partials, fin_ticket, xcd_bounds, xrows, xirr, ddet_ptr, ddet_row,
+        ddet_F;
     Buffer ser_tot, ser_det, ser_exp, ser_abs_exp, amp, smax;
     Buffer src_tile, src_row, src_id, src_rhs, src_w;
     Buffer det_tile, det_row, det_id, det_F;
@@ -213,23 +214,45 @@ template <typename E> std::vector<int32_t> tile_offsets_bounds(const std::vector
 bool spmm_of(const drts_solver *S) { return S->n_rhs > 1; }
 bool structured_of(const drts_solver *S) { return S->opt.kernel != DRTS_KERNEL_CSR; }
 
-// Tile row boundaries of the structured kernels: segments of kStructSegLen
-// voxels of every x-line, then the escape rows in tiles of kEscTileRows.
+// Tile row boundaries of the structured kernel: segments of kStructSegLen
+// voxels of every x-line (the last boundary is n_states).
 std::vector<int64_t> structured_bounds(const Model &M, StructArgs *sa)
 {
     const int L = kStructSegLen;
     const int segs = (M.nx + L - 1) / L;
     const int64_t lines = (int64_t)M.ny * M.nz;
     std::vector<int64_t> b;
-    b.reserve((size_t)(lines * segs + M.n_escape / kEscTileRows + 2));
+    b.reserve((size_t)(lines * segs + 1));
     for (int64_t line = 0; line < lines; ++line)
         for (int sg = 0; sg < segs; ++sg) b.push_back((int64_t)kDirs * (sg * L + (int64_t)M.nx * line));
-    for (int64_t r = M.n_states; r < M.n_rows; r += kEscTileRows) b.push_back(r);
-    b.push_back(M.n_rows);
+    b.push_back(M.n_states);
     sa->seg_len = L;
     sa->segs_per_line = segs;
     sa->n_vox_tiles = lines * segs;
     return b;
+}
+
+// Rows of the second structured kernel: the irregular rows, then the escape
+// rows, ascending; with each row's range of the (row-sorted) irregular-move
+// list, so the kernel needs no search (escape rows: empty ranges).
+void structured_xrows(const Model &M, std::vector<int64_t> *rows, std::vector<int64_t> *irr)
+{
+    std::vector<int64_t> &r = *rows, &k = *irr;
+    r.clear();
+    k.clear();
+    r.reserve(M.irr_row.size() + (size_t)M.n_escape);
+    k.reserve(M.irr_row.size() + (size_t)M.n_escape + 1);
+    for (size_t i = 0; i < M.irr_row.size(); ++i)
+        if (r.empty() || r.back() != M.irr_row[i]) {
+            r.push_back(M.irr_row[i]);
+            k.push_back((int64_t)i);
+        }
+    const int64_t n_irr = (int64_t)M.irr_row.size();
+    for (int64_t e = M.n_states; e < M.n_rows; ++e) {
+        r.push_back(e);
+        k.push_back(n_irr);
+    }
+    k.push_back(n_irr);
 }
 
 // XCD-aware order of a solver's chunks.  With the remapped walk, XCD i takes
@@ -333,10 +356,41 @@ int prepare(drts_solver *S)
         sa.escape_state = A.escape_state.as<int64_t>();
         bounds = structured_bounds(A.model, &sa);
         S->n_tiles = (int64_t)bounds.size() - 1;
+        std::vector<int64_t> xr, xk;
+        structured_xrows(A.model, &xr, &xk);
+        if ((rc = upload_vec(dev, S->xrows, xr))) return rc;
+        if ((rc = upload_vec(dev, S->xirr, xk))) return rc;
+        sa.xrows = S->xrows.as<int64_t>();
+        sa.xirr = S->xirr.as<int64_t>();
+        sa.n_xrows = (int64_t)xr.size();
+        S->n_xchunks = (sa.n_xrows + kStructXRows - 1) / kStructXRows;
+        sa.n_src_entries = (int64_t)S->srcs.size();
+        sa.n_det_entries = (int64_t)S->dets.size();
+        {
+            // detector entries grouped by detector (stable: rows stay ascending)
+            std::vector<int64_t> ptr((size_t)S->n_det + 1, 0), row(S->dets.size());
+            std::vector<double> F(S->dets.size());
+            for (const DetEntry &d : S->dets) ++ptr[(size_t)d.id + 1];
+            for (int d = 0; d < S->n_det; ++d) ptr[(size_t)d + 1] += ptr[(size_t)d];
+            std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+            for (const DetEntry &d : S->dets) {
+                const size_t at = (size_t)fill[(size_t)d.id]++;
+                row[at] = d.row;
+                F[at] = d.F;
+            }
+            if ((rc = upload_vec(dev, S->ddet_ptr, ptr))) return rc;
+            if ((rc = upload_vec(dev, S->ddet_row, row))) return rc;
+            if ((rc = upload_vec(dev, S->ddet_F, F))) return rc;
+            sa.ddet_ptr = S->ddet_ptr.as<int64_t>();
+            sa.ddet_row = S->ddet_row.as<int64_t>();
+            sa.ddet_F = S->ddet_F.as<double>();
+        }
     } else {
         S->n_tiles = (A.model.n_rows + o.rows_per_tile - 1) / o.rows_per_tile;
+        S->n_xchunks = 0;
     }
     S->n_chunks = (S->n_tiles + o.tiles_per_chunk - 1) / o.tiles_per_chunk;
+    if (structured_of(S)) S->sa.chunk_base = S->n_chunks;
     S->grid = o.grid > 0 ? o.grid : device_cu_count() * (spmm_of(S) ? 4 : 8);
     if (S->n_chunks > INT32_MAX) return set_error(DRTS_E_RANGE, "too many chunks");
 
@@ -349,7 +403,8 @@ int prepare(drts_solver *S)
         if ((rc = upload_vec(dev, S->det_tile, tile_offsets(S->dets, S->n_tiles, o.rows_per_tile)))) return rc;
     }
     const size_t slots = (size_t)(kSlotDet + S->n_det) * S->n_rhs;
-    if ((rc = S->partials.allocate(&dev, slots * (size_t)(S->n_chunks + kFinSeg) * sizeof(double)))) return rc;
+    if ((rc = S->partials.allocate(&dev, slots * (size_t)(S->n_chunks + S->n_xchunks + kFinSeg) * sizeof(double))))
+        return rc;
     if ((rc = S->fin_ticket.allocate(&dev, (size_t)S->n_rhs * sizeof(int32_t)))) return rc;
     DRTS_HIP(hipMemsetAsync(S->fin_ticket.ptr, 0, (size_t)S->n_rhs * sizeof(int32_t), dev.stream));
 
@@ -392,7 +447,7 @@ int prepare(drts_solver *S)
     I.n_mat = (int32_t)A.model.mats.size();
     I.max_steps = S->max_steps;
     I.partials = S->partials.as<double>();
-    I.n_chunks = S->n_chunks;
+    I.n_chunks = S->n_chunks + S->n_xchunks;   // the finalize reduces both kernels' chunks
     I.fin_ticket = S->fin_ticket.as<int32_t>();
     I.ser_tot = S->ser_tot.as<double>();
     I.ser_det = S->ser_det.as<double>();
@@ -594,14 +649,15 @@ int ensure_graph(drts_solver *S, int K)
 
 drts_options_t default_options(const drts_solver *S)
 {
-    // defaults measured on MI355X for the 128^3 three-layer workload (one rhs):
-    // 256-row tiles, 4 tiles per chunk, 32 workgroups per CU launched (the
-    // surplus waits and gives dynamic balance), fixed walk
+    // defaults measured on MI355X: one rhs on the 128^3 three-layer workload
+    // (256-row tiles, 4 tiles per chunk, 32 workgroups per CU launched: the
+    // surplus waits and gives dynamic balance; fixed walk), 64 rhs on the 96^3
+    // slab (64-row tiles, 16 tiles per chunk, 16 workgroups per CU)
     drts_options_t o{};
     o.kernel = DRTS_KERNEL_CSR;
     o.rows_per_tile = spmm_of(S) ? 64 : 256;
-    o.tiles_per_chunk = spmm_of(S) ? 128 : 4;
-    o.grid = spmm_of(S) ? 0 : device_cu_count() * 32;
+    o.tiles_per_chunk = spmm_of(S) ? 16 : 4;
+    o.grid = device_cu_count() * (spmm_of(S) ? 16 : 32);
     o.xcd_remap = 0;
     o.graph_steps = 0;
     o.rescale = 1;

@@ -109,15 +109,29 @@ struct StructArgs {
     const uint32_t *irr_bits;
     int64_t n_irr;
     const int64_t *escape_state;
-    // tiling: first the voxel tiles (segments of seg_len voxels of one x-line,
-    // segs_per_line of them per line), then escape tiles of kEscTileRows rows
+    // tiling: voxel tiles, segments of seg_len voxels of one x-line,
+    // segs_per_line of them per line, n_vox_tiles in all
     int32_t seg_len, segs_per_line;
     int64_t n_vox_tiles;
+    // rows left to the second kernel: irregular rows and escape rows, in
+    // ascending order; its work item j writes the partials of chunk
+    // chunk_base + j
+    const int64_t *xrows;
+    const int64_t *xirr;       // [n_xrows + 1]: row k's irregular moves are xirr[k] .. xirr[k+1]-1
+    int64_t n_xrows;
+    int64_t chunk_base;
+    // entries of the row-sorted source and detector lists
+    int64_t n_src_entries, n_det_entries;
+    // detector entries grouped by detector, rows ascending within each:
+    // detector d owns ddet_row/ddet_F [ddet_ptr[d], ddet_ptr[d+1])
+    const int64_t *ddet_ptr, *ddet_row;
+    const double *ddet_F;
 };
-constexpr int kEscTileRows = 256;
 constexpr int kStructSegLen = 16;
+constexpr int kStructXRows = 1024;
 // mode: 0 = exact values with global gathers, 1 = exact nearest values with
-// the LDS halo, 2 = hi + lo values with the LDS halo
+// the LDS halo, 2 = hi + lo values with the LDS halo, 3 = hi + lo values with
+// global gathers (more materials than the LDS holds)
 hipError_t launch_structured(const StructArgs &sa, const StepInst *insts_dev, const WorkItem *work_dev,
                              int64_t n_work, int value_f64, int mode, int grid, int xcd_remap,
                              const int64_t *xcd_bounds, hipStream_t stream);

@@ -1188,7 +1188,8 @@ template <> struct StructVals<double> {
 // fma(hi, x, lo x): one rounding of the (almost exact) product, so the value
 // rounding error disappears.  Otherwise values are rounded as stored.
 template <typename VT, int MODE>
-__device__ __forceinline__ VT struct_row(const StructArgs &sa, int64_t r, const GLB VT *x)
+__device__ __forceinline__ VT struct_row(const StructArgs &sa, int64_t r, const GLB VT *x, int64_t k_first = -1,
+                                         int64_t k_end = -1)
 {
     const GLB float *Chi = gp(sa.blocks32);
     const GLB float *Clo = gp(sa.blocks32lo);
@@ -1231,7 +1232,11 @@ __device__ __forceinline__ VT struct_row(const StructArgs &sa, int64_t r, const 
     const GLB int64_t *irr_row = gp(sa.irr_row), *irr_vox = gp(sa.irr_vox);
     const GLB int32_t *irr_dir = gp(sa.irr_dir);
     const GLB double *irr_f = gp(sa.irr_f);
-    if (sa.n_irr > 0 && ((gp(sa.irr_bits)[r >> 5] >> (r & 31)) & 1u)) {
+    if (k_first >= 0) {
+        // the caller knows the row's range of the irregular-move list
+        k = k_first;
+        kend = k_end;
+    } else if (sa.n_irr > 0 && ((gp(sa.irr_bits)[r >> 5] >> (r & 31)) & 1u)) {
         int64_t lo = 0, hi = sa.n_irr;
         while (lo < hi) {
             const int64_t mid = (lo + hi) >> 1;
@@ -1273,42 +1278,82 @@ __device__ __forceinline__ VT struct_row(const StructArgs &sa, int64_t r, const 
     return acc;
 }
 
+// Plain-move value of regular row r = (w, m'), x from global memory: the
+// upstream voxel's block row when that voxel lies inside and has w's
+// refractive index, else zero.
+template <typename VT, int MODE>
+__device__ __forceinline__ VT struct_plain_row(const StructArgs &sa, int64_t r, const GLB VT *x)
+{
+    const GLB uint8_t *mat = gp(sa.mat);
+    const GLB double *index = gp(sa.index);
+    const int64_t w = r / kDirs;
+    const int mp = (int)(r % kDirs);
+    const int x0 = (int)(w % sa.nx), y0 = (int)((w / sa.nx) % sa.ny), z0 = (int)(w / ((int64_t)sa.nx * sa.ny));
+    const int ux = x0 - dir_dx(mp), uy = y0 - dir_dy(mp), uz = z0 - dir_dz(mp);
+    VT acc = 0;
+    if (ux >= 0 && ux < sa.nx && uy >= 0 && uy < sa.ny && uz >= 0 && uz < sa.nz) {
+        const int64_t u = ux + (int64_t)sa.nx * (uy + (int64_t)sa.ny * uz);
+        const int q = mat[u];
+        if (index[q] == index[mat[w]]) {
+            const int off = (q * kDirs + mp) * kDirs;
+            const GLB VT *xu = x + kDirs * u;
+            const GLB float *Chi = gp(sa.blocks32);
+            const GLB float *Clo = gp(sa.blocks32lo);
+            const GLB double *Cd = gp(sa.blocks64);
+            VT xv[kDirs];
+#pragma unroll
+            for (int n = 0; n < kDirs; ++n) xv[n] = xu[n];
+#pragma unroll
+            for (int n = 0; n < kDirs; ++n) {
+                if (MODE == 2 || MODE == 3) {
+                    acc += (VT)__builtin_fmaf(Chi[off + n], (float)xv[n], Clo[off + n] * (float)xv[n]);
+                } else {
+                    const VT c = StructVals<VT>::plain(Chi[off + n], Cd[off + n], sa.rounding, r, kDirs * u + n);
+                    acc += c * xv[n];
+                }
+            }
+        }
+    }
+    return acc;
+}
+
+__device__ __forceinline__ bool struct_irregular(const StructArgs &sa, int64_t r)
+{
+    return sa.n_irr > 0 && ((gp(sa.irr_bits)[r >> 5] >> (r & 31)) & 1u);
+}
+
+// A voxel tile: a segment of seg_len voxels of one x-line.
 struct StructTile {
     int64_t row0;
     int nrows;
-    bool vox;
     int x0, len;
-    int64_t line;   // y + ny z of a voxel tile
+    int64_t line;   // y + ny z
 };
 
+// 32-bit index arithmetic throughout: a single-rhs state has fewer than 2^30
+// rows (the solver refuses larger ones), so every row index fits.
 __device__ __forceinline__ StructTile struct_tile(const StructArgs &sa, int64_t k)
 {
     StructTile T;
-    if (k < sa.n_vox_tiles) {
-        T.line = k / sa.segs_per_line;
-        T.x0 = (int)(k % sa.segs_per_line) * sa.seg_len;
-        T.len = min(sa.seg_len, sa.nx - T.x0);
-        T.row0 = (int64_t)kDirs * (T.x0 + (int64_t)sa.nx * T.line);
-        T.nrows = kDirs * T.len;
-        T.vox = true;
-    } else {
-        T.line = 0;
-        T.x0 = 0;
-        T.len = 0;
-        T.row0 = sa.n_states + (k - sa.n_vox_tiles) * kEscTileRows;
-        T.nrows = (int)min((int64_t)kEscTileRows, sa.n_rows - T.row0);
-        T.vox = false;
-    }
+    const uint32_t kk = (uint32_t)k, spl = (uint32_t)sa.segs_per_line;
+    const uint32_t line = kk / spl;
+    T.line = line;
+    T.x0 = (int)(kk - line * spl) * sa.seg_len;
+    T.len = min(sa.seg_len, sa.nx - T.x0);
+    T.row0 = (int64_t)(uint32_t)(kDirs * (T.x0 + sa.nx * (int)line));
+    T.nrows = kDirs * T.len;
     return T;
 }
 
+// Matrix-free step, regular rows of the voxel tiles.  Irregular rows (wall
+// reflections, Fresnel splits) and escape rows are left to step_struct_x.
 // MODE 0: exact values, x gathered from global memory (FP64, dither).
-// MODE 1: exact nearest values, regular rows read x from an LDS halo.
-// MODE 2: hi + lo values, regular rows read x from an LDS halo.
+// MODE 1: exact nearest values, x from an LDS halo.
+// MODE 2: hi + lo values, x from an LDS halo.
 // MODE 3: hi + lo values, x gathered from global memory (many materials).
-// A voxel tile is a segment of L voxels of one x-line; the halo holds the x
-// blocks of the 3 x 3 neighbouring line segments (L + 2 voxels each), loaded
-// with contiguous reads, since a regular row's upstream voxel is one of them.
+// The halo holds the x blocks of the 3 x 3 neighbouring line segments (L + 2
+// voxels each), loaded with contiguous reads, since a regular row's upstream
+// voxel is one of them.
 template <typename VT, int MODE>
 __global__ void __launch_bounds__(256) step_struct(StructArgs sa, const StepInst *__restrict__ insts,
                                                     const WorkItem *__restrict__ work, int64_t n_work,
@@ -1316,9 +1361,10 @@ __global__ void __launch_bounds__(256) step_struct(StructArgs sa, const StepInst
 {
     constexpr int NT = 256, NW = NT / 64, L = kStructSegLen;
     constexpr int HV = L + 2;                       // voxels per halo line segment
-    constexpr int ROWS = kDirs * L > kEscTileRows ? kDirs * L : kEscTileRows;
+    constexpr int ROWS = kDirs * L;
     extern __shared__ double s_dyn[];
     __shared__ uint8_t s_q[9 * HV];
+    __shared__ uint32_t s_bits[(ROWS + 31) / 32 + 1];
     __shared__ int32_t s_src[kChunkMax + 1];
     __shared__ int32_t s_det[kChunkMax + 1];
     __shared__ double s_abs[kMatMax];
@@ -1340,6 +1386,13 @@ __global__ void __launch_bounds__(256) step_struct(StructArgs sa, const StepInst
     }
     for (int q = tid; q < sa.n_mat; q += NT) s_idx[q] = gp(sa.index)[q];
     __syncthreads();
+    // halo modes (at most kStructMatLds materials): bit qu * kStructMatLds + qw
+    // says whether materials qu and qw have the same refractive index
+    uint64_t same_idx = 0;
+    if (HALO)
+        for (int a = 0; a < sa.n_mat; ++a)
+            for (int b = 0; b < sa.n_mat; ++b)
+                if (s_idx[a] == s_idx[b]) same_idx |= 1ull << (a * kStructMatLds + b);
     const Walk wk = walk_of(n_work, xcd_remap, xcd_bounds);
     for (int64_t wi = wk.begin; wi < wk.end; wi += wk.stride) {
         const WorkItem item = work[wi];
@@ -1350,7 +1403,6 @@ __global__ void __launch_bounds__(256) step_struct(StructArgs sa, const StepInst
         const VT scale = (VT)ldexp(1.0, -sc.k);
         const GLB VT *x = gp((const VT *)((t & 1) ? I.buf1 : I.buf0));
         GLB VT *y = gpw((VT *)((t & 1) ? I.buf0 : I.buf1));
-        const int64_t n_states = I.n_states;
         const int64_t tile0 = (int64_t)item.chunk * I.tiles_per_chunk;
         const int ntc = (int)min((int64_t)I.tiles_per_chunk, I.n_tiles - tile0);
         for (int j = tid; j <= ntc; j += NT) {
@@ -1359,59 +1411,109 @@ __global__ void __launch_bounds__(256) step_struct(StructArgs sa, const StepInst
         }
         for (int q = tid; q < I.n_mat; q += NT) s_abs[q] = gp(I.absorb)[q];
         __syncthreads();
-        double sN = 0.0, sE = 0.0, sA = 0.0, dsum = 0.0;
+        double sN = 0.0, sA = 0.0, dsum = 0.0;
         VT mx = 0;
-        for (int j = 0; j < ntc; ++j) {
-            const StructTile T = struct_tile(sa, tile0 + j);
-            const bool halo = HALO && T.vox;
-            if (halo) {
-                // every load is issued before the first LDS store: coordinates
-                // are clamped into the grid and voxels outside it stored as zero
-                constexpr int SEGW = HV * kDirs;              // floats per halo line segment
-                constexpr int TOT = 9 * SEGW;
-                constexpr int PER = (TOT + NT - 1) / NT;
-                const int yv0 = (int)(T.line % sa.ny), zv0 = (int)(T.line / sa.ny);
-                float hv[PER];
+        // halo modes: the halos of the next two tiles (a halo line segment is
+        // SEGW contiguous floats of x: two loads per thread per segment from a
+        // uniform base, index clamped into the state, voxels outside the grid
+        // stored as zero), their material bytes and irregular-row bits are in
+        // flight in registers while the current tile is computed
+        constexpr int SEGW = HV * kDirs;
+        constexpr int PER = (SEGW + NT - 1) / NT;
+        static_assert(PER == 2, "halo segment loads per thread");
+        constexpr int BITW = (ROWS + 31) / 32 + 1;      // bitmap words a tile's rows touch
+        struct HaloRegs {
+            float hv[9][PER];
+            uint8_t q;
+            uint32_t b;
+        };
+        const int64_t n_words = (sa.n_states + 31) / 32;
+        const int n_st = (int)sa.n_states;
+        // a thread's rows sit at the same places of every tile (lr = tid +
+        // p NT): their direction and LDS offsets are computed once
+        constexpr int NPASS = (ROWS + NT - 1) / NT;
+        struct RowPos {
+            int mp, xo, qu, qw;
+        };
+        RowPos RP[NPASS];
 #pragma unroll
-                for (int k = 0; k < PER; ++k) {
-                    const int idx = min(tid + k * NT, TOT - 1);
-                    const int sg = idx / SEGW, rem = idx - sg * SEGW;
-                    const int iv = rem / kDirs, n = rem - iv * kDirs;
-                    const int xv = T.x0 - 1 + iv, yv = yv0 + sg % 3 - 1, zv = zv0 + sg / 3 - 1;
-                    const bool in = xv >= 0 && xv < sa.nx && yv >= 0 && yv < sa.ny && zv >= 0 && zv < sa.nz;
-                    const int xc = min(max(xv, 0), sa.nx - 1), yc = min(max(yv, 0), sa.ny - 1);
-                    const int zc = min(max(zv, 0), sa.nz - 1);
-                    const float v = (float)x[(int64_t)kDirs * (xc + (int64_t)sa.nx * (yc + (int64_t)sa.ny * zc)) + n];
-                    hv[k] = in ? v : 0.f;
-                }
+        for (int p = 0; p < NPASS; ++p) {
+            const int lr = min(tid + p * NT, ROWS - 1);
+            const int i = lr / kDirs, mp = lr - i * kDirs;
+            const int sg = (1 - dir_dz(mp)) * 3 + (1 - dir_dy(mp));
+            const int ix = i - dir_dx(mp) + 1;
+            RP[p].mp = mp;
+            RP[p].xo = (sg * HV + ix) * kDirs;
+            RP[p].qu = sg * HV + ix;
+            RP[p].qw = 4 * HV + i + 1;
+        }
+        auto fetch = [&](const StructTile &T, HaloRegs &P) {
+            const uint32_t line = (uint32_t)T.line;
+            const int zv0 = (int)(line / (uint32_t)sa.ny), yv0 = (int)line - zv0 * sa.ny;
+            // per-lane element offsets and x positions, the same for all 9 segments
+            int eo[PER];
+            bool xin[PER];
 #pragma unroll
-                for (int k = 0; k < PER; ++k) {
-                    const int idx = tid + k * NT;
-                    if (idx < TOT) s_x[idx] = hv[k];
-                }
-                if (tid < 9 * HV) {
-                    const int sg = tid / HV, iv = tid - sg * HV;
-                    const int xv = T.x0 - 1 + iv, yv = yv0 + sg % 3 - 1, zv = zv0 + sg / 3 - 1;
-                    uint8_t q = 255;
-                    if (xv >= 0 && xv < sa.nx && yv >= 0 && yv < sa.ny && zv >= 0 && zv < sa.nz)
-                        q = gp(sa.mat)[xv + (int64_t)sa.nx * (yv + (int64_t)sa.ny * zv)];
-                    s_q[tid] = q;
-                }
-                __syncthreads();
+            for (int k = 0; k < PER; ++k) {
+                eo[k] = min(tid + k * NT, SEGW - 1);
+                const int xv = T.x0 - 1 + eo[k] / kDirs;
+                xin[k] = xv >= 0 && xv < sa.nx;
             }
-            for (int lr = tid; lr < T.nrows; lr += NT) {
+#pragma unroll
+            for (int sg = 0; sg < 9; ++sg) {
+                const int yv = yv0 + sg % 3 - 1, zv = zv0 + sg / 3 - 1;
+                const bool line_in = yv >= 0 && yv < sa.ny && zv >= 0 && zv < sa.nz;
+                const int base = kDirs * (T.x0 - 1 + sa.nx * (min(max(yv, 0), sa.ny - 1) +
+                                                              sa.ny * min(max(zv, 0), sa.nz - 1)));
+#pragma unroll
+                for (int k = 0; k < PER; ++k) {
+                    const int at = min(max(base + eo[k], 0), n_st - 1);
+                    const float v = (float)x[at];
+                    P.hv[sg][k] = (line_in && xin[k]) ? v : 0.f;
+                }
+            }
+            P.q = 255;
+            if (tid < 9 * HV) {
+                const int sg = tid / HV, iv = tid - sg * HV;
+                const int xv = T.x0 - 1 + iv, yv = yv0 + sg % 3 - 1, zv = zv0 + sg / 3 - 1;
+                if (xv >= 0 && xv < sa.nx && yv >= 0 && yv < sa.ny && zv >= 0 && zv < sa.nz)
+                    P.q = gp(sa.mat)[xv + sa.nx * (yv + sa.ny * zv)];
+            }
+            P.b = 0;
+            if (tid < BITW && sa.n_irr > 0) P.b = gp(sa.irr_bits)[min((int)(T.row0 >> 5) + tid, (int)n_words - 1)];
+        };
+        auto do_tile = [&](int j, HaloRegs &P) {
+            const StructTile T = struct_tile(sa, tile0 + j);
+            if (HALO) {
+#pragma unroll
+                for (int sg = 0; sg < 9; ++sg)
+#pragma unroll
+                    for (int k = 0; k < PER; ++k) {
+                        const int e = tid + k * NT;
+                        if (e < SEGW) s_x[sg * SEGW + e] = P.hv[sg][k];
+                    }
+                if (tid < 9 * HV) s_q[tid] = P.q;
+                if (tid < BITW) s_bits[tid] = P.b;
+                __syncthreads();
+                if (j + 2 < ntc) fetch(struct_tile(sa, tile0 + j + 2), P);
+            }
+#pragma unroll
+            for (int p = 0; p < NPASS; ++p) {
+                const int lr = tid + p * NT;
+                if (lr >= T.nrows) continue;
                 const int64_t r = T.row0 + lr;
-                VT acc;
-                const bool irr = T.vox && sa.n_irr > 0 && ((gp(sa.irr_bits)[r >> 5] >> (r & 31)) & 1u);
-                if (halo && !irr) {
-                    const int i = lr / kDirs, mp = lr - i * kDirs;
-                    const int sg = (1 - dir_dz(mp)) * 3 + (1 - dir_dy(mp));
-                    const int ix = i - dir_dx(mp) + 1;
-                    const int qu = s_q[sg * HV + ix], qw = s_q[4 * HV + i + 1];
-                    acc = 0;
-                    if (qu != 255 && s_idx[qu] == s_idx[qw]) {
-                        const float *xs = s_x + (sg * HV + ix) * kDirs;
-                        const int off = (qu * kDirs + mp) * kDirs;
+                const int r32 = (int)r, rb0 = (int)(T.row0 >> 5);
+                const bool irr = HALO ? ((s_bits[(r32 >> 5) - rb0] >> (r32 & 31)) & 1u) != 0
+                                      : struct_irregular(sa, r);
+                if (irr) continue;   // step_struct_x computes it
+                VT acc = 0;
+                int qw;
+                if (HALO) {
+                    const int qu = s_q[RP[p].qu];
+                    qw = s_q[RP[p].qw];
+                    if (qu != 255 && (qu == qw || (same_idx >> (qu * kStructMatLds + qw)) & 1ull)) {
+                        const float *xs = s_x + RP[p].xo;
+                        const int off = (qu * kDirs + RP[p].mp) * kDirs;
 #pragma unroll
                         for (int n = 0; n < kDirs; ++n) {
                             if (MODE == 2) acc += (VT)__builtin_fmaf(s_Chi[off + n], xs[n], s_Clo[off + n] * xs[n]);
@@ -1419,7 +1521,8 @@ __global__ void __launch_bounds__(256) step_struct(StructArgs sa, const StepInst
                         }
                     }
                 } else {
-                    acc = struct_row<VT, (MODE == 2 || MODE == 3) ? 2 : 0>(sa, r, x);
+                    acc = struct_plain_row<VT, MODE>(sa, r, x);
+                    qw = gp(sa.mat)[r / kDirs];
                 }
                 VT v = acc * scale;
                 const int sb = s_src[j], se = s_src[j + 1];
@@ -1435,27 +1538,33 @@ __global__ void __launch_bounds__(256) step_struct(StructArgs sa, const StepInst
                 }
                 y[r] = v;
                 s_y[lr] = v;
-                if (r < n_states) {
-                    sN += (double)v;
-                    sA += s_abs[gp(sa.mat)[r / kDirs]] * (double)v;
-                    mx = v > mx ? v : mx;
-                } else {
-                    sE += (double)v;
-                }
+                sN += (double)v;
+                sA += s_abs[qw] * (double)v;
+                mx = v > mx ? v : mx;
             }
             __syncthreads();
             const int db = s_det[j], de = s_det[j + 1];
             if (db < de && tid < I.n_det) {
-                for (int e2 = db; e2 < de; ++e2)
-                    if (gp(I.det_id)[e2] == tid) dsum += gp(I.det_F)[e2] * (double)s_y[gp(I.det_row)[e2] - T.row0];
+                for (int e2 = db; e2 < de; ++e2) {
+                    if (gp(I.det_id)[e2] != tid) continue;
+                    const int64_t row = gp(I.det_row)[e2];
+                    if (!struct_irregular(sa, row)) dsum += gp(I.det_F)[e2] * (double)s_y[row - T.row0];
+                }
             }
             __syncthreads();
+        };
+        HaloRegs PA, PB;
+        if (HALO && ntc > 0) fetch(struct_tile(sa, tile0), PA);
+        if (HALO && ntc > 1) fetch(struct_tile(sa, tile0 + 1), PB);
+        for (int j = 0; j < ntc; j += 2) {
+            do_tile(j, PA);
+            if (j + 1 < ntc) do_tile(j + 1, PB);
         }
         const int64_t nc = I.n_chunks, c = item.chunk;
-        const double wN = wave_sum(sN), wE = wave_sum(sE), wA = wave_sum(sA), wM = wave_max((double)mx);
+        const double wN = wave_sum(sN), wA = wave_sum(sA), wM = wave_max((double)mx);
         if (lane == 0) {
             s_wred[0][wave] = wN;
-            s_wred[1][wave] = wE;
+            s_wred[1][wave] = 0.0;
             s_wred[2][wave] = wA;
             s_wred[3][wave] = wM;
         }
@@ -1467,6 +1576,124 @@ __global__ void __launch_bounds__(256) step_struct(StructArgs sa, const StepInst
             part[(int64_t)tid * nc + c] = a;
         }
         if (tid < I.n_det) part[(int64_t)(kSlotDet + tid) * nc + c] = dsum;
+        __syncthreads();
+    }
+}
+
+// Matrix-free step, the rows step_struct leaves: irregular rows and escape
+// rows, listed in ascending order in sa.xrows, kStructXRows per work item.
+// Each row is built from its move lists (struct_row) with x from global
+// memory; its partials go to chunk sa.chunk_base + item.
+template <typename VT, int MODE>
+__global__ void __launch_bounds__(256) step_struct_x(StructArgs sa, const StepInst *__restrict__ insts)
+{
+    constexpr int NT = 256, NW = NT / 64, XR = kStructXRows;
+    __shared__ VT s_y[XR];
+    __shared__ int64_t s_r[XR];
+    __shared__ double s_abs[kMatMax];
+    __shared__ double s_wred[4][NW];
+    __shared__ double s_red[NT];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const StepInst &I = insts[0];
+    const int64_t t = I.t[0];
+    if (t >= *I.t_end) return;
+    const Scale sc = step_scale(I, 0, t);
+    const VT scale = (VT)ldexp(1.0, -sc.k);
+    const GLB VT *x = gp((const VT *)((t & 1) ? I.buf1 : I.buf0));
+    GLB VT *y = gpw((VT *)((t & 1) ? I.buf0 : I.buf1));
+    const GLB int64_t *xrows = gp(sa.xrows);
+    const int64_t n_items = (sa.n_xrows + XR - 1) / XR;
+    for (int q = tid; q < I.n_mat; q += NT) s_abs[q] = gp(I.absorb)[q];
+    __syncthreads();
+    for (int64_t j = blockIdx.x; j < n_items; j += gridDim.x) {
+        const int64_t k0 = j * XR;
+        const int n = (int)min((int64_t)XR, sa.n_xrows - k0);
+        double sN = 0.0, sE = 0.0, sA = 0.0;
+        VT mx = 0;
+        for (int i = tid; i < n; i += NT) {
+            const int64_t r = xrows[k0 + i];
+            s_r[i] = r;
+            // irregular rows come with their range of the irregular-move list
+            const int64_t kf = gp(sa.xirr)[k0 + i], ke = gp(sa.xirr)[k0 + i + 1];
+            VT v = struct_row<VT, (MODE == 2 || MODE == 3) ? 2 : 0>(sa, r, x, kf, ke) * scale;
+            if (sa.n_src_entries > 0 && r < sa.n_states) {
+                int e2 = lower_bound_rows<int32_t>(I.src_row, 0, (int)sa.n_src_entries, r);
+                double s = 0.0;
+                bool any = false;
+                for (; e2 < sa.n_src_entries && gp(I.src_row)[e2] == r; ++e2) {
+                    s += gp(I.src_w)[e2] * gp(I.amp)[t * I.n_src + gp(I.src_id)[e2]];
+                    any = true;
+                }
+                if (any) v += (VT)ldexp(s, -sc.En);
+            }
+            y[r] = v;
+            s_y[i] = v;
+            if (r < sa.n_states) {
+                sN += (double)v;
+                sA += s_abs[gp(sa.mat)[r / kDirs]] * (double)v;
+                mx = v > mx ? v : mx;
+            } else {
+                sE += (double)v;
+            }
+        }
+        __syncthreads();
+        // detectors: per detector, its entries whose rows lie in this item's
+        // row span (a range of its row-sorted list), shared by all threads,
+        // then a fixed-order block sum; entries of rows not in the item
+        // belong to step_struct
+        const int64_t nc = I.n_chunks, c = sa.chunk_base + j;
+        GLB double *part = gpw(I.partials);
+        {
+            const int64_t ra = s_r[0], rb = s_r[n - 1];
+            const GLB int64_t *dp = gp(sa.ddet_ptr);
+            const GLB int64_t *drow = gp(sa.ddet_row);
+            const GLB double *dF = gp(sa.ddet_F);
+            for (int d = 0; d < I.n_det; ++d) {
+                int64_t lo = dp[d], hi = dp[d + 1];
+                {
+                    int64_t a = lo, b = hi;
+                    while (a < b) {
+                        const int64_t mid = (a + b) >> 1;
+                        if (drow[mid] < ra) a = mid + 1;
+                        else b = mid;
+                    }
+                    lo = a;
+                    b = hi;
+                    while (a < b) {
+                        const int64_t mid = (a + b) >> 1;
+                        if (drow[mid] <= rb) a = mid + 1;
+                        else b = mid;
+                    }
+                    hi = a;
+                }
+                double acc = 0.0;
+                for (int64_t e2 = lo + tid; e2 < hi; e2 += NT) {
+                    const int64_t row = drow[e2];
+                    int l = 0, h = n;
+                    while (l < h) {
+                        const int mid = (l + h) >> 1;
+                        if (s_r[mid] < row) l = mid + 1;
+                        else h = mid;
+                    }
+                    if (l < n && s_r[l] == row) acc += dF[e2] * (double)s_y[l];
+                }
+                acc = block_sum<NT>(acc, s_red);
+                if (tid == 0) part[(int64_t)(kSlotDet + d) * nc + c] = acc;
+            }
+        }
+        const double wN = wave_sum(sN), wE = wave_sum(sE), wA = wave_sum(sA), wM = wave_max((double)mx);
+        if (lane == 0) {
+            s_wred[0][wave] = wN;
+            s_wred[1][wave] = wE;
+            s_wred[2][wave] = wA;
+            s_wred[3][wave] = wM;
+        }
+        __syncthreads();
+        if (tid < 4) {
+            double a = s_wred[tid][0];
+            for (int w = 1; w < NW; ++w) a = (tid == 3) ? fmax(a, s_wred[tid][w]) : a + s_wred[tid][w];
+            part[(int64_t)tid * nc + c] = a;
+        }
         __syncthreads();
     }
 }
@@ -1559,24 +1786,41 @@ hipError_t launch_structured(const StructArgs &sa, const StepInst *insts_dev, co
                              int64_t n_work, int value_f64, int mode, int grid, int xcd_remap,
                              const int64_t *xcd_bounds, hipStream_t stream)
 {
-    if (n_work <= 0) return hipSuccess;
+    if (n_work <= 0 && sa.n_xrows <= 0) return hipSuccess;
     // the halo modes keep every direction block in LDS
     if (sa.n_mat > kStructMatLds) mode = (mode == 2) ? 3 : 0;
     const size_t blk = (size_t)sa.n_mat * kDirs * kDirs * 2 * sizeof(float);
     const size_t halo = (size_t)9 * (kStructSegLen + 2) * kDirs * sizeof(float);
     const dim3 g((unsigned)grid), b(256);
-    if (value_f64) {
-        hipLaunchKernelGGL((step_struct<double, 0>), g, b, 0, stream, sa, insts_dev, work_dev, n_work, xcd_remap & 1, xcd_bounds);
-    } else if (mode == 0) {
-        hipLaunchKernelGGL((step_struct<float, 0>), g, b, 0, stream, sa, insts_dev, work_dev, n_work, xcd_remap & 1, xcd_bounds);
-    } else if (mode == 1) {
-        hipLaunchKernelGGL((step_struct<float, 1>), g, b, blk + halo, stream, sa, insts_dev, work_dev, n_work,
-                           xcd_remap & 1, xcd_bounds);
-    } else if (mode == 2) {
-        hipLaunchKernelGGL((step_struct<float, 2>), g, b, blk + halo, stream, sa, insts_dev, work_dev, n_work,
-                           xcd_remap & 1, xcd_bounds);
-    } else {
-        hipLaunchKernelGGL((step_struct<float, 3>), g, b, 0, stream, sa, insts_dev, work_dev, n_work, xcd_remap & 1, xcd_bounds);
+    if (n_work > 0) {
+        if (value_f64) {
+            hipLaunchKernelGGL((step_struct<double, 0>), g, b, 0, stream, sa, insts_dev, work_dev, n_work,
+                               xcd_remap & 1, xcd_bounds);
+        } else if (mode == 0) {
+            hipLaunchKernelGGL((step_struct<float, 0>), g, b, 0, stream, sa, insts_dev, work_dev, n_work,
+                               xcd_remap & 1, xcd_bounds);
+        } else if (mode == 1) {
+            hipLaunchKernelGGL((step_struct<float, 1>), g, b, blk + halo, stream, sa, insts_dev, work_dev, n_work,
+                               xcd_remap & 1, xcd_bounds);
+        } else if (mode == 2) {
+            hipLaunchKernelGGL((step_struct<float, 2>), g, b, blk + halo, stream, sa, insts_dev, work_dev, n_work,
+                               xcd_remap & 1, xcd_bounds);
+        } else {
+            hipLaunchKernelGGL((step_struct<float, 3>), g, b, 0, stream, sa, insts_dev, work_dev, n_work,
+                               xcd_remap & 1, xcd_bounds);
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (sa.n_xrows > 0) {
+        const int64_t items = (sa.n_xrows + kStructXRows - 1) / kStructXRows;
+        const dim3 gx((unsigned)min(items, (int64_t)grid));
+        if (value_f64)
+            hipLaunchKernelGGL((step_struct_x<double, 0>), gx, b, 0, stream, sa, insts_dev);
+        else if (mode == 0 || mode == 1)
+            hipLaunchKernelGGL((step_struct_x<float, 0>), gx, b, 0, stream, sa, insts_dev);
+        else
+            hipLaunchKernelGGL((step_struct_x<float, 2>), gx, b, 0, stream, sa, insts_dev);
     }
     return hipGetLastError();
 }
