@@ -248,6 +248,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the SpMM, batch, serving and matrix-free measurements")
+    ap.add_argument("--struct-only", action="store_true",
+                    help="of the extra measurements, run only the matrix-free step (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, launch an elementwise kernel that reads and writes 1 GiB (counter scale)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
@@ -329,7 +331,7 @@ def main():
         line["structured"] = structured_step(torch, A, wl, tab)
     S.close()
     A.close()
-    if not args.no_extras:
+    if not args.no_extras and not args.struct_only:
         _log("C3 SpMM")
         line["spmm"] = spmm_vs_plain(torch)
         _log("C4 batch")
