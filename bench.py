@@ -210,12 +210,13 @@ def serving_vs_fifo(torch, n_req=32, step_scale=0.1):
     torch.cuda.empty_cache()
     budget = serve.footprint_budget(0.7)
     _log("C5: serving %d requests (budget %.1f GB)" % (n_req, budget / 1e9))
-    s = serve.serve(reqs, budget, quantum=50)
+    s = serve.serve(reqs, budget, quantum=50, max_active=4, policy="shortest")
     _log("C5: FIFO plain")
     f = serve.fifo_plain(reqs)
     r = lambda d: {k: round(v, 4) if isinstance(v, float) else v for k, v in d.items()}
     return {"workload": "C5 sample: first %d requests, 200/s Poisson arrivals, edges 32..128, steps %d..%d" %
                         (n_req, lo, hi),
+            "server": "least work first, at most 4 admitted, 50 steps per tick, budget 70% of free HBM",
             "served": r(s), "fifo_plain": r(f),
             "speedup_solves_per_s": round(s["solves_per_s"] / f["solves_per_s"], 2)}
 

@@ -310,9 +310,11 @@ void drts_batch_destroy(drts_batch_t *B);
 /* A request loop over the uneven batch, for many media solved at once.
  * Submitted requests wait in arrival order.  Each tick
  *   1. admits waiting requests whose HBM footprint fits the budget beside the
- *      requests already admitted, first-fit in arrival order (a request that
- *      has been passed over max_skips times stops later ones from being
- *      admitted ahead of it), and assembles their matrices on the device;
+ *      requests already admitted, first-fit in the policy's order (arrival,
+ *      or least work first; a request that has been passed over max_skips
+ *      times stops the ones after it from being admitted ahead of it), and
+ *      assembles their matrices on the device (the host model built at
+ *      submission is reused);
  *   2. advances every admitted request by up to `quantum` steps in batched
  *      launches: one launch per step covers all of them, so their work
  *      overlaps on the device;
@@ -323,10 +325,13 @@ void drts_batch_destroy(drts_batch_t *B);
  * medium before assembly, the exact size after), two state buffers, its
  * series and its source table.  Results equal those of the same solve run
  * alone (drts_run), bit for bit.  budget_bytes > 0; 1 <= quantum <= 100000;
- * 1 <= max_active <= 4096; max_skips >= 0.  Calls on one server must not
- * overlap. */
+ * 1 <= max_active <= 4096; max_skips >= 0; policy DRTS_SERVE_*.  Calls on
+ * one server must not overlap. */
+#define DRTS_SERVE_ARRIVAL 0  /* waiting requests are considered in arrival order */
+#define DRTS_SERVE_SHORTEST 1 /* ... in order of work (entries x steps), least first */
+
 int drts_serve_create(const drts_device_t *dev, int64_t budget_bytes, int32_t quantum, int32_t max_active,
-                      int32_t max_skips, drts_server_t **out);
+                      int32_t max_skips, int32_t policy, drts_server_t **out);
 
 /* Queues one solve of n_steps steps: an FP32 medium (its host arrays are
  * copied), its sources (the table must stay valid until the request has

@@ -703,6 +703,38 @@ extern "C" {
 
 const char *drts_last_error(void) { return g_error.c_str(); }
 
+}  // extern "C"
+
+namespace drts {
+
+int build_matrix_from_model(Model &&model, const drts_device_t *dev, drts_matrix_t **out)
+{
+    if (!out) return set_error(DRTS_E_INVALID, "out is NULL");
+    *out = nullptr;
+    drts_matrix *A = new (std::nothrow) drts_matrix;
+    if (!A) return set_error(DRTS_E_NOMEM, "host allocation failed");
+    A->m.dev = make_device(dev);
+    int rc;
+    try {
+        A->m.model = std::move(model);
+        rc = assemble_on_device(&A->m);
+    } catch (const std::bad_alloc &) {
+        rc = set_error(DRTS_E_NOMEM, "host allocation failed during assembly");
+    } catch (...) {
+        rc = set_error(DRTS_E_INVALID, "unexpected failure during assembly");
+    }
+    if (rc) {
+        delete A;
+        return rc;
+    }
+    *out = A;
+    return DRTS_OK;
+}
+
+}  // namespace drts
+
+extern "C" {
+
 int drts_build_matrix(const drts_medium_t *medium, const drts_device_t *dev, drts_matrix_t **out)
 {
     if (!out) return set_error(DRTS_E_INVALID, "out is NULL");

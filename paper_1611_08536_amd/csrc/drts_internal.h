@@ -95,4 +95,8 @@ struct Matrix {
 
 int assemble_on_device(Matrix *A);
 
+// drts_build_matrix for a medium whose host model is already built (the
+// model is moved into the matrix).
+int build_matrix_from_model(Model &&model, const drts_device_t *dev, drts_matrix_t **out);
+
 }  // namespace drts

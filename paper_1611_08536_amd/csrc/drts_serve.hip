@@ -39,6 +39,8 @@ struct Request {
     const drts_source_table_t *src = nullptr;
     int64_t est_bytes = 0;   // footprint bound before assembly
     int64_t bytes = 0;       // footprint held while admitted
+    double work = 0;         // entries of [A; L] (bound) x steps: the shortest-first key
+    Model model;             // host model, built once at submission, moved into the matrix
     drts_matrix_t *A = nullptr;
     drts_solver_t *S = nullptr;
     bool finished = false;
@@ -71,7 +73,7 @@ int64_t solver_bytes(int64_t n_rows, int64_t n_steps, int32_t n_det, int32_t n_s
 struct drts_server {
     drts_device_t dev{};
     int64_t budget = 0, used = 0;
-    int32_t quantum = 0, max_active = 0, max_skips = 0;
+    int32_t quantum = 0, max_active = 0, max_skips = 0, policy = 0;
     int64_t next_id = 1;
     std::deque<Request *> waiting;
     std::vector<Request *> active;
@@ -124,19 +126,24 @@ int copy_request(Request &q, const drts_medium_t *m, const drts_detectors_t *det
 // move), every entry 8 bytes (FP32 value, int32 column).
 int estimate_bytes(Request &q)
 {
-    Model M;
+    Model &M = q.model;
     int rc = build_model(&q.med, &M);
     if (rc) return rc;
     const int64_t nnz_ub = (int64_t)kDirs * (M.n_rows + (int64_t)M.irr_row.size());
     const int64_t mat = 8 * (nnz_ub + 4) + 8 * (M.n_rows + 1) + M.n_vox + (1 << 20);
     const int32_t n_src = q.src ? q.src->n_src : 0;
     q.est_bytes = mat + solver_bytes(M.n_rows, q.n_steps, q.n_det, n_src);
+    q.work = (double)nnz_ub * (double)q.n_steps;
     return DRTS_OK;
 }
 
 int admit(drts_server *Q, Request &q)
 {
-    int rc = drts_build_matrix(&q.med, &Q->dev, &q.A);
+    // the host model built at submission goes into the matrix (rebuilt if an
+    // earlier admission attempt consumed it)
+    int rc = DRTS_OK;
+    if (q.model.n_states == 0) rc = build_model(&q.med, &q.model);
+    if (!rc) rc = build_matrix_from_model(std::move(q.model), &Q->dev, &q.A);
     if (rc) return rc;
     drts_detectors_t det{};
     det.n_det = q.n_det;
@@ -179,9 +186,11 @@ int retire(drts_server *Q, Request &q)
 extern "C" {
 
 int drts_serve_create(const drts_device_t *dev, int64_t budget_bytes, int32_t quantum, int32_t max_active,
-                      int32_t max_skips, drts_server_t **out)
+                      int32_t max_skips, int32_t policy, drts_server_t **out)
 {
     if (!out) return set_error(DRTS_E_INVALID, "out is NULL");
+    if (policy != DRTS_SERVE_ARRIVAL && policy != DRTS_SERVE_SHORTEST)
+        return set_error(DRTS_E_INVALID, "unknown admission policy %d", policy);
     *out = nullptr;
     if (budget_bytes <= 0) return set_error(DRTS_E_INVALID, "budget_bytes must be positive");
     if (quantum < 1 || quantum > 100000) return set_error(DRTS_E_INVALID, "quantum in 1..100000");
@@ -194,6 +203,7 @@ int drts_serve_create(const drts_device_t *dev, int64_t budget_bytes, int32_t qu
     Q->quantum = quantum;
     Q->max_active = max_active;
     Q->max_skips = max_skips;
+    Q->policy = policy;
     *out = Q;
     return DRTS_OK;
 }
@@ -253,6 +263,10 @@ int drts_serve_tick(drts_server_t *Q, int32_t *n_active, int32_t *n_waiting, int
     int32_t finished = 0;
     // 1. admission: first fit in arrival order; a request passed over
     //    max_skips times blocks the ones behind it
+    if (Q->policy == DRTS_SERVE_SHORTEST)
+        // least work first; ties keep arrival order
+        std::stable_sort(Q->waiting.begin(), Q->waiting.end(),
+                         [](const Request *a, const Request *b) { return a->work < b->work; });
     std::vector<Request *> passed;   // earlier requests that did not fit this tick
     for (auto it = Q->waiting.begin(); it != Q->waiting.end() && (int)Q->active.size() < Q->max_active;) {
         Request &q = **it;

@@ -21,6 +21,7 @@ ROUND_NEAREST, ROUND_DITHER = 0, 1
 GEOM = {"voxels": 0, "homog": 0, "layers_z": 1, "sphere": 2}
 BC = {"vacuum": 0, "reflect": 1}
 KERNEL_CSR, KERNEL_STRUCTURED, KERNEL_STRUCTURED_SPLIT = 0, 1, 2
+SERVE_ARRIVAL, SERVE_SHORTEST = 0, 1
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libdrts.so is not built (run paper_1611_08536_amd._build.build())")
@@ -130,7 +131,7 @@ _sig("drts_batch_create", C.c_int, [C.POINTER(P), i32, C.POINTER(DeviceT), C.POI
 _sig("drts_batch_run", C.c_int, [P, C.POINTER(C.POINTER(SourceTableT)), C.POINTER(i64)])
 _sig("drts_batch_destroy", None, [P])
 _sig("drts_autotune", C.c_int, [P, C.c_char_p, C.POINTER(OptionsT)])
-_sig("drts_serve_create", C.c_int, [C.POINTER(DeviceT), i64, i32, i32, i32, C.POINTER(P)])
+_sig("drts_serve_create", C.c_int, [C.POINTER(DeviceT), i64, i32, i32, i32, i32, C.POINTER(P)])
 _sig("drts_serve_submit", C.c_int, [P, C.POINTER(MediumT), C.POINTER(SourceTableT), C.POINTER(DetectorsT), i64,
                                     C.POINTER(i64)])
 _sig("drts_serve_footprint", C.c_int, [C.POINTER(MediumT), C.POINTER(SourceTableT), C.POINTER(DetectorsT), i64,
@@ -472,11 +473,12 @@ class Server:
     """Continuous batching of independent FP32 solves (drts_serve_*)."""
 
     def __init__(self, budget_bytes: int, quantum: int = 50, max_active: int = 256, max_skips: int = 8,
-                 device: Optional[TorchDevice] = None):
+                 policy: str = "arrival", device: Optional[TorchDevice] = None):
         self.device = device or default_device()
         h = P()
+        pol = {"arrival": SERVE_ARRIVAL, "shortest": SERVE_SHORTEST}[policy]
         _check(_lib.drts_serve_create(C.byref(self.device.c), int(budget_bytes), int(quantum), int(max_active),
-                                      int(max_skips), C.byref(h)), "drts_serve_create")
+                                      int(max_skips), pol, C.byref(h)), "drts_serve_create")
         self._h = h
         self._req = {}     # id -> (n_steps, n_det, source table kept alive)
 

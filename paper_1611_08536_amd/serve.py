@@ -30,10 +30,10 @@ def _summary(lat: List[float], wall: float, n: int) -> dict:
 
 
 def serve(requests, budget_bytes: int, quantum: int = 50, max_active: int = 256, max_skips: int = 8,
-          keep_results: bool = False, log=None) -> dict:
+          policy: str = "arrival", keep_results: bool = False, log=None) -> dict:
     """Replays `requests` through one server; returns the latency summary and,
     with keep_results, every request's series in submission order."""
-    S = drts.Server(budget_bytes, quantum, max_active, max_skips)
+    S = drts.Server(budget_bytes, quantum, max_active, max_skips, policy)
     order = sorted(range(len(requests)), key=lambda i: requests[i].arrival_s)
     tables, rid_of, arrival_of = {}, {}, {}
     done_at, results = {}, {}

@@ -38,11 +38,12 @@ def _same(a, b):
             and np.array_equal(a["det"], b["det"]))
 
 
-def test_served_results_equal_solo_runs():
+@pytest.mark.parametrize("policy", ["arrival", "shortest"])
+def test_served_results_equal_solo_runs(policy):
     reqs = _requests(8)
     fps = sorted(_footprints(reqs))
     budget = sum(fps[-3:])
-    out = serve.serve(reqs, budget, quantum=16, max_active=6, max_skips=2, keep_results=True)
+    out = serve.serve(reqs, budget, quantum=16, max_active=6, max_skips=2, policy=policy, keep_results=True)
     assert 2 <= out["peak_active"] < len(reqs), out["peak_active"]
     solo = serve.fifo_plain(reqs, keep_results=True)
     for i in range(len(reqs)):

@@ -16,9 +16,9 @@ from paper_1611_08536_amd import sources  # noqa: E402
 lib = drts._lib
 
 
-def _server(budget, quantum=10, max_active=4, max_skips=2):
+def _server(budget, quantum=10, max_active=4, max_skips=2, policy=0):
     h = C.c_void_p()
-    assert lib.drts_serve_create(None, budget, quantum, max_active, max_skips, C.byref(h)) == 0
+    assert lib.drts_serve_create(None, budget, quantum, max_active, max_skips, policy, C.byref(h)) == 0
     return h
 
 
@@ -44,11 +44,12 @@ def _footprint(wl, n_steps=None):
 
 def test_create_rejects_bad_arguments():
     h = C.c_void_p()
-    assert lib.drts_serve_create(None, 0, 10, 4, 0, C.byref(h)) == -1
-    assert lib.drts_serve_create(None, 1 << 30, 0, 4, 0, C.byref(h)) == -1
-    assert lib.drts_serve_create(None, 1 << 30, 10, 0, 0, C.byref(h)) == -1
-    assert lib.drts_serve_create(None, 1 << 30, 10, 4, -1, C.byref(h)) == -1
-    assert lib.drts_serve_create(None, 1 << 30, 10, 4, 0, None) == -1
+    assert lib.drts_serve_create(None, 0, 10, 4, 0, 0, C.byref(h)) == -1
+    assert lib.drts_serve_create(None, 1 << 30, 0, 4, 0, 0, C.byref(h)) == -1
+    assert lib.drts_serve_create(None, 1 << 30, 10, 0, 0, 0, C.byref(h)) == -1
+    assert lib.drts_serve_create(None, 1 << 30, 10, 4, -1, 0, C.byref(h)) == -1
+    assert lib.drts_serve_create(None, 1 << 30, 10, 4, 0, 2, C.byref(h)) == -1
+    assert lib.drts_serve_create(None, 1 << 30, 10, 4, 0, 0, None) == -1
 
 
 @pytest.mark.parametrize("edge", [(10, 10), (14, 14)])
