@@ -133,11 +133,15 @@ def _state_and_series(wl, n, **kw):
     return out["x"], out["x_exp"], out["tot"], out["exp2"], out["det"]
 
 
-def test_step_run_and_graph_replay_identical():
+@pytest.mark.parametrize("kernel", [0, 2], ids=["csr", "struct_split"])
+def test_step_run_and_graph_replay_identical(kernel):
+    """Eager steps, drts_run and replays of a captured 8-step graph (the
+    matrix-free step forks its second kernel onto another stream inside the
+    capture) give the same state and series bit for bit."""
     wl = W.c2(n=16)
-    a = _state_and_series(wl, 50, use_run=False)
-    b = _state_and_series(wl, 50)
-    c = _state_and_series(wl, 50, options={"graph_steps": 8})
+    a = _state_and_series(wl, 50, use_run=False, options={"kernel": kernel})
+    b = _state_and_series(wl, 50, options={"kernel": kernel})
+    c = _state_and_series(wl, 50, options={"graph_steps": 8, "kernel": kernel})
     for x, y, z in zip(a, b, c):
         assert np.array_equal(x, y) and np.array_equal(y, z)
 
