@@ -198,12 +198,15 @@ void drts_matrix_destroy(drts_matrix_t *A);
 #define DRTS_KERNEL_STRUCTURED 1 /* matrix-free: every entry re-derived from the
                                     per-voxel direction block and rounded as
                                     stored, so the result equals the CSR step's
-                                    bit for bit (one rhs) */
+                                    bit for bit (one rhs: any rounding; several
+                                    rhs: nearest-rounded FP32 values only) */
 #define DRTS_KERNEL_STRUCTURED_SPLIT 2 /* matrix-free with each FP32 value carried
                                     as a hi + lo pair (about 48-bit values):
                                     more accurate than either stored rounding,
-                                    equal to the CSR step within rounding (one
-                                    rhs, FP32) */
+                                    equal to the CSR step within rounding (FP32;
+                                    several rhs: at most 8 materials).  With
+                                    several rhs each column equals the one-rhs
+                                    result of this kernel bit for bit */
 
 typedef struct {
     int32_t kernel;       /* DRTS_KERNEL_* */

@@ -125,8 +125,8 @@ struct drts_solver {
     int64_t n_tiles = 0, n_chunks = 0, n_xchunks = 0;
     int64_t t_host = 0;
 
-    Buffer buf0, buf1, ctl_t, ctl_E, ctl_M, ctl_abs, t_end, partials, fin_ticket, xcd_bounds, xrows, xirr, ddet_ptr, ddet_row,
-        ddet_F;
+    Buffer buf0, buf1, ctl_t, ctl_E, ctl_M, ctl_abs, t_end, partials, xcd_bounds, xrows, xirr, ddet_ptr, ddet_row,
+        ddet_F, pull_bits;
     Buffer ser_tot, ser_det, ser_exp, ser_abs_exp, amp, smax;
     Buffer src_tile, src_row, src_id, src_rhs, src_w;
     Buffer det_tile, det_row, det_id, det_F;
@@ -255,6 +255,56 @@ void structured_xrows(const Model &M, std::vector<int64_t> *rows, std::vector<in
     k.push_back(n_irr);
 }
 
+// Rows the many-rhs push kernel leaves to the pull kernel: irregular rows,
+// rows holding a source or a detector entry, and rows that take no plain move
+// (upstream voxel outside the grid or across an index change); then every
+// escape row.  Ascending, with each row's range of the irregular-move list.
+void structured_mm_pull(const Model &M, const std::vector<SourceEntry> &srcs, const std::vector<DetEntry> &dets,
+                        std::vector<uint32_t> *bits, std::vector<int64_t> *rows, std::vector<int64_t> *irr)
+{
+    std::vector<uint32_t> &b = *bits;
+    b.assign((size_t)((M.n_states + 31) / 32), 0u);
+    auto mark = [&](int64_t r) { b[(size_t)(r >> 5)] |= 1u << (r & 31); };
+    for (int64_t r : M.irr_row) mark(r);
+    for (const SourceEntry &e : srcs) mark(e.row);
+    for (const DetEntry &e : dets)
+        if (e.row < M.n_states) mark(e.row);
+    for (int z = 0; z < M.nz; ++z)
+        for (int y = 0; y < M.ny; ++y)
+            for (int x = 0; x < M.nx; ++x) {
+                const int64_t w = x + (int64_t)M.nx * (y + (int64_t)M.ny * z);
+                const double nw = M.index[M.mat_of_voxel[(size_t)w]];
+                for (int m = 0; m < kDirs; ++m) {
+                    const int ux = x - dir_dx(m), uy = y - dir_dy(m), uz = z - dir_dz(m);
+                    bool plain = ux >= 0 && ux < M.nx && uy >= 0 && uy < M.ny && uz >= 0 && uz < M.nz;
+                    if (plain) {
+                        const int64_t u = ux + (int64_t)M.nx * (uy + (int64_t)M.ny * uz);
+                        plain = M.index[M.mat_of_voxel[(size_t)u]] == nw;
+                    }
+                    if (!plain) mark(kDirs * w + m);
+                }
+            }
+    // row k's irregular moves are entries irr[k] .. irr[k+1]-1: irr[k] is the
+    // first entry at or after row k; every irregular row is listed, so no
+    // entry lies between two listed rows and the ranges are exact (empty for
+    // rows that are not irregular)
+    rows->clear();
+    irr->clear();
+    size_t k = 0;
+    const int64_t n_irr = (int64_t)M.irr_row.size();
+    for (int64_t r = 0; r < M.n_states; ++r) {
+        if (!((b[(size_t)(r >> 5)] >> (r & 31)) & 1u)) continue;
+        while (k < M.irr_row.size() && M.irr_row[k] < r) ++k;
+        rows->push_back(r);
+        irr->push_back((int64_t)k);
+    }
+    for (int64_t e = M.n_states; e < M.n_rows; ++e) {
+        rows->push_back(e);
+        irr->push_back(n_irr);
+    }
+    irr->push_back(n_irr);
+}
+
 // XCD-aware order of a solver's chunks.  With the remapped walk, XCD i takes
 // the i-th eighth of the work list; this order makes that eighth one slab of
 // y lines (ny / 8 of them) swept in z, so the x values a chunk gathers (the
@@ -354,16 +404,27 @@ int prepare(drts_solver *S)
         sa.irr_bits = A.irr_bits.as<uint32_t>();
         sa.n_irr = (int64_t)A.model.irr_row.size();
         sa.escape_state = A.escape_state.as<int64_t>();
-        bounds = structured_bounds(A.model, &sa);
-        S->n_tiles = (int64_t)bounds.size() - 1;
         std::vector<int64_t> xr, xk;
-        structured_xrows(A.model, &xr, &xk);
+        if (spmm_of(S)) {
+            // many rhs: push work items of kStructVoxPerChunk voxels, the pull list
+            const int64_t nvox = A.model.n_states / kDirs;
+            S->n_tiles = (nvox + kStructVoxPerChunk - 1) / kStructVoxPerChunk;
+            std::vector<uint32_t> pb;
+            structured_mm_pull(A.model, S->srcs, S->dets, &pb, &xr, &xk);
+            if ((rc = upload_vec(dev, S->pull_bits, pb))) return rc;
+            sa.pull_bits = S->pull_bits.as<uint32_t>();
+            S->n_xchunks = ((int64_t)xr.size() + kStructMmXRows - 1) / kStructMmXRows;
+        } else {
+            bounds = structured_bounds(A.model, &sa);
+            S->n_tiles = (int64_t)bounds.size() - 1;
+            structured_xrows(A.model, &xr, &xk);
+            S->n_xchunks = ((int64_t)xr.size() + kStructXRows - 1) / kStructXRows;
+        }
         if ((rc = upload_vec(dev, S->xrows, xr))) return rc;
         if ((rc = upload_vec(dev, S->xirr, xk))) return rc;
         sa.xrows = S->xrows.as<int64_t>();
         sa.xirr = S->xirr.as<int64_t>();
         sa.n_xrows = (int64_t)xr.size();
-        S->n_xchunks = (sa.n_xrows + kStructXRows - 1) / kStructXRows;
         sa.n_src_entries = (int64_t)S->srcs.size();
         sa.n_det_entries = (int64_t)S->dets.size();
         {
@@ -389,13 +450,30 @@ int prepare(drts_solver *S)
         S->n_tiles = (A.model.n_rows + o.rows_per_tile - 1) / o.rows_per_tile;
         S->n_xchunks = 0;
     }
-    S->n_chunks = (S->n_tiles + o.tiles_per_chunk - 1) / o.tiles_per_chunk;
+    // a work item of the many-rhs matrix-free step is one tile (kStructVoxPerChunk
+    // voxels); its kernels keep one set of partials per workgroup
+    const bool smm = structured_of(S) && spmm_of(S);
+    const int64_t tpc = smm ? 1 : o.tiles_per_chunk;
+    S->n_chunks = (S->n_tiles + tpc - 1) / tpc;
     if (structured_of(S)) S->sa.chunk_base = S->n_chunks;
+    int64_t n_part = S->n_chunks + S->n_xchunks;   // chunk partials the finalize reduces
     S->grid = o.grid > 0 ? o.grid : device_cu_count() * (spmm_of(S) ? 4 : 8);
+    if (smm) {
+        S->sa.mm_push_grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>(S->grid, S->n_chunks));
+        S->sa.mm_pull_grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>(S->grid, S->n_xchunks));
+        S->sa.chunk_base = S->sa.mm_push_grid;
+        n_part = S->sa.mm_push_grid + (S->n_xchunks > 0 ? S->sa.mm_pull_grid : 0);
+    }
     if (S->n_chunks > INT32_MAX) return set_error(DRTS_E_RANGE, "too many chunks");
 
-    // sources and detectors per tile
-    if (structured_of(S)) {
+    // sources and detectors per tile (the many-rhs matrix-free kernels look
+    // them up in the row-sorted lists instead)
+    if (structured_of(S) && spmm_of(S)) {
+        if ((rc = upload_vec(dev, S->src_tile, tile_offsets(S->srcs, S->n_tiles, kStructVoxPerChunk * kDirs))))
+            return rc;
+        if ((rc = upload_vec(dev, S->det_tile, tile_offsets(S->dets, S->n_tiles, kStructVoxPerChunk * kDirs))))
+            return rc;
+    } else if (structured_of(S)) {
         if ((rc = upload_vec(dev, S->src_tile, tile_offsets_bounds(S->srcs, bounds)))) return rc;
         if ((rc = upload_vec(dev, S->det_tile, tile_offsets_bounds(S->dets, bounds)))) return rc;
     } else {
@@ -403,10 +481,7 @@ int prepare(drts_solver *S)
         if ((rc = upload_vec(dev, S->det_tile, tile_offsets(S->dets, S->n_tiles, o.rows_per_tile)))) return rc;
     }
     const size_t slots = (size_t)(kSlotDet + S->n_det) * S->n_rhs;
-    if ((rc = S->partials.allocate(&dev, slots * (size_t)(S->n_chunks + S->n_xchunks + kFinSeg) * sizeof(double))))
-        return rc;
-    if ((rc = S->fin_ticket.allocate(&dev, (size_t)S->n_rhs * sizeof(int32_t)))) return rc;
-    DRTS_HIP(hipMemsetAsync(S->fin_ticket.ptr, 0, (size_t)S->n_rhs * sizeof(int32_t), dev.stream));
+    if ((rc = S->partials.allocate(&dev, slots * (size_t)(n_part + kFinSeg) * sizeof(double)))) return rc;
 
     StepInst &I = S->inst_h;
     memset(&I, 0, sizeof I);
@@ -419,7 +494,7 @@ int prepare(drts_solver *S)
     I.rp64 = A.rp64 ? 1 : 0;
     I.rows_per_tile = o.rows_per_tile;
     I.n_tiles = S->n_tiles;
-    I.tiles_per_chunk = o.tiles_per_chunk;
+    I.tiles_per_chunk = (int32_t)tpc;
     I.n_rhs = S->n_rhs;
     I.buf0 = S->buf0.ptr;
     I.buf1 = S->buf1.ptr;
@@ -447,8 +522,7 @@ int prepare(drts_solver *S)
     I.n_mat = (int32_t)A.model.mats.size();
     I.max_steps = S->max_steps;
     I.partials = S->partials.as<double>();
-    I.n_chunks = S->n_chunks + S->n_xchunks;   // the finalize reduces both kernels' chunks
-    I.fin_ticket = S->fin_ticket.as<int32_t>();
+    I.n_chunks = n_part;   // the finalize reduces both kernels' chunks
     I.ser_tot = S->ser_tot.as<double>();
     I.ser_det = S->ser_det.as<double>();
     I.ser_exp = S->ser_exp.as<int32_t>();
@@ -460,7 +534,7 @@ int prepare(drts_solver *S)
     if (o.xcd_remap == 2) order_by_slabs(S, bounds);
     if ((rc = upload_vec(dev, S->work_dev, S->work_h))) return rc;
     S->xcd_bounds.reset();
-    if (o.xcd_remap) {
+    if (o.xcd_remap && !(structured_of(S) && spmm_of(S))) {
         std::vector<int64_t> xb;
         if ((rc = balanced_xcd_bounds(S, bounds, &xb))) return rc;
         if ((rc = upload_vec(dev, S->xcd_bounds, xb))) return rc;
@@ -589,7 +663,10 @@ int launch_one(drts_solver *S, hipStream_t stream)
     }
     int32_t *queue = (!spmm && S->opt.queue && S->opt.kernel == DRTS_KERNEL_CSR) ? S->queue.as<int32_t>() : nullptr;
     hipError_t e;
-    if (structured_of(S)) {
+    if (structured_of(S) && spmm) {
+        e = launch_structured_mm(S->sa, S->inst_dev.as<StepInst>(), S->work_dev.as<WorkItem>(), S->n_chunks,
+                                 S->opt.kernel == DRTS_KERNEL_STRUCTURED_SPLIT ? 2 : 1, S->grid, S->n_det, stream);
+    } else if (structured_of(S)) {
         const bool f64 = A.model.value_type == DRTS_F64;
         int mode = 2;
         if (S->opt.kernel == DRTS_KERNEL_STRUCTURED) mode = (f64 || A.model.rounding == DRTS_ROUND_DITHER) ? 0 : 1;
@@ -670,8 +747,16 @@ int check_options(const drts_solver *S, const drts_options_t *o)
 {
     if (o->kernel < DRTS_KERNEL_CSR || o->kernel > DRTS_KERNEL_STRUCTURED_SPLIT)
         return set_error(DRTS_E_INVALID, "unknown kernel %d", o->kernel);
-    if (o->kernel != DRTS_KERNEL_CSR && S->n_rhs != 1)
-        return set_error(DRTS_E_INVALID, "the structured kernel takes one right-hand side");
+    if (o->kernel != DRTS_KERNEL_CSR && S->n_rhs != 1) {
+        const Model &M = S->A->m.model;
+        if (M.mats.size() > (size_t)kStructMatLdsHost)
+            return set_error(DRTS_E_INVALID, "the many-rhs matrix-free step takes at most %d materials",
+                             kStructMatLdsHost);
+        if (o->kernel == DRTS_KERNEL_STRUCTURED && M.rounding != DRTS_ROUND_NEAREST)
+            return set_error(DRTS_E_INVALID,
+                             "the exact many-rhs matrix-free step needs nearest-rounded values "
+                             "(use DRTS_KERNEL_STRUCTURED_SPLIT)");
+    }
     if (S->n_rhs == 1) {
         if (o->rows_per_tile != 64 && o->rows_per_tile != 128 && o->rows_per_tile != 256)
             return set_error(DRTS_E_INVALID, "rows_per_tile must be 64, 128 or 256 for one right-hand side");

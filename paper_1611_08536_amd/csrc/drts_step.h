@@ -9,7 +9,7 @@ namespace drts {
 
 // Slots of the per-chunk FP64 partials, each [n_rhs] wide.
 enum : int { kSlotN = 0, kSlotEsc = 1, kSlotAbs = 2, kSlotMax = 3, kSlotDet = 4 };
-// Segments of the first reduction level of the finalize kernel; the partials
+// Segments of the first reduction level of the finalize kernels; the partials
 // buffer holds [slots][n_chunks] chunk values followed by [slots][kFinSeg].
 constexpr int kFinSeg = 256;
 constexpr int kFinDetMax = 256;   // detectors per solver
@@ -61,7 +61,6 @@ struct StepInst {
     // partials [slot * n_rhs + rhs][n_chunks], then [slot * n_rhs + rhs][kFinSeg]
     double *partials;
     int64_t n_chunks;
-    int32_t *fin_ticket;    // [n_rhs] finalize blocks done this step (zero between steps)
     // series
     double *ser_tot;        // [max_steps][3][n_rhs]: N(t+1), escaped(t), absorbed(t)
     double *ser_det;        // [max_steps][n_det][n_rhs]
@@ -122,6 +121,11 @@ struct StructArgs {
     int64_t chunk_base;
     // entries of the row-sorted source and detector lists
     int64_t n_src_entries, n_det_entries;
+    // many right-hand sides: rows the push kernel leaves to the pull kernel
+    // (besides the escape rows), one bit per state
+    const uint32_t *pull_bits;
+    // their grids: one set of partials per workgroup, push then pull
+    int32_t mm_push_grid, mm_pull_grid;
     // detector entries grouped by detector, rows ascending within each:
     // detector d owns ddet_row/ddet_F [ddet_ptr[d], ddet_ptr[d+1])
     const int64_t *ddet_ptr, *ddet_row;
@@ -129,11 +133,20 @@ struct StructArgs {
 };
 constexpr int kStructSegLen = 16;
 constexpr int kStructXRows = 1024;
+constexpr int kStructMatLdsHost = 8;      // materials whose blocks the LDS holds
+constexpr int kStructVoxPerChunk = 64;   // voxels per work item of the push kernel
+constexpr int kStructMmXRows = 64;       // rows per work item of the many-rhs pull kernel
 // mode: 0 = exact values with global gathers, 1 = exact nearest values with
 // the LDS halo, 2 = hi + lo values with the LDS halo, 3 = hi + lo values with
 // global gathers (more materials than the LDS holds)
 hipError_t launch_structured(const StructArgs &sa, const StepInst *insts_dev, const WorkItem *work_dev,
                              int64_t n_work, int value_f64, int mode, int grid, int xcd_remap,
                              const int64_t *xcd_bounds, hipStream_t stream);
+
+// Matrix-free step for n_rhs > 1 (FP32; mode 1 = exact nearest values, 2 =
+// hi + lo): the push kernel over the voxel chunks of the work list, then the
+// pull kernel over sa.xrows.
+hipError_t launch_structured_mm(const StructArgs &sa, const StepInst *insts_dev, const WorkItem *work_dev,
+                                int64_t n_work, int mode, int grid, int n_det, hipStream_t stream);
 
 }  // namespace drts

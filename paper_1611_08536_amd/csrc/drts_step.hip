@@ -1034,21 +1034,17 @@ __global__ void __launch_bounds__(kNT) step_spmm(const StepInst *__restrict__ in
 // ---------------------------------------------------------------------------
 // finalize: fixed-order reduction of the chunk partials, series and control
 // ---------------------------------------------------------------------------
-// Two-level reduction of the per-chunk partials in a fixed order.  Block
-// (seg, inst, rhs) sums the chunks of segment seg (contiguous, kFinSeg of them
-// per instance) for every slot and stores one value per slot; the block that
-// takes the last ticket sums the segments in ascending order, records the
-// series and advances the control words.  The order of every addition depends
-// only on the number of chunks, never on which block finishes first.
-__global__ void __launch_bounds__(kNT) finalize_step(const StepInst *__restrict__ insts, int32_t *queue)
+// Two-level reduction of the per-chunk partials in a fixed order, in two
+// kernels (the kernel boundary orders the levels; no device-scope fence).
+// finalize_seg: block (seg, inst, rhs) sums the chunks of segment seg
+// (contiguous, kFinSeg segments per instance) for every slot and stores one
+// value per slot.  finalize_step: block (inst, rhs) sums the segments in
+// ascending order, records the series and advances the control words.  The
+// order of every addition depends only on the number of chunks.
+__global__ void __launch_bounds__(kNT) finalize_seg(const StepInst *__restrict__ insts)
 {
     constexpr int NW = kNT / 64;
     __shared__ double s_w[4][NW];
-    __shared__ double s_fin[kSlotDet + kFinDetMax];
-    __shared__ int s_last;
-    // the step kernel that used the work counter has completed: reset it for
-    // the next step (a kernel store, so the step loop can be graph-captured)
-    if (queue && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) *queue = 0;
     const StepInst &I = insts[blockIdx.y];
     const int rhs = blockIdx.z;
     if (rhs >= I.n_rhs) return;
@@ -1062,7 +1058,7 @@ __global__ void __launch_bounds__(kNT) finalize_step(const StepInst *__restrict_
     const int nr = I.n_rhs, nslot = kSlotDet + I.n_det;
     const int64_t c0 = seg * nc / nseg, c1 = (seg + 1) * nc / nseg;
     const GLB double *part = gp(I.partials);
-    double *segp = I.partials + (int64_t)nslot * nr * nc;   // [slot * n_rhs + rhs][kFinSeg]
+    GLB double *segp = gpw(I.partials + (int64_t)nslot * nr * nc);   // [slot * n_rhs + rhs][kFinSeg]
     // up to four slots per pass, so their loads are in flight together
     for (int k0 = 0; k0 < nslot; k0 += 4) {
         double a[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1087,23 +1083,37 @@ __global__ void __launch_bounds__(kNT) finalize_step(const StepInst *__restrict_
             double r = s_w[tid][0];
             for (int w = 1; w < NW; ++w) r = (k == kSlotMax) ? fmax(r, s_w[tid][w]) : r + s_w[tid][w];
             segp[((int64_t)k * nr + rhs) * kFinSeg + seg] = r;
-            __threadfence();   // release this block's segment values before its ticket
         }
         __syncthreads();
     }
-    if (tid == 0) s_last = atomicAdd(&I.fin_ticket[rhs], 1) == nseg - 1;
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();   // acquire the other blocks' segment values
+}
+
+__global__ void __launch_bounds__(kNT) finalize_step(const StepInst *__restrict__ insts, int32_t *queue)
+{
+    constexpr int NW = kNT / 64;
+    __shared__ double s_fin[kSlotDet + kFinDetMax];
+    // the step kernel that used the work counter has completed: reset it for
+    // the next step (a kernel store, so the step loop can be graph-captured)
+    if (queue && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *queue = 0;
+    const StepInst &I = insts[blockIdx.x];
+    const int rhs = blockIdx.y;
+    if (rhs >= I.n_rhs) return;
+    const int64_t t = I.t[rhs];
+    if (t >= *I.t_end) return;
+    const int64_t nc = I.n_chunks;
+    const int nseg = (int)min((int64_t)kFinSeg, nc);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nr = I.n_rhs, nslot = kSlotDet + I.n_det;
+    const GLB double *segp = gp(I.partials + (int64_t)nslot * nr * nc);
     // lane l combines segments l, l + 64, ... in ascending order, then the wave
     for (int k = wave; k < nslot; k += NW) {
-        const double *sp = segp + ((int64_t)k * nr + rhs) * kFinSeg;
+        const GLB double *sp = segp + ((int64_t)k * nr + rhs) * kFinSeg;
         double v = 0.0;
 #pragma unroll
         for (int j = 0; j < kFinSeg / 64; ++j) {
             const int sg = lane + 64 * j;
             if (sg < nseg) {
-                const double u = __hip_atomic_load(sp + sg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const double u = sp[sg];
                 v = (k == kSlotMax) ? fmax(v, u) : v + u;
             }
         }
@@ -1114,7 +1124,6 @@ __global__ void __launch_bounds__(kNT) finalize_step(const StepInst *__restrict_
     const Scale sc = step_scale(I, rhs, t);
     for (int d = tid; d < I.n_det; d += kNT) I.ser_det[(t * I.n_det + d) * nr + rhs] = s_fin[kSlotDet + d];
     if (tid == 0) {
-        I.fin_ticket[rhs] = 0;
         I.ser_tot[(t * 3 + 0) * nr + rhs] = s_fin[kSlotN];
         I.ser_tot[(t * 3 + 1) * nr + rhs] = s_fin[kSlotEsc];
         I.ser_tot[(t * 3 + 2) * nr + rhs] = I.abs_cur[rhs];
@@ -1140,7 +1149,7 @@ __global__ void __launch_bounds__(kNT) finalize_step(const StepInst *__restrict_
 // for bit, while the matrix itself never leaves the chip (per row only the
 // upstream voxel's 26 states of x are read, from L2).
 // ---------------------------------------------------------------------------
-constexpr int kStructMatLds = 8;   // direction blocks (hi, lo) kept in LDS up to this many materials
+constexpr int kStructMatLds = kStructMatLdsHost;   // direction blocks (hi, lo) kept in LDS up to this many materials
 
 __device__ __forceinline__ uint64_t mix64_dev(uint64_t x)
 {
@@ -1187,9 +1196,21 @@ template <> struct StructVals<double> {
 // MODE 2 carries every FP32 value as hi + lo and forms each term as
 // fma(hi, x, lo x): one rounding of the (almost exact) product, so the value
 // rounding error disappears.  Otherwise values are rounded as stored.
-template <typename VT, int MODE>
-__device__ __forceinline__ VT struct_row(const StructArgs &sa, int64_t r, const GLB VT *x, int64_t k_first = -1,
-                                         int64_t k_end = -1)
+// x access of struct_row: x[c] of a single state, or X[c][lane] of a state
+// with n_rhs columns (lanes past n_rhs read a valid column and drop it)
+template <typename VT> struct XPlain {
+    const GLB VT *x;
+    __device__ __forceinline__ VT operator()(int64_t c) const { return x[c]; }
+};
+struct XColumn {
+    const GLB float *x;
+    int k, lane;
+    __device__ __forceinline__ float operator()(int64_t c) const { return x[c * k + lane]; }
+};
+
+template <typename VT, int MODE, typename XA>
+__device__ __forceinline__ VT struct_row_a(const StructArgs &sa, int64_t r, const XA &xa, int64_t k_first,
+                                           int64_t k_end)
 {
     const GLB float *Chi = gp(sa.blocks32);
     const GLB float *Clo = gp(sa.blocks32lo);
@@ -1200,10 +1221,9 @@ __device__ __forceinline__ VT struct_row(const StructArgs &sa, int64_t r, const 
     auto plain_group = [&](int64_t u, int m) {
         const int q = mat[u];
         const int off = (q * kDirs + m) * kDirs;
-        const GLB VT *xu = x + kDirs * u;
         VT xv[kDirs];
 #pragma unroll
-        for (int n = 0; n < kDirs; ++n) xv[n] = xu[n];
+        for (int n = 0; n < kDirs; ++n) xv[n] = xa(kDirs * u + n);
 #pragma unroll
         for (int n = 0; n < kDirs; ++n) {
             if (MODE == 2) {
@@ -1264,7 +1284,7 @@ __device__ __forceinline__ VT struct_row(const StructArgs &sa, int64_t r, const 
                 if (c != 0.0) a = a + irr_f[kk] * c;
             }
             if (a != 0.0) {
-                const VT xv = x[kDirs * ug + n];
+                const VT xv = xa(kDirs * ug + n);
                 if (MODE == 2) {
                     const float h = (float)a, l = (float)(a - (double)h);
                     acc += (VT)__builtin_fmaf(h, (float)xv, l * (float)xv);
@@ -1276,6 +1296,13 @@ __device__ __forceinline__ VT struct_row(const StructArgs &sa, int64_t r, const 
         k = k1;
     }
     return acc;
+}
+
+template <typename VT, int MODE>
+__device__ __forceinline__ VT struct_row(const StructArgs &sa, int64_t r, const GLB VT *x, int64_t k_first = -1,
+                                         int64_t k_end = -1)
+{
+    return struct_row_a<VT, MODE>(sa, r, XPlain<VT>{x}, k_first, k_end);
 }
 
 // Plain-move value of regular row r = (w, m'), x from global memory: the
@@ -1698,6 +1725,216 @@ __global__ void __launch_bounds__(256) step_struct_x(StructArgs sa, const StepIn
     }
 }
 
+// ---------------------------------------------------------------------------
+// Matrix-free step for n_rhs right-hand sides (lanes = right-hand sides)
+//
+// Push form: one wave per source voxel u.  The wave reads u's 26 rows of X
+// once (a coalesced 4 n_rhs-byte load each), forms z[m] = sum_n C[m][n] X[n]
+// with the block coefficients read from LDS at uniform addresses, and writes
+// z[m] as the whole row (u + e_m, m) of Y: every regular row is written by
+// exactly one voxel, so X is read once per step instead of once per using
+// row.  Rows marked in sa.pull_bits (irregular, source and detector rows,
+// rows whose upstream voxel is outside or across an index change) and the
+// escape rows are left to the pull kernel.  Terms are added in column order
+// as the single-rhs kernels add them.
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ void __launch_bounds__(256) step_struct_mm(StructArgs sa, const StepInst *__restrict__ insts,
+                                                       const WorkItem *__restrict__ work, int64_t n_work)
+{
+    constexpr int NT = 256, NW = NT / 64;
+    extern __shared__ double s_dyn[];
+    __shared__ double s_abs[kMatMax];
+    __shared__ double s_w[4][NW][64];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nblk = sa.n_mat * kDirs * kDirs;
+    float *s_Chi = (float *)s_dyn;
+    float *s_Clo = s_Chi + nblk;
+    for (int i = tid; i < nblk; i += NT) {
+        s_Chi[i] = gp(sa.blocks32)[i];
+        s_Clo[i] = gp(sa.blocks32lo)[i];
+    }
+    const StepInst &I = insts[0];
+    for (int q = tid; q < I.n_mat; q += NT) s_abs[q] = gp(I.absorb)[q];
+    __syncthreads();
+    const int64_t t = I.t[0];
+    if (t >= *I.t_end) return;
+    const int nrhs = I.n_rhs;
+    const bool active = lane < nrhs;
+    const int xl = min(lane, nrhs - 1);
+    Scale sc{0, 0};
+    if (active) sc = step_scale(I, lane, t);
+    const float scale = ldexpf(1.0f, -sc.k);
+    const GLB float *X = gp((const float *)((t & 1) ? I.buf1 : I.buf0));
+    GLB float *Y = gpw((float *)((t & 1) ? I.buf0 : I.buf1));
+    const GLB uint8_t *mat = gp(sa.mat);
+    const GLB uint32_t *pull = gp(sa.pull_bits);
+    const int nvox = (int)(sa.n_states / kDirs);
+    const int64_t nc = I.n_chunks;
+    // one set of partials per workgroup (chunk blockIdx.x): the walk over the
+    // work items is fixed, so the sums are too
+    double sN = 0.0, sA = 0.0;
+    float mx = 0.0f;
+    for (int64_t wi = blockIdx.x; wi < n_work; wi += gridDim.x) {
+        const int c = work[wi].chunk;
+        const int v0 = c * kStructVoxPerChunk, v1 = min(v0 + kStructVoxPerChunk, nvox);
+        for (int u = v0 + wave; u < v1; u += NW) {
+            const int q = mat[u];
+            const int ux = u % sa.nx, uy = (u / sa.nx) % sa.ny, uz = u / (sa.nx * sa.ny);
+            float xv[kDirs];
+#pragma unroll
+            for (int n = 0; n < kDirs; ++n) xv[n] = X[(int64_t)(kDirs * u + n) * nrhs + xl];
+            // lane m < 26 looks up target row (u + e_m, m) once: inside the grid
+            // and not a pull row, and the material of its voxel
+            int lr = 0, lq = 0;
+            bool lok = false;
+            if (lane < kDirs) {
+                const int wx = ux + dir_dx(lane), wy = uy + dir_dy(lane), wz = uz + dir_dz(lane);
+                if (wx >= 0 && wx < sa.nx && wy >= 0 && wy < sa.ny && wz >= 0 && wz < sa.nz) {
+                    const int w = wx + sa.nx * (wy + sa.ny * wz);
+                    lr = kDirs * w + lane;
+                    lok = !((pull[lr >> 5] >> (lr & 31)) & 1u);
+                    lq = mat[w];
+                }
+            }
+            const uint64_t pushed = __ballot(lok);
+            for (int m = 0; m < kDirs; ++m) {
+                if (!((pushed >> m) & 1ull)) continue;
+                const int r = __builtin_amdgcn_readlane(lr, m);
+                const int qw = __builtin_amdgcn_readlane(lq, m);
+                const int off = (q * kDirs + m) * kDirs;
+                float acc = 0.0f;
+#pragma unroll
+                for (int n = 0; n < kDirs; ++n) {
+                    if (MODE == 2) acc += __builtin_fmaf(s_Chi[off + n], xv[n], s_Clo[off + n] * xv[n]);
+                    else acc += s_Chi[off + n] * xv[n];
+                }
+                const float v = acc * scale;
+                if (active) {
+                    Y[(int64_t)r * nrhs + lane] = v;
+                    sN += (double)v;
+                    sA += s_abs[qw] * (double)v;
+                    mx = fmaxf(mx, v);
+                }
+            }
+        }
+    }
+    s_w[0][wave][lane] = sN;
+    s_w[1][wave][lane] = sA;
+    s_w[2][wave][lane] = (double)mx;
+    __syncthreads();
+    const int64_t c = blockIdx.x;
+    if (wave == 0 && active) {
+        const double N = ((s_w[0][0][lane] + s_w[0][1][lane]) + s_w[0][2][lane]) + s_w[0][3][lane];
+        const double A = ((s_w[1][0][lane] + s_w[1][1][lane]) + s_w[1][2][lane]) + s_w[1][3][lane];
+        const double M = fmax(fmax(s_w[2][0][lane], s_w[2][1][lane]), fmax(s_w[2][2][lane], s_w[2][3][lane]));
+        GLB double *part = gpw(I.partials);
+        part[((int64_t)kSlotN * nrhs + lane) * nc + c] = N;
+        part[((int64_t)kSlotEsc * nrhs + lane) * nc + c] = 0.0;
+        part[((int64_t)kSlotAbs * nrhs + lane) * nc + c] = A;
+        part[((int64_t)kSlotMax * nrhs + lane) * nc + c] = M;
+        for (int d = 0; d < I.n_det; ++d) part[((int64_t)(kSlotDet + d) * nrhs + lane) * nc + c] = 0.0;
+    }
+}
+
+// Pull rows of the matrix-free many-rhs step (sa.xrows, kStructMmXRows per
+// work item): each row from its move lists (struct_row) with X read per lane;
+// sources of the row's own right-hand side; detector sums per wave in LDS,
+// combined over the waves in a fixed order.  Partials go to chunk
+// sa.chunk_base + item.
+template <int MODE>
+__global__ void __launch_bounds__(256) step_struct_mm_x(StructArgs sa, const StepInst *__restrict__ insts)
+{
+    constexpr int NT = 256, NW = NT / 64, XR = kStructMmXRows;
+    extern __shared__ double s_det[];   // [NW][n_det][64]
+    __shared__ double s_abs[kMatMax];
+    __shared__ double s_w[4][NW][64];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const StepInst &I = insts[0];
+    for (int q = tid; q < I.n_mat; q += NT) s_abs[q] = gp(I.absorb)[q];
+    __syncthreads();
+    const int64_t t = I.t[0];
+    if (t >= *I.t_end) return;
+    const int nrhs = I.n_rhs, nd = I.n_det;
+    const bool active = lane < nrhs;
+    const int xl = min(lane, nrhs - 1);
+    Scale sc{0, 0};
+    if (active) sc = step_scale(I, lane, t);
+    const float scale = ldexpf(1.0f, -sc.k);
+    const GLB float *X = gp((const float *)((t & 1) ? I.buf1 : I.buf0));
+    GLB float *Y = gpw((float *)((t & 1) ? I.buf0 : I.buf1));
+    const XColumn xa{X, nrhs, xl};
+    const GLB int64_t *xrows = gp(sa.xrows);
+    const GLB int64_t *xirr = gp(sa.xirr);
+    const int64_t n_items = (sa.n_xrows + XR - 1) / XR;
+    const int64_t nc = I.n_chunks;
+    double *my_det = s_det + (int64_t)wave * nd * 64;
+    // one set of partials per workgroup (chunk chunk_base + blockIdx.x), over a
+    // fixed walk of the work items
+    for (int d = 0; d < nd; ++d) my_det[d * 64 + lane] = 0.0;
+    double sN = 0.0, sE = 0.0, sA = 0.0;
+    float mx = 0.0f;
+    for (int64_t j = blockIdx.x; j < n_items; j += gridDim.x) {
+        const int64_t k0 = j * XR, k1 = min(k0 + XR, sa.n_xrows);
+        for (int64_t k = k0 + wave; k < k1; k += NW) {
+            const int64_t r = xrows[k];
+            float v = struct_row_a<float, (MODE == 2) ? 2 : 0>(sa, r, xa, xirr[k], xirr[k + 1]) * scale;
+            if (sa.n_src_entries > 0 && r < sa.n_states) {
+                int e2 = lower_bound_rows<int32_t>(I.src_row, 0, (int)sa.n_src_entries, r);
+                double s = 0.0;
+                bool any = false;
+                for (; e2 < sa.n_src_entries && gp(I.src_row)[e2] == r; ++e2) {
+                    if (gp(I.src_rhs)[e2] == lane) {
+                        s += gp(I.src_w)[e2] * gp(I.amp)[t * I.n_src + gp(I.src_id)[e2]];
+                        any = true;
+                    }
+                }
+                if (any) v += (float)ldexp(s, -sc.En);
+            }
+            if (active) {
+                Y[r * nrhs + lane] = v;
+                if (r < sa.n_states) {
+                    sN += (double)v;
+                    sA += s_abs[gp(sa.mat)[r / kDirs]] * (double)v;
+                    mx = fmaxf(mx, v);
+                } else {
+                    sE += (double)v;
+                }
+                if (sa.n_det_entries > 0) {
+                    int e2 = lower_bound_rows<int32_t>(I.det_row, 0, (int)sa.n_det_entries, r);
+                    for (; e2 < sa.n_det_entries && gp(I.det_row)[e2] == r; ++e2)
+                        my_det[gp(I.det_id)[e2] * 64 + lane] += gp(I.det_F)[e2] * (double)v;
+                }
+            }
+        }
+    }
+    s_w[0][wave][lane] = sN;
+    s_w[1][wave][lane] = sE;
+    s_w[2][wave][lane] = sA;
+    s_w[3][wave][lane] = (double)mx;
+    __syncthreads();
+    const int64_t c = sa.chunk_base + blockIdx.x;
+    if (wave == 0 && active) {
+        const double N = ((s_w[0][0][lane] + s_w[0][1][lane]) + s_w[0][2][lane]) + s_w[0][3][lane];
+        const double Es = ((s_w[1][0][lane] + s_w[1][1][lane]) + s_w[1][2][lane]) + s_w[1][3][lane];
+        const double A = ((s_w[2][0][lane] + s_w[2][1][lane]) + s_w[2][2][lane]) + s_w[2][3][lane];
+        const double M = fmax(fmax(s_w[3][0][lane], s_w[3][1][lane]), fmax(s_w[3][2][lane], s_w[3][3][lane]));
+        GLB double *part = gpw(I.partials);
+        part[((int64_t)kSlotN * nrhs + lane) * nc + c] = N;
+        part[((int64_t)kSlotEsc * nrhs + lane) * nc + c] = Es;
+        part[((int64_t)kSlotAbs * nrhs + lane) * nc + c] = A;
+        part[((int64_t)kSlotMax * nrhs + lane) * nc + c] = M;
+        for (int d = 0; d < nd; ++d) {
+            const double D = ((s_det[(0 * nd + d) * 64 + lane] + s_det[(1 * nd + d) * 64 + lane]) +
+                              s_det[(2 * nd + d) * 64 + lane]) +
+                             s_det[(3 * nd + d) * 64 + lane];
+            part[((int64_t)(kSlotDet + d) * nrhs + lane) * nc + c] = D;
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int64_t n_work, int n_inst,
@@ -1825,13 +2062,42 @@ hipError_t launch_structured(const StructArgs &sa, const StepInst *insts_dev, co
     return hipGetLastError();
 }
 
+hipError_t launch_structured_mm(const StructArgs &sa, const StepInst *insts_dev, const WorkItem *work_dev,
+                                int64_t n_work, int mode, int grid, int n_det, hipStream_t stream)
+{
+    const size_t blk = (size_t)sa.n_mat * kDirs * kDirs * 2 * sizeof(float);
+    const dim3 b(256);
+    (void)grid;
+    if (n_work > 0) {
+        const dim3 g((unsigned)sa.mm_push_grid);
+        if (mode == 2)
+            hipLaunchKernelGGL((step_struct_mm<2>), g, b, blk, stream, sa, insts_dev, work_dev, n_work);
+        else
+            hipLaunchKernelGGL((step_struct_mm<1>), g, b, blk, stream, sa, insts_dev, work_dev, n_work);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (sa.n_xrows > 0) {
+        const dim3 gx((unsigned)sa.mm_pull_grid);
+        const size_t lds = (size_t)4 * n_det * 64 * sizeof(double);
+        if (mode == 2)
+            hipLaunchKernelGGL((step_struct_mm_x<2>), gx, b, lds, stream, sa, insts_dev);
+        else
+            hipLaunchKernelGGL((step_struct_mm_x<1>), gx, b, lds, stream, sa, insts_dev);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_finalize(const StepInst *insts_dev, int n_inst, int n_rhs_max, int n_det_max, int32_t *queue,
                            hipStream_t stream)
 {
     (void)n_det_max;
     if (n_inst <= 0) return hipSuccess;
-    hipLaunchKernelGGL(finalize_step, dim3((unsigned)kFinSeg, (unsigned)n_inst, (unsigned)n_rhs_max), dim3(kNT), 0,
-                       stream, insts_dev,
+    hipLaunchKernelGGL(finalize_seg, dim3((unsigned)kFinSeg, (unsigned)n_inst, (unsigned)n_rhs_max), dim3(kNT), 0,
+                       stream, insts_dev);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(finalize_step, dim3((unsigned)n_inst, (unsigned)n_rhs_max), dim3(kNT), 0, stream, insts_dev,
                        queue);
     return hipGetLastError();
 }
