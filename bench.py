@@ -134,12 +134,19 @@ def spmm_vs_plain(torch, steps=20):
     from paper_1611_08536_amd import drts, solve
     wl = W.c3(n_steps=steps + 4)
     A = drts.Matrix(wl.medium, wl.value_type, wl.rounding, wl.n_ref)
-    S = drts.Solver(A, wl.n_rhs, wl.detectors, max_steps=steps + 4)
+    S = drts.Solver(A, wl.n_rhs, wl.detectors, max_steps=2 * steps + 8)
     tab = solve.source_table(A, wl)
     S.run(tab, 2)
     S.profile(True)
     t_mm = _timed(lambda: S.run(tab, steps), torch)
     n_l, k_ms = S.profile_stats()
+    # the matrix-free many-rhs step (hi + lo values) on the same solver
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    S.set_options(kernel=drts.KERNEL_STRUCTURED_SPLIT, grid=16 * cus)
+    S.run(tab, 2)
+    S.profile(True)
+    t_mf = _timed(lambda: S.run(tab, steps), torch)
+    n_f, f_ms = S.profile_stats()
     S.close()
     w1 = copy.copy(wl)
     w1.sources = [copy.copy(x) for x in wl.sources if x.rhs == 0]
@@ -161,6 +168,14 @@ def spmm_vs_plain(torch, steps=20):
            "ms_per_step": round(t_mm / steps * 1e3, 3), "plain_ms_per_step": round(t_1 / steps * 1e3, 3),
            "kernel": "step_spmm<int32>", "kernel_ms": round(kern_s * 1e3, 3),
            "achieved_GBs": round(nbytes / kern_s / 1e9, 1), "frac": round(nbytes / kern_s / 1e9 / PEAK_HBM_GBS, 4)}
+    mf_s = f_ms / max(n_f, 1) * 1e-3
+    mf_bytes = 4 * k * A.n_states + 4 * k * A.n_rows + A.n_states // 26
+    out["matrix_free"] = {"kernel": "step_struct_mm<2> + step_struct_mm_x<2> (hi+lo values)",
+                          "ms_per_step": round(t_mf / steps * 1e3, 3), "kernel_ms": round(mf_s * 1e3, 3),
+                          "solve_steps_per_s": round(k * steps / t_mf, 1),
+                          "speedup_vs_plain": round((k * steps / t_mf) / (steps / t_1), 2),
+                          "algorithmic_bytes": mf_bytes, "achieved_GBs": round(mf_bytes / mf_s / 1e9, 1),
+                          "frac": round(mf_bytes / mf_s / 1e9 / PEAK_HBM_GBS, 4)}
     A.close()
     return out
 

@@ -126,7 +126,7 @@ struct drts_solver {
     int64_t t_host = 0;
 
     Buffer buf0, buf1, ctl_t, ctl_E, ctl_M, ctl_abs, t_end, partials, xcd_bounds, xrows, xirr, ddet_ptr, ddet_row,
-        ddet_F, pull_bits;
+        ddet_F, pull_bits, esc_base;
     Buffer ser_tot, ser_det, ser_exp, ser_abs_exp, amp, smax;
     Buffer src_tile, src_row, src_id, src_rhs, src_w;
     Buffer det_tile, det_row, det_id, det_F;
@@ -256,19 +256,20 @@ void structured_xrows(const Model &M, std::vector<int64_t> *rows, std::vector<in
 }
 
 // Rows the many-rhs push kernel leaves to the pull kernel: irregular rows,
-// rows holding a source or a detector entry, and rows that take no plain move
-// (upstream voxel outside the grid or across an index change); then every
-// escape row.  Ascending, with each row's range of the irregular-move list.
+// rows holding a source or a detector entry (escape rows included), and state
+// rows that take no plain move (upstream voxel outside the grid or across an
+// index change).  Ascending, with each row's range of the irregular-move list;
+// and per voxel the offset of its first escape row.
 void structured_mm_pull(const Model &M, const std::vector<SourceEntry> &srcs, const std::vector<DetEntry> &dets,
-                        std::vector<uint32_t> *bits, std::vector<int64_t> *rows, std::vector<int64_t> *irr)
+                        std::vector<uint32_t> *bits, std::vector<int64_t> *rows, std::vector<int64_t> *irr,
+                        std::vector<int32_t> *esc_base)
 {
     std::vector<uint32_t> &b = *bits;
-    b.assign((size_t)((M.n_states + 31) / 32), 0u);
+    b.assign((size_t)((M.n_rows + 31) / 32), 0u);
     auto mark = [&](int64_t r) { b[(size_t)(r >> 5)] |= 1u << (r & 31); };
     for (int64_t r : M.irr_row) mark(r);
     for (const SourceEntry &e : srcs) mark(e.row);
-    for (const DetEntry &e : dets)
-        if (e.row < M.n_states) mark(e.row);
+    for (const DetEntry &e : dets) mark(e.row);
     for (int z = 0; z < M.nz; ++z)
         for (int y = 0; y < M.ny; ++y)
             for (int x = 0; x < M.nx; ++x) {
@@ -291,18 +292,16 @@ void structured_mm_pull(const Model &M, const std::vector<SourceEntry> &srcs, co
     rows->clear();
     irr->clear();
     size_t k = 0;
-    const int64_t n_irr = (int64_t)M.irr_row.size();
-    for (int64_t r = 0; r < M.n_states; ++r) {
+    for (int64_t r = 0; r < M.n_rows; ++r) {
         if (!((b[(size_t)(r >> 5)] >> (r & 31)) & 1u)) continue;
         while (k < M.irr_row.size() && M.irr_row[k] < r) ++k;
         rows->push_back(r);
         irr->push_back((int64_t)k);
     }
-    for (int64_t e = M.n_states; e < M.n_rows; ++e) {
-        rows->push_back(e);
-        irr->push_back(n_irr);
-    }
-    irr->push_back(n_irr);
+    irr->push_back((int64_t)M.irr_row.size());
+    esc_base->assign((size_t)M.n_vox, 0);
+    for (int64_t i = (int64_t)M.escape_state.size() - 1; i >= 0; --i)
+        (*esc_base)[(size_t)(M.escape_state[(size_t)i] / kDirs)] = (int32_t)i;
 }
 
 // XCD-aware order of a solver's chunks.  With the remapped walk, XCD i takes
@@ -410,9 +409,12 @@ int prepare(drts_solver *S)
             const int64_t nvox = A.model.n_states / kDirs;
             S->n_tiles = (nvox + kStructVoxPerChunk - 1) / kStructVoxPerChunk;
             std::vector<uint32_t> pb;
-            structured_mm_pull(A.model, S->srcs, S->dets, &pb, &xr, &xk);
+            std::vector<int32_t> eb;
+            structured_mm_pull(A.model, S->srcs, S->dets, &pb, &xr, &xk, &eb);
             if ((rc = upload_vec(dev, S->pull_bits, pb))) return rc;
+            if ((rc = upload_vec(dev, S->esc_base, eb))) return rc;
             sa.pull_bits = S->pull_bits.as<uint32_t>();
+            sa.esc_base = S->esc_base.as<int32_t>();
             S->n_xchunks = ((int64_t)xr.size() + kStructMmXRows - 1) / kStructMmXRows;
         } else {
             bounds = structured_bounds(A.model, &sa);

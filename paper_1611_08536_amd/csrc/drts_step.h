@@ -121,9 +121,11 @@ struct StructArgs {
     int64_t chunk_base;
     // entries of the row-sorted source and detector lists
     int64_t n_src_entries, n_det_entries;
-    // many right-hand sides: rows the push kernel leaves to the pull kernel
-    // (besides the escape rows), one bit per state
+    // many right-hand sides: rows the push kernel leaves to the pull kernel,
+    // one bit per row of [A; L]; and per voxel, the offset of its first
+    // escape row from n_states (its escape rows follow in ascending m)
     const uint32_t *pull_bits;
+    const int32_t *esc_base;
     // their grids: one set of partials per workgroup, push then pull
     int32_t mm_push_grid, mm_pull_grid;
     // detector entries grouped by detector, rows ascending within each:

@@ -1733,10 +1733,11 @@ __global__ void __launch_bounds__(256) step_struct_x(StructArgs sa, const StepIn
 // with the block coefficients read from LDS at uniform addresses, and writes
 // z[m] as the whole row (u + e_m, m) of Y: every regular row is written by
 // exactly one voxel, so X is read once per step instead of once per using
-// row.  Rows marked in sa.pull_bits (irregular, source and detector rows,
-// rows whose upstream voxel is outside or across an index change) and the
-// escape rows are left to the pull kernel.  Terms are added in column order
-// as the single-rhs kernels add them.
+// row; a target outside the grid is u's escape row for m.  Rows marked in
+// sa.pull_bits (irregular, source and detector rows, state rows whose
+// upstream voxel is outside or across an index change) are left to the pull
+// kernel.  Terms are added in column order as the single-rhs kernels add
+// them.
 // ---------------------------------------------------------------------------
 template <int MODE>
 __global__ void __launch_bounds__(256) step_struct_mm(StructArgs sa, const StepInst *__restrict__ insts,
@@ -1774,7 +1775,7 @@ __global__ void __launch_bounds__(256) step_struct_mm(StructArgs sa, const StepI
     const int64_t nc = I.n_chunks;
     // one set of partials per workgroup (chunk blockIdx.x): the walk over the
     // work items is fixed, so the sums are too
-    double sN = 0.0, sA = 0.0;
+    double sN = 0.0, sA = 0.0, sE = 0.0;
     float mx = 0.0f;
     for (int64_t wi = blockIdx.x; wi < n_work; wi += gridDim.x) {
         const int c = work[wi].chunk;
@@ -1785,24 +1786,37 @@ __global__ void __launch_bounds__(256) step_struct_mm(StructArgs sa, const StepI
             float xv[kDirs];
 #pragma unroll
             for (int n = 0; n < kDirs; ++n) xv[n] = X[(int64_t)(kDirs * u + n) * nrhs + xl];
-            // lane m < 26 looks up target row (u + e_m, m) once: inside the grid
-            // and not a pull row, and the material of its voxel
+            // lane m < 26 looks up target row (u + e_m, m) once: the state row of
+            // the neighbour inside the grid, or else u's escape row for m (escape
+            // rows of a voxel are consecutive, in ascending m); it is written here
+            // unless it is a pull row; and the target voxel's material
+            bool out = false;
             int lr = 0, lq = 0;
-            bool lok = false;
             if (lane < kDirs) {
                 const int wx = ux + dir_dx(lane), wy = uy + dir_dy(lane), wz = uz + dir_dz(lane);
-                if (wx >= 0 && wx < sa.nx && wy >= 0 && wy < sa.ny && wz >= 0 && wz < sa.nz) {
+                out = !(wx >= 0 && wx < sa.nx && wy >= 0 && wy < sa.ny && wz >= 0 && wz < sa.nz);
+                if (!out) {
                     const int w = wx + sa.nx * (wy + sa.ny * wz);
                     lr = kDirs * w + lane;
-                    lok = !((pull[lr >> 5] >> (lr & 31)) & 1u);
                     lq = mat[w];
                 }
+            }
+            const uint64_t outs = __ballot(out);
+            bool lok = false;
+            if (lane < kDirs) {
+                // with reflecting walls nothing leaves: no escape rows, and the
+                // reflected moves are irregular (pull) rows
+                const bool has_row = !out || sa.n_rows > sa.n_states;
+                if (out && has_row)
+                    lr = (int)sa.n_states + gp(sa.esc_base)[u] + __popcll(outs & ((1ull << lane) - 1ull));
+                lok = has_row && !((pull[lr >> 5] >> (lr & 31)) & 1u);
             }
             const uint64_t pushed = __ballot(lok);
             for (int m = 0; m < kDirs; ++m) {
                 if (!((pushed >> m) & 1ull)) continue;
                 const int r = __builtin_amdgcn_readlane(lr, m);
                 const int qw = __builtin_amdgcn_readlane(lq, m);
+                const bool esc = (outs >> m) & 1ull;
                 const int off = (q * kDirs + m) * kDirs;
                 float acc = 0.0f;
 #pragma unroll
@@ -1813,9 +1827,13 @@ __global__ void __launch_bounds__(256) step_struct_mm(StructArgs sa, const StepI
                 const float v = acc * scale;
                 if (active) {
                     Y[(int64_t)r * nrhs + lane] = v;
-                    sN += (double)v;
-                    sA += s_abs[qw] * (double)v;
-                    mx = fmaxf(mx, v);
+                    if (esc) {
+                        sE += (double)v;
+                    } else {
+                        sN += (double)v;
+                        sA += s_abs[qw] * (double)v;
+                        mx = fmaxf(mx, v);
+                    }
                 }
             }
         }
@@ -1823,15 +1841,17 @@ __global__ void __launch_bounds__(256) step_struct_mm(StructArgs sa, const StepI
     s_w[0][wave][lane] = sN;
     s_w[1][wave][lane] = sA;
     s_w[2][wave][lane] = (double)mx;
+    s_w[3][wave][lane] = sE;
     __syncthreads();
     const int64_t c = blockIdx.x;
     if (wave == 0 && active) {
         const double N = ((s_w[0][0][lane] + s_w[0][1][lane]) + s_w[0][2][lane]) + s_w[0][3][lane];
         const double A = ((s_w[1][0][lane] + s_w[1][1][lane]) + s_w[1][2][lane]) + s_w[1][3][lane];
         const double M = fmax(fmax(s_w[2][0][lane], s_w[2][1][lane]), fmax(s_w[2][2][lane], s_w[2][3][lane]));
+        const double E = ((s_w[3][0][lane] + s_w[3][1][lane]) + s_w[3][2][lane]) + s_w[3][3][lane];
         GLB double *part = gpw(I.partials);
         part[((int64_t)kSlotN * nrhs + lane) * nc + c] = N;
-        part[((int64_t)kSlotEsc * nrhs + lane) * nc + c] = 0.0;
+        part[((int64_t)kSlotEsc * nrhs + lane) * nc + c] = E;
         part[((int64_t)kSlotAbs * nrhs + lane) * nc + c] = A;
         part[((int64_t)kSlotMax * nrhs + lane) * nc + c] = M;
         for (int d = 0; d < I.n_det; ++d) part[((int64_t)(kSlotDet + d) * nrhs + lane) * nc + c] = 0.0;

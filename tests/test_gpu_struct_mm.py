@@ -60,8 +60,18 @@ def test_exact_mode_equals_csr_spmm():
     assert np.allclose(a["det"], b["det"], rtol=1e-13, atol=0)
 
 
-@pytest.mark.parametrize("make", [lambda: _layered_many(), lambda: W.c3(n=18, k=6, n_steps=40)],
-                         ids=["layered_4rhs", "slab_6rhs"])
+def _reflecting_many(n=10, k=3, n_steps=30):
+    """A closed box (reflecting walls: no escape rows) with k sources."""
+    wl = copy.copy(W.c3(n=n, k=k, n_steps=n_steps))
+    wl.medium = copy.copy(wl.medium)
+    wl.medium.bc = "reflect"
+    wl.detectors = []
+    return wl
+
+
+@pytest.mark.parametrize("make", [lambda: _layered_many(), lambda: W.c3(n=18, k=6, n_steps=40),
+                                  lambda: _reflecting_many()],
+                         ids=["layered_4rhs", "slab_6rhs", "reflecting_3rhs"])
 def test_split_columns_equal_single_rhs_runs(make):
     wl = make()
     A = drts.Matrix(wl.medium, wl.value_type, wl.rounding, wl.n_ref)
