@@ -266,6 +266,8 @@ def main():
                     help="skip the SpMM, batch, serving and matrix-free measurements")
     ap.add_argument("--struct-only", action="store_true",
                     help="of the extra measurements, run only the matrix-free step (for profiling)")
+    ap.add_argument("--spmm-only", action="store_true",
+                    help="of the extra measurements, run only the 64-rhs steps (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, launch an elementwise kernel that reads and writes 1 GiB (counter scale)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
@@ -342,7 +344,7 @@ def main():
                      "kernel": "step_spmv<float, int, 256, 256, 0, 0>", "kernel_ms": round(avg_kernel_ms, 4),
                      "algorithmic_bytes": nbytes, "traffic_unit": "GB per launch"},
     }
-    if not args.no_extras and args.n == 128:
+    if not args.no_extras and args.n == 128 and not args.spmm_only:
         _log("structured step")
         line["structured"] = structured_step(torch, A, wl, tab)
     S.close()
@@ -350,6 +352,7 @@ def main():
     if not args.no_extras and not args.struct_only:
         _log("C3 SpMM")
         line["spmm"] = spmm_vs_plain(torch)
+    if not args.no_extras and not args.struct_only and not args.spmm_only:
         _log("C4 batch")
         line["batch"] = batch_vs_sequential(torch)
         line["serving"] = serving_vs_fifo(torch)
