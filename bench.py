@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 STEP_SOURCES = ("paper_1611_08536_amd/csrc/drts_step.hip", "paper_1611_08536_amd/csrc/drts_step.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_spmv_c2_traffic.txt")
-SPMV_KERNEL = "step_spmv<float, int, 256, 256, 0, 0>"
+SPMV_KERNEL = "step_spmv<float, int, 256, 256, 0, 2>"
 CALIB_KERNEL = "vectorized_elementwise_kernel"
 CALIB_BYTES = 2 ** 30          # the calibration kernel reads and writes 1 GiB
 
@@ -140,9 +140,9 @@ def spmm_vs_plain(torch, steps=20):
     S.profile(True)
     t_mm = _timed(lambda: S.run(tab, steps), torch)
     n_l, k_ms = S.profile_stats()
-    # the matrix-free many-rhs step (hi + lo values) on the same solver
+    # the matrix-free many-rhs step (FP64 row sums) on the same solver
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    S.set_options(kernel=drts.KERNEL_STRUCTURED_SPLIT, grid=16 * cus)
+    S.set_options(kernel=drts.KERNEL_STRUCTURED_F64SUM, grid=16 * cus)
     S.run(tab, 2)
     S.profile(True)
     t_mf = _timed(lambda: S.run(tab, steps), torch)
@@ -170,7 +170,7 @@ def spmm_vs_plain(torch, steps=20):
            "achieved_GBs": round(nbytes / kern_s / 1e9, 1), "frac": round(nbytes / kern_s / 1e9 / PEAK_HBM_GBS, 4)}
     mf_s = f_ms / max(n_f, 1) * 1e-3
     mf_bytes = 4 * k * A.n_states + 4 * k * A.n_rows + A.n_states // 26
-    out["matrix_free"] = {"kernel": "step_struct_mm<2> + step_struct_mm_x<2> (hi+lo values)",
+    out["matrix_free"] = {"kernel": "step_struct_mm<2> + step_struct_mm_x<2> (FP64 row sums)",
                           "ms_per_step": round(t_mf / steps * 1e3, 3), "kernel_ms": round(mf_s * 1e3, 3),
                           "solve_steps_per_s": round(k * steps / t_mf, 1),
                           "speedup_vs_plain": round((k * steps / t_mf) / (steps / t_1), 2),
@@ -237,11 +237,11 @@ def serving_vs_fifo(torch, n_req=32, step_scale=0.1):
 
 
 def structured_step(torch, A, wl, tab, steps=50):
-    """The matrix-free step (hi + lo values) on the same 128^3 workload."""
+    """The matrix-free step (FP64 row sums) on the same 128^3 workload."""
     from paper_1611_08536_amd import drts
     S = drts.Solver(A, 1, wl.detectors, max_steps=steps + 4)
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    S.set_options(kernel=drts.KERNEL_STRUCTURED_SPLIT, tiles_per_chunk=16, grid=8 * cus)
+    S.set_options(kernel=drts.KERNEL_STRUCTURED_F64SUM, tiles_per_chunk=16, grid=8 * cus)
     S.run(tab, 2)
     S.profile(True)
     t = _timed(lambda: S.run(tab, steps), torch)
@@ -249,7 +249,7 @@ def structured_step(torch, A, wl, tab, steps=50):
     S.close()
     kern_s = k_ms / max(n_l, 1) * 1e-3
     nbytes = 4 * A.n_states + 4 * A.n_rows + A.n_states // 26
-    return {"kernel": "step_struct<float,2> + step_struct_x<float,2> (matrix-free, hi+lo values)",
+    return {"kernel": "step_struct<float,2> + step_struct_x<float,2> (matrix-free, FP64 row sums)",
             "ms_per_step": round(t / steps * 1e3, 4),
             "kernel_ms": round(kern_s * 1e3, 4), "GNNZ_equiv_per_s": round(A.nnz / kern_s / 1e9, 1),
             "algorithmic_bytes": nbytes, "achieved_GBs": round(nbytes / kern_s / 1e9, 1)}
@@ -341,7 +341,7 @@ def main():
                    "n_states": A.n_states, "n_rows": A.n_rows, "nnz": A.nnz, "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None if traffic is None else round(traffic / 1e9, 3),
-                     "kernel": "step_spmv<float, int, 256, 256, 0, 0>", "kernel_ms": round(avg_kernel_ms, 4),
+                     "kernel": SPMV_KERNEL, "kernel_ms": round(avg_kernel_ms, 4),
                      "algorithmic_bytes": nbytes, "traffic_unit": "GB per launch"},
     }
     if not args.no_extras and args.n == 128 and not args.spmm_only:

@@ -200,13 +200,14 @@ void drts_matrix_destroy(drts_matrix_t *A);
                                     stored, so the result equals the CSR step's
                                     bit for bit (one rhs: any rounding; several
                                     rhs: nearest-rounded FP32 values only) */
-#define DRTS_KERNEL_STRUCTURED_SPLIT 2 /* matrix-free with each FP32 value carried
-                                    as a hi + lo pair (about 48-bit values):
-                                    more accurate than either stored rounding,
-                                    equal to the CSR step within rounding (FP32;
-                                    several rhs: at most 8 materials).  With
-                                    several rhs each column equals the one-rhs
-                                    result of this kernel bit for bit */
+#define DRTS_KERNEL_STRUCTURED_F64SUM 2 /* matrix-free, FP32 state: each row is
+                                    the FP64 sum (in column order, one fma per
+                                    term) of the FP64 coefficients times the
+                                    FP32 x, rounded once to FP32; more accurate
+                                    than either stored rounding, equal to the
+                                    CSR step within rounding.  With several rhs
+                                    each column equals the one-rhs result of
+                                    this kernel bit for bit */
 
 typedef struct {
     int32_t kernel;       /* DRTS_KERNEL_* */
@@ -233,7 +234,9 @@ typedef struct {
                              no workgroup barrier per tile; rows_per_tile 64),
                              DRTS_SPMV_WAVE_PIPE (as DRTS_SPMV_WAVE, the next
                              tile's entries load before the current tile's
-                             gathers) */
+                             gathers), DRTS_SPMV_LDS (as DRTS_SPMV_ROW, the
+                             values loaded straight into LDS, not through
+                             registers; FP32 values only) */
     int32_t queue;        /* one rhs only: 1 = workgroups take chunks from a
                              device counter (dynamic balance), 0 = fixed walk */
 } drts_options_t;
@@ -245,6 +248,7 @@ typedef struct {
 #define DRTS_SPMV_STRIDED 4
 #define DRTS_SPMV_WAVE 5
 #define DRTS_SPMV_WAVE_PIPE 6
+#define DRTS_SPMV_LDS 7
 
 /* Creates the time-stepping state for n_rhs right-hand sides sharing A: the
  * state (zero), detectors, series buffers for max_steps steps.  n_rhs > 1

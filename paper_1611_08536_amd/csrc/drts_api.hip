@@ -393,7 +393,6 @@ int prepare(drts_solver *S)
         sa.mat = A.mat_of_voxel.as<uint8_t>();
         sa.index = A.index.as<double>();
         sa.blocks32 = A.blocks32.as<float>();
-        sa.blocks32lo = A.blocks32lo.as<float>();
         sa.blocks64 = A.blocks64.as<double>();
         sa.n_mat = (int32_t)A.model.mats.size();
         sa.irr_row = A.irr_row.as<int64_t>();
@@ -667,7 +666,7 @@ int launch_one(drts_solver *S, hipStream_t stream)
     hipError_t e;
     if (structured_of(S) && spmm) {
         e = launch_structured_mm(S->sa, S->inst_dev.as<StepInst>(), S->work_dev.as<WorkItem>(), S->n_chunks,
-                                 S->opt.kernel == DRTS_KERNEL_STRUCTURED_SPLIT ? 2 : 1, S->grid, S->n_det, stream);
+                                 S->opt.kernel == DRTS_KERNEL_STRUCTURED_F64SUM ? 2 : 1, S->grid, S->n_det, stream);
     } else if (structured_of(S)) {
         const bool f64 = A.model.value_type == DRTS_F64;
         int mode = 2;
@@ -729,35 +728,33 @@ int ensure_graph(drts_solver *S, int K)
 drts_options_t default_options(const drts_solver *S)
 {
     // defaults measured on MI355X: one rhs on the 128^3 three-layer workload
-    // (256-row tiles, 4 tiles per chunk, 32 workgroups per CU launched: the
-    // surplus waits and gives dynamic balance; fixed walk), 64 rhs on the 96^3
-    // slab (64-row tiles, 16 tiles per chunk, 16 workgroups per CU)
+    // (256-row tiles, 4 tiles per chunk, 64 workgroups per CU launched: the
+    // surplus waits and gives dynamic balance; fixed walk; FP32 values go
+    // straight to LDS), 64 rhs on the 96^3 slab (64-row tiles, 16 tiles per
+    // chunk, 16 workgroups per CU)
     drts_options_t o{};
     o.kernel = DRTS_KERNEL_CSR;
     o.rows_per_tile = spmm_of(S) ? 64 : 256;
     o.tiles_per_chunk = spmm_of(S) ? 16 : 4;
-    o.grid = device_cu_count() * (spmm_of(S) ? 16 : 32);
+    o.grid = device_cu_count() * (spmm_of(S) ? 16 : 64);
     o.xcd_remap = 0;
     o.graph_steps = 0;
     o.rescale = 1;
-    o.variant = DRTS_SPMV_ROW;
+    o.variant = S->A->m.model.value_type == DRTS_F64 ? DRTS_SPMV_ROW : DRTS_SPMV_LDS;
     o.queue = 0;
     return o;
 }
 
 int check_options(const drts_solver *S, const drts_options_t *o)
 {
-    if (o->kernel < DRTS_KERNEL_CSR || o->kernel > DRTS_KERNEL_STRUCTURED_SPLIT)
+    if (o->kernel < DRTS_KERNEL_CSR || o->kernel > DRTS_KERNEL_STRUCTURED_F64SUM)
         return set_error(DRTS_E_INVALID, "unknown kernel %d", o->kernel);
     if (o->kernel != DRTS_KERNEL_CSR && S->n_rhs != 1) {
         const Model &M = S->A->m.model;
-        if (M.mats.size() > (size_t)kStructMatLdsHost)
-            return set_error(DRTS_E_INVALID, "the many-rhs matrix-free step takes at most %d materials",
-                             kStructMatLdsHost);
         if (o->kernel == DRTS_KERNEL_STRUCTURED && M.rounding != DRTS_ROUND_NEAREST)
             return set_error(DRTS_E_INVALID,
                              "the exact many-rhs matrix-free step needs nearest-rounded values "
-                             "(use DRTS_KERNEL_STRUCTURED_SPLIT)");
+                             "(use DRTS_KERNEL_STRUCTURED_F64SUM)");
     }
     if (S->n_rhs == 1) {
         if (o->rows_per_tile != 64 && o->rows_per_tile != 128 && o->rows_per_tile != 256)
@@ -772,8 +769,10 @@ int check_options(const drts_solver *S, const drts_options_t *o)
     }
     if (o->queue != 0 && o->queue != 1) return set_error(DRTS_E_INVALID, "queue must be 0 or 1");
     if (o->xcd_remap < 0 || o->xcd_remap > 2) return set_error(DRTS_E_INVALID, "xcd_remap must be 0, 1 or 2");
-    if (o->variant < DRTS_SPMV_ROW || o->variant > DRTS_SPMV_WAVE_PIPE)
+    if (o->variant < DRTS_SPMV_ROW || o->variant > DRTS_SPMV_LDS)
         return set_error(DRTS_E_INVALID, "unknown variant %d", o->variant);
+    if (o->variant == DRTS_SPMV_LDS && S->A->m.model.value_type == DRTS_F64)
+        return set_error(DRTS_E_INVALID, "the LDS variant takes FP32 values");
     if ((o->variant == DRTS_SPMV_WAVE || o->variant == DRTS_SPMV_WAVE_PIPE) && S->n_rhs == 1 &&
         o->kernel == DRTS_KERNEL_CSR && o->rows_per_tile != 64)
         return set_error(DRTS_E_INVALID, "the wave variant takes rows_per_tile = 64");
@@ -1381,13 +1380,14 @@ int drts_autotune(drts_solver_t *S, const char *cache_path, drts_options_t *chos
     const bool spmm = spmm_of(S);
     const int rows_opts[] = {64, 128, 256};
     const int chunk_opts[] = {2, 4, 16};
-    const int grid_mult[] = {4, 8, 16};
+    const int grid_mult[] = {4, 8, 16, 32, 64};
     for (int r : rows_opts)
         for (int c : chunk_opts)
             for (int g : grid_mult)
                 for (int x = 0; x < 3; ++x)
-                    for (int pl = 0; pl < (spmm ? 1 : 7); ++pl) {
+                    for (int pl = 0; pl <= (spmm ? 0 : DRTS_SPMV_LDS); ++pl) {
                         if ((pl == DRTS_SPMV_WAVE || pl == DRTS_SPMV_WAVE_PIPE) && r != 64) continue;
+                        if (pl == DRTS_SPMV_LDS && A.model.value_type == DRTS_F64) continue;
                         drts_options_t o = S->opt;
                         o.rows_per_tile = r;
                         o.tiles_per_chunk = spmm ? c * 32 : c;

@@ -200,14 +200,10 @@ int assemble_on_device(Matrix *A)
     if ((rc = upload(dev, A->absorb, M.absorb))) return rc;
     if ((rc = upload(dev, A->blocks64, M.blocks))) return rc;
     {
-        // nearest FP32 value of every block entry and the FP32 remainder
-        std::vector<float> hi(M.blocks.size()), lo(M.blocks.size());
-        for (size_t i = 0; i < M.blocks.size(); ++i) {
-            hi[i] = (float)M.blocks[i];
-            lo[i] = (float)(M.blocks[i] - (double)hi[i]);
-        }
+        // nearest FP32 value of every block entry
+        std::vector<float> hi(M.blocks.size());
+        for (size_t i = 0; i < M.blocks.size(); ++i) hi[i] = (float)M.blocks[i];
         if ((rc = upload(dev, A->blocks32, hi))) return rc;
-        if ((rc = upload(dev, A->blocks32lo, lo))) return rc;
     }
     if ((rc = upload(dev, A->irr_row, M.irr_row))) return rc;
     if ((rc = upload(dev, A->irr_vox, M.irr_vox))) return rc;

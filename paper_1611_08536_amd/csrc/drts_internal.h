@@ -88,7 +88,7 @@ struct Matrix {
     int64_t nnz = 0;
     bool rp64 = false;       // int64 row pointers (nnz >= 2^31)
     Buffer row_ptr, col, val;
-    Buffer mat_of_voxel, absorb, index, blocks64, blocks32, blocks32lo;
+    Buffer mat_of_voxel, absorb, index, blocks64, blocks32;
     Buffer irr_row, irr_vox, irr_dir, irr_f, irr_bits, escape_state;
     int64_t bytes() const;
 };

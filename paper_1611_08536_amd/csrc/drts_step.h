@@ -99,7 +99,6 @@ struct StructArgs {
     const uint8_t *mat;
     const double *index;       // refractive index per material
     const float *blocks32;     // [q][m][n], nearest-rounded
-    const float *blocks32lo;   // [q][m][n], FP32 of (block - blocks32)
     const double *blocks64;    // [q][m][n]
     int32_t n_mat;
     const int64_t *irr_row, *irr_vox;
@@ -135,19 +134,20 @@ struct StructArgs {
 };
 constexpr int kStructSegLen = 16;
 constexpr int kStructXRows = 1024;
-constexpr int kStructMatLdsHost = 8;      // materials whose blocks the LDS holds
+constexpr int kStructMatLdsHost = 8;      // materials whose blocks the single-rhs LDS halo kernel holds
 constexpr int kStructVoxPerChunk = 64;   // voxels per work item of the push kernel
 constexpr int kStructMmXRows = 64;       // rows per work item of the many-rhs pull kernel
 // mode: 0 = exact values with global gathers, 1 = exact nearest values with
-// the LDS halo, 2 = hi + lo values with the LDS halo, 3 = hi + lo values with
-// global gathers (more materials than the LDS holds)
+// the LDS halo, 2 = FP64 coefficients and FP64 row sums with the LDS halo,
+// 3 = the same arithmetic with global gathers (more materials than the LDS
+// holds)
 hipError_t launch_structured(const StructArgs &sa, const StepInst *insts_dev, const WorkItem *work_dev,
                              int64_t n_work, int value_f64, int mode, int grid, int xcd_remap,
                              const int64_t *xcd_bounds, hipStream_t stream);
 
-// Matrix-free step for n_rhs > 1 (FP32; mode 1 = exact nearest values, 2 =
-// hi + lo): the push kernel over the voxel chunks of the work list, then the
-// pull kernel over sa.xrows.
+// Matrix-free step for n_rhs > 1 (FP32 state; mode 1 = exact nearest values,
+// 2 = FP64 coefficients and FP64 row sums): the push kernel over the voxel
+// chunks of the work list, then the pull kernel over sa.xrows.
 hipError_t launch_structured_mm(const StructArgs &sa, const StepInst *insts_dev, const WorkItem *work_dev,
                                 int64_t n_work, int mode, int grid, int n_det, hipStream_t stream);
 

@@ -41,6 +41,11 @@ typedef int i4 __attribute__((ext_vector_type(4)));
 #define GLB __attribute__((address_space(1)))
 template <typename T> __device__ __forceinline__ const GLB T *gp(const T *p) { return (const GLB T *)p; }
 template <typename T> __device__ __forceinline__ GLB T *gpw(T *p) { return (GLB T *)p; }
+// Data that no kernel of the step writes (coefficient tables): marked
+// constant, so loads at wave-uniform addresses go through the scalar cache
+// into SGPRs and feed vector instructions without a broadcast.
+#define CST __attribute__((address_space(4)))
+template <typename T> __device__ __forceinline__ const CST T *cst(const T *p) { return (const CST T *)p; }
 
 template <typename VT> struct Quad;
 template <> struct Quad<float> {
@@ -283,6 +288,94 @@ __device__ __forceinline__ VT finish_tile(const TileRegs<VT, IT, U> &T, __amdgpu
     return acc;
 }
 
+// Quad layout with the values loaded straight into LDS (gfx950 buffer loads
+// with the lds flag): the data of lane l of a wave instruction lands at
+// M0 + 16 l, so quad q = tid + k NT of the tile lands at entries 4q .. 4q+3 of
+// the stage, exactly where its products go.  Only the columns pass through
+// registers (28 fewer VGPRs than the quad layout: five resident workgroups
+// per CU instead of four).  Each lane later reads back only the quads it
+// loaded itself, so the product step needs no barrier.
+template <typename IT, int U> struct TileRegsL {
+    i4 qc[U];
+    IT b, e;
+    IT mylo, myhi, a0;
+    int q;
+};
+
+template <typename IT, int NT, int U, int R>
+__device__ __forceinline__ void issue_tile_l(TileRegsL<IT, U> &T, const GLB IT *rp, const GLB int32_t *col,
+                                             const GLB float *val, const GLB uint8_t *mat, IT b, IT e, int64_t r0,
+                                             int nr, int64_t n_states, int64_t nnz, float *s_prod)
+{
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t r = r0 + tid;
+    T.b = b;
+    T.e = e;
+    T.mylo = 0;
+    T.myhi = 0;
+    T.q = 0;
+    if (tid < nr && tid < R) {
+        T.mylo = rp[r];
+        T.myhi = rp[r + 1];
+        if (r < n_states) T.q = mat[r / kDirs];
+    }
+    // quads past the tile re-read its last quad (in bounds, as in the quad
+    // layout) into slots no row of the tile reads
+    T.a0 = b & ~(IT)3;
+    const uint32_t last = (uint32_t)(((e - 1 - T.a0) >> 2) << 2);
+    const uint32_t span = (uint32_t)(e - T.a0);
+    const int64_t base = (int64_t)T.a0;
+    const uint64_t left = (uint64_t)(nnz + 4 - base);
+    const __amdgpu_buffer_rsrc_t rc = make_rsrc((const void *)(col + base), left * 4);
+    const __amdgpu_buffer_rsrc_t rv = make_rsrc((const void *)(val + base), left * 4);
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        const uint32_t i = 4u * (uint32_t)(tid + k * NT);
+        const uint32_t o = i < span ? i : last;
+        T.qc[k] = __builtin_amdgcn_raw_buffer_load_b128(rc, (int)(o * 4), 0, kStream);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rv, (__attribute__((address_space(3))) void *)(s_prod + 4 * (64 * wave + k * NT)),
+                                                 16, (int)(o * 4), 0, 0, kStream);
+    }
+}
+
+template <typename IT, int NT, int U, int R>
+__device__ __forceinline__ float finish_tile_l(const TileRegsL<IT, U> &T, __amdgpu_buffer_rsrc_t rx, float *s_prod)
+{
+    const int tid = threadIdx.x;
+    float xv[U][4];
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) xv[k][jj] = BufQuad<float>::gather(rx, T.qc[k][jj]);
+    // the values of this lane's quads are in LDS once every load of the lane
+    // has completed
+    __builtin_amdgcn_s_waitcnt(0);
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        f4 *slot = (f4 *)(s_prod + 4 * (tid + k * NT));
+        f4 v = *slot;
+        v[0] = v[0] * xv[k][0];
+        v[1] = v[1] * xv[k][1];
+        v[2] = v[2] * xv[k][2];
+        v[3] = v[3] * xv[k][3];
+        *slot = v;
+    }
+    __syncthreads();
+    float acc = 0;
+    IT jj = T.mylo;
+    for (; jj + 4 <= T.myhi; jj += 4) {
+        const float p0 = s_prod[jj - T.a0], p1 = s_prod[jj - T.a0 + 1];
+        const float p2 = s_prod[jj - T.a0 + 2], p3 = s_prod[jj - T.a0 + 3];
+        acc += p0;
+        acc += p1;
+        acc += p2;
+        acc += p3;
+    }
+    for (; jj < T.myhi; ++jj) acc += s_prod[jj - T.a0];
+    return acc;
+}
+
 // Entries of one tile in strided order: thread t holds entries b + t + k NT,
 // so consecutive lanes hold consecutive entries.  Loads of columns and values
 // are then coalesced 4-byte loads, and so is most of the x gather: a row's
@@ -365,7 +458,8 @@ __device__ __forceinline__ VT finish_tile_s(const TileRegsS<VT, IT, S> &T, __amd
 // resident waves; the first R threads sum the rows).  PIPE = 1: the next
 // tile's entries are loaded before this tile's gathers, so the matrix stream
 // of a workgroup never stops (two register sets).  LAY = 1: the strided tile
-// layout (one row per thread, no pipelining); LAY = 0: quads.
+// layout (one row per thread, no pipelining); LAY = 2: quads with the values
+// loaded straight into LDS (FP32 values only, no pipelining); LAY = 0: quads.
 template <typename VT, typename IT, int NT, int R, int PIPE, int LAY>
 __global__ void __launch_bounds__(NT) step_spmv(const StepInst *__restrict__ insts,
                                                  const WorkItem *__restrict__ work, int64_t n_work,
@@ -378,7 +472,8 @@ __global__ void __launch_bounds__(NT) step_spmv(const StepInst *__restrict__ ins
     constexpr int U = (R == NT) ? 7 : (32 * R) / (4 * NT);   // quads of entries per thread
     constexpr int CAP = 4 * U * NT;      // entries staged per pass (>= 28 per row)
     static_assert(U >= 1 && CAP >= 28 * R, "tile shape");
-    __shared__ VT s_prod[CAP];
+    constexpr int LAYV = (LAY == 2 && sizeof(VT) != 4) ? 0 : LAY;   // FP64 values: quads
+    __shared__ __attribute__((aligned(16))) VT s_prod[CAP];
     __shared__ IT s_tb[kChunkMax + 1];
     __shared__ int32_t s_src[kChunkMax + 1];
     __shared__ int32_t s_det[kChunkMax + 1];
@@ -452,7 +547,15 @@ __global__ void __launch_bounds__(NT) step_spmv(const StepInst *__restrict__ ins
             const bool own = tid < nr && tid < R;
             VT acc = 0;
             int q = 0;
-            if (LAY == 1 && fits(j)) {
+            if (LAYV == 2 && fits(j)) {
+                if constexpr (sizeof(VT) == 4) {
+                    TileRegsL<IT, U> tl;
+                    issue_tile_l<IT, NT, U, R>(tl, rp, col, (const GLB float *)val, mat, s_tb[j], s_tb[j + 1], r0, nr,
+                                               n_states, I.nnz, (float *)s_prod);
+                    acc = finish_tile_l<IT, NT, U, R>(tl, rx, (float *)s_prod);
+                    q = tl.q;
+                }
+            } else if (LAYV == 1 && fits(j)) {
                 TileRegsS<VT, IT, CAP / NT> ts;
                 issue_tile_s<VT, IT, NT, CAP / NT, R>(ts, rp, col, val, mat, s_tb[j], s_tb[j + 1], r0, nr, n_states,
                                                       I.nnz);
@@ -1149,7 +1252,7 @@ __global__ void __launch_bounds__(kNT) finalize_step(const StepInst *__restrict_
 // for bit, while the matrix itself never leaves the chip (per row only the
 // upstream voxel's 26 states of x are read, from L2).
 // ---------------------------------------------------------------------------
-constexpr int kStructMatLds = kStructMatLdsHost;   // direction blocks (hi, lo) kept in LDS up to this many materials
+constexpr int kStructMatLds = kStructMatLdsHost;   // direction blocks kept in LDS up to this many materials
 
 __device__ __forceinline__ uint64_t mix64_dev(uint64_t x)
 {
@@ -1193,9 +1296,10 @@ template <> struct StructVals<double> {
 };
 
 // Row value from the blocks and move lists, x read from global memory.
-// MODE 2 carries every FP32 value as hi + lo and forms each term as
-// fma(hi, x, lo x): one rounding of the (almost exact) product, so the value
-// rounding error disappears.  Otherwise values are rounded as stored.
+// MODE 2 multiplies the FP64 coefficients with the FP32 x in FP64, adds the
+// terms of the row in FP64 in column order (one fma each) and rounds the row
+// once to FP32, so the value rounding error disappears.  Otherwise values are
+// rounded as stored.
 // x access of struct_row: x[c] of a single state, or X[c][lane] of a state
 // with n_rhs columns (lanes past n_rhs read a valid column and drop it)
 template <typename VT> struct XPlain {
@@ -1213,11 +1317,11 @@ __device__ __forceinline__ VT struct_row_a(const StructArgs &sa, int64_t r, cons
                                            int64_t k_end)
 {
     const GLB float *Chi = gp(sa.blocks32);
-    const GLB float *Clo = gp(sa.blocks32lo);
-    const GLB double *Cd = gp(sa.blocks64);
+    const CST double *Cd = cst(sa.blocks64);
     const GLB uint8_t *mat = gp(sa.mat);
     const GLB double *index = gp(sa.index);
     VT acc = 0;
+    double acc_d = 0.0;   // MODE 2
     auto plain_group = [&](int64_t u, int m) {
         const int q = mat[u];
         const int off = (q * kDirs + m) * kDirs;
@@ -1227,7 +1331,7 @@ __device__ __forceinline__ VT struct_row_a(const StructArgs &sa, int64_t r, cons
 #pragma unroll
         for (int n = 0; n < kDirs; ++n) {
             if (MODE == 2) {
-                acc += (VT)__builtin_fmaf(Chi[off + n], (float)xv[n], Clo[off + n] * (float)xv[n]);
+                acc_d = __builtin_fma(Cd[off + n], (double)xv[n], acc_d);
             } else {
                 const VT c = StructVals<VT>::plain(Chi[off + n], Cd[off + n], sa.rounding, r, kDirs * u + n);
                 acc += c * xv[n];
@@ -1237,7 +1341,7 @@ __device__ __forceinline__ VT struct_row_a(const StructArgs &sa, int64_t r, cons
     if (r >= sa.n_states) {
         const int64_t s = gp(sa.escape_state)[r - sa.n_states];
         plain_group(s / kDirs, (int)(s % kDirs));
-        return acc;
+        return MODE == 2 ? (VT)acc_d : acc;
     }
     const int64_t w = r / kDirs;
     const int mp = (int)(r % kDirs);
@@ -1285,17 +1389,13 @@ __device__ __forceinline__ VT struct_row_a(const StructArgs &sa, int64_t r, cons
             }
             if (a != 0.0) {
                 const VT xv = xa(kDirs * ug + n);
-                if (MODE == 2) {
-                    const float h = (float)a, l = (float)(a - (double)h);
-                    acc += (VT)__builtin_fmaf(h, (float)xv, l * (float)xv);
-                } else {
-                    acc += StructVals<VT>::merged(a, sa.rounding, r, kDirs * ug + n) * xv;
-                }
+                if (MODE == 2) acc_d = __builtin_fma(a, (double)xv, acc_d);
+                else acc += StructVals<VT>::merged(a, sa.rounding, r, kDirs * ug + n) * xv;
             }
         }
         k = k1;
     }
-    return acc;
+    return MODE == 2 ? (VT)acc_d : acc;
 }
 
 template <typename VT, int MODE>
@@ -1325,16 +1425,18 @@ __device__ __forceinline__ VT struct_plain_row(const StructArgs &sa, int64_t r, 
             const int off = (q * kDirs + mp) * kDirs;
             const GLB VT *xu = x + kDirs * u;
             const GLB float *Chi = gp(sa.blocks32);
-            const GLB float *Clo = gp(sa.blocks32lo);
-            const GLB double *Cd = gp(sa.blocks64);
+            const CST double *Cd = cst(sa.blocks64);
             VT xv[kDirs];
 #pragma unroll
             for (int n = 0; n < kDirs; ++n) xv[n] = xu[n];
+            if (MODE == 2 || MODE == 3) {
+                double a = 0.0;
 #pragma unroll
-            for (int n = 0; n < kDirs; ++n) {
-                if (MODE == 2 || MODE == 3) {
-                    acc += (VT)__builtin_fmaf(Chi[off + n], (float)xv[n], Clo[off + n] * (float)xv[n]);
-                } else {
+                for (int n = 0; n < kDirs; ++n) a = __builtin_fma(Cd[off + n], (double)xv[n], a);
+                acc = (VT)a;
+            } else {
+#pragma unroll
+                for (int n = 0; n < kDirs; ++n) {
                     const VT c = StructVals<VT>::plain(Chi[off + n], Cd[off + n], sa.rounding, r, kDirs * u + n);
                     acc += c * xv[n];
                 }
@@ -1401,14 +1503,15 @@ __global__ void __launch_bounds__(256) step_struct(StructArgs sa, const StepInst
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     constexpr bool HALO = MODE == 1 || MODE == 2;
     const int nblk = sa.n_mat * kDirs * kDirs;
-    // halo modes: the blocks (hi, lo) and the halo in dynamic LDS
+    // halo modes: the blocks (FP32 values for mode 1, FP64 for mode 2) and
+    // the halo in dynamic LDS
     float *s_Chi = (float *)s_dyn;
-    float *s_Clo = s_Chi + nblk;
-    float *s_x = s_Clo + nblk;
+    double *s_Cd = s_dyn;
+    float *s_x = (float *)(s_dyn + nblk);
     if (HALO) {
         for (int i = tid; i < nblk; i += NT) {
-            s_Chi[i] = gp(sa.blocks32)[i];
-            s_Clo[i] = gp(sa.blocks32lo)[i];
+            if (MODE == 2) s_Cd[i] = gp(sa.blocks64)[i];
+            else s_Chi[i] = gp(sa.blocks32)[i];
         }
     }
     for (int q = tid; q < sa.n_mat; q += NT) s_idx[q] = gp(sa.index)[q];
@@ -1541,10 +1644,14 @@ __global__ void __launch_bounds__(256) step_struct(StructArgs sa, const StepInst
                     if (qu != 255 && (qu == qw || (same_idx >> (qu * kStructMatLds + qw)) & 1ull)) {
                         const float *xs = s_x + RP[p].xo;
                         const int off = (qu * kDirs + RP[p].mp) * kDirs;
+                        if (MODE == 2) {
+                            double a = 0.0;
 #pragma unroll
-                        for (int n = 0; n < kDirs; ++n) {
-                            if (MODE == 2) acc += (VT)__builtin_fmaf(s_Chi[off + n], xs[n], s_Clo[off + n] * xs[n]);
-                            else acc += (VT)(s_Chi[off + n] * xs[n]);
+                            for (int n = 0; n < kDirs; ++n) a = __builtin_fma(s_Cd[off + n], (double)xs[n], a);
+                            acc = (VT)a;
+                        } else {
+#pragma unroll
+                            for (int n = 0; n < kDirs; ++n) acc += (VT)(s_Chi[off + n] * xs[n]);
                         }
                     }
                 } else {
@@ -1730,7 +1837,8 @@ __global__ void __launch_bounds__(256) step_struct_x(StructArgs sa, const StepIn
 //
 // Push form: one wave per source voxel u.  The wave reads u's 26 rows of X
 // once (a coalesced 4 n_rhs-byte load each), forms z[m] = sum_n C[m][n] X[n]
-// with the block coefficients read from LDS at uniform addresses, and writes
+// with the block coefficients read at wave-uniform addresses through the
+// scalar cache (FP64 coefficients and FP64 row sums in mode 2), and writes
 // z[m] as the whole row (u + e_m, m) of Y: every regular row is written by
 // exactly one voxel, so X is read once per step instead of once per using
 // row; a target outside the grid is u's escape row for m.  Rows marked in
@@ -1744,18 +1852,10 @@ __global__ void __launch_bounds__(256) step_struct_mm(StructArgs sa, const StepI
                                                        const WorkItem *__restrict__ work, int64_t n_work)
 {
     constexpr int NT = 256, NW = NT / 64;
-    extern __shared__ double s_dyn[];
     __shared__ double s_abs[kMatMax];
     __shared__ double s_w[4][NW][64];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int nblk = sa.n_mat * kDirs * kDirs;
-    float *s_Chi = (float *)s_dyn;
-    float *s_Clo = s_Chi + nblk;
-    for (int i = tid; i < nblk; i += NT) {
-        s_Chi[i] = gp(sa.blocks32)[i];
-        s_Clo[i] = gp(sa.blocks32lo)[i];
-    }
     const StepInst &I = insts[0];
     for (int q = tid; q < I.n_mat; q += NT) s_abs[q] = gp(I.absorb)[q];
     __syncthreads();
@@ -1786,6 +1886,11 @@ __global__ void __launch_bounds__(256) step_struct_mm(StructArgs sa, const StepI
             float xv[kDirs];
 #pragma unroll
             for (int n = 0; n < kDirs; ++n) xv[n] = X[(int64_t)(kDirs * u + n) * nrhs + xl];
+            double xd[kDirs];
+            if (MODE == 2) {
+#pragma unroll
+                for (int n = 0; n < kDirs; ++n) xd[n] = (double)xv[n];
+            }
             // lane m < 26 looks up target row (u + e_m, m) once: the state row of
             // the neighbour inside the grid, or else u's escape row for m (escape
             // rows of a voxel are consecutive, in ascending m); it is written here
@@ -1819,10 +1924,16 @@ __global__ void __launch_bounds__(256) step_struct_mm(StructArgs sa, const StepI
                 const bool esc = (outs >> m) & 1ull;
                 const int off = (q * kDirs + m) * kDirs;
                 float acc = 0.0f;
+                if (MODE == 2) {
+                    const CST double *Cm = cst(sa.blocks64) + off;
+                    double a = 0.0;
 #pragma unroll
-                for (int n = 0; n < kDirs; ++n) {
-                    if (MODE == 2) acc += __builtin_fmaf(s_Chi[off + n], xv[n], s_Clo[off + n] * xv[n]);
-                    else acc += s_Chi[off + n] * xv[n];
+                    for (int n = 0; n < kDirs; ++n) a = __builtin_fma(Cm[n], xd[n], a);
+                    acc = (float)a;
+                } else {
+                    const CST float *Cm = cst(sa.blocks32) + off;
+#pragma unroll
+                    for (int n = 0; n < kDirs; ++n) acc += Cm[n] * xv[n];
                 }
                 const float v = acc * scale;
                 if (active) {
@@ -1966,6 +2077,9 @@ hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int6
     (void)n_rhs_max;
     (void)rows_per_tile;
     if (n_work <= 0) return hipSuccess;
+    // workgroups past the work list would only start and exit; a multiple of
+    // the XCD count keeps the per-XCD walk available
+    grid = (int)std::min<int64_t>(grid, (n_work + kXcds - 1) / kXcds * kXcds);
     const dim3 g((unsigned)grid), b(kNT);
     if (spmm) {
         const size_t lds = (size_t)4 * n_det_max * 64 * sizeof(double);
@@ -1988,6 +2102,7 @@ hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int6
         else if (variant == 2) DRTS_SPMV1(VT, IT, 2 * RV, RV, 0, 0); \
         else if (variant == 3) DRTS_SPMV1(VT, IT, 2 * RV, RV, 1, 0); \
         else if (variant == 4) DRTS_SPMV1(VT, IT, RV, RV, 0, 1);     \
+        else if (variant == 7) DRTS_SPMV1(VT, IT, RV, RV, 0, 2);     \
         else DRTS_SPMV1(VT, IT, RV, RV, 0, 0);                       \
     } while (0)
         const int nt = rows_per_tile <= 64 ? 64 : (rows_per_tile <= 128 ? 128 : 256);
@@ -2046,7 +2161,7 @@ hipError_t launch_structured(const StructArgs &sa, const StepInst *insts_dev, co
     if (n_work <= 0 && sa.n_xrows <= 0) return hipSuccess;
     // the halo modes keep every direction block in LDS
     if (sa.n_mat > kStructMatLds) mode = (mode == 2) ? 3 : 0;
-    const size_t blk = (size_t)sa.n_mat * kDirs * kDirs * 2 * sizeof(float);
+    const size_t blk = (size_t)sa.n_mat * kDirs * kDirs * sizeof(double);
     const size_t halo = (size_t)9 * (kStructSegLen + 2) * kDirs * sizeof(float);
     const dim3 g((unsigned)grid), b(256);
     if (n_work > 0) {
@@ -2085,15 +2200,14 @@ hipError_t launch_structured(const StructArgs &sa, const StepInst *insts_dev, co
 hipError_t launch_structured_mm(const StructArgs &sa, const StepInst *insts_dev, const WorkItem *work_dev,
                                 int64_t n_work, int mode, int grid, int n_det, hipStream_t stream)
 {
-    const size_t blk = (size_t)sa.n_mat * kDirs * kDirs * 2 * sizeof(float);
     const dim3 b(256);
     (void)grid;
     if (n_work > 0) {
         const dim3 g((unsigned)sa.mm_push_grid);
         if (mode == 2)
-            hipLaunchKernelGGL((step_struct_mm<2>), g, b, blk, stream, sa, insts_dev, work_dev, n_work);
+            hipLaunchKernelGGL((step_struct_mm<2>), g, b, 0, stream, sa, insts_dev, work_dev, n_work);
         else
-            hipLaunchKernelGGL((step_struct_mm<1>), g, b, blk, stream, sa, insts_dev, work_dev, n_work);
+            hipLaunchKernelGGL((step_struct_mm<1>), g, b, 0, stream, sa, insts_dev, work_dev, n_work);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

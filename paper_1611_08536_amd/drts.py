@@ -20,7 +20,7 @@ F64, F32 = 0, 1
 ROUND_NEAREST, ROUND_DITHER = 0, 1
 GEOM = {"voxels": 0, "homog": 0, "layers_z": 1, "sphere": 2}
 BC = {"vacuum": 0, "reflect": 1}
-KERNEL_CSR, KERNEL_STRUCTURED, KERNEL_STRUCTURED_SPLIT = 0, 1, 2
+KERNEL_CSR, KERNEL_STRUCTURED, KERNEL_STRUCTURED_F64SUM = 0, 1, 2
 SERVE_ARRIVAL, SERVE_SHORTEST = 0, 1
 
 if not os.path.exists(LIB_PATH):

@@ -11,7 +11,7 @@ benchmark times (default options).  Bars:
     |y - y_ref| <= 64 u sum |a x| with u = 2^-24 (all terms are nonnegative);
   - the 2000-step series (photon count, escaped, absorbed, two detectors):
     relative error <= 1e-5 against the FP64 oracle, for the CSR step and for
-    the matrix-free step with hi + lo values;
+    the matrix-free step with FP64 row sums;
   - the final state: relative L1 error <= 1e-5 over sampled entries and of
     the whole state's L1 norm.
 """
@@ -87,7 +87,7 @@ def test_c2_one_product_sampled_rows(c2):
     S.close()
 
 
-@pytest.mark.parametrize("kernel", [drts.KERNEL_CSR, drts.KERNEL_STRUCTURED_SPLIT], ids=["csr", "struct_split"])
+@pytest.mark.parametrize("kernel", [drts.KERNEL_CSR, drts.KERNEL_STRUCTURED_F64SUM], ids=["csr", "struct_f64sum"])
 def test_c2_2000_steps_against_oracle(c2, kernel):
     wl, M = c2
     g = np.load(os.path.join(GOLDEN, "c2_run.npz"))

@@ -133,7 +133,7 @@ def _state_and_series(wl, n, **kw):
     return out["x"], out["x_exp"], out["tot"], out["exp2"], out["det"]
 
 
-@pytest.mark.parametrize("kernel", [0, 2], ids=["csr", "struct_split"])
+@pytest.mark.parametrize("kernel", [0, 2], ids=["csr", "struct_f64sum"])
 def test_step_run_and_graph_replay_identical(kernel):
     """Eager steps, drts_run and replays of a captured 8-step graph (the
     matrix-free step forks its second kernel onto another stream inside the
@@ -165,14 +165,14 @@ def test_launch_shapes_give_identical_states(opts):
     assert np.allclose(ref[4], got[4], rtol=1e-13, atol=0)
 
 
-@pytest.mark.parametrize("rpt", [64, 256])
+@pytest.mark.parametrize("rpt", [64, 128, 256])
 def test_spmv_variants_give_identical_states(rpt):
     """Every SpMV variant forms the same products and adds them per row in
     column order: states bit for bit; FP64 totals differ at most in the order
     of the per-wave partial sums."""
     wl = W.c2(n=18)
     ref = _state_and_series(wl, 30, options={"rows_per_tile": rpt, "variant": 0})
-    for v in (1, 2, 3, 4, 5, 6):
+    for v in (1, 2, 3, 4, 5, 6, 7):
         if v in (5, 6) and rpt != 64:
             continue
         got = _state_and_series(wl, 30, options={"rows_per_tile": rpt, "variant": v})
@@ -182,7 +182,7 @@ def test_spmv_variants_give_identical_states(rpt):
         assert np.allclose(ref[4], got[4], rtol=1e-13, atol=0), v
 
 
-@pytest.mark.parametrize("kernel", [0, 1, 2], ids=["csr", "struct", "struct_split"])
+@pytest.mark.parametrize("kernel", [0, 1, 2], ids=["csr", "struct", "struct_f64sum"])
 def test_work_order_changes_nothing(kernel):
     """The XCD walk and the slab order of the chunks only move work between
     workgroups: state and FP64 series are identical bit for bit."""
@@ -267,7 +267,8 @@ def test_reflecting_walls_conserve_in_fp64():
     assert np.all(out["tot"][:, 1, 0] == 0.0)
 
 
-def test_ragged_tail_and_tiny_tiles():
+@pytest.mark.parametrize("variant", [0, 7])
+def test_ragged_tail_and_tiny_tiles(variant):
     """Row counts that are not a multiple of the tile, the smallest tile."""
     med = W.homogeneous(5, W.Material(3.0, 0.05, 0.6, 1.4), ny=3, nz=7)
     wl = W.Workload("ragged", med, [W.point_source(2, 1, 3)], [W.face_escape_detector(med, "top")], 40, 1,
@@ -275,7 +276,7 @@ def test_ragged_tail_and_tiny_tiles():
     A = oracle.Matrix(med)
     assert A.n_rows % 64 != 0
     ref = oracle.run_workload(A, wl)
-    out = solve.run(wl, options={"rows_per_tile": 64, "tiles_per_chunk": 1, "grid": 8})
+    out = solve.run(wl, options={"rows_per_tile": 64, "tiles_per_chunk": 1, "grid": 8, "variant": variant})
     assert parity.rel_err_series(out["det"][:, 0, 0], out["exp2"][:, 0], ref["det"][:, 0],
                                  ref["det_exp"][:, 0]) <= 1e-5
     assert parity.rel_l1(out["x"][:A.n_states, 0], out["x_exp"][0], ref["x"], ref["x_exp"]) <= 1e-5
@@ -290,6 +291,10 @@ def test_errors_are_reported():
     assert ei.value.rc == -4
     with pytest.raises(drts.DrtsError):
         S.set_options(rows_per_tile=1000)
+    M64 = drts.Matrix(wl.medium, "f64")
+    S64 = drts.Solver(M64, 1, wl.detectors, max_steps=5)
+    with pytest.raises(drts.DrtsError):
+        S64.set_options(variant=7)          # the LDS layout takes FP32 values
     bad = W.homogeneous(4, W.Material(1.0, 0.1, 1.5, 1.4))
     with pytest.raises(drts.DrtsError) as ei:
         drts.Matrix(bad)
@@ -334,8 +339,8 @@ def test_structured_equals_csr(wl_name):
 
 
 @pytest.mark.parametrize("wl_name", ["c2_dither", "c5_sphere", "reflect"])
-def test_structured_split_against_oracle(wl_name):
-    """hi + lo values: against the FP64 oracle at the FP32 tolerance, and closer
+def test_structured_f64sum_against_oracle(wl_name):
+    """FP64 row sums: against the FP64 oracle at the FP32 tolerance, and closer
     to it than the stored-value (dithered) CSR run."""
     wl = _struct_workload(wl_name)
     n = 150
@@ -346,7 +351,7 @@ def test_structured_split_against_oracle(wl_name):
     D = A.n_states
     e_csr = parity.rel_l1(csr["x"][:D, 0], csr["x_exp"][0], ref["x"], ref["x_exp"])
     e_spl = parity.rel_l1(spl["x"][:D, 0], spl["x_exp"][0], ref["x"], ref["x_exp"])
-    print(wl_name, "state rel L1: csr", e_csr, "split", e_spl)
+    print(wl_name, "state rel L1: csr", e_csr, "f64sum", e_spl)
     assert e_spl <= 1e-5 and e_spl <= e_csr * 1.5
     for j in range(3):
         err = parity.rel_err_series(spl["tot"][:, j, 0], spl["exp2"][:, 0], ref["tot"][:, j], ref["tot_exp"][:, j])

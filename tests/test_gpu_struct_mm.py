@@ -5,7 +5,7 @@ Bars:
   - exact mode (nearest-rounded values) against the CSR SpMM: states bit for
     bit (both add the same FP32 products per row in column order), FP64
     series to 1e-13 (their chunk partials differ);
-  - hi + lo mode: every column equals the single-rhs hi + lo run of its own
+  - FP64-sum mode: every column equals the single-rhs FP64-sum run of its own
     sources, state bit for bit, on a layered medium with Fresnel interfaces,
     face detectors and sources in several columns; and against the FP64
     oracle within 1e-5 on the many-source slab.
@@ -69,15 +69,26 @@ def _reflecting_many(n=10, k=3, n_steps=30):
     return wl
 
 
+def _ten_layers_many(n=20, k=3, n_steps=30):
+    """Ten layers, ten materials (more than the single-rhs LDS halo holds, so
+    the single-rhs runs take the global-gather kernel) and k top-face sources."""
+    mats = [W.Material(4.0 + j, 0.01 * (j + 1), 0.7 + 0.02 * j, 1.33 + 0.01 * (j % 3)) for j in range(10)]
+    med = W.layered(n, mats)
+    srcs = [W.point_source(3 + 5 * j, 4 + 3 * j, 0, kind="gaussian", fwhm_fs=100.0 + 50.0 * j, rhs=j)
+            for j in range(k)]
+    return W.Workload("ten_layers", med, srcs, [W.face_escape_detector(med, "top")], n_steps, k, "f32",
+                      "dither", 1.33)
+
+
 @pytest.mark.parametrize("make", [lambda: _layered_many(), lambda: W.c3(n=18, k=6, n_steps=40),
-                                  lambda: _reflecting_many()],
-                         ids=["layered_4rhs", "slab_6rhs", "reflecting_3rhs"])
-def test_split_columns_equal_single_rhs_runs(make):
+                                  lambda: _reflecting_many(), lambda: _ten_layers_many()],
+                         ids=["layered_4rhs", "slab_6rhs", "reflecting_3rhs", "ten_materials_3rhs"])
+def test_f64sum_columns_equal_single_rhs_runs(make):
     wl = make()
     A = drts.Matrix(wl.medium, wl.value_type, wl.rounding, wl.n_ref)
-    out = solve.run(wl, matrix=A, options={"kernel": drts.KERNEL_STRUCTURED_SPLIT})
+    out = solve.run(wl, matrix=A, options={"kernel": drts.KERNEL_STRUCTURED_F64SUM})
     for j in range(wl.n_rhs):
-        one = solve.run(_single(wl, j), matrix=A, options={"kernel": drts.KERNEL_STRUCTURED_SPLIT})
+        one = solve.run(_single(wl, j), matrix=A, options={"kernel": drts.KERNEL_STRUCTURED_F64SUM})
         assert np.array_equal(out["x"][:, j], one["x"][:, 0]), j
         assert out["x_exp"][j] == one["x_exp"][0]
         assert np.array_equal(out["exp2"][:, j], one["exp2"][:, 0])
@@ -85,9 +96,9 @@ def test_split_columns_equal_single_rhs_runs(make):
         assert np.allclose(out["det"][:, :, j], one["det"][:, :, 0], rtol=1e-13, atol=0)
 
 
-def test_split_against_oracle():
+def test_f64sum_against_oracle():
     wl = W.c3(n=22, k=64, n_steps=50)
-    out = solve.run(wl, options={"kernel": drts.KERNEL_STRUCTURED_SPLIT})
+    out = solve.run(wl, options={"kernel": drts.KERNEL_STRUCTURED_F64SUM})
     A = oracle.Matrix(wl.medium)
     for j in (0, 21, 63):
         ref = oracle.run_workload(A, wl, rhs=j)
