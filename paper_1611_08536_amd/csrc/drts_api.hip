@@ -125,7 +125,7 @@ struct drts_solver {
     int64_t n_tiles = 0, n_chunks = 0, n_xchunks = 0;
     int64_t t_host = 0;
 
-    Buffer buf0, buf1, ctl_t, ctl_E, ctl_M, ctl_abs, t_end, partials, xcd_bounds, xrows, xirr, ddet_ptr, ddet_row,
+    Buffer buf0, buf1, ctl_t, ctl_E, ctl_M, ctl_abs, t_end, partials, xcd_bounds, xrows, xirr, xsrc, xdet, ddet_ptr, ddet_row,
         ddet_F, pull_bits, esc_base;
     Buffer ser_tot, ser_det, ser_exp, ser_abs_exp, amp, smax;
     Buffer src_tile, src_row, src_id, src_rhs, src_w;
@@ -304,6 +304,21 @@ void structured_mm_pull(const Model &M, const std::vector<SourceEntry> &srcs, co
         (*esc_base)[(size_t)(M.escape_state[(size_t)i] / kDirs)] = (int32_t)i;
 }
 
+// For each listed row (ascending), the index of the first entry of a
+// row-sorted entry list at or after that row: the kernels walk a row's
+// entries from there without a search.
+template <typename E>
+std::vector<int32_t> first_entries(const std::vector<int64_t> &rows, const std::vector<E> &entries)
+{
+    std::vector<int32_t> f(rows.size());
+    size_t k = 0;
+    for (size_t i = 0; i < rows.size(); ++i) {
+        while (k < entries.size() && entries[k].row < rows[i]) ++k;
+        f[i] = (int32_t)k;
+    }
+    return f;
+}
+
 // XCD-aware order of a solver's chunks.  With the remapped walk, XCD i takes
 // the i-th eighth of the work list; this order makes that eighth one slab of
 // y lines (ny / 8 of them) swept in z, so the x values a chunk gathers (the
@@ -423,8 +438,12 @@ int prepare(drts_solver *S)
         }
         if ((rc = upload_vec(dev, S->xrows, xr))) return rc;
         if ((rc = upload_vec(dev, S->xirr, xk))) return rc;
+        if ((rc = upload_vec(dev, S->xsrc, first_entries(xr, S->srcs)))) return rc;
+        if ((rc = upload_vec(dev, S->xdet, first_entries(xr, S->dets)))) return rc;
         sa.xrows = S->xrows.as<int64_t>();
         sa.xirr = S->xirr.as<int64_t>();
+        sa.xsrc = S->xsrc.as<int32_t>();
+        sa.xdet = S->xdet.as<int32_t>();
         sa.n_xrows = (int64_t)xr.size();
         sa.n_src_entries = (int64_t)S->srcs.size();
         sa.n_det_entries = (int64_t)S->dets.size();

@@ -1751,7 +1751,7 @@ __global__ void __launch_bounds__(256) step_struct_x(StructArgs sa, const StepIn
             const int64_t kf = gp(sa.xirr)[k0 + i], ke = gp(sa.xirr)[k0 + i + 1];
             VT v = struct_row<VT, (MODE == 2 || MODE == 3) ? 2 : 0>(sa, r, x, kf, ke) * scale;
             if (sa.n_src_entries > 0 && r < sa.n_states) {
-                int e2 = lower_bound_rows<int32_t>(I.src_row, 0, (int)sa.n_src_entries, r);
+                int e2 = gp(sa.xsrc)[k0 + i];
                 double s = 0.0;
                 bool any = false;
                 for (; e2 < sa.n_src_entries && gp(I.src_row)[e2] == r; ++e2) {
@@ -2013,7 +2013,7 @@ __global__ void __launch_bounds__(256) step_struct_mm_x(StructArgs sa, const Ste
             const int64_t r = xrows[k];
             float v = struct_row_a<float, (MODE == 2) ? 2 : 0>(sa, r, xa, xirr[k], xirr[k + 1]) * scale;
             if (sa.n_src_entries > 0 && r < sa.n_states) {
-                int e2 = lower_bound_rows<int32_t>(I.src_row, 0, (int)sa.n_src_entries, r);
+                int e2 = gp(sa.xsrc)[k];
                 double s = 0.0;
                 bool any = false;
                 for (; e2 < sa.n_src_entries && gp(I.src_row)[e2] == r; ++e2) {
@@ -2034,7 +2034,7 @@ __global__ void __launch_bounds__(256) step_struct_mm_x(StructArgs sa, const Ste
                     sE += (double)v;
                 }
                 if (sa.n_det_entries > 0) {
-                    int e2 = lower_bound_rows<int32_t>(I.det_row, 0, (int)sa.n_det_entries, r);
+                    int e2 = gp(sa.xdet)[k];
                     for (; e2 < sa.n_det_entries && gp(I.det_row)[e2] == r; ++e2)
                         my_det[gp(I.det_id)[e2] * 64 + lane] += gp(I.det_F)[e2] * (double)v;
                 }
