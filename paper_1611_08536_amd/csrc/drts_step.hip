@@ -1253,6 +1253,7 @@ __global__ void __launch_bounds__(kNT) finalize_step(const StepInst *__restrict_
 // upstream voxel's 26 states of x are read, from L2).
 // ---------------------------------------------------------------------------
 constexpr int kStructMatLds = kStructMatLdsHost;   // direction blocks kept in LDS up to this many materials
+constexpr int kStructLdsStride = 27;               // LDS elements per block row and per halo voxel
 
 __device__ __forceinline__ uint64_t mix64_dev(uint64_t x)
 {
@@ -1495,23 +1496,29 @@ __global__ void __launch_bounds__(256) step_struct(StructArgs sa, const StepInst
     __shared__ uint8_t s_q[9 * HV];
     __shared__ uint32_t s_bits[(ROWS + 31) / 32 + 1];
     __shared__ int32_t s_src[kChunkMax + 1];
+    constexpr bool HALO = MODE == 1 || MODE == 2;
+    constexpr int MATS = HALO ? kStructMatLds : kMatMax;   // the halo modes take at most kStructMatLds materials
     __shared__ int32_t s_det[kChunkMax + 1];
-    __shared__ double s_abs[kMatMax];
-    __shared__ double s_idx[kMatMax];
+    __shared__ double s_abs[MATS];
+    __shared__ double s_idx[MATS];
     __shared__ VT s_y[ROWS];
     __shared__ double s_wred[4][NW];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    constexpr bool HALO = MODE == 1 || MODE == 2;
     const int nblk = sa.n_mat * kDirs * kDirs;
     // halo modes: the blocks (FP32 values for mode 1, FP64 for mode 2) and
-    // the halo in dynamic LDS
+    // the halo in dynamic LDS.  Block rows and halo voxel blocks sit
+    // kStructLdsStride elements apart (odd): the lanes of a wave read rows of
+    // different directions and blocks of different voxels, and an odd stride
+    // spreads them over all LDS banks
+    constexpr int KS = kStructLdsStride;
     float *s_Chi = (float *)s_dyn;
     double *s_Cd = s_dyn;
-    float *s_x = (float *)(s_dyn + nblk);
+    float *s_x = (float *)(s_dyn + sa.n_mat * kDirs * KS);
     if (HALO) {
         for (int i = tid; i < nblk; i += NT) {
-            if (MODE == 2) s_Cd[i] = gp(sa.blocks64)[i];
-            else s_Chi[i] = gp(sa.blocks32)[i];
+            const int at = (i / kDirs) * KS + i % kDirs;
+            if (MODE == 2) s_Cd[at] = gp(sa.blocks64)[i];
+            else s_Chi[at] = gp(sa.blocks32)[i];
         }
     }
     for (int q = tid; q < sa.n_mat; q += NT) s_idx[q] = gp(sa.index)[q];
@@ -1573,7 +1580,7 @@ __global__ void __launch_bounds__(256) step_struct(StructArgs sa, const StepInst
             const int sg = (1 - dir_dz(mp)) * 3 + (1 - dir_dy(mp));
             const int ix = i - dir_dx(mp) + 1;
             RP[p].mp = mp;
-            RP[p].xo = (sg * HV + ix) * kDirs;
+            RP[p].xo = (sg * HV + ix) * KS;
             RP[p].qu = sg * HV + ix;
             RP[p].qw = 4 * HV + i + 1;
         }
@@ -1620,7 +1627,7 @@ __global__ void __launch_bounds__(256) step_struct(StructArgs sa, const StepInst
 #pragma unroll
                     for (int k = 0; k < PER; ++k) {
                         const int e = tid + k * NT;
-                        if (e < SEGW) s_x[sg * SEGW + e] = P.hv[sg][k];
+                        if (e < SEGW) s_x[sg * HV * KS + (e / kDirs) * KS + e % kDirs] = P.hv[sg][k];
                     }
                 if (tid < 9 * HV) s_q[tid] = P.q;
                 if (tid < BITW) s_bits[tid] = P.b;
@@ -1643,7 +1650,7 @@ __global__ void __launch_bounds__(256) step_struct(StructArgs sa, const StepInst
                     qw = s_q[RP[p].qw];
                     if (qu != 255 && (qu == qw || (same_idx >> (qu * kStructMatLds + qw)) & 1ull)) {
                         const float *xs = s_x + RP[p].xo;
-                        const int off = (qu * kDirs + RP[p].mp) * kDirs;
+                        const int off = (qu * kDirs + RP[p].mp) * KS;
                         if (MODE == 2) {
                             double a = 0.0;
 #pragma unroll
@@ -2161,8 +2168,8 @@ hipError_t launch_structured(const StructArgs &sa, const StepInst *insts_dev, co
     if (n_work <= 0 && sa.n_xrows <= 0) return hipSuccess;
     // the halo modes keep every direction block in LDS
     if (sa.n_mat > kStructMatLds) mode = (mode == 2) ? 3 : 0;
-    const size_t blk = (size_t)sa.n_mat * kDirs * kDirs * sizeof(double);
-    const size_t halo = (size_t)9 * (kStructSegLen + 2) * kDirs * sizeof(float);
+    const size_t blk = (size_t)sa.n_mat * kDirs * kStructLdsStride * sizeof(double);
+    const size_t halo = (size_t)9 * (kStructSegLen + 2) * kStructLdsStride * sizeof(float);
     const dim3 g((unsigned)grid), b(256);
     if (n_work > 0) {
         if (value_f64) {
