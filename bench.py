@@ -249,7 +249,7 @@ def structured_step(torch, A, wl, tab, steps=50):
     S.close()
     kern_s = k_ms / max(n_l, 1) * 1e-3
     nbytes = 4 * A.n_states + 4 * A.n_rows + A.n_states // 26
-    return {"kernel": "step_struct<float,2> + step_struct_x<float,2> (matrix-free, FP64 row sums)",
+    return {"kernel": "step_struct_dm<2> + step_struct_x<float,2> (matrix-free, FP64 row sums)",
             "ms_per_step": round(t / steps * 1e3, 4),
             "kernel_ms": round(kern_s * 1e3, 4), "GNNZ_equiv_per_s": round(A.nnz / kern_s / 1e9, 1),
             "algorithmic_bytes": nbytes, "achieved_GBs": round(nbytes / kern_s / 1e9, 1)}

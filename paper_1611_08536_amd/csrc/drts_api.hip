@@ -216,9 +216,22 @@ bool structured_of(const drts_solver *S) { return S->opt.kernel != DRTS_KERNEL_C
 
 // Tile row boundaries of the structured kernel: segments of kStructSegLen
 // voxels of every x-line (the last boundary is n_states).
-std::vector<int64_t> structured_bounds(const Model &M, StructArgs *sa)
+// Kernel mode of a single-rhs matrix-free step: 0 exact values with global
+// gathers (FP64, dithered FP32), 1 exact nearest FP32 values, 2 FP64 row sums,
+// 3 FP64 row sums with global gathers (more materials than the
+// direction-major kernel takes).
+int structured_mode(const drts_solver *S)
 {
-    const int L = kStructSegLen;
+    const Model &M = S->A->m.model;
+    const bool f64 = M.value_type == DRTS_F64;
+    const bool many = M.mats.size() > (size_t)kStructMatLdsHost;
+    if (S->opt.kernel == DRTS_KERNEL_STRUCTURED)
+        return (f64 || M.rounding == DRTS_ROUND_DITHER || many) ? 0 : 1;
+    return f64 ? 0 : (many ? 3 : 2);
+}
+
+std::vector<int64_t> structured_bounds(const Model &M, StructArgs *sa, int L)
+{
     const int segs = (M.nx + L - 1) / L;
     const int64_t lines = (int64_t)M.ny * M.nz;
     std::vector<int64_t> b;
@@ -431,7 +444,8 @@ int prepare(drts_solver *S)
             sa.esc_base = S->esc_base.as<int32_t>();
             S->n_xchunks = ((int64_t)xr.size() + kStructMmXRows - 1) / kStructMmXRows;
         } else {
-            bounds = structured_bounds(A.model, &sa);
+            const int mode = structured_mode(S);
+            bounds = structured_bounds(A.model, &sa, (mode == 1 || mode == 2) ? kStructDmSeg : kStructSegLen);
             S->n_tiles = (int64_t)bounds.size() - 1;
             structured_xrows(A.model, &xr, &xk);
             S->n_xchunks = ((int64_t)xr.size() + kStructXRows - 1) / kStructXRows;
@@ -687,11 +701,9 @@ int launch_one(drts_solver *S, hipStream_t stream)
         e = launch_structured_mm(S->sa, S->inst_dev.as<StepInst>(), S->work_dev.as<WorkItem>(), S->n_chunks,
                                  S->opt.kernel == DRTS_KERNEL_STRUCTURED_F64SUM ? 2 : 1, S->grid, S->n_det, stream);
     } else if (structured_of(S)) {
-        const bool f64 = A.model.value_type == DRTS_F64;
-        int mode = 2;
-        if (S->opt.kernel == DRTS_KERNEL_STRUCTURED) mode = (f64 || A.model.rounding == DRTS_ROUND_DITHER) ? 0 : 1;
-        e = launch_structured(S->sa, S->inst_dev.as<StepInst>(), S->work_dev.as<WorkItem>(), S->n_chunks, f64, mode,
-                              S->grid, S->opt.xcd_remap ? 1 : 0, S->xcd_bounds.as<int64_t>(), stream);
+        e = launch_structured(S->sa, S->inst_dev.as<StepInst>(), S->work_dev.as<WorkItem>(), S->n_chunks,
+                              A.model.value_type == DRTS_F64, structured_mode(S), S->grid,
+                              S->opt.xcd_remap ? 1 : 0, S->xcd_bounds.as<int64_t>(), stream);
     } else {
     e = launch_step(S->inst_dev.as<StepInst>(), S->work_dev.as<WorkItem>(), S->n_chunks, 1, S->n_rhs,
                                A.model.value_type == DRTS_F64, A.rp64 ? 1 : 0, spmm ? 1 : 0, S->grid,

@@ -134,7 +134,8 @@ struct StructArgs {
     const int64_t *ddet_ptr, *ddet_row;
     const double *ddet_F;
 };
-constexpr int kStructSegLen = 16;
+constexpr int kStructSegLen = 16;         // voxels per tile of the gather kernel (modes 0 and 3)
+constexpr int kStructDmSeg = 64;          // voxels per tile of the direction-major kernel (modes 1 and 2)
 constexpr int kStructXRows = 1024;
 constexpr int kStructMatLdsHost = 8;      // materials whose blocks the single-rhs LDS halo kernel holds
 constexpr int kStructVoxPerChunk = 64;   // voxels per work item of the push kernel

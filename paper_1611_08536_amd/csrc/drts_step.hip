@@ -1479,8 +1479,8 @@ __device__ __forceinline__ StructTile struct_tile(const StructArgs &sa, int64_t 
 // reflections, Fresnel splits) and escape rows are left to step_struct_x.
 // MODE 0: exact values, x gathered from global memory (FP64, dither).
 // MODE 1: exact nearest values, x from an LDS halo.
-// MODE 2: hi + lo values, x from an LDS halo.
-// MODE 3: hi + lo values, x gathered from global memory (many materials).
+// MODE 2: FP64 row sums, x from an LDS halo.
+// MODE 3: FP64 row sums, x gathered from global memory (many materials).
 // The halo holds the x blocks of the 3 x 3 neighbouring line segments (L + 2
 // voxels each), loaded with contiguous reads, since a regular row's upstream
 // voxel is one of them.
@@ -1700,6 +1700,236 @@ __global__ void __launch_bounds__(256) step_struct(StructArgs sa, const StepInst
         for (int j = 0; j < ntc; j += 2) {
             do_tile(j, PA);
             if (j + 1 < ntc) do_tile(j + 1, PB);
+        }
+        const int64_t nc = I.n_chunks, c = item.chunk;
+        const double wN = wave_sum(sN), wA = wave_sum(sA), wM = wave_max((double)mx);
+        if (lane == 0) {
+            s_wred[0][wave] = wN;
+            s_wred[1][wave] = 0.0;
+            s_wred[2][wave] = wA;
+            s_wred[3][wave] = wM;
+        }
+        __syncthreads();
+        GLB double *part = gpw(I.partials);
+        if (tid < 4) {
+            double a = s_wred[tid][0];
+            for (int w = 1; w < NW; ++w) a = (tid == 3) ? fmax(a, s_wred[tid][w]) : a + s_wred[tid][w];
+            part[(int64_t)tid * nc + c] = a;
+        }
+        if (tid < I.n_det) part[(int64_t)(kSlotDet + tid) * nc + c] = dsum;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Matrix-free step, one rhs, direction-major tiles (modes 1 and 2).
+//
+// A tile is a segment of up to kStructDmSeg = 64 voxels of one x-line; lane i
+// of every wave is voxel x0 + i.  Wave w computes the rows of directions
+// m = w, w + 4, ... for all 64 voxels: for a fixed m the upstream voxels
+// x0 + i - e_m lie on one neighbouring line, so when they share a material
+// (always inside a layer) the coefficient row of (material, m) is
+// wave-uniform and comes through the scalar cache into SGPRs, and LDS holds
+// only x.  The x blocks of the 3 x 3 neighbouring line segments (66 voxels of
+// 26 floats each, contiguous in HBM) are copied straight into LDS with
+// LDS-destination buffer loads; with 26 floats per voxel, the 8-byte reads of
+// 32 lanes from consecutive voxels cover all 64 banks once.  Once every wave
+// has its values, the row values reuse the halo's LDS and the epilogue
+// (sources, y store, FP64 sums) runs a thread per row in row order.
+// Irregular rows are left to step_struct_x.  Terms are added in column order
+// as in every other kernel: mode 1 with the nearest FP32 values (mul, then
+// add), mode 2 in FP64 (one fma per term), rounded once.
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ void __launch_bounds__(256) step_struct_dm(StructArgs sa, const StepInst *__restrict__ insts,
+                                                       const WorkItem *__restrict__ work, int64_t n_work,
+                                                       int xcd_remap, const int64_t *__restrict__ xcd_bounds)
+{
+    constexpr int NT = 256, NW = NT / 64, L = kStructDmSeg, HV = L + 2;
+    constexpr int SEGF = HV * kDirs;        // floats per halo line segment
+    constexpr int SEGQ = SEGF / 4;          // 16-byte pieces per segment
+    constexpr int ROWS = kDirs * L;
+    constexpr int BITW = ROWS / 32 + 2;     // bitmap words a tile's rows touch
+    constexpr int MPW = (kDirs + NW - 1) / NW;   // directions per wave
+    constexpr int RPT = (ROWS + NT - 1) / NT;    // epilogue rows per thread
+    static_assert(SEGF % 4 == 0 && SEGQ <= 2 * NT, "halo segment pieces");
+    extern __shared__ __attribute__((aligned(16))) float s_dm[];   // 9 SEGF floats: the halo, then the row values
+    __shared__ uint8_t s_q[9 * HV];         // material of every halo voxel, 255 outside the grid
+    __shared__ uint32_t s_bits[BITW];
+    __shared__ int32_t s_src[kChunkMax + 1];
+    __shared__ int32_t s_det[kChunkMax + 1];
+    __shared__ double s_abs[kStructMatLds];
+    __shared__ double s_idx[kStructMatLds];
+    __shared__ double s_wred[4][NW];
+    float *s_x = s_dm;
+    float *s_y = s_dm;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    for (int q = tid; q < sa.n_mat; q += NT) s_idx[q] = gp(sa.index)[q];
+    __syncthreads();
+    // bit qu * kStructMatLds + qw: materials qu and qw have the same index
+    uint64_t same_idx = 0;
+    for (int a = 0; a < sa.n_mat; ++a)
+        for (int b = 0; b < sa.n_mat; ++b)
+            if (s_idx[a] == s_idx[b]) same_idx |= 1ull << (a * kStructMatLds + b);
+    const int64_t n_words = (sa.n_states + 31) / 32;
+    const Walk wk = walk_of(n_work, xcd_remap, xcd_bounds);
+    for (int64_t wi = wk.begin; wi < wk.end; wi += wk.stride) {
+        const WorkItem item = work[wi];
+        const StepInst &I = insts[item.inst];
+        const int64_t t = I.t[0];
+        if (t >= *I.t_end) continue;
+        const Scale sc = step_scale(I, 0, t);
+        const float scale = ldexpf(1.0f, -sc.k);
+        const float *x = (const float *)((t & 1) ? I.buf1 : I.buf0);
+        GLB float *y = gpw((float *)((t & 1) ? I.buf0 : I.buf1));
+        const __amdgpu_buffer_rsrc_t rx = make_rsrc((const void *)x, (uint64_t)sa.n_states * 4);
+        const int64_t tile0 = (int64_t)item.chunk * I.tiles_per_chunk;
+        const int ntc = (int)min((int64_t)I.tiles_per_chunk, I.n_tiles - tile0);
+        for (int j = tid; j <= ntc; j += NT) {
+            s_src[j] = gp(I.src_tile)[tile0 + j];
+            s_det[j] = gp(I.det_tile)[tile0 + j];
+        }
+        for (int q = tid; q < I.n_mat; q += NT) s_abs[q] = gp(I.absorb)[q];
+        __syncthreads();
+        double sN = 0.0, sA = 0.0, dsum = 0.0;
+        float mx = 0.0f;
+        for (int j = 0; j < ntc; ++j) {
+            const StructTile T = struct_tile(sa, tile0 + j);
+            const int line = (int)T.line;
+            const int zv0 = line / sa.ny, yv0 = line - zv0 * sa.ny;
+            // the halo: segment sg holds line (y0 + sg % 3 - 1, z0 + sg / 3 - 1),
+            // voxels x0 - 1 .. x0 + len.  A segment whose 16-byte pieces all lie
+            // inside the state is copied straight into LDS; the others (the
+            // first and last line of the grid) float by float with a bounds
+            // check.  Voxels outside the grid are marked in s_q, so no row uses
+            // what their slots hold.
+            const int segf = (T.len + 2) * kDirs;   // floats the tile needs per segment
+            const int segq = (segf + 3) / 4;        // their 16-byte pieces
+#pragma unroll
+            for (int sg = 0; sg < 9; ++sg) {
+                const int yv = yv0 + sg % 3 - 1, zv = zv0 + sg / 3 - 1;
+                if (yv < 0 || yv >= sa.ny || zv < 0 || zv >= sa.nz) continue;
+                const int64_t fo = (int64_t)kDirs * (T.x0 - 1 + (int64_t)sa.nx * (yv + (int64_t)sa.ny * zv));
+                if (fo >= 0 && fo + 4 * (int64_t)segq <= sa.n_states) {
+                    const uint32_t bo = (uint32_t)(4 * fo);   // 4 n_states < 2^32
+#pragma unroll
+                    for (int k = 0; k < 2; ++k) {
+                        const int c = k * NT + tid;
+                        if (c < segq)
+                            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                                rx,
+                                (__attribute__((address_space(3))) void *)(s_x + sg * SEGF + 4 * (k * NT + 64 * wave)),
+                                16, (int)(bo + 16u * (uint32_t)c), 0, 0, 0);
+                    }
+                } else {
+                    for (int e = tid; e < segf; e += NT) {
+                        const int64_t f = fo + e;
+                        s_x[sg * SEGF + e] = (f >= 0 && f < sa.n_states) ? gp(x)[f] : 0.0f;
+                    }
+                }
+            }
+            for (int h = tid; h < 9 * HV; h += NT) {
+                const int sg = h / HV, iv = h - sg * HV;
+                const int xv = T.x0 - 1 + iv, yv = yv0 + sg % 3 - 1, zv = zv0 + sg / 3 - 1;
+                uint8_t q = 255;
+                if (xv >= 0 && xv < sa.nx && yv >= 0 && yv < sa.ny && zv >= 0 && zv < sa.nz)
+                    q = gp(sa.mat)[xv + sa.nx * (yv + sa.ny * zv)];
+                s_q[h] = q;
+            }
+            const int rb0 = (int)(T.row0 >> 5);
+            if (tid < BITW)
+                s_bits[tid] = sa.n_irr > 0 ? gp(sa.irr_bits)[min(rb0 + tid, (int)n_words - 1)] : 0u;
+            // every lane's halo pieces are in LDS once its loads have completed
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            const int qw = s_q[4 * HV + lane + 1];   // the row voxel (255 past the line)
+            float vals[MPW];
+#pragma unroll
+            for (int mi = 0; mi < MPW; ++mi) {
+                const int m = wave + NW * mi;
+                vals[mi] = 0.0f;
+                if (m >= kDirs) continue;
+                const int dx = dir_dx(m), dy = dir_dy(m), dz = dir_dz(m);
+                const int sg = (1 - dz) * 3 + (1 - dy), ix = lane + 1 - dx;
+                const int qu = s_q[sg * HV + ix];
+                // material bytes index the coefficient tables: only materials
+                // of the medium count as inside
+                const bool plain = qu < sa.n_mat && qw < sa.n_mat &&
+                                   (qu == qw || ((same_idx >> (qu * kStructMatLds + qw)) & 1ull));
+                const uint64_t pm = __ballot(plain);
+                if (pm == 0) continue;
+                const int qf = __builtin_amdgcn_readlane(qu, (int)__builtin_ctzll(pm));
+                const bool uni = __ballot(plain && qu != qf) == 0;
+                const float *xs = s_x + sg * SEGF + ix * kDirs;
+                float v;
+                if (MODE == 2) {
+                    auto row_sum = [&](const CST double *C) {
+                        double a = 0.0;
+#pragma unroll
+                        for (int n = 0; n < kDirs; ++n) a = __builtin_fma(C[n], (double)xs[n], a);
+                        return (float)a;
+                    };
+                    v = uni ? row_sum(cst(sa.blocks64) + (qf * kDirs + m) * kDirs)
+                            : row_sum(cst(sa.blocks64) + ((plain ? qu : 0) * kDirs + m) * kDirs);
+                } else {
+                    auto row_sum = [&](const CST float *C) {
+                        float a = 0.0f;
+#pragma unroll
+                        for (int n = 0; n < kDirs; ++n) a += C[n] * xs[n];
+                        return a;
+                    };
+                    v = uni ? row_sum(cst(sa.blocks32) + (qf * kDirs + m) * kDirs)
+                            : row_sum(cst(sa.blocks32) + ((plain ? qu : 0) * kDirs + m) * kDirs);
+                }
+                vals[mi] = plain ? v * scale : 0.0f;
+            }
+            __syncthreads();   // the halo is read: its LDS takes the row values
+#pragma unroll
+            for (int mi = 0; mi < MPW; ++mi) {
+                const int m = wave + NW * mi;
+                if (m < kDirs) s_y[kDirs * lane + m] = vals[mi];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int p = 0; p < RPT; ++p) {
+                const int lr = tid + p * NT;
+                if (lr >= T.nrows) continue;
+                const int64_t r = T.row0 + lr;
+                const int r32 = (int)r;
+                if ((s_bits[(r32 >> 5) - rb0] >> (r32 & 31)) & 1u) continue;   // step_struct_x computes it
+                float v = s_y[lr];
+                const int sb = s_src[j], se = s_src[j + 1];
+                if (sb < se) {
+                    int e2 = lower_bound_rows<int32_t>(I.src_row, sb, se, r);
+                    double s = 0.0;
+                    bool any = false;
+                    for (; e2 < se && gp(I.src_row)[e2] == r; ++e2) {
+                        s += gp(I.src_w)[e2] * gp(I.amp)[t * I.n_src + gp(I.src_id)[e2]];
+                        any = true;
+                    }
+                    if (any) {
+                        v += (float)ldexp(s, -sc.En);
+                        s_y[lr] = v;
+                    }
+                }
+                y[r] = v;
+                sN += (double)v;
+                sA += s_abs[s_q[4 * HV + lr / kDirs + 1]] * (double)v;
+                mx = v > mx ? v : mx;
+            }
+            __syncthreads();
+            const int db = s_det[j], de = s_det[j + 1];
+            if (db < de && tid < I.n_det) {
+                for (int e2 = db; e2 < de; ++e2) {
+                    if (gp(I.det_id)[e2] != tid) continue;
+                    const int64_t row = gp(I.det_row)[e2];
+                    const int r32 = (int)row;
+                    if (!((s_bits[(r32 >> 5) - rb0] >> (r32 & 31)) & 1u))
+                        dsum += gp(I.det_F)[e2] * (double)s_y[row - T.row0];
+                }
+            }
+            __syncthreads();   // before the next tile's halo overwrites the row values
         }
         const int64_t nc = I.n_chunks, c = item.chunk;
         const double wN = wave_sum(sN), wA = wave_sum(sA), wM = wave_max((double)mx);
@@ -2166,10 +2396,13 @@ hipError_t launch_structured(const StructArgs &sa, const StepInst *insts_dev, co
                              const int64_t *xcd_bounds, hipStream_t stream)
 {
     if (n_work <= 0 && sa.n_xrows <= 0) return hipSuccess;
-    // the halo modes keep every direction block in LDS
-    if (sa.n_mat > kStructMatLds) mode = (mode == 2) ? 3 : 0;
-    const size_t blk = (size_t)sa.n_mat * kDirs * kStructLdsStride * sizeof(double);
-    const size_t halo = (size_t)9 * (kStructSegLen + 2) * kStructLdsStride * sizeof(float);
+    // the tiles must be the ones the mode's kernel takes (the host chooses
+    // both): modes 1 and 2 run the direction-major kernel (at most
+    // kStructMatLds materials), modes 0 and 3 the gather kernel
+    const bool dm_mode = !value_f64 && (mode == 1 || mode == 2);
+    if (dm_mode ? (sa.seg_len != kStructDmSeg || sa.n_mat > kStructMatLds) : sa.seg_len != kStructSegLen)
+        return hipErrorInvalidValue;
+    const size_t dm = (size_t)9 * (kStructDmSeg + 2) * kDirs * sizeof(float);
     const dim3 g((unsigned)grid), b(256);
     if (n_work > 0) {
         if (value_f64) {
@@ -2179,11 +2412,11 @@ hipError_t launch_structured(const StructArgs &sa, const StepInst *insts_dev, co
             hipLaunchKernelGGL((step_struct<float, 0>), g, b, 0, stream, sa, insts_dev, work_dev, n_work,
                                xcd_remap & 1, xcd_bounds);
         } else if (mode == 1) {
-            hipLaunchKernelGGL((step_struct<float, 1>), g, b, blk + halo, stream, sa, insts_dev, work_dev, n_work,
-                               xcd_remap & 1, xcd_bounds);
+            hipLaunchKernelGGL((step_struct_dm<1>), g, b, dm, stream, sa, insts_dev, work_dev, n_work, xcd_remap & 1,
+                               xcd_bounds);
         } else if (mode == 2) {
-            hipLaunchKernelGGL((step_struct<float, 2>), g, b, blk + halo, stream, sa, insts_dev, work_dev, n_work,
-                               xcd_remap & 1, xcd_bounds);
+            hipLaunchKernelGGL((step_struct_dm<2>), g, b, dm, stream, sa, insts_dev, work_dev, n_work, xcd_remap & 1,
+                               xcd_bounds);
         } else {
             hipLaunchKernelGGL((step_struct<float, 3>), g, b, 0, stream, sa, insts_dev, work_dev, n_work,
                                xcd_remap & 1, xcd_bounds);
