@@ -137,7 +137,7 @@ struct StructArgs {
 constexpr int kStructSegLen = 16;         // voxels per tile of the gather kernel (modes 0 and 3)
 constexpr int kStructDmSeg = 64;          // voxels per tile of the direction-major kernel (modes 1 and 2)
 constexpr int kStructXRows = 1024;
-constexpr int kStructMatLdsHost = 8;      // materials whose blocks the single-rhs LDS halo kernel holds
+constexpr int kStructMatLdsHost = 8;      // materials the single-rhs direction-major kernel takes
 constexpr int kStructVoxPerChunk = 64;   // voxels per work item of the push kernel
 constexpr int kStructMmXRows = 64;       // rows per work item of the many-rhs pull kernel
 // mode: 0 = exact values with global gathers, 1 = exact nearest values with

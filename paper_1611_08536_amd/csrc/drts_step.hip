@@ -1252,8 +1252,7 @@ __global__ void __launch_bounds__(kNT) finalize_step(const StepInst *__restrict_
 // for bit, while the matrix itself never leaves the chip (per row only the
 // upstream voxel's 26 states of x are read, from L2).
 // ---------------------------------------------------------------------------
-constexpr int kStructMatLds = kStructMatLdsHost;   // direction blocks kept in LDS up to this many materials
-constexpr int kStructLdsStride = 27;               // LDS elements per block row and per halo voxel
+constexpr int kStructMatLds = kStructMatLdsHost;   // materials the direction-major kernel takes (8 x 8 index-pair mask)
 
 __device__ __forceinline__ uint64_t mix64_dev(uint64_t x)
 {
@@ -1475,61 +1474,27 @@ __device__ __forceinline__ StructTile struct_tile(const StructArgs &sa, int64_t 
     return T;
 }
 
-// Matrix-free step, regular rows of the voxel tiles.  Irregular rows (wall
-// reflections, Fresnel splits) and escape rows are left to step_struct_x.
-// MODE 0: exact values, x gathered from global memory (FP64, dither).
-// MODE 1: exact nearest values, x from an LDS halo.
-// MODE 2: FP64 row sums, x from an LDS halo.
-// MODE 3: FP64 row sums, x gathered from global memory (many materials).
-// The halo holds the x blocks of the 3 x 3 neighbouring line segments (L + 2
-// voxels each), loaded with contiguous reads, since a regular row's upstream
-// voxel is one of them.
+// Matrix-free step, regular rows of the voxel tiles, x gathered from global
+// memory: modes 0 (exact values: FP64, or FP32 values that need the dithered
+// rounding of each entry) and 3 (FP64 row sums for media with more materials
+// than the direction-major kernel takes).  A tile is kStructSegLen voxels of
+// one x-line, a thread per row.  Irregular rows (wall reflections, Fresnel
+// splits) and escape rows are left to step_struct_x.
 template <typename VT, int MODE>
 __global__ void __launch_bounds__(256) step_struct(StructArgs sa, const StepInst *__restrict__ insts,
                                                     const WorkItem *__restrict__ work, int64_t n_work,
                                                     int xcd_remap, const int64_t *__restrict__ xcd_bounds)
 {
+    static_assert(MODE == 0 || MODE == 3, "gather modes");
     constexpr int NT = 256, NW = NT / 64, L = kStructSegLen;
-    constexpr int HV = L + 2;                       // voxels per halo line segment
     constexpr int ROWS = kDirs * L;
-    extern __shared__ double s_dyn[];
-    __shared__ uint8_t s_q[9 * HV];
-    __shared__ uint32_t s_bits[(ROWS + 31) / 32 + 1];
+    constexpr int NPASS = (ROWS + NT - 1) / NT;
     __shared__ int32_t s_src[kChunkMax + 1];
-    constexpr bool HALO = MODE == 1 || MODE == 2;
-    constexpr int MATS = HALO ? kStructMatLds : kMatMax;   // the halo modes take at most kStructMatLds materials
     __shared__ int32_t s_det[kChunkMax + 1];
-    __shared__ double s_abs[MATS];
-    __shared__ double s_idx[MATS];
+    __shared__ double s_abs[kMatMax];
     __shared__ VT s_y[ROWS];
     __shared__ double s_wred[4][NW];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int nblk = sa.n_mat * kDirs * kDirs;
-    // halo modes: the blocks (FP32 values for mode 1, FP64 for mode 2) and
-    // the halo in dynamic LDS.  Block rows and halo voxel blocks sit
-    // kStructLdsStride elements apart (odd): the lanes of a wave read rows of
-    // different directions and blocks of different voxels, and an odd stride
-    // spreads them over all LDS banks
-    constexpr int KS = kStructLdsStride;
-    float *s_Chi = (float *)s_dyn;
-    double *s_Cd = s_dyn;
-    float *s_x = (float *)(s_dyn + sa.n_mat * kDirs * KS);
-    if (HALO) {
-        for (int i = tid; i < nblk; i += NT) {
-            const int at = (i / kDirs) * KS + i % kDirs;
-            if (MODE == 2) s_Cd[at] = gp(sa.blocks64)[i];
-            else s_Chi[at] = gp(sa.blocks32)[i];
-        }
-    }
-    for (int q = tid; q < sa.n_mat; q += NT) s_idx[q] = gp(sa.index)[q];
-    __syncthreads();
-    // halo modes (at most kStructMatLds materials): bit qu * kStructMatLds + qw
-    // says whether materials qu and qw have the same refractive index
-    uint64_t same_idx = 0;
-    if (HALO)
-        for (int a = 0; a < sa.n_mat; ++a)
-            for (int b = 0; b < sa.n_mat; ++b)
-                if (s_idx[a] == s_idx[b]) same_idx |= 1ull << (a * kStructMatLds + b);
     const Walk wk = walk_of(n_work, xcd_remap, xcd_bounds);
     for (int64_t wi = wk.begin; wi < wk.end; wi += wk.stride) {
         const WorkItem item = work[wi];
@@ -1550,121 +1515,16 @@ __global__ void __launch_bounds__(256) step_struct(StructArgs sa, const StepInst
         __syncthreads();
         double sN = 0.0, sA = 0.0, dsum = 0.0;
         VT mx = 0;
-        // halo modes: the halos of the next two tiles (a halo line segment is
-        // SEGW contiguous floats of x: two loads per thread per segment from a
-        // uniform base, index clamped into the state, voxels outside the grid
-        // stored as zero), their material bytes and irregular-row bits are in
-        // flight in registers while the current tile is computed
-        constexpr int SEGW = HV * kDirs;
-        constexpr int PER = (SEGW + NT - 1) / NT;
-        static_assert(PER == 2, "halo segment loads per thread");
-        constexpr int BITW = (ROWS + 31) / 32 + 1;      // bitmap words a tile's rows touch
-        struct HaloRegs {
-            float hv[9][PER];
-            uint8_t q;
-            uint32_t b;
-        };
-        const int64_t n_words = (sa.n_states + 31) / 32;
-        const int n_st = (int)sa.n_states;
-        // a thread's rows sit at the same places of every tile (lr = tid +
-        // p NT): their direction and LDS offsets are computed once
-        constexpr int NPASS = (ROWS + NT - 1) / NT;
-        struct RowPos {
-            int mp, xo, qu, qw;
-        };
-        RowPos RP[NPASS];
-#pragma unroll
-        for (int p = 0; p < NPASS; ++p) {
-            const int lr = min(tid + p * NT, ROWS - 1);
-            const int i = lr / kDirs, mp = lr - i * kDirs;
-            const int sg = (1 - dir_dz(mp)) * 3 + (1 - dir_dy(mp));
-            const int ix = i - dir_dx(mp) + 1;
-            RP[p].mp = mp;
-            RP[p].xo = (sg * HV + ix) * KS;
-            RP[p].qu = sg * HV + ix;
-            RP[p].qw = 4 * HV + i + 1;
-        }
-        auto fetch = [&](const StructTile &T, HaloRegs &P) {
-            const uint32_t line = (uint32_t)T.line;
-            const int zv0 = (int)(line / (uint32_t)sa.ny), yv0 = (int)line - zv0 * sa.ny;
-            // per-lane element offsets and x positions, the same for all 9 segments
-            int eo[PER];
-            bool xin[PER];
-#pragma unroll
-            for (int k = 0; k < PER; ++k) {
-                eo[k] = min(tid + k * NT, SEGW - 1);
-                const int xv = T.x0 - 1 + eo[k] / kDirs;
-                xin[k] = xv >= 0 && xv < sa.nx;
-            }
-#pragma unroll
-            for (int sg = 0; sg < 9; ++sg) {
-                const int yv = yv0 + sg % 3 - 1, zv = zv0 + sg / 3 - 1;
-                const bool line_in = yv >= 0 && yv < sa.ny && zv >= 0 && zv < sa.nz;
-                const int base = kDirs * (T.x0 - 1 + sa.nx * (min(max(yv, 0), sa.ny - 1) +
-                                                              sa.ny * min(max(zv, 0), sa.nz - 1)));
-#pragma unroll
-                for (int k = 0; k < PER; ++k) {
-                    const int at = min(max(base + eo[k], 0), n_st - 1);
-                    const float v = (float)x[at];
-                    P.hv[sg][k] = (line_in && xin[k]) ? v : 0.f;
-                }
-            }
-            P.q = 255;
-            if (tid < 9 * HV) {
-                const int sg = tid / HV, iv = tid - sg * HV;
-                const int xv = T.x0 - 1 + iv, yv = yv0 + sg % 3 - 1, zv = zv0 + sg / 3 - 1;
-                if (xv >= 0 && xv < sa.nx && yv >= 0 && yv < sa.ny && zv >= 0 && zv < sa.nz)
-                    P.q = gp(sa.mat)[xv + sa.nx * (yv + sa.ny * zv)];
-            }
-            P.b = 0;
-            if (tid < BITW && sa.n_irr > 0) P.b = gp(sa.irr_bits)[min((int)(T.row0 >> 5) + tid, (int)n_words - 1)];
-        };
-        auto do_tile = [&](int j, HaloRegs &P) {
+        for (int j = 0; j < ntc; ++j) {
             const StructTile T = struct_tile(sa, tile0 + j);
-            if (HALO) {
-#pragma unroll
-                for (int sg = 0; sg < 9; ++sg)
-#pragma unroll
-                    for (int k = 0; k < PER; ++k) {
-                        const int e = tid + k * NT;
-                        if (e < SEGW) s_x[sg * HV * KS + (e / kDirs) * KS + e % kDirs] = P.hv[sg][k];
-                    }
-                if (tid < 9 * HV) s_q[tid] = P.q;
-                if (tid < BITW) s_bits[tid] = P.b;
-                __syncthreads();
-                if (j + 2 < ntc) fetch(struct_tile(sa, tile0 + j + 2), P);
-            }
 #pragma unroll
             for (int p = 0; p < NPASS; ++p) {
                 const int lr = tid + p * NT;
                 if (lr >= T.nrows) continue;
                 const int64_t r = T.row0 + lr;
-                const int r32 = (int)r, rb0 = (int)(T.row0 >> 5);
-                const bool irr = HALO ? ((s_bits[(r32 >> 5) - rb0] >> (r32 & 31)) & 1u) != 0
-                                      : struct_irregular(sa, r);
-                if (irr) continue;   // step_struct_x computes it
-                VT acc = 0;
-                int qw;
-                if (HALO) {
-                    const int qu = s_q[RP[p].qu];
-                    qw = s_q[RP[p].qw];
-                    if (qu != 255 && (qu == qw || (same_idx >> (qu * kStructMatLds + qw)) & 1ull)) {
-                        const float *xs = s_x + RP[p].xo;
-                        const int off = (qu * kDirs + RP[p].mp) * KS;
-                        if (MODE == 2) {
-                            double a = 0.0;
-#pragma unroll
-                            for (int n = 0; n < kDirs; ++n) a = __builtin_fma(s_Cd[off + n], (double)xs[n], a);
-                            acc = (VT)a;
-                        } else {
-#pragma unroll
-                            for (int n = 0; n < kDirs; ++n) acc += (VT)(s_Chi[off + n] * xs[n]);
-                        }
-                    }
-                } else {
-                    acc = struct_plain_row<VT, MODE>(sa, r, x);
-                    qw = gp(sa.mat)[r / kDirs];
-                }
+                if (struct_irregular(sa, r)) continue;   // step_struct_x computes it
+                const VT acc = struct_plain_row<VT, MODE>(sa, r, x);
+                const int qw = gp(sa.mat)[r / kDirs];
                 VT v = acc * scale;
                 const int sb = s_src[j], se = s_src[j + 1];
                 if (sb < se) {
@@ -1693,13 +1553,6 @@ __global__ void __launch_bounds__(256) step_struct(StructArgs sa, const StepInst
                 }
             }
             __syncthreads();
-        };
-        HaloRegs PA, PB;
-        if (HALO && ntc > 0) fetch(struct_tile(sa, tile0), PA);
-        if (HALO && ntc > 1) fetch(struct_tile(sa, tile0 + 1), PB);
-        for (int j = 0; j < ntc; j += 2) {
-            do_tile(j, PA);
-            if (j + 1 < ntc) do_tile(j + 1, PB);
         }
         const int64_t nc = I.n_chunks, c = item.chunk;
         const double wN = wave_sum(sN), wA = wave_sum(sA), wM = wave_max((double)mx);
