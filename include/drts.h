@@ -332,8 +332,12 @@ void drts_batch_destroy(drts_batch_t *B);
  * medium before assembly, the exact size after), two state buffers, its
  * series and its source table.  Results equal those of the same solve run
  * alone (drts_run), bit for bit.  budget_bytes > 0; 1 <= quantum <= 100000;
- * 1 <= max_active <= 4096; max_skips >= 0; policy DRTS_SERVE_*.  Calls on
- * one server must not overlap. */
+ * 1 <= max_active <= 4096; max_skips >= 0; policy DRTS_SERVE_*.
+ * drts_serve_submit may be called from any thread, also while another call
+ * on the same server runs (it builds the request's host model before it
+ * takes the server's lock), so a client can keep submitting while a tick
+ * runs on the device; the other calls on one server must not overlap each
+ * other, and drts_serve_destroy must not overlap any call. */
 #define DRTS_SERVE_ARRIVAL 0  /* waiting requests are considered in arrival order */
 #define DRTS_SERVE_SHORTEST 1 /* ... in order of work (entries x steps), least first */
 
@@ -342,9 +346,11 @@ int drts_serve_create(const drts_device_t *dev, int64_t budget_bytes, int32_t qu
 
 /* Queues one solve of n_steps steps: an FP32 medium (its host arrays are
  * copied), its sources (the table must stay valid until the request has
- * finished) and detectors (copied; NULL for none).  DRTS_E_NOMEM when the
- * request's footprint exceeds the whole budget; DRTS_E_INVALID for an FP64
- * medium or a malformed argument. */
+ * finished) and detectors (copied; NULL for none).  Ids increase in the
+ * order the calls start, and that is the arrival order of the queue, also
+ * when calls on several threads overlap.  DRTS_E_NOMEM when the request's
+ * footprint exceeds the whole budget; DRTS_E_INVALID for an FP64 medium or
+ * a malformed argument. */
 int drts_serve_submit(drts_server_t *Q, const drts_medium_t *medium, const drts_source_table_t *src,
                       const drts_detectors_t *det, int64_t n_steps, int64_t *request_id);
 

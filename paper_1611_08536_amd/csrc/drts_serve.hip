@@ -5,6 +5,8 @@
 // uneven batch (one launch per step for all of them) and runs a quantum of
 // steps.  Admission is by device footprint against a budget; retirement
 // copies the series to host memory and frees the request's device memory.
+// Submission builds the request's host model outside the server's lock, so
+// clients may submit from other threads while a tick runs on the device.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -12,6 +14,7 @@
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -74,8 +77,11 @@ struct drts_server {
     drts_device_t dev{};
     int64_t budget = 0, used = 0;
     int32_t quantum = 0, max_active = 0, max_skips = 0, policy = 0;
+    // guards next_id and everything below: submissions may run on other
+    // threads concurrently with the other calls
+    mutable std::mutex mu;
     int64_t next_id = 1;
-    std::deque<Request *> waiting;
+    std::deque<Request *> waiting;   // ascending id (submission order)
     std::vector<Request *> active;
     std::map<int64_t, std::unique_ptr<Request>> all;
     std::deque<int64_t> unreported;
@@ -216,8 +222,16 @@ int drts_serve_submit(drts_server_t *Q, const drts_medium_t *medium, const drts_
     if (n_steps < 1) return set_error(DRTS_E_INVALID, "n_steps must be >= 1");
     std::unique_ptr<Request> q;
     int rc;
+    int64_t id;
+    {
+        // the id fixes the request's place in submission order
+        std::lock_guard<std::mutex> lk(Q->mu);
+        id = Q->next_id++;
+    }
     try {
+        // host work (copy, model): outside the lock
         q.reset(new Request);
+        q->id = id;
         q->n_steps = n_steps;
         q->src = src;
         rc = copy_request(*q, medium, det);
@@ -229,10 +243,12 @@ int drts_serve_submit(drts_server_t *Q, const drts_medium_t *medium, const drts_
     if (q->est_bytes > Q->budget)
         return set_error(DRTS_E_NOMEM, "request needs about %lld bytes, beyond the budget of %lld",
                          (long long)q->est_bytes, (long long)Q->budget);
-    q->id = Q->next_id++;
-    *request_id = q->id;
-    Q->waiting.push_back(q.get());
-    Q->all[q->id] = std::move(q);
+    std::lock_guard<std::mutex> lk(Q->mu);
+    auto at = Q->waiting.end();
+    while (at != Q->waiting.begin() && (*(at - 1))->id > id) --at;
+    Q->waiting.insert(at, q.get());
+    *request_id = id;
+    Q->all[id] = std::move(q);
     return DRTS_OK;
 }
 
@@ -259,6 +275,7 @@ int drts_serve_tick(drts_server_t *Q, int32_t *n_active, int32_t *n_waiting, int
                     int64_t *bytes_in_use)
 {
     if (!Q) return set_error(DRTS_E_INVALID, "server is NULL");
+    std::lock_guard<std::mutex> lk(Q->mu);
     int rc = DRTS_OK;
     int32_t finished = 0;
     // 1. admission: first fit in arrival order; a request passed over
@@ -329,6 +346,7 @@ int drts_serve_tick(drts_server_t *Q, int32_t *n_active, int32_t *n_waiting, int
 int drts_serve_poll(drts_server_t *Q, int64_t *ids, int32_t cap, int32_t *n_out)
 {
     if (!Q || !n_out || (cap > 0 && !ids)) return set_error(DRTS_E_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(Q->mu);
     int32_t n = 0;
     while (n < cap && !Q->unreported.empty()) {
         ids[n++] = Q->unreported.front();
@@ -341,6 +359,7 @@ int drts_serve_poll(drts_server_t *Q, int64_t *ids, int32_t cap, int32_t *n_out)
 int drts_serve_result(const drts_server_t *Q, int64_t request_id, double *series, int32_t *exp2, double *totals)
 {
     if (!Q) return set_error(DRTS_E_INVALID, "server is NULL");
+    std::lock_guard<std::mutex> lk(Q->mu);
     auto it = Q->all.find(request_id);
     if (it == Q->all.end()) return set_error(DRTS_E_INVALID, "unknown request %lld", (long long)request_id);
     const Request &q = *it->second;
@@ -354,6 +373,7 @@ int drts_serve_result(const drts_server_t *Q, int64_t request_id, double *series
 int drts_serve_release(drts_server_t *Q, int64_t request_id)
 {
     if (!Q) return set_error(DRTS_E_INVALID, "server is NULL");
+    std::lock_guard<std::mutex> lk(Q->mu);
     auto it = Q->all.find(request_id);
     if (it == Q->all.end()) return set_error(DRTS_E_INVALID, "unknown request %lld", (long long)request_id);
     if (!it->second->finished) return set_error(DRTS_E_STATE, "request %lld has not finished", (long long)request_id);

@@ -2,7 +2,9 @@
 
 `serve` replays a list of timed requests (workloads.Request: arrival time and
 workload) against one drts.Server: every request is submitted once the wall
-clock passes its arrival time, and the loop ticks (admit, one quantum of
+clock passes its arrival time, by a small pool of submitting threads (a
+submission builds the request's host model, which the library does outside
+the server's lock), while the main thread ticks (admit, one quantum of
 batched steps, retire) until all have finished.  `fifo_plain` is the
 comparison: the same requests solved one after another in arrival order, each
 alone with drts_run.  Both report per-request latency (completion - arrival)
@@ -10,6 +12,7 @@ and the solves per second of the whole replay.
 """
 from __future__ import annotations
 
+import concurrent.futures as cf
 import time
 from typing import List, Optional
 
@@ -30,41 +33,67 @@ def _summary(lat: List[float], wall: float, n: int) -> dict:
 
 
 def serve(requests, budget_bytes: int, quantum: int = 50, max_active: int = 256, max_skips: int = 8,
-          policy: str = "arrival", keep_results: bool = False, log=None) -> dict:
+          policy: str = "arrival", keep_results: bool = False, log=None, submit_threads: int = 4) -> dict:
     """Replays `requests` through one server; returns the latency summary and,
-    with keep_results, every request's series in submission order."""
+    with keep_results, every request's series in submission order.
+    submit_threads = 0 submits on the calling thread (every request that has
+    arrived is queued before the next tick)."""
     S = drts.Server(budget_bytes, quantum, max_active, max_skips, policy)
     order = sorted(range(len(requests)), key=lambda i: requests[i].arrival_s)
     tables, rid_of, arrival_of = {}, {}, {}
     done_at, results = {}, {}
+    pending = {}   # submission future -> request index
     k = 0
     peak_active = 0
-    t0 = time.perf_counter()
-    while len(done_at) < len(requests):
-        now = time.perf_counter() - t0
-        while k < len(order) and requests[order[k]].arrival_s <= now:
-            i = order[k]
-            wl = requests[i].workload
-            tab = _table(wl)
-            rid = S.submit(wl.medium, tab, wl.detectors, wl.n_steps, wl.rounding, wl.n_ref)
-            tables[rid] = tab
+    pool = cf.ThreadPoolExecutor(max_workers=submit_threads) if submit_threads > 0 else None
+
+    def collect():
+        for fut in [f for f in pending if f.done()]:
+            i = pending.pop(fut)
+            rid = fut.result()   # raises the submission's error
             rid_of[rid] = i
             arrival_of[rid] = requests[i].arrival_s
-            k += 1
-        info = S.tick()
-        peak_active = max(peak_active, info["active"] + info["finished"])   # ran during the tick
-        t = time.perf_counter() - t0
-        for rid in S.poll():
-            done_at[rid] = t
-            if keep_results:
-                results[rid_of[rid]] = S.result(rid)
-            S.release(rid)
-            tables.pop(rid, None)
-        if log and info["finished"]:
-            log("serve: t=%.2fs active=%d waiting=%d done=%d/%d" %
-                (t, info["active"], info["waiting"], len(done_at), len(requests)))
-        if info["active"] == 0 and info["waiting"] == 0 and k < len(order):
-            time.sleep(max(0.0, requests[order[k]].arrival_s - (time.perf_counter() - t0)))
+
+    t0 = time.perf_counter()
+    try:
+        while len(done_at) < len(requests):
+            now = time.perf_counter() - t0
+            while k < len(order) and requests[order[k]].arrival_s <= now:
+                i = order[k]
+                wl = requests[i].workload
+                tables[i] = _table(wl)   # stays valid until the request has finished
+                args = (wl.medium, tables[i], wl.detectors, wl.n_steps, wl.rounding, wl.n_ref)
+                if pool is None:
+                    fut = cf.Future()
+                    fut.set_result(S.submit(*args))
+                else:
+                    fut = pool.submit(S.submit, *args)
+                pending[fut] = i
+                k += 1
+            collect()
+            info = S.tick()
+            peak_active = max(peak_active, info["active"] + info["finished"])   # ran during the tick
+            t = time.perf_counter() - t0
+            collect()
+            for rid in S.poll():
+                done_at[rid] = t
+                if keep_results:
+                    results[rid_of[rid]] = S.result(rid)
+                S.release(rid)
+                tables.pop(rid_of[rid], None)
+            if log and info["finished"]:
+                log("serve: t=%.2fs active=%d waiting=%d done=%d/%d" %
+                    (t, info["active"], info["waiting"], len(done_at), len(requests)))
+            if info["active"] == 0 and info["waiting"] == 0:
+                # nothing on the device: wait for a submission or the next arrival
+                wait = (requests[order[k]].arrival_s - (time.perf_counter() - t0)) if k < len(order) else None
+                if pending:
+                    cf.wait(list(pending), timeout=wait, return_when=cf.FIRST_COMPLETED)
+                elif wait is not None:
+                    time.sleep(max(0.0, wait))
+    finally:
+        if pool is not None:
+            pool.shutdown(wait=True)
     wall = time.perf_counter() - t0
     S.close()
     out = _summary([done_at[r] - arrival_of[r] for r in done_at], wall, len(requests))

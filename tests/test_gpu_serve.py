@@ -54,8 +54,9 @@ def test_strict_fifo_and_single_slot_give_the_same_results():
     reqs = _requests(5, steps=(20, 60))
     for q in reqs:
         q.arrival_s = 0.0          # all submitted before the first tick
-    a = serve.serve(reqs, 1 << 34, quantum=7, max_active=1, max_skips=0, keep_results=True)
-    b = serve.serve(reqs, 1 << 34, quantum=64, max_active=64, max_skips=0, keep_results=True)
+    # submissions on the ticking thread: all five are queued before the first tick
+    a = serve.serve(reqs, 1 << 34, quantum=7, max_active=1, max_skips=0, keep_results=True, submit_threads=0)
+    b = serve.serve(reqs, 1 << 34, quantum=64, max_active=64, max_skips=0, keep_results=True, submit_threads=0)
     assert a["peak_active"] == 1 and b["peak_active"] == len(reqs)
     for i in range(len(reqs)):
         assert _same(a["results"][i], b["results"][i]), i

@@ -94,3 +94,43 @@ def test_tick_on_an_empty_server_does_nothing():
     assert lib.drts_serve_tick(h, C.byref(a), C.byref(w), C.byref(f), C.byref(b)) == 0
     assert (a.value, w.value, f.value, b.value) == (0, 0, 0, 0)
     lib.drts_serve_destroy(h)
+
+
+def test_concurrent_submissions_queue_every_request_once():
+    """Submissions from several threads at once (each builds its host model
+    outside the server's lock): every call gets its own id, ids are the
+    consecutive range of the calls, every request is queued (known and not
+    finished), and a failing submission on one thread does not disturb the
+    others."""
+    import threading
+    reqs = W.c5(n_req=8, edge=(10, 16), steps=(20, 40))
+    h = _server(1 << 34)
+    out, errs = {}, []
+    keep = []
+    barrier = threading.Barrier(len(reqs) + 1)
+
+    def work(i):
+        barrier.wait()
+        rc, rid, tab = _submit(h, reqs[i].workload)
+        keep.append(tab)
+        out[i] = (rc, rid)
+
+    def bad():
+        barrier.wait()
+        errs.append(_submit(h, reqs[0].workload, value_type="f64")[0])
+
+    ts = [threading.Thread(target=work, args=(i,)) for i in range(len(reqs))] + [threading.Thread(target=bad)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert errs == [-1]
+    assert all(rc == 0 for rc, _ in out.values())
+    ids = sorted(rid for _, rid in out.values())
+    assert ids == list(range(1, len(reqs) + 1))   # the FP64 medium is refused before it takes an id
+    for rid in ids:
+        assert lib.drts_serve_result(h, rid, None, None, None) == -5   # queued, not finished
+    n = C.c_int32()
+    pid = (C.c_int64 * 16)()
+    assert lib.drts_serve_poll(h, pid, 16, C.byref(n)) == 0 and n.value == 0
+    lib.drts_serve_destroy(h)
