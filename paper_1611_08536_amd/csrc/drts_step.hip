@@ -1578,20 +1578,24 @@ __global__ void __launch_bounds__(256) step_struct(StructArgs sa, const StepInst
 // Matrix-free step, one rhs, direction-major tiles (modes 1 and 2).
 //
 // A tile is a segment of up to kStructDmSeg = 64 voxels of one x-line; lane i
-// of every wave is voxel x0 + i.  Wave w computes the rows of directions
-// m = w, w + 4, ... for all 64 voxels: for a fixed m the upstream voxels
-// x0 + i - e_m lie on one neighbouring line, so when they share a material
-// (always inside a layer) the coefficient row of (material, m) is
-// wave-uniform and comes through the scalar cache into SGPRs, and LDS holds
-// only x.  The x blocks of the 3 x 3 neighbouring line segments (66 voxels of
-// 26 floats each, contiguous in HBM) are copied straight into LDS with
-// LDS-destination buffer loads; with 26 floats per voxel, the 8-byte reads of
-// 32 lanes from consecutive voxels cover all 64 banks once.  Once every wave
-// has its values, the row values reuse the halo's LDS and the epilogue
-// (sources, y store, FP64 sums) runs a thread per row in row order.
-// Irregular rows are left to step_struct_x.  Terms are added in column order
-// as in every other kernel: mode 1 with the nearest FP32 values (mul, then
-// add), mode 2 in FP64 (one fma per term), rounded once.
+// of every wave is voxel x0 + i.  The rows of a direction m take x from the
+// upstream voxels x0 + i - e_m, which lie on one of the 3 x 3 neighbouring
+// line segments; for a fixed m they share a material inside a layer, so the
+// coefficient row of (material, m) is wave-uniform and comes through the
+// scalar cache into SGPRs, and LDS holds only x.  A tile runs in three
+// phases, one per plane of upstream voxels (directions 17..25 read the plane
+// below in z, 9..16 their own, 0..8 the plane above): each phase copies its
+// three line segments (66 voxels of 26 floats each, contiguous in HBM)
+// straight into LDS with LDS-destination buffer loads, and the four waves
+// compute its directions (wave w every fourth one), writing each row value
+// to the tile's row buffer.  A phase's halo is a third of the tile's, so five
+// workgroups fit per CU and their copies overlap each other's work.  With 26
+// floats per voxel, the 8-byte LDS reads of 32 lanes from consecutive voxels
+// cover all 64 banks once.  The epilogue (sources, y store, FP64 sums,
+// detectors) then runs a thread per row in row order.  Irregular rows are
+// left to step_struct_x.  Terms are added in column order as in every other
+// kernel: mode 1 with the nearest FP32 values (mul, then add), mode 2 in FP64
+// (one fma per term), rounded once.
 // ---------------------------------------------------------------------------
 template <int MODE>
 __global__ void __launch_bounds__(256) step_struct_dm(StructArgs sa, const StepInst *__restrict__ insts,
@@ -1600,13 +1604,15 @@ __global__ void __launch_bounds__(256) step_struct_dm(StructArgs sa, const StepI
 {
     constexpr int NT = 256, NW = NT / 64, L = kStructDmSeg, HV = L + 2;
     constexpr int SEGF = HV * kDirs;        // floats per halo line segment
-    constexpr int SEGQ = SEGF / 4;          // 16-byte pieces per segment
     constexpr int ROWS = kDirs * L;
     constexpr int BITW = ROWS / 32 + 2;     // bitmap words a tile's rows touch
-    constexpr int MPW = (kDirs + NW - 1) / NW;   // directions per wave
     constexpr int RPT = (ROWS + NT - 1) / NT;    // epilogue rows per thread
-    static_assert(SEGF % 4 == 0 && SEGQ <= 2 * NT, "halo segment pieces");
-    extern __shared__ __attribute__((aligned(16))) float s_dm[];   // 9 SEGF floats: the halo, then the row values
+    static_assert(SEGF % 4 == 0 && SEGF / 4 <= 2 * NT, "halo segment pieces");
+    // phase ph reads upstream plane z0 + ph - 1 (halo segments 3 ph .. 3 ph + 2);
+    // in the lattice order d = k - [k > 13], k = 9 (dz + 1) + 3 (dy + 1) + dx + 1,
+    // its directions (dz = 1 - ph) are 17..25, 9..16 and 0..8
+    static_assert(kDirs == 26, "direction order");
+    extern __shared__ __attribute__((aligned(16))) float s_dm[];   // 3 SEGF halo floats, then ROWS row values
     __shared__ uint8_t s_q[9 * HV];         // material of every halo voxel, 255 outside the grid
     __shared__ uint32_t s_bits[BITW];
     __shared__ int32_t s_src[kChunkMax + 1];
@@ -1615,7 +1621,7 @@ __global__ void __launch_bounds__(256) step_struct_dm(StructArgs sa, const StepI
     __shared__ double s_idx[kStructMatLds];
     __shared__ double s_wred[4][NW];
     float *s_x = s_dm;
-    float *s_y = s_dm;
+    float *s_y = s_dm + 3 * SEGF;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     for (int q = tid; q < sa.n_mat; q += NT) s_idx[q] = gp(sa.index)[q];
@@ -1651,37 +1657,9 @@ __global__ void __launch_bounds__(256) step_struct_dm(StructArgs sa, const StepI
             const StructTile T = struct_tile(sa, tile0 + j);
             const int line = (int)T.line;
             const int zv0 = line / sa.ny, yv0 = line - zv0 * sa.ny;
-            // the halo: segment sg holds line (y0 + sg % 3 - 1, z0 + sg / 3 - 1),
-            // voxels x0 - 1 .. x0 + len.  A segment whose 16-byte pieces all lie
-            // inside the state is copied straight into LDS; the others (the
-            // first and last line of the grid) float by float with a bounds
-            // check.  Voxels outside the grid are marked in s_q, so no row uses
-            // what their slots hold.
             const int segf = (T.len + 2) * kDirs;   // floats the tile needs per segment
             const int segq = (segf + 3) / 4;        // their 16-byte pieces
-#pragma unroll
-            for (int sg = 0; sg < 9; ++sg) {
-                const int yv = yv0 + sg % 3 - 1, zv = zv0 + sg / 3 - 1;
-                if (yv < 0 || yv >= sa.ny || zv < 0 || zv >= sa.nz) continue;
-                const int64_t fo = (int64_t)kDirs * (T.x0 - 1 + (int64_t)sa.nx * (yv + (int64_t)sa.ny * zv));
-                if (fo >= 0 && fo + 4 * (int64_t)segq <= sa.n_states) {
-                    const uint32_t bo = (uint32_t)(4 * fo);   // 4 n_states < 2^32
-#pragma unroll
-                    for (int k = 0; k < 2; ++k) {
-                        const int c = k * NT + tid;
-                        if (c < segq)
-                            __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                                rx,
-                                (__attribute__((address_space(3))) void *)(s_x + sg * SEGF + 4 * (k * NT + 64 * wave)),
-                                16, (int)(bo + 16u * (uint32_t)c), 0, 0, 0);
-                    }
-                } else {
-                    for (int e = tid; e < segf; e += NT) {
-                        const int64_t f = fo + e;
-                        s_x[sg * SEGF + e] = (f >= 0 && f < sa.n_states) ? gp(x)[f] : 0.0f;
-                    }
-                }
-            }
+            const int rb0 = (int)(T.row0 >> 5);
             for (int h = tid; h < 9 * HV; h += NT) {
                 const int sg = h / HV, iv = h - sg * HV;
                 const int xv = T.x0 - 1 + iv, yv = yv0 + sg % 3 - 1, zv = zv0 + sg / 3 - 1;
@@ -1690,60 +1668,90 @@ __global__ void __launch_bounds__(256) step_struct_dm(StructArgs sa, const StepI
                     q = gp(sa.mat)[xv + sa.nx * (yv + sa.ny * zv)];
                 s_q[h] = q;
             }
-            const int rb0 = (int)(T.row0 >> 5);
             if (tid < BITW)
                 s_bits[tid] = sa.n_irr > 0 ? gp(sa.irr_bits)[min(rb0 + tid, (int)n_words - 1)] : 0u;
-            // every lane's halo pieces are in LDS once its loads have completed
-            __builtin_amdgcn_s_waitcnt(0);
-            __syncthreads();
-            const int qw = s_q[4 * HV + lane + 1];   // the row voxel (255 past the line)
-            float vals[MPW];
 #pragma unroll
-            for (int mi = 0; mi < MPW; ++mi) {
-                const int m = wave + NW * mi;
-                vals[mi] = 0.0f;
-                if (m >= kDirs) continue;
-                const int dx = dir_dx(m), dy = dir_dy(m), dz = dir_dz(m);
-                const int sg = (1 - dz) * 3 + (1 - dy), ix = lane + 1 - dx;
-                const int qu = s_q[sg * HV + ix];
-                // material bytes index the coefficient tables: only materials
-                // of the medium count as inside
-                const bool plain = qu < sa.n_mat && qw < sa.n_mat &&
-                                   (qu == qw || ((same_idx >> (qu * kStructMatLds + qw)) & 1ull));
-                const uint64_t pm = __ballot(plain);
-                if (pm == 0) continue;
-                const int qf = __builtin_amdgcn_readlane(qu, (int)__builtin_ctzll(pm));
-                const bool uni = __ballot(plain && qu != qf) == 0;
-                const float *xs = s_x + sg * SEGF + ix * kDirs;
-                float v;
-                if (MODE == 2) {
-                    auto row_sum = [&](const CST double *C) {
-                        double a = 0.0;
+            for (int ph = 0; ph < 3; ++ph) {
+                // this phase's three segments: line (y0 + k - 1, z0 + ph - 1),
+                // voxels x0 - 1 .. x0 + len.  A segment whose 16-byte pieces all
+                // lie inside the state is copied straight into LDS; the others
+                // (first and last line of the grid) float by float with a bounds
+                // check.  Voxels outside the grid are marked in s_q, so no row
+                // uses what their slots hold.
+                const int zv = zv0 + ph - 1;
+                const bool plane_in = zv >= 0 && zv < sa.nz;
 #pragma unroll
-                        for (int n = 0; n < kDirs; ++n) a = __builtin_fma(C[n], (double)xs[n], a);
-                        return (float)a;
-                    };
-                    v = uni ? row_sum(cst(sa.blocks64) + (qf * kDirs + m) * kDirs)
-                            : row_sum(cst(sa.blocks64) + ((plain ? qu : 0) * kDirs + m) * kDirs);
-                } else {
-                    auto row_sum = [&](const CST float *C) {
-                        float a = 0.0f;
+                for (int k = 0; k < 3; ++k) {
+                    const int yv = yv0 + k - 1;
+                    if (!plane_in || yv < 0 || yv >= sa.ny) continue;
+                    float *seg = s_x + k * SEGF;
+                    const int64_t fo = (int64_t)kDirs * (T.x0 - 1 + (int64_t)sa.nx * (yv + (int64_t)sa.ny * zv));
+                    if (fo >= 0 && fo + 4 * (int64_t)segq <= sa.n_states) {
+                        const uint32_t bo = (uint32_t)(4 * fo);   // 4 n_states < 2^32
 #pragma unroll
-                        for (int n = 0; n < kDirs; ++n) a += C[n] * xs[n];
-                        return a;
-                    };
-                    v = uni ? row_sum(cst(sa.blocks32) + (qf * kDirs + m) * kDirs)
-                            : row_sum(cst(sa.blocks32) + ((plain ? qu : 0) * kDirs + m) * kDirs);
+                        for (int u = 0; u < 2; ++u) {
+                            const int c = u * NT + tid;
+                            if (c < segq)
+                                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                                    rx, (__attribute__((address_space(3))) void *)(seg + 4 * (u * NT + 64 * wave)), 16,
+                                    (int)(bo + 16u * (uint32_t)c), 0, 0, 0);
+                        }
+                    } else {
+                        for (int e = tid; e < segf; e += NT) {
+                            const int64_t f = fo + e;
+                            seg[e] = (f >= 0 && f < sa.n_states) ? gp(x)[f] : 0.0f;
+                        }
+                    }
                 }
-                vals[mi] = plain ? v * scale : 0.0f;
-            }
-            __syncthreads();   // the halo is read: its LDS takes the row values
+                // every lane's pieces are in LDS once its loads have completed
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+                const int qw = s_q[4 * HV + lane + 1];   // the row voxel (255 past the line)
+                const int m0 = ph == 0 ? 17 : (ph == 1 ? 9 : 0);
+                const int mn = ph == 1 ? 8 : 9;
 #pragma unroll
-            for (int mi = 0; mi < MPW; ++mi) {
-                const int m = wave + NW * mi;
-                if (m < kDirs) s_y[kDirs * lane + m] = vals[mi];
+                for (int i = 0; i < 3; ++i) {
+                    const int e = wave + NW * i;
+                    if (e >= mn) continue;
+                    const int m = m0 + e;
+                    const int dx = dir_dx(m), dy = dir_dy(m);
+                    const int k = 1 - dy, sg = 3 * ph + k, ix = lane + 1 - dx;
+                    const int qu = s_q[sg * HV + ix];
+                    // material bytes index the coefficient tables: only
+                    // materials of the medium count as inside
+                    const bool plain = qu < sa.n_mat && qw < sa.n_mat &&
+                                       (qu == qw || ((same_idx >> (qu * kStructMatLds + qw)) & 1ull));
+                    const uint64_t pm = __ballot(plain);
+                    float v = 0.0f;
+                    if (pm != 0) {
+                        const int qf = __builtin_amdgcn_readlane(qu, (int)__builtin_ctzll(pm));
+                        const bool uni = __ballot(plain && qu != qf) == 0;
+                        const float *xs = s_x + k * SEGF + ix * kDirs;
+                        if (MODE == 2) {
+                            auto row_sum = [&](const CST double *C) {
+                                double a = 0.0;
+#pragma unroll
+                                for (int n = 0; n < kDirs; ++n) a = __builtin_fma(C[n], (double)xs[n], a);
+                                return (float)a;
+                            };
+                            v = uni ? row_sum(cst(sa.blocks64) + (qf * kDirs + m) * kDirs)
+                                    : row_sum(cst(sa.blocks64) + ((plain ? qu : 0) * kDirs + m) * kDirs);
+                        } else {
+                            auto row_sum = [&](const CST float *C) {
+                                float a = 0.0f;
+#pragma unroll
+                                for (int n = 0; n < kDirs; ++n) a += C[n] * xs[n];
+                                return a;
+                            };
+                            v = uni ? row_sum(cst(sa.blocks32) + (qf * kDirs + m) * kDirs)
+                                    : row_sum(cst(sa.blocks32) + ((plain ? qu : 0) * kDirs + m) * kDirs);
+                        }
+                        v = plain ? v * scale : 0.0f;
+                    }
+                    s_y[kDirs * lane + m] = v;
+                }
+                __syncthreads();   // the phase's halo is read before the next one lands
             }
-            __syncthreads();
 #pragma unroll
             for (int p = 0; p < RPT; ++p) {
                 const int lr = tid + p * NT;
@@ -1782,7 +1790,7 @@ __global__ void __launch_bounds__(256) step_struct_dm(StructArgs sa, const StepI
                         dsum += gp(I.det_F)[e2] * (double)s_y[row - T.row0];
                 }
             }
-            __syncthreads();   // before the next tile's halo overwrites the row values
+            __syncthreads();   // before the next tile's materials, bits and rows
         }
         const int64_t nc = I.n_chunks, c = item.chunk;
         const double wN = wave_sum(sN), wA = wave_sum(sA), wM = wave_max((double)mx);
@@ -2255,7 +2263,7 @@ hipError_t launch_structured(const StructArgs &sa, const StepInst *insts_dev, co
     const bool dm_mode = !value_f64 && (mode == 1 || mode == 2);
     if (dm_mode ? (sa.seg_len != kStructDmSeg || sa.n_mat > kStructMatLds) : sa.seg_len != kStructSegLen)
         return hipErrorInvalidValue;
-    const size_t dm = (size_t)9 * (kStructDmSeg + 2) * kDirs * sizeof(float);
+    const size_t dm = (size_t)(3 * (kStructDmSeg + 2) + kStructDmSeg) * kDirs * sizeof(float);
     const dim3 g((unsigned)grid), b(256);
     if (n_work > 0) {
         if (value_f64) {
