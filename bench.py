@@ -241,7 +241,7 @@ def structured_step(torch, A, wl, tab, steps=50):
     from paper_1611_08536_amd import drts
     S = drts.Solver(A, 1, wl.detectors, max_steps=steps + 4)
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    S.set_options(kernel=drts.KERNEL_STRUCTURED_F64SUM, tiles_per_chunk=16, grid=8 * cus)
+    S.set_options(kernel=drts.KERNEL_STRUCTURED_F64SUM, tiles_per_chunk=8, grid=16 * cus)
     S.run(tab, 2)
     S.profile(True)
     t = _timed(lambda: S.run(tab, steps), torch)

@@ -1597,8 +1597,10 @@ __global__ void __launch_bounds__(256) step_struct(StructArgs sa, const StepInst
 // kernel: mode 1 with the nearest FP32 values (mul, then add), mode 2 in FP64
 // (one fma per term), rounded once.
 // ---------------------------------------------------------------------------
+// Five waves per SIMD (96 VGPRs, a few spilled outside the row loop) beat
+// four without spills on the 128^3 layered workload.
 template <int MODE>
-__global__ void __launch_bounds__(256) step_struct_dm(StructArgs sa, const StepInst *__restrict__ insts,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) step_struct_dm(StructArgs sa, const StepInst *__restrict__ insts,
                                                        const WorkItem *__restrict__ work, int64_t n_work,
                                                        int xcd_remap, const int64_t *__restrict__ xcd_bounds)
 {
@@ -2264,7 +2266,10 @@ hipError_t launch_structured(const StructArgs &sa, const StepInst *insts_dev, co
     if (dm_mode ? (sa.seg_len != kStructDmSeg || sa.n_mat > kStructMatLds) : sa.seg_len != kStructSegLen)
         return hipErrorInvalidValue;
     const size_t dm = (size_t)(3 * (kStructDmSeg + 2) + kStructDmSeg) * kDirs * sizeof(float);
-    const dim3 g((unsigned)grid), b(256);
+    // workgroups past the work list would only start and exit; a multiple of
+    // the XCD count keeps the per-XCD walk available
+    const dim3 g((unsigned)std::min<int64_t>(grid, std::max<int64_t>((n_work + kXcds - 1) / kXcds * kXcds, kXcds))),
+        b(256);
     if (n_work > 0) {
         if (value_f64) {
             hipLaunchKernelGGL((step_struct<double, 0>), g, b, 0, stream, sa, insts_dev, work_dev, n_work,
