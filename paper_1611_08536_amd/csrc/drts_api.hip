@@ -125,7 +125,7 @@ struct drts_solver {
     int64_t n_tiles = 0, n_chunks = 0, n_xchunks = 0;
     int64_t t_host = 0;
 
-    Buffer buf0, buf1, ctl_t, ctl_E, ctl_M, ctl_abs, t_end, partials, xcd_bounds, xrows, xirr, xsrc, xdet, ddet_ptr, ddet_row,
+    Buffer buf0, buf1, ctl_t, ctl_E, ctl_M, ctl_abs, t_end, partials, xcd_bounds, xrows, xirr, xsrc, xdet, zrows, ddet_ptr, ddet_row,
         ddet_F, pull_bits, esc_base;
     Buffer ser_tot, ser_det, ser_exp, ser_abs_exp, amp, smax;
     Buffer src_tile, src_row, src_id, src_rhs, src_w;
@@ -268,21 +268,33 @@ void structured_xrows(const Model &M, std::vector<int64_t> *rows, std::vector<in
     k.push_back(n_irr);
 }
 
-// Rows the many-rhs push kernel leaves to the pull kernel: irregular rows,
-// rows holding a source or a detector entry (escape rows included), and state
-// rows that take no plain move (upstream voxel outside the grid or across an
-// index change).  Ascending, with each row's range of the irregular-move list;
-// and per voxel the offset of its first escape row.
+// Rows the many-rhs push kernel leaves to the pull kernel (marked in *bits):
+// irregular rows, rows holding a source or a detector entry (escape rows
+// included), and state rows that take no plain move (upstream voxel outside
+// the grid or across an index change).  Those of them that take no move at
+// all and no source (their value is zero; a detector entry adds nothing) go
+// to *zero; the others to *rows, ascending, with each row's range of the
+// irregular-move list.  And per voxel the offset of its first escape row.
 void structured_mm_pull(const Model &M, const std::vector<SourceEntry> &srcs, const std::vector<DetEntry> &dets,
                         std::vector<uint32_t> *bits, std::vector<int64_t> *rows, std::vector<int64_t> *irr,
-                        std::vector<int32_t> *esc_base)
+                        std::vector<int64_t> *zero, std::vector<int32_t> *esc_base)
 {
     std::vector<uint32_t> &b = *bits;
-    b.assign((size_t)((M.n_rows + 31) / 32), 0u);
+    const size_t words = (size_t)((M.n_rows + 31) / 32);
+    b.assign(words, 0u);
+    std::vector<uint32_t> full(words, 0u);   // rows with an irregular move or a source
     auto mark = [&](int64_t r) { b[(size_t)(r >> 5)] |= 1u << (r & 31); };
-    for (int64_t r : M.irr_row) mark(r);
-    for (const SourceEntry &e : srcs) mark(e.row);
+    auto mark_full = [&](int64_t r) { full[(size_t)(r >> 5)] |= 1u << (r & 31); };
+    for (int64_t r : M.irr_row) {
+        mark(r);
+        mark_full(r);
+    }
+    for (const SourceEntry &e : srcs) {
+        mark(e.row);
+        mark_full(e.row);
+    }
     for (const DetEntry &e : dets) mark(e.row);
+    std::vector<uint32_t> noplain(words, 0u);
     for (int z = 0; z < M.nz; ++z)
         for (int y = 0; y < M.ny; ++y)
             for (int x = 0; x < M.nx; ++x) {
@@ -295,7 +307,11 @@ void structured_mm_pull(const Model &M, const std::vector<SourceEntry> &srcs, co
                         const int64_t u = ux + (int64_t)M.nx * (uy + (int64_t)M.ny * uz);
                         plain = M.index[M.mat_of_voxel[(size_t)u]] == nw;
                     }
-                    if (!plain) mark(kDirs * w + m);
+                    if (!plain) {
+                        const int64_t r = kDirs * w + m;
+                        mark(r);
+                        noplain[(size_t)(r >> 5)] |= 1u << (r & 31);
+                    }
                 }
             }
     // row k's irregular moves are entries irr[k] .. irr[k+1]-1: irr[k] is the
@@ -304,9 +320,15 @@ void structured_mm_pull(const Model &M, const std::vector<SourceEntry> &srcs, co
     // rows that are not irregular)
     rows->clear();
     irr->clear();
+    zero->clear();
     size_t k = 0;
     for (int64_t r = 0; r < M.n_rows; ++r) {
-        if (!((b[(size_t)(r >> 5)] >> (r & 31)) & 1u)) continue;
+        const uint32_t bit = 1u << (r & 31);
+        if (!(b[(size_t)(r >> 5)] & bit)) continue;
+        if ((noplain[(size_t)(r >> 5)] & bit) && !(full[(size_t)(r >> 5)] & bit)) {
+            zero->push_back(r);
+            continue;
+        }
         while (k < M.irr_row.size() && M.irr_row[k] < r) ++k;
         rows->push_back(r);
         irr->push_back((int64_t)k);
@@ -437,15 +459,24 @@ int prepare(drts_solver *S)
             S->n_tiles = (nvox + kStructVoxPerChunk - 1) / kStructVoxPerChunk;
             std::vector<uint32_t> pb;
             std::vector<int32_t> eb;
-            structured_mm_pull(A.model, S->srcs, S->dets, &pb, &xr, &xk, &eb);
+            std::vector<int64_t> zr;
+            structured_mm_pull(A.model, S->srcs, S->dets, &pb, &xr, &xk, &zr, &eb);
             if ((rc = upload_vec(dev, S->pull_bits, pb))) return rc;
             if ((rc = upload_vec(dev, S->esc_base, eb))) return rc;
+            if ((rc = upload_vec(dev, S->zrows, zr))) return rc;
             sa.pull_bits = S->pull_bits.as<uint32_t>();
             sa.esc_base = S->esc_base.as<int32_t>();
-            S->n_xchunks = ((int64_t)xr.size() + kStructMmXRows - 1) / kStructMmXRows;
+            sa.zrows = S->zrows.as<int64_t>();
+            sa.n_zrows = (int64_t)zr.size();
+            // the pull kernel's workgroups: its row items, or the zero rows
+            // (kStructMmXRows per workgroup) if those are more
+            S->n_xchunks = std::max(((int64_t)xr.size() + kStructMmXRows - 1) / kStructMmXRows,
+                                    (sa.n_zrows + kStructMmXRows - 1) / kStructMmXRows);
         } else {
             const int mode = structured_mode(S);
             bounds = structured_bounds(A.model, &sa, (mode == 1 || mode == 2) ? kStructDmSeg : kStructSegLen);
+            sa.zrows = nullptr;
+            sa.n_zrows = 0;
             S->n_tiles = (int64_t)bounds.size() - 1;
             structured_xrows(A.model, &xr, &xk);
             S->n_xchunks = ((int64_t)xr.size() + kStructXRows - 1) / kStructXRows;

@@ -2102,6 +2102,11 @@ __global__ void __launch_bounds__(256) step_struct_mm_x(StructArgs sa, const Ste
     const int64_t n_items = (sa.n_xrows + XR - 1) / XR;
     const int64_t nc = I.n_chunks;
     double *my_det = s_det + (int64_t)wave * nd * 64;
+    // rows that take no move and no source: zero (a wave per row, the lanes
+    // write its columns); they add nothing to the sums
+    if (active)
+        for (int64_t k = (int64_t)blockIdx.x * NW + wave; k < sa.n_zrows; k += (int64_t)gridDim.x * NW)
+            Y[gp(sa.zrows)[k] * nrhs + lane] = 0.0f;
     // one set of partials per workgroup (chunk chunk_base + blockIdx.x), over a
     // fixed walk of the work items
     for (int d = 0; d < nd; ++d) my_det[d * 64 + lane] = 0.0;
@@ -2317,7 +2322,7 @@ hipError_t launch_structured_mm(const StructArgs &sa, const StepInst *insts_dev,
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (sa.n_xrows > 0) {
+    if (sa.n_xrows > 0 || sa.n_zrows > 0) {
         const dim3 gx((unsigned)sa.mm_pull_grid);
         const size_t lds = (size_t)4 * n_det * 64 * sizeof(double);
         if (mode == 2)

@@ -3,7 +3,8 @@ configuration the benchmark times, checked through properties that hold at
 any size (the single-rhs step they are compared with is itself held to the
 FP64 oracle at full size by the 128^3 layered tests):
   - 96^3 slab, 64 right-hand sides: sampled SpMM columns equal the single-rhs
-    runs of their own sources, bit for bit (state, exponents, series);
+    runs of their own sources, bit for bit (state, exponents, series), and
+    sampled matrix-free columns equal the single-rhs matrix-free runs;
   - 256 media of edges 16..64 in one batch: sampled members equal the same
     solver run alone, bit for bit.
 """
@@ -33,6 +34,35 @@ def test_c3_full_spmm_columns_equal_single_rhs_runs():
             s.rhs = 0
         w.n_rhs = 1
         one = solve.run(w, n_steps=steps, matrix=A)
+        assert np.array_equal(out["x"][:, j], one["x"][:, 0]), j
+        assert out["x_exp"][j] == one["x_exp"][0]
+        assert np.array_equal(out["exp2"][:, j], one["exp2"][:, 0])
+        assert np.allclose(out["tot"][:, :, j], one["tot"][:, :, 0], rtol=1e-13, atol=0)
+        assert np.allclose(out["det"][:, :, j], one["det"][:, :, 0], rtol=1e-13, atol=0)
+        one["solver"].close()
+    out["solver"].close()
+    A.close()
+
+
+def test_c3_full_matrix_free_columns_equal_single_rhs_runs():
+    """The matrix-free step for 64 right-hand sides (push and pull kernels,
+    FP64 row sums) at full C3 size in the launch shape the benchmark times:
+    sampled columns equal the single-rhs matrix-free runs of their own
+    sources bit for bit (state, exponents), series to 1e-13."""
+    import torch
+    steps = 12
+    wl = W.c3(n_steps=steps)
+    A = drts.Matrix(wl.medium, wl.value_type, wl.rounding, wl.n_ref)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    opts = {"kernel": drts.KERNEL_STRUCTURED_F64SUM, "grid": 16 * cus}
+    out = solve.run(wl, n_steps=steps, matrix=A, options=opts)
+    for j in (0, 40, 63):
+        w = copy.copy(wl)
+        w.sources = [copy.copy(s) for s in wl.sources if s.rhs == j]
+        for s in w.sources:
+            s.rhs = 0
+        w.n_rhs = 1
+        one = solve.run(w, n_steps=steps, matrix=A, options={"kernel": drts.KERNEL_STRUCTURED_F64SUM})
         assert np.array_equal(out["x"][:, j], one["x"][:, 0]), j
         assert out["x_exp"][j] == one["x_exp"][0]
         assert np.array_equal(out["exp2"][:, j], one["exp2"][:, 0])
