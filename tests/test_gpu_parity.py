@@ -315,6 +315,13 @@ def _struct_workload(name):
         return wl
     if name == "c1_f64":
         return W.c1(n=12)
+    if name == "long_lines_nearest":
+        # x-lines of 70 voxels: a full 64-voxel tile and a ragged 6-voxel one
+        med = W.Medium(70, 6, 5, 0.1, [W.Material(5, 0.1, 0.8, 1.33), W.Material(15, 0.2, 0.9, 1.45)],
+                       np.repeat(np.array([0, 0, 1, 1, 0], dtype=np.uint8)[:, None, None], 6, 1).repeat(70, 2),
+                       "voxels", "vacuum")
+        return W.Workload("long_lines", med, [W.point_source(66, 3, 0), W.point_source(5, 2, 0)],
+                          [W.face_escape_detector(med, "top")], 60, 1, "f32", "nearest", 1.33)
     med = W.layered(9, [W.Material(5, 0.1, 0.8, 1.33), W.Material(15, 0.2, 0.9, 1.45),
                         W.Material(10, 0.1, 0.3, 1.4)], bc="reflect")
     rnd = "nearest" if name.endswith("nearest") else "dither"
@@ -322,7 +329,7 @@ def _struct_workload(name):
 
 
 @pytest.mark.parametrize("wl_name", ["c2_dither", "c2_nearest", "c5_sphere", "c5_sphere_nearest", "c1_f64",
-                                     "reflect", "reflect_nearest"])
+                                     "reflect", "reflect_nearest", "long_lines_nearest"])
 def test_structured_equals_csr(wl_name):
     """The matrix-free kernel re-derives every entry exactly as assembled:
     states and step exponents equal the CSR run bit for bit (nearest values go
