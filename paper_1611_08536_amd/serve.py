@@ -94,8 +94,8 @@ def serve(requests, budget_bytes: int, quantum: int = 50, max_active: int = 256,
     finally:
         if pool is not None:
             pool.shutdown(wait=True)
+        S.close()
     wall = time.perf_counter() - t0
-    S.close()
     out = _summary([done_at[r] - arrival_of[r] for r in done_at], wall, len(requests))
     out["peak_active"] = peak_active
     if keep_results:
