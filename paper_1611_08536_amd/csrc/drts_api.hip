@@ -125,7 +125,8 @@ struct drts_solver {
     int64_t n_tiles = 0, n_chunks = 0, n_xchunks = 0;
     int64_t t_host = 0;
 
-    Buffer buf0, buf1, ctl_t, ctl_E, ctl_M, ctl_abs, t_end, partials, xcd_bounds, xrows, xirr, xsrc, xdet, zrows, ddet_ptr, ddet_row,
+    Buffer buf0, buf1, ctl_t, ctl_E, ctl_M, ctl_abs, t_end, partials, xcd_bounds, xrows, xirr, xsrc, xdet, zrows, xdrng,
+        ddet_ptr, ddet_row,
         ddet_F, pull_bits, esc_base;
     Buffer ser_tot, ser_det, ser_exp, ser_abs_exp, amp, smax;
     Buffer src_tile, src_row, src_id, src_rhs, src_w;
@@ -507,6 +508,24 @@ int prepare(drts_solver *S)
             if ((rc = upload_vec(dev, S->ddet_ptr, ptr))) return rc;
             if ((rc = upload_vec(dev, S->ddet_row, row))) return rc;
             if ((rc = upload_vec(dev, S->ddet_F, F))) return rc;
+            if (!spmm_of(S)) {
+                // per work item of the second kernel (kStructXRows listed rows) and
+                // detector: the range of the detector's entries whose rows lie in
+                // the item's row span
+                const int64_t n_items = ((int64_t)xr.size() + kStructXRows - 1) / kStructXRows;
+                std::vector<int64_t> rng((size_t)std::max<int64_t>(n_items * S->n_det * 2, 1), 0);
+                for (int d = 0; d < S->n_det; ++d) {
+                    const auto b0 = row.begin() + ptr[(size_t)d], b1 = row.begin() + ptr[(size_t)d + 1];
+                    for (int64_t j = 0; j < n_items; ++j) {
+                        const int64_t ra = xr[(size_t)(j * kStructXRows)];
+                        const int64_t rb = xr[(size_t)std::min<int64_t>((j + 1) * kStructXRows, (int64_t)xr.size()) - 1];
+                        rng[(size_t)((j * S->n_det + d) * 2)] = std::lower_bound(b0, b1, ra) - row.begin();
+                        rng[(size_t)((j * S->n_det + d) * 2 + 1)] = std::upper_bound(b0, b1, rb) - row.begin();
+                    }
+                }
+                if ((rc = upload_vec(dev, S->xdrng, rng))) return rc;
+                sa.xdrng = S->xdrng.as<int64_t>();
+            }
             sa.ddet_ptr = S->ddet_ptr.as<int64_t>();
             sa.ddet_row = S->ddet_row.as<int64_t>();
             sa.ddet_F = S->ddet_F.as<double>();

@@ -118,6 +118,7 @@ struct StructArgs {
     const int64_t *xirr;       // [n_xrows + 1]: row k's irregular moves are xirr[k] .. xirr[k+1]-1
     const int32_t *xsrc;       // [n_xrows]: first source entry at or after row k (row-sorted list)
     const int32_t *xdet;       // [n_xrows]: first detector entry at or after row k
+    const int64_t *xdrng;      // one rhs: [work item][detector][2], the item's range of the detector's entries
     const int64_t *zrows;      // many rhs: rows with no move and no source (value zero), written by the pull kernel
     int64_t n_zrows;
     int64_t n_xrows;

@@ -1872,34 +1872,16 @@ __global__ void __launch_bounds__(256) step_struct_x(StructArgs sa, const StepIn
         }
         __syncthreads();
         // detectors: per detector, its entries whose rows lie in this item's
-        // row span (a range of its row-sorted list), shared by all threads,
-        // then a fixed-order block sum; entries of rows not in the item
-        // belong to step_struct
+        // row span (a range of its row-sorted list, found on the host),
+        // shared by all threads, then a fixed-order block sum; entries of rows
+        // not in the item belong to the tile kernel
         const int64_t nc = I.n_chunks, c = sa.chunk_base + j;
         GLB double *part = gpw(I.partials);
         {
-            const int64_t ra = s_r[0], rb = s_r[n - 1];
-            const GLB int64_t *dp = gp(sa.ddet_ptr);
             const GLB int64_t *drow = gp(sa.ddet_row);
             const GLB double *dF = gp(sa.ddet_F);
             for (int d = 0; d < I.n_det; ++d) {
-                int64_t lo = dp[d], hi = dp[d + 1];
-                {
-                    int64_t a = lo, b = hi;
-                    while (a < b) {
-                        const int64_t mid = (a + b) >> 1;
-                        if (drow[mid] < ra) a = mid + 1;
-                        else b = mid;
-                    }
-                    lo = a;
-                    b = hi;
-                    while (a < b) {
-                        const int64_t mid = (a + b) >> 1;
-                        if (drow[mid] <= rb) a = mid + 1;
-                        else b = mid;
-                    }
-                    hi = a;
-                }
+                const int64_t lo = gp(sa.xdrng)[(j * I.n_det + d) * 2], hi = gp(sa.xdrng)[(j * I.n_det + d) * 2 + 1];
                 double acc = 0.0;
                 for (int64_t e2 = lo + tid; e2 < hi; e2 += NT) {
                     const int64_t row = drow[e2];
