@@ -139,7 +139,7 @@ struct StructArgs {
 };
 constexpr int kStructSegLen = 16;         // voxels per tile of the gather kernel (modes 0 and 3)
 constexpr int kStructDmSeg = 64;          // voxels per tile of the direction-major kernel (modes 1 and 2)
-constexpr int kStructXRows = 1024;
+constexpr int kStructXRows = 256;     // rows per work item of the single-rhs second kernel
 constexpr int kStructMatLdsHost = 8;      // materials the single-rhs direction-major kernel takes
 constexpr int kStructVoxPerChunk = 64;   // voxels per work item of the push kernel
 constexpr int kStructMmXRows = 64;       // rows per work item of the many-rhs pull kernel
