@@ -333,8 +333,8 @@ def _struct_workload(name):
 def test_structured_equals_csr(wl_name):
     """The matrix-free kernel re-derives every entry exactly as assembled:
     states and step exponents equal the CSR run bit for bit (nearest values go
-    through the LDS halo path, FP64 and dithered values through the gather
-    path)."""
+    through the direction-major kernel, FP64 and dithered values through the
+    gather kernel)."""
     wl = _struct_workload(wl_name)
     n = 45
     a = solve.run(wl, n_steps=n)

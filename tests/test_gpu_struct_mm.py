@@ -70,8 +70,9 @@ def _reflecting_many(n=10, k=3, n_steps=30):
 
 
 def _ten_layers_many(n=20, k=3, n_steps=30):
-    """Ten layers, ten materials (more than the single-rhs LDS halo holds, so
-    the single-rhs runs take the global-gather kernel) and k top-face sources."""
+    """Ten layers, ten materials (more than the single-rhs direction-major
+    kernel takes, so the single-rhs runs take the gather kernel) and k
+    top-face sources."""
     mats = [W.Material(4.0 + j, 0.01 * (j + 1), 0.7 + 0.02 * j, 1.33 + 0.01 * (j % 3)) for j in range(10)]
     med = W.layered(n, mats)
     srcs = [W.point_source(3 + 5 * j, 4 + 3 * j, 0, kind="gaussian", fwhm_fs=100.0 + 50.0 * j, rhs=j)
