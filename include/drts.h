@@ -236,7 +236,10 @@ typedef struct {
                              tile's entries load before the current tile's
                              gathers), DRTS_SPMV_LDS (as DRTS_SPMV_ROW, the
                              values loaded straight into LDS, not through
-                             registers; FP32 values only) */
+                             registers; FP32 values only),
+                             DRTS_SPMV_WAVE_LDS (as DRTS_SPMV_WAVE with the
+                             values through LDS and the chunk's tile bounds
+                             staged once; FP32 values, rows_per_tile 64) */
     int32_t queue;        /* one rhs only: 1 = workgroups take chunks from a
                              device counter (dynamic balance), 0 = fixed walk */
 } drts_options_t;
@@ -249,6 +252,7 @@ typedef struct {
 #define DRTS_SPMV_WAVE 5
 #define DRTS_SPMV_WAVE_PIPE 6
 #define DRTS_SPMV_LDS 7
+#define DRTS_SPMV_WAVE_LDS 8
 
 /* Creates the time-stepping state for n_rhs right-hand sides sharing A: the
  * state (zero), detectors, series buffers for max_steps steps.  n_rhs > 1

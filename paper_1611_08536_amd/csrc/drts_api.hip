@@ -758,7 +758,7 @@ int launch_one(drts_solver *S, hipStream_t stream)
     } else {
     e = launch_step(S->inst_dev.as<StepInst>(), S->work_dev.as<WorkItem>(), S->n_chunks, 1, S->n_rhs,
                                A.model.value_type == DRTS_F64, A.rp64 ? 1 : 0, spmm ? 1 : 0, S->grid,
-                               (S->opt.xcd_remap ? 1 : 0) | ((S->opt.variant & 7) << 1), S->xcd_bounds.as<int64_t>(),
+                               (S->opt.xcd_remap ? 1 : 0) | ((S->opt.variant & 15) << 1), S->xcd_bounds.as<int64_t>(),
                                S->opt.rows_per_tile, S->n_det, queue, stream);
     }
     if (e != hipSuccess) return set_error(DRTS_E_HIP, "step launch failed: %s", hipGetErrorString(e));
@@ -851,13 +851,13 @@ int check_options(const drts_solver *S, const drts_options_t *o)
     }
     if (o->queue != 0 && o->queue != 1) return set_error(DRTS_E_INVALID, "queue must be 0 or 1");
     if (o->xcd_remap < 0 || o->xcd_remap > 2) return set_error(DRTS_E_INVALID, "xcd_remap must be 0, 1 or 2");
-    if (o->variant < DRTS_SPMV_ROW || o->variant > DRTS_SPMV_LDS)
+    if (o->variant < DRTS_SPMV_ROW || o->variant > DRTS_SPMV_WAVE_LDS)
         return set_error(DRTS_E_INVALID, "unknown variant %d", o->variant);
-    if (o->variant == DRTS_SPMV_LDS && S->A->m.model.value_type == DRTS_F64)
-        return set_error(DRTS_E_INVALID, "the LDS variant takes FP32 values");
-    if ((o->variant == DRTS_SPMV_WAVE || o->variant == DRTS_SPMV_WAVE_PIPE) && S->n_rhs == 1 &&
-        o->kernel == DRTS_KERNEL_CSR && o->rows_per_tile != 64)
-        return set_error(DRTS_E_INVALID, "the wave variant takes rows_per_tile = 64");
+    if ((o->variant == DRTS_SPMV_LDS || o->variant == DRTS_SPMV_WAVE_LDS) && S->A->m.model.value_type == DRTS_F64)
+        return set_error(DRTS_E_INVALID, "the LDS variants take FP32 values");
+    if ((o->variant == DRTS_SPMV_WAVE || o->variant == DRTS_SPMV_WAVE_PIPE || o->variant == DRTS_SPMV_WAVE_LDS) &&
+        S->n_rhs == 1 && o->kernel == DRTS_KERNEL_CSR && o->rows_per_tile != 64)
+        return set_error(DRTS_E_INVALID, "the wave variants take rows_per_tile = 64");
     if (o->grid < 0 || o->graph_steps < 0 || o->graph_steps > 4096)
         return set_error(DRTS_E_INVALID, "bad grid or graph_steps");
     return DRTS_OK;
@@ -1265,7 +1265,7 @@ int batch_launch(drts_batch *B, int64_t n_work, int n_inst, int rows_per_tile, h
     const int grid = device_cu_count() * 16;
     int32_t *queue = S0->opt.queue ? B->queue.as<int32_t>() : nullptr;
     hipError_t e = launch_step(B->inst_dev.as<StepInst>(), B->work_dev.as<WorkItem>(), n_work, n_inst, 1, 0,
-                               S0->A->m.rp64 ? 1 : 0, 0, grid, (S0->opt.variant & 7) << 1, nullptr, rows_per_tile, 0,
+                               S0->A->m.rp64 ? 1 : 0, 0, grid, (S0->opt.variant & 15) << 1, nullptr, rows_per_tile, 0,
                                queue, stream);
     if (e != hipSuccess) return set_error(DRTS_E_HIP, "batch step launch failed: %s", hipGetErrorString(e));
     e = launch_finalize(B->inst_dev.as<StepInst>(), n_inst, 1, 0, queue, stream);
@@ -1467,9 +1467,10 @@ int drts_autotune(drts_solver_t *S, const char *cache_path, drts_options_t *chos
         for (int c : chunk_opts)
             for (int g : grid_mult)
                 for (int x = 0; x < 3; ++x)
-                    for (int pl = 0; pl <= (spmm ? 0 : DRTS_SPMV_LDS); ++pl) {
-                        if ((pl == DRTS_SPMV_WAVE || pl == DRTS_SPMV_WAVE_PIPE) && r != 64) continue;
-                        if (pl == DRTS_SPMV_LDS && A.model.value_type == DRTS_F64) continue;
+                    for (int pl = 0; pl <= (spmm ? 0 : DRTS_SPMV_WAVE_LDS); ++pl) {
+                        if ((pl == DRTS_SPMV_WAVE || pl == DRTS_SPMV_WAVE_PIPE || pl == DRTS_SPMV_WAVE_LDS) && r != 64)
+                            continue;
+                        if ((pl == DRTS_SPMV_LDS || pl == DRTS_SPMV_WAVE_LDS) && A.model.value_type == DRTS_F64) continue;
                         drts_options_t o = S->opt;
                         o.rows_per_tile = r;
                         o.tiles_per_chunk = spmm ? c * 32 : c;

@@ -242,7 +242,7 @@ __device__ __forceinline__ void issue_tile(TileRegs<VT, IT, U> &T, const GLB IT 
     // tiles or to the zero padding: their columns are valid state indices
     // and their products land in LDS slots no row of this tile reads.
     T.a0 = b & ~(IT)3;
-    const uint32_t last = (uint32_t)(((e - 1 - T.a0) >> 2) << 2);
+    const uint32_t last = e > T.a0 ? (uint32_t)(((e - 1 - T.a0) >> 2) << 2) : 0u;   // an empty tile re-reads its first quad
     const uint32_t span = (uint32_t)(e - T.a0);
 #pragma unroll
     for (int k = 0; k < U; ++k) {
@@ -323,7 +323,7 @@ __device__ __forceinline__ void issue_tile_l(TileRegsL<IT, U> &T, const GLB IT *
     // quads past the tile re-read its last quad (in bounds, as in the quad
     // layout) into slots no row of the tile reads
     T.a0 = b & ~(IT)3;
-    const uint32_t last = (uint32_t)(((e - 1 - T.a0) >> 2) << 2);
+    const uint32_t last = e > T.a0 ? (uint32_t)(((e - 1 - T.a0) >> 2) << 2) : 0u;   // an empty tile re-reads its first quad
     const uint32_t span = (uint32_t)(e - T.a0);
     const int64_t base = (int64_t)T.a0;
     const uint64_t left = (uint64_t)(nnz + 4 - base);
@@ -917,6 +917,239 @@ __global__ void __launch_bounds__(256) step_spmv_wave(const StepInst *__restrict
         __syncthreads();
         GLB double *part = gpw(I.partials);
         const int tid = threadIdx.x;
+        if (tid < 4) {
+            double a = s_wred[tid][0];
+            for (int w = 1; w < NW; ++w) a = (tid == 3) ? fmax(a, s_wred[tid][w]) : a + s_wred[tid][w];
+            part[(int64_t)tid * nc + c] = a;
+        }
+        for (int d = tid; d < nd; d += 256) {
+            const double a = ((s_wdet[0][d] + s_wdet[1][d]) + s_wdet[2][d]) + s_wdet[3][d];
+            part[(int64_t)(kSlotDet + d) * nc + c] = a;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// SpMV step, one wave per 64-row tile, FP32 values straight into the wave's
+// LDS slice.  The chunk's tile bounds (row_ptr at tile starts) and its
+// per-tile source and detector offsets go to LDS once per chunk; then every
+// wave carries its own tiles (every fourth of the chunk) through all phases
+// without a workgroup barrier: its rows' bounds, the column quads into
+// registers and the value quads into its LDS slice in one round trip, the
+// gathers of x, the products in place (a lane multiplies the quads it
+// loaded), the row sums in column order, the epilogue.  The waves meet once
+// per chunk to combine their FP64 partials in a fixed order.
+// ---------------------------------------------------------------------------
+template <typename IT>
+__global__ void __launch_bounds__(256) step_spmv_wl(const StepInst *__restrict__ insts,
+                                                     const WorkItem *__restrict__ work, int64_t n_work,
+                                                     int xcd_remap, const int64_t *__restrict__ xcd_bounds)
+{
+    constexpr int NW = 4, U = 7, R = kWaveTileRows;
+    constexpr int CAPW = 4 * U * 64;     // entries one wave stages (28 per row)
+    __shared__ __attribute__((aligned(16))) float s_prod[NW][CAPW];
+    __shared__ float s_yw[NW][64];
+    __shared__ IT s_tb[kChunkMax + 1];
+    __shared__ int32_t s_src[kChunkMax + 1];
+    __shared__ int32_t s_det[kChunkMax + 1];
+    __shared__ double s_abs[kMatMax];
+    __shared__ double s_wred[4][NW];
+    // the waves' detector partials reuse the product slices once every wave
+    // has finished its tiles
+    static_assert(sizeof(double) * NW * kFinDetMax <= sizeof(float) * NW * CAPW, "detector partials fit");
+    double (*s_wdet)[kFinDetMax] = reinterpret_cast<double (*)[kFinDetMax]>(&s_prod[0][0]);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    float *my_prod = s_prod[wave];
+    const Walk wk = walk_of(n_work, xcd_remap, xcd_bounds);
+    for (int64_t wi = wk.begin; wi < wk.end; wi += wk.stride) {
+        const WorkItem item = work[wi];
+        const StepInst &I = insts[item.inst];
+        const int64_t t = I.t[0];
+        if (t >= *I.t_end) continue;
+        const Scale sc = step_scale(I, 0, t);
+        const float scale = (float)ldexp(1.0, -sc.k);
+        const GLB IT *rp = gp((const IT *)I.row_ptr);
+        const GLB int32_t *col = gp(I.col);
+        const GLB float *val = gp((const float *)I.val);
+        const GLB float *x = gp((const float *)((t & 1) ? I.buf1 : I.buf0));
+        const __amdgpu_buffer_rsrc_t rx = make_rsrc((const void *)x, (uint64_t)I.n_rows * sizeof(float));
+        GLB float *y = gpw((float *)((t & 1) ? I.buf0 : I.buf1));
+        const GLB uint8_t *mat = gp(I.mat);
+        const int64_t n_rows = I.n_rows, n_states = I.n_states;
+        const int nd = I.n_det;
+        const int64_t tile0 = (int64_t)item.chunk * I.tiles_per_chunk;
+        const int ntc = (int)min((int64_t)I.tiles_per_chunk, I.n_tiles - tile0);
+        for (int j = tid; j <= ntc; j += 256) {
+            s_tb[j] = rp[min((tile0 + j) * R, n_rows)];
+            s_src[j] = gp(I.src_tile)[tile0 + j];
+            s_det[j] = gp(I.det_tile)[tile0 + j];
+        }
+        for (int q = tid; q < I.n_mat; q += 256) s_abs[q] = gp(I.absorb)[q];
+        __syncthreads();
+        double sN = 0.0, sE = 0.0, sA = 0.0;
+        double dsum[kFinDetMax / 64] = {0.0, 0.0, 0.0, 0.0};
+        float mx = 0;
+        for (int j = wave; j < ntc; j += NW) {
+            const int64_t r0 = (tile0 + j) * R;
+            const int nr = (int)min((int64_t)R, n_rows - r0);
+            const int64_t r = r0 + lane;
+            const bool own = lane < nr;
+            const IT b = s_tb[j], e = s_tb[j + 1];
+            IT mylo = 0, myhi = 0;
+            int q = 0;
+            if (own) {
+                mylo = rp[r];
+                myhi = rp[r + 1];
+                if (r < n_states) q = mat[r / kDirs];
+            }
+            float acc = 0;
+            if (e - b <= (IT)CAPW - 3) {
+                // quads past the tile re-read its last quad (an empty tile its
+                // first) into slots no row of the tile reads
+                const IT a0 = b & ~(IT)3;
+                const uint32_t last = e > a0 ? (uint32_t)(((e - 1 - a0) >> 2) << 2) : 0u;
+                const uint32_t span = (uint32_t)(e - a0);
+                const int64_t base = (int64_t)a0;
+                const uint64_t left = (uint64_t)(I.nnz + 4 - base);
+                const __amdgpu_buffer_rsrc_t rc = make_rsrc((const void *)(col + base), left * 4);
+                const __amdgpu_buffer_rsrc_t rv = make_rsrc((const void *)(val + base), left * 4);
+                i4 qc[U];
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    const uint32_t i = 4u * (uint32_t)(lane + 64 * k);
+                    const uint32_t o = i < span ? i : last;
+                    qc[k] = __builtin_amdgcn_raw_buffer_load_b128(rc, (int)(o * 4), 0, kStream);
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                        rv, (__attribute__((address_space(3))) void *)(my_prod + 4 * 64 * k), 16, (int)(o * 4), 0, 0,
+                        kStream);
+                }
+                float xv[U][4];
+#pragma unroll
+                for (int k = 0; k < U; ++k)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) xv[k][jj] = BufQuad<float>::gather(rx, qc[k][jj]);
+                // the values of this lane's quads are in LDS once every load of
+                // the lane has completed
+                __builtin_amdgcn_s_waitcnt(0);
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    f4 *slot = (f4 *)(my_prod + 4 * (lane + 64 * k));
+                    f4 v = *slot;
+                    v[0] = v[0] * xv[k][0];
+                    v[1] = v[1] * xv[k][1];
+                    v[2] = v[2] * xv[k][2];
+                    v[3] = v[3] * xv[k][3];
+                    *slot = v;
+                }
+                // the wave's own LDS writes, then its reads: in order within the wave
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (own) {
+                    IT jj = mylo;
+                    for (; jj + 4 <= myhi; jj += 4) {
+                        const float p0 = my_prod[jj - a0], p1 = my_prod[jj - a0 + 1];
+                        const float p2 = my_prod[jj - a0 + 2], p3 = my_prod[jj - a0 + 3];
+                        acc += p0;
+                        acc += p1;
+                        acc += p2;
+                        acc += p3;
+                    }
+                    for (; jj < myhi; ++jj) acc += my_prod[jj - a0];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            } else {
+                // long rows: passes of CAPW entries through the wave's slice
+                for (IT a = b & ~(IT)3; a < e; a += CAPW) {
+                    const IT cs = a < b ? b : a;
+                    const IT ce = (e - a < (IT)CAPW) ? e : a + (IT)CAPW;
+                    for (IT i = a + 4 * lane; i < ce; i += 4 * 64) {
+                        const i4 c4 = __builtin_nontemporal_load((const GLB i4 *)(col + i));
+                        Quad<float> v4;
+                        v4.load(val + i);
+#pragma unroll
+                        for (int jj = 0; jj < 4; ++jj) {
+                            const IT idx = i + jj;
+                            if (idx >= cs && idx < ce) my_prod[idx - a] = v4[jj] * x[c4[jj]];
+                        }
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    if (own) {
+                        const IT lo = mylo > cs ? mylo : cs;
+                        const IT hi = myhi < ce ? myhi : ce;
+                        for (IT jj = lo; jj < hi; ++jj) acc += my_prod[jj - a];
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                }
+            }
+            // epilogue: rescale, sources, store, FP64 totals
+            float v = acc * scale;
+            const int sb = s_src[j], se = s_src[j + 1];
+            if (own && sb < se) {
+                const GLB int64_t *srow = gp(I.src_row);
+                int e2 = lower_bound_rows<IT>(I.src_row, sb, se, r);
+                double s = 0.0;
+                bool any = false;
+                for (; e2 < se && srow[e2] == r; ++e2) {
+                    s += gp(I.src_w)[e2] * gp(I.amp)[t * I.n_src + gp(I.src_id)[e2]];
+                    any = true;
+                }
+                if (any) v += (float)ldexp(s, -sc.En);
+            }
+            if (own) {
+                y[r] = v;
+                if (r < n_states) {
+                    sN += (double)v;
+                    sA += s_abs[q] * (double)v;
+                    mx = v > mx ? v : mx;
+                } else {
+                    sE += (double)v;
+                }
+            }
+            const int db = s_det[j], de = s_det[j + 1];
+            if (db < de) {
+                s_yw[wave][lane] = v;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                // detector d is summed by lane d % 64 in register d / 64
+                for (int e2 = db; e2 < de; ++e2) {
+                    const int d = gp(I.det_id)[e2];
+                    if ((d & 63) == lane) {
+                        const double f = gp(I.det_F)[e2] * (double)s_yw[wave][gp(I.det_row)[e2] - r0];
+#pragma unroll
+                        for (int h = 0; h < kFinDetMax / 64; ++h)
+                            if ((d >> 6) == h) dsum[h] += f;
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+        }
+        // chunk partials: wave butterflies, then the waves in order
+        const int64_t nc = I.n_chunks, c = item.chunk;
+        const double wN = wave_sum(sN), wE = wave_sum(sE), wA = wave_sum(sA), wM = wave_max((double)mx);
+        if (lane == 0) {
+            s_wred[0][wave] = wN;
+            s_wred[1][wave] = wE;
+            s_wred[2][wave] = wA;
+            s_wred[3][wave] = wM;
+        }
+        __syncthreads();   // every wave is done with its product slice
+#pragma unroll
+        for (int h = 0; h < kFinDetMax / 64; ++h)
+            if (h * 64 + lane < nd) s_wdet[wave][h * 64 + lane] = dsum[h];
+        __syncthreads();
+        GLB double *part = gpw(I.partials);
         if (tid < 4) {
             double a = s_wred[tid][0];
             for (int w = 1; w < NW; ++w) a = (tid == 3) ? fmax(a, s_wred[tid][w]) : a + s_wred[tid][w];
@@ -2178,7 +2411,7 @@ hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int6
                                xcd_bounds);
     } else {
         const dim3 g1((unsigned)grid);
-        const int variant = (xcd_remap >> 1) & 7;
+        const int variant = (xcd_remap >> 1) & 15;
         const int remap = xcd_remap & 1;
 #define DRTS_SPMV1(VT, IT, NTV, RV, P, L) \
     hipLaunchKernelGGL((step_spmv<VT, IT, NTV, RV, P, L>), g1, dim3(NTV), 0, stream, insts_dev, work_dev, n_work, \
@@ -2193,6 +2426,16 @@ hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int6
         else DRTS_SPMV1(VT, IT, RV, RV, 0, 0);                       \
     } while (0)
         const int nt = rows_per_tile <= 64 ? 64 : (rows_per_tile <= 128 ? 128 : 256);
+        if (variant == 8 && !value_f64) {
+            // tiles of kWaveTileRows rows, one wave each, values through LDS
+            if (rp64)
+                hipLaunchKernelGGL((step_spmv_wl<int64_t>), g1, dim3(256), 0, stream, insts_dev, work_dev, n_work,
+                                   remap, xcd_bounds);
+            else
+                hipLaunchKernelGGL((step_spmv_wl<int32_t>), g1, dim3(256), 0, stream, insts_dev, work_dev, n_work,
+                                   remap, xcd_bounds);
+            return hipGetLastError();
+        }
         if (variant == 5 || variant == 6) {
             // tiles of kWaveTileRows rows, one wave each
 #define DRTS_WAVE(VT, IT)                                                                                          \

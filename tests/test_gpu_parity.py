@@ -172,8 +172,8 @@ def test_spmv_variants_give_identical_states(rpt):
     of the per-wave partial sums."""
     wl = W.c2(n=18)
     ref = _state_and_series(wl, 30, options={"rows_per_tile": rpt, "variant": 0})
-    for v in (1, 2, 3, 4, 5, 6, 7):
-        if v in (5, 6) and rpt != 64:
+    for v in (1, 2, 3, 4, 5, 6, 7, 8):
+        if v in (5, 6, 8) and rpt != 64:
             continue
         got = _state_and_series(wl, 30, options={"rows_per_tile": rpt, "variant": v})
         assert np.array_equal(ref[0], got[0]) and np.array_equal(ref[1], got[1]), v
@@ -294,7 +294,9 @@ def test_errors_are_reported():
     M64 = drts.Matrix(wl.medium, "f64")
     S64 = drts.Solver(M64, 1, wl.detectors, max_steps=5)
     with pytest.raises(drts.DrtsError):
-        S64.set_options(variant=7)          # the LDS layout takes FP32 values
+        S64.set_options(variant=7)          # the LDS layouts take FP32 values
+    with pytest.raises(drts.DrtsError):
+        S64.set_options(variant=8, rows_per_tile=64)
     bad = W.homogeneous(4, W.Material(1.0, 0.1, 1.5, 1.4))
     with pytest.raises(drts.DrtsError) as ei:
         drts.Matrix(bad)
