@@ -23,6 +23,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "drts_oracle.c")
 _LIB = os.path.join(_HERE, "_drts_oracle.so")
+# tests/test_oracle_mutants.py points this at a build of a deliberately
+# broken copy of drts_oracle.c, to show that the pins catch the mistake
+_LIB_OVERRIDE = os.environ.get("DRTS_ORACLE_LIB")
 _lock = threading.Lock()
 _lib = None
 
@@ -57,7 +60,7 @@ def _load():
     with _lock:
         if _lib is not None:
             return _lib
-        lib = C.CDLL(build())
+        lib = C.CDLL(_LIB_OVERRIDE if _LIB_OVERRIDE else build())
         P = C.c_void_p
         i64, i32, dbl = C.c_int64, C.c_int32, C.c_double
         lib.or_build.restype = P
