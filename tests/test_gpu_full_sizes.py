@@ -6,7 +6,9 @@ FP64 oracle at full size by the 128^3 layered tests):
     runs of their own sources, bit for bit (state, exponents, series), and
     sampled matrix-free columns equal the single-rhs matrix-free runs;
   - 256 media of edges 16..64 in one batch: sampled members equal the same
-    solver run alone, bit for bit.
+    solver run alone, bit for bit;
+  - a medium beyond 2^31 nonzeros (int64 row pointers): CSR steps equal the
+    exact matrix-free steps bit for bit.
 """
 import copy
 
@@ -70,6 +72,27 @@ def test_c3_full_matrix_free_columns_equal_single_rhs_runs():
         assert np.allclose(out["det"][:, :, j], one["det"][:, :, 0], rtol=1e-13, atol=0)
         one["solver"].close()
     out["solver"].close()
+    A.close()
+
+
+def test_int64_row_pointers_equal_matrix_free():
+    """A 165^3 three-layer medium has more than 2^31 nonzeros, so its CSR
+    takes int64 row pointers (assembly and step kernels of that width): its
+    steps in the launch shape of the benchmark equal the exact matrix-free
+    steps (nearest-rounded values), which never read the CSR, bit for bit."""
+    steps = 6
+    wl = W.c2(n=165, n_steps=steps, rounding="nearest")
+    A = drts.Matrix(wl.medium, wl.value_type, wl.rounding, wl.n_ref)
+    assert A.nnz > 2 ** 31 - 1, A.nnz
+    csr = solve.run(wl, n_steps=steps, matrix=A)
+    mf = solve.run(wl, n_steps=steps, matrix=A, options={"kernel": drts.KERNEL_STRUCTURED})
+    assert np.array_equal(csr["x"], mf["x"]) and np.array_equal(csr["x_exp"], mf["x_exp"])
+    assert np.array_equal(csr["exp2"], mf["exp2"])
+    assert np.allclose(csr["tot"], mf["tot"], rtol=1e-13, atol=0)
+    assert np.allclose(csr["det"], mf["det"], rtol=1e-13, atol=0)
+    assert (csr["tot"][:, 0, 0] > 0).all()
+    csr["solver"].close()
+    mf["solver"].close()
     A.close()
 
 
