@@ -1614,16 +1614,29 @@ __device__ __forceinline__ VT struct_row_a(const StructArgs &sa, int64_t r, cons
         int64_t k1 = k;
         while (k1 < kend && irr_vox[k1] == ug) ++k1;
         const int q = mat[ug];
-        for (int n = 0; n < kDirs; ++n) {
-            double a = 0.0;
-            for (int64_t kk = k; kk < k1; ++kk) {
-                const double c = Cd[(q * kDirs + irr_dir[kk]) * kDirs + n];
-                if (c != 0.0) a = a + irr_f[kk] * c;
+        // all loads of the group are independent of each other: x of ug and
+        // each move's block row are requested at once, and the merged
+        // coefficient of column n sums the moves in list order as before
+        VT xv[kDirs];
+#pragma unroll
+        for (int n = 0; n < kDirs; ++n) xv[n] = xa(kDirs * ug + n);
+        double a[kDirs];
+#pragma unroll
+        for (int n = 0; n < kDirs; ++n) a[n] = 0.0;
+        for (int64_t kk = k; kk < k1; ++kk) {
+            const double f = irr_f[kk];
+            const int off = (q * kDirs + irr_dir[kk]) * kDirs;
+#pragma unroll
+            for (int n = 0; n < kDirs; ++n) {
+                const double c = Cd[off + n];
+                if (c != 0.0) a[n] = a[n] + f * c;
             }
-            if (a != 0.0) {
-                const VT xv = xa(kDirs * ug + n);
-                if (MODE == 2) acc_d = __builtin_fma(a, (double)xv, acc_d);
-                else acc += StructVals<VT>::merged(a, sa.rounding, r, kDirs * ug + n) * xv;
+        }
+#pragma unroll
+        for (int n = 0; n < kDirs; ++n) {
+            if (a[n] != 0.0) {
+                if (MODE == 2) acc_d = __builtin_fma(a[n], (double)xv[n], acc_d);
+                else acc += StructVals<VT>::merged(a[n], sa.rounding, r, kDirs * ug + n) * xv[n];
             }
         }
         k = k1;
