@@ -191,9 +191,18 @@ def batch_vs_sequential(torch, steps=40):
     solvers = [drts.Solver(m, 1, [], max_steps=2 * steps + 4) for m in mats]
     tabs = [solve.source_table(m, w) for m, w in zip(mats, wls)]
     B = drts.Batch(solvers)
+    keys = ("rows_per_tile", "tiles_per_chunk", "variant", "grid", "xcd_remap")
+    defaults = [{k: S.options[k] for k in keys} for S in solvers]
+    _log("C4: autotuning the batch's launch shape")
+    t0 = time.perf_counter()
+    chosen = B.autotune()
+    t_tune = time.perf_counter() - t0
     B.run(tabs, [2] * len(solvers))
     t_b = _timed(lambda: B.run(tabs, [steps] * len(solvers)), torch)
     B.close()
+    # the sequential runs keep each solver's own default shape
+    for S, d in zip(solvers, defaults):
+        S.set_options(**d)
 
     def seq():
         for S, t in zip(solvers, tabs):
@@ -211,7 +220,10 @@ def batch_vs_sequential(torch, steps=40):
             "speedup_vs_sequential": round(t_s / t_b, 2),
             "solves_per_s": round(n * steps / t_b / 500, 3),
             "sequential_solves_per_s": round(n * steps / t_s / 500, 3),
-            "GNNZ_per_s": round(nnz * steps / t_b / 1e9, 1)}
+            "GNNZ_per_s": round(nnz * steps / t_b / 1e9, 1),
+            "batch_shape": "autotuned in %.1f s: %d rows per tile, %d tiles per chunk, variant %d, %d workgroups" %
+                           (t_tune, chosen["rows_per_tile"], chosen["tiles_per_chunk"], chosen["variant"],
+                            chosen["grid"])}
 
 
 def serving_vs_fifo(torch, n_req=32, step_scale=0.1):

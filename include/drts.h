@@ -314,6 +314,15 @@ int drts_batch_create(drts_solver_t *const *solvers, int32_t n, const drts_devic
  * solvers that finish drop out of later launches. */
 int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const int64_t *n_steps);
 
+/* Chooses one launch shape for the whole batch (rows per tile, tiles per
+ * chunk, kernel variant, workgroups of the step launch) by timing a few
+ * steps of every member at once for each candidate, then restores every
+ * member's state and control words and keeps the fastest shape in all
+ * members' options (chosen, may be NULL, receives it; its grid is the
+ * batch's).  Before the first step of every member (DRTS_E_STATE otherwise);
+ * results stay equal to solo runs with the same options, bit for bit. */
+int drts_batch_autotune(drts_batch_t *B, drts_options_t *chosen);
+
 void drts_batch_destroy(drts_batch_t *B);
 
 /* ---- serving: continuous batching of independent solves ----------------------- */

@@ -162,6 +162,7 @@ struct drts_batch {
     Device dev;
     std::vector<drts_solver *> solvers;
     Buffer inst_dev, work_dev, queue;
+    int grid = 0;   // workgroups of the step launch; 0: 16 per CU
 };
 
 namespace {
@@ -1262,7 +1263,7 @@ namespace {
 int batch_launch(drts_batch *B, int64_t n_work, int n_inst, int rows_per_tile, hipStream_t stream)
 {
     const drts_solver *S0 = B->solvers[0];
-    const int grid = device_cu_count() * 16;
+    const int grid = B->grid > 0 ? B->grid : device_cu_count() * 16;
     int32_t *queue = S0->opt.queue ? B->queue.as<int32_t>() : nullptr;
     hipError_t e = launch_step(B->inst_dev.as<StepInst>(), B->work_dev.as<WorkItem>(), n_work, n_inst, 1, 0,
                                S0->A->m.rp64 ? 1 : 0, 0, grid, (S0->opt.variant & 15) << 1, nullptr, rows_per_tile, 0,
@@ -1397,6 +1398,143 @@ int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const
         DRTS_HIP(hipMemcpyAsync(S->t_end.ptr, &S->max_steps, sizeof(int64_t), hipMemcpyHostToDevice, s));
     }
     DRTS_HIP(hipStreamSynchronize(s));
+    return DRTS_OK;
+}
+
+int drts_batch_autotune(drts_batch_t *B, drts_options_t *chosen)
+{
+    if (!B) return set_error(DRTS_E_INVALID, "batch is NULL");
+    const int n = (int)B->solvers.size();
+    for (int i = 0; i < n; ++i)
+        if (B->solvers[(size_t)i]->t_host != 0) return set_error(DRTS_E_STATE, "autotune before the first step");
+    Device &dev = B->dev;
+    hipStream_t s = dev.stream;
+    // every member's state and control words (exponent, maximum, absorbed
+    // sum at t = 0), restored afterwards
+    std::vector<Buffer> save((size_t)n);
+    std::vector<int32_t> save_E((size_t)n);
+    std::vector<double> save_M((size_t)n), save_abs((size_t)n);
+    int rc = DRTS_OK;
+    for (int i = 0; i < n && !rc; ++i) {
+        drts_solver *S = B->solvers[(size_t)i];
+        DRTS_HIP(hipStreamSynchronize(S->dev.stream));
+        const size_t st = (size_t)S->A->m.model.n_rows * 4;
+        if ((rc = save[(size_t)i].allocate(&dev, st))) break;
+        DRTS_HIP(hipMemcpyAsync(save[(size_t)i].ptr, S->buf0.ptr, st, hipMemcpyDeviceToDevice, s));
+        DRTS_HIP(hipMemcpyAsync(&save_E[(size_t)i], S->ctl_E.ptr, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        DRTS_HIP(hipMemcpyAsync(&save_M[(size_t)i], S->ctl_M.ptr, sizeof(double), hipMemcpyDeviceToHost, s));
+        DRTS_HIP(hipMemcpyAsync(&save_abs[(size_t)i], S->ctl_abs.ptr, sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    if (rc) return rc;
+    DRTS_HIP(hipStreamSynchronize(s));
+    const int cus = device_cu_count();
+    const drts_solver *S0 = B->solvers[0];
+    int64_t min_steps = INT64_MAX;
+    for (const drts_solver *S : B->solvers) min_steps = std::min(min_steps, S->max_steps);
+    const int steps = (int)std::max<int64_t>(1, std::min<int64_t>(3, min_steps - 1));
+    struct Cand {
+        int rpt, tpc, variant, grid;
+    };
+    std::vector<Cand> cands;
+    for (int r : {64, 128, 256})
+        for (int c : {1, 2, 4, 8, 16})
+            for (int v : {(int)DRTS_SPMV_ROW, (int)DRTS_SPMV_LDS, (int)DRTS_SPMV_WAVE_LDS})
+                for (int g : {16, 64}) {
+                    if (v == DRTS_SPMV_WAVE_LDS && r != 64) continue;
+                    cands.push_back({r, c, v, cus * g});
+                }
+    const std::vector<drts_options_t> orig = [&] {
+        std::vector<drts_options_t> o;
+        for (const drts_solver *S : B->solvers) o.push_back(S->opt);
+        return o;
+    }();
+    // one candidate's options on every member, the batch lists for all members
+    std::vector<StepInst> insts((size_t)n);
+    std::vector<WorkItem> work;
+    auto apply = [&](const Cand &c) -> int {
+        work.clear();
+        for (int i = 0; i < n; ++i) {
+            drts_solver *S = B->solvers[(size_t)i];
+            drts_options_t o = orig[(size_t)i];
+            o.rows_per_tile = c.rpt;
+            o.tiles_per_chunk = c.tpc;
+            o.variant = c.variant;
+            o.xcd_remap = 0;
+            int e = check_options(S, &o);
+            if (e) return e;
+            S->opt = o;
+            if ((e = prepare(S))) return e;
+            insts[(size_t)i] = S->inst_h;
+            for (int64_t k = 0; k < S->n_chunks; ++k) work.push_back({i, (int32_t)k});
+        }
+        B->grid = c.grid;
+        int e = upload_vec(dev, B->inst_dev, insts);
+        if (!e) e = upload_vec(dev, B->work_dev, work);
+        return e;
+    };
+    std::vector<int64_t> zero_t((size_t)n, 0);
+    auto reset_t = [&]() -> int {
+        for (int i = 0; i < n; ++i)
+            DRTS_HIP(hipMemcpyAsync(B->solvers[(size_t)i]->ctl_t.ptr, &zero_t[(size_t)i], sizeof(int64_t),
+                                    hipMemcpyHostToDevice, s));
+        return DRTS_OK;
+    };
+    hipEvent_t e0, e1;
+    DRTS_HIP(hipEventCreate(&e0));
+    DRTS_HIP(hipEventCreate(&e1));
+    float best_ms = INFINITY;
+    Cand best = {S0->opt.rows_per_tile, S0->opt.tiles_per_chunk, S0->opt.variant, cus * 16};
+    for (const Cand &c : cands) {
+        if ((rc = apply(c))) break;
+        const int64_t n_work = (int64_t)work.size();
+        if ((rc = reset_t())) break;
+        if ((rc = batch_launch(B, n_work, n, c.rpt, s))) break;   // warm-up
+        if ((rc = reset_t())) break;
+        if (hipEventRecord(e0, s) != hipSuccess) {
+            rc = set_error(DRTS_E_HIP, "hipEventRecord failed");
+            break;
+        }
+        for (int k = 0; k < steps && !rc; ++k) rc = batch_launch(B, n_work, n, c.rpt, s);
+        if (rc) break;
+        float ms = 0.f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = set_error(DRTS_E_HIP, "event timing failed");
+            break;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // restore every member's state and control words, then apply the choice
+    for (int i = 0; i < n; ++i) {
+        drts_solver *S = B->solvers[(size_t)i];
+        const size_t st = (size_t)S->A->m.model.n_rows * 4;
+        DRTS_HIP(hipMemcpyAsync(S->buf0.ptr, save[(size_t)i].ptr, st, hipMemcpyDeviceToDevice, s));
+        DRTS_HIP(hipMemcpyAsync(S->ctl_t.ptr, &zero_t[(size_t)i], sizeof(int64_t), hipMemcpyHostToDevice, s));
+        DRTS_HIP(hipMemcpyAsync(S->ctl_E.ptr, &save_E[(size_t)i], sizeof(int32_t), hipMemcpyHostToDevice, s));
+        DRTS_HIP(hipMemcpyAsync(S->ctl_M.ptr, &save_M[(size_t)i], sizeof(double), hipMemcpyHostToDevice, s));
+        DRTS_HIP(hipMemcpyAsync(S->ctl_abs.ptr, &save_abs[(size_t)i], sizeof(double), hipMemcpyHostToDevice, s));
+    }
+    DRTS_HIP(hipStreamSynchronize(s));
+    if (rc) {
+        // leave the members as they were
+        for (int i = 0; i < n; ++i) {
+            B->solvers[(size_t)i]->opt = orig[(size_t)i];
+            (void)prepare(B->solvers[(size_t)i]);
+        }
+        B->grid = 0;
+        return rc;
+    }
+    if ((rc = apply(best))) return rc;
+    DRTS_HIP(hipStreamSynchronize(s));
+    if (chosen) {
+        *chosen = B->solvers[0]->opt;
+        chosen->grid = best.grid;
+    }
     return DRTS_OK;
 }
 

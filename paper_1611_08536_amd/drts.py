@@ -130,6 +130,7 @@ _sig("drts_solver_destroy", None, [P])
 _sig("drts_batch_create", C.c_int, [C.POINTER(P), i32, C.POINTER(DeviceT), C.POINTER(P)])
 _sig("drts_batch_run", C.c_int, [P, C.POINTER(C.POINTER(SourceTableT)), C.POINTER(i64)])
 _sig("drts_batch_destroy", None, [P])
+_sig("drts_batch_autotune", C.c_int, [P, C.POINTER(OptionsT)])
 _sig("drts_autotune", C.c_int, [P, C.c_char_p, C.POINTER(OptionsT)])
 _sig("drts_serve_create", C.c_int, [C.POINTER(DeviceT), i64, i32, i32, i32, i32, C.POINTER(P)])
 _sig("drts_serve_submit", C.c_int, [P, C.POINTER(MediumT), C.POINTER(SourceTableT), C.POINTER(DetectorsT), i64,
@@ -147,7 +148,7 @@ EXPORTED = [
     "drts_matrix_destroy", "drts_solver_create", "drts_solver_get_options", "drts_solver_set_options",
     "drts_step", "drts_run", "drts_solver_time", "drts_detector_readout", "drts_state_read",
     "drts_state_write", "drts_solver_profile", "drts_solver_profile_stats", "drts_solver_destroy",
-    "drts_batch_create", "drts_batch_run", "drts_batch_destroy", "drts_autotune", "drts_last_error",
+    "drts_batch_create", "drts_batch_run", "drts_batch_destroy", "drts_batch_autotune", "drts_autotune", "drts_last_error",
     "drts_serve_create", "drts_serve_submit", "drts_serve_footprint", "drts_serve_tick", "drts_serve_poll", "drts_serve_result",
     "drts_serve_release", "drts_serve_destroy",
 ]
@@ -467,6 +468,11 @@ class Batch:
         self._keep = tables
         steps = np.ascontiguousarray(n_steps, dtype=np.int64)
         _check(_lib.drts_batch_run(self._h, ptrs, steps.ctypes.data_as(C.POINTER(i64))), "drts_batch_run")
+
+    def autotune(self) -> dict:
+        o = OptionsT()
+        _check(_lib.drts_batch_autotune(self._h, C.byref(o)), "drts_batch_autotune")
+        return {k: getattr(o, k) for k, _ in OptionsT._fields_}
 
 
 class Server:

@@ -89,6 +89,33 @@ def test_batch_members_equal_solo_runs():
         assert np.array_equal(r["tot"], solo["tot"]) and np.array_equal(r["exp2"], solo["exp2"]), i
 
 
+def test_batch_autotune_keeps_results():
+    """drts_batch_autotune before the first step: every member gets the one
+    chosen shape, the tuning steps leave no trace in state or series, and each
+    member then equals its solo run with the chosen options, bit for bit."""
+    wls = _c4_small(n_inst=7, edge=(6, 14))
+    steps = [40, 25, 40, 7, 33, 40, 1]
+    mats = [drts.Matrix(w.medium, w.value_type, w.rounding, w.n_ref) for w in wls]
+    solvers = [drts.Solver(m, 1, w.detectors, max_steps=40) for m, w in zip(mats, wls)]
+    tabs = [solve.source_table(m, w) for m, w in zip(mats, wls)]
+    B = drts.Batch(solvers)
+    chosen = B.autotune()
+    assert chosen["rows_per_tile"] in (64, 128, 256) and chosen["grid"] > 0
+    keys = ("rows_per_tile", "tiles_per_chunk", "variant")
+    for S in solvers:
+        assert {k: S.options[k] for k in keys} == {k: chosen[k] for k in keys}
+    B.run(tabs, steps)
+    for i, (w, m, S) in enumerate(zip(wls, mats, solvers)):
+        solo = solve.run(w, n_steps=steps[i], matrix=m, options={k: chosen[k] for k in keys})
+        x, e, t = S.state()
+        assert t == steps[i]
+        assert np.array_equal(x, solo["x"]) and np.array_equal(e, solo["x_exp"]), i
+        r = S.readout(0, steps[i])
+        assert np.array_equal(r["tot"], solo["tot"]) and np.array_equal(r["exp2"], solo["exp2"]), i
+    with pytest.raises(drts.DrtsError):
+        B.autotune()          # members have stepped
+
+
 def test_batch_against_oracle_and_continues():
     wls = _c4_small(n_inst=5, edge=(8, 12))
     mats = [drts.Matrix(w.medium, w.value_type, w.rounding, w.n_ref) for w in wls]
