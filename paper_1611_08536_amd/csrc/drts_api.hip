@@ -1319,6 +1319,8 @@ int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const
         drts_solver *S = B->solvers[i];
         if (S->opt.rows_per_tile != rpt)
             return set_error(DRTS_E_INVALID, "solver %d: every batch member needs the same rows_per_tile", i);
+        if (S->opt.kernel != DRTS_KERNEL_CSR)
+            return set_error(DRTS_E_INVALID, "solver %d: batches run the CSR step (kernel option)", i);
         if (n_steps[i] < 0 || S->t_host + n_steps[i] > S->max_steps)
             return set_error(DRTS_E_RANGE, "solver %d: steps beyond max_steps", i);
         if (n_steps[i] == 0) continue;
@@ -1405,8 +1407,11 @@ int drts_batch_autotune(drts_batch_t *B, drts_options_t *chosen)
 {
     if (!B) return set_error(DRTS_E_INVALID, "batch is NULL");
     const int n = (int)B->solvers.size();
-    for (int i = 0; i < n; ++i)
+    for (int i = 0; i < n; ++i) {
         if (B->solvers[(size_t)i]->t_host != 0) return set_error(DRTS_E_STATE, "autotune before the first step");
+        if (B->solvers[(size_t)i]->opt.kernel != DRTS_KERNEL_CSR)
+            return set_error(DRTS_E_INVALID, "solver %d: batches run the CSR step (kernel option)", i);
+    }
     Device &dev = B->dev;
     hipStream_t s = dev.stream;
     // every member's state and control words (exponent, maximum, absorbed

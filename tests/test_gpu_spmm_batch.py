@@ -146,6 +146,18 @@ def test_batch_rejects_mixed_inputs():
         drts.Batch([s32, s64])
     with pytest.raises(drts.DrtsError):
         drts.Batch([s32, s32])
+    # a member switched to the matrix-free step: the batch runs the CSR step only
+    m_mf = drts.Matrix(w32.medium, "f32")
+    s_mf = drts.Solver(m_mf, 1, [], max_steps=5)
+    B = drts.Batch([s32, s_mf])
+    s_mf.set_options(kernel=drts.KERNEL_STRUCTURED)
+    with pytest.raises(drts.DrtsError):
+        B.autotune()
+    with pytest.raises(drts.DrtsError):
+        B.run([None, None], [2, 2])
+    s_mf.set_options(kernel=drts.KERNEL_CSR)
+    B.run([None, None], [2, 2])
+    assert s32.state()[2] == 2 and s_mf.state()[2] == 2
 
 
 def test_autotune_keeps_results_and_caches(tmp_path):
