@@ -238,6 +238,10 @@ def serving_vs_fifo(torch, n_req=32, step_scale=0.1):
     budget = serve.footprint_budget(0.7)
     _log("C5: serving %d requests (budget %.1f GB)" % (n_req, budget / 1e9))
     s = serve.serve(reqs, budget, quantum=50, max_active=4, policy="shortest")
+    _log("C5: serving with the matrix-free step")
+    torch.cuda.empty_cache()
+    from paper_1611_08536_amd import drts
+    m = serve.serve(reqs, budget, quantum=50, max_active=4, policy="shortest", kernel=drts.KERNEL_STRUCTURED_F64SUM)
     _log("C5: FIFO plain")
     f = serve.fifo_plain(reqs)
     r = lambda d: {k: round(v, 4) if isinstance(v, float) else v for k, v in d.items()}
@@ -245,7 +249,9 @@ def serving_vs_fifo(torch, n_req=32, step_scale=0.1):
                         (n_req, lo, hi),
             "server": "least work first, at most 4 admitted, 50 steps per tick, budget 70% of free HBM",
             "served": r(s), "fifo_plain": r(f),
-            "speedup_solves_per_s": round(s["solves_per_s"] / f["solves_per_s"], 2)}
+            "speedup_solves_per_s": round(s["solves_per_s"] / f["solves_per_s"], 2),
+            "served_matrix_free": r(m),
+            "matrix_free_speedup_solves_per_s": round(m["solves_per_s"] / f["solves_per_s"], 2)}
 
 
 def structured_step(torch, A, wl, tab, steps=50):

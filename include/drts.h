@@ -359,6 +359,17 @@ void drts_batch_destroy(drts_batch_t *B);
 int drts_serve_create(const drts_device_t *dev, int64_t budget_bytes, int32_t quantum, int32_t max_active,
                       int32_t max_skips, int32_t policy, drts_server_t **out);
 
+/* Selects the step of the requests admitted from now on: DRTS_KERNEL_CSR
+ * (the default: all CSR requests advance together, one batched launch per
+ * step) or a matrix-free kernel (DRTS_KERNEL_STRUCTURED or
+ * DRTS_KERNEL_STRUCTURED_F64SUM: each such request runs its quantum with its
+ * own graph-replayed drts_run, in turn, on the server's stream, with 8 tiles
+ * per chunk and 16 workgroups per CU).  A served result equals the same
+ * solve run alone with the same options, bit for bit.  The matrix is still
+ * assembled (and counted in the footprint).  DRTS_E_INVALID for another
+ * kernel.  Thread-safe like drts_serve_submit. */
+int drts_serve_set_step(drts_server_t *Q, int32_t kernel);
+
 /* Queues one solve of n_steps steps: an FP32 medium (its host arrays are
  * copied), its sources (the table must stay valid until the request has
  * finished) and detectors (copied; NULL for none).  Ids increase in the

@@ -46,6 +46,7 @@ struct Request {
     Model model;             // host model, built once at submission, moved into the matrix
     drts_matrix_t *A = nullptr;
     drts_solver_t *S = nullptr;
+    int32_t kernel = DRTS_KERNEL_CSR;   // the step it runs, fixed at admission
     bool finished = false;
     // results, copied at retirement
     std::vector<double> series, totals;
@@ -77,6 +78,7 @@ struct drts_server {
     drts_device_t dev{};
     int64_t budget = 0, used = 0;
     int32_t quantum = 0, max_active = 0, max_skips = 0, policy = 0;
+    int32_t kernel = DRTS_KERNEL_CSR;   // the step of requests admitted from now on
     // guards next_id and everything below: submissions may run on other
     // threads concurrently with the other calls
     mutable std::mutex mu;
@@ -158,10 +160,27 @@ int admit(drts_server *Q, Request &q)
     det.escape = q.det_esc.data();
     det.F = q.det_F.data();
     rc = drts_solver_create(q.A, 1, q.n_det > 0 ? &det : nullptr, q.n_steps, &Q->dev, &q.S);
+    if (!rc && Q->kernel != DRTS_KERNEL_CSR) {
+        // the matrix-free step with its measured launch shape: 8 tiles per
+        // chunk, 16 workgroups per CU
+        int dev = 0, cus = 0;
+        drts_options_t o{};
+        rc = drts_solver_get_options(q.S, &o);
+        if (!rc && (hipGetDevice(&dev) != hipSuccess ||
+                    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess))
+            rc = set_error(DRTS_E_HIP, "device attributes");
+        if (!rc) {
+            o.kernel = Q->kernel;
+            o.tiles_per_chunk = 8;
+            o.grid = 16 * std::max(cus, 1);
+            rc = drts_solver_set_options(q.S, &o);
+        }
+    }
     if (rc) {
         q.free_device();
         return rc;
     }
+    q.kernel = Q->kernel;
     int64_t n_states = 0, n_escape = 0, nnz = 0, mbytes = 0;
     double dt = 0;
     drts_matrix_info(q.A, &n_states, &n_escape, &nnz, &mbytes, &dt);
@@ -211,6 +230,16 @@ int drts_serve_create(const drts_device_t *dev, int64_t budget_bytes, int32_t qu
     Q->max_skips = max_skips;
     Q->policy = policy;
     *out = Q;
+    return DRTS_OK;
+}
+
+int drts_serve_set_step(drts_server_t *Q, int32_t kernel)
+{
+    if (!Q) return set_error(DRTS_E_INVALID, "server is NULL");
+    if (kernel != DRTS_KERNEL_CSR && kernel != DRTS_KERNEL_STRUCTURED && kernel != DRTS_KERNEL_STRUCTURED_F64SUM)
+        return set_error(DRTS_E_INVALID, "unknown kernel %d", kernel);
+    std::lock_guard<std::mutex> lk(Q->mu);
+    Q->kernel = kernel;
     return DRTS_OK;
 }
 
@@ -300,24 +329,36 @@ int drts_serve_tick(drts_server_t *Q, int32_t *n_active, int32_t *n_waiting, int
         passed.push_back(&q);
         ++it;
     }
-    // 2. one quantum for every admitted request, one launch per step
+    // 2. one quantum for every admitted request: the CSR ones as one batch
+    //    (one launch per step), the matrix-free ones each with its own
+    //    graph-replayed run, in turn on the same stream
     if (!Q->active.empty()) {
+        std::vector<Request *> csr, mf;
+        for (Request *q : Q->active) (q->kernel == DRTS_KERNEL_CSR ? csr : mf).push_back(q);
         if (Q->batch_dirty) {
             if (Q->batch) drts_batch_destroy(Q->batch);
             Q->batch = nullptr;
             std::vector<drts_solver_t *> ss;
-            for (Request *q : Q->active) ss.push_back(q->S);
-            if ((rc = drts_batch_create(ss.data(), (int32_t)ss.size(), &Q->dev, &Q->batch))) return rc;
+            for (Request *q : csr) ss.push_back(q->S);
+            if (!ss.empty() && (rc = drts_batch_create(ss.data(), (int32_t)ss.size(), &Q->dev, &Q->batch)))
+                return rc;
             Q->batch_dirty = false;
         }
-        std::vector<const drts_source_table_t *> tabs;
-        std::vector<int64_t> steps;
-        for (Request *q : Q->active) {
-            tabs.push_back(q->src);
-            steps.push_back(std::min<int64_t>(Q->quantum, q->n_steps - q->done));
+        if (!csr.empty()) {
+            std::vector<const drts_source_table_t *> tabs;
+            std::vector<int64_t> steps;
+            for (Request *q : csr) {
+                tabs.push_back(q->src);
+                steps.push_back(std::min<int64_t>(Q->quantum, q->n_steps - q->done));
+            }
+            if ((rc = drts_batch_run(Q->batch, tabs.data(), steps.data()))) return rc;
+            for (size_t i = 0; i < csr.size(); ++i) csr[i]->done += steps[i];
         }
-        if ((rc = drts_batch_run(Q->batch, tabs.data(), steps.data()))) return rc;
-        for (size_t i = 0; i < Q->active.size(); ++i) Q->active[i]->done += steps[i];
+        for (Request *q : mf) {
+            const int64_t n = std::min<int64_t>(Q->quantum, q->n_steps - q->done);
+            if ((rc = drts_run(q->S, q->src, n))) return rc;
+            q->done += n;
+        }
         // 3. retirement
         std::vector<Request *> keep;
         for (Request *q : Q->active) {

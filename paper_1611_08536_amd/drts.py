@@ -142,6 +142,7 @@ _sig("drts_serve_poll", C.c_int, [P, C.POINTER(i64), i32, C.POINTER(i32)])
 _sig("drts_serve_result", C.c_int, [P, i64, P, P, P])
 _sig("drts_serve_release", C.c_int, [P, i64])
 _sig("drts_serve_destroy", None, [P])
+_sig("drts_serve_set_step", C.c_int, [P, i32])
 
 EXPORTED = [
     "drts_build_matrix", "drts_matrix_info", "drts_matrix_row_of", "drts_matrix_export_rows",
@@ -150,7 +151,7 @@ EXPORTED = [
     "drts_state_write", "drts_solver_profile", "drts_solver_profile_stats", "drts_solver_destroy",
     "drts_batch_create", "drts_batch_run", "drts_batch_destroy", "drts_batch_autotune", "drts_autotune", "drts_last_error",
     "drts_serve_create", "drts_serve_submit", "drts_serve_footprint", "drts_serve_tick", "drts_serve_poll", "drts_serve_result",
-    "drts_serve_release", "drts_serve_destroy",
+    "drts_serve_release", "drts_serve_destroy", "drts_serve_set_step",
 ]
 
 
@@ -479,13 +480,15 @@ class Server:
     """Continuous batching of independent FP32 solves (drts_serve_*)."""
 
     def __init__(self, budget_bytes: int, quantum: int = 50, max_active: int = 256, max_skips: int = 8,
-                 policy: str = "arrival", device: Optional[TorchDevice] = None):
+                 policy: str = "arrival", device: Optional[TorchDevice] = None, kernel: int = KERNEL_CSR):
         self.device = device or default_device()
         h = P()
         pol = {"arrival": SERVE_ARRIVAL, "shortest": SERVE_SHORTEST}[policy]
         _check(_lib.drts_serve_create(C.byref(self.device.c), int(budget_bytes), int(quantum), int(max_active),
                                       int(max_skips), pol, C.byref(h)), "drts_serve_create")
         self._h = h
+        if kernel != KERNEL_CSR:
+            _check(_lib.drts_serve_set_step(self._h, int(kernel)), "drts_serve_set_step")
         self._req = {}     # id -> (n_steps, n_det, source table kept alive)
 
     def close(self):

@@ -33,12 +33,13 @@ def _summary(lat: List[float], wall: float, n: int) -> dict:
 
 
 def serve(requests, budget_bytes: int, quantum: int = 50, max_active: int = 256, max_skips: int = 8,
-          policy: str = "arrival", keep_results: bool = False, log=None, submit_threads: int = 4) -> dict:
+          policy: str = "arrival", keep_results: bool = False, log=None, submit_threads: int = 4,
+          kernel: int = drts.KERNEL_CSR) -> dict:
     """Replays `requests` through one server; returns the latency summary and,
     with keep_results, every request's series in submission order.
     submit_threads = 0 submits on the calling thread (every request that has
     arrived is queued before the next tick)."""
-    S = drts.Server(budget_bytes, quantum, max_active, max_skips, policy)
+    S = drts.Server(budget_bytes, quantum, max_active, max_skips, policy, kernel=kernel)
     order = sorted(range(len(requests)), key=lambda i: requests[i].arrival_s)
     tables, rid_of, arrival_of = {}, {}, {}
     done_at, results = {}, {}
@@ -103,8 +104,19 @@ def serve(requests, budget_bytes: int, quantum: int = 50, max_active: int = 256,
     return out
 
 
-def fifo_plain(requests, keep_results: bool = False, log=None) -> dict:
-    """The same requests, one at a time in arrival order, each solved alone."""
+def solo_options(kernel: int) -> Optional[dict]:
+    """The launch options the server gives a request run with `kernel`."""
+    if kernel == drts.KERNEL_CSR:
+        return None
+    import torch
+    cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+    return {"kernel": kernel, "tiles_per_chunk": 8, "grid": 16 * cus}
+
+
+def fifo_plain(requests, keep_results: bool = False, log=None, kernel: int = drts.KERNEL_CSR) -> dict:
+    """The same requests, one at a time in arrival order, each solved alone
+    (with the options the server gives a request run with `kernel`)."""
+    opts = solo_options(kernel)
     order = sorted(range(len(requests)), key=lambda i: requests[i].arrival_s)
     lat, results = [], {}
     t0 = time.perf_counter()
@@ -116,6 +128,8 @@ def fifo_plain(requests, keep_results: bool = False, log=None) -> dict:
         wl = req.workload
         A = drts.Matrix(wl.medium, wl.value_type, wl.rounding, wl.n_ref)
         Sv = drts.Solver(A, 1, wl.detectors, max_steps=wl.n_steps)
+        if opts:
+            Sv.set_options(**opts)
         Sv.run(_table(wl), wl.n_steps)
         r = Sv.readout(0, wl.n_steps)       # synchronizes
         lat.append(time.perf_counter() - t0 - req.arrival_s)

@@ -9,7 +9,10 @@ Bars:
   - served results against the FP64 oracle: relative error <= 1e-5;
   - admission keeps the admitted footprint within the budget: with a budget
     of about three requests, several requests run at once and the rest wait
-    until earlier ones retire.
+    until earlier ones retire;
+  - requests served with the matrix-free step (FP64 row sums) equal the same
+    solves run alone with the server's options, bit for bit, and meet the
+    same 1e-5 bar against the oracle.
 """
 import numpy as np
 import pytest
@@ -74,3 +77,30 @@ def test_served_results_against_oracle():
             assert err <= 1e-5, (i, c, err)
         err = parity.rel_err_series(r["det"][:, 0], r["exp2"], ref["det"][:, 0], ref["det_exp"][:, 0])
         assert err <= 1e-5, (i, "det", err)
+
+
+def test_matrix_free_served_results_equal_solo_runs_and_oracle():
+    reqs = _requests(6)
+    fps = sorted(_footprints(reqs))
+    k = drts.KERNEL_STRUCTURED_F64SUM
+    out = serve.serve(reqs, sum(fps[-3:]), quantum=16, max_active=4, max_skips=2, policy="shortest",
+                      keep_results=True, kernel=k)
+    assert 2 <= out["peak_active"] < len(reqs), out["peak_active"]
+    solo = serve.fifo_plain(reqs, keep_results=True, kernel=k)
+    for i in range(len(reqs)):
+        assert _same(out["results"][i], solo["results"][i]), i
+    for i in (0, 5):
+        wl = reqs[i].workload
+        ref = oracle.run_workload(oracle.Matrix(wl.medium), wl)
+        r = out["results"][i]
+        for c in range(3):
+            err = parity.rel_err_series(r["tot"][:, c], r["exp2"], ref["tot"][:, c], ref["tot_exp"][:, c])
+            assert err <= 1e-5, (i, c, err)
+        err = parity.rel_err_series(r["det"][:, 0], r["exp2"], ref["det"][:, 0], ref["det_exp"][:, 0])
+        assert err <= 1e-5, (i, "det", err)
+
+
+def test_server_rejects_unknown_step():
+    with pytest.raises(drts.DrtsError):
+        drts.Server(1 << 30, kernel=7)
+
