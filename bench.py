@@ -95,7 +95,7 @@ def spmv_bytes(nnz, n_rows, n_states, val_bytes=4):
     return val_bytes * nnz + 4 * nnz + 4 * (n_rows + 1) + val_bytes * n_states + val_bytes * n_rows
 
 
-def cpu_baseline(n=128, steps=50):
+def cpu_baseline(n=128, steps=50, steps_1=3):
     """The FP64 oracle (as it stands) on the host cores: a bounded sample of the
     same workload (the first `steps` steps of the 128^3 layered medium), timed
     after its assembly."""
@@ -107,10 +107,18 @@ def cpu_baseline(n=128, steps=50):
     oracle.run_workload(A, wl, n_steps=steps)
     dt = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # the same oracle on one thread, over the first steps_1 steps
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    oracle.run_workload(A, wl, n_steps=steps_1)
+    dt1 = time.perf_counter() - t0
+    oracle.set_threads(threads)
     return {"value": round(A.nnz * steps / dt / 1e9, 4), "unit": "GNNZ/s", "cores": threads,
             "kind": "oracle",
             "sample": "first %d of the 2000 FP64 steps of the %d^3 layered workload (%d nnz), %.1f s" %
-                      (steps, n, A.nnz, dt)}
+                      (steps, n, A.nnz, dt),
+            "value_1_thread": round(A.nnz * steps_1 / dt1 / 1e9, 4),
+            "sample_1_thread": "first %d steps, %.1f s" % (steps_1, dt1)}
 
 
 def _log(msg):

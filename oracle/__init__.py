@@ -76,6 +76,8 @@ def _load():
         lib.or_row_of.argtypes = [P, i64, C.c_int]
         lib.or_round_f32.argtypes = [P, C.c_int, P]
         lib.or_spmv.argtypes = [P, P, P, P]
+        lib.or_set_threads.argtypes = [C.c_int]
+        lib.or_set_threads.restype = None
         lib.or_run.restype = C.c_int
         lib.or_run.argtypes = [P, P, i64, P, i32,
                                i64, P, P, P, i32, P,
@@ -96,6 +98,12 @@ def _ptr(a):
 
 
 # ---- scalar pieces, exposed for the pins ----------------------------------
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's SpMV loop from now on (timing only; n < 1 keeps
+    the OpenMP default).  Results do not depend on it."""
+    _load().or_set_threads(int(n))
+
 
 def collision_block(mu_s, mu_a, g, h_mm) -> np.ndarray:
     """26x26 direction block C[m, n] of one material (Eq. (9), (10), (19), (21))."""

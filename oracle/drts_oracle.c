@@ -36,6 +36,9 @@
  * order.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -509,6 +512,18 @@ void or_round_f32(const or_csr_t *A, int mode, float *out)
 }
 
 /* ---- time stepping ----------------------------------------------------------- */
+
+/* Threads of the SpMV loop (OpenMP) for the calls that follow; n < 1 leaves
+ * the runtime's default.  Only the timing of the oracle uses it: the row sums
+ * are the same sequential sums with any number of threads. */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
 
 /* y = A x over all rows (state rows then escape rows), each row summed in
  * ascending column order; vals32 replaces the FP64 values when not NULL */

@@ -8,6 +8,7 @@ test vectors and numerical quadrature.
 """
 import ctypes
 import math
+import os
 
 import numpy as np
 import pytest
@@ -486,3 +487,19 @@ def test_sizes_of_homogeneous_vacuum_cube(orc, n):
     assert A.nnz == 26 * A.n_states
     if n == 16:
         assert (A.n_states, A.nnz, A.n_escape) == (106496, 2768896, 13256)
+
+
+def test_thread_count_does_not_change_results(orc):
+    """The oracle's thread count (used only to time it on one core) leaves every
+    row's sequential sum, and so every state and series value, unchanged."""
+    wl = W.c2(n=10, n_steps=12)
+    A = orc.Matrix(wl.medium)
+    try:
+        orc.set_threads(1)
+        one = orc.run_workload(A, wl)
+        orc.set_threads(4)
+        four = orc.run_workload(A, wl)
+    finally:
+        orc.set_threads(os.cpu_count() or 1)
+    for k in ("x", "x_exp", "tot", "tot_exp", "det", "det_exp"):
+        assert np.array_equal(one[k], four[k]), k
