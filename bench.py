@@ -219,6 +219,20 @@ def batch_vs_sequential(torch, steps=40):
     nnz = sum(m.nnz for m in mats)
     for S in solvers:
         S.close()
+    # the same media with the matrix-free step (FP64 row sums, 8 tiles per
+    # chunk): one batch (one launch per kernel and step), then one after another
+    _log("C4: matrix-free batch")
+    mf = {"kernel": drts.KERNEL_STRUCTURED_F64SUM, "tiles_per_chunk": 8}
+    solvers = [drts.Solver(m, 1, [], max_steps=2 * steps + 4) for m in mats]
+    for S in solvers:
+        S.set_options(**mf)
+    B = drts.Batch(solvers)
+    B.run(tabs, [2] * len(solvers))
+    t_mb = _timed(lambda: B.run(tabs, [steps] * len(solvers)), torch)
+    B.close()
+    t_ms = _timed(seq, torch)
+    for S in solvers:
+        S.close()
     for m in mats:
         m.close()
     n = len(wls)
@@ -231,7 +245,13 @@ def batch_vs_sequential(torch, steps=40):
             "GNNZ_per_s": round(nnz * steps / t_b / 1e9, 1),
             "batch_shape": "autotuned in %.1f s: %d rows per tile, %d tiles per chunk, variant %d, %d workgroups" %
                            (t_tune, chosen["rows_per_tile"], chosen["tiles_per_chunk"], chosen["variant"],
-                            chosen["grid"])}
+                            chosen["grid"]),
+            "matrix_free": {"kernel": "step_struct_dm<2, true> + step_struct_x<float, 2, true> (FP64 row sums)",
+                            "instance_steps_per_s": round(n * steps / t_mb, 1),
+                            "sequential_instance_steps_per_s": round(n * steps / t_ms, 1),
+                            "speedup_vs_sequential": round(t_ms / t_mb, 2),
+                            "speedup_vs_csr_sequential": round(t_s / t_mb, 2),
+                            "GNNZ_equiv_per_s": round(nnz * steps / t_mb / 1e9, 1)}}
 
 
 def serving_vs_fifo(torch, n_req=32, step_scale=0.1):

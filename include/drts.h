@@ -312,8 +312,11 @@ int drts_batch_create(drts_solver_t *const *solvers, int32_t n, const drts_devic
 
 /* Advances solver i by n_steps[i] steps (0 = idle) with source table src[i];
  * solvers that finish drop out of later launches.  Every member must use the
- * CSR step (kernel option DRTS_KERNEL_CSR) and the same rows_per_tile
- * (DRTS_E_INVALID otherwise). */
+ * same step (DRTS_E_INVALID otherwise): the CSR step (kernel option
+ * DRTS_KERNEL_CSR, the same rows_per_tile for all), or the matrix-free step
+ * with direction-major tiles (DRTS_KERNEL_STRUCTURED on nearest-rounded
+ * values, or DRTS_KERNEL_STRUCTURED_F64SUM; at most 8 materials), whose two
+ * kernels then each cover every member in one launch per step. */
 int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const int64_t *n_steps);
 
 /* Chooses one launch shape for the whole batch (rows per tile, tiles per

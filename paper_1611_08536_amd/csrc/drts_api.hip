@@ -162,7 +162,9 @@ struct drts_batch {
     Device dev;
     std::vector<drts_solver *> solvers;
     Buffer inst_dev, work_dev, queue;
-    int grid = 0;   // workgroups of the step launch; 0: 16 per CU
+    Buffer sas_dev, xwork_dev;   // matrix-free members: their arguments, their irregular-row items
+    int grid = 0;                // workgroups of the step launch; 0: 16 per CU
+    int mode = 0;                // 0: CSR step; 1 or 2: the matrix-free mode of every member
 };
 
 namespace {
@@ -1260,14 +1262,21 @@ void drts_solver_destroy(drts_solver_t *S)
 
 namespace {
 
-int batch_launch(drts_batch *B, int64_t n_work, int n_inst, int rows_per_tile, hipStream_t stream)
+int batch_launch(drts_batch *B, int64_t n_work, int n_inst, int rows_per_tile, hipStream_t stream,
+                 int64_t n_xwork = 0)
 {
     const drts_solver *S0 = B->solvers[0];
     const int grid = B->grid > 0 ? B->grid : device_cu_count() * 16;
-    int32_t *queue = S0->opt.queue ? B->queue.as<int32_t>() : nullptr;
-    hipError_t e = launch_step(B->inst_dev.as<StepInst>(), B->work_dev.as<WorkItem>(), n_work, n_inst, 1, 0,
-                               S0->A->m.rp64 ? 1 : 0, 0, grid, (S0->opt.variant & 15) << 1, nullptr, rows_per_tile, 0,
-                               queue, stream);
+    int32_t *queue = (B->mode == 0 && S0->opt.queue) ? B->queue.as<int32_t>() : nullptr;
+    hipError_t e;
+    if (B->mode != 0)
+        e = launch_structured_batch(B->sas_dev.as<StructArgs>(), B->inst_dev.as<StepInst>(),
+                                    B->work_dev.as<WorkItem>(), n_work, B->xwork_dev.as<WorkItem>(), n_xwork, B->mode,
+                                    grid, stream);
+    else
+        e = launch_step(B->inst_dev.as<StepInst>(), B->work_dev.as<WorkItem>(), n_work, n_inst, 1, 0,
+                        S0->A->m.rp64 ? 1 : 0, 0, grid, (S0->opt.variant & 15) << 1, nullptr, rows_per_tile, 0,
+                        queue, stream);
     if (e != hipSuccess) return set_error(DRTS_E_HIP, "batch step launch failed: %s", hipGetErrorString(e));
     e = launch_finalize(B->inst_dev.as<StepInst>(), n_inst, 1, 0, queue, stream);
     if (e != hipSuccess) return set_error(DRTS_E_HIP, "batch finalize launch failed: %s", hipGetErrorString(e));
@@ -1315,12 +1324,23 @@ int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const
     std::vector<int> order;
     int rc;
     const int rpt = B->solvers[0]->opt.rows_per_tile;
+    // every member runs the CSR step (step -1), or every member the
+    // matrix-free step in the same direction-major mode (1 or 2)
+    auto step_of = [](const drts_solver *S) { return structured_of(S) ? structured_mode(S) : -1; };
+    const int kind = step_of(B->solvers[0]);
+    if (kind != -1 && kind != 1 && kind != 2)
+        return set_error(DRTS_E_INVALID, "solver 0: a batch takes the matrix-free step only in modes 1 and 2 "
+                                         "(FP32, nearest-rounded values or FP64 row sums, at most %d materials)",
+                         kStructMatLdsHost);
+    const int mode = kind == -1 ? 0 : kind;
     for (int i = 0; i < n; ++i) {
         drts_solver *S = B->solvers[i];
-        if (S->opt.rows_per_tile != rpt)
+        if (step_of(S) != kind)
+            return set_error(DRTS_E_INVALID, "solver %d: every batch member needs the same step (kernel option)", i);
+        if (mode != 0 && (S->sa.seg_len != kStructDmSeg || S->sa.n_mat > kStructMatLdsHost))
+            return set_error(DRTS_E_INVALID, "solver %d: matrix-free tiles of another shape", i);
+        if (mode == 0 && S->opt.rows_per_tile != rpt)
             return set_error(DRTS_E_INVALID, "solver %d: every batch member needs the same rows_per_tile", i);
-        if (S->opt.kernel != DRTS_KERNEL_CSR)
-            return set_error(DRTS_E_INVALID, "solver %d: batches run the CSR step (kernel option)", i);
         if (n_steps[i] < 0 || S->t_host + n_steps[i] > S->max_steps)
             return set_error(DRTS_E_RANGE, "solver %d: steps beyond max_steps", i);
         if (n_steps[i] == 0) continue;
@@ -1332,15 +1352,23 @@ int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n_steps[a] > n_steps[b]; });
     const int P = (int)order.size();
     std::vector<StepInst> insts((size_t)P);
-    std::vector<WorkItem> work;
-    std::vector<int64_t> prefix((size_t)P), tend((size_t)P);
+    std::vector<StructArgs> sas;
+    std::vector<WorkItem> work, xwork;
+    std::vector<int64_t> prefix((size_t)P), xprefix((size_t)P), tend((size_t)P);
     for (int j = 0; j < P; ++j) {
         drts_solver *S = B->solvers[(size_t)order[(size_t)j]];
         insts[(size_t)j] = S->inst_h;
         for (int64_t c = 0; c < S->n_chunks; ++c) work.push_back({j, (int32_t)c});
+        if (mode != 0) {
+            sas.push_back(S->sa);
+            const int64_t items = (S->sa.n_xrows + kStructXRows - 1) / kStructXRows;
+            for (int64_t k = 0; k < items; ++k) xwork.push_back({j, (int32_t)k});
+        }
         prefix[(size_t)j] = (int64_t)work.size();
+        xprefix[(size_t)j] = (int64_t)xwork.size();
         tend[(size_t)j] = S->t_host + n_steps[order[(size_t)j]];
     }
+    B->mode = mode;
     Device &dev = B->dev;
     hipStream_t s = dev.stream;
     for (int j = 0; j < P; ++j) {
@@ -1351,6 +1379,10 @@ int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const
     }
     if ((rc = upload_vec(dev, B->inst_dev, insts))) return rc;
     if ((rc = upload_vec(dev, B->work_dev, work))) return rc;
+    if (mode != 0) {
+        if ((rc = upload_vec(dev, B->sas_dev, sas))) return rc;
+        if ((rc = upload_vec(dev, B->xwork_dev, xwork))) return rc;
+    }
     DRTS_HIP(hipStreamSynchronize(s));
 
     // launches: while step < n of the j-th longest, the first j+1 solvers are active
@@ -1363,13 +1395,14 @@ int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const
         while (active < P && n_steps[order[(size_t)active]] > step) ++active;
         const int64_t seg_end = n_steps[order[(size_t)active - 1]];   // active set constant until here
         const int64_t n_work = prefix[(size_t)active - 1];
+        const int64_t n_xwork = xprefix[(size_t)active - 1];
         int64_t len = seg_end - step;
         if (len >= 2 * K) {
             if (!cap) DRTS_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
             hipGraph_t g = nullptr;
             hipGraphExec_t ge = nullptr;
             DRTS_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-            for (int k = 0; k < K && rc == DRTS_OK; ++k) rc = batch_launch(B, n_work, active, rpt, cap);
+            for (int k = 0; k < K && rc == DRTS_OK; ++k) rc = batch_launch(B, n_work, active, rpt, cap, n_xwork);
             hipError_t e = hipStreamEndCapture(cap, &g);
             if (rc == DRTS_OK && e != hipSuccess) rc = set_error(DRTS_E_HIP, "capture: %s", hipGetErrorString(e));
             if (rc == DRTS_OK && hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess)
@@ -1384,7 +1417,7 @@ int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const
             if (rc) break;
         }
         for (; len > 0; --len, ++step)
-            if ((rc = batch_launch(B, n_work, active, rpt, s))) break;
+            if ((rc = batch_launch(B, n_work, active, rpt, s, n_xwork))) break;
         if (rc) break;
     }
     if (cap) (void)hipStreamDestroy(cap);
@@ -1410,8 +1443,9 @@ int drts_batch_autotune(drts_batch_t *B, drts_options_t *chosen)
     for (int i = 0; i < n; ++i) {
         if (B->solvers[(size_t)i]->t_host != 0) return set_error(DRTS_E_STATE, "autotune before the first step");
         if (B->solvers[(size_t)i]->opt.kernel != DRTS_KERNEL_CSR)
-            return set_error(DRTS_E_INVALID, "solver %d: batches run the CSR step (kernel option)", i);
+            return set_error(DRTS_E_INVALID, "solver %d: the batch autotuner takes CSR members", i);
     }
+    B->mode = 0;
     Device &dev = B->dev;
     hipStream_t s = dev.stream;
     // every member's state and control words (exponent, maximum, absorbed

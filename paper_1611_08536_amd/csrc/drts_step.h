@@ -151,6 +151,15 @@ hipError_t launch_structured(const StructArgs &sa, const StepInst *insts_dev, co
                              int64_t n_work, int value_f64, int mode, int grid, int xcd_remap,
                              const int64_t *xcd_bounds, hipStream_t stream);
 
+// Matrix-free step of an uneven batch in one launch per kernel (FP32, modes 1
+// and 2: the direction-major tiles): sas_dev[i] holds instance i's arguments
+// (each checked on the host as launch_structured checks its own), the work
+// list (instance, chunk) covers the tiles of all active instances and the
+// x list (instance, item) their irregular and escape rows.
+hipError_t launch_structured_batch(const StructArgs *sas_dev, const StepInst *insts_dev, const WorkItem *work_dev,
+                                   int64_t n_work, const WorkItem *xwork_dev, int64_t n_xwork, int mode, int grid,
+                                   hipStream_t stream);
+
 // Matrix-free step for n_rhs > 1 (FP32 state; mode 1 = exact nearest values,
 // 2 = FP64 coefficients and FP64 row sums): the push kernel over the voxel
 // chunks of the work list, then the pull kernel over sa.xrows.

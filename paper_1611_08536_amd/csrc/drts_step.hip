@@ -1845,8 +1845,12 @@ __global__ void __launch_bounds__(256) step_struct(StructArgs sa, const StepInst
 // ---------------------------------------------------------------------------
 // Five waves per SIMD (96 VGPRs, a few spilled outside the row loop) beat
 // four without spills on the 128^3 layered workload.
-template <int MODE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) step_struct_dm(StructArgs sa, const StepInst *__restrict__ insts,
+// BATCH: the work items belong to several instances, each with its own
+// arguments in sas[item.inst] (an uneven batch in one launch); otherwise all
+// items use sa0.
+template <int MODE, bool BATCH>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) step_struct_dm(StructArgs sa0, const StructArgs *__restrict__ sas,
+                                                       const StepInst *__restrict__ insts,
                                                        const WorkItem *__restrict__ work, int64_t n_work,
                                                        int xcd_remap, const int64_t *__restrict__ xcd_bounds)
 {
@@ -1872,17 +1876,30 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
     float *s_y = s_dm + 3 * SEGF;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    for (int q = tid; q < sa.n_mat; q += NT) s_idx[q] = gp(sa.index)[q];
-    __syncthreads();
-    // bit qu * kStructMatLds + qw: materials qu and qw have the same index
+    // per instance: bit qu * kStructMatLds + qw of same_idx says materials qu
+    // and qw have the same index; n_words is the size of the row bitmap
     uint64_t same_idx = 0;
-    for (int a = 0; a < sa.n_mat; ++a)
-        for (int b = 0; b < sa.n_mat; ++b)
-            if (s_idx[a] == s_idx[b]) same_idx |= 1ull << (a * kStructMatLds + b);
-    const int64_t n_words = (sa.n_states + 31) / 32;
+    int64_t n_words = 0;
+    int cached = -1;
+    auto setup = [&](const StructArgs &s) {
+        __syncthreads();   // every thread is done with the previous instance's table
+        for (int q = tid; q < s.n_mat; q += NT) s_idx[q] = gp(s.index)[q];
+        __syncthreads();
+        same_idx = 0;
+        for (int a = 0; a < s.n_mat; ++a)
+            for (int b = 0; b < s.n_mat; ++b)
+                if (s_idx[a] == s_idx[b]) same_idx |= 1ull << (a * kStructMatLds + b);
+        n_words = (s.n_states + 31) / 32;
+    };
+    if (!BATCH) setup(sa0);
     const Walk wk = walk_of(n_work, xcd_remap, xcd_bounds);
     for (int64_t wi = wk.begin; wi < wk.end; wi += wk.stride) {
         const WorkItem item = work[wi];
+        const StructArgs &sa = BATCH ? sas[item.inst] : sa0;
+        if (BATCH && item.inst != cached) {
+            setup(sa);
+            cached = item.inst;
+        }
         const StepInst &I = insts[item.inst];
         const int64_t t = I.t[0];
         if (t >= *I.t_end) continue;
@@ -2064,8 +2081,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
 // rows, listed in ascending order in sa.xrows, kStructXRows per work item.
 // Each row is built from its move lists (struct_row) with x from global
 // memory; its partials go to chunk sa.chunk_base + item.
-template <typename VT, int MODE>
-__global__ void __launch_bounds__(256) step_struct_x(StructArgs sa, const StepInst *__restrict__ insts)
+template <typename VT, int MODE, bool BATCH>
+__global__ void __launch_bounds__(256) step_struct_x(StructArgs sa0, const StructArgs *__restrict__ sas,
+                                                      const StepInst *__restrict__ insts,
+                                                      const WorkItem *__restrict__ xwork, int64_t n_xwork)
 {
     constexpr int NT = 256, NW = NT / 64, XR = kStructXRows;
     __shared__ VT s_y[XR];
@@ -2074,18 +2093,28 @@ __global__ void __launch_bounds__(256) step_struct_x(StructArgs sa, const StepIn
     __shared__ double s_wred[4][NW];
     __shared__ double s_red[NT];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const StepInst &I = insts[0];
-    const int64_t t = I.t[0];
-    if (t >= *I.t_end) return;
-    const Scale sc = step_scale(I, 0, t);
-    const VT scale = (VT)ldexp(1.0, -sc.k);
-    const GLB VT *x = gp((const VT *)((t & 1) ? I.buf1 : I.buf0));
-    GLB VT *y = gpw((VT *)((t & 1) ? I.buf0 : I.buf1));
-    const GLB int64_t *xrows = gp(sa.xrows);
-    const int64_t n_items = (sa.n_xrows + XR - 1) / XR;
-    for (int q = tid; q < I.n_mat; q += NT) s_abs[q] = gp(I.absorb)[q];
-    __syncthreads();
-    for (int64_t j = blockIdx.x; j < n_items; j += gridDim.x) {
+    int cached = -1;
+    // one instance (its work items 0 .. n_items - 1) or the batch's list of
+    // (instance, item) pairs
+    const int64_t n_iter = BATCH ? n_xwork : (sa0.n_xrows + XR - 1) / XR;
+    for (int64_t wq = blockIdx.x; wq < n_iter; wq += gridDim.x) {
+        const WorkItem it = BATCH ? xwork[wq] : WorkItem{0, (int32_t)wq};
+        const StructArgs &sa = BATCH ? sas[it.inst] : sa0;
+        const StepInst &I = insts[it.inst];
+        const int64_t t = I.t[0];
+        if (t >= *I.t_end) continue;
+        if (it.inst != cached) {
+            __syncthreads();   // every thread is done with the previous instance's table
+            for (int q = tid; q < I.n_mat; q += NT) s_abs[q] = gp(I.absorb)[q];
+            __syncthreads();
+            cached = it.inst;
+        }
+        const Scale sc = step_scale(I, 0, t);
+        const VT scale = (VT)ldexp(1.0, -sc.k);
+        const GLB VT *x = gp((const VT *)((t & 1) ? I.buf1 : I.buf0));
+        GLB VT *y = gpw((VT *)((t & 1) ? I.buf0 : I.buf1));
+        const GLB int64_t *xrows = gp(sa.xrows);
+        const int64_t j = it.chunk;
         const int64_t k0 = j * XR;
         const int n = (int)min((int64_t)XR, sa.n_xrows - k0);
         double sN = 0.0, sE = 0.0, sA = 0.0;
@@ -2521,10 +2550,10 @@ hipError_t launch_structured(const StructArgs &sa, const StepInst *insts_dev, co
             hipLaunchKernelGGL((step_struct<float, 0>), g, b, 0, stream, sa, insts_dev, work_dev, n_work,
                                xcd_remap & 1, xcd_bounds);
         } else if (mode == 1) {
-            hipLaunchKernelGGL((step_struct_dm<1>), g, b, dm, stream, sa, insts_dev, work_dev, n_work, xcd_remap & 1,
+            hipLaunchKernelGGL((step_struct_dm<1, false>), g, b, dm, stream, sa, nullptr, insts_dev, work_dev, n_work, xcd_remap & 1,
                                xcd_bounds);
         } else if (mode == 2) {
-            hipLaunchKernelGGL((step_struct_dm<2>), g, b, dm, stream, sa, insts_dev, work_dev, n_work, xcd_remap & 1,
+            hipLaunchKernelGGL((step_struct_dm<2, false>), g, b, dm, stream, sa, nullptr, insts_dev, work_dev, n_work, xcd_remap & 1,
                                xcd_bounds);
         } else {
             hipLaunchKernelGGL((step_struct<float, 3>), g, b, 0, stream, sa, insts_dev, work_dev, n_work,
@@ -2537,11 +2566,41 @@ hipError_t launch_structured(const StructArgs &sa, const StepInst *insts_dev, co
         const int64_t items = (sa.n_xrows + kStructXRows - 1) / kStructXRows;
         const dim3 gx((unsigned)min(items, (int64_t)grid));
         if (value_f64)
-            hipLaunchKernelGGL((step_struct_x<double, 0>), gx, b, 0, stream, sa, insts_dev);
+            hipLaunchKernelGGL((step_struct_x<double, 0, false>), gx, b, 0, stream, sa, nullptr, insts_dev, nullptr, 0);
         else if (mode == 0 || mode == 1)
-            hipLaunchKernelGGL((step_struct_x<float, 0>), gx, b, 0, stream, sa, insts_dev);
+            hipLaunchKernelGGL((step_struct_x<float, 0, false>), gx, b, 0, stream, sa, nullptr, insts_dev, nullptr, 0);
         else
-            hipLaunchKernelGGL((step_struct_x<float, 2>), gx, b, 0, stream, sa, insts_dev);
+            hipLaunchKernelGGL((step_struct_x<float, 2, false>), gx, b, 0, stream, sa, nullptr, insts_dev, nullptr, 0);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_structured_batch(const StructArgs *sas_dev, const StepInst *insts_dev, const WorkItem *work_dev,
+                                   int64_t n_work, const WorkItem *xwork_dev, int64_t n_xwork, int mode, int grid,
+                                   hipStream_t stream)
+{
+    if (mode != 1 && mode != 2) return hipErrorInvalidValue;
+    const size_t dm = (size_t)(3 * (kStructDmSeg + 2) + kStructDmSeg) * kDirs * sizeof(float);
+    const dim3 b(256);
+    if (n_work > 0) {
+        const dim3 g((unsigned)std::min<int64_t>(grid, std::max<int64_t>((n_work + kXcds - 1) / kXcds * kXcds, kXcds)));
+        if (mode == 1)
+            hipLaunchKernelGGL((step_struct_dm<1, true>), g, b, dm, stream, StructArgs{}, sas_dev, insts_dev, work_dev,
+                               n_work, 0, nullptr);
+        else
+            hipLaunchKernelGGL((step_struct_dm<2, true>), g, b, dm, stream, StructArgs{}, sas_dev, insts_dev, work_dev,
+                               n_work, 0, nullptr);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (n_xwork > 0) {
+        const dim3 gx((unsigned)std::min<int64_t>(n_xwork, (int64_t)grid));
+        if (mode == 1)
+            hipLaunchKernelGGL((step_struct_x<float, 0, true>), gx, b, 0, stream, StructArgs{}, sas_dev, insts_dev,
+                               xwork_dev, n_xwork);
+        else
+            hipLaunchKernelGGL((step_struct_x<float, 2, true>), gx, b, 0, stream, StructArgs{}, sas_dev, insts_dev,
+                               xwork_dev, n_xwork);
     }
     return hipGetLastError();
 }

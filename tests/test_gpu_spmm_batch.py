@@ -4,7 +4,8 @@ Bars: each right-hand side against the FP64 oracle run of its own sources
 (1e-5); each SpMM column against the single-rhs SpMV run of the same source
 (bit-exact state: the per-row sums are the same operations in the same order);
 each batch member against the same solver run alone (bit-exact state and
-series); autotuned launch shapes against the defaults (bit-exact state).
+series), with the CSR step and with the matrix-free step; autotuned launch
+shapes against the defaults (bit-exact state).
 """
 import numpy as np
 import pytest
@@ -116,6 +117,53 @@ def test_batch_autotune_keeps_results():
         B.autotune()          # members have stepped
 
 
+def _mf_batch(kernel, n=6):
+    """Sphere-inclusion media (Fresnel interfaces, detectors), nearest-rounded
+    values, as matrix-free solvers with the given kernel."""
+    import dataclasses
+    reqs = W.c5(n_req=n, rate=1e6, edge=(10, 16), steps=(30, 60))
+    wls = [dataclasses.replace(q.workload, rounding="nearest") for q in reqs]
+    opts = {"kernel": kernel, "tiles_per_chunk": 2}
+    mats = [drts.Matrix(w.medium, w.value_type, w.rounding, w.n_ref) for w in wls]
+    solvers = [drts.Solver(m, 1, w.detectors, max_steps=w.n_steps) for m, w in zip(mats, wls)]
+    for S in solvers:
+        S.set_options(**opts)
+    tabs = [solve.source_table(m, w) for m, w in zip(mats, wls)]
+    return wls, mats, solvers, tabs, opts
+
+
+@pytest.mark.parametrize("kernel", [1, 2], ids=["exact", "f64sum"])
+def test_matrix_free_batch_members_equal_solo_runs(kernel):
+    """Matrix-free members advanced together (one launch per kernel and step)
+    equal the same solvers run alone: states, exponents, totals and detector
+    series bit for bit."""
+    wls, mats, solvers, tabs, opts = _mf_batch(kernel)
+    steps = [w.n_steps for w in wls]
+    B = drts.Batch(solvers)
+    B.run(tabs, steps)
+    for i, (w, m, S) in enumerate(zip(wls, mats, solvers)):
+        solo = solve.run(w, n_steps=steps[i], matrix=m, options=opts)
+        x, e, t = S.state()
+        assert t == steps[i]
+        assert np.array_equal(x, solo["x"]) and np.array_equal(e, solo["x_exp"]), i
+        r = S.readout(0, steps[i])
+        for k in ("tot", "exp2", "det"):
+            assert np.array_equal(r[k], solo[k]), (i, k)
+
+
+def test_matrix_free_batch_against_oracle():
+    wls, mats, solvers, tabs, _ = _mf_batch(2, n=4)
+    B = drts.Batch(solvers)
+    B.run(tabs, [w.n_steps for w in wls])
+    for i, w in enumerate(wls):
+        ref = oracle.run_workload(oracle.Matrix(w.medium), w)
+        r = solvers[i].readout(0, w.n_steps)
+        err = parity.rel_err_series(r["tot"][:, 0, 0], r["exp2"][:, 0], ref["tot"][:, 0], ref["tot_exp"][:, 0])
+        assert err <= 1e-5, (i, err)
+        err = parity.rel_err_series(r["det"][:, 0, 0], r["exp2"][:, 0], ref["det"][:, 0], ref["det_exp"][:, 0])
+        assert err <= 1e-5, (i, "det", err)
+
+
 def test_batch_against_oracle_and_continues():
     wls = _c4_small(n_inst=5, edge=(8, 12))
     mats = [drts.Matrix(w.medium, w.value_type, w.rounding, w.n_ref) for w in wls]
@@ -146,15 +194,23 @@ def test_batch_rejects_mixed_inputs():
         drts.Batch([s32, s64])
     with pytest.raises(drts.DrtsError):
         drts.Batch([s32, s32])
-    # a member switched to the matrix-free step: the batch runs the CSR step only
+    # every member needs the same step: CSR with matrix-free (the exact
+    # matrix-free step of dithered values, mode 0, or FP64 row sums) is refused,
+    # and so is a batch of mode-0 members (the gather kernel has no batch form)
     m_mf = drts.Matrix(w32.medium, "f32")
     s_mf = drts.Solver(m_mf, 1, [], max_steps=5)
     B = drts.Batch([s32, s_mf])
+    for k in (drts.KERNEL_STRUCTURED, drts.KERNEL_STRUCTURED_F64SUM):
+        s_mf.set_options(kernel=k)
+        with pytest.raises(drts.DrtsError):
+            B.autotune()
+        with pytest.raises(drts.DrtsError):
+            B.run([None, None], [2, 2])
+    s32.set_options(kernel=drts.KERNEL_STRUCTURED)
     s_mf.set_options(kernel=drts.KERNEL_STRUCTURED)
     with pytest.raises(drts.DrtsError):
-        B.autotune()
-    with pytest.raises(drts.DrtsError):
         B.run([None, None], [2, 2])
+    s32.set_options(kernel=drts.KERNEL_CSR)
     s_mf.set_options(kernel=drts.KERNEL_CSR)
     B.run([None, None], [2, 2])
     assert s32.state()[2] == 2 and s_mf.state()[2] == 2
