@@ -365,10 +365,12 @@ int drts_serve_create(const drts_device_t *dev, int64_t budget_bytes, int32_t qu
 /* Selects the step of the requests admitted from now on: DRTS_KERNEL_CSR
  * (the default: all CSR requests advance together, one batched launch per
  * step) or a matrix-free kernel (DRTS_KERNEL_STRUCTURED or
- * DRTS_KERNEL_STRUCTURED_F64SUM: each such request runs its quantum with its
- * own graph-replayed drts_run, in turn, on the server's stream, with 8 tiles
- * per chunk and 16 workgroups per CU).  A served result equals the same
- * solve run alone with the same options, bit for bit.  The matrix is still
+ * DRTS_KERNEL_STRUCTURED_F64SUM, with 8 tiles per chunk and 16 workgroups
+ * per CU): the matrix-free requests that a batch takes (FP64 row sums, or
+ * exact values when nearest-rounded; at most 8 materials) advance together
+ * as a second batch, any other runs its quantum with its own graph-replayed
+ * drts_run, all in turn on the server's stream.  A served result equals the
+ * same solve run alone with the same options, bit for bit.  The matrix is still
  * assembled (and counted in the footprint).  DRTS_E_INVALID for another
  * kernel.  Thread-safe like drts_serve_submit. */
 int drts_serve_set_step(drts_server_t *Q, int32_t kernel);

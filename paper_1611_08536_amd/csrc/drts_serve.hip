@@ -20,6 +20,7 @@
 
 #include "drts.h"
 #include "drts_internal.h"
+#include "drts_step.h"
 
 using namespace drts;
 
@@ -47,6 +48,7 @@ struct Request {
     drts_matrix_t *A = nullptr;
     drts_solver_t *S = nullptr;
     int32_t kernel = DRTS_KERNEL_CSR;   // the step it runs, fixed at admission
+    bool batched_mf = false;            // matrix-free with direction-major tiles: joins the matrix-free batch
     bool finished = false;
     // results, copied at retirement
     std::vector<double> series, totals;
@@ -87,12 +89,14 @@ struct drts_server {
     std::vector<Request *> active;
     std::map<int64_t, std::unique_ptr<Request>> all;
     std::deque<int64_t> unreported;
-    drts_batch_t *batch = nullptr;
+    drts_batch_t *batch = nullptr;      // the admitted CSR requests
+    drts_batch_t *mf_batch = nullptr;   // the admitted matrix-free requests
     bool batch_dirty = true;
 
     ~drts_server()
     {
         if (batch) drts_batch_destroy(batch);
+        if (mf_batch) drts_batch_destroy(mf_batch);
     }
 };
 
@@ -181,6 +185,12 @@ int admit(drts_server *Q, Request &q)
         return rc;
     }
     q.kernel = Q->kernel;
+    if (q.kernel != DRTS_KERNEL_CSR) {
+        // the direction-major modes batch: FP64 row sums, or exact values when
+        // nearest-rounded, with at most 8 materials
+        const bool f64sum = q.kernel == DRTS_KERNEL_STRUCTURED_F64SUM;
+        q.batched_mf = q.med.n_mat <= kStructMatLdsHost && (f64sum || q.med.rounding == DRTS_ROUND_NEAREST);
+    }
     int64_t n_states = 0, n_escape = 0, nnz = 0, mbytes = 0;
     double dt = 0;
     drts_matrix_info(q.A, &n_states, &n_escape, &nnz, &mbytes, &dt);
@@ -329,32 +339,45 @@ int drts_serve_tick(drts_server_t *Q, int32_t *n_active, int32_t *n_waiting, int
         passed.push_back(&q);
         ++it;
     }
-    // 2. one quantum for every admitted request: the CSR ones as one batch
-    //    (one launch per step), the matrix-free ones each with its own
-    //    graph-replayed run, in turn on the same stream
+    // 2. one quantum for every admitted request: the CSR ones as one batch,
+    //    the matrix-free ones of the batched kind (direction-major tiles) as
+    //    another (one launch per kernel and step each), any other
+    //    matrix-free one with its own graph-replayed run, all in turn on the
+    //    same stream
     if (!Q->active.empty()) {
-        std::vector<Request *> csr, mf;
-        for (Request *q : Q->active) (q->kernel == DRTS_KERNEL_CSR ? csr : mf).push_back(q);
+        std::vector<Request *> csr, mf, solo;
+        for (Request *q : Q->active) {
+            if (q->kernel == DRTS_KERNEL_CSR) csr.push_back(q);
+            else if (q->batched_mf) mf.push_back(q);
+            else solo.push_back(q);
+        }
         if (Q->batch_dirty) {
-            if (Q->batch) drts_batch_destroy(Q->batch);
-            Q->batch = nullptr;
-            std::vector<drts_solver_t *> ss;
-            for (Request *q : csr) ss.push_back(q->S);
-            if (!ss.empty() && (rc = drts_batch_create(ss.data(), (int32_t)ss.size(), &Q->dev, &Q->batch)))
-                return rc;
+            for (drts_batch_t **b : {&Q->batch, &Q->mf_batch}) {
+                if (*b) drts_batch_destroy(*b);
+                *b = nullptr;
+            }
+            for (int k = 0; k < 2; ++k) {
+                std::vector<drts_solver_t *> ss;
+                for (Request *q : (k == 0 ? csr : mf)) ss.push_back(q->S);
+                if (!ss.empty() && (rc = drts_batch_create(ss.data(), (int32_t)ss.size(), &Q->dev,
+                                                           k == 0 ? &Q->batch : &Q->mf_batch)))
+                    return rc;
+            }
             Q->batch_dirty = false;
         }
-        if (!csr.empty()) {
+        for (int k = 0; k < 2; ++k) {
+            std::vector<Request *> &group = k == 0 ? csr : mf;
+            if (group.empty()) continue;
             std::vector<const drts_source_table_t *> tabs;
             std::vector<int64_t> steps;
-            for (Request *q : csr) {
+            for (Request *q : group) {
                 tabs.push_back(q->src);
                 steps.push_back(std::min<int64_t>(Q->quantum, q->n_steps - q->done));
             }
-            if ((rc = drts_batch_run(Q->batch, tabs.data(), steps.data()))) return rc;
-            for (size_t i = 0; i < csr.size(); ++i) csr[i]->done += steps[i];
+            if ((rc = drts_batch_run(k == 0 ? Q->batch : Q->mf_batch, tabs.data(), steps.data()))) return rc;
+            for (size_t i = 0; i < group.size(); ++i) group[i]->done += steps[i];
         }
-        for (Request *q : mf) {
+        for (Request *q : solo) {
             const int64_t n = std::min<int64_t>(Q->quantum, q->n_steps - q->done);
             if ((rc = drts_run(q->S, q->src, n))) return rc;
             q->done += n;
@@ -371,10 +394,12 @@ int drts_serve_tick(drts_server_t *Q, int32_t *n_active, int32_t *n_waiting, int
             }
         }
         Q->active.swap(keep);
-        if (Q->batch_dirty && Q->batch) {
-            // the batch refers to retired solvers: drop it before anything else runs
-            drts_batch_destroy(Q->batch);
-            Q->batch = nullptr;
+        if (Q->batch_dirty) {
+            // the batches refer to retired solvers: drop them before anything else runs
+            for (drts_batch_t **b : {&Q->batch, &Q->mf_batch}) {
+                if (*b) drts_batch_destroy(*b);
+                *b = nullptr;
+            }
         }
     }
     if (n_active) *n_active = (int32_t)Q->active.size();

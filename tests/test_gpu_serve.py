@@ -79,10 +79,12 @@ def test_served_results_against_oracle():
         assert err <= 1e-5, (i, "det", err)
 
 
-def test_matrix_free_served_results_equal_solo_runs_and_oracle():
+@pytest.mark.parametrize("k", [1, 2], ids=["exact_dithered_solo", "f64sum_batched"])
+def test_matrix_free_served_results_equal_solo_runs_and_oracle(k):
+    """Dithered values with the exact matrix-free step (the gather kernel)
+    run request by request; FP64 row sums run as one matrix-free batch."""
     reqs = _requests(6)
     fps = sorted(_footprints(reqs))
-    k = drts.KERNEL_STRUCTURED_F64SUM
     out = serve.serve(reqs, sum(fps[-3:]), quantum=16, max_active=4, max_skips=2, policy="shortest",
                       keep_results=True, kernel=k)
     assert 2 <= out["peak_active"] < len(reqs), out["peak_active"]
