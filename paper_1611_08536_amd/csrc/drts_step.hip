@@ -180,6 +180,8 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, ui
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)n, 0x00020000);
 }
 constexpr int kStream = 2;  // cache policy bits of a buffer load: nontemporal
+// s_waitcnt immediate (gfx9 encoding): vmcnt <= 1, expcnt and lgkmcnt not waited on
+constexpr int kWaitVm1 = 0x0F71;
 
 template <typename VT> struct BufQuad;
 template <> struct BufQuad<float> {
@@ -339,8 +341,12 @@ __device__ __forceinline__ void issue_tile_l(TileRegsL<IT, U> &T, const GLB IT *
     }
 }
 
-template <typename IT, int NT, int U, int R>
-__device__ __forceinline__ float finish_tile_l(const TileRegsL<IT, U> &T, __amdgpu_buffer_rsrc_t rx, float *s_prod)
+// after_gathers runs once the gathers are issued; when it issues one store
+// from this wave (stored), the wait leaves that store, the newest memory
+// operation, in flight
+template <typename IT, int NT, int U, int R, typename F>
+__device__ __forceinline__ float finish_tile_l(const TileRegsL<IT, U> &T, __amdgpu_buffer_rsrc_t rx, float *s_prod,
+                                               F after_gathers, bool stored)
 {
     const int tid = threadIdx.x;
     float xv[U][4];
@@ -348,9 +354,12 @@ __device__ __forceinline__ float finish_tile_l(const TileRegsL<IT, U> &T, __amdg
     for (int k = 0; k < U; ++k)
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) xv[k][jj] = BufQuad<float>::gather(rx, T.qc[k][jj]);
+    after_gathers();
     // the values of this lane's quads are in LDS once every load of the lane
-    // has completed
-    __builtin_amdgcn_s_waitcnt(0);
+    // has completed (the compiler does not order LDS reads after
+    // LDS-destination loads by itself)
+    if (stored) __builtin_amdgcn_s_waitcnt(kWaitVm1);
+    else __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll
     for (int k = 0; k < U; ++k) {
         f4 *slot = (f4 *)(s_prod + 4 * (tid + k * NT));
@@ -461,7 +470,7 @@ __device__ __forceinline__ VT finish_tile_s(const TileRegsS<VT, IT, S> &T, __amd
 // layout (one row per thread, no pipelining); LAY = 2: quads with the values
 // loaded straight into LDS (FP32 values only, no pipelining); LAY = 0: quads.
 template <typename VT, typename IT, int NT, int R, int PIPE, int LAY>
-__global__ void __launch_bounds__(NT) step_spmv(const StepInst *__restrict__ insts,
+__global__ void __launch_bounds__(NT, (LAY == 2 ? 5 : 1)) step_spmv(const StepInst *__restrict__ insts,
                                                  const WorkItem *__restrict__ work, int64_t n_work,
                                                  int xcd_remap, const int64_t *__restrict__ xcd_bounds,
                                                  int32_t *__restrict__ queue)
@@ -482,6 +491,28 @@ __global__ void __launch_bounds__(NT) step_spmv(const StepInst *__restrict__ ins
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const Walk wk = walk_of(n_work, xcd_remap, xcd_bounds);
+    // LDS layout: a tile's y values are stored only after the next tile's
+    // gathers have been issued, so the wait for those gathers (and for the
+    // values landing in LDS) need not wait for the store as well.  The pending
+    // tile: its y, first row and row count (uniform), each lane's value.
+    GLB VT *pend_y = nullptr;
+    int64_t pend_r0 = 0;
+    int pend_nr = 0;
+    VT pend_v = 0;
+    auto flush = [&]() {
+        if (pend_y) {
+            // a buffer store: the tile's base in SGPRs, each lane's 32-bit offset
+            if (threadIdx.x < pend_nr && (int)threadIdx.x < R) {
+                if constexpr (sizeof(VT) == 4)
+                    __builtin_amdgcn_raw_buffer_store_b32(
+                        __builtin_bit_cast(uint32_t, pend_v),
+                        make_rsrc((const void *)(pend_y + pend_r0), (uint64_t)pend_nr * 4), (int)(4 * threadIdx.x), 0, 0);
+                else
+                    pend_y[pend_r0 + threadIdx.x] = pend_v;
+            }
+            pend_y = nullptr;
+        }
+    };
     // work items come from a global counter (dynamic balance) or a fixed walk
     int64_t wi = wk.begin;
     int cached = -1;
@@ -552,7 +583,10 @@ __global__ void __launch_bounds__(NT) step_spmv(const StepInst *__restrict__ ins
                     TileRegsL<IT, U> tl;
                     issue_tile_l<IT, NT, U, R>(tl, rp, col, (const GLB float *)val, mat, s_tb[j], s_tb[j + 1], r0, nr,
                                                n_states, I.nnz, (float *)s_prod);
-                    acc = finish_tile_l<IT, NT, U, R>(tl, rx, (float *)s_prod);
+                    // the previous tile's store goes out after this tile's
+                    // gathers; a wave that issued it then waits for all but it
+                    const bool mine = pend_y != nullptr && 64 * wave < pend_nr;
+                    acc = finish_tile_l<IT, NT, U, R>(tl, rx, (float *)s_prod, [&]() { flush(); }, mine);
                     q = tl.q;
                 }
             } else if (LAYV == 1 && fits(j)) {
@@ -611,6 +645,8 @@ __global__ void __launch_bounds__(NT) step_spmv(const StepInst *__restrict__ ins
             }
 
             // epilogue: rescale, sources, store, FP64 totals
+            constexpr bool kDefer = LAYV == 2 && sizeof(VT) == 4;
+            if (kDefer) flush();   // a store still pending (a multi-pass tile did not issue it)
             if (own) {
                 VT v = acc * scale;
                 const int sb = s_src[j], se = s_src[j + 1];
@@ -625,7 +661,8 @@ __global__ void __launch_bounds__(NT) step_spmv(const StepInst *__restrict__ ins
                     }
                     if (any) v += (VT)ldexp(s, -sc.En);
                 }
-                y[r] = v;
+                if (kDefer) pend_v = v;
+                else y[r] = v;
                 s_y[tid] = v;
                 if (r < n_states) {
                     sN += (double)v;
@@ -634,6 +671,11 @@ __global__ void __launch_bounds__(NT) step_spmv(const StepInst *__restrict__ ins
                 } else {
                     sE += (double)v;
                 }
+            }
+            if (kDefer) {
+                pend_y = y;
+                pend_r0 = r0;
+                pend_nr = nr;
             }
             __syncthreads();
             const int db = s_det[j], de = s_det[j + 1];
@@ -660,6 +702,7 @@ __global__ void __launch_bounds__(NT) step_spmv(const StepInst *__restrict__ ins
         }
         if (tid < I.n_det) part[(int64_t)(kSlotDet + tid) * nc + c] = dsum;
     }
+    flush();
 }
 
 // value of lane l (uniform l) of a 64-bit per-lane value
