@@ -179,6 +179,17 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, ui
     const uint32_t n = bytes >= 0xffffffffull ? 0xffffffffu : (uint32_t)bytes;
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)n, 0x00020000);
 }
+// A value every lane holds the same, made a scalar: loads of control words
+// from device memory land in vector registers, and anything derived from
+// them (the state buffer chosen by the step's parity, the buffer descriptors
+// built on it) would otherwise need a per-lane descriptor loop at every use.
+__device__ __forceinline__ int64_t scalar_i64(int64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 constexpr int kStream = 2;  // cache policy bits of a buffer load: nontemporal
 // s_waitcnt immediate (gfx9 encoding): vmcnt <= 1, expcnt and lgkmcnt not waited on
 constexpr int kWaitVm1 = 0x0F71;
@@ -1428,7 +1439,7 @@ __global__ void __launch_bounds__(kNT) finalize_seg(const StepInst *__restrict__
     const int rhs = blockIdx.z;
     if (rhs >= I.n_rhs) return;
     const int64_t t = I.t[rhs];
-    if (t >= *I.t_end) return;
+    if (t >= scalar_i64(*I.t_end)) return;
     const int64_t nc = I.n_chunks;
     const int nseg = (int)min((int64_t)kFinSeg, nc);
     const int seg = blockIdx.x;
@@ -1478,7 +1489,7 @@ __global__ void __launch_bounds__(kNT) finalize_step(const StepInst *__restrict_
     const int rhs = blockIdx.y;
     if (rhs >= I.n_rhs) return;
     const int64_t t = I.t[rhs];
-    if (t >= *I.t_end) return;
+    if (t >= scalar_i64(*I.t_end)) return;
     const int64_t nc = I.n_chunks;
     const int nseg = (int)min((int64_t)kFinSeg, nc);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1788,8 +1799,8 @@ __global__ void __launch_bounds__(256) step_struct(StructArgs sa, const StepInst
     for (int64_t wi = wk.begin; wi < wk.end; wi += wk.stride) {
         const WorkItem item = work[wi];
         const StepInst &I = insts[item.inst];
-        const int64_t t = I.t[0];
-        if (t >= *I.t_end) continue;
+        const int64_t t = scalar_i64(I.t[0]);
+        if (t >= scalar_i64(*I.t_end)) continue;
         const Scale sc = step_scale(I, 0, t);
         const VT scale = (VT)ldexp(1.0, -sc.k);
         const GLB VT *x = gp((const VT *)((t & 1) ? I.buf1 : I.buf0));
@@ -1944,8 +1955,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
             cached = item.inst;
         }
         const StepInst &I = insts[item.inst];
-        const int64_t t = I.t[0];
-        if (t >= *I.t_end) continue;
+        const int64_t t = scalar_i64(I.t[0]);
+        if (t >= scalar_i64(*I.t_end)) continue;
         const Scale sc = step_scale(I, 0, t);
         const float scale = ldexpf(1.0f, -sc.k);
         const float *x = (const float *)((t & 1) ? I.buf1 : I.buf0);
@@ -2144,8 +2155,8 @@ __global__ void __launch_bounds__(256) step_struct_x(StructArgs sa0, const Struc
         const WorkItem it = BATCH ? xwork[wq] : WorkItem{0, (int32_t)wq};
         const StructArgs &sa = BATCH ? sas[it.inst] : sa0;
         const StepInst &I = insts[it.inst];
-        const int64_t t = I.t[0];
-        if (t >= *I.t_end) continue;
+        const int64_t t = scalar_i64(I.t[0]);
+        if (t >= scalar_i64(*I.t_end)) continue;
         if (it.inst != cached) {
             __syncthreads();   // every thread is done with the previous instance's table
             for (int q = tid; q < I.n_mat; q += NT) s_abs[q] = gp(I.absorb)[q];
@@ -2259,8 +2270,8 @@ __global__ void __launch_bounds__(256) step_struct_mm(StructArgs sa, const StepI
     const StepInst &I = insts[0];
     for (int q = tid; q < I.n_mat; q += NT) s_abs[q] = gp(I.absorb)[q];
     __syncthreads();
-    const int64_t t = I.t[0];
-    if (t >= *I.t_end) return;
+    const int64_t t = scalar_i64(I.t[0]);
+    if (t >= scalar_i64(*I.t_end)) return;
     const int nrhs = I.n_rhs;
     const bool active = lane < nrhs;
     const int xl = min(lane, nrhs - 1);
@@ -2386,8 +2397,8 @@ __global__ void __launch_bounds__(256) step_struct_mm_x(StructArgs sa, const Ste
     const StepInst &I = insts[0];
     for (int q = tid; q < I.n_mat; q += NT) s_abs[q] = gp(I.absorb)[q];
     __syncthreads();
-    const int64_t t = I.t[0];
-    if (t >= *I.t_end) return;
+    const int64_t t = scalar_i64(I.t[0]);
+    if (t >= scalar_i64(*I.t_end)) return;
     const int nrhs = I.n_rhs, nd = I.n_det;
     const bool active = lane < nrhs;
     const int xl = min(lane, nrhs - 1);
