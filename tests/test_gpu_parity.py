@@ -282,6 +282,36 @@ def test_ragged_tail_and_tiny_tiles(variant):
     assert parity.rel_l1(out["x"][:A.n_states, 0], out["x_exp"][0], ref["x"], ref["x_exp"]) <= 1e-5
 
 
+@pytest.mark.parametrize("rpt,tpc", [(64, 1), (64, 4), (256, 2)])
+def test_multi_pass_tiles_between_fitting_tiles(rpt, tpc):
+    """Refractive index alternating every z-plane: rows crossing a plane hold
+    the transmitted and the reflected group (about 45 entries), so many tiles
+    exceed the stage (28 entries per row) and take the multi-pass path between
+    tiles that fit.  The LDS layout (whose y stores wait for the next tile)
+    equals the plain layout bit for bit, and the oracle within 1e-5."""
+    n = 6
+    mp = np.zeros((n, n, n), dtype=np.uint8)
+    mp[1::2] = 1
+    med = W.Medium(n, n, n, 0.1, [W.Material(5.0, 0.02, 0.8, 1.33), W.Material(8.0, 0.03, 0.85, 1.45)], mp,
+                   "voxels", "vacuum")
+    wl = W.Workload("alternating", med, [W.point_source(3, 3, 0)], [W.face_escape_detector(med, "bottom")], 40, 1,
+                    "f32", "nearest", 1.33)
+    A = oracle.Matrix(med)
+    rp = A.row_ptr
+    per_tile = [(rp[min((k + 1) * rpt, A.n_rows)] - rp[k * rpt]) / rpt for k in range((A.n_rows + rpt - 1) // rpt)]
+    assert any(a > 28 for a in per_tile) and any(a <= 27 for a in per_tile)
+    got = {}
+    for v in (0, 7):
+        got[v] = solve.run(wl, options={"rows_per_tile": rpt, "tiles_per_chunk": tpc, "grid": 16, "variant": v})
+    for k in ("x", "x_exp", "tot", "exp2", "det"):
+        assert np.array_equal(got[0][k], got[7][k]), k
+    ref = oracle.run_workload(A, wl)
+    out = got[7]
+    assert parity.rel_err_series(out["det"][:, 0, 0], out["exp2"][:, 0], ref["det"][:, 0],
+                                 ref["det_exp"][:, 0]) <= 1e-5
+    assert parity.rel_l1(out["x"][:A.n_states, 0], out["x_exp"][0], ref["x"], ref["x_exp"]) <= 1e-5
+
+
 def test_errors_are_reported():
     wl = W.c2(n=8)
     M = drts.Matrix(wl.medium, "f32")
