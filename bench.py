@@ -9,7 +9,7 @@ injection, FP64 totals and detector sums, plus the finalize reduction.  The
 matrix is assembled on the device before the timed region; inputs are
 resident in HBM when timing starts.
 
-Prints one JSON line.  --gpus above 1 exits: this build runs on one GPU.
+Prints one JSON line.  --gpus above 1 exits: the step runs on one GPU.
 """
 from __future__ import annotations
 
