@@ -324,8 +324,9 @@ int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const
  * steps of every member at once for each candidate, then restores every
  * member's state and control words and keeps the fastest shape in all
  * members' options (chosen, may be NULL, receives it; its grid is the
- * batch's).  Before the first step of every member (DRTS_E_STATE otherwise);
- * results stay equal to solo runs with the same options, bit for bit. */
+ * batch's).  Before the first step of every member (DRTS_E_STATE otherwise)
+ * and for CSR members only (DRTS_E_INVALID otherwise); results stay equal to
+ * solo runs with the same options, bit for bit. */
 int drts_batch_autotune(drts_batch_t *B, drts_options_t *chosen);
 
 void drts_batch_destroy(drts_batch_t *B);
