@@ -1,0 +1,70 @@
+"""Host logic of the benchmark: the HBM traffic figure from two rocprofv3
+counter passes, and the rule that a committed figure counts only for the
+kernel sources it was taken on."""
+import csv
+import importlib.util
+import json
+import os
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def _counters(path, counter, rows):
+    """A counter_collection.csv with (kernel, value in KiB) rows."""
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        for i, (k, v) in enumerate(rows):
+            w.writerow([i, k, counter, v])
+
+
+def test_traffic_scales_each_counter_by_the_copy_kernel(bench, tmp_path):
+    step = "void drts::(anonymous namespace)::%s(args)" % bench.SPMV_KERNEL
+    calib = "void at::native::%s<...>(args)" % bench.CALIB_KERNEL
+    gib_kib = bench.CALIB_BYTES / 1024.0
+    # the copy kernel reads 1 GiB and writes 1 GiB; its FETCH_SIZE reads half
+    _counters(tmp_path / "f.csv", "FETCH_SIZE", [(step, 1000.0), (step, 3000.0), (calib, gib_kib / 2),
+                                                 ("other", 7.0)])
+    _counters(tmp_path / "w.csv", "WRITE_SIZE", [(step, 50.0), (step, 150.0), (calib, gib_kib)])
+    t = bench.traffic_from_counters(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"))
+    assert t["fetch_kib"] == 2000.0 and t["write_kib"] == 100.0      # per-dispatch means
+    assert t["fetch_factor"] == 2.0 and t["write_factor"] == 1.0
+    assert t["bytes_per_launch"] == 2000.0 * 1024 * 2 + 100.0 * 1024
+    assert t["source_sha256"] == bench.step_source_hash()
+
+
+def test_traffic_needs_both_kernels(bench, tmp_path):
+    _counters(tmp_path / "f.csv", "FETCH_SIZE", [("other", 1.0)])
+    _counters(tmp_path / "w.csv", "WRITE_SIZE", [("other", 1.0)])
+    with pytest.raises(SystemExit):
+        bench.traffic_from_counters(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"))
+
+
+def test_committed_traffic_counts_only_for_its_sources(bench, tmp_path, monkeypatch):
+    good = {"bytes_per_launch": 123.0, "source_sha256": bench.step_source_hash()}
+    stale = dict(good, source_sha256="0" * 16)
+    for d, expect in ((good, 123.0), (stale, None)):
+        p = tmp_path / "traffic.txt"
+        p.write_text("# header\n" + json.dumps(d) + "\n")
+        monkeypatch.setattr(bench, "TRAFFIC_FILE", str(p))
+        assert bench.load_traffic() == expect
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
+    assert bench.load_traffic() is None
+
+
+def test_more_than_one_gpu_is_refused():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
