@@ -314,6 +314,8 @@ def main():
                     help="of the extra measurements, run only the matrix-free step (for profiling)")
     ap.add_argument("--spmm-only", action="store_true",
                     help="of the extra measurements, run only the 64-rhs steps (for profiling)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="of the extra measurements, run only the uneven batch of 256 media (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, launch an elementwise kernel that reads and writes 1 GiB (counter scale)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
@@ -390,17 +392,19 @@ def main():
                      "kernel": SPMV_KERNEL, "kernel_ms": round(avg_kernel_ms, 4),
                      "algorithmic_bytes": nbytes, "traffic_unit": "GB per launch"},
     }
-    if not args.no_extras and args.n == 128 and not args.spmm_only:
+    only = args.struct_only or args.spmm_only or args.batch_only
+    if not args.no_extras and args.n == 128 and (args.struct_only or not only):
         _log("structured step")
         line["structured"] = structured_step(torch, A, wl, tab)
     S.close()
     A.close()
-    if not args.no_extras and not args.struct_only:
+    if not args.no_extras and (args.spmm_only or not only):
         _log("C3 SpMM")
         line["spmm"] = spmm_vs_plain(torch)
-    if not args.no_extras and not args.struct_only and not args.spmm_only:
+    if not args.no_extras and (args.batch_only or not only):
         _log("C4 batch")
         line["batch"] = batch_vs_sequential(torch)
+    if not args.no_extras and not only:
         line["serving"] = serving_vs_fifo(torch)
     if not args.no_cpu:
         _log("CPU oracle baseline")
