@@ -254,7 +254,7 @@ def batch_vs_sequential(torch, steps=40):
                             "GNNZ_equiv_per_s": round(nnz * steps / t_mb / 1e9, 1)}}
 
 
-def serving_vs_fifo(torch, n_req=32, step_scale=0.1):
+def serving_vs_fifo(torch, n_req=32, step_scale=0.1, csr_server=True):
     """C5 sample: the first n_req requests of the Poisson (200/s) stream of
     sphere-inclusion media (edges 32..128), step counts scaled by step_scale,
     through the serving loop and through sequential FIFO plain runs."""
@@ -265,21 +265,25 @@ def serving_vs_fifo(torch, n_req=32, step_scale=0.1):
     torch.cuda.empty_cache()
     budget = serve.footprint_budget(0.7)
     _log("C5: serving %d requests (budget %.1f GB)" % (n_req, budget / 1e9))
-    s = serve.serve(reqs, budget, quantum=50, max_active=4, policy="shortest")
+    s = serve.serve(reqs, budget, quantum=50, max_active=4, policy="shortest") if csr_server else None
     _log("C5: serving with the matrix-free step")
     torch.cuda.empty_cache()
     from paper_1611_08536_amd import drts
-    m = serve.serve(reqs, budget, quantum=50, max_active=4, policy="shortest", kernel=drts.KERNEL_STRUCTURED_F64SUM)
+    m = serve.serve(reqs, budget, quantum=50, max_active=4, policy="shortest", kernel=drts.KERNEL_STRUCTURED_F64SUM,
+                    log=None if csr_server else _log)
     _log("C5: FIFO plain")
-    f = serve.fifo_plain(reqs)
+    f = serve.fifo_plain(reqs, log=None if csr_server else _log)
     r = lambda d: {k: round(v, 4) if isinstance(v, float) else v for k, v in d.items()}
-    return {"workload": "C5 sample: first %d requests, 200/s Poisson arrivals, edges 32..128, steps %d..%d" %
-                        (n_req, lo, hi),
-            "server": "least work first, at most 4 admitted, 50 steps per tick, budget 70% of free HBM",
-            "served": r(s), "fifo_plain": r(f),
-            "speedup_solves_per_s": round(s["solves_per_s"] / f["solves_per_s"], 2),
+    out = {"workload": "C5%s: first %d requests, 200/s Poisson arrivals, edges 32..128, steps %d..%d" %
+                       ("" if n_req == 256 and step_scale == 1.0 else " sample", n_req, lo, hi),
+           "server": "least work first, at most 4 admitted, 50 steps per tick, budget 70% of free HBM",
+           "fifo_plain": r(f)}
+    if s is not None:
+        out.update({"served": r(s), "speedup_solves_per_s": round(s["solves_per_s"] / f["solves_per_s"], 2)})
+    out.update({
             "served_matrix_free": r(m),
-            "matrix_free_speedup_solves_per_s": round(m["solves_per_s"] / f["solves_per_s"], 2)}
+            "matrix_free_speedup_solves_per_s": round(m["solves_per_s"] / f["solves_per_s"], 2)})
+    return out
 
 
 def structured_step(torch, A, wl, tab, steps=50):
@@ -316,6 +320,9 @@ def main():
                     help="of the extra measurements, run only the 64-rhs steps (for profiling)")
     ap.add_argument("--batch-only", action="store_true",
                     help="of the extra measurements, run only the uneven batch of 256 media (for profiling)")
+    ap.add_argument("--serving-full", action="store_true",
+                    help="only the serving loop on all 256 requests of C5 with their full step counts, "
+                         "matrix-free server against FIFO plain runs (about 15 minutes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, launch an elementwise kernel that reads and writes 1 GiB (counter scale)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
@@ -330,6 +337,10 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.serving_full:
+        print(json.dumps({"serving_full": serving_vs_fifo(torch, n_req=256, step_scale=1.0, csr_server=False)}),
+              flush=True)
+        return
     import workloads as W
     from paper_1611_08536_amd import drts, solve
 
