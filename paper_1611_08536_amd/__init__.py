@@ -2,7 +2,9 @@
 
 J(t + dt) = A J(t) + B P(t) on gfx950: device assembly of the sparse system
 matrix, a CSR SpMV / SpMM time step with fused rescale, source injection and
-FP64 detector reduction, uneven persistent batches and an autotuner.  The
+FP64 detector reduction, a matrix-free form of the same step built from the
+per-material direction blocks, uneven persistent batches (CSR or
+matrix-free members), autotuners and a continuous-batching server.  The
 public ABI is include/drts.h; ``drts`` is its Python binding.
 """
 from . import sources  # noqa: F401

@@ -441,7 +441,9 @@ class Solver:
 
 
 class Batch:
-    """Uneven batch of single-rhs FP32 solvers advanced by one launch per step."""
+    """Uneven batch of single-rhs FP32 solvers advanced by one launch per step
+    (per kernel): all members on the CSR step, or all on the matrix-free step
+    in a direction-major mode (drts_batch_*)."""
 
     def __init__(self, solvers: List[Solver], device: Optional[TorchDevice] = None):
         self.solvers = list(solvers)
@@ -471,13 +473,17 @@ class Batch:
         _check(_lib.drts_batch_run(self._h, ptrs, steps.ctypes.data_as(C.POINTER(i64))), "drts_batch_run")
 
     def autotune(self) -> dict:
+        """drts_batch_autotune: one launch shape for all CSR members, before
+        their first step; returns the chosen options (grid: the batch's)."""
         o = OptionsT()
         _check(_lib.drts_batch_autotune(self._h, C.byref(o)), "drts_batch_autotune")
         return {k: getattr(o, k) for k, _ in OptionsT._fields_}
 
 
 class Server:
-    """Continuous batching of independent FP32 solves (drts_serve_*)."""
+    """Continuous batching of independent FP32 solves (drts_serve_*); kernel
+    other than KERNEL_CSR selects the matrix-free step for every request
+    admitted (drts_serve_set_step)."""
 
     def __init__(self, budget_bytes: int, quantum: int = 50, max_active: int = 256, max_skips: int = 8,
                  policy: str = "arrival", device: Optional[TorchDevice] = None, kernel: int = KERNEL_CSR):
