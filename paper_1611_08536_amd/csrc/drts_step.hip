@@ -481,7 +481,7 @@ __device__ __forceinline__ VT finish_tile_s(const TileRegsS<VT, IT, S> &T, __amd
 // layout (one row per thread, no pipelining); LAY = 2: quads with the values
 // loaded straight into LDS (FP32 values only, no pipelining); LAY = 0: quads.
 template <typename VT, typename IT, int NT, int R, int PIPE, int LAY>
-__global__ void __launch_bounds__(NT, (LAY == 2 ? 5 : 1)) step_spmv(const StepInst *__restrict__ insts,
+__global__ void __launch_bounds__(NT, (LAY == 2 && sizeof(VT) == 4 && sizeof(IT) == 4 && R >= 128 ? 5 : 1)) step_spmv(const StepInst *__restrict__ insts,
                                                  const WorkItem *__restrict__ work, int64_t n_work,
                                                  int xcd_remap, const int64_t *__restrict__ xcd_bounds,
                                                  int32_t *__restrict__ queue)
