@@ -132,6 +132,13 @@ typedef struct {
 } drts_device_t;
 
 /* ---- sources: s(t) = B P(t) (Eq. 26) ------------------------------------------ */
+/* Ownership: the library keeps the table's address, never a copy.  A solver
+ * calls support() when it is first handed a table and stages the result; on
+ * later calls it recognises the table by its address, ctx and n_src and calls
+ * only amplitude().  A caller that changes what support() returns therefore
+ * passes a table at another address or with another ctx.  The table and its
+ * ctx stay valid while a solver may still run with it, and until a submitted
+ * serving request has finished. */
 typedef struct {
     void *ctx;
     int32_t n_src; /* number of source functions */

@@ -468,7 +468,11 @@ class Batch:
         n = len(self.solvers)
         ptrs = (C.POINTER(SourceTableT) * n)(
             *[C.pointer(t.c) if t is not None else C.POINTER(SourceTableT)() for t in tables])
-        self._keep = tables
+        # each member solver recognises its staged sources by the table's
+        # address: keep every table it has seen alive as long as the solver
+        for s, t in zip(self.solvers, tables):
+            if t is not None and t not in s._tables:
+                s._tables.append(t)
         steps = np.ascontiguousarray(n_steps, dtype=np.int64)
         _check(_lib.drts_batch_run(self._h, ptrs, steps.ctypes.data_as(C.POINTER(i64))), "drts_batch_run")
 
