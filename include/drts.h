@@ -271,12 +271,15 @@ int drts_solver_get_options(const drts_solver_t *S, drts_options_t *opt);
 int drts_solver_set_options(drts_solver_t *S, const drts_options_t *opt);
 
 /* One step J <- A J + B P(t) (Eq. 26), t += 1.  Calls src->amplitude for the
- * current step only.  Asynchronous. */
+ * current step only.  Returns once the step's amplitudes are copied to the
+ * device (which waits for work already queued on the stream), without
+ * waiting for the step itself. */
 int drts_step(drts_solver_t *S, const drts_source_table_t *src);
 
 /* n_steps steps.  Calls src->amplitude for all of them up front, then
  * replays hipGraphs of graph_steps steps (no host synchronisation inside).
- * DRTS_E_RANGE when t + n_steps exceeds max_steps.  Asynchronous. */
+ * DRTS_E_RANGE when t + n_steps exceeds max_steps.  Returns once the
+ * amplitudes are copied (as drts_step), without waiting for the steps. */
 int drts_run(drts_solver_t *S, const drts_source_table_t *src, int64_t n_steps);
 
 /* Current step count (synchronises). */
