@@ -276,8 +276,31 @@ int drts_solver_set_options(drts_solver_t *S, const drts_options_t *opt);
  * waiting for the step itself. */
 int drts_step(drts_solver_t *S, const drts_source_table_t *src);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same step as
+ * drts_step -- same kernels, same results bit for bit -- whose scratch memory
+ * (the device copy of the step descriptor, the work counter of the dynamic
+ * walk and the per-chunk FP64 partials of the totals and detectors) lives in
+ * a fixed 16 MiB device array of the library instead of the solver's
+ * buffers.  It allocates nothing, device or host.  Each GPU that runs it
+ * holds its own copy of the array until the process ends; the call looks up
+ * that copy's address on the current device (which must be the solver's) the
+ * first time it runs there.  Every call on one GPU shares the array and the
+ * call rewrites what it reads (descriptor, counter, partials) before reading
+ * it, so nothing carries over from a previous call; calls that overlap on one
+ * GPU (two host threads, or two streams with work in flight) race and must
+ * not be issued.  Errors: DRTS_E_STATE when src is not the source table
+ * already staged in the solver (staging another table allocates: hand it to
+ * drts_step or drts_run once first; a solver created without sources accepts
+ * src = NULL); DRTS_E_RANGE when the step's partials exceed the array
+ * (16 MiB - 4 KiB: (4 + n_det) x n_rhs x (chunks + 256) doubles; use more
+ * tiles per chunk, or drts_step) or beyond max_steps; DRTS_E_HIP. */
+int drts_step_noalloc(drts_solver_t *S, const drts_source_table_t *src);
+
 /* n_steps steps.  Calls src->amplitude for all of them up front, then
  * replays hipGraphs of graph_steps steps (no host synchronisation inside).
+ * n_steps = 0 only stages the source table (its support is read and
+ * uploaded), which a later drts_step_noalloc requires.
  * DRTS_E_RANGE when t + n_steps exceeds max_steps.  Returns once the
  * amplitudes are copied (as drts_step), without waiting for the steps. */
 int drts_run(drts_solver_t *S, const drts_source_table_t *src, int64_t n_steps);

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -689,6 +690,9 @@ int set_sources(drts_solver *S, const drts_source_table_t *src)
     if ((rc = upload_vec(dev, S->src_w, w))) return rc;
     if ((rc = S->amp.allocate(&dev, (size_t)S->max_steps * std::max(S->n_src, 1) * sizeof(double)))) return rc;
     DRTS_HIP(hipMemsetAsync(S->amp.ptr, 0, S->amp.bytes, dev.stream));
+    // one step's host amplitudes never reallocate after this (drts_step_noalloc)
+    S->amp_h.reserve((size_t)std::max(S->n_src, 1));
+    S->smax_h.reserve((size_t)S->n_rhs);
     return prepare(S);
 }
 
@@ -738,10 +742,15 @@ hipEvent_t next_event(drts_solver *S)
     return S->ev_pool[S->ev_used++];
 }
 
-int launch_one(drts_solver *S, hipStream_t stream)
+// One step's launches.  inst (NULL = the solver's own) is the device copy of
+// the step descriptor the kernels read (matrix, state, partials, series);
+// queue_override (used when inst is given) is the work counter of the
+// dynamic walk.
+int launch_one(drts_solver *S, hipStream_t stream, const StepInst *inst = nullptr, int32_t *queue_override = nullptr)
 {
     const Matrix &A = S->A->m;
     const bool spmm = spmm_of(S);
+    const StepInst *insts = inst ? inst : S->inst_dev.as<StepInst>();
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (S->profile && stream == S->dev.stream) {
         e0 = next_event(S);
@@ -749,24 +758,26 @@ int launch_one(drts_solver *S, hipStream_t stream)
         if (!e0 || !e1) return set_error(DRTS_E_HIP, "hipEventCreate failed");
         DRTS_HIP(hipEventRecord(e0, stream));
     }
-    int32_t *queue = (!spmm && S->opt.queue && S->opt.kernel == DRTS_KERNEL_CSR) ? S->queue.as<int32_t>() : nullptr;
+    int32_t *queue = (!spmm && S->opt.queue && S->opt.kernel == DRTS_KERNEL_CSR)
+                         ? (inst ? queue_override : S->queue.as<int32_t>())
+                         : nullptr;
     hipError_t e;
     if (structured_of(S) && spmm) {
-        e = launch_structured_mm(S->sa, S->inst_dev.as<StepInst>(), S->work_dev.as<WorkItem>(), S->n_chunks,
+        e = launch_structured_mm(S->sa, insts, S->work_dev.as<WorkItem>(), S->n_chunks,
                                  S->opt.kernel == DRTS_KERNEL_STRUCTURED_F64SUM ? 2 : 1, S->grid, S->n_det, stream);
     } else if (structured_of(S)) {
-        e = launch_structured(S->sa, S->inst_dev.as<StepInst>(), S->work_dev.as<WorkItem>(), S->n_chunks,
+        e = launch_structured(S->sa, insts, S->work_dev.as<WorkItem>(), S->n_chunks,
                               A.model.value_type == DRTS_F64, structured_mode(S), S->grid,
                               S->opt.xcd_remap ? 1 : 0, S->xcd_bounds.as<int64_t>(), stream);
     } else {
-    e = launch_step(S->inst_dev.as<StepInst>(), S->work_dev.as<WorkItem>(), S->n_chunks, 1, S->n_rhs,
+    e = launch_step(insts, S->work_dev.as<WorkItem>(), S->n_chunks, 1, S->n_rhs,
                                A.model.value_type == DRTS_F64, A.rp64 ? 1 : 0, spmm ? 1 : 0, S->grid,
                                (S->opt.xcd_remap ? 1 : 0) | ((S->opt.variant & 15) << 1), S->xcd_bounds.as<int64_t>(),
                                S->opt.rows_per_tile, S->n_det, queue, stream);
     }
     if (e != hipSuccess) return set_error(DRTS_E_HIP, "step launch failed: %s", hipGetErrorString(e));
     if (e1) DRTS_HIP(hipEventRecord(e1, stream));
-    e = launch_finalize(S->inst_dev.as<StepInst>(), 1, S->n_rhs, S->n_det, queue, stream);
+    e = launch_finalize(insts, 1, S->n_rhs, S->n_det, queue, stream);
     if (e != hipSuccess) return set_error(DRTS_E_HIP, "finalize launch failed: %s", hipGetErrorString(e));
     return DRTS_OK;
 }
@@ -1008,6 +1019,7 @@ int drts_solver_create(const drts_matrix_t *A, int32_t n_rhs, const drts_detecto
     const Model &M = A->m.model;
     int rc = DRTS_OK;
     try {
+        S->smax_h.reserve((size_t)n_rhs);
         if (det && det->n_det > 0) {
             const int nd_max = n_rhs > 1 ? 32 : 256;
             if (det->n_det > nd_max) rc = set_error(DRTS_E_INVALID, "at most %d detectors", nd_max);
@@ -1118,15 +1130,107 @@ int drts_step(drts_solver_t *S, const drts_source_table_t *src)
     return DRTS_OK;
 }
 
+}  // extern "C"
+
+// ---- the step without allocation ----------------------------------------------
+//
+// drts_step_noalloc takes the step's scratch memory -- the device copy of the
+// step descriptor, the counter of the dynamic walk and the per-chunk FP64
+// partials with their finalize segments -- from this file-scope array instead
+// of the solver's buffers.  Every device that runs it holds one copy of the
+// array until the process ends; its address on a device comes from
+// hipGetSymbolAddress (the array's name in host code is not a device address).
+namespace {
+
+constexpr size_t kScratchBytes = size_t(16) << 20;
+constexpr size_t kScratchInstOff = 0;      // StepInst (well under 1 KiB)
+constexpr size_t kScratchQueueOff = 1024;  // int32 work counter
+constexpr size_t kScratchPartOff = 4096;   // FP64 partials, then the finalize segments
+static_assert(sizeof(StepInst) <= kScratchQueueOff, "step descriptor fits its scratch slot");
+constexpr int kScratchMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kScratchMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+int scratch_on_current_device(unsigned char **out)
+{
+    int dev = -1;
+    DRTS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kScratchMaxDevices) return set_error(DRTS_E_RANGE, "device %d beyond %d", dev, kScratchMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(DRTS_E_HIP, "hipGetSymbolAddress(scratch) on device %d failed: %s", dev, hip_name(e));
+        g_scratch_dev[dev] = p;
+    }
+    *out = static_cast<unsigned char *>(g_scratch_dev[dev]);
+    return DRTS_OK;
+}
+
+// Writes the step descriptor into the scratch slot and clears the work counter
+// (a kernel, not a memset or a pageable copy: plain stream-ordered writes).
+__global__ void stage_step_scratch(StepInst inst, StepInst *dst, int32_t *queue)
+{
+    if (threadIdx.x == 0) {
+        *dst = inst;
+        *queue = 0;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int drts_step_noalloc(drts_solver_t *S, const drts_source_table_t *src)
+{
+    if (!S) return set_error(DRTS_E_INVALID, "solver is NULL");
+    if (S->t_host + 1 > S->max_steps) return set_error(DRTS_E_RANGE, "step %lld beyond max_steps", (long long)S->t_host);
+    // staging another source table allocates: only the staged one is accepted
+    const bool staged = (!src || src->n_src <= 0) ? (S->n_src == 0 && S->src_key == nullptr)
+                                                  : (src == S->src_key && src->ctx == S->src_ctx_key &&
+                                                     src->n_src == S->n_src);
+    if (!staged)
+        return set_error(DRTS_E_STATE, "drts_step_noalloc: the source table is not the one staged in the solver "
+                                       "(hand it to drts_step or drts_run once first)");
+    const StepInst &I0 = S->inst_h;
+    const size_t slots = (size_t)(kSlotDet + S->n_det) * S->n_rhs;
+    const size_t part_bytes = slots * (size_t)(I0.n_chunks + kFinSeg) * sizeof(double);
+    if (part_bytes > kScratchBytes - kScratchPartOff)
+        return set_error(DRTS_E_RANGE,
+                         "drts_step_noalloc: the step needs %zu bytes of partials, the scratch array holds %zu "
+                         "(fewer chunks: more tiles per chunk; or use drts_step)",
+                         part_bytes, kScratchBytes - kScratchPartOff);
+    unsigned char *base = nullptr;
+    int rc = scratch_on_current_device(&base);
+    if (rc) return rc;
+    // amplitudes of this step: host vectors sized when the table was staged
+    if ((rc = upload_amplitudes(S, src, S->t_host, 1))) return rc;
+    StepInst I = I0;
+    I.partials = reinterpret_cast<double *>(base + kScratchPartOff);
+    StepInst *inst_dev = reinterpret_cast<StepInst *>(base + kScratchInstOff);
+    int32_t *queue = reinterpret_cast<int32_t *>(base + kScratchQueueOff);
+    hipLaunchKernelGGL(stage_step_scratch, dim3(1), dim3(64), 0, S->dev.stream, I, inst_dev, queue);
+    DRTS_HIP(hipGetLastError());
+    if ((rc = launch_one(S, S->dev.stream, inst_dev, queue))) return rc;
+    S->t_host += 1;
+    return DRTS_OK;
+}
+
 int drts_run(drts_solver_t *S, const drts_source_table_t *src, int64_t n_steps)
 {
     if (!S) return set_error(DRTS_E_INVALID, "solver is NULL");
     if (n_steps < 0 || S->t_host + n_steps > S->max_steps)
         return set_error(DRTS_E_RANGE, "steps %lld..%lld beyond max_steps %lld", (long long)S->t_host,
                          (long long)(S->t_host + n_steps), (long long)S->max_steps);
-    if (n_steps == 0) return DRTS_OK;
+    // a run of zero steps only stages the source table
     int rc = set_sources(S, src);
-    if (!rc) rc = upload_amplitudes(S, src, S->t_host, n_steps);
+    if (rc || n_steps == 0) return rc;
+    rc = upload_amplitudes(S, src, S->t_host, n_steps);
     if (rc) return rc;
     const int K = S->opt.graph_steps;
     int64_t done = 0;

@@ -119,6 +119,7 @@ _sig("drts_solver_create", C.c_int, [P, i32, C.POINTER(DetectorsT), i64, C.POINT
 _sig("drts_solver_get_options", C.c_int, [P, C.POINTER(OptionsT)])
 _sig("drts_solver_set_options", C.c_int, [P, C.POINTER(OptionsT)])
 _sig("drts_step", C.c_int, [P, C.POINTER(SourceTableT)])
+_sig("drts_step_noalloc", C.c_int, [P, C.POINTER(SourceTableT)])
 _sig("drts_run", C.c_int, [P, C.POINTER(SourceTableT), i64])
 _sig("drts_solver_time", C.c_int, [P, C.POINTER(i64)])
 _sig("drts_detector_readout", C.c_int, [P, i64, i64, P, P, P])
@@ -147,7 +148,7 @@ _sig("drts_serve_set_step", C.c_int, [P, i32])
 EXPORTED = [
     "drts_build_matrix", "drts_matrix_info", "drts_matrix_row_of", "drts_matrix_export_rows",
     "drts_matrix_destroy", "drts_solver_create", "drts_solver_get_options", "drts_solver_set_options",
-    "drts_step", "drts_run", "drts_solver_time", "drts_detector_readout", "drts_state_read",
+    "drts_step", "drts_step_noalloc", "drts_run", "drts_solver_time", "drts_detector_readout", "drts_state_read",
     "drts_state_write", "drts_solver_profile", "drts_solver_profile_stats", "drts_solver_destroy",
     "drts_batch_create", "drts_batch_run", "drts_batch_destroy", "drts_batch_autotune", "drts_autotune", "drts_last_error",
     "drts_serve_create", "drts_serve_submit", "drts_serve_footprint", "drts_serve_tick", "drts_serve_poll", "drts_serve_result",
@@ -392,6 +393,11 @@ class Solver:
 
     def step(self, sources: Optional[SourceTable] = None):
         _check(_lib.drts_step(self._h, self._table(sources)), "drts_step")
+
+    def step_noalloc(self, sources: Optional[SourceTable] = None):
+        """drts_step_noalloc: the same step with the library's fixed scratch
+        array (the table must already be staged by step() or run())."""
+        _check(_lib.drts_step_noalloc(self._h, self._table(sources)), "drts_step_noalloc")
 
     def run(self, sources: Optional[SourceTable], n_steps: int):
         _check(_lib.drts_run(self._h, self._table(sources), int(n_steps)), "drts_run")
