@@ -25,7 +25,8 @@
  *     population by the unpolarised Fresnel reflectance (Sec. 4.2): the
  *     reflected part stays in v with the lattice direction nearest the
  *     specular direction, the transmitted part enters v + e_m with the
- *     lattice direction nearest the Snell direction;
+ *     lattice direction nearest the Snell direction (directions tied within
+ *     1e-12 in cosine share a part evenly);
  *   - at vacuum faces the population leaving the grid is collected in escape
  *     rows (row index >= n_states), so the matrix is [A; L] with
  *     n_rows = n_states + n_escape rows; at reflecting faces every leaving

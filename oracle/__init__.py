@@ -23,9 +23,6 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "drts_oracle.c")
 _LIB = os.path.join(_HERE, "_drts_oracle.so")
-# tests/test_oracle_mutants.py points this at a build of a deliberately
-# broken copy of drts_oracle.c, to show that the pins catch the mistake
-_LIB_OVERRIDE = os.environ.get("DRTS_ORACLE_LIB")
 _lock = threading.Lock()
 _lib = None
 
@@ -60,7 +57,7 @@ def _load():
     with _lock:
         if _lib is not None:
             return _lib
-        lib = C.CDLL(_LIB_OVERRIDE if _LIB_OVERRIDE else build())
+        lib = C.CDLL(build())
         P = C.c_void_p
         i64, i32, dbl = C.c_int64, C.c_int32, C.c_double
         lib.or_build.restype = P
@@ -84,7 +81,7 @@ def _load():
                                i64, P, P, P, i32,
                                P, P, P, P, P, P]
         lib.or_collision_block.argtypes = [dbl, dbl, dbl, dbl, P]
-        lib.or_fresnel.argtypes = [C.c_int, dbl, dbl, P, P, P, P, P]
+        lib.or_fresnel.argtypes = [C.c_int, dbl, dbl, P, P, P, P, P, P, P]
         lib.or_dt_seconds.restype = dbl
         lib.or_dt_seconds.argtypes = [dbl, dbl]
         lib.or_gaussian_step.restype = dbl
@@ -113,12 +110,14 @@ def collision_block(mu_s, mu_a, g, h_mm) -> np.ndarray:
 
 
 def fresnel(m: int, n1: float, n2: float, normal) -> tuple:
-    """(R, T, m_reflected, m_transmitted) for lattice direction m crossing n1 -> n2."""
+    """(R, T, reflected directions, transmitted directions) for lattice
+    direction m crossing n1 -> n2; tied directions share their part evenly."""
     N = np.ascontiguousarray(normal, dtype=np.float64)
     R, T = C.c_double(), C.c_double()
-    mr, mt = C.c_int(), C.c_int()
-    _load().or_fresnel(m, n1, n2, _ptr(N), C.byref(R), C.byref(T), C.byref(mr), C.byref(mt))
-    return R.value, T.value, mr.value, mt.value
+    mr, mt = (C.c_int * 26)(), (C.c_int * 26)()
+    nr, nt = C.c_int(), C.c_int()
+    _load().or_fresnel(m, n1, n2, _ptr(N), C.byref(R), C.byref(T), mr, C.byref(nr), mt, C.byref(nt))
+    return R.value, T.value, list(mr[:nr.value]), list(mt[:nt.value])
 
 
 def dt_seconds(h_mm: float, n_ref: float) -> float:

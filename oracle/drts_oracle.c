@@ -133,35 +133,45 @@ void or_collision_block(double mu_s, double mu_a, double g, double h,
 
 /* ---- interfaces ---------------------------------------------------------- */
 
-/* argmax of s_d . target over directions d whose side test (s_d . N) has the
- * requested sign; a later direction must beat the best by more than 1e-12 */
-static int or_snap(const double target[3], const double N[3], int side)
+/* Lattice directions nearest to `target` among those d whose side test
+ * (s_d . N) has the requested sign: every such d whose s_d . target lies
+ * within 1e-12 of the largest value.  Writes them in ascending order to
+ * out[] and returns how many there are (0 when no direction is on that side).
+ * A population snapped to k tied directions is split evenly between them. */
+static int or_snap(const double target[3], const double N[3], int side, int out[NDIR])
 {
-    int best_d = -1;
     double best = -INFINITY;
+    int any = 0;
     for (int d = 0; d < NDIR; ++d) {
         double s[3];
         or_dir_unit(d, s);
         double sn = or_dot3(s, N);
         if ((side < 0 && sn < 0.0) || (side > 0 && sn > 0.0)) {
             double v = or_dot3(s, target);
-            if (best_d < 0 || v > best + 1e-12) {
-                best = v;
-                best_d = d;
-            }
+            if (!any || v > best) best = v;
+            any = 1;
         }
     }
-    return best_d;
+    int k = 0;
+    for (int d = 0; any && d < NDIR; ++d) {
+        double s[3];
+        or_dir_unit(d, s);
+        double sn = or_dot3(s, N);
+        if ((side < 0 && sn < 0.0) || (side > 0 && sn > 0.0))
+            if (or_dot3(s, target) >= best - 1e-12) out[k++] = d;
+    }
+    return k;
 }
 
 /*
  * Fresnel split of a population with lattice direction m crossing from index
  * n1 into index n2 through a surface with unit normal N (oriented so that
  * s_m . N > 0).  Outputs the reflectance R (1 on total internal reflection),
- * T = 1 - R, and the snapped reflected / transmitted directions.
+ * T = 1 - R, and the snapped reflected / transmitted directions (n_r and n_t
+ * of them, tied directions sharing their part evenly; n_t = 0 when T = 0).
  */
 void or_fresnel(int m, double n1, double n2, const double N[3],
-                double *R_out, double *T_out, int *mr_out, int *mt_out)
+                double *R_out, double *T_out, int *mr_out, int *nr_out, int *mt_out, int *nt_out)
 {
     double s[3];
     or_dir_unit(m, s);
@@ -187,8 +197,8 @@ void or_fresnel(int m, double n1, double n2, const double N[3],
     }
     *R_out = R;
     *T_out = T;
-    *mr_out = or_snap(r, N, -1);
-    *mt_out = (T > 0.0) ? or_snap(t, N, +1) : -1;
+    *nr_out = or_snap(r, N, -1, mr_out);
+    *nt_out = (T > 0.0) ? or_snap(t, N, +1, mt_out) : 0;
 }
 
 /* ---- medium ---------------------------------------------------------------- */
@@ -256,8 +266,8 @@ typedef struct {
 
 typedef struct {
     int count;
-    int64_t row[2];
-    double f[2];
+    int64_t row[2 * NDIR];
+    double f[2 * NDIR];
 } or_targets_t;
 
 /* where the population that leaves voxel v=(x,y,z) with direction m goes */
@@ -299,15 +309,18 @@ static void or_move(const or_medium_t *M, const or_csr_t *A, int64_t v, int x, i
     or_dir_unit(m, s);
     or_normal(M, x, y, z, e, s, N);
     double R, Tr;
-    int mr, mt;
-    or_fresnel(m, n1, n2, N, &R, &Tr, &mr, &mt);
-    T->count = 1;
-    T->row[0] = NDIR * v + mr;
-    T->f[0] = R;
-    if (Tr > 0.0) {
-        T->count = 2;
-        T->row[1] = NDIR * u + mt;
-        T->f[1] = Tr;
+    int mr[NDIR], mt[NDIR], nr, nt;
+    or_fresnel(m, n1, n2, N, &R, &Tr, mr, &nr, mt, &nt);
+    T->count = 0;
+    for (int i = 0; i < nr; ++i) {
+        T->row[T->count] = NDIR * v + mr[i];
+        T->f[T->count] = R / (double)nr;
+        T->count++;
+    }
+    for (int i = 0; i < nt; ++i) {
+        T->row[T->count] = NDIR * u + mt[i];
+        T->f[T->count] = Tr / (double)nt;
+        T->count++;
     }
 }
 

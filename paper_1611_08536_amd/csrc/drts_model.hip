@@ -74,29 +74,36 @@ void direction_block(const drts_material_t &q, double h, double *C)
     }
 }
 
-// Lattice direction on side `side` of the surface (sign of s_d . N) whose unit
-// vector is closest to `want`; a later candidate must win by more than 1e-12.
-int nearest_direction(const double *want, const double *N, int side)
+// Lattice directions on side `side` of the surface (sign of s_d . N) whose unit
+// vectors are closest to `want`: every one whose s_d . want lies within 1e-12
+// of the largest value, written in ascending order; returns their count.  A
+// population snapped to k of them is split evenly (no direction index is
+// preferred, so the split keeps the medium's symmetries).
+int nearest_directions(const double *want, const double *N, int side, int *out)
 {
     const Unit &U = units();
-    int arg = -1;
     double best = -INFINITY;
+    bool any = false;
     for (int d = 0; d < kDirs; ++d) {
         const double sn = dot3(U.s[d], N);
-        const bool ok = side < 0 ? sn < 0.0 : sn > 0.0;
-        if (!ok) continue;
+        if (!(side < 0 ? sn < 0.0 : sn > 0.0)) continue;
         const double v = dot3(U.s[d], want);
-        if (arg < 0 || v > best + 1e-12) {
-            best = v;
-            arg = d;
-        }
+        if (!any || v > best) best = v;
+        any = true;
     }
-    return arg;
+    int k = 0;
+    for (int d = 0; any && d < kDirs; ++d) {
+        const double sn = dot3(U.s[d], N);
+        if (!(side < 0 ? sn < 0.0 : sn > 0.0)) continue;
+        if (dot3(U.s[d], want) >= best - 1e-12) out[k++] = d;
+    }
+    return k;
 }
 
 struct Split {
     double R, T;
-    int m_refl, m_trans;
+    int n_refl = 0, n_trans = 0;
+    int m_refl[kDirs], m_trans[kDirs];
 };
 
 // Unpolarised Fresnel split (Sec. 4.2) of direction m going from index n1 to n2
@@ -125,8 +132,8 @@ Split fresnel_split(int m, double n1, double n2, const double *N)
         r[i] = s[i] - (2.0 * ci) * N[i];
         t[i] = eta * s[i] + (ct - eta * ci) * N[i];
     }
-    out.m_refl = nearest_direction(r, N, -1);
-    out.m_trans = out.T > 0.0 ? nearest_direction(t, N, +1) : -1;
+    out.n_refl = nearest_directions(r, N, -1, out.m_refl);
+    out.n_trans = out.T > 0.0 ? nearest_directions(t, N, +1, out.m_trans) : 0;
     return out;
 }
 
@@ -294,8 +301,10 @@ int build_model(const drts_medium_t *m, Model *M)
                     double N[3];
                     crossing_normal(m->geom, x, y, z, d, N);
                     const Split sp = fresnel_split(d, n1, n2, N);
-                    irr.push_back({kDirs * v + sp.m_refl, v, d, sp.R});
-                    if (sp.T > 0.0) irr.push_back({kDirs * u + sp.m_trans, v, d, sp.T});
+                    for (int i = 0; i < sp.n_refl; ++i)
+                        irr.push_back({kDirs * v + sp.m_refl[i], v, d, sp.R / (double)sp.n_refl});
+                    for (int i = 0; i < sp.n_trans; ++i)
+                        irr.push_back({kDirs * u + sp.m_trans[i], v, d, sp.T / (double)sp.n_trans});
                 }
             }
     M->n_escape = (int64_t)M->escape_state.size();

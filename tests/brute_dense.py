@@ -63,15 +63,18 @@ def block(mat, h):
 
 
 def snap(target, N, side):
-    best_d, best = -1, -math.inf
+    """All directions on the requested side whose s_d . target is within 1e-12
+    of the largest (tied directions share the population evenly)."""
+    vals = {}
     for d in range(26):
         s = unit(d)
         sn = dot(s, N)
         if (side < 0 and sn < 0.0) or (side > 0 and sn > 0.0):
-            v = dot(s, target)
-            if best_d < 0 or v > best + 1e-12:
-                best, best_d = v, d
-    return best_d
+            vals[d] = dot(s, target)
+    if not vals:
+        return []
+    top = max(vals.values())
+    return [d for d in sorted(vals) if vals[d] >= top - 1e-12]
 
 
 def fresnel(m, n1, n2, N):
@@ -89,7 +92,7 @@ def fresnel(m, n1, n2, N):
         T = 1.0 - R
     r = [s[i] - (2.0 * ci) * N[i] for i in range(3)]
     t = [eta * s[i] + (ct - eta * ci) * N[i] for i in range(3)]
-    return R, T, snap(r, N, -1), (snap(t, N, +1) if T > 0.0 else -1)
+    return R, T, snap(r, N, -1), (snap(t, N, +1) if T > 0.0 else [])
 
 
 def normal(med, x, y, z, e, s):
@@ -156,8 +159,8 @@ def build_dense(med):
                 s = unit(m)
                 N = normal(med, ux, uy, uz, e, s)
                 Rf, Tf, mr, mt = fresnel(m, n1, n2, N)
-                if Tf > 0.0 and mt == mp:
-                    out.append((u, m, Tf))
+                if Tf > 0.0 and mp in mt:
+                    out.append((u, m, Tf / len(mt)))
         # populations of w itself turned back: walls and interface reflection
         for m in range(26):
             e = LV[m]
@@ -176,8 +179,8 @@ def build_dense(med):
                 s = unit(m)
                 N = normal(med, x, y, z, e, s)
                 Rf, Tf, mr, mt = fresnel(m, n1, n2, N)
-                if mr == mp:
-                    out.append((w, m, Rf))
+                if mp in mr:
+                    out.append((w, m, Rf / len(mr)))
         return sorted(out)
 
     def fill(row, moves):

@@ -6,6 +6,12 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
+# tests/test_oracle_mutants.py runs the oracle's pins against a copy of the
+# oracle package with one planted mistake: that copy is imported instead
+_ORACLE_COPY = os.environ.get("DRTS_ORACLE_COPY")
+if _ORACLE_COPY:
+    sys.path.insert(0, _ORACLE_COPY)
+    import oracle  # noqa: E402,F401  (cached now, so later imports get the copy)
 
 
 def pytest_configure(config):
@@ -16,5 +22,7 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def orc():
     import oracle
+    if _ORACLE_COPY:
+        assert os.path.abspath(oracle.__file__).startswith(os.path.abspath(_ORACLE_COPY))
     oracle.build()
     return oracle

@@ -57,6 +57,15 @@ def test_assembly_bitexact_layers_and_sphere(vt, rnd):
         _assert_same_csr(q.workload.medium, vt, rnd)
 
 
+def test_assembly_bitexact_tied_interface_directions():
+    """A sphere centred on the middle column of an odd grid: many crossings
+    snap to tied lattice directions, whose parts are split evenly."""
+    bg, inc = W.Material(10.0, 0.05, 0.8, 1.0), W.Material(6.0, 0.2, 0.5, 1.6)
+    med = W.sphere_inclusion(9, bg, inc, (4.5, 4.5, 4.0), 2.6)
+    for vt, rnd in (("f64", "nearest"), ("f32", "dither")):
+        _assert_same_csr(med, vt, rnd)
+
+
 def test_assembly_from_geometry_equals_map():
     """mat_of_voxel = NULL: the library derives the same map from the geometry."""
     for med in (W.c2(n=20).medium, W.c5(n_req=1, edge=(18, 18))[0].workload.medium):

@@ -1,64 +1,87 @@
 """The oracle's pins catch plausible mistakes.
 
-Each case copies oracle/drts_oracle.c, plants one mistake of the kind the
-pins are meant to catch (a dropped term, a wrong sign, a transposed index,
-an off-by-one range, a wrong coefficient), builds the copy with the
-oracle's own compiler flags and runs tests/test_oracle_pins.py against it in
-a subprocess: the pin suite must fail.  A control case builds the copy
-unchanged and must pass.  Only the copy is changed; the oracle itself is
-never modified."""
+Each case copies the oracle package (oracle/drts_oracle.c and
+oracle/__init__.py), plants one mistake of the kind the pins are meant to
+catch (a dropped term, a wrong sign, a transposed index, an off-by-one range,
+a wrong coefficient, a wrong operand), and runs tests/test_oracle_pins.py
+against the copy in a subprocess (the copy builds its own library with the
+oracle's compiler flags): the pin suite must fail.  A control case copies the
+package unchanged and must pass.  Only the copy is changed; the oracle itself
+is never modified."""
 import os
+import shutil
 import subprocess
 import sys
 
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SRC = os.path.join(ROOT, "oracle", "drts_oracle.c")
+ORACLE = os.path.join(ROOT, "oracle")
 
-# (name, text of the oracle, planted replacement)
+C_SRC, PY_SRC = "drts_oracle.c", "__init__.py"
+
+# (name, file of the oracle, text, planted replacement)
 MUTANTS = [
-    ("hg_sign", "double q = 1.0 + g * g - 2.0 * g * cs;", "double q = 1.0 + g * g + 2.0 * g * cs;"),
+    ("hg_sign", C_SRC, "double q = 1.0 + g * g - 2.0 * g * cs;", "double q = 1.0 + g * g + 2.0 * g * cs;"),
     # (p[m][n] is symmetric, so transposing the normalisation sum changes
     # nothing; the block itself is not: its normalisation differs per column)
-    ("block_transposed", "C[m * NDIR + n] = (m != n)", "C[n * NDIR + m] = (m != n)"),
-    ("forward_term_dropped", "alpha * (P0 + Ps * G)", "alpha * (Ps * G)"),
-    ("absorption_coefficient", "double alpha = exp(-mu_a * h);", "double alpha = exp(-mu_s * h);"),
-    ("fresnel_average", "R = 0.5 * (rs * rs + rp * rp);", "R = rs * rs;"),
-    ("specular_factor", "r[i] = s[i] - (2.0 * cos_i) * N[i];", "r[i] = s[i] - cos_i * N[i];"),
-    ("escaped_off_by_one", "for (int64_t r = D; r < R; ++r)\n            esc += y[r];",
+    ("block_transposed", C_SRC, "C[m * NDIR + n] = (m != n)", "C[n * NDIR + m] = (m != n)"),
+    ("forward_term_dropped", C_SRC, "alpha * (P0 + Ps * G)", "alpha * (Ps * G)"),
+    ("absorption_coefficient", C_SRC, "double alpha = exp(-mu_a * h);", "double alpha = exp(-mu_s * h);"),
+    ("fresnel_average", C_SRC, "R = 0.5 * (rs * rs + rp * rp);", "R = rs * rs;"),
+    ("specular_factor", C_SRC, "r[i] = s[i] - (2.0 * cos_i) * N[i];", "r[i] = s[i] - cos_i * N[i];"),
+    ("escaped_off_by_one", C_SRC, "for (int64_t r = D; r < R; ++r)\n            esc += y[r];",
      "for (int64_t r = D + 1; r < R; ++r)\n            esc += y[r];"),
-    ("pulse_window", "double hi = erfc(((double)(t + 1) * dt_s - tc) / k);",
+    ("pulse_window", C_SRC, "double hi = erfc(((double)(t + 1) * dt_s - tc) / k);",
      "double hi = erfc(((double)(t + 2) * dt_s - tc) / k);"),
-    ("rescale_sign", "y[r] = ldexp(y[r], E - En);", "y[r] = ldexp(y[r], En - E);"),
-    ("absorbed_weight", "absorbed += A->absorb_of_voxel[v] * sv;", "absorbed += sv;"),
+    ("rescale_sign", C_SRC, "y[r] = ldexp(y[r], E - En);", "y[r] = ldexp(y[r], En - E);"),
+    ("absorbed_weight", C_SRC, "absorbed += A->absorb_of_voxel[v] * sv;", "absorbed += sv;"),
+    # detector sums of Eq. (27)
+    ("detector_reads_previous_state", C_SRC, "det[n_det * t + det_id[i]] += det_F[i] * y[det_row[i]];",
+     "det[n_det * t + det_id[i]] += det_F[i] * x[det_row[i]];"),
+    ("detector_weight_dropped", C_SRC, "det[n_det * t + det_id[i]] += det_F[i] * y[det_row[i]];",
+     "det[n_det * t + det_id[i]] += y[det_row[i]];"),
+    ("detector_state_row_for_escape", PY_SRC, "r = A.rows_of(st, d.escape)", "r = A.rows_of(st, False)"),
+    # interface normal of the sphere: at the first voxel's centre, not the step midpoint
+    ("sphere_normal_at_voxel_centre", C_SRC,
+     "double P[3] = {(double)x + 0.5 + 0.5 * (double)e[0],\n"
+     "                       (double)y + 0.5 + 0.5 * (double)e[1],\n"
+     "                       (double)z + 0.5 + 0.5 * (double)e[2]};",
+     "double P[3] = {(double)x + 0.5, (double)y + 0.5, (double)z + 0.5};"),
+    # tied snap directions: the lowest index takes everything
+    ("snap_ties_to_lowest", C_SRC, "if (or_dot3(s, target) >= best - 1e-12) out[k++] = d;",
+     "if (or_dot3(s, target) >= best - 1e-12 && k == 0) out[k++] = d;"),
+    # dither key with row and column swapped
+    ("dither_key_swapped", C_SRC, "uint64_t key = ((uint64_t)r << 32) ^ (uint64_t)(uint32_t)A->col[j];",
+     "uint64_t key = ((uint64_t)(uint32_t)A->col[j] << 32) ^ (uint64_t)r;"),
 ]
 
 
-def _build(tmp_path, text):
-    src = tmp_path / "drts_oracle.c"
-    src.write_text(text)
-    lib = tmp_path / "_mutant.so"
-    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-                           "-o", str(lib), str(src), "-lm"])
-    return str(lib)
+def _copy(tmp_path, fname=None, old=None, new=None):
+    dst = tmp_path / "pkg" / "oracle"
+    dst.mkdir(parents=True)
+    for f in (C_SRC, PY_SRC):
+        shutil.copy(os.path.join(ORACLE, f), dst / f)
+    if fname is not None:
+        text = (dst / fname).read_text()
+        assert text.count(old) == 1, (fname, old)
+        (dst / fname).write_text(text.replace(old, new))
+    return str(tmp_path / "pkg")
 
 
-def _pins(lib):
-    env = dict(os.environ, DRTS_ORACLE_LIB=lib)
+def _pins(pkg):
+    env = dict(os.environ, DRTS_ORACLE_COPY=pkg)
     return subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", "test_oracle_pins.py"),
                            "-x", "-q", "-p", "no:cacheprovider"], cwd=ROOT, env=env,
                           stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, timeout=600)
 
 
 def test_unchanged_copy_passes_the_pins(tmp_path):
-    r = _pins(_build(tmp_path, open(SRC).read()))
+    r = _pins(_copy(tmp_path))
     assert r.returncode == 0, r.stdout[-2000:]
 
 
-@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
-def test_planted_mistake_fails_a_pin(tmp_path, name, old, new):
-    text = open(SRC).read()
-    assert text.count(old) == 1, name
-    r = _pins(_build(tmp_path, text.replace(old, new)))
+@pytest.mark.parametrize("name,fname,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_planted_mistake_fails_a_pin(tmp_path, name, fname, old, new):
+    r = _pins(_copy(tmp_path, fname, old, new))
     assert r.returncode != 0, "%s passed every pin:\n%s" % (name, r.stdout[-2000:])

@@ -69,7 +69,7 @@ def test_interfaces_present_in_tiny_media(orc):
     homog = orc.Matrix(W.homogeneous(5, med.materials[0]))
     assert A.nnz > homog.nnz      # the reflected parts add entries
     R, T, mr, mt = orc.fresnel(DIR[(1, 1, 1)], 1.6, 1.0, np.array([1.0, 0.0, 0.0]))
-    assert R == 1.0 and T == 0.0 and mt == -1
+    assert R == 1.0 and T == 0.0 and mt == []
 
 
 # ---- direction block: Eq. (9)-(10), (19), (21), (24) ---------------------------
@@ -140,7 +140,7 @@ def test_fresnel_normal_incidence(orc):
         R, T, mr, mt = orc.fresnel(DIR[(0, 0, 1)], n1, n2, np.array([0.0, 0.0, 1.0]))
         assert R == pytest.approx(((n1 - n2) / (n1 + n2)) ** 2, rel=1e-13)
         assert R + T == 1.0
-        assert mr == DIR[(0, 0, -1)] and mt == DIR[(0, 0, 1)]
+        assert mr == [DIR[(0, 0, -1)]] and mt == [DIR[(0, 0, 1)]]
 
 
 def test_fresnel_oblique_matches_trig_form(orc):
@@ -156,15 +156,15 @@ def test_fresnel_oblique_matches_trig_form(orc):
         Rp = math.tan(ti - tt) ** 2 / math.tan(ti + tt) ** 2
         assert R == pytest.approx(0.5 * (Rs + Rp), rel=1e-11)
         # planar interface: the mirror direction and, at these contrasts, the same direction
-        assert mr == DIR[(d[0], d[1], -d[2])]
-        assert mt == m
+        assert mr == [DIR[(d[0], d[1], -d[2])]]
+        assert mt == [m]
 
 
 def test_fresnel_total_internal_reflection(orc):
     """Beyond the critical angle asin(n2/n1) everything is reflected."""
     m = DIR[(1, 0, 1)]   # 45 degrees
     R, T, mr, mt = orc.fresnel(m, 1.6, 1.0, np.array([0.0, 0.0, 1.0]))   # critical 38.7 deg
-    assert (R, T, mt) == (1.0, 0.0, -1)
+    assert (R, T, mt) == (1.0, 0.0, [])
     R, T, mr, mt = orc.fresnel(m, 1.3, 1.0, np.array([0.0, 0.0, 1.0]))   # critical 50.3 deg
     assert 0 < R < 1 and T == 1 - R
 
@@ -503,3 +503,191 @@ def test_thread_count_does_not_change_results(orc):
         orc.set_threads(os.cpu_count() or 1)
     for k in ("x", "x_exp", "tot", "tot_exp", "det", "det_exp"):
         assert np.array_equal(one[k], four[k]), k
+
+
+# ---- detectors, Eq. (27) with a one-step window ---------------------------------
+
+def _face_partition_detectors(med):
+    """Six detectors that split the escape rows: each (voxel, direction) that
+    leaves the grid belongs to the first face it crosses in the order
+    -x, +x, -y, +y, -z, +z."""
+    x, y, z = _coords(med)
+    vox = np.stack([x, y, z], axis=1)
+    dims = (med.nx, med.ny, med.nz)
+    parts = [[] for _ in range(6)]
+    for d, e in enumerate(LV):
+        out_lo = [(vox[:, a] + e[a] < 0) for a in range(3)]
+        out_hi = [(vox[:, a] + e[a] >= dims[a]) for a in range(3)]
+        taken = np.zeros(len(vox), dtype=bool)
+        for a in range(3):
+            for k, out in ((2 * a, out_lo[a]), (2 * a + 1, out_hi[a])):
+                sel = out & ~taken
+                for v in np.flatnonzero(sel):
+                    parts[k].append((v, d))
+                taken |= out
+    dets = []
+    for k in range(6):
+        vs = np.array([p[0] for p in parts[k]], dtype=np.int64)
+        ds = np.array([p[1] for p in parts[k]], dtype=np.int64)
+        dets.append(W.Detector(vox[vs], LV[ds], np.ones(len(vs), dtype=bool), np.ones(len(vs)), "face%d" % k))
+    return dets
+
+
+def test_face_detectors_partition_escaped(orc):
+    """Detectors over a partition of the escape rows add up to the escaped
+    total of every step (the detector sums are linear in J, Eq. (27)); a
+    layered scattering medium with Fresnel interfaces and a Gaussian source."""
+    base = W.c2(n=9, n_steps=30)
+    dets = _face_partition_detectors(base.medium)
+    wl = W.Workload("parts", base.medium, base.sources, dets, 30)
+    A = orc.Matrix(wl.medium)
+    assert sum(len(d.F) for d in dets) == A.n_escape
+    r = orc.run_workload(A, wl)
+    det = np.ldexp(r["det"], r["det_exp"])
+    esc = np.ldexp(r["tot"][:, 1], r["tot_exp"][:, 1])
+    assert np.all(esc[3:] > 0)
+    assert np.allclose(det.sum(axis=1), esc, rtol=1e-13, atol=0)
+    assert np.all(det[-1] > 0)
+
+
+def _ballistic_states(med, x0, t):
+    """Closed form of the state after t steps with mu_s = mu_a = 0 (Eq. (11)):
+    every population moves one voxel per step along its own direction."""
+    x, y, z = _coords(med)
+    xs = x0.reshape(-1, 26)
+    out = np.zeros_like(xs)
+    for d, e in enumerate(LV):
+        sx, sy, sz = x - t * e[0], y - t * e[1], z - t * e[2]
+        ok = (sx >= 0) & (sx < med.nx) & (sy >= 0) & (sy < med.ny) & (sz >= 0) & (sz < med.nz)
+        src = sx + med.nx * (sy + med.ny * sz)
+        out[ok, d] = xs[src[ok], d]
+    return out
+
+
+def test_detectors_ballistic_closed_form(orc):
+    """mu_s = mu_a = 0: a detector on the escape rows of the z = 0 face reads,
+    during step t, the weighted populations of the plane z = 0 that move
+    towards -z in the state entering the step; a detector on states reads the
+    state after the step.  Weights are drawn per entry, so a dropped or
+    misplaced weight fails, and doubling every weight doubles the reading."""
+    med = W.homogeneous(6, _mat(0.0, 0.0, 0.9), ny=5, nz=7)
+    A = orc.Matrix(med)
+    rng = np.random.default_rng(27)
+    x0 = W.seeded_state(A.n_states, 5) + 0.25
+    top = W.face_escape_detector(med, "top")
+    top.F = rng.uniform(0.5, 2.0, size=len(top.F))
+    sv = rng.integers(1, [med.nx - 1, med.ny - 1, med.nz - 1], size=(40, 3))
+    sd = LV[rng.integers(0, 26, size=40)]
+    state_det = W.Detector(sv, sd, np.zeros(40, dtype=bool), rng.uniform(0.5, 2.0, size=40), "states")
+    wl = W.Workload("ballistic", med, [], [top, state_det], 3)
+    dr, di, dF, nd = orc.detector_arrays(A, wl)
+    T = 3
+    r = A.run(T, det_rows=dr, det_ids=di, det_F=dF, n_det=nd, x0=x0)
+    r2 = A.run(T, det_rows=dr, det_ids=di, det_F=2.0 * dF, n_det=nd, x0=x0)
+    det = np.ldexp(r["det"], r["det_exp"])
+    assert np.array_equal(np.ldexp(r2["det"], r2["det_exp"]), 2.0 * det)
+    tv = top.vox[:, 0] + med.nx * (top.vox[:, 1] + med.ny * top.vox[:, 2])
+    td = np.array([DIR[tuple(e)] for e in top.dirs])
+    svi = sv[:, 0] + med.nx * (sv[:, 1] + med.ny * sv[:, 2])
+    sdi = np.array([DIR[tuple(e)] for e in sd])
+    for t in range(T):
+        xt = _ballistic_states(med, x0, t)
+        xt1 = _ballistic_states(med, x0, t + 1)
+        want_top = float(np.sum(top.F * xt[tv, td]))
+        want_st = float(np.sum(state_det.F * xt1[svi, sdi]))
+        assert want_top > 0 and want_st > 0
+        assert det[t, 0] == pytest.approx(want_top, rel=1e-14)
+        assert det[t, 1] == pytest.approx(want_st, rel=1e-14)
+
+
+# ---- sphere interfaces: the normal of a crossing (Sec. 4.2) --------------------
+
+def test_sphere_normal_at_step_midpoint(orc):
+    """The normal of a crossing is the sphere's radial direction at the midpoint
+    of the two voxel centres.  The sphere is placed so that this direction is
+    (1,1,0)/sqrt(2) for the +x move out of voxel (3,3,3): the incidence is
+    45 degrees, the specular direction is exactly -y, and the reflected
+    fraction is the textbook Fresnel value at 45 degrees (at the voxel centre
+    the radial direction would be far more oblique, beyond the critical angle)."""
+    inc, bg = _mat(0.0, 0.0, 0.9, 1.45), _mat(0.0, 0.0, 0.9, 1.33)
+    c = (4.0 - 0.8, 3.5 - 0.8, 3.5)
+    med = W.sphere_inclusion(7, bg, inc, c, 1.2)
+    v = 3 + 7 * (3 + 7 * 3)
+    u = 4 + 7 * (3 + 7 * 3)
+    assert med.mat_of_voxel.reshape(-1)[v] == 1 and med.mat_of_voxel.reshape(-1)[u] == 0
+    A = orc.Matrix(med)
+    S = A.to_scipy().tocsc()
+    col = 26 * v + DIR[(1, 0, 0)]
+    rows = S.indices[S.indptr[col]:S.indptr[col + 1]]
+    vals = S.data[S.indptr[col]:S.indptr[col + 1]]
+    entry = dict(zip(rows.tolist(), vals.tolist()))
+    ti = math.pi / 4
+    tt = math.asin(1.45 / 1.33 * math.sin(ti))
+    Rs = math.sin(ti - tt) ** 2 / math.sin(ti + tt) ** 2
+    Rp = math.tan(ti - tt) ** 2 / math.tan(ti + tt) ** 2
+    R = 0.5 * (Rs + Rp)
+    assert entry[26 * v + DIR[(0, -1, 0)]] == pytest.approx(R, rel=1e-12)
+    assert len(entry) == 2
+    (rt, T), = [(k, w) for k, w in entry.items() if k != 26 * v + DIR[(0, -1, 0)]]
+    assert rt // 26 == u and T == pytest.approx(1.0 - R, rel=1e-14)
+
+
+def test_square_symmetry_centred_sphere(orc):
+    """A sphere centred on the middle voxel's column of an odd grid, with a
+    centred +z source and a contrast that reaches total internal reflection:
+    the state is invariant under the 8 symmetries of the square in the xy
+    plane (a normal rule that did not commute with them would break it)."""
+    n, c = 9, 4
+    bg, inc = _mat(10.0, 0.05, 0.8, 1.0), _mat(6.0, 0.2, 0.5, 1.6)
+    med = W.sphere_inclusion(n, bg, inc, (4.5, 4.5, 4.0), 2.6)
+    A = orc.Matrix(med)
+    x0 = np.zeros(A.n_states)
+    x0[26 * (c + n * (c + n * 1)) + DIR[(0, 0, 1)]] = 1.0
+    r = A.run(7, x0=x0)
+    J = np.ldexp(r["x"], r["x_exp"]).reshape(n, n, n, 26)
+    maps = [lambda a, b: (a, b), lambda a, b: (-a, b), lambda a, b: (a, -b), lambda a, b: (-a, -b),
+            lambda a, b: (b, a), lambda a, b: (-b, a), lambda a, b: (b, -a), lambda a, b: (-b, -a)]
+    R, _, _, _ = orc.fresnel(DIR[(1, 1, 1)], 1.6, 1.0, np.array([1.0, 1.0, 1.0]) / math.sqrt(3.0))
+    assert R < 1.0
+    for f in maps:
+        perm = [DIR[(*f(e[0], e[1]), e[2])] for e in LV]
+        K = np.empty_like(J)
+        for yy in range(n):
+            for xx in range(n):
+                ax, ay = f(xx - c, yy - c)
+                K[:, ay + c, ax + c, :][:, perm] = J[:, yy, xx, :]
+        assert np.allclose(K, J, rtol=1e-12, atol=1e-300)
+
+
+# ---- the dither rounding's key, written out from its definition -----------------
+
+def _splitmix64(x):
+    m = (1 << 64) - 1
+    z = (x + 0x9E3779B97F4A7C15) & m
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & m
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & m
+    return z ^ (z >> 31)
+
+
+def test_dither_decisions_follow_the_row_column_key(orc):
+    """Every FP32 value of the dithered matrix, derived here from the rounding
+    rule: r = RN32(a), r' = the other float neighbour of a, p = |r - a|/|r' - r|,
+    u = (splitmix64((row << 32) xor col) >> 11) 2^-53, take r' iff u < p."""
+    A = orc.Matrix(W.layered(4, W.C2_MATS))
+    got = A.round_f32("dither")
+    rp, col, val = A.row_ptr, A.col, A.val
+    n_taken = 0
+    for row in range(A.n_rows):
+        for j in range(rp[row], rp[row + 1]):
+            a = float(val[j])
+            r = np.float32(a)
+            want = r
+            if float(r) != a:
+                r2 = np.nextafter(r, np.float32(np.inf) if float(r) < a else np.float32(-np.inf))
+                p = abs(float(r) - a) / abs(float(r2) - float(r))
+                u = (_splitmix64((row << 32) ^ int(col[j])) >> 11) * 2.0 ** -53
+                if u < p:
+                    want = r2
+                    n_taken += 1
+            assert got[j] == want, (row, int(col[j]))
+    assert n_taken > 100
