@@ -122,6 +122,14 @@ typedef struct {
     int32_t value_type; /* DRTS_F64 | DRTS_F32 */
     int32_t rounding;   /* DRTS_ROUND_* (DRTS_F32 only) */
     double n_ref;       /* refractive index that sets dt = h n_ref / c0 */
+    int32_t scatter_order; /* scatterings within one step that the direction
+                              block resolves (Eq. 4): 0 or 1 = at most one
+                              (Eq. 6-7: every scattered photon changes
+                              direction once); K in 2..16 = the Poisson
+                              weights of 0..K-1 scatterings with powers of the
+                              scattering kernel (a sequence of single
+                              scatterings), the remaining probability taking
+                              K scatterings */
 } drts_medium_t;
 
 /* ---- device hooks ---------------------------------------------------------- */

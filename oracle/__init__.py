@@ -49,6 +49,7 @@ class _Medium(C.Structure):
         ("mat_of_voxel", C.POINTER(C.c_uint8)),
         ("geom", C.c_int32), ("bc", C.c_int32),
         ("sphere_c", C.c_double * 3), ("sphere_r", C.c_double),
+        ("scatter_order", C.c_int32),
     ]
 
 
@@ -81,6 +82,7 @@ def _load():
                                i64, P, P, P, i32,
                                P, P, P, P, P, P]
         lib.or_collision_block.argtypes = [dbl, dbl, dbl, dbl, P]
+        lib.or_collision_block_k.argtypes = [dbl, dbl, dbl, dbl, C.c_int, P]
         lib.or_fresnel.argtypes = [C.c_int, dbl, dbl, P, P, P, P, P, P, P]
         lib.or_dt_seconds.restype = dbl
         lib.or_dt_seconds.argtypes = [dbl, dbl]
@@ -102,10 +104,14 @@ def set_threads(n: int) -> None:
     _load().or_set_threads(int(n))
 
 
-def collision_block(mu_s, mu_a, g, h_mm) -> np.ndarray:
-    """26x26 direction block C[m, n] of one material (Eq. (9), (10), (19), (21))."""
+def collision_block(mu_s, mu_a, g, h_mm, order: int = 1) -> np.ndarray:
+    """26x26 direction block C[m, n] of one material (Eq. (9), (10), (19), (21));
+    order K > 1 resolves up to K scatterings per step (Eq. (4))."""
     out = np.zeros(26 * 26, dtype=np.float64)
-    _load().or_collision_block(mu_s, mu_a, g, h_mm, _ptr(out))
+    if order == 1:
+        _load().or_collision_block(mu_s, mu_a, g, h_mm, _ptr(out))
+    else:
+        _load().or_collision_block_k(mu_s, mu_a, g, h_mm, int(order), _ptr(out))
     return out.reshape(26, 26)
 
 
@@ -170,6 +176,7 @@ class Matrix:
         c = medium.sphere_c if medium.sphere_c is not None else (0.0, 0.0, 0.0)
         st.sphere_c = (C.c_double * 3)(*c)
         st.sphere_r = medium.sphere_r or 0.0
+        st.scatter_order = getattr(medium, "scatter_order", 1)
         self._st = st
         self.medium = medium
         h = lib.or_build(C.byref(st))

@@ -93,20 +93,27 @@ static double or_hg(double g, double cs)
  * Direction block C[m][n] of one material: the fraction of the population of
  * direction n in a voxel that leaves it in direction m during one step.
  *   P0 = exp(-mu_s h)        unscattered, Eq. (9) without absorption
- *   Ps = 1 - P0              scattered once, Eq. (7)
  *   alpha = exp(-mu_a h)     survival against absorption, Eq. (8)
  *   G[m][n] = p(cos_mn) / sum_k p(cos_kn)     discrete g(S_n, S_m)
- *   C[m][n] = alpha (Ps G[m][n])              m != n      (w1 of Eq. (19))
- *   C[n][n] = alpha (P0 + Ps G[n][n])                     (w0 + w1, Eq. (21))
+ *   C[m][n] = alpha S[m][n]                   m != n      (w1 of Eq. (19))
+ *   C[n][n] = alpha (P0 + S[n][n])                        (w0 + w1, Eq. (21))
+ * where S is the scattered part.  With at most one scattering per step
+ * (order K = 1, Eq. (6)-(7)): S = Ps G, Ps = 1 - P0.  With order K > 1, the
+ * population scattered i times during the step (Poisson probability P_i of
+ * Eq. (4)) leaves in the direction of i successive single scatterings, so
+ * its share of the block is P_i G^i; the counts 0..K-1 take their Poisson
+ * probabilities and count K takes what remains:
+ *   S = P_1 G^1 + ... + P_{K-1} G^{K-1} + (1 - P_0 - ... - P_{K-1}) G^K
+ * added in that order, with P_i = P_{i-1} (mu_s h) / i and
+ * G^i[m][n] = sum_k G[m][k] G^{i-1}[k][n] (ascending k).
  * Here h = c dt is the voxel edge.
  */
-void or_collision_block(double mu_s, double mu_a, double g, double h,
-                        double *C /* [26*26], row m, column n */)
+void or_collision_block_k(double mu_s, double mu_a, double g, double h, int K,
+                          double *C /* [26*26], row m, column n */)
 {
     double P0 = exp(-mu_s * h);
-    double Ps = 1.0 - P0;
     double alpha = exp(-mu_a * h);
-    double p[NDIR][NDIR];
+    double p[NDIR][NDIR], G[NDIR][NDIR], Gi[NDIR][NDIR], Gn[NDIR][NDIR], S[NDIR][NDIR];
     for (int m = 0; m < NDIR; ++m) {
         int em[3];
         or_dir_vec(m, em);
@@ -124,11 +131,45 @@ void or_collision_block(double mu_s, double mu_a, double g, double h,
         double Z = 0.0;
         for (int k = 0; k < NDIR; ++k)
             Z += p[k][n];
-        for (int m = 0; m < NDIR; ++m) {
-            double G = p[m][n] / Z;
-            C[m * NDIR + n] = (m != n) ? alpha * (Ps * G) : alpha * (P0 + Ps * G);
+        for (int m = 0; m < NDIR; ++m)
+            G[m][n] = p[m][n] / Z;
+    }
+    if (K < 1) K = 1;
+    double lam = mu_s * h;
+    double Pi = P0, seen = P0;
+    memcpy(Gi, G, sizeof G);
+    for (int i = 1; i <= K; ++i) {
+        double w;
+        if (i < K) {
+            Pi = (Pi * lam) / (double)i;   /* Poisson probability of i scatterings */
+            w = Pi;
+            seen = seen + Pi;
+        } else {
+            w = 1.0 - seen;                /* K or more scatterings */
+        }
+        for (int m = 0; m < NDIR; ++m)
+            for (int n = 0; n < NDIR; ++n)
+                S[m][n] = (i == 1) ? w * Gi[m][n] : S[m][n] + w * Gi[m][n];
+        if (i < K) {
+            for (int m = 0; m < NDIR; ++m)
+                for (int n = 0; n < NDIR; ++n) {
+                    double acc = 0.0;
+                    for (int k = 0; k < NDIR; ++k)
+                        acc += G[m][k] * Gi[k][n];
+                    Gn[m][n] = acc;
+                }
+            memcpy(Gi, Gn, sizeof Gi);
         }
     }
+    for (int n = 0; n < NDIR; ++n)
+        for (int m = 0; m < NDIR; ++m)
+            C[m * NDIR + n] = (m != n) ? alpha * S[m][n] : alpha * (P0 + S[n][n]);
+}
+
+/* the single-scatter block (order 1) */
+void or_collision_block(double mu_s, double mu_a, double g, double h, double *C)
+{
+    or_collision_block_k(mu_s, mu_a, g, h, 1, C);
 }
 
 /* ---- interfaces ---------------------------------------------------------- */
@@ -216,6 +257,7 @@ typedef struct {
     int32_t bc;                  /* outer faces */
     double sphere_c[3];          /* voxel units; voxel centres at index + 0.5 */
     double sphere_r;
+    int32_t scatter_order;       /* scatterings per step the direction block resolves */
 } or_medium_t;
 
 /* unit normal at the crossing of voxel (x,y,z) along lattice vector e,
@@ -356,8 +398,8 @@ or_csr_t *or_build(const or_medium_t *M)
     if (!A->escape_of_state || !A->absorb_of_voxel || !Cq) goto fail;
 
     for (int q = 0; q < M->n_mat; ++q)
-        or_collision_block(M->mat[4 * q], M->mat[4 * q + 1], M->mat[4 * q + 2], M->h_mm,
-                           Cq + (int64_t)q * NDIR * NDIR);
+        or_collision_block_k(M->mat[4 * q], M->mat[4 * q + 1], M->mat[4 * q + 2], M->h_mm, M->scatter_order,
+                             Cq + (int64_t)q * NDIR * NDIR);
 
     /* escape rows: (v, m) pairs leaving the grid, ascending state order */
     int64_t ne = 0;

@@ -65,6 +65,7 @@ struct Model {
     double h_mm = 0, dt_s = 0;
     int bc = DRTS_BC_VACUUM;
     int value_type = DRTS_F32, rounding = DRTS_ROUND_DITHER;
+    int scatter_order = 1;                  // scatterings per step resolved by the blocks
     std::vector<drts_material_t> mats;
     std::vector<uint8_t> mat_of_voxel;      // [n_vox]
     std::vector<double> blocks;             // [n_mat][26][26] C_q[m][n]

@@ -46,13 +46,18 @@ inline double phase_hg(double g, double cs)
     return (1.0 - g * g) / (q * std::sqrt(q));
 }
 
-// C[m][n] = alpha (Ps G[m][n]) off the diagonal, alpha (P0 + Ps G[n][n]) on it,
-// with P0 = exp(-mu_s h), Ps = 1 - P0, alpha = exp(-mu_a h) and
-// G[m][n] = p(cos_mn) / sum_k p(cos_kn) (Eq. (9)-(10), (19), (21)).
-void direction_block(const drts_material_t &q, double h, double *C)
+// C[m][n] = alpha (S[m][n]) off the diagonal, alpha (P0 + S[n][n]) on it, with
+// P0 = exp(-mu_s h), alpha = exp(-mu_a h), G[m][n] = p(cos_mn) / sum_k p(cos_kn)
+// (Eq. (9)-(10), (19), (21)) and S the scattered part.  With at most one
+// scattering per step (K = 1, Eq. (6)-(7)) S = Ps G, Ps = 1 - P0.  With K > 1
+// the photons scattered i times in the step (Poisson weight P_i of Eq. (4),
+// P_i = P_{i-1} (mu_s h) / i) end in the direction of i successive single
+// scatterings, G^i = G G^{i-1}:
+//   S = P_1 G + P_2 G^2 + ... + P_{K-1} G^{K-1} + (1 - P_0 - ... - P_{K-1}) G^K,
+// summed in that order (the last weight takes every larger count).
+void direction_block(const drts_material_t &q, double h, int K, double *C)
 {
     const double P0 = std::exp(-q.mu_s * h);
-    const double Ps = 1.0 - P0;
     const double alpha = std::exp(-q.mu_a * h);
     double phase[kDirs][kDirs];
     for (int a = 0; a < kDirs; ++a) {
@@ -64,14 +69,42 @@ void direction_block(const drts_material_t &q, double h, double *C)
             phase[a][b] = phase_hg(q.g, (double)ip / std::sqrt((double)(la * lb)));
         }
     }
+    std::vector<double> G((size_t)kDirs * kDirs), Gi, next((size_t)kDirs * kDirs), S((size_t)kDirs * kDirs, 0.0);
     for (int n = 0; n < kDirs; ++n) {
         double Z = 0.0;
         for (int k = 0; k < kDirs; ++k) Z += phase[k][n];
-        for (int m = 0; m < kDirs; ++m) {
-            const double G = phase[m][n] / Z;
-            C[m * kDirs + n] = (m == n) ? alpha * (P0 + Ps * G) : alpha * (Ps * G);
+        for (int m = 0; m < kDirs; ++m) G[(size_t)m * kDirs + n] = phase[m][n] / Z;
+    }
+    // Poisson weights and the remaining probability
+    double Pi = P0, cum = P0;
+    const double lam = q.mu_s * h;
+    Gi = G;   // G^1
+    for (int i = 1; i <= K; ++i) {
+        double w;
+        if (i < K) {
+            Pi = (Pi * lam) / (double)i;
+            w = Pi;
+            cum = cum + Pi;
+        } else {
+            w = 1.0 - cum;
+        }
+        for (size_t e = 0; e < S.size(); ++e) S[e] = (i == 1) ? w * Gi[e] : S[e] + w * Gi[e];
+        if (i < K) {
+            // G^{i+1}[m][n] = sum_k G[m][k] G^i[k][n], ascending k
+            for (int m = 0; m < kDirs; ++m)
+                for (int n = 0; n < kDirs; ++n) {
+                    double acc = 0.0;
+                    for (int k = 0; k < kDirs; ++k) acc += G[(size_t)m * kDirs + k] * Gi[(size_t)k * kDirs + n];
+                    next[(size_t)m * kDirs + n] = acc;
+                }
+            Gi.swap(next);
         }
     }
+    for (int n = 0; n < kDirs; ++n)
+        for (int m = 0; m < kDirs; ++m) {
+            const double s = S[(size_t)m * kDirs + n];
+            C[m * kDirs + n] = (m == n) ? alpha * (P0 + s) : alpha * s;
+        }
 }
 
 // Lattice directions on side `side` of the surface (sign of s_d . N) whose unit
@@ -203,6 +236,8 @@ int build_model(const drts_medium_t *m, Model *M)
     if (m->geom.kind < DRTS_GEOM_VOXELS || m->geom.kind > DRTS_GEOM_SPHERE)
         return set_error(DRTS_E_INVALID, "bad geometry kind %d", m->geom.kind);
     if (!(m->n_ref > 0.0)) return set_error(DRTS_E_INVALID, "n_ref must be positive");
+    if (m->scatter_order < 0 || m->scatter_order > 16)
+        return set_error(DRTS_E_INVALID, "scatter_order must be in 0..16");
     for (int q = 0; q < m->n_mat; ++q) {
         const drts_material_t &mt = m->mat[q];
         if (!(mt.mu_s >= 0.0) || !(mt.mu_a >= 0.0) || !(mt.g > -1.0 && mt.g < 1.0) || !(mt.n > 0.0) ||
@@ -223,6 +258,7 @@ int build_model(const drts_medium_t *m, Model *M)
     M->bc = m->bc;
     M->value_type = m->value_type;
     M->rounding = m->rounding;
+    M->scatter_order = m->scatter_order < 1 ? 1 : m->scatter_order;
     M->mats.assign(m->mat, m->mat + m->n_mat);
 
     // material map
@@ -265,7 +301,7 @@ int build_model(const drts_medium_t *m, Model *M)
     M->absorb.resize(m->n_mat);
     M->index.resize(m->n_mat);
     for (int q = 0; q < m->n_mat; ++q) {
-        direction_block(m->mat[q], g.h_mm, &M->blocks[(size_t)q * kDirs * kDirs]);
+        direction_block(m->mat[q], g.h_mm, M->scatter_order, &M->blocks[(size_t)q * kDirs * kDirs]);
         M->absorb[q] = -std::expm1(-m->mat[q].mu_a * g.h_mm);
         M->index[q] = m->mat[q].n;
     }

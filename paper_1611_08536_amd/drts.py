@@ -70,7 +70,7 @@ class Geometry(C.Structure):
 class MediumT(C.Structure):
     _fields_ = [("grid", Grid), ("n_mat", i32), ("mat", C.POINTER(MaterialT)),
                 ("mat_of_voxel", C.POINTER(C.c_uint8)), ("geom", Geometry), ("bc", i32),
-                ("value_type", i32), ("rounding", i32), ("n_ref", dbl)]
+                ("value_type", i32), ("rounding", i32), ("n_ref", dbl), ("scatter_order", i32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(P, P, C.c_size_t, P)
@@ -246,6 +246,7 @@ def _medium_struct(medium, value_type="f32", rounding="dither", n_ref=None, use_
     m.value_type = F64 if value_type == "f64" else F32
     m.rounding = ROUND_DITHER if rounding == "dither" else ROUND_NEAREST
     m.n_ref = n_ref if n_ref is not None else medium.materials[0].n
+    m.scatter_order = getattr(medium, "scatter_order", 1)
     return m, (mats, vmap, z0)
 
 

@@ -26,7 +26,7 @@ MUTANTS = [
     # (p[m][n] is symmetric, so transposing the normalisation sum changes
     # nothing; the block itself is not: its normalisation differs per column)
     ("block_transposed", C_SRC, "C[m * NDIR + n] = (m != n)", "C[n * NDIR + m] = (m != n)"),
-    ("forward_term_dropped", C_SRC, "alpha * (P0 + Ps * G)", "alpha * (Ps * G)"),
+    ("forward_term_dropped", C_SRC, "alpha * (P0 + S[n][n])", "alpha * (S[n][n])"),
     ("absorption_coefficient", C_SRC, "double alpha = exp(-mu_a * h);", "double alpha = exp(-mu_s * h);"),
     ("fresnel_average", C_SRC, "R = 0.5 * (rs * rs + rp * rp);", "R = rs * rs;"),
     ("specular_factor", C_SRC, "r[i] = s[i] - (2.0 * cos_i) * N[i];", "r[i] = s[i] - cos_i * N[i];"),
@@ -51,6 +51,14 @@ MUTANTS = [
     # tied snap directions: the lowest index takes everything
     ("snap_ties_to_lowest", C_SRC, "if (or_dot3(s, target) >= best - 1e-12) out[k++] = d;",
      "if (or_dot3(s, target) >= best - 1e-12 && k == 0) out[k++] = d;"),
+    # several scatterings per step (Eq. (4)): Poisson weight without 1/i,
+    # the kernel power never advancing past G^2, the remaining probability
+    # dropped, the medium's order not reaching the assembly
+    ("poisson_factorial_dropped", C_SRC, "Pi = (Pi * lam) / (double)i;", "Pi = Pi * lam;"),
+    ("kernel_power_stuck", C_SRC, "acc += G[m][k] * Gi[k][n];", "acc += G[m][k] * G[k][n];"),
+    ("remaining_probability_dropped", C_SRC, "w = 1.0 - seen;", "w = 0.0 * seen;"),
+    ("medium_order_ignored", PY_SRC, 'st.scatter_order = getattr(medium, "scatter_order", 1)',
+     "st.scatter_order = 1"),
     # dither key with row and column swapped
     ("dither_key_swapped", C_SRC, "uint64_t key = ((uint64_t)r << 32) ^ (uint64_t)(uint32_t)A->col[j];",
      "uint64_t key = ((uint64_t)(uint32_t)A->col[j] << 32) ^ (uint64_t)r;"),

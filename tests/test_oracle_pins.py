@@ -691,3 +691,68 @@ def test_dither_decisions_follow_the_row_column_key(orc):
                     n_taken += 1
             assert got[j] == want, (row, int(col[j]))
     assert n_taken > 100
+
+
+# ---- several scatterings within one step (Eq. (4)-(5)) ---------------------------
+
+def _single_scatter_kernel(orc, mu_s, g, h):
+    """The discrete scattering kernel G recovered from the single-scatter block
+    (pinned above against the Henyey-Greenstein form): C1 = P0 I + (1 - P0) G
+    without absorption."""
+    C1 = orc.collision_block(mu_s, 0.0, g, h)
+    P0 = math.exp(-mu_s * h)
+    return (C1 - P0 * np.eye(26)) / (1.0 - P0)
+
+
+@pytest.mark.parametrize("K", [2, 3, 5, 9])
+def test_higher_order_block_columns_sum_to_survival(orc, K):
+    """Every order keeps the column sums at exp(-mu_a c dt) (Eq. (24))."""
+    for mu_s, mu_a, g in [(10, 0.01, 0.9), (20, 0.1, 0.7), (3, 0.5, 0.0)]:
+        C = orc.collision_block(mu_s, mu_a, g, 0.1, order=K)
+        assert np.allclose(C.sum(axis=0), math.exp(-mu_a * 0.1), rtol=0, atol=40 * 2.3e-16)
+        assert np.all(C >= 0)
+
+
+def test_higher_order_isotropic_equals_single_scatter(orc):
+    """g = 0: one scatter already spreads uniformly (G^i = G), so every order
+    gives the single-scatter block."""
+    C1 = orc.collision_block(15.0, 0.2, 0.0, 0.1)
+    for K in (2, 4, 7):
+        assert np.allclose(orc.collision_block(15.0, 0.2, 0.0, 0.1, order=K), C1, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("mu_s,g", [(10.0, 0.9), (20.0, 0.7), (5.0, 0.3)])
+def test_high_order_limit_is_the_matrix_exponential(orc, mu_s, g):
+    """Poisson-weighted powers of the kernel sum to exp(lambda (G - I)) with
+    lambda = mu_s c dt (a continuous-time Markov chain over directions,
+    scatterings at rate mu_s c): at order 16 the omitted tail is below 1e-13."""
+    from scipy.linalg import expm
+    h, mu_a = 0.1, 0.03
+    G = _single_scatter_kernel(orc, mu_s, g, h)
+    lam = mu_s * h
+    want = math.exp(-mu_a * h) * expm(lam * (G - np.eye(26)))
+    got = orc.collision_block(mu_s, mu_a, g, h, order=16)
+    assert np.allclose(got, want, rtol=0, atol=2e-13)
+    # order 2 is the two-scatter truncation: P0 I + P1 G + (1 - P0 - P1) G^2
+    P0, P1 = math.exp(-lam), math.exp(-lam) * lam
+    want2 = math.exp(-mu_a * h) * (P0 * np.eye(26) + P1 * G + (1 - P0 - P1) * (G @ G))
+    assert np.allclose(orc.collision_block(mu_s, mu_a, g, h, order=2), want2, rtol=0, atol=1e-14)
+
+
+def test_higher_order_medium_steps_with_its_block(orc):
+    """A medium of scatter order 3: before anything reaches a face, the angular
+    marginal follows the order-3 block, sum_v J_t = C3^t J_0."""
+    mat = _mat(20.0, 0.05, 0.8)
+    med = W.homogeneous(11, mat)
+    med.scatter_order = 3
+    A = orc.Matrix(med)
+    C3 = orc.collision_block(mat.mu_s, mat.mu_a, mat.g, med.h_mm, order=3)
+    assert not np.allclose(C3, orc.collision_block(mat.mu_s, mat.mu_a, mat.g, med.h_mm), rtol=1e-6)
+    x0 = np.zeros(A.n_states)
+    v0 = 5 + 11 * (5 + 11 * 5)
+    j0 = W.seeded_state(26, 6)
+    x0[26 * v0: 26 * v0 + 26] = j0
+    for t in (1, 4):
+        r = A.run(t, x0=x0)
+        marg = np.ldexp(r["x"], r["x_exp"]).reshape(-1, 26).sum(axis=0)
+        assert np.allclose(marg, np.linalg.matrix_power(C3, t) @ j0, rtol=1e-13, atol=0)

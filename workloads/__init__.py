@@ -65,6 +65,7 @@ class Medium:
     sphere_c: Optional[Tuple[float, float, float]] = None   # voxel units, centres at i + 0.5
     sphere_r: Optional[float] = None
     layer_z0: Tuple[int, ...] = ()
+    scatter_order: int = 1              # scatterings per step the direction block resolves
 
     @property
     def n_vox(self) -> int:
