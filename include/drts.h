@@ -328,6 +328,24 @@ int drts_solver_time(const drts_solver_t *S, int64_t *t);
 int drts_detector_readout(const drts_solver_t *S, int64_t first, int64_t count, double *series,
                           int32_t *exp2, double *totals);
 
+/* Windowed measurement (Eq. 27 with a window of several steps, Sec. 4.2): a
+ * sensor responds to the photons reaching it through its impulse response,
+ * so its reading at step t is the per-step detector sum m_d (the series of
+ * drts_detector_readout) filtered by that response:
+ *     M_d(t) = sum_{j=0}^{n_taps-1} taps[d][j] m_d(t - tap0 - j)
+ * taps: host [n_det][n_taps], detector d's response at delays
+ * tap0 .. tap0 + n_taps - 1 steps (tap0 < 0 lets a reading include later
+ * steps, the symmetric window of Eq. 27).  Steps outside 0 .. t - 1 of the
+ * solver's current step count t contribute nothing.  Output for steps
+ * [first, first + count): out[t][d][k] * 2^out_exp[t][d][k] (host arrays),
+ * computed on the device in FP64 (each reading's terms brought to the largest
+ * exponent among them, added in ascending tap order).  Synchronises the
+ * stream; device memory for the taps and the output comes from the solver's
+ * hooks during the call.  Errors: DRTS_E_INVALID (no detectors, n_taps
+ * outside 1..65536, NULL arrays), DRTS_E_RANGE (steps beyond max_steps). */
+int drts_detector_window(const drts_solver_t *S, const double *taps, int32_t n_taps, int32_t tap0, int64_t first,
+                         int64_t count, double *out, int32_t *out_exp);
+
 /* State transfer for checkpoint/resume (bit-exact): host_x is
  * [n_rows][n_rhs] in the value type (state rows, then the escape rows of the
  * last step), exp2[n_rhs], t.  state_write zeroes nothing else and keeps the

@@ -286,6 +286,31 @@ class Matrix:
                 "x": x_out, "x_exp": int(e_out.value)}
 
 
+# ---- windowed measurement ------------------------------------------------------
+
+def window(det, det_exp, taps, tap0=0, t_done=None):
+    """Readings of sensors with impulse responses (Eq. (27) over several steps):
+    M_d(t) = sum_j taps[d][j] m_d(t - tap0 - j) for every step t of the series,
+    where m_d(s) = det[s, d] * 2^det_exp[s, d] is the one-step detector sum and
+    steps outside 0 .. t_done - 1 contribute nothing.  Plain FP64 loops,
+    ascending j; returns physical values [T, n_det]."""
+    det = np.asarray(det, dtype=np.float64)
+    T, nd = det.shape
+    t_done = T if t_done is None else t_done
+    m = np.ldexp(det, np.asarray(det_exp))
+    taps = np.broadcast_to(np.asarray(taps, dtype=np.float64), (nd, np.asarray(taps).shape[-1]))
+    out = np.zeros((T, nd))
+    for t in range(T):
+        for d in range(nd):
+            acc = 0.0
+            for j in range(taps.shape[1]):
+                s = t - tap0 - j
+                if 0 <= s < t_done and taps[d, j] != 0.0:
+                    acc += taps[d, j] * m[s, d]
+            out[t, d] = acc
+    return out
+
+
 # ---- workload helpers (oracle side of the row mapping) ----------------------
 
 def state_of(medium, vox, dirs) -> np.ndarray:

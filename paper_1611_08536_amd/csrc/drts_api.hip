@@ -1282,6 +1282,44 @@ int drts_detector_readout(const drts_solver_t *S, int64_t first, int64_t count, 
     return DRTS_OK;
 }
 
+int drts_detector_window(const drts_solver_t *S, const double *taps, int32_t n_taps, int32_t tap0, int64_t first,
+                         int64_t count, double *out, int32_t *out_exp)
+{
+    if (!S || !taps || !out || !out_exp) return set_error(DRTS_E_INVALID, "NULL argument");
+    if (S->n_det < 1) return set_error(DRTS_E_INVALID, "the solver has no detectors");
+    if (n_taps < 1 || n_taps > 65536) return set_error(DRTS_E_INVALID, "n_taps must be in 1..65536");
+    if (first < 0 || count < 0 || first + count > S->max_steps) return set_error(DRTS_E_RANGE, "steps out of range");
+    if (count == 0) return DRTS_OK;
+    Device &dev = const_cast<drts_solver *>(S)->dev;
+    const size_t n_out = (size_t)count * S->n_det * S->n_rhs;
+    Buffer dtaps, dout, dexp;
+    int rc;
+    if ((rc = dtaps.allocate(&dev, (size_t)S->n_det * n_taps * sizeof(double)))) return rc;
+    if ((rc = dout.allocate(&dev, n_out * sizeof(double)))) return rc;
+    if ((rc = dexp.allocate(&dev, n_out * sizeof(int32_t)))) return rc;
+    DRTS_HIP(hipMemcpyAsync(dtaps.ptr, taps, (size_t)S->n_det * n_taps * sizeof(double), hipMemcpyHostToDevice,
+                            dev.stream));
+    WindowArgs a;
+    a.ser_det = S->ser_det.as<double>();
+    a.ser_exp = S->ser_exp.as<int32_t>();
+    a.taps = dtaps.as<double>();
+    a.n_det = S->n_det;
+    a.n_rhs = S->n_rhs;
+    a.n_taps = n_taps;
+    a.tap0 = tap0;
+    a.first = first;
+    a.count = count;
+    a.t_done = S->t_host;
+    a.out = dout.as<double>();
+    a.out_exp = dexp.as<int32_t>();
+    hipError_t e = launch_detector_window(a, dev.stream);
+    if (e != hipSuccess) return set_error(DRTS_E_HIP, "window launch failed: %s", hipGetErrorString(e));
+    DRTS_HIP(hipMemcpyAsync(out, dout.ptr, n_out * sizeof(double), hipMemcpyDeviceToHost, dev.stream));
+    DRTS_HIP(hipMemcpyAsync(out_exp, dexp.ptr, n_out * sizeof(int32_t), hipMemcpyDeviceToHost, dev.stream));
+    DRTS_HIP(hipStreamSynchronize(dev.stream));
+    return DRTS_OK;
+}
+
 int drts_state_read(const drts_solver_t *S, void *host_x, int32_t *exp2, int64_t *t)
 {
     if (!S) return set_error(DRTS_E_INVALID, "solver is NULL");

@@ -96,6 +96,18 @@ struct Matrix {
 
 int assemble_on_device(Matrix *A);
 
+// ---- windowed measurement (Eq. 27 over several steps) --------------------------
+struct WindowArgs {
+    const double *ser_det;   // [max_steps][n_det][n_rhs]
+    const int32_t *ser_exp;  // [max_steps][n_rhs]
+    const double *taps;      // [n_det][n_taps]
+    int32_t n_det, n_rhs, n_taps, tap0;
+    int64_t first, count, t_done;
+    double *out;             // [count][n_det][n_rhs]
+    int32_t *out_exp;        // [count][n_det][n_rhs]
+};
+hipError_t launch_detector_window(const WindowArgs &a, hipStream_t stream);
+
 // drts_build_matrix for a medium whose host model is already built (the
 // model is moved into the matrix).
 int build_matrix_from_model(Model &&model, const drts_device_t *dev, drts_matrix_t **out);

@@ -123,6 +123,7 @@ _sig("drts_step_noalloc", C.c_int, [P, C.POINTER(SourceTableT)])
 _sig("drts_run", C.c_int, [P, C.POINTER(SourceTableT), i64])
 _sig("drts_solver_time", C.c_int, [P, C.POINTER(i64)])
 _sig("drts_detector_readout", C.c_int, [P, i64, i64, P, P, P])
+_sig("drts_detector_window", C.c_int, [P, P, i32, i32, i64, i64, P, P])
 _sig("drts_state_read", C.c_int, [P, P, P, C.POINTER(i64)])
 _sig("drts_state_write", C.c_int, [P, P, P, i64])
 _sig("drts_solver_profile", C.c_int, [P, i32])
@@ -148,7 +149,7 @@ _sig("drts_serve_set_step", C.c_int, [P, i32])
 EXPORTED = [
     "drts_build_matrix", "drts_matrix_info", "drts_matrix_row_of", "drts_matrix_export_rows",
     "drts_matrix_destroy", "drts_solver_create", "drts_solver_get_options", "drts_solver_set_options",
-    "drts_step", "drts_step_noalloc", "drts_run", "drts_solver_time", "drts_detector_readout", "drts_state_read",
+    "drts_step", "drts_step_noalloc", "drts_run", "drts_solver_time", "drts_detector_readout", "drts_detector_window", "drts_state_read",
     "drts_state_write", "drts_solver_profile", "drts_solver_profile_stats", "drts_solver_destroy",
     "drts_batch_create", "drts_batch_run", "drts_batch_destroy", "drts_batch_autotune", "drts_autotune", "drts_last_error",
     "drts_serve_create", "drts_serve_submit", "drts_serve_footprint", "drts_serve_tick", "drts_serve_poll", "drts_serve_result",
@@ -417,6 +418,19 @@ class Solver:
         _check(_lib.drts_detector_readout(self._h, first, count, ser.ctypes.data, e.ctypes.data, tot.ctypes.data),
                "drts_detector_readout")
         return {"det": ser[:, :nd, :], "exp2": e, "tot": tot}
+
+    def window(self, taps, tap0: int = 0, first: int = 0, count: Optional[int] = None):
+        """drts_detector_window: readings of sensors with impulse responses
+        taps [n_det, n_taps] (delays tap0 ..), as (value [count, n_det, n_rhs],
+        exp2 [count, n_det, n_rhs])."""
+        taps = np.ascontiguousarray(np.broadcast_to(np.asarray(taps, dtype=np.float64),
+                                                    (self.n_det, np.asarray(taps).shape[-1])))
+        count = (self.max_steps - first) if count is None else count
+        out = np.zeros((count, self.n_det, self.n_rhs))
+        e = np.zeros((count, self.n_det, self.n_rhs), dtype=np.int32)
+        _check(_lib.drts_detector_window(self._h, taps.ctypes.data, taps.shape[1], int(tap0), int(first), int(count),
+                                         out.ctypes.data, e.ctypes.data), "drts_detector_window")
+        return out, e
 
     def state(self):
         dtype = np.float64 if self.A.value_type == "f64" else np.float32

@@ -59,6 +59,10 @@ MUTANTS = [
     ("remaining_probability_dropped", C_SRC, "w = 1.0 - seen;", "w = 0.0 * seen;"),
     ("medium_order_ignored", PY_SRC, 'st.scatter_order = getattr(medium, "scatter_order", 1)',
      "st.scatter_order = 1"),
+    # windowed measurement (Eq. (27)): response applied backwards in time,
+    # delay of the response with the wrong sign
+    ("window_response_reversed", PY_SRC, "s = t - tap0 - j", "s = t - tap0 + j"),
+    ("window_delay_sign", PY_SRC, "s = t - tap0 - j", "s = t + tap0 - j"),
     # dither key with row and column swapped
     ("dither_key_swapped", C_SRC, "uint64_t key = ((uint64_t)r << 32) ^ (uint64_t)(uint32_t)A->col[j];",
      "uint64_t key = ((uint64_t)(uint32_t)A->col[j] << 32) ^ (uint64_t)r;"),

@@ -756,3 +756,78 @@ def test_higher_order_medium_steps_with_its_block(orc):
         r = A.run(t, x0=x0)
         marg = np.ldexp(r["x"], r["x_exp"]).reshape(-1, 26).sum(axis=0)
         assert np.allclose(marg, np.linalg.matrix_power(C3, t) @ j0, rtol=1e-13, atol=0)
+
+
+# ---- windowed measurement and outside sensors (Eq. (27), Sec. 4.2) ---------------
+
+def test_window_of_a_ballistic_impulse_is_the_sensor_response(orc):
+    """mu_s = mu_a = 0: one photon moving -z from depth z0 leaves through the
+    z = 0 face during step z0 exactly, so the one-step detector is a unit
+    impulse at z0 and a sensor reading is its impulse response, delayed:
+    M(t) = h(t - z0 - tap0)."""
+    med = W.homogeneous(5, _mat(0.0, 0.0, 0.9), nz=9)
+    A = orc.Matrix(med)
+    z0 = 6
+    x0 = np.zeros(A.n_states)
+    x0[26 * (2 + 5 * (2 + 5 * z0)) + DIR[(0, 0, -1)]] = 1.0
+    top = W.face_escape_detector(med, "top")
+    wl = W.Workload("imp", med, [], [top], 20)
+    dr, di, dF, nd = orc.detector_arrays(A, wl)
+    r = A.run(20, det_rows=dr, det_ids=di, det_F=dF, n_det=nd, x0=x0)
+    m = np.ldexp(r["det"][:, 0], r["det_exp"][:, 0])
+    assert m[z0] == 1.0 and np.count_nonzero(m) == 1
+    h = np.array([0.1, 0.5, 0.25, 0.125, 0.0625])
+    for tap0 in (0, 2, -3):
+        M = orc.window(r["det"], r["det_exp"], h[None, :], tap0)[:, 0]
+        want = np.zeros(20)
+        for j, hj in enumerate(h):
+            if 0 <= z0 + tap0 + j < 20:
+                want[z0 + tap0 + j] = hj
+        assert np.array_equal(M, want), tap0
+
+
+def test_window_over_the_whole_run_balances_energy(orc):
+    """A sensor that integrates every step (all-ones response) over all escape
+    rows reads the photons that have left by step t; with those absorbed and
+    those still inside it accounts for everything emitted (Eq. (24), Sec. 3)."""
+    base = W.c2(n=8, n_steps=40)
+    dets = _face_partition_detectors(base.medium)
+    wl = W.Workload("parts", base.medium, base.sources, dets, 40)
+    A = orc.Matrix(wl.medium)
+    r = orc.run_workload(A, wl)
+    T = 40
+    M = orc.window(r["det"], r["det_exp"], np.ones((6, T)), 0)
+    escaped_by_t = M.sum(axis=1)
+    tot = np.ldexp(r["tot"], r["tot_exp"])
+    absorbed_by_t = np.cumsum(tot[:, 2])
+    _, _, sw, amp = orc.source_arrays(A, wl)
+    emitted_by_t = np.cumsum(amp[:T, 0]) * sw.sum()
+    assert np.allclose(escaped_by_t + absorbed_by_t + tot[:, 0], emitted_by_t, rtol=1e-12, atol=0)
+
+
+def test_outside_sensor_reads_the_delayed_escape_flux(orc):
+    """Free space added above the surface (Sec. 4.2: no scattering or
+    absorption, photons keep their direction): a sensor on the top face of
+    the extension reads, gap steps later, the photons that left the original
+    surface in directions that keep them over the sensor for gap steps."""
+    gap, T = 3, 30
+    base = W.c2(n=9, n_steps=T)
+    med = base.medium
+    ext = W.extend_top(med, gap)
+    assert ext.mat_of_voxel[gap:].min() >= 1 and (ext.mat_of_voxel[:gap] == 0).all()
+    # the sensor: escape rows of the extension's top face
+    sensor = W.face_escape_detector(ext, "top")
+    we = W.Workload("ext", ext, [W.shifted_z(s, gap) for s in base.sources], [sensor], T)
+    # on the original: its top-face escapes weighted by whether the photon stays
+    # over the sensor for gap steps
+    top = W.face_escape_detector(med, "top")
+    end = top.vox[:, :2] + gap * top.dirs[:, :2]
+    top.F = (((end >= 0) & (end < np.array([med.nx, med.ny]))).all(axis=1)).astype(np.float64)
+    wo = W.Workload("orig", med, base.sources, [top], T)
+    re = orc.run_workload(orc.Matrix(ext), we)
+    ro = orc.run_workload(orc.Matrix(med), wo)
+    se = np.ldexp(re["det"][:, 0], re["det_exp"][:, 0])
+    so = np.ldexp(ro["det"][:, 0], ro["det_exp"][:, 0])
+    assert np.all(se[:gap] == 0)
+    assert so[3:].max() > 0
+    assert np.allclose(se[gap:], so[:T - gap], rtol=1e-12, atol=1e-300)

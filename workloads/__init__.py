@@ -145,6 +145,33 @@ def sphere_inclusion(n: int, bg: Material, inc: Material, c, r, h_mm: float = 0.
                   sphere_c=tuple(float(v) for v in c), sphere_r=float(r))
 
 
+def extend_top(med: Medium, gap: int, n_ext: Optional[float] = None) -> Medium:
+    """The medium with `gap` planes of free space (no scattering, no
+    absorption) added above its z = 0 face, so that a sensor outside the
+    volume can be placed in the grid (Sec. 4.2).  Voxel (x, y, z) of the
+    original is voxel (x, y, z + gap) of the result.  The free space has index
+    n_ext, by default the index of the original's top voxels (no interface at
+    the original surface, as at its vacuum faces)."""
+    top = med.materials[int(med.mat_of_voxel[0, 0, 0])]
+    free = Material(0.0, 0.0, 0.0, top.n if n_ext is None else n_ext)
+    m = np.empty((med.nz + gap, med.ny, med.nx), dtype=np.uint8)
+    m[:gap] = 0
+    m[gap:] = med.mat_of_voxel + 1
+    sc = None if med.sphere_c is None else (med.sphere_c[0], med.sphere_c[1], med.sphere_c[2] + gap)
+    z0 = (0,) + tuple(gap + z for z in med.layer_z0) if med.layer_z0 else ()
+    return Medium(med.nx, med.ny, med.nz + gap, med.h_mm, [free] + list(med.materials), m, med.geom, med.bc,
+                  sc, med.sphere_r, z0, med.scatter_order)
+
+
+def shifted_z(item, gap: int):
+    """A source or detector of the original medium, on the medium extended by
+    extend_top(med, gap)."""
+    import copy
+    out = copy.copy(item)
+    out.vox = np.asarray(item.vox) + np.array([0, 0, gap])
+    return out
+
+
 def point_source(x, y, z, d=(0, 0, 1), kind="impulse", fwhm_fs=0.0, rhs=0, w=1.0) -> Source:
     return Source(kind, np.array([[x, y, z]]), np.array([d]), np.array([w], dtype=np.float64),
                   fwhm_fs, rhs)
