@@ -50,7 +50,11 @@ class _Medium(C.Structure):
         ("geom", C.c_int32), ("bc", C.c_int32),
         ("sphere_c", C.c_double * 3), ("sphere_r", C.c_double),
         ("scatter_order", C.c_int32),
+        ("directions", C.c_int32), ("c_dt", C.c_double),
     ]
+
+
+DIRECTIONS = {"lattice26": 0, "lebedev86": 1}
 
 
 def _load():
@@ -81,6 +85,20 @@ def _load():
                                i64, P, P, P, i32, P,
                                i64, P, P, P, i32,
                                P, P, P, P, P, P]
+        lib.or_n_dir.restype = C.c_int
+        lib.or_n_dir.argtypes = [P]
+        lib.or_lebedev86.argtypes = [P, P]
+        lib.or_leb_open.restype = P
+        lib.or_leb_open.argtypes = [C.POINTER(_Medium)]
+        lib.or_leb_close.argtypes = [P]
+        for name in ("or_leb_n_rows", "or_leb_n_escape"):
+            getattr(lib, name).restype = i64
+            getattr(lib, name).argtypes = [P]
+        lib.or_leb_row.restype = i64
+        lib.or_leb_row.argtypes = [P, i64, P, P, i64]
+        lib.or_leb_stencil.restype = i64
+        lib.or_leb_stencil.argtypes = [P, C.c_int, C.c_int, P, P, i64]
+        lib.or_leb_block.argtypes = [P, C.c_int, P]
         lib.or_collision_block.argtypes = [dbl, dbl, dbl, dbl, P]
         lib.or_collision_block_k.argtypes = [dbl, dbl, dbl, dbl, C.c_int, P]
         lib.or_fresnel.argtypes = [C.c_int, dbl, dbl, P, P, P, P, P, P, P]
@@ -126,6 +144,15 @@ def fresnel(m: int, n1: float, n2: float, normal) -> tuple:
     return R.value, T.value, list(mr[:nr.value]), list(mt[:nt.value])
 
 
+def lebedev86():
+    """(S [86, 3], w [86]): the directions (ascending z, y, x) and normalised
+    weights of Lebedev's 86-point rule."""
+    S = np.zeros((86, 3))
+    w = np.zeros(86)
+    _load().or_lebedev86(_ptr(S), _ptr(w))
+    return S, w
+
+
 def dt_seconds(h_mm: float, n_ref: float) -> float:
     return _load().or_dt_seconds(h_mm, n_ref)
 
@@ -156,27 +183,78 @@ def dir_index(dx: int, dy: int, dz: int) -> int:
 
 # ---- assembled matrix -------------------------------------------------------
 
+def _medium_struct(medium):
+    mat = np.ascontiguousarray(
+        [[m.mu_s, m.mu_a, m.g, m.n] for m in medium.materials], dtype=np.float64).reshape(-1)
+    vmap = np.ascontiguousarray(medium.mat_of_voxel, dtype=np.uint8).reshape(-1)
+    assert vmap.size == medium.nx * medium.ny * medium.nz
+    st = _Medium()
+    st.nx, st.ny, st.nz = medium.nx, medium.ny, medium.nz
+    st.n_mat = len(medium.materials)
+    st.h_mm = medium.h_mm
+    st.mat = mat.ctypes.data_as(C.POINTER(C.c_double))
+    st.mat_of_voxel = vmap.ctypes.data_as(C.POINTER(C.c_uint8))
+    st.geom = GEOM[medium.geom]
+    st.bc = BC[medium.bc]
+    c = medium.sphere_c if medium.sphere_c is not None else (0.0, 0.0, 0.0)
+    st.sphere_c = (C.c_double * 3)(*c)
+    st.sphere_r = medium.sphere_r or 0.0
+    st.scatter_order = getattr(medium, "scatter_order", 1)
+    st.directions = DIRECTIONS[getattr(medium, "directions", "lattice26")]
+    st.c_dt = getattr(medium, "c_dt", 1.0)
+    return st, (mat, vmap)
+
+
+class LebedevRows:
+    """Single rows of a Lebedev medium's [A; L] without assembling it (the
+    same products as the assembly; for sampled checks of large media)."""
+
+    def __init__(self, medium):
+        self._st, self._keep = _medium_struct(medium)
+        self._h = _load().or_leb_open(C.byref(self._st))
+        if not self._h:
+            raise MemoryError("oracle model failed")
+        self.n_states = 86 * medium.nx * medium.ny * medium.nz
+        self.n_rows = _load().or_leb_n_rows(self._h)
+        self.n_escape = _load().or_leb_n_escape(self._h)
+
+    def row(self, r: int):
+        cap = 4096
+        col = np.zeros(cap, dtype=np.int32)
+        val = np.zeros(cap)
+        k = _load().or_leb_row(self._h, int(r), _ptr(col), _ptr(val), cap)
+        assert k <= cap
+        return col[:k].copy(), val[:k].copy()
+
+    def stencil(self, m: int, n: int):
+        off = np.zeros((4096, 3), dtype=np.int32)
+        w = np.zeros(4096)
+        k = _load().or_leb_stencil(self._h, m, n, _ptr(off), _ptr(w), 4096)
+        return off[:k].copy(), w[:k].copy()
+
+    def block(self, q: int = 0) -> np.ndarray:
+        C_ = np.zeros(86 * 86)
+        _load().or_leb_block(self._h, q, _ptr(C_))
+        return C_.reshape(86, 86)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _load().or_leb_close(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Matrix:
     """Oracle assembly of [A; L] for one medium (FP64, int64 row pointers)."""
 
     def __init__(self, medium):
         lib = _load()
-        self._mat = np.ascontiguousarray(
-            [[m.mu_s, m.mu_a, m.g, m.n] for m in medium.materials], dtype=np.float64).reshape(-1)
-        self._map = np.ascontiguousarray(medium.mat_of_voxel, dtype=np.uint8).reshape(-1)
-        assert self._map.size == medium.nx * medium.ny * medium.nz
-        st = _Medium()
-        st.nx, st.ny, st.nz = medium.nx, medium.ny, medium.nz
-        st.n_mat = len(medium.materials)
-        st.h_mm = medium.h_mm
-        st.mat = self._mat.ctypes.data_as(C.POINTER(C.c_double))
-        st.mat_of_voxel = self._map.ctypes.data_as(C.POINTER(C.c_uint8))
-        st.geom = GEOM[medium.geom]
-        st.bc = BC[medium.bc]
-        c = medium.sphere_c if medium.sphere_c is not None else (0.0, 0.0, 0.0)
-        st.sphere_c = (C.c_double * 3)(*c)
-        st.sphere_r = medium.sphere_r or 0.0
-        st.scatter_order = getattr(medium, "scatter_order", 1)
+        st, (self._mat, self._map) = _medium_struct(medium)
         self._st = st
         self.medium = medium
         h = lib.or_build(C.byref(st))
@@ -188,6 +266,7 @@ class Matrix:
         self.n_escape = lib.or_n_escape(h)
         self.n_rows = lib.or_n_rows(h)
         self.nnz = lib.or_nnz(h)
+        self.n_dir = lib.or_n_dir(h)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -314,10 +393,18 @@ def window(det, det_exp, taps, tap0=0, t_done=None):
 # ---- workload helpers (oracle side of the row mapping) ----------------------
 
 def state_of(medium, vox, dirs) -> np.ndarray:
-    """State index 26 v + d of voxels (x,y,z) and lattice vectors (dx,dy,dz)."""
+    """State index of voxels (x,y,z) and directions: 26 v + d for lattice
+    vectors (dx,dy,dz); on Lebedev media 86 v + n with n the rule's direction
+    nearest the given vector (largest cosine, the lowest index on ties)."""
     vox = np.asarray(vox, dtype=np.int64).reshape(-1, 3)
-    dirs = np.asarray(dirs, dtype=np.int64).reshape(-1, 3)
     v = vox[:, 0] + medium.nx * (vox[:, 1] + medium.ny * vox[:, 2])
+    if getattr(medium, "directions", "lattice26") == "lebedev86":
+        S, _ = lebedev86()
+        dv = np.asarray(dirs, dtype=np.float64).reshape(-1, 3)
+        dv = dv / np.linalg.norm(dv, axis=1, keepdims=True)
+        d = np.argmax(dv @ S.T, axis=1)
+        return 86 * v + d
+    dirs = np.asarray(dirs, dtype=np.int64).reshape(-1, 3)
     k = 9 * (dirs[:, 2] + 1) + 3 * (dirs[:, 1] + 1) + (dirs[:, 0] + 1)
     d = np.where(k < 13, k, k - 1)
     return 26 * v + d

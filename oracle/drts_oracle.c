@@ -258,7 +258,11 @@ typedef struct {
     double sphere_c[3];          /* voxel units; voxel centres at index + 0.5 */
     double sphere_r;
     int32_t scatter_order;       /* scatterings per step the direction block resolves */
+    int32_t directions;          /* 0: the 26 lattice directions; 1: Lebedev's 86 */
+    double c_dt;                 /* Lebedev: the distance c dt light travels per step, in voxels */
 } or_medium_t;
+
+enum { OR_DIRS_LATTICE = 0, OR_DIRS_LEBEDEV86 = 1 };
 
 /* unit normal at the crossing of voxel (x,y,z) along lattice vector e,
  * oriented so that it points from the first voxel to the second */
@@ -299,6 +303,7 @@ static void or_normal(const or_medium_t *M, int x, int y, int z, const int e[3],
 
 typedef struct {
     int64_t n_vox, n_states, n_escape, n_rows, nnz;
+    int n_dir;               /* directions per voxel: 26 (lattice) or 86 (Lebedev) */
     int64_t *row_ptr;        /* [n_rows+1] */
     int32_t *col;            /* [nnz] */
     double *val;             /* [nnz] */
@@ -385,10 +390,14 @@ void or_free(or_csr_t *A)
  * and several contributions of one column to one row are adjacent; they are
  * summed in m order.  Exact zeros are not stored.
  */
+or_csr_t *or_build_lebedev(const or_medium_t *M);
+
 or_csr_t *or_build(const or_medium_t *M)
 {
+    if (M->directions == OR_DIRS_LEBEDEV86) return or_build_lebedev(M);
     or_csr_t *A = (or_csr_t *)calloc(1, sizeof(or_csr_t));
     if (!A) return NULL;
+    A->n_dir = NDIR;
     int64_t V = (int64_t)M->nx * M->ny * M->nz;
     A->n_vox = V;
     A->n_states = NDIR * V;
@@ -517,12 +526,13 @@ int64_t or_n_states(const or_csr_t *A) { return A->n_states; }
 int64_t or_n_escape(const or_csr_t *A) { return A->n_escape; }
 int64_t or_n_rows(const or_csr_t *A) { return A->n_rows; }
 int64_t or_nnz(const or_csr_t *A) { return A->nnz; }
+int or_n_dir(const or_csr_t *A) { return A->n_dir; }
 const int64_t *or_row_ptr(const or_csr_t *A) { return A->row_ptr; }
 const int32_t *or_col(const or_csr_t *A) { return A->col; }
 const double *or_val(const or_csr_t *A) { return A->val; }
 const double *or_absorb_of_voxel(const or_csr_t *A) { return A->absorb_of_voxel; }
 
-/* row index of state s = 26 v + m (escape = 0) or of its escape row (escape = 1);
+/* row index of state s = n_dir v + m (escape = 0) or of its escape row (escape = 1);
  * -1 when the state does not leave the grid */
 int64_t or_row_of(const or_csr_t *A, int64_t s, int escape)
 {
@@ -646,8 +656,8 @@ int or_run(const or_csr_t *A, const float *vals32, int64_t n_steps,
         double absorbed = 0.0;
         for (int64_t v = 0; v < A->n_vox; ++v) {
             double sv = 0.0;
-            for (int n = 0; n < NDIR; ++n)
-                sv += x[NDIR * v + n];
+            for (int n = 0; n < A->n_dir; ++n)
+                sv += x[(int64_t)A->n_dir * v + n];
             absorbed += A->absorb_of_voxel[v] * sv;
         }
         tot[3 * t + 2] = absorbed;
@@ -732,3 +742,521 @@ double or_gaussian_step(double fwhm_s, double dt_s, int64_t t)
 /* the splitmix64 finaliser, exposed so that it can be checked against its
  * published output sequence */
 uint64_t or_splitmix64_value(uint64_t x) { return or_splitmix64(x); }
+
+/* ==== Lebedev-86 directions with multi-voxel weights (Sec. 3, Eq. (18)-(21)) ==== */
+
+#define NLEB 86
+
+/*
+ * Lebedev's 86-point quadrature rule on the unit sphere (exact for spherical
+ * polynomials of degree 15), built from its published generators:
+ *   a1: the 6 points (+-1, 0, 0) and permutations
+ *   a3: the 8 points (+-r, +-r, +-r), r = sqrt(1/3)
+ *   b_k: the 24 points (+-l, +-l, +-m) and permutations, m = sqrt(1 - 2 l^2),
+ *        for two values of l
+ *   c_1: the 24 points (+-p, +-q, 0) and permutations, q = sqrt(1 - p^2)
+ * Weights are normalised to sum to one.  The points are ordered by ascending
+ * z, then y, then x (the direction index of a state).
+ */
+static const double OR_LEB_A1 = 0.1154401154401154e-1;
+static const double OR_LEB_A3 = 0.1194390908585628e-1;
+static const double OR_LEB_B_L[2] = {0.3696028464541502, 0.6943540066026664};
+static const double OR_LEB_B_W[2] = {0.1111055571060340e-1, 0.1187650129453714e-1};
+static const double OR_LEB_C_P = 0.3742430390903412;
+static const double OR_LEB_C_W = 0.1181230374690448e-1;
+
+static int or_leb_add(double S[NLEB][3], double w[NLEB], int k, double x, double y, double z, double wt)
+{
+    S[k][0] = x;
+    S[k][1] = y;
+    S[k][2] = z;
+    w[k] = wt;
+    return k + 1;
+}
+
+/* all sign combinations of (a, b, c), skipping signs of zero components */
+static int or_leb_signs(double S[NLEB][3], double w[NLEB], int k, double a, double b, double c, double wt)
+{
+    for (int sa = -1; sa <= 1; sa += 2)
+        for (int sb = -1; sb <= 1; sb += 2)
+            for (int sc = -1; sc <= 1; sc += 2) {
+                if ((a == 0.0 && sa < 0) || (b == 0.0 && sb < 0) || (c == 0.0 && sc < 0)) continue;
+                k = or_leb_add(S, w, k, sa * a, sb * b, sc * c, wt);
+            }
+    return k;
+}
+
+static int or_leb_before(const double *a, const double *b)
+{
+    if (a[2] != b[2]) return a[2] < b[2];
+    if (a[1] != b[1]) return a[1] < b[1];
+    return a[0] < b[0];
+}
+
+void or_lebedev86(double *S_out /* [86][3] */, double *w_out /* [86] */)
+{
+    double S[NLEB][3], w[NLEB];
+    int k = 0;
+    k = or_leb_signs(S, w, k, 1.0, 0.0, 0.0, OR_LEB_A1);
+    k = or_leb_signs(S, w, k, 0.0, 1.0, 0.0, OR_LEB_A1);
+    k = or_leb_signs(S, w, k, 0.0, 0.0, 1.0, OR_LEB_A1);
+    double r = sqrt(1.0 / 3.0);
+    k = or_leb_signs(S, w, k, r, r, r, OR_LEB_A3);
+    for (int i = 0; i < 2; ++i) {
+        double l = OR_LEB_B_L[i], m = sqrt(1.0 - 2.0 * l * l);
+        k = or_leb_signs(S, w, k, l, l, m, OR_LEB_B_W[i]);
+        k = or_leb_signs(S, w, k, l, m, l, OR_LEB_B_W[i]);
+        k = or_leb_signs(S, w, k, m, l, l, OR_LEB_B_W[i]);
+    }
+    double p = OR_LEB_C_P, q = sqrt(1.0 - p * p);
+    k = or_leb_signs(S, w, k, p, q, 0.0, OR_LEB_C_W);
+    k = or_leb_signs(S, w, k, q, p, 0.0, OR_LEB_C_W);
+    k = or_leb_signs(S, w, k, p, 0.0, q, OR_LEB_C_W);
+    k = or_leb_signs(S, w, k, q, 0.0, p, OR_LEB_C_W);
+    k = or_leb_signs(S, w, k, 0.0, p, q, OR_LEB_C_W);
+    k = or_leb_signs(S, w, k, 0.0, q, p, OR_LEB_C_W);
+    /* insertion sort by (z, y, x) */
+    for (int i = 1; i < NLEB; ++i) {
+        double t[3] = {S[i][0], S[i][1], S[i][2]}, tw = w[i];
+        int j = i - 1;
+        while (j >= 0 && or_leb_before(t, S[j])) {
+            S[j + 1][0] = S[j][0];
+            S[j + 1][1] = S[j][1];
+            S[j + 1][2] = S[j][2];
+            w[j + 1] = w[j];
+            --j;
+        }
+        S[j + 1][0] = t[0];
+        S[j + 1][1] = t[1];
+        S[j + 1][2] = t[2];
+        w[j + 1] = tw;
+    }
+    double sum = 0.0;
+    for (int i = 0; i < NLEB; ++i)
+        sum += w[i];
+    for (int i = 0; i < NLEB; ++i) {
+        S_out[3 * i + 0] = S[i][0];
+        S_out[3 * i + 1] = S[i][1];
+        S_out[3 * i + 2] = S[i][2];
+        w_out[i] = w[i] / sum;
+    }
+}
+
+/*
+ * Direction block of one material over the 86 directions, for a step in
+ * which light travels L = c dt (mm):
+ *   P0 = exp(-mu_s L), Ps = 1 - P0, alpha = exp(-mu_a L)          (Eq. (9)-(10))
+ *   G[m][n] = w_m p(S_m . S_n) / sum_k w_k p(S_k . S_n)           (kernel g of Eq. (19),
+ *             the quadrature weights w of the rule measuring the solid angle of each direction)
+ *   C[m][n] = alpha (Ps G[m][n]), C[n][n] = alpha (P0 + Ps G[n][n])   (Eq. (21))
+ */
+void or_lebedev_block(double mu_s, double mu_a, double g, double L, const double *S, const double *wq,
+                      double *C /* [86*86] */)
+{
+    double P0 = exp(-mu_s * L);
+    double Ps = 1.0 - P0;
+    double alpha = exp(-mu_a * L);
+    for (int n = 0; n < NLEB; ++n) {
+        double p[NLEB];
+        double Z = 0.0;
+        for (int m = 0; m < NLEB; ++m) {
+            double cs = S[3 * m] * S[3 * n] + S[3 * m + 1] * S[3 * n + 1] + S[3 * m + 2] * S[3 * n + 2];
+            p[m] = wq[m] * or_hg(g, cs);
+        }
+        for (int k = 0; k < NLEB; ++k)
+            Z += p[k];
+        for (int m = 0; m < NLEB; ++m) {
+            double G = p[m] / Z;
+            C[m * NLEB + n] = (m != n) ? alpha * (Ps * G) : alpha * (P0 + Ps * G);
+        }
+    }
+}
+
+/* distance from point P to the segment from a to b (a point when a == b) */
+static double or_seg_dist(const double P[3], const double a[3], const double b[3])
+{
+    double ab[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    double ap[3] = {P[0] - a[0], P[1] - a[1], P[2] - a[2]};
+    double L2 = ab[0] * ab[0] + ab[1] * ab[1] + ab[2] * ab[2];
+    double t = 0.0;
+    if (L2 > 0.0) {
+        t = (ap[0] * ab[0] + ap[1] * ab[1] + ap[2] * ab[2]) / L2;
+        if (t < 0.0) t = 0.0;
+        if (t > 1.0) t = 1.0;
+    }
+    double q[3] = {a[0] + t * ab[0], a[1] + t * ab[1], a[2] + t * ab[2]};
+    double d[3] = {P[0] - q[0], P[1] - q[1], P[2] - q[2]};
+    return sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+}
+
+/*
+ * Multi-voxel weights of Eq. (18)-(19).  Voxel centres are the lattice points
+ * (spacing h) and the partition spheres have radius dr = h/2, so 2 dr is one
+ * voxel.  A population of voxel X_i in direction S_n that leaves in
+ * direction S_m arrives, after the step, spread over the voxels X_j whose
+ * centres lie within 2 dr of the segment AB, A = X_i + c dt S_m,
+ * B = X_i + c dt S_n (for m = n the segment is the point B: the unscattered
+ * population of Eq. (18) together with the zero-angle scatter of Eq. (21)),
+ * with weights (2 dr - d(X_j, AB)) / sum_k (2 dr - d(X_k, AB)).  In voxel
+ * units: offsets delta = X_j - X_i, distance below 1, weight (1 - d) / sum.
+ * The weights depend only on (m, n) and the offset; offsets are scanned in
+ * ascending (dz, dy, dx) over the box [-R, R]^3, R = ceil(c + 1), and the sum
+ * is taken in that order.
+ */
+typedef struct {
+    int R;
+    int64_t ptr[NLEB * NLEB + 1]; /* pair (m, n) -> entries ptr[m*86+n] .. ptr[m*86+n+1]-1 */
+    int8_t *off;                  /* [entries][3] */
+    double *w;                    /* [entries] */
+} or_stencil_t;
+
+static or_stencil_t *or_stencil(const double *S, double c)
+{
+    or_stencil_t *T = (or_stencil_t *)calloc(1, sizeof(or_stencil_t));
+    if (!T) return NULL;
+    T->R = (int)ceil(c + 1.0);
+    int R = T->R, B = 2 * R + 1;
+    int64_t cap = (int64_t)NLEB * NLEB * B * B * B;
+    int8_t *off = (int8_t *)malloc((size_t)cap * 3);
+    double *w = (double *)malloc(sizeof(double) * (size_t)cap);
+    if (!off || !w) {
+        free(off);
+        free(w);
+        free(T);
+        return NULL;
+    }
+    int64_t k = 0;
+    double raw[1024];
+    for (int m = 0; m < NLEB; ++m)
+        for (int n = 0; n < NLEB; ++n) {
+            double a[3] = {c * S[3 * m], c * S[3 * m + 1], c * S[3 * m + 2]};
+            double b[3] = {c * S[3 * n], c * S[3 * n + 1], c * S[3 * n + 2]};
+            T->ptr[m * NLEB + n] = k;
+            int cnt = 0;
+            double sum = 0.0;
+            for (int dz = -R; dz <= R; ++dz)
+                for (int dy = -R; dy <= R; ++dy)
+                    for (int dx = -R; dx <= R; ++dx) {
+                        double P[3] = {(double)dx, (double)dy, (double)dz};
+                        double d = or_seg_dist(P, a, b);
+                        if (d < 1.0) {
+                            off[3 * (k + cnt) + 0] = (int8_t)dx;
+                            off[3 * (k + cnt) + 1] = (int8_t)dy;
+                            off[3 * (k + cnt) + 2] = (int8_t)dz;
+                            raw[cnt] = 1.0 - d;
+                            sum += raw[cnt];
+                            ++cnt;
+                        }
+                    }
+            for (int i = 0; i < cnt; ++i)
+                w[k + i] = raw[i] / sum;
+            k += cnt;
+        }
+    T->ptr[NLEB * NLEB] = k;
+    T->off = off;
+    T->w = w;
+    return T;
+}
+
+static void or_stencil_free(or_stencil_t *T)
+{
+    if (!T) return;
+    free(T->off);
+    free(T->w);
+    free(T);
+}
+
+/* the host tables of a Lebedev medium, shared by the push assembly and the
+ * single-row function */
+typedef struct {
+    int nx, ny, nz;
+    int64_t V, D;
+    double S[NLEB * 3], wq[NLEB];
+    double *Cq;             /* [n_mat][86][86] */
+    const uint8_t *mat;
+    or_stencil_t *st;
+    int8_t *m_out;          /* [86][(2R+1)^3]: 1 when some n puts direction m at that offset */
+    int32_t *escape_of_state; /* [D], escape row index - D, or -1 */
+    int64_t n_escape;
+    double *absorb_of_voxel;
+} or_leb_t;
+
+static int or_leb_inside(const or_leb_t *L, int x, int y, int z)
+{
+    return x >= 0 && x < L->nx && y >= 0 && y < L->ny && z >= 0 && z < L->nz;
+}
+
+static void or_leb_free(or_leb_t *L)
+{
+    if (!L) return;
+    free(L->Cq);
+    or_stencil_free(L->st);
+    free(L->m_out);
+    free(L->escape_of_state);
+    free(L->absorb_of_voxel);
+    free(L);
+}
+
+static or_leb_t *or_leb_model(const or_medium_t *M)
+{
+    or_leb_t *L = (or_leb_t *)calloc(1, sizeof(or_leb_t));
+    if (!L) return NULL;
+    L->nx = M->nx;
+    L->ny = M->ny;
+    L->nz = M->nz;
+    L->V = (int64_t)M->nx * M->ny * M->nz;
+    L->D = NLEB * L->V;
+    L->mat = M->mat_of_voxel;
+    or_lebedev86(L->S, L->wq);
+    double c = M->c_dt > 0.0 ? M->c_dt : 1.0;
+    double Lmm = c * M->h_mm;
+    L->Cq = (double *)malloc(sizeof(double) * NLEB * NLEB * M->n_mat);
+    L->st = or_stencil(L->S, c);
+    int R = L->st ? L->st->R : 0, B = 2 * R + 1;
+    L->m_out = (int8_t *)calloc((size_t)NLEB * B * B * B, 1);
+    L->escape_of_state = (int32_t *)malloc(sizeof(int32_t) * (size_t)L->D);
+    L->absorb_of_voxel = (double *)malloc(sizeof(double) * (size_t)L->V);
+    if (!L->Cq || !L->st || !L->m_out || !L->escape_of_state || !L->absorb_of_voxel) {
+        or_leb_free(L);
+        return NULL;
+    }
+    for (int q = 0; q < M->n_mat; ++q)
+        or_lebedev_block(M->mat[4 * q], M->mat[4 * q + 1], M->mat[4 * q + 2], Lmm, L->S, L->wq,
+                         L->Cq + (int64_t)q * NLEB * NLEB);
+    /* offsets any column can send direction m to */
+    for (int m = 0; m < NLEB; ++m)
+        for (int n = 0; n < NLEB; ++n)
+            for (int64_t e = L->st->ptr[m * NLEB + n]; e < L->st->ptr[m * NLEB + n + 1]; ++e) {
+                const int8_t *o = L->st->off + 3 * e;
+                L->m_out[(int64_t)m * B * B * B + ((o[2] + R) * B + (o[1] + R)) * B + (o[0] + R)] = 1;
+            }
+    /* escape rows: (v, m) such that some offset of direction m leaves the grid */
+    int64_t ne = 0;
+    for (int64_t v = 0; v < L->V; ++v) {
+        int x = (int)(v % L->nx), y = (int)((v / L->nx) % L->ny), z = (int)(v / ((int64_t)L->nx * L->ny));
+        L->absorb_of_voxel[v] = -expm1(-M->mat[4 * M->mat_of_voxel[v] + 1] * Lmm);
+        for (int m = 0; m < NLEB; ++m) {
+            int out = 0;
+            for (int i = 0; i < B * B * B && !out; ++i) {
+                if (!L->m_out[(int64_t)m * B * B * B + i]) continue;
+                int dx = i % B - R, dy = (i / B) % B - R, dz = i / (B * B) - R;
+                out = !or_leb_inside(L, x + dx, y + dy, z + dz);
+            }
+            L->escape_of_state[NLEB * v + m] = out ? (int32_t)(ne++) : -1;
+        }
+    }
+    L->n_escape = ne;
+    return L;
+}
+
+/*
+ * Push assembly of [A; L] for a Lebedev medium.  For every column (v, n) in
+ * ascending order, every arrival direction m in ascending order and every
+ * offset of the pair's stencil in its scan order, the value
+ * w_{nm}(offset) C_q(v)[m][n] goes to row (v + offset, m) when that voxel is
+ * inside the grid; the weights of the offsets outside the grid are summed (in
+ * scan order) and their total times C_q(v)[m][n] goes to the escape row of
+ * (v, m).  A column reaches each row at most once, so every entry is one
+ * product.  Exact zeros are not stored.
+ */
+or_csr_t *or_build_lebedev(const or_medium_t *M)
+{
+    or_leb_t *L = or_leb_model(M);
+    if (!L) return NULL;
+    or_csr_t *A = (or_csr_t *)calloc(1, sizeof(or_csr_t));
+    int64_t *cnt = NULL, *fill = NULL;
+    if (!A) goto fail;
+    A->n_dir = NLEB;
+    A->n_vox = L->V;
+    A->n_states = L->D;
+    A->n_escape = L->n_escape;
+    A->n_rows = L->D + L->n_escape;
+    A->escape_of_state = L->escape_of_state;
+    A->absorb_of_voxel = L->absorb_of_voxel;
+    L->escape_of_state = NULL;
+    L->absorb_of_voxel = NULL;
+    cnt = (int64_t *)calloc((size_t)A->n_rows + 1, sizeof(int64_t));
+    if (!cnt) goto fail;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int64_t v = 0; v < L->V; ++v) {
+            int x = (int)(v % L->nx), y = (int)((v / L->nx) % L->ny), z = (int)(v / ((int64_t)L->nx * L->ny));
+            const double *C = L->Cq + (int64_t)L->mat[v] * NLEB * NLEB;
+            for (int n = 0; n < NLEB; ++n) {
+                int32_t col = (int32_t)(NLEB * v + n);
+                for (int m = 0; m < NLEB; ++m) {
+                    double cmn = C[m * NLEB + n];
+                    if (cmn == 0.0) continue;
+                    double esc = 0.0;
+                    int any_out = 0;
+                    for (int64_t e = L->st->ptr[m * NLEB + n]; e < L->st->ptr[m * NLEB + n + 1]; ++e) {
+                        const int8_t *o = L->st->off + 3 * e;
+                        int ux = x + o[0], uy = y + o[1], uz = z + o[2];
+                        if (or_leb_inside(L, ux, uy, uz)) {
+                            int64_t r = NLEB * ((int64_t)ux + (int64_t)L->nx * ((int64_t)uy + (int64_t)L->ny * uz)) + m;
+                            double a = L->st->w[e] * cmn;
+                            if (a == 0.0) continue;
+                            if (pass == 0) {
+                                cnt[r]++;
+                            } else {
+                                A->col[fill[r]] = col;
+                                A->val[fill[r]] = a;
+                                fill[r]++;
+                            }
+                        } else {
+                            esc += L->st->w[e];
+                            any_out = 1;
+                        }
+                    }
+                    if (any_out) {
+                        int64_t r = A->n_states + A->escape_of_state[NLEB * v + m];
+                        double a = esc * cmn;
+                        if (a == 0.0) continue;
+                        if (pass == 0) {
+                            cnt[r]++;
+                        } else {
+                            A->col[fill[r]] = col;
+                            A->val[fill[r]] = a;
+                            fill[r]++;
+                        }
+                    }
+                }
+            }
+        }
+        if (pass == 0) {
+            A->row_ptr = (int64_t *)malloc(sizeof(int64_t) * ((size_t)A->n_rows + 1));
+            fill = (int64_t *)malloc(sizeof(int64_t) * ((size_t)A->n_rows + 1));
+            if (!A->row_ptr || !fill) goto fail;
+            A->row_ptr[0] = 0;
+            for (int64_t r = 0; r < A->n_rows; ++r)
+                A->row_ptr[r + 1] = A->row_ptr[r] + cnt[r];
+            A->nnz = A->row_ptr[A->n_rows];
+            for (int64_t r = 0; r < A->n_rows; ++r)
+                fill[r] = A->row_ptr[r];
+            A->col = (int32_t *)malloc(sizeof(int32_t) * (size_t)(A->nnz > 0 ? A->nnz : 1));
+            A->val = (double *)malloc(sizeof(double) * (size_t)(A->nnz > 0 ? A->nnz : 1));
+            if (!A->col || !A->val) goto fail;
+        }
+    }
+    free(cnt);
+    free(fill);
+    or_leb_free(L);
+    return A;
+fail:
+    free(cnt);
+    free(fill);
+    or_leb_free(L);
+    or_free(A);
+    return NULL;
+}
+
+/* ---- single rows of a Lebedev medium, without assembling the matrix --------- */
+
+void *or_leb_open(const or_medium_t *M) { return or_leb_model(M); }
+void or_leb_close(void *h) { or_leb_free((or_leb_t *)h); }
+int64_t or_leb_n_rows(const void *h) { return ((const or_leb_t *)h)->D + ((const or_leb_t *)h)->n_escape; }
+int64_t or_leb_n_escape(const void *h) { return ((const or_leb_t *)h)->n_escape; }
+
+/*
+ * Entries of one row of [A; L] pulled from its sources (the same products as
+ * the push assembly, so the same values): a state row (j, m) takes, from
+ * every voxel i = j - offset and direction n whose stencil (m, n) holds the
+ * offset, w C_q(i)[m][n]; an escape row (v, m) takes, per direction n, the
+ * scan-order sum of the weights of the offsets leaving the grid times
+ * C_q(v)[m][n].  Writes at most cap entries in ascending column order and
+ * returns the row's entry count.
+ */
+int64_t or_leb_row(const void *h, int64_t row, int32_t *col, double *val, int64_t cap)
+{
+    const or_leb_t *L = (const or_leb_t *)h;
+    int64_t k = 0;
+    if (row < L->D) {
+        int m = (int)(row % NLEB);
+        int64_t j = row / NLEB;
+        int jx = (int)(j % L->nx), jy = (int)((j / L->nx) % L->ny), jz = (int)(j / ((int64_t)L->nx * L->ny));
+        for (int n = 0; n < NLEB; ++n)
+            for (int64_t e = L->st->ptr[m * NLEB + n]; e < L->st->ptr[m * NLEB + n + 1]; ++e) {
+                const int8_t *o = L->st->off + 3 * e;
+                int ix = jx - o[0], iy = jy - o[1], iz = jz - o[2];
+                if (!or_leb_inside(L, ix, iy, iz)) continue;
+                int64_t i = (int64_t)ix + (int64_t)L->nx * ((int64_t)iy + (int64_t)L->ny * iz);
+                double cmn = L->Cq[(int64_t)L->mat[i] * NLEB * NLEB + m * NLEB + n];
+                double a = L->st->w[e] * cmn;
+                if (cmn == 0.0 || a == 0.0) continue;
+                if (k < cap) {
+                    col[k] = (int32_t)(NLEB * i + n);
+                    val[k] = a;
+                }
+                ++k;
+            }
+        /* ascending columns (insertion sort; rows hold a few hundred entries) */
+        int64_t kk = k < cap ? k : cap;
+        for (int64_t a = 1; a < kk; ++a) {
+            int32_t c0 = col[a];
+            double v0 = val[a];
+            int64_t b = a - 1;
+            while (b >= 0 && col[b] > c0) {
+                col[b + 1] = col[b];
+                val[b + 1] = val[b];
+                --b;
+            }
+            col[b + 1] = c0;
+            val[b + 1] = v0;
+        }
+        return k;
+    }
+    /* escape row: find its state */
+    int64_t ei = row - L->D;
+    int64_t s = -1;
+    for (int64_t t = 0; t < L->D; ++t)
+        if (L->escape_of_state[t] == ei) {
+            s = t;
+            break;
+        }
+    if (s < 0) return 0;
+    int m = (int)(s % NLEB);
+    int64_t v = s / NLEB;
+    int x = (int)(v % L->nx), y = (int)((v / L->nx) % L->ny), z = (int)(v / ((int64_t)L->nx * L->ny));
+    const double *C = L->Cq + (int64_t)L->mat[v] * NLEB * NLEB;
+    for (int n = 0; n < NLEB; ++n) {
+        double cmn = C[m * NLEB + n];
+        if (cmn == 0.0) continue;
+        double esc = 0.0;
+        int any_out = 0;
+        for (int64_t e = L->st->ptr[m * NLEB + n]; e < L->st->ptr[m * NLEB + n + 1]; ++e) {
+            const int8_t *o = L->st->off + 3 * e;
+            if (!or_leb_inside(L, x + o[0], y + o[1], z + o[2])) {
+                esc += L->st->w[e];
+                any_out = 1;
+            }
+        }
+        double a = esc * cmn;
+        if (!any_out || a == 0.0) continue;
+        if (k < cap) {
+            col[k] = (int32_t)(NLEB * v + n);
+            val[k] = a;
+        }
+        ++k;
+    }
+    return k;
+}
+
+/* the stencil of one pair (m, n) for the pins: count, offsets [cnt][3], weights */
+int64_t or_leb_stencil(const void *h, int m, int n, int32_t *off, double *w, int64_t cap)
+{
+    const or_leb_t *L = (const or_leb_t *)h;
+    int64_t b = L->st->ptr[m * NLEB + n], e = L->st->ptr[m * NLEB + n + 1];
+    for (int64_t i = b; i < e && i - b < cap; ++i) {
+        off[3 * (i - b) + 0] = L->st->off[3 * i + 0];
+        off[3 * (i - b) + 1] = L->st->off[3 * i + 1];
+        off[3 * (i - b) + 2] = L->st->off[3 * i + 2];
+        w[i - b] = L->st->w[i];
+    }
+    return e - b;
+}
+
+/* the direction block of material q of an open Lebedev medium */
+void or_leb_block(const void *h, int q, double *C)
+{
+    const or_leb_t *L = (const or_leb_t *)h;
+    memcpy(C, L->Cq + (int64_t)q * NLEB * NLEB, sizeof(double) * NLEB * NLEB);
+}

@@ -3,10 +3,10 @@
 Each case copies the oracle package (oracle/drts_oracle.c and
 oracle/__init__.py), plants one mistake of the kind the pins are meant to
 catch (a dropped term, a wrong sign, a transposed index, an off-by-one range,
-a wrong coefficient, a wrong operand), and runs tests/test_oracle_pins.py
-against the copy in a subprocess (the copy builds its own library with the
-oracle's compiler flags): the pin suite must fail.  A control case copies the
-package unchanged and must pass.  Only the copy is changed; the oracle itself
+a wrong coefficient, a wrong operand), and runs tests/test_oracle_pins.py and
+tests/test_oracle_pins_lebedev.py against the copy in a subprocess (the copy
+builds its own library with the oracle's compiler flags): the pin suite must
+fail.  A control case copies the package unchanged and must pass.  Only the copy is changed; the oracle itself
 is never modified."""
 import os
 import shutil
@@ -63,6 +63,18 @@ MUTANTS = [
     # delay of the response with the wrong sign
     ("window_response_reversed", PY_SRC, "s = t - tap0 - j", "s = t - tap0 + j"),
     ("window_delay_sign", PY_SRC, "s = t - tap0 - j", "s = t + tap0 - j"),
+    # Lebedev-86 with the weights of Eq. (18)-(19): distance to the line
+    # instead of the segment, the weight ramp inverted, the kernel without the
+    # rule's solid-angle weights, offsets applied with the wrong sign, escape
+    # weights counted as one, two digits of a generator value of the rule swapped
+    ("leb_segment_as_line", C_SRC, "if (t > 1.0) t = 1.0;", ""),
+    ("leb_weight_ramp_inverted", C_SRC, "raw[cnt] = 1.0 - d;", "raw[cnt] = d;"),
+    ("leb_kernel_without_solid_angle", C_SRC, "p[m] = wq[m] * or_hg(g, cs);", "p[m] = or_hg(g, cs);"),
+    ("leb_offset_sign", C_SRC, "int ux = x + o[0], uy = y + o[1], uz = z + o[2];",
+     "int ux = x - o[0], uy = y - o[1], uz = z - o[2];"),
+    ("leb_escape_weight", C_SRC, "esc += L->st->w[e];\n                            any_out = 1;",
+     "esc += 1.0;\n                            any_out = 1;"),
+    ("leb_generator_value", C_SRC, "0.6943540066026664", "0.6943450066026664"),
     # dither key with row and column swapped
     ("dither_key_swapped", C_SRC, "uint64_t key = ((uint64_t)r << 32) ^ (uint64_t)(uint32_t)A->col[j];",
      "uint64_t key = ((uint64_t)(uint32_t)A->col[j] << 32) ^ (uint64_t)r;"),
@@ -84,6 +96,7 @@ def _copy(tmp_path, fname=None, old=None, new=None):
 def _pins(pkg):
     env = dict(os.environ, DRTS_ORACLE_COPY=pkg)
     return subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                           os.path.join(ROOT, "tests", "test_oracle_pins_lebedev.py"),
                            "-x", "-q", "-p", "no:cacheprovider"], cwd=ROOT, env=env,
                           stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, timeout=600)
 

@@ -66,6 +66,8 @@ class Medium:
     sphere_r: Optional[float] = None
     layer_z0: Tuple[int, ...] = ()
     scatter_order: int = 1              # scatterings per step the direction block resolves
+    directions: str = "lattice26"       # "lattice26" | "lebedev86" (Sec. 3, Eq. (18)-(19))
+    c_dt: float = 1.0                   # lebedev86: light path per step, in voxels
 
     @property
     def n_vox(self) -> int:
