@@ -130,7 +130,38 @@ typedef struct {
                               scattering kernel (a sequence of single
                               scatterings), the remaining probability taking
                               K scatterings */
+    int32_t directions;    /* DRTS_DIRS_*: the angular partition (Sec. 3) */
+    double c_dt;           /* DRTS_DIRS_LEBEDEV86: the distance light travels
+                              per step, in voxels (0 = 1); dt = c_dt h n_ref / c0.
+                              Must be 0 or 1 with the lattice directions */
 } drts_medium_t;
+
+/* Angular partitions (Sec. 3 allows any):
+ *   DRTS_DIRS_LATTICE26  the 26 lattice directions above: every population
+ *                        moves to the neighbour voxel e_m in one step;
+ *   DRTS_DIRS_LEBEDEV86  Lebedev's 86-point rule (degree 15), the paper's own
+ *                        choice, with the multi-voxel weights of Eq. (18)-(19):
+ *                        partition spheres of radius dr = h/2 on the voxel
+ *                        centres; a population of X_i in direction S_n leaving
+ *                        in direction S_m (Eq. 21) arrives spread over the
+ *                        voxels whose centres lie within 2 dr of the segment
+ *                        from X_i + c dt S_m to X_i + c dt S_n (a point when
+ *                        m = n), weighted by the normalised ramp 2 dr - d; the
+ *                        scattering kernel weighs each direction by the rule's
+ *                        solid angle.  States index 86 v + n with the
+ *                        directions in ascending (z, y, x) order
+ *                        (drts_direction_set).  Vacuum faces, one refractive
+ *                        index, scatter_order 0 or 1, 0 < c_dt <= 8 voxels;
+ *                        the CSR step kernels only (not the matrix-free ones,
+ *                        not the serving loop).  Rows hold several hundred
+ *                        entries. */
+#define DRTS_DIRS_LATTICE26 0
+#define DRTS_DIRS_LEBEDEV86 1
+
+/* Unit vectors [n][3] and solid-angle weights [n] (summing to one; 1/26 each
+ * for the lattice) of an angular partition; either output may be NULL.
+ * Returns the number of directions, or DRTS_E_INVALID. */
+int drts_direction_set(int32_t directions, double *unit, double *weight);
 
 /* ---- device hooks ---------------------------------------------------------- */
 typedef struct {

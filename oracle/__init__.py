@@ -413,7 +413,8 @@ def state_of(medium, vox, dirs) -> np.ndarray:
 def source_arrays(A: Matrix, workload, rhs=None):
     """(rows, ids, weights, amplitudes) of the workload's sources feeding one rhs."""
     med = workload.medium
-    dt = dt_seconds(med.h_mm, workload.n_ref)
+    # the step: light crosses c_dt voxels (one on the lattice)
+    dt = dt_seconds(med.h_mm * getattr(med, "c_dt", 1.0), workload.n_ref)
     srcs = [s for s in workload.sources if rhs is None or s.rhs == rhs]
     rows, ids, w = [], [], []
     for j, s in enumerate(srcs):

@@ -608,6 +608,7 @@ int prepare(drts_solver *S)
     I.t_end = S->t_end.as<int64_t>();
     I.rescale = o.rescale;
     I.n_mat = (int32_t)A.model.mats.size();
+    I.vox_mul = vox_mul_of(A.model.n_dir);
     I.max_steps = S->max_steps;
     I.partials = S->partials.as<double>();
     I.n_chunks = n_part;   // the finalize reduces both kernels' chunks
@@ -742,6 +743,10 @@ hipEvent_t next_event(drts_solver *S)
     return S->ev_pool[S->ev_used++];
 }
 
+// Matrices whose rows hold several hundred entries (the multi-voxel weights of
+// Lebedev media) step with the wave-per-row SpMV.
+bool long_rows(const Matrix &A) { return A.model.n_rows > 0 && A.nnz >= (int64_t)kLongRowMean * A.model.n_rows; }
+
 // One step's launches.  inst (NULL = the solver's own) is the device copy of
 // the step descriptor the kernels read (matrix, state, partials, series);
 // queue_override (used when inst is given) is the work counter of the
@@ -770,9 +775,10 @@ int launch_one(drts_solver *S, hipStream_t stream, const StepInst *inst = nullpt
                               A.model.value_type == DRTS_F64, structured_mode(S), S->grid,
                               S->opt.xcd_remap ? 1 : 0, S->xcd_bounds.as<int64_t>(), stream);
     } else {
+    const int variant = long_rows(A) ? kVariantLongRows : S->opt.variant;
     e = launch_step(insts, S->work_dev.as<WorkItem>(), S->n_chunks, 1, S->n_rhs,
                                A.model.value_type == DRTS_F64, A.rp64 ? 1 : 0, spmm ? 1 : 0, S->grid,
-                               (S->opt.xcd_remap ? 1 : 0) | ((S->opt.variant & 15) << 1), S->xcd_bounds.as<int64_t>(),
+                               (S->opt.xcd_remap ? 1 : 0) | ((variant & 15) << 1), S->xcd_bounds.as<int64_t>(),
                                S->opt.rows_per_tile, S->n_det, queue, stream);
     }
     if (e != hipSuccess) return set_error(DRTS_E_HIP, "step launch failed: %s", hipGetErrorString(e));
@@ -845,6 +851,8 @@ int check_options(const drts_solver *S, const drts_options_t *o)
 {
     if (o->kernel < DRTS_KERNEL_CSR || o->kernel > DRTS_KERNEL_STRUCTURED_F64SUM)
         return set_error(DRTS_E_INVALID, "unknown kernel %d", o->kernel);
+    if (o->kernel != DRTS_KERNEL_CSR && S->A->m.model.n_dir != kDirs)
+        return set_error(DRTS_E_INVALID, "the matrix-free steps take the 26 lattice directions");
     if (o->kernel != DRTS_KERNEL_CSR && S->n_rhs != 1) {
         const Model &M = S->A->m.model;
         if (o->kernel == DRTS_KERNEL_STRUCTURED && M.rounding != DRTS_ROUND_NEAREST)
@@ -939,6 +947,22 @@ int drts_build_matrix(const drts_medium_t *medium, const drts_device_t *dev, drt
     }
     *out = A;
     return DRTS_OK;
+}
+
+int drts_direction_set(int32_t directions, double *unit, double *weight)
+{
+    if (directions == DRTS_DIRS_LEBEDEV86) {
+        lebedev86(unit, weight);
+        return 86;
+    }
+    if (directions != DRTS_DIRS_LATTICE26) return set_error(DRTS_E_INVALID, "unknown directions %d", directions);
+    for (int d = 0; d < kDirs; ++d) {
+        const int e[3] = {dir_dx(d), dir_dy(d), dir_dz(d)};
+        const double len = std::sqrt((double)(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]));
+        for (int i = 0; i < 3 && unit; ++i) unit[3 * d + i] = (double)e[i] / len;
+        if (weight) weight[d] = 1.0 / kDirs;
+    }
+    return kDirs;
 }
 
 int drts_matrix_info(const drts_matrix_t *A, int64_t *n_states, int64_t *n_escape, int64_t *nnz, int64_t *bytes,
@@ -1347,7 +1371,7 @@ int drts_state_write(drts_solver_t *S, const void *host_x, const int32_t *exp2, 
     const bool f64 = M.value_type == DRTS_F64;
     std::vector<double> mx((size_t)nr, 0.0), ab((size_t)nr, 0.0);
     for (int64_t r = 0; r < M.n_states; ++r) {
-        const double a = M.absorb[M.mat_of_voxel[(size_t)(r / kDirs)]];
+        const double a = M.absorb[M.mat_of_voxel[(size_t)(r / M.n_dir)]];
         for (int k = 0; k < nr; ++k) {
             const double v = f64 ? ((const double *)host_x)[r * nr + k] : (double)((const float *)host_x)[r * nr + k];
             mx[(size_t)k] = std::max(mx[(size_t)k], v);
@@ -1417,8 +1441,9 @@ int batch_launch(drts_batch *B, int64_t n_work, int n_inst, int rows_per_tile, h
                                     grid, stream);
     else
         e = launch_step(B->inst_dev.as<StepInst>(), B->work_dev.as<WorkItem>(), n_work, n_inst, 1, 0,
-                        S0->A->m.rp64 ? 1 : 0, 0, grid, (S0->opt.variant & 15) << 1, nullptr, rows_per_tile, 0,
-                        queue, stream);
+                        S0->A->m.rp64 ? 1 : 0, 0, grid,
+                        ((long_rows(S0->A->m) ? kVariantLongRows : S0->opt.variant) & 15) << 1, nullptr,
+                        rows_per_tile, 0, queue, stream);
     if (e != hipSuccess) return set_error(DRTS_E_HIP, "batch step launch failed: %s", hipGetErrorString(e));
     e = launch_finalize(B->inst_dev.as<StepInst>(), n_inst, 1, 0, queue, stream);
     if (e != hipSuccess) return set_error(DRTS_E_HIP, "batch finalize launch failed: %s", hipGetErrorString(e));
@@ -1483,6 +1508,9 @@ int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const
             return set_error(DRTS_E_INVALID, "solver %d: matrix-free tiles of another shape", i);
         if (mode == 0 && S->opt.rows_per_tile != rpt)
             return set_error(DRTS_E_INVALID, "solver %d: every batch member needs the same rows_per_tile", i);
+        if (mode == 0 && long_rows(S->A->m) != long_rows(B->solvers[0]->A->m))
+            return set_error(DRTS_E_INVALID, "solver %d: a batch takes either long-row (Lebedev) members or "
+                                             "lattice members", i);
         if (n_steps[i] < 0 || S->t_host + n_steps[i] > S->max_steps)
             return set_error(DRTS_E_RANGE, "solver %d: steps beyond max_steps", i);
         if (n_steps[i] == 0) continue;

@@ -148,6 +148,94 @@ __global__ void __launch_bounds__(256) assemble_rows(AsmArgs a, int64_t *counts,
     if (!FILL) counts[r] = total;
 }
 
+// ---- Lebedev-86 media (Sec. 3, Eq. (18)-(21)) -------------------------------------
+//
+// Pull formulation, one thread per row.  State row (j, m) walks direction m's
+// list of (offset, n, weight) -- descending offsets, ascending n, so that the
+// source voxels i = j - offset and the columns 86 i + n come out ascending --
+// and takes w C_q(i)[m][n] from every source voxel inside the grid.  Escape row
+// (v, m) takes, per direction n, the scan-order sum of the weights of the
+// pair's offsets that leave the grid, times C_q(v)[m][n].  Each entry is one
+// product (or one weight sum times one coefficient): the same values the push
+// assembly of the method gives.
+struct LebArgs {
+    int nx, ny, nz;
+    int rounding;
+    int64_t n_states, n_rows;
+    const uint8_t *mat;
+    const double *blocks;          // [q][86][86]
+    const int64_t *pair_ptr;       // [86*86 + 1]
+    const uint32_t *pair_key;
+    const double *pair_w;
+    const int64_t *arr_ptr;        // [86 + 1]
+    const uint32_t *arr_key;
+    const double *arr_w;
+    const int64_t *escape_state;
+};
+
+constexpr int kLebDirs = 86;
+
+template <bool FILL, typename VT, typename IT>
+__global__ void __launch_bounds__(256) assemble_leb_rows(LebArgs a, int64_t *counts, const IT *row_ptr,
+                                                          int32_t *col, VT *val)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.n_rows) return;
+    int64_t pos = FILL ? (int64_t)row_ptr[r] : 0;
+    int64_t cnt = 0;
+    if (r < a.n_states) {
+        const int m = (int)(r % kLebDirs);
+        const int64_t j = r / kLebDirs;
+        const int x = (int)(j % a.nx), y = (int)((j / a.nx) % a.ny), z = (int)(j / ((int64_t)a.nx * a.ny));
+        for (int64_t e = a.arr_ptr[m]; e < a.arr_ptr[m + 1]; ++e) {
+            const uint32_t k = a.arr_key[e];
+            const int ix = x - off_dx(k), iy = y - off_dy(k), iz = z - off_dz(k);
+            if (ix < 0 || ix >= a.nx || iy < 0 || iy >= a.ny || iz < 0 || iz >= a.nz) continue;
+            const int64_t i = ix + (int64_t)a.nx * (iy + (int64_t)a.ny * iz);
+            const int n = off_n(k);
+            const double c = a.blocks[((int64_t)a.mat[i] * kLebDirs + m) * kLebDirs + n];
+            if (c == 0.0) continue;
+            const double v = a.arr_w[e] * c;
+            if (v == 0.0) continue;
+            if (FILL) {
+                const int64_t cc = kLebDirs * i + n;
+                col[pos + cnt] = (int32_t)cc;
+                val[pos + cnt] = Store<VT>::cvt(v, a.rounding, r, cc);
+            }
+            ++cnt;
+        }
+    } else {
+        const int64_t s = a.escape_state[r - a.n_states];
+        const int m = (int)(s % kLebDirs);
+        const int64_t v = s / kLebDirs;
+        const int x = (int)(v % a.nx), y = (int)((v / a.nx) % a.ny), z = (int)(v / ((int64_t)a.nx * a.ny));
+        const double *C = a.blocks + ((int64_t)a.mat[v] * kLebDirs + m) * kLebDirs;
+        for (int n = 0; n < kLebDirs; ++n) {
+            const double c = C[n];
+            if (c == 0.0) continue;
+            double esc = 0.0;
+            bool any = false;
+            for (int64_t e = a.pair_ptr[m * kLebDirs + n]; e < a.pair_ptr[m * kLebDirs + n + 1]; ++e) {
+                const uint32_t k = a.pair_key[e];
+                const int ux = x + off_dx(k), uy = y + off_dy(k), uz = z + off_dz(k);
+                if (ux < 0 || ux >= a.nx || uy < 0 || uy >= a.ny || uz < 0 || uz >= a.nz) {
+                    esc += a.pair_w[e];
+                    any = true;
+                }
+            }
+            const double vv = esc * c;
+            if (!any || vv == 0.0) continue;
+            if (FILL) {
+                const int64_t cc = kLebDirs * v + n;
+                col[pos + cnt] = (int32_t)cc;
+                val[pos + cnt] = Store<VT>::cvt(vv, a.rounding, r, cc);
+            }
+            ++cnt;
+        }
+    }
+    if (!FILL) counts[r] = cnt;
+}
+
 template <typename IT>
 __global__ void narrow_row_ptr(const int64_t *in, IT *out, int64_t n)
 {
@@ -165,7 +253,7 @@ template <typename T> int upload(Device &dev, Buffer &b, const std::vector<T> &h
 }
 
 template <typename VT>
-int fill_values(Matrix *A, const AsmArgs &args, Buffer &rp64)
+int fill_values(Matrix *A, const AsmArgs &args, const LebArgs *leb, Buffer &rp64)
 {
     Device &dev = A->dev;
     const int64_t R = args.n_rows;
@@ -176,7 +264,13 @@ int fill_values(Matrix *A, const AsmArgs &args, Buffer &rp64)
     if (rc) return rc;
     DRTS_HIP(hipMemsetAsync(A->col.as<int32_t>() + A->nnz, 0, pad * sizeof(int32_t), dev.stream));
     DRTS_HIP(hipMemsetAsync(A->val.as<VT>() + A->nnz, 0, pad * sizeof(VT), dev.stream));
-    if (A->rp64) {
+    if (leb && A->rp64) {
+        hipLaunchKernelGGL((assemble_leb_rows<true, VT, int64_t>), dim3(blocks), dim3(256), 0, dev.stream, *leb,
+                           (int64_t *)nullptr, A->row_ptr.as<int64_t>(), A->col.as<int32_t>(), A->val.as<VT>());
+    } else if (leb) {
+        hipLaunchKernelGGL((assemble_leb_rows<true, VT, int32_t>), dim3(blocks), dim3(256), 0, dev.stream, *leb,
+                           (int64_t *)nullptr, A->row_ptr.as<int32_t>(), A->col.as<int32_t>(), A->val.as<VT>());
+    } else if (A->rp64) {
         hipLaunchKernelGGL((assemble_rows<true, VT, int64_t>), dim3(blocks), dim3(256), 0, dev.stream, args,
                            (int64_t *)nullptr, A->row_ptr.as<int64_t>(), A->col.as<int32_t>(), A->val.as<VT>());
     } else {
@@ -234,14 +328,44 @@ int assemble_on_device(Matrix *A)
     args.irr_bits = A->irr_bits.as<uint32_t>();
     args.escape_state = A->escape_state.as<int64_t>();
 
+    LebArgs leb{};
+    const bool is_leb = M.n_dir != kDirs;
+    if (is_leb) {
+        if ((rc = upload(dev, A->pair_ptr, M.pair_ptr))) return rc;
+        if ((rc = upload(dev, A->pair_key, M.pair_key))) return rc;
+        if ((rc = upload(dev, A->pair_w, M.pair_w))) return rc;
+        if ((rc = upload(dev, A->arr_ptr, M.arr_ptr))) return rc;
+        if ((rc = upload(dev, A->arr_key, M.arr_key))) return rc;
+        if ((rc = upload(dev, A->arr_w, M.arr_w))) return rc;
+        leb.nx = M.nx;
+        leb.ny = M.ny;
+        leb.nz = M.nz;
+        leb.rounding = M.rounding;
+        leb.n_states = M.n_states;
+        leb.n_rows = M.n_rows;
+        leb.mat = A->mat_of_voxel.as<uint8_t>();
+        leb.blocks = A->blocks64.as<double>();
+        leb.pair_ptr = A->pair_ptr.as<int64_t>();
+        leb.pair_key = A->pair_key.as<uint32_t>();
+        leb.pair_w = A->pair_w.as<double>();
+        leb.arr_ptr = A->arr_ptr.as<int64_t>();
+        leb.arr_key = A->arr_key.as<uint32_t>();
+        leb.arr_w = A->arr_w.as<double>();
+        leb.escape_state = A->escape_state.as<int64_t>();
+    }
+
     const int64_t R = M.n_rows;
     Buffer counts, rp64, tmp;
     if ((rc = counts.allocate(&dev, (R + 1) * sizeof(int64_t)))) return rc;
     if ((rc = rp64.allocate(&dev, (R + 1) * sizeof(int64_t)))) return rc;
     DRTS_HIP(hipMemsetAsync(counts.as<int64_t>() + R, 0, sizeof(int64_t), dev.stream));
     const unsigned blocks = (unsigned)((R + 255) / 256);
-    hipLaunchKernelGGL((assemble_rows<false, double, int64_t>), dim3(blocks), dim3(256), 0, dev.stream, args,
-                       counts.as<int64_t>(), (const int64_t *)nullptr, (int32_t *)nullptr, (double *)nullptr);
+    if (is_leb)
+        hipLaunchKernelGGL((assemble_leb_rows<false, double, int64_t>), dim3(blocks), dim3(256), 0, dev.stream, leb,
+                           counts.as<int64_t>(), (const int64_t *)nullptr, (int32_t *)nullptr, (double *)nullptr);
+    else
+        hipLaunchKernelGGL((assemble_rows<false, double, int64_t>), dim3(blocks), dim3(256), 0, dev.stream, args,
+                           counts.as<int64_t>(), (const int64_t *)nullptr, (int32_t *)nullptr, (double *)nullptr);
     DRTS_HIP(hipGetLastError());
 
     size_t tmp_bytes = 0;
@@ -269,7 +393,8 @@ int assemble_on_device(Matrix *A)
                            dev.stream, rp64.as<int64_t>(), A->row_ptr.as<int32_t>(), R + 1);
         DRTS_HIP(hipGetLastError());
     }
-    rc = (M.value_type == DRTS_F64) ? fill_values<double>(A, args, rp64) : fill_values<float>(A, args, rp64);
+    rc = (M.value_type == DRTS_F64) ? fill_values<double>(A, args, is_leb ? &leb : nullptr, rp64)
+                                    : fill_values<float>(A, args, is_leb ? &leb : nullptr, rp64);
     if (rc) return rc;
     DRTS_HIP(hipStreamSynchronize(dev.stream));
     return DRTS_OK;

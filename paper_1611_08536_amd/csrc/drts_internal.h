@@ -66,6 +66,21 @@ struct Model {
     int bc = DRTS_BC_VACUUM;
     int value_type = DRTS_F32, rounding = DRTS_ROUND_DITHER;
     int scatter_order = 1;                  // scatterings per step resolved by the blocks
+    int n_dir = kDirs;                      // directions per voxel: 26 (lattice) or 86 (Lebedev)
+    double c_dt = 1.0;                      // light path per step, in voxels
+    // Lebedev-86 (n_dir = 86): the rule, and the multi-voxel weights of every
+    // direction pair (m, n): offsets within one voxel of the arrival segment
+    // in scan order (ascending dz, dy, dx) with their weights ...
+    std::vector<double> dir_unit, dir_w;    // [86][3], [86]
+    std::vector<int64_t> pair_ptr;          // [86*86 + 1], pair m*86+n
+    std::vector<uint32_t> pair_key;         // packed offset
+    std::vector<double> pair_w;
+    // ... and, per arrival direction m, every (offset, n) it receives from, in
+    // descending (dz, dy, dx) then ascending n: a row pulls its entries in
+    // ascending column order
+    std::vector<int64_t> arr_ptr;           // [86 + 1]
+    std::vector<uint32_t> arr_key;          // packed offset | n << 15
+    std::vector<double> arr_w;
     std::vector<drts_material_t> mats;
     std::vector<uint8_t> mat_of_voxel;      // [n_vox]
     std::vector<double> blocks;             // [n_mat][26][26] C_q[m][n]
@@ -82,6 +97,14 @@ struct Model {
 
 int build_model(const drts_medium_t *m, Model *out);
 
+// Lebedev's 86-point rule (ascending z, y, x; weights summing to one).
+void lebedev86(double *unit, double *weight);
+// packed lattice offset of the Lebedev tables: (dx + 16) | (dy + 16) << 5 | (dz + 16) << 10
+__host__ __device__ inline int off_dx(uint32_t k) { return (int)(k & 31u) - 16; }
+__host__ __device__ inline int off_dy(uint32_t k) { return (int)((k >> 5) & 31u) - 16; }
+__host__ __device__ inline int off_dz(uint32_t k) { return (int)((k >> 10) & 31u) - 16; }
+__host__ __device__ inline int off_n(uint32_t k) { return (int)(k >> 15); }
+
 // ---- assembled matrix ----------------------------------------------------------
 struct Matrix {
     Device dev;
@@ -91,6 +114,7 @@ struct Matrix {
     Buffer row_ptr, col, val;
     Buffer mat_of_voxel, absorb, index, blocks64, blocks32;
     Buffer irr_row, irr_vox, irr_dir, irr_f, irr_bits, escape_state;
+    Buffer pair_ptr, pair_key, pair_w, arr_ptr, arr_key, arr_w;   // Lebedev weights
     int64_t bytes() const;
 };
 

@@ -218,7 +218,248 @@ struct IrrMove {
     }
 };
 
+// ---- Lebedev-86 directions with multi-voxel weights (Sec. 3, Eq. (18)-(21)) ----
+
+// Published generators of the 86-point rule (degree 15): the octahedron
+// vertices (a1), the cube vertices (a3), two orbits (+-l, +-l, +-m) (b_k) and
+// one orbit (+-p, +-q, 0) (c_1), with their weights.
+constexpr double kLebA1 = 0.1154401154401154e-1;
+constexpr double kLebA3 = 0.1194390908585628e-1;
+constexpr double kLebBL[2] = {0.3696028464541502, 0.6943540066026664};
+constexpr double kLebBW[2] = {0.1111055571060340e-1, 0.1187650129453714e-1};
+constexpr double kLebCP = 0.3742430390903412;
+constexpr double kLebCW = 0.1181230374690448e-1;
+constexpr int kLeb = 86;
+
+struct LebPoint {
+    double x, y, z, w;
+};
+
+// every sign combination of (a, b, c), a zero component taking only +0
+void leb_orbit(std::vector<LebPoint> &out, double a, double b, double c, double w)
+{
+    for (int sa = -1; sa <= 1; sa += 2)
+        for (int sb = -1; sb <= 1; sb += 2)
+            for (int sc = -1; sc <= 1; sc += 2) {
+                if ((a == 0.0 && sa < 0) || (b == 0.0 && sb < 0) || (c == 0.0 && sc < 0)) continue;
+                out.push_back({sa * a, sb * b, sc * c, w});
+            }
+}
+
+// distance from P to the segment a -> b (the point a when a == b)
+double segment_distance(const double *P, const double *a, const double *b)
+{
+    const double ab[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    const double ap[3] = {P[0] - a[0], P[1] - a[1], P[2] - a[2]};
+    const double L2 = ab[0] * ab[0] + ab[1] * ab[1] + ab[2] * ab[2];
+    double t = 0.0;
+    if (L2 > 0.0) {
+        t = (ap[0] * ab[0] + ap[1] * ab[1] + ap[2] * ab[2]) / L2;
+        if (t < 0.0) t = 0.0;
+        if (t > 1.0) t = 1.0;
+    }
+    const double q[3] = {a[0] + t * ab[0], a[1] + t * ab[1], a[2] + t * ab[2]};
+    const double d[3] = {P[0] - q[0], P[1] - q[1], P[2] - q[2]};
+    return std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+}
+
+inline uint32_t pack_off(int dx, int dy, int dz)
+{
+    return (uint32_t)(dx + 16) | ((uint32_t)(dy + 16) << 5) | ((uint32_t)(dz + 16) << 10);
+}
+
+// Direction block over the 86 directions for a step of light path L (mm):
+// C[m][n] = alpha (Ps G[m][n]) off the diagonal, alpha (P0 + Ps G[n][n]) on it,
+// G[m][n] = w_m p(S_m . S_n) / sum_k w_k p(S_k . S_n) (each direction weighted
+// by its solid angle, the rule's weight).
+void lebedev_block(const drts_material_t &q, double L, const double *S, const double *w, double *C)
+{
+    const double P0 = std::exp(-q.mu_s * L);
+    const double Ps = 1.0 - P0;
+    const double alpha = std::exp(-q.mu_a * L);
+    double p[kLeb];
+    for (int n = 0; n < kLeb; ++n) {
+        for (int m = 0; m < kLeb; ++m) {
+            const double cs = S[3 * m] * S[3 * n] + S[3 * m + 1] * S[3 * n + 1] + S[3 * m + 2] * S[3 * n + 2];
+            p[m] = w[m] * phase_hg(q.g, cs);
+        }
+        double Z = 0.0;
+        for (int k = 0; k < kLeb; ++k) Z += p[k];
+        for (int m = 0; m < kLeb; ++m) {
+            const double G = p[m] / Z;
+            C[m * kLeb + n] = (m == n) ? alpha * (P0 + Ps * G) : alpha * (Ps * G);
+        }
+    }
+}
+
+// The host model of a Lebedev medium: blocks, stencils of every direction
+// pair (voxels within 2 dr = one voxel of the arrival segment, weights the
+// normalised ramp 1 - d summed in scan order), the per-direction pull lists
+// and the escape states.
+int build_lebedev_model(const drts_medium_t *m, Model *M)
+{
+    const double c = m->c_dt > 0.0 ? m->c_dt : 1.0;
+    if (!(c <= 8.0)) return set_error(DRTS_E_INVALID, "c_dt must be in (0, 8] voxels");
+    if (m->bc != DRTS_BC_VACUUM) return set_error(DRTS_E_INVALID, "Lebedev directions take vacuum faces");
+    if (m->scatter_order > 1) return set_error(DRTS_E_INVALID, "Lebedev directions take scatter_order 0 or 1");
+    for (int q = 1; q < m->n_mat; ++q)
+        if (m->mat[q].n != m->mat[0].n)
+            return set_error(DRTS_E_INVALID, "Lebedev directions take one refractive index (no interfaces)");
+    if (M->n_vox * kLeb > (int64_t)INT32_MAX - 1)
+        return set_error(DRTS_E_RANGE, "%lld states exceed the int32 column range", (long long)(M->n_vox * kLeb));
+    M->n_dir = kLeb;
+    M->c_dt = c;
+    M->n_states = M->n_vox * kLeb;
+    M->dt_s = c * m->grid.h_mm * 1e-3 * m->n_ref / kC0;
+    M->dir_unit.resize(3 * kLeb);
+    M->dir_w.resize(kLeb);
+    lebedev86(M->dir_unit.data(), M->dir_w.data());
+    const double *S = M->dir_unit.data();
+    const double L = c * m->grid.h_mm;
+    M->blocks.resize((size_t)m->n_mat * kLeb * kLeb);
+    for (int q = 0; q < m->n_mat; ++q) {
+        lebedev_block(m->mat[q], L, S, M->dir_w.data(), &M->blocks[(size_t)q * kLeb * kLeb]);
+        M->absorb[q] = -std::expm1(-m->mat[q].mu_a * L);
+    }
+    // stencils of the pairs, offsets in scan order (ascending dz, dy, dx)
+    const int R = (int)std::ceil(c + 1.0);
+    M->pair_ptr.assign((size_t)kLeb * kLeb + 1, 0);
+    M->pair_key.clear();
+    M->pair_w.clear();
+    std::vector<double> raw;
+    std::vector<uint32_t> keys;
+    for (int mm = 0; mm < kLeb; ++mm)
+        for (int n = 0; n < kLeb; ++n) {
+            const double a[3] = {c * S[3 * mm], c * S[3 * mm + 1], c * S[3 * mm + 2]};
+            const double b[3] = {c * S[3 * n], c * S[3 * n + 1], c * S[3 * n + 2]};
+            M->pair_ptr[(size_t)mm * kLeb + n] = (int64_t)M->pair_key.size();
+            raw.clear();
+            keys.clear();
+            double sum = 0.0;
+            for (int dz = -R; dz <= R; ++dz)
+                for (int dy = -R; dy <= R; ++dy)
+                    for (int dx = -R; dx <= R; ++dx) {
+                        const double P[3] = {(double)dx, (double)dy, (double)dz};
+                        const double d = segment_distance(P, a, b);
+                        if (d < 1.0) {
+                            keys.push_back(pack_off(dx, dy, dz));
+                            raw.push_back(1.0 - d);
+                            sum += raw.back();
+                        }
+                    }
+            for (size_t i = 0; i < raw.size(); ++i) {
+                M->pair_key.push_back(keys[i]);
+                M->pair_w.push_back(raw[i] / sum);
+            }
+        }
+    M->pair_ptr[(size_t)kLeb * kLeb] = (int64_t)M->pair_key.size();
+    // per arrival direction: (offset, n) in descending offset order, ascending n
+    M->arr_ptr.assign(kLeb + 1, 0);
+    M->arr_key.clear();
+    M->arr_w.clear();
+    struct E {
+        int dz, dy, dx, n;
+        double w;
+    };
+    std::vector<E> es;
+    for (int mm = 0; mm < kLeb; ++mm) {
+        es.clear();
+        for (int n = 0; n < kLeb; ++n)
+            for (int64_t e = M->pair_ptr[(size_t)mm * kLeb + n]; e < M->pair_ptr[(size_t)mm * kLeb + n + 1]; ++e) {
+                const uint32_t k = M->pair_key[(size_t)e];
+                es.push_back({off_dz(k), off_dy(k), off_dx(k), n, M->pair_w[(size_t)e]});
+            }
+        std::sort(es.begin(), es.end(), [](const E &u, const E &v) {
+            if (u.dz != v.dz) return u.dz > v.dz;
+            if (u.dy != v.dy) return u.dy > v.dy;
+            if (u.dx != v.dx) return u.dx > v.dx;
+            return u.n < v.n;
+        });
+        M->arr_ptr[(size_t)mm] = (int64_t)M->arr_key.size();
+        for (const E &e : es) {
+            M->arr_key.push_back(pack_off(e.dx, e.dy, e.dz) | ((uint32_t)e.n << 15));
+            M->arr_w.push_back(e.w);
+        }
+    }
+    M->arr_ptr[kLeb] = (int64_t)M->arr_key.size();
+    // escape states: (v, m) with some offset of direction m outside the grid
+    std::vector<int> lo(3 * kLeb, 0), hi(3 * kLeb, 0);   // extent of every direction's offsets
+    for (int mm = 0; mm < kLeb; ++mm)
+        for (int64_t e = M->arr_ptr[(size_t)mm]; e < M->arr_ptr[(size_t)mm + 1]; ++e) {
+            const uint32_t k = M->arr_key[(size_t)e];
+            const int o[3] = {off_dx(k), off_dy(k), off_dz(k)};
+            for (int i = 0; i < 3; ++i) {
+                if (e == M->arr_ptr[(size_t)mm] || o[i] < lo[3 * mm + i]) lo[3 * mm + i] = o[i];
+                if (e == M->arr_ptr[(size_t)mm] || o[i] > hi[3 * mm + i]) hi[3 * mm + i] = o[i];
+            }
+        }
+    M->escape_state.clear();
+    const int nx = M->nx, ny = M->ny, nz = M->nz;
+    for (int64_t v = 0; v < M->n_vox; ++v) {
+        const int x = (int)(v % nx), y = (int)((v / nx) % ny), z = (int)(v / ((int64_t)nx * ny));
+        for (int mm = 0; mm < kLeb; ++mm) {
+            // the offsets of a direction span a box; any offset leaving the grid
+            // leaves through a face of that box, so test the offsets themselves
+            bool out = false;
+            if (x + lo[3 * mm] < 0 || x + hi[3 * mm] >= nx || y + lo[3 * mm + 1] < 0 || y + hi[3 * mm + 1] >= ny ||
+                z + lo[3 * mm + 2] < 0 || z + hi[3 * mm + 2] >= nz) {
+                for (int64_t e = M->arr_ptr[(size_t)mm]; e < M->arr_ptr[(size_t)mm + 1] && !out; ++e) {
+                    const uint32_t k = M->arr_key[(size_t)e];
+                    const int ux = x + off_dx(k), uy = y + off_dy(k), uz = z + off_dz(k);
+                    out = ux < 0 || ux >= nx || uy < 0 || uy >= ny || uz < 0 || uz >= nz;
+                }
+            }
+            if (out) M->escape_state.push_back(kLeb * v + mm);
+        }
+    }
+    M->n_escape = (int64_t)M->escape_state.size();
+    M->n_rows = M->n_states + M->n_escape;
+    M->irr_row.clear();
+    M->irr_vox.clear();
+    M->irr_dir.clear();
+    M->irr_f.clear();
+    return DRTS_OK;
+}
+
 }  // namespace
+
+void lebedev86(double *unit, double *weight)
+{
+    std::vector<LebPoint> P;
+    leb_orbit(P, 1.0, 0.0, 0.0, kLebA1);
+    leb_orbit(P, 0.0, 1.0, 0.0, kLebA1);
+    leb_orbit(P, 0.0, 0.0, 1.0, kLebA1);
+    const double r = std::sqrt(1.0 / 3.0);
+    leb_orbit(P, r, r, r, kLebA3);
+    for (int i = 0; i < 2; ++i) {
+        const double l = kLebBL[i], mz = std::sqrt(1.0 - 2.0 * l * l);
+        leb_orbit(P, l, l, mz, kLebBW[i]);
+        leb_orbit(P, l, mz, l, kLebBW[i]);
+        leb_orbit(P, mz, l, l, kLebBW[i]);
+    }
+    const double p = kLebCP, q = std::sqrt(1.0 - p * p);
+    leb_orbit(P, p, q, 0.0, kLebCW);
+    leb_orbit(P, q, p, 0.0, kLebCW);
+    leb_orbit(P, p, 0.0, q, kLebCW);
+    leb_orbit(P, q, 0.0, p, kLebCW);
+    leb_orbit(P, 0.0, p, q, kLebCW);
+    leb_orbit(P, 0.0, q, p, kLebCW);
+    std::sort(P.begin(), P.end(), [](const LebPoint &a, const LebPoint &b) {
+        if (a.z != b.z) return a.z < b.z;
+        if (a.y != b.y) return a.y < b.y;
+        return a.x < b.x;
+    });
+    double sum = 0.0;
+    for (const LebPoint &t : P) sum += t.w;
+    for (int i = 0; i < kLeb; ++i) {
+        if (unit) {
+            unit[3 * i] = P[(size_t)i].x;
+            unit[3 * i + 1] = P[(size_t)i].y;
+            unit[3 * i + 2] = P[(size_t)i].z;
+        }
+        if (weight) weight[i] = P[(size_t)i].w / sum;
+    }
+}
 
 int build_model(const drts_medium_t *m, Model *M)
 {
@@ -297,9 +538,15 @@ int build_model(const drts_medium_t *m, Model *M)
     }
 
     // per-material tables
-    M->blocks.resize((size_t)m->n_mat * kDirs * kDirs);
     M->absorb.resize(m->n_mat);
     M->index.resize(m->n_mat);
+    for (int q = 0; q < m->n_mat; ++q) M->index[q] = m->mat[q].n;
+    if (m->directions == DRTS_DIRS_LEBEDEV86) return build_lebedev_model(m, M);
+    if (m->directions != DRTS_DIRS_LATTICE26) return set_error(DRTS_E_INVALID, "unknown directions %d", m->directions);
+    if (m->c_dt != 0.0 && m->c_dt != 1.0)
+        return set_error(DRTS_E_INVALID, "the lattice directions move one voxel per step (c_dt 0 or 1)");
+    M->n_dir = kDirs;
+    M->blocks.resize((size_t)m->n_mat * kDirs * kDirs);
     for (int q = 0; q < m->n_mat; ++q) {
         direction_block(m->mat[q], g.h_mm, M->scatter_order, &M->blocks[(size_t)q * kDirs * kDirs]);
         M->absorb[q] = -std::expm1(-m->mat[q].mu_a * g.h_mm);

@@ -258,6 +258,8 @@ int drts_serve_submit(drts_server_t *Q, const drts_medium_t *medium, const drts_
 {
     if (!Q || !medium || !request_id) return set_error(DRTS_E_INVALID, "NULL argument");
     if (medium->value_type != DRTS_F32) return set_error(DRTS_E_INVALID, "served solves take FP32 media");
+    if (medium->directions != DRTS_DIRS_LATTICE26)
+        return set_error(DRTS_E_INVALID, "served solves take the 26 lattice directions");
     if (n_steps < 1) return set_error(DRTS_E_INVALID, "n_steps must be >= 1");
     std::unique_ptr<Request> q;
     int rc;

@@ -57,6 +57,7 @@ struct StepInst {
     const int64_t *t_end;   // steps are skipped once t >= *t_end
     int32_t rescale;
     int32_t n_mat;          // entries of absorb
+    uint64_t vox_mul;       // vox_mul_of(directions per voxel): row -> voxel
     int64_t max_steps;
     // partials [slot * n_rhs + rhs][n_chunks], then [slot * n_rhs + rhs][kFinSeg]
     double *partials;
@@ -68,11 +69,24 @@ struct StepInst {
     int32_t *ser_abs_exp;   // [max_steps][n_rhs]: exponent E_t of absorbed(t)
 };
 
+// Voxel of state row r (< 2^32): r / n_dir as the high half of r * mul with
+// mul = ceil(2^64 / n_dir), exact for every r < 2^32 (the error of mul, below
+// n_dir, moves r * mul by less than 2^64 / n_dir).
+__device__ __forceinline__ int64_t vox_of(int64_t r, uint64_t mul) { return (int64_t)__umul64hi((uint64_t)r, mul); }
+inline uint64_t vox_mul_of(int n_dir) { return ~0ull / (uint64_t)n_dir + 1ull; }
+
 // One unit of work of a launch: chunk `chunk` of instance `inst`.
 struct WorkItem {
     int32_t inst;
     int32_t chunk;
 };
+
+// Launch variant (bits 1..4 of xcd_remap) of the wave-per-row SpMV for rows of
+// several hundred entries; chosen by the library for such matrices, not an
+// option of the caller.
+constexpr int kVariantLongRows = 9;
+// mean entries per row from which a matrix takes the wave-per-row SpMV
+constexpr int kLongRowMean = 96;
 
 // Launches the SpMV (n_rhs == 1) or SpMM step over a work list.  xcd_remap
 // bit 0 selects the XCD-aware order, bit 1 the pipelined SpMV.  Returns a

@@ -234,7 +234,7 @@ template <typename VT, typename IT, int U> struct TileRegs {
 template <typename VT, typename IT, int NT, int U, int R>
 __device__ __forceinline__ void issue_tile(TileRegs<VT, IT, U> &T, const GLB IT *rp, const GLB int32_t *col,
                                            const GLB VT *val, const GLB uint8_t *mat, IT b, IT e, int64_t r0,
-                                           int nr, int64_t n_states, int64_t nnz)
+                                           int nr, int64_t n_states, uint64_t vmul, int64_t nnz)
 {
     const int tid = threadIdx.x;
     const int64_t r = r0 + tid;
@@ -246,7 +246,7 @@ __device__ __forceinline__ void issue_tile(TileRegs<VT, IT, U> &T, const GLB IT 
     if (tid < nr && tid < R) {
         T.mylo = rp[r];
         T.myhi = rp[r + 1];
-        if (r < n_states) T.q = mat[r / kDirs];
+        if (r < n_states) T.q = mat[vox_of(r, vmul)];
     }
     // Every lane runs U quads without branches: a quad index at or past e is
     // clamped to the last quad holding entries of the tile, so the lane
@@ -318,7 +318,7 @@ template <typename IT, int U> struct TileRegsL {
 template <typename IT, int NT, int U, int R>
 __device__ __forceinline__ void issue_tile_l(TileRegsL<IT, U> &T, const GLB IT *rp, const GLB int32_t *col,
                                              const GLB float *val, const GLB uint8_t *mat, IT b, IT e, int64_t r0,
-                                             int nr, int64_t n_states, int64_t nnz, float *s_prod)
+                                             int nr, int64_t n_states, uint64_t vmul, int64_t nnz, float *s_prod)
 {
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -331,7 +331,7 @@ __device__ __forceinline__ void issue_tile_l(TileRegsL<IT, U> &T, const GLB IT *
     if (tid < nr && tid < R) {
         T.mylo = rp[r];
         T.myhi = rp[r + 1];
-        if (r < n_states) T.q = mat[r / kDirs];
+        if (r < n_states) T.q = mat[vox_of(r, vmul)];
     }
     // quads past the tile re-read its last quad (in bounds, as in the quad
     // layout) into slots no row of the tile reads
@@ -413,7 +413,7 @@ template <typename VT, typename IT, int S> struct TileRegsS {
 template <typename VT, typename IT, int NT, int S, int R>
 __device__ __forceinline__ void issue_tile_s(TileRegsS<VT, IT, S> &T, const GLB IT *rp, const GLB int32_t *col,
                                              const GLB VT *val, const GLB uint8_t *mat, IT b, IT e, int64_t r0,
-                                             int nr, int64_t n_states, int64_t nnz)
+                                             int nr, int64_t n_states, uint64_t vmul, int64_t nnz)
 {
     const int tid = threadIdx.x;
     const int64_t r = r0 + tid;
@@ -425,7 +425,7 @@ __device__ __forceinline__ void issue_tile_s(TileRegsS<VT, IT, S> &T, const GLB 
     if (tid < nr && tid < R) {
         T.mylo = rp[r];
         T.myhi = rp[r + 1];
-        if (r < n_states) T.q = mat[r / kDirs];
+        if (r < n_states) T.q = mat[vox_of(r, vmul)];
     }
     // indices past the tile are clamped to its last entry (an empty tile reads
     // entry b, at worst the zero padding): no branches, every load in bounds;
@@ -560,6 +560,7 @@ __global__ void __launch_bounds__(NT, (LAY == 2 && sizeof(VT) == 4 && sizeof(IT)
         GLB VT *y = gpw((VT *)((t & 1) ? I.buf0 : I.buf1));
         const GLB uint8_t *mat = gp(I.mat);
         const int64_t n_rows = I.n_rows, n_states = I.n_states;
+        const uint64_t vmul = I.vox_mul;
         const int64_t tile0 = (int64_t)item.chunk * I.tiles_per_chunk;
         const int ntc = (int)min((int64_t)I.tiles_per_chunk, I.n_tiles - tile0);
 
@@ -579,7 +580,7 @@ __global__ void __launch_bounds__(NT, (LAY == 2 && sizeof(VT) == 4 && sizeof(IT)
         auto rows_of = [&](int j) { return (int)min((int64_t)R, n_rows - (tile0 + j) * R); };
         bool have = false;
         if (PIPE && ntc > 0 && fits(0)) {
-            issue_tile<VT, IT, NT, U, R>(cur, rp, col, val, mat, s_tb[0], s_tb[1], tile0 * R, rows_of(0), n_states, I.nnz);
+            issue_tile<VT, IT, NT, U, R>(cur, rp, col, val, mat, s_tb[0], s_tb[1], tile0 * R, rows_of(0), n_states, vmul, I.nnz);
             have = true;
         }
         for (int j = 0; j < ntc; ++j) {
@@ -593,7 +594,7 @@ __global__ void __launch_bounds__(NT, (LAY == 2 && sizeof(VT) == 4 && sizeof(IT)
                 if constexpr (sizeof(VT) == 4) {
                     TileRegsL<IT, U> tl;
                     issue_tile_l<IT, NT, U, R>(tl, rp, col, (const GLB float *)val, mat, s_tb[j], s_tb[j + 1], r0, nr,
-                                               n_states, I.nnz, (float *)s_prod);
+                                               n_states, vmul, I.nnz, (float *)s_prod);
                     // the previous tile's store goes out after this tile's
                     // gathers; a wave that issued it then waits for all but it
                     const bool mine = pend_y != nullptr && 64 * wave < pend_nr;
@@ -603,16 +604,16 @@ __global__ void __launch_bounds__(NT, (LAY == 2 && sizeof(VT) == 4 && sizeof(IT)
             } else if (LAYV == 1 && fits(j)) {
                 TileRegsS<VT, IT, CAP / NT> ts;
                 issue_tile_s<VT, IT, NT, CAP / NT, R>(ts, rp, col, val, mat, s_tb[j], s_tb[j + 1], r0, nr, n_states,
-                                                      I.nnz);
+                                                      vmul, I.nnz);
                 acc = finish_tile_s<VT, IT, NT, CAP / NT, R>(ts, rx, s_prod);
                 q = ts.q;
             } else if (fits(j)) {
                 if (!have)
-                    issue_tile<VT, IT, NT, U, R>(cur, rp, col, val, mat, s_tb[j], s_tb[j + 1], r0, nr, n_states, I.nnz);
+                    issue_tile<VT, IT, NT, U, R>(cur, rp, col, val, mat, s_tb[j], s_tb[j + 1], r0, nr, n_states, vmul, I.nnz);
                 bool more = false;
                 if (PIPE && j + 1 < ntc && fits(j + 1)) {
                     issue_tile<VT, IT, NT, U, R>(nxt, rp, col, val, mat, s_tb[j + 1], s_tb[j + 2], r0 + R, rows_of(j + 1),
-                                              n_states, I.nnz);
+                                              n_states, vmul, I.nnz);
                     more = true;
                 }
                 acc = finish_tile<VT, IT, NT, U, R>(cur, rx, s_prod);
@@ -626,7 +627,7 @@ __global__ void __launch_bounds__(NT, (LAY == 2 && sizeof(VT) == 4 && sizeof(IT)
                 if (own) {
                     mylo = rp[r];
                     myhi = rp[r + 1];
-                    if (r < n_states) q = mat[r / kDirs];
+                    if (r < n_states) q = mat[vox_of(r, vmul)];
                 }
                 for (IT a = b & ~(IT)3; a < e; a += CAP) {
                     const IT cs = a < b ? b : a;
@@ -650,7 +651,7 @@ __global__ void __launch_bounds__(NT, (LAY == 2 && sizeof(VT) == 4 && sizeof(IT)
                 have = false;
                 if (PIPE && j + 1 < ntc && fits(j + 1)) {
                     issue_tile<VT, IT, NT, U, R>(cur, rp, col, val, mat, s_tb[j + 1], s_tb[j + 2], r0 + R, rows_of(j + 1),
-                                              n_states, I.nnz);
+                                              n_states, vmul, I.nnz);
                     have = true;
                 }
             }
@@ -716,6 +717,152 @@ __global__ void __launch_bounds__(NT, (LAY == 2 && sizeof(VT) == 4 && sizeof(IT)
     flush();
 }
 
+// ---------------------------------------------------------------------------
+// SpMV step for long rows (several hundred entries, as the multi-voxel
+// weights of Lebedev media give): one wave per row while summing
+//
+// A workgroup takes a tile of R rows.  Each wave sums every fourth row of the
+// tile: lane l multiplies entries lo + l, lo + l + 64, ... (four loads in
+// flight per lane, each a coalesced 256-byte stream of the wave) and adds them
+// in that order; a butterfly then adds the 64 lane sums in a fixed order.
+// The tile's sums go to LDS and the epilogue (rescale, sources, y store, FP64
+// totals and detectors, chunk partials) is the one of the tile kernels, a
+// thread per row.  Results are reproducible run to run; they are not the
+// tile kernels' sequential row sums bit for bit.
+// ---------------------------------------------------------------------------
+template <typename VT, typename IT>
+__global__ void __launch_bounds__(kNT) step_spmv_long(const StepInst *__restrict__ insts,
+                                                       const WorkItem *__restrict__ work, int64_t n_work,
+                                                       int xcd_remap, const int64_t *__restrict__ xcd_bounds)
+{
+    constexpr int NT = kNT, NW = NT / 64;
+    __shared__ double s_wred[4][NW];
+    __shared__ IT s_tb[kChunkMax + 1];
+    __shared__ int32_t s_src[kChunkMax + 1];
+    __shared__ int32_t s_det[kChunkMax + 1];
+    __shared__ double s_abs[kMatMax];
+    __shared__ VT s_y[NT];
+    __shared__ VT s_acc[NT];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const Walk wk = walk_of(n_work, xcd_remap, xcd_bounds);
+    int cached = -1;
+    int64_t t = 0;
+    bool live = false;
+    Scale sc{0, 0};
+    VT scale = 1;
+    for (int64_t wi = wk.begin; wi < wk.end; wi += wk.stride) {
+        const WorkItem item = work[wi];
+        const StepInst &I = insts[item.inst];
+        if (item.inst != cached) {
+            cached = item.inst;
+            t = I.t[0];
+            live = t < *I.t_end;
+            if (live) {
+                sc = step_scale(I, 0, t);
+                scale = (VT)ldexp(1.0, -sc.k);
+            }
+        }
+        if (!live) continue;
+        const int R = I.rows_per_tile;
+        const GLB IT *rp = gp((const IT *)I.row_ptr);
+        const GLB int32_t *col = gp(I.col);
+        const GLB VT *val = gp((const VT *)I.val);
+        const GLB VT *x = gp((const VT *)((t & 1) ? I.buf1 : I.buf0));
+        GLB VT *y = gpw((VT *)((t & 1) ? I.buf0 : I.buf1));
+        const GLB uint8_t *mat = gp(I.mat);
+        const int64_t n_rows = I.n_rows, n_states = I.n_states;
+        const uint64_t vmul = I.vox_mul;
+        const int64_t tile0 = (int64_t)item.chunk * I.tiles_per_chunk;
+        const int ntc = (int)min((int64_t)I.tiles_per_chunk, I.n_tiles - tile0);
+        for (int j = tid; j <= ntc; j += NT) {
+            s_tb[j] = rp[min((tile0 + j) * R, n_rows)];
+            s_src[j] = gp(I.src_tile)[tile0 + j];
+            s_det[j] = gp(I.det_tile)[tile0 + j];
+        }
+        for (int q = tid; q < I.n_mat; q += NT) s_abs[q] = gp(I.absorb)[q];
+        __syncthreads();
+        double sN = 0.0, sE = 0.0, sA = 0.0, dsum = 0.0;
+        VT mx = 0;
+        for (int j = 0; j < ntc; ++j) {
+            const int64_t r0 = (tile0 + j) * R;
+            const int nr = (int)min((int64_t)R, n_rows - r0);
+            // row sums, a wave per row
+            for (int rr = wave; rr < nr; rr += NW) {
+                const IT lo = rp[r0 + rr], hi = rp[r0 + rr + 1];
+                VT a = 0;
+                for (IT k = lo + lane; k < hi; k += 256) {
+                    VT p[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const IT kk = k + 64 * u;
+                        p[u] = 0;
+                        if (kk < hi) p[u] = __builtin_nontemporal_load(val + kk) * x[__builtin_nontemporal_load(col + kk)];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) a += p[u];
+                }
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+                if (lane == 0) s_acc[rr] = a;
+            }
+            __syncthreads();
+            // epilogue: a thread per row
+            const int64_t r = r0 + tid;
+            const bool own = tid < nr;
+            if (own) {
+                VT v = s_acc[tid] * scale;
+                const int sb = s_src[j], se = s_src[j + 1];
+                if (sb < se) {
+                    const GLB int64_t *srow = gp(I.src_row);
+                    int e2 = lower_bound_rows<IT>(I.src_row, sb, se, r);
+                    double s = 0.0;
+                    bool any = false;
+                    for (; e2 < se && srow[e2] == r; ++e2) {
+                        s += gp(I.src_w)[e2] * gp(I.amp)[t * I.n_src + gp(I.src_id)[e2]];
+                        any = true;
+                    }
+                    if (any) v += (VT)ldexp(s, -sc.En);
+                }
+                y[r] = v;
+                s_y[tid] = v;
+                if (r < n_states) {
+                    sN += (double)v;
+                    sA += s_abs[mat[vox_of(r, vmul)]] * (double)v;
+                    mx = v > mx ? v : mx;
+                } else {
+                    sE += (double)v;
+                }
+            }
+            __syncthreads();
+            const int db = s_det[j], de = s_det[j + 1];
+            if (db < de && tid < I.n_det) {
+                for (int e2 = db; e2 < de; ++e2)
+                    if (gp(I.det_id)[e2] == tid) dsum += gp(I.det_F)[e2] * (double)s_y[gp(I.det_row)[e2] - r0];
+            }
+        }
+        // chunk partials: wave butterflies, then the waves in order
+        const int64_t nc = I.n_chunks, c = item.chunk;
+        const double wN = wave_sum(sN), wE = wave_sum(sE), wA = wave_sum(sA), wM = wave_max((double)mx);
+        if (lane == 0) {
+            s_wred[0][wave] = wN;
+            s_wred[1][wave] = wE;
+            s_wred[2][wave] = wA;
+            s_wred[3][wave] = wM;
+        }
+        __syncthreads();
+        GLB double *part = gpw(I.partials);
+        if (tid < 4) {
+            double a = s_wred[tid][0];
+            for (int w = 1; w < NW; ++w) a = (tid == 3) ? fmax(a, s_wred[tid][w]) : a + s_wred[tid][w];
+            part[(int64_t)tid * nc + c] = a;
+        }
+        if (tid < I.n_det) part[(int64_t)(kSlotDet + tid) * nc + c] = dsum;
+        __syncthreads();   // s_tb, s_src, s_det and s_wred are rewritten by the next item
+    }
+}
+
 // value of lane l (uniform l) of a 64-bit per-lane value
 __device__ __forceinline__ int64_t lane_i64(int64_t v, int l)
 {
@@ -768,6 +915,7 @@ __global__ void __launch_bounds__(256) step_spmv_wave(const StepInst *__restrict
         GLB VT *y = gpw((VT *)((t & 1) ? I.buf0 : I.buf1));
         const GLB uint8_t *mat = gp(I.mat);
         const int64_t n_rows = I.n_rows, n_states = I.n_states;
+        const uint64_t vmul = I.vox_mul;
         const int nd = I.n_det;
         const int64_t tile0 = (int64_t)item.chunk * I.tiles_per_chunk;
         const int64_t tile1 = min(tile0 + (int64_t)I.tiles_per_chunk, I.n_tiles);
@@ -831,7 +979,7 @@ __global__ void __launch_bounds__(256) step_spmv_wave(const StepInst *__restrict
             const bool own = lane < nr;
             const IT mylo = cur.mylo, myhi = cur.myhi, b = cur.b, e = cur.e;
             int q = 0;
-            if (own && r < n_states) q = mat[r / kDirs];
+            if (own && r < n_states) q = mat[vox_of(r, vmul)];
             VT acc = 0;
             if (fits_w(cur)) {
                 if (!have) stream_of(cur);
@@ -1032,6 +1180,7 @@ __global__ void __launch_bounds__(256) step_spmv_wl(const StepInst *__restrict__
         GLB float *y = gpw((float *)((t & 1) ? I.buf0 : I.buf1));
         const GLB uint8_t *mat = gp(I.mat);
         const int64_t n_rows = I.n_rows, n_states = I.n_states;
+        const uint64_t vmul = I.vox_mul;
         const int nd = I.n_det;
         const int64_t tile0 = (int64_t)item.chunk * I.tiles_per_chunk;
         const int ntc = (int)min((int64_t)I.tiles_per_chunk, I.n_tiles - tile0);
@@ -1056,7 +1205,7 @@ __global__ void __launch_bounds__(256) step_spmv_wl(const StepInst *__restrict__
             if (own) {
                 mylo = rp[r];
                 myhi = rp[r + 1];
-                if (r < n_states) q = mat[r / kDirs];
+                if (r < n_states) q = mat[vox_of(r, vmul)];
             }
             float acc = 0;
             if (e - b <= (IT)CAPW - 3) {
@@ -1374,7 +1523,7 @@ __global__ void __launch_bounds__(kNT) step_spmm(const StepInst *__restrict__ in
                     Y[r * nrhs + lane] = v;
                     if (r < I.n_states) {
                         sN += (double)v;
-                        sA += s_abs[mat[r / kDirs]] * (double)v;
+                        sA += s_abs[mat[vox_of(r, I.vox_mul)]] * (double)v;
                         mx = fmaxf(mx, v);
                     } else {
                         sE += (double)v;
@@ -2522,6 +2671,17 @@ hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int6
         else DRTS_SPMV1(VT, IT, RV, RV, 0, 0);                       \
     } while (0)
         const int nt = rows_per_tile <= 64 ? 64 : (rows_per_tile <= 128 ? 128 : 256);
+        if (variant == kVariantLongRows) {
+            // rows of several hundred entries: a wave per row
+            if (value_f64) {
+                if (rp64) hipLaunchKernelGGL((step_spmv_long<double, int64_t>), g1, dim3(kNT), 0, stream, insts_dev, work_dev, n_work, remap, xcd_bounds);
+                else hipLaunchKernelGGL((step_spmv_long<double, int32_t>), g1, dim3(kNT), 0, stream, insts_dev, work_dev, n_work, remap, xcd_bounds);
+            } else {
+                if (rp64) hipLaunchKernelGGL((step_spmv_long<float, int64_t>), g1, dim3(kNT), 0, stream, insts_dev, work_dev, n_work, remap, xcd_bounds);
+                else hipLaunchKernelGGL((step_spmv_long<float, int32_t>), g1, dim3(kNT), 0, stream, insts_dev, work_dev, n_work, remap, xcd_bounds);
+            }
+            return hipGetLastError();
+        }
         if (variant == 8 && !value_f64) {
             // tiles of kWaveTileRows rows, one wave each, values through LDS
             if (rp64)

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libdrts.so")
 F64, F32 = 0, 1
 ROUND_NEAREST, ROUND_DITHER = 0, 1
 GEOM = {"voxels": 0, "homog": 0, "layers_z": 1, "sphere": 2}
+DIRECTIONS = {"lattice26": 0, "lebedev86": 1}
 BC = {"vacuum": 0, "reflect": 1}
 KERNEL_CSR, KERNEL_STRUCTURED, KERNEL_STRUCTURED_F64SUM = 0, 1, 2
 SERVE_ARRIVAL, SERVE_SHORTEST = 0, 1
@@ -70,7 +71,8 @@ class Geometry(C.Structure):
 class MediumT(C.Structure):
     _fields_ = [("grid", Grid), ("n_mat", i32), ("mat", C.POINTER(MaterialT)),
                 ("mat_of_voxel", C.POINTER(C.c_uint8)), ("geom", Geometry), ("bc", i32),
-                ("value_type", i32), ("rounding", i32), ("n_ref", dbl), ("scatter_order", i32)]
+                ("value_type", i32), ("rounding", i32), ("n_ref", dbl), ("scatter_order", i32),
+                ("directions", i32), ("c_dt", dbl)]
 
 
 ALLOC_FN = C.CFUNCTYPE(P, P, C.c_size_t, P)
@@ -110,6 +112,7 @@ def _sig(name, res, args):
 
 _sig("drts_last_error", C.c_char_p, [])
 _sig("drts_build_matrix", C.c_int, [C.POINTER(MediumT), C.POINTER(DeviceT), C.POINTER(P)])
+_sig("drts_direction_set", C.c_int, [i32, P, P])
 _sig("drts_matrix_info", C.c_int, [P, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64),
                                    C.POINTER(dbl)])
 _sig("drts_matrix_row_of", i64, [P, i64, i32])
@@ -147,7 +150,7 @@ _sig("drts_serve_destroy", None, [P])
 _sig("drts_serve_set_step", C.c_int, [P, i32])
 
 EXPORTED = [
-    "drts_build_matrix", "drts_matrix_info", "drts_matrix_row_of", "drts_matrix_export_rows",
+    "drts_direction_set", "drts_build_matrix", "drts_matrix_info", "drts_matrix_row_of", "drts_matrix_export_rows",
     "drts_matrix_destroy", "drts_solver_create", "drts_solver_get_options", "drts_solver_set_options",
     "drts_step", "drts_step_noalloc", "drts_run", "drts_solver_time", "drts_detector_readout", "drts_detector_window", "drts_state_read",
     "drts_state_write", "drts_solver_profile", "drts_solver_profile_stats", "drts_solver_destroy",
@@ -212,10 +215,27 @@ def default_device() -> TorchDevice:
 
 # ---- state layout of the library ---------------------------------------------
 
+def direction_set(name: str = "lattice26"):
+    """(unit [n, 3], weight [n]) of an angular partition (drts_direction_set)."""
+    code = DIRECTIONS[name]
+    n = _lib.drts_direction_set(code, None, None)
+    unit, w = np.zeros((n, 3)), np.zeros(n)
+    _check(0 if _lib.drts_direction_set(code, unit.ctypes.data, w.ctypes.data) == n else -1, "drts_direction_set")
+    return unit, w
+
+
 def state_index(medium, vox, dirs) -> np.ndarray:
     """State 26 v + d of voxels (x, y, z) and lattice vectors (dx, dy, dz), with
-    v = x + nx (y + ny z) and d = k - (k > 13), k = 9(dz+1) + 3(dy+1) + (dx+1)."""
+    v = x + nx (y + ny z) and d = k - (k > 13), k = 9(dz+1) + 3(dy+1) + (dx+1);
+    on Lebedev media 86 v + n, n the library's direction nearest the given
+    vector (largest cosine, the lowest index on ties)."""
     vox = np.asarray(vox, dtype=np.int64).reshape(-1, 3)
+    if getattr(medium, "directions", "lattice26") == "lebedev86":
+        unit, _ = direction_set("lebedev86")
+        dv = np.asarray(dirs, dtype=np.float64).reshape(-1, 3)
+        dv = dv / np.linalg.norm(dv, axis=1, keepdims=True)
+        v = vox[:, 0] + medium.nx * (vox[:, 1] + medium.ny * vox[:, 2])
+        return 86 * v + np.argmax(dv @ unit.T, axis=1)
     dirs = np.asarray(dirs, dtype=np.int64).reshape(-1, 3)
     k = 9 * (dirs[:, 2] + 1) + 3 * (dirs[:, 1] + 1) + (dirs[:, 0] + 1)
     d = k - (k > 13)
@@ -248,6 +268,8 @@ def _medium_struct(medium, value_type="f32", rounding="dither", n_ref=None, use_
     m.rounding = ROUND_DITHER if rounding == "dither" else ROUND_NEAREST
     m.n_ref = n_ref if n_ref is not None else medium.materials[0].n
     m.scatter_order = getattr(medium, "scatter_order", 1)
+    m.directions = DIRECTIONS[getattr(medium, "directions", "lattice26")]
+    m.c_dt = getattr(medium, "c_dt", 1.0)
     return m, (mats, vmap, z0)
 
 

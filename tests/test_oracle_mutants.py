@@ -75,6 +75,8 @@ MUTANTS = [
     ("leb_escape_weight", C_SRC, "esc += L->st->w[e];\n                            any_out = 1;",
      "esc += 1.0;\n                            any_out = 1;"),
     ("leb_generator_value", C_SRC, "0.6943540066026664", "0.6943450066026664"),
+    ("leb_step_time_one_voxel", PY_SRC, 'dt = dt_seconds(med.h_mm * getattr(med, "c_dt", 1.0), workload.n_ref)',
+     "dt = dt_seconds(med.h_mm, workload.n_ref)"),
     # dither key with row and column swapped
     ("dither_key_swapped", C_SRC, "uint64_t key = ((uint64_t)r << 32) ^ (uint64_t)(uint32_t)A->col[j];",
      "uint64_t key = ((uint64_t)(uint32_t)A->col[j] << 32) ^ (uint64_t)r;"),

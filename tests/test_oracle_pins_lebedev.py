@@ -272,3 +272,19 @@ def test_push_assembly_equals_numpy_pull(orc):
             for x in ws:
                 acc += x
             assert row[0, 86 * i + n] == acc * C[m, n], (i, m, n)
+
+
+def test_source_steps_follow_the_light_path(orc):
+    """A step lasts the time light takes for c dt: with half a voxel per step
+    the pulse integrals of Sec. 4.1 are taken over steps half as long, so their
+    running sum is the Gaussian's distribution function at (k + 1) dt."""
+    from scipy.stats import norm
+    med = _lebedev_medium(4, W.Material(10.0, 0.01, 0.9, 1.4), c_dt=0.5)
+    src = W.point_source(1, 1, 0, kind="gaussian", fwhm_fs=300.0)
+    wl = W.Workload("pulse", med, [src], [], 12, 1, "f32", "dither", 1.4)
+    A = orc.Matrix(med)
+    _, _, _, amp = orc.source_arrays(A, wl)
+    dt = 0.5 * med.h_mm * 1e-3 * 1.4 / 299792458.0
+    sig = 300e-15 / (2 * math.sqrt(2 * math.log(2)))
+    want = norm.cdf(((np.arange(12) + 1) * dt - 3 * sig) / sig)
+    assert np.allclose(np.cumsum(amp[:, 0]), want, rtol=0, atol=1e-13)
