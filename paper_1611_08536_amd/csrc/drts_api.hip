@@ -72,6 +72,14 @@ void Buffer::reset()
 }
 
 int64_t Matrix::bytes() const { return (int64_t)(row_ptr.bytes + col.bytes + val.bytes); }
+int64_t Matrix::table_bytes() const
+{
+    const Buffer *b[] = {&mat_of_voxel, &absorb, &index, &blocks64, &blocks32, &irr_row, &irr_vox, &irr_dir,
+                         &irr_f, &irr_bits, &escape_state, &pair_ptr, &pair_key, &pair_w, &arr_ptr, &arr_key, &arr_w};
+    int64_t n = 0;
+    for (const Buffer *x : b) n += (int64_t)x->bytes;
+    return n;
+}
 
 static Device make_device(const drts_device_t *d)
 {
@@ -166,6 +174,9 @@ struct drts_batch {
     Buffer sas_dev, xwork_dev;   // matrix-free members: their arguments, their irregular-row items
     int grid = 0;                // workgroups of the step launch; 0: 16 per CU
     int mode = 0;                // 0: CSR step; 1 or 2: the matrix-free mode of every member
+    // graphs of the last run, destroyed once the stream has passed them
+    std::vector<hipGraphExec_t> spent;
+    hipEvent_t done = nullptr;   // recorded after the last run's launches
 };
 
 namespace {
@@ -763,6 +774,8 @@ int launch_one(drts_solver *S, hipStream_t stream, const StepInst *inst = nullpt
         if (!e0 || !e1) return set_error(DRTS_E_HIP, "hipEventCreate failed");
         DRTS_HIP(hipEventRecord(e0, stream));
     }
+    if (!structured_of(S) && !A.has_csr)
+        return set_error(DRTS_E_STATE, "the CSR step needs the matrix's CSR arrays (built without them)");
     int32_t *queue = (!spmm && S->opt.queue && S->opt.kernel == DRTS_KERNEL_CSR)
                          ? (inst ? queue_override : S->queue.as<int32_t>())
                          : nullptr;
@@ -897,7 +910,18 @@ const char *drts_last_error(void) { return g_error.c_str(); }
 
 namespace drts {
 
-int build_matrix_from_model(Model &&model, const drts_device_t *dev, drts_matrix_t **out)
+int64_t matrix_device_bytes(const drts_matrix_t *A) { return A->m.bytes() + A->m.table_bytes(); }
+
+int solver_set_stream(drts_solver_t *S, hipStream_t stream)
+{
+    DRTS_HIP(hipStreamSynchronize(S->dev.stream));
+    drop_graph(S);
+    S->dev.stream = stream;
+    S->dev.hooks.stream = (void *)stream;
+    return DRTS_OK;
+}
+
+int build_matrix_from_model(Model &&model, const drts_device_t *dev, drts_matrix_t **out, bool with_csr)
 {
     if (!out) return set_error(DRTS_E_INVALID, "out is NULL");
     *out = nullptr;
@@ -907,7 +931,7 @@ int build_matrix_from_model(Model &&model, const drts_device_t *dev, drts_matrix
     int rc;
     try {
         A->m.model = std::move(model);
-        rc = assemble_on_device(&A->m);
+        rc = assemble_on_device(&A->m, with_csr);
     } catch (const std::bad_alloc &) {
         rc = set_error(DRTS_E_NOMEM, "host allocation failed during assembly");
     } catch (...) {
@@ -992,6 +1016,7 @@ int drts_matrix_export_rows(const drts_matrix_t *A, int64_t row0, int64_t n_rows
 {
     if (!A || !row_ptr) return set_error(DRTS_E_INVALID, "matrix or row_ptr is NULL");
     const Matrix &M = A->m;
+    if (!M.has_csr) return set_error(DRTS_E_STATE, "the matrix was built without its CSR arrays");
     if (row0 < 0 || n_rows < 0 || row0 + n_rows > M.model.n_rows) return set_error(DRTS_E_RANGE, "rows out of range");
     hipStream_t s = M.dev.stream;
     if (M.rp64) {
@@ -1428,6 +1453,20 @@ void drts_solver_destroy(drts_solver_t *S)
 
 namespace {
 
+// Every instance's step limit back to its solver's max_steps (stream-ordered,
+// after the batch's launches).
+__global__ void restore_t_end(const StepInst *insts, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) *const_cast<int64_t *>(insts[i].t_end) = insts[i].max_steps;
+}
+
+void release_spent(drts_batch *B)
+{
+    for (hipGraphExec_t g : B->spent) (void)hipGraphExecDestroy(g);
+    B->spent.clear();
+}
+
 int batch_launch(drts_batch *B, int64_t n_work, int n_inst, int rows_per_tile, hipStream_t stream,
                  int64_t n_xwork = 0)
 {
@@ -1508,6 +1547,8 @@ int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const
             return set_error(DRTS_E_INVALID, "solver %d: matrix-free tiles of another shape", i);
         if (mode == 0 && S->opt.rows_per_tile != rpt)
             return set_error(DRTS_E_INVALID, "solver %d: every batch member needs the same rows_per_tile", i);
+        if (mode == 0 && !S->A->m.has_csr)
+            return set_error(DRTS_E_STATE, "solver %d: the CSR step needs the matrix's CSR arrays", i);
         if (mode == 0 && long_rows(S->A->m) != long_rows(B->solvers[0]->A->m))
             return set_error(DRTS_E_INVALID, "solver %d: a batch takes either long-row (Lebedev) members or "
                                              "lattice members", i);
@@ -1554,6 +1595,7 @@ int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const
         if ((rc = upload_vec(dev, B->xwork_dev, xwork))) return rc;
     }
     DRTS_HIP(hipStreamSynchronize(s));
+    release_spent(B);   // the previous run's graphs are done
 
     // launches: while step < n of the j-th longest, the first j+1 solvers are active
     const int K = 25;
@@ -1580,10 +1622,8 @@ int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const
             if (g) (void)hipGraphDestroy(g);
             for (; rc == DRTS_OK && len >= K; len -= K, step += K)
                 if (hipGraphLaunch(ge, s) != hipSuccess) rc = set_error(DRTS_E_HIP, "graph launch failed");
-            if (ge) {
-                (void)hipStreamSynchronize(s);
-                (void)hipGraphExecDestroy(ge);
-            }
+            // destroyed once the stream has run it (next run, or the batch's destruction)
+            if (ge) B->spent.push_back(ge);
             if (rc) break;
         }
         for (; len > 0; --len, ++step)
@@ -1591,18 +1631,35 @@ int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const
         if (rc) break;
     }
     if (cap) (void)hipStreamDestroy(cap);
-    if (rc) return rc;
+    if (rc) {
+        // some steps ran: bring every member back to a consistent state (its
+        // own step limit, its step count as the device has it)
+        (void)hipStreamSynchronize(s);
+        release_spent(B);
+        for (int j = 0; j < P; ++j) {
+            drts_solver *S = B->solvers[(size_t)order[(size_t)j]];
+            int64_t tt = S->t_host;
+            (void)hipMemcpy(S->t_end.ptr, &S->max_steps, sizeof(int64_t), hipMemcpyHostToDevice);
+            if (hipMemcpy(&tt, S->ctl_t.ptr, sizeof(int64_t), hipMemcpyDeviceToHost) == hipSuccess) S->t_host = tt;
+        }
+        return rc;
+    }
     for (int j = 0; j < P; ++j) {
         drts_solver *S = B->solvers[(size_t)order[(size_t)j]];
         S->t_host += n_steps[order[(size_t)j]];
     }
-    // restore the solvers' own step limit once the batch's work is done
-    DRTS_HIP(hipStreamSynchronize(s));
+    // the solvers' own step limits come back after the batch's launches, in
+    // stream order: the call returns without waiting for the steps
+    hipLaunchKernelGGL(restore_t_end, dim3((unsigned)((P + 63) / 64)), dim3(64), 0, s, B->inst_dev.as<StepInst>(), P);
+    DRTS_HIP(hipGetLastError());
+    // work a member's own stream takes later (readout, its own steps) waits for
+    // the batch
+    if (!B->done) DRTS_HIP(hipEventCreateWithFlags(&B->done, hipEventDisableTiming));
+    DRTS_HIP(hipEventRecord(B->done, s));
     for (int j = 0; j < P; ++j) {
         drts_solver *S = B->solvers[(size_t)order[(size_t)j]];
-        DRTS_HIP(hipMemcpyAsync(S->t_end.ptr, &S->max_steps, sizeof(int64_t), hipMemcpyHostToDevice, s));
+        if (S->dev.stream != s) DRTS_HIP(hipStreamWaitEvent(S->dev.stream, B->done, 0));
     }
-    DRTS_HIP(hipStreamSynchronize(s));
     return DRTS_OK;
 }
 
@@ -1750,7 +1807,9 @@ int drts_batch_autotune(drts_batch_t *B, drts_options_t *chosen)
 void drts_batch_destroy(drts_batch_t *B)
 {
     if (!B) return;
-    if (B->dev.stream) (void)hipStreamSynchronize(B->dev.stream);
+    (void)hipStreamSynchronize(B->dev.stream);
+    release_spent(B);
+    if (B->done) (void)hipEventDestroy(B->done);
     delete B;
 }
 

@@ -284,7 +284,7 @@ int fill_values(Matrix *A, const AsmArgs &args, const LebArgs *leb, Buffer &rp64
 
 }  // namespace
 
-int assemble_on_device(Matrix *A)
+int assemble_on_device(Matrix *A, bool with_csr)
 {
     Device &dev = A->dev;
     Model &M = A->model;
@@ -381,6 +381,10 @@ int assemble_on_device(Matrix *A)
     counts.reset();
     A->nnz = nnz;
     A->rp64 = nnz > (int64_t)INT32_MAX - 8;
+    if (!with_csr) {
+        A->has_csr = false;
+        return DRTS_OK;
+    }
     if (A->rp64) {
         A->row_ptr.dev = rp64.dev;
         A->row_ptr.ptr = rp64.ptr;

@@ -111,14 +111,18 @@ struct Matrix {
     Model model;
     int64_t nnz = 0;
     bool rp64 = false;       // int64 row pointers (nnz >= 2^31)
+    bool has_csr = true;     // false: only the tables the matrix-free steps read were built
     Buffer row_ptr, col, val;
     Buffer mat_of_voxel, absorb, index, blocks64, blocks32;
     Buffer irr_row, irr_vox, irr_dir, irr_f, irr_bits, escape_state;
     Buffer pair_ptr, pair_key, pair_w, arr_ptr, arr_key, arr_w;   // Lebedev weights
-    int64_t bytes() const;
+    int64_t bytes() const;         // the CSR arrays
+    int64_t table_bytes() const;   // everything else on the device (tables of the model)
 };
 
-int assemble_on_device(Matrix *A);
+// with_csr = false builds only the tables the matrix-free steps read (and
+// counts the entries the CSR would hold).
+int assemble_on_device(Matrix *A, bool with_csr = true);
 
 // ---- windowed measurement (Eq. 27 over several steps) --------------------------
 struct WindowArgs {
@@ -134,6 +138,11 @@ hipError_t launch_detector_window(const WindowArgs &a, hipStream_t stream);
 
 // drts_build_matrix for a medium whose host model is already built (the
 // model is moved into the matrix).
-int build_matrix_from_model(Model &&model, const drts_device_t *dev, drts_matrix_t **out);
+int build_matrix_from_model(Model &&model, const drts_device_t *dev, drts_matrix_t **out, bool with_csr = true);
+// device bytes a matrix holds (CSR arrays and tables)
+int64_t matrix_device_bytes(const drts_matrix_t *A);
+// moves a solver's work to another stream (after finishing what its current
+// stream holds)
+int solver_set_stream(drts_solver_t *S, hipStream_t stream);
 
 }  // namespace drts

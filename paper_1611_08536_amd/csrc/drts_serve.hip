@@ -41,7 +41,8 @@ struct Request {
     std::vector<uint8_t> det_esc;
     std::vector<double> det_F;
     const drts_source_table_t *src = nullptr;
-    int64_t est_bytes = 0;   // footprint bound before assembly
+    int64_t est_base = 0;    // footprint bound before assembly, without the CSR arrays
+    int64_t est_csr = 0;     // bound of the CSR arrays (built for the CSR step only)
     int64_t bytes = 0;       // footprint held while admitted
     double work = 0;         // entries of [A; L] (bound) x steps: the shortest-first key
     Model model;             // host model, built once at submission, moved into the matrix
@@ -78,6 +79,7 @@ int64_t solver_bytes(int64_t n_rows, int64_t n_steps, int32_t n_det, int32_t n_s
 
 struct drts_server {
     drts_device_t dev{};
+    hipStream_t build_stream = nullptr;   // admissions assemble here while a quantum runs
     int64_t budget = 0, used = 0;
     int32_t quantum = 0, max_active = 0, max_skips = 0, policy = 0;
     int32_t kernel = DRTS_KERNEL_CSR;   // the step of requests admitted from now on
@@ -97,6 +99,10 @@ struct drts_server {
     {
         if (batch) drts_batch_destroy(batch);
         if (mf_batch) drts_batch_destroy(mf_batch);
+        if (build_stream) {
+            (void)hipStreamSynchronize(build_stream);
+            (void)hipStreamDestroy(build_stream);
+        }
     }
 };
 
@@ -133,29 +139,51 @@ int copy_request(Request &q, const drts_medium_t *m, const drts_detectors_t *det
     return DRTS_OK;
 }
 
-// Upper bound of the request's device footprint, from the medium alone: a row
-// holds at most 26 entries per move group (the plain move and each irregular
-// move), every entry 8 bytes (FP32 value, int32 column).
-int estimate_bytes(Request &q)
+// Upper bound of the request's device footprint, from the medium alone.  The
+// CSR arrays: a row holds at most 26 entries per move group (the plain move
+// and each irregular move), every entry 8 bytes (FP32 value, int32 column),
+// plus the row pointers.  The tables every step reads or the assembly needs:
+// the material map, the direction blocks (FP64 and FP32), the irregular-move
+// and escape lists with the row bitmap, and the matrix-free solver's row lists
+// (about 32 bytes per irregular or escape row, one bit per row).
+int estimate_bytes(Request &q, int32_t kernel = DRTS_KERNEL_CSR)
 {
     Model &M = q.model;
     int rc = build_model(&q.med, &M);
     if (rc) return rc;
-    const int64_t nnz_ub = (int64_t)kDirs * (M.n_rows + (int64_t)M.irr_row.size());
-    const int64_t mat = 8 * (nnz_ub + 4) + 8 * (M.n_rows + 1) + M.n_vox + (1 << 20);
+    const int64_t n_irr = (int64_t)M.irr_row.size();
+    const int64_t nnz_ub = (int64_t)kDirs * (M.n_rows + n_irr);
+    q.est_csr = 8 * (nnz_ub + 4) + 8 * (M.n_rows + 1);
+    const int64_t tables = M.n_vox + (int64_t)M.mats.size() * kDirs * kDirs * 12 + 28 * n_irr + 8 * M.n_escape +
+                           M.n_states / 8 + 32 * (n_irr + M.n_escape) + M.n_rows / 8 + (1 << 20);
     const int32_t n_src = q.src ? q.src->n_src : 0;
-    q.est_bytes = mat + solver_bytes(M.n_rows, q.n_steps, q.n_det, n_src);
+    q.est_base = tables + solver_bytes(M.n_rows, q.n_steps, q.n_det, n_src);
+    (void)kernel;
     q.work = (double)nnz_ub * (double)q.n_steps;
     return DRTS_OK;
 }
 
+// The footprint bound of a request admitted with `kernel` as its step.
+int64_t bound_for(const Request &q, int32_t kernel)
+{
+    return q.est_base + (kernel == DRTS_KERNEL_CSR ? q.est_csr : 0);
+}
+
+// Assembles an admitted request's matrix (only the tables the matrix-free
+// steps read, when it takes one) and creates its solver, on the server's build
+// stream -- so that admission overlaps a quantum running on the server's
+// stream -- then moves the solver to the server's stream.
 int admit(drts_server *Q, Request &q)
 {
     // the host model built at submission goes into the matrix (rebuilt if an
     // earlier admission attempt consumed it)
     int rc = DRTS_OK;
+    if (!Q->build_stream && hipStreamCreateWithFlags(&Q->build_stream, hipStreamNonBlocking) != hipSuccess)
+        return set_error(DRTS_E_HIP, "creating the build stream failed");
+    drts_device_t bdev = Q->dev;
+    bdev.stream = (void *)Q->build_stream;
     if (q.model.n_states == 0) rc = build_model(&q.med, &q.model);
-    if (!rc) rc = build_matrix_from_model(std::move(q.model), &Q->dev, &q.A);
+    if (!rc) rc = build_matrix_from_model(std::move(q.model), &bdev, &q.A, Q->kernel == DRTS_KERNEL_CSR);
     if (rc) return rc;
     drts_detectors_t det{};
     det.n_det = q.n_det;
@@ -163,7 +191,7 @@ int admit(drts_server *Q, Request &q)
     det.state = q.det_state.data();
     det.escape = q.det_esc.data();
     det.F = q.det_F.data();
-    rc = drts_solver_create(q.A, 1, q.n_det > 0 ? &det : nullptr, q.n_steps, &Q->dev, &q.S);
+    rc = drts_solver_create(q.A, 1, q.n_det > 0 ? &det : nullptr, q.n_steps, &bdev, &q.S);
     if (!rc && Q->kernel != DRTS_KERNEL_CSR) {
         // the matrix-free step with its measured launch shape: 8 tiles per
         // chunk, 16 workgroups per CU
@@ -180,6 +208,7 @@ int admit(drts_server *Q, Request &q)
             rc = drts_solver_set_options(q.S, &o);
         }
     }
+    if (!rc) rc = solver_set_stream(q.S, (hipStream_t)Q->dev.stream);
     if (rc) {
         q.free_device();
         return rc;
@@ -191,11 +220,10 @@ int admit(drts_server *Q, Request &q)
         const bool f64sum = q.kernel == DRTS_KERNEL_STRUCTURED_F64SUM;
         q.batched_mf = q.med.n_mat <= kStructMatLdsHost && (f64sum || q.med.rounding == DRTS_ROUND_NEAREST);
     }
-    int64_t n_states = 0, n_escape = 0, nnz = 0, mbytes = 0;
-    double dt = 0;
-    drts_matrix_info(q.A, &n_states, &n_escape, &nnz, &mbytes, &dt);
+    int64_t n_states = 0, n_escape = 0;
+    drts_matrix_info(q.A, &n_states, &n_escape, nullptr, nullptr, nullptr);
     const int32_t n_src = q.src ? q.src->n_src : 0;
-    q.bytes = mbytes + (n_states + n_escape) + (1 << 20) +
+    q.bytes = matrix_device_bytes(q.A) + 32 * n_escape + (n_states + n_escape) / 8 +
               solver_bytes(n_states + n_escape, q.n_steps, q.n_det, n_src);
     return DRTS_OK;
 }
@@ -264,10 +292,12 @@ int drts_serve_submit(drts_server_t *Q, const drts_medium_t *medium, const drts_
     std::unique_ptr<Request> q;
     int rc;
     int64_t id;
+    int32_t kernel;
     {
         // the id fixes the request's place in submission order
         std::lock_guard<std::mutex> lk(Q->mu);
         id = Q->next_id++;
+        kernel = Q->kernel;
     }
     try {
         // host work (copy, model): outside the lock
@@ -275,15 +305,16 @@ int drts_serve_submit(drts_server_t *Q, const drts_medium_t *medium, const drts_
         q->id = id;
         q->n_steps = n_steps;
         q->src = src;
+        q->kernel = kernel;
         rc = copy_request(*q, medium, det);
-        if (!rc) rc = estimate_bytes(*q);
+        if (!rc) rc = estimate_bytes(*q, kernel);
     } catch (const std::bad_alloc &) {
         return set_error(DRTS_E_NOMEM, "host allocation failed");
     }
     if (rc) return rc;
-    if (q->est_bytes > Q->budget)
+    if (bound_for(*q, kernel) > Q->budget)
         return set_error(DRTS_E_NOMEM, "request needs about %lld bytes, beyond the budget of %lld",
-                         (long long)q->est_bytes, (long long)Q->budget);
+                         (long long)bound_for(*q, kernel), (long long)Q->budget);
     std::lock_guard<std::mutex> lk(Q->mu);
     auto at = Q->waiting.end();
     while (at != Q->waiting.begin() && (*(at - 1))->id > id) --at;
@@ -304,8 +335,8 @@ int drts_serve_footprint(const drts_medium_t *medium, const drts_source_table_t 
         q.n_steps = n_steps;
         q.src = src;
         rc = copy_request(q, medium, det);
-        if (!rc) rc = estimate_bytes(q);
-        if (!rc) *bytes = q.est_bytes;
+        if (!rc) rc = estimate_bytes(q, DRTS_KERNEL_CSR);
+        if (!rc) *bytes = bound_for(q, DRTS_KERNEL_CSR);
     } catch (const std::bad_alloc &) {
         return set_error(DRTS_E_NOMEM, "host allocation failed");
     }
@@ -319,36 +350,45 @@ int drts_serve_tick(drts_server_t *Q, int32_t *n_active, int32_t *n_waiting, int
     std::lock_guard<std::mutex> lk(Q->mu);
     int rc = DRTS_OK;
     int32_t finished = 0;
-    // 1. admission: first fit in arrival order; a request passed over
-    //    max_skips times blocks the ones behind it
-    if (Q->policy == DRTS_SERVE_SHORTEST)
-        // least work first; ties keep arrival order
-        std::stable_sort(Q->waiting.begin(), Q->waiting.end(),
-                         [](const Request *a, const Request *b) { return a->work < b->work; });
-    std::vector<Request *> passed;   // earlier requests that did not fit this tick
-    for (auto it = Q->waiting.begin(); it != Q->waiting.end() && (int)Q->active.size() < Q->max_active;) {
-        Request &q = **it;
-        if (Q->used + q.est_bytes <= Q->budget) {
-            if ((rc = admit(Q, q))) return rc;
-            Q->used += q.bytes;
-            Q->active.push_back(&q);
-            Q->batch_dirty = true;
-            for (Request *p : passed) ++p->skips;
-            it = Q->waiting.erase(it);
-            continue;
+    // admission: first fit in the policy's order; a request passed over
+    // max_skips times blocks the ones behind it
+    auto admission = [&]() -> int {
+        if (Q->policy == DRTS_SERVE_SHORTEST)
+            // least work first; ties keep arrival order
+            std::stable_sort(Q->waiting.begin(), Q->waiting.end(),
+                             [](const Request *a, const Request *b) { return a->work < b->work; });
+        std::vector<Request *> passed;   // earlier requests that did not fit this tick
+        for (auto it = Q->waiting.begin(); it != Q->waiting.end() && (int)Q->active.size() < Q->max_active;) {
+            Request &q = **it;
+            if (Q->used + bound_for(q, Q->kernel) <= Q->budget) {
+                int r = admit(Q, q);
+                if (r) return r;
+                Q->used += q.bytes;
+                Q->active.push_back(&q);
+                Q->batch_dirty = true;
+                for (Request *p : passed) ++p->skips;
+                it = Q->waiting.erase(it);
+                continue;
+            }
+            if (q.skips >= Q->max_skips) break;
+            passed.push_back(&q);
+            ++it;
         }
-        if (q.skips >= Q->max_skips) break;
-        passed.push_back(&q);
-        ++it;
-    }
-    // 2. one quantum for every admitted request: the CSR ones as one batch,
-    //    the matrix-free ones of the batched kind (direction-major tiles) as
-    //    another (one launch per kernel and step each), any other
+        return DRTS_OK;
+    };
+    // 1. with nothing running, admit first; otherwise the admissions below
+    //    assemble on the build stream while this tick's quantum runs
+    const bool admit_first = Q->active.empty();
+    if (admit_first && (rc = admission())) return rc;
+    // 2. one quantum for every request admitted before: the CSR ones as one
+    //    batch, the matrix-free ones of the batched kind (direction-major
+    //    tiles) as another (one launch per kernel and step each), any other
     //    matrix-free one with its own graph-replayed run, all in turn on the
-    //    same stream
-    if (!Q->active.empty()) {
+    //    server's stream; the launches return without waiting for the steps
+    std::vector<Request *> ran = Q->active;
+    if (!ran.empty()) {
         std::vector<Request *> csr, mf, solo;
-        for (Request *q : Q->active) {
+        for (Request *q : ran) {
             if (q->kernel == DRTS_KERNEL_CSR) csr.push_back(q);
             else if (q->batched_mf) mf.push_back(q);
             else solo.push_back(q);
@@ -384,24 +424,29 @@ int drts_serve_tick(drts_server_t *Q, int32_t *n_active, int32_t *n_waiting, int
             if ((rc = drts_run(q->S, q->src, n))) return rc;
             q->done += n;
         }
-        // 3. retirement
-        std::vector<Request *> keep;
-        for (Request *q : Q->active) {
-            if (q->done >= q->n_steps) {
-                if ((rc = retire(Q, *q))) return rc;
-                ++finished;
-                Q->batch_dirty = true;
-            } else {
-                keep.push_back(q);
-            }
+    }
+    // 3. admissions overlapping the quantum (they join the next one)
+    if (!admit_first && (rc = admission())) return rc;
+    if (!ran.empty()) DRTS_HIP(hipStreamSynchronize((hipStream_t)Q->dev.stream));
+    // 4. retirement
+    bool retired = false;
+    std::vector<Request *> keep;
+    for (Request *q : Q->active) {
+        if (q->done >= q->n_steps) {
+            if ((rc = retire(Q, *q))) return rc;
+            ++finished;
+            retired = true;
+        } else {
+            keep.push_back(q);
         }
-        Q->active.swap(keep);
-        if (Q->batch_dirty) {
-            // the batches refer to retired solvers: drop them before anything else runs
-            for (drts_batch_t **b : {&Q->batch, &Q->mf_batch}) {
-                if (*b) drts_batch_destroy(*b);
-                *b = nullptr;
-            }
+    }
+    Q->active.swap(keep);
+    if (retired) {
+        // the batches refer to retired solvers: drop them before anything else runs
+        Q->batch_dirty = true;
+        for (drts_batch_t **b : {&Q->batch, &Q->mf_batch}) {
+            if (*b) drts_batch_destroy(*b);
+            *b = nullptr;
         }
     }
     if (n_active) *n_active = (int32_t)Q->active.size();
