@@ -19,15 +19,20 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+F64SUM_NOTE = ("FP32 values and state, each row summed in FP64 and rounded once: outside the "
+               "FP32-accumulation precision pattern (more accurate than it)")
 STEP_SOURCES = ("paper_1611_08536_amd/csrc/drts_step.hip", "paper_1611_08536_amd/csrc/drts_step.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_spmv_c2_traffic.txt")
 SPMV_KERNEL = "step_spmv<float, int, 256, 256, 0, 2>"
 CALIB_KERNEL = "vectorized_elementwise_kernel"
 CALIB_BYTES = 2 ** 30          # the calibration kernel reads and writes 1 GiB
+GRAPH_STEPS = 50               # steps per hipGraph replay in the timed run
 
 
 def step_source_hash():
@@ -178,13 +183,36 @@ def spmm_vs_plain(torch, steps=20):
            "achieved_GBs": round(nbytes / kern_s / 1e9, 1), "frac": round(nbytes / kern_s / 1e9 / PEAK_HBM_GBS, 4)}
     mf_s = f_ms / max(n_f, 1) * 1e-3
     mf_bytes = 4 * k * A.n_states + 4 * k * A.n_rows + A.n_states // 26
+    out["precision"] = "FP32 values, state and accumulation (CSR SpMM)"
     out["matrix_free"] = {"kernel": "step_struct_mm<2> + step_struct_mm_x<2> (FP64 row sums)",
+                          "precision": F64SUM_NOTE,
                           "ms_per_step": round(t_mf / steps * 1e3, 3), "kernel_ms": round(mf_s * 1e3, 3),
                           "solve_steps_per_s": round(k * steps / t_mf, 1),
                           "speedup_vs_plain": round((k * steps / t_mf) / (steps / t_1), 2),
                           "algorithmic_bytes": mf_bytes, "achieved_GBs": round(mf_bytes / mf_s / 1e9, 1),
                           "frac": round(mf_bytes / mf_s / 1e9 / PEAK_HBM_GBS, 4)}
     A.close()
+    # the exact matrix-free step (FP32 accumulation, equal to the CSR step bit
+    # for bit) takes nearest-rounded values: the same slab assembled so
+    torch.cuda.empty_cache()
+    An = drts.Matrix(wl.medium, wl.value_type, "nearest", wl.n_ref)
+    Sn = drts.Solver(An, wl.n_rhs, wl.detectors, max_steps=steps + 4)
+    Sn.set_options(kernel=drts.KERNEL_STRUCTURED, grid=16 * cus)
+    tabn = solve.source_table(An, wl)
+    Sn.run(tabn, 2)
+    Sn.profile(True)
+    t_ex = _timed(lambda: Sn.run(tabn, steps), torch)
+    n_x, x_ms = Sn.profile_stats()
+    Sn.close()
+    An.close()
+    ex_s = x_ms / max(n_x, 1) * 1e-3
+    out["matrix_free_exact"] = {"kernel": "step_struct_mm<1> + step_struct_mm_x<1> (nearest-rounded values)",
+                                "precision": "FP32 values, state and accumulation (equal to the CSR step)",
+                                "ms_per_step": round(t_ex / steps * 1e3, 3), "kernel_ms": round(ex_s * 1e3, 3),
+                                "solve_steps_per_s": round(k * steps / t_ex, 1),
+                                "speedup_vs_plain": round((k * steps / t_ex) / (steps / t_1), 2),
+                                "achieved_GBs": round(mf_bytes / ex_s / 1e9, 1),
+                                "frac": round(mf_bytes / ex_s / 1e9 / PEAK_HBM_GBS, 4)}
     return out
 
 
@@ -235,6 +263,23 @@ def batch_vs_sequential(torch, steps=40):
         S.close()
     for m in mats:
         m.close()
+    # the exact matrix-free step (FP32 accumulation) on the same media with
+    # nearest-rounded values, one batch
+    _log("C4: exact matrix-free batch (nearest-rounded values)")
+    torch.cuda.empty_cache()
+    mats = [drts.Matrix(w.medium, w.value_type, "nearest", w.n_ref) for w in wls]
+    solvers = [drts.Solver(m, 1, [], max_steps=2 * steps + 4) for m in mats]
+    tabs = [solve.source_table(m, w) for m, w in zip(mats, wls)]
+    for S in solvers:
+        S.set_options(kernel=drts.KERNEL_STRUCTURED, tiles_per_chunk=8)
+    B = drts.Batch(solvers)
+    B.run(tabs, [2] * len(solvers))
+    t_xb = _timed(lambda: B.run(tabs, [steps] * len(solvers)), torch)
+    B.close()
+    for S in solvers:
+        S.close()
+    for m in mats:
+        m.close()
     n = len(wls)
     return {"workload": "C4: %d media, %d nnz in all, %d of the 500 steps timed" % (n, nnz, steps),
             "instance_steps_per_s": round(n * steps / t_b, 1),
@@ -246,49 +291,135 @@ def batch_vs_sequential(torch, steps=40):
             "batch_shape": "autotuned in %.1f s: %d rows per tile, %d tiles per chunk, variant %d, %d workgroups" %
                            (t_tune, chosen["rows_per_tile"], chosen["tiles_per_chunk"], chosen["variant"],
                             chosen["grid"]),
+            "precision": "FP32 values, state and accumulation (CSR)",
             "matrix_free": {"kernel": "step_struct_dm<2, true> + step_struct_x<float, 2, true> (FP64 row sums)",
+                            "precision": F64SUM_NOTE,
                             "instance_steps_per_s": round(n * steps / t_mb, 1),
                             "sequential_instance_steps_per_s": round(n * steps / t_ms, 1),
                             "speedup_vs_sequential": round(t_ms / t_mb, 2),
-                            "speedup_vs_csr_sequential": round(t_s / t_mb, 2),
-                            "GNNZ_equiv_per_s": round(nnz * steps / t_mb / 1e9, 1)}}
+                            "cross_kernel_speedup_vs_csr_sequential": round(t_s / t_mb, 2),
+                            "GNNZ_equiv_per_s": round(nnz * steps / t_mb / 1e9, 1)},
+            "matrix_free_exact": {"kernel": "step_struct_dm<1, true> + step_struct_x<float, 0, true> "
+                                            "(nearest-rounded values)",
+                                  "precision": "FP32 values, state and accumulation (equal to the CSR step)",
+                                  "instance_steps_per_s": round(n * steps / t_xb, 1),
+                                  "cross_kernel_speedup_vs_csr_sequential": round(t_s / t_xb, 2),
+                                  "GNNZ_equiv_per_s": round(nnz * steps / t_xb / 1e9, 1)}}
 
 
-def serving_vs_fifo(torch, n_req=32, step_scale=0.1, csr_server=True):
+def serving_vs_fifo(torch, n_req=32, step_scale=0.1, kinds=("csr", "mf_f64sum", "mf_exact")):
     """C5 sample: the first n_req requests of the Poisson (200/s) stream of
     sphere-inclusion media (edges 32..128), step counts scaled by step_scale,
-    through the serving loop and through sequential FIFO plain runs."""
+    through the serving loop and through sequential FIFO runs of the same
+    step, for each step kind: the CSR step, the matrix-free step with FP64 row
+    sums, and the exact matrix-free step (FP32 accumulation) on
+    nearest-rounded requests."""
+    import copy
     import workloads as W
-    from paper_1611_08536_amd import serve
+    from paper_1611_08536_amd import drts, serve
     lo, hi = int(500 * step_scale), int(5000 * step_scale)
     reqs = W.c5(n_req=n_req, steps=(lo, hi))
-    torch.cuda.empty_cache()
-    budget = serve.footprint_budget(0.7)
-    _log("C5: serving %d requests (budget %.1f GB)" % (n_req, budget / 1e9))
-    s = serve.serve(reqs, budget, quantum=50, max_active=4, policy="shortest") if csr_server else None
-    _log("C5: serving with the matrix-free step")
-    torch.cuda.empty_cache()
-    from paper_1611_08536_amd import drts
-    m = serve.serve(reqs, budget, quantum=50, max_active=4, policy="shortest", kernel=drts.KERNEL_STRUCTURED_F64SUM,
-                    log=None if csr_server else _log)
-    _log("C5: FIFO plain")
-    f = serve.fifo_plain(reqs, log=None if csr_server else _log)
     r = lambda d: {k: round(v, 4) if isinstance(v, float) else v for k, v in d.items()}
     out = {"workload": "C5%s: first %d requests, 200/s Poisson arrivals, edges 32..128, steps %d..%d" %
                        ("" if n_req == 256 and step_scale == 1.0 else " sample", n_req, lo, hi),
-           "server": "least work first, at most 4 admitted, 50 steps per tick, budget 70% of free HBM",
-           "fifo_plain": r(f)}
-    if s is not None:
-        out.update({"served": r(s), "speedup_solves_per_s": round(s["solves_per_s"] / f["solves_per_s"], 2)})
-    out.update({
-            "served_matrix_free": r(m),
-            "matrix_free_speedup_solves_per_s": round(m["solves_per_s"] / f["solves_per_s"], 2)})
+           "server": "least work first, at most 4 admitted, 50 steps per tick, budget 70% of free HBM"}
+    step = {"csr": (drts.KERNEL_CSR, "FP32 values, state and accumulation (CSR)"),
+            "mf_f64sum": (drts.KERNEL_STRUCTURED_F64SUM, F64SUM_NOTE),
+            "mf_exact": (drts.KERNEL_STRUCTURED, "FP32 values, state and accumulation (equal to the CSR step); "
+                                                 "nearest-rounded requests")}
+    fifo_csr = None
+    for kind in kinds:
+        kernel, note = step[kind]
+        rq = reqs
+        if kind == "mf_exact":
+            rq = [copy.copy(q) for q in reqs]
+            for q in rq:
+                q.workload = copy.copy(q.workload)
+                q.workload.rounding = "nearest"
+        torch.cuda.empty_cache()
+        budget = serve.footprint_budget(0.7)
+        _log("C5 %s: serving %d requests (budget %.1f GB)" % (kind, n_req, budget / 1e9))
+        sv = serve.serve(rq, budget, quantum=50, max_active=4, policy="shortest", kernel=kernel,
+                         log=_log if n_req > 64 else None)
+        _log("C5 %s: FIFO runs of the same step" % kind)
+        torch.cuda.empty_cache()
+        ff = serve.fifo_plain(rq, kernel=kernel, log=_log if n_req > 64 else None)
+        out[kind] = {"precision": note, "served": r(sv), "fifo": r(ff),
+                     "speedup_solves_per_s": round(sv["solves_per_s"] / ff["solves_per_s"], 2)}
+        if kind == "csr":
+            fifo_csr = ff
+        elif fifo_csr is not None:
+            out[kind]["cross_kernel_speedup_vs_fifo_csr"] = round(sv["solves_per_s"] / fifo_csr["solves_per_s"], 2)
+    return out
+
+
+def lebedev_step(torch, n=64, steps=20):
+    """The paper's own discretisation: Lebedev-86 directions with the
+    multi-voxel weights of Eq. (18)-(19), a homogeneous n^3 cube (mu_s 10,
+    mu_a 0.01, g 0.9), light path one voxel per step, FP32 values; rows of
+    about 640 entries step with the wave-per-row SpMV."""
+    import workloads as W
+    from paper_1611_08536_amd import drts, solve
+    med = W.homogeneous(n, W.C3_MAT)
+    med.directions = "lebedev86"
+    c = n // 2
+    wl = W.Workload("lebedev", med, [W.point_source(c, c, 0)], [], steps + 4, 1, "f32", "dither", 1.4)
+    torch.cuda.empty_cache()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    A = drts.Matrix(med, "f32", "dither", 1.4)
+    torch.cuda.synchronize()
+    t_asm = time.perf_counter() - t0
+    S = drts.Solver(A, 1, [], max_steps=2 * steps + 4)
+    tab = solve.source_table(A, wl)
+    S.run(tab, 2)
+    t = _timed(lambda: S.run(tab, steps), torch)
+    S.profile(True)
+    S.run(tab, steps)
+    n_l, k_ms = S.profile_stats()
+    S.close()
+    kern_s = k_ms / max(n_l, 1) * 1e-3
+    nbytes = 8 * A.nnz + 8 * (A.n_rows + 1) + 4 * A.n_states + 4 * A.n_rows
+    out = {"workload": "%d^3 homogeneous (10, 0.01, 0.9), Lebedev-86 directions, Eq. 18-19 weights, c dt = h, "
+                       "FP32 CSR" % n,
+           "n_rows": A.n_rows, "nnz": A.nnz, "entries_per_row": round(A.nnz / A.n_rows, 1),
+           "assembly_s": round(t_asm, 3), "ms_per_step": round(t / steps * 1e3, 3),
+           "GNNZ_per_s": round(A.nnz * steps / t / 1e9, 1), "kernel": "step_spmv_long<float, long>",
+           "kernel_ms": round(kern_s * 1e3, 3), "algorithmic_bytes": nbytes,
+           "roofline": {"bound": "hbm", "achieved": round(nbytes / kern_s / 1e9, 1), "peak": PEAK_HBM_GBS,
+                        "unit": "GB/s", "frac": round(nbytes / kern_s / 1e9 / PEAK_HBM_GBS, 4)}}
+    A.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def higher_order_step(torch, n=128, order=4, steps=20):
+    """Several scatterings within one step (Eq. 4): the 128^3 layered medium
+    with direction blocks of scatter order 4 (same sparsity, same kernel)."""
+    import workloads as W
+    from paper_1611_08536_amd import drts, solve
+    wl = W.c2(n=n, n_steps=steps + 4)
+    wl.medium.scatter_order = order
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    A = drts.Matrix(wl.medium, wl.value_type, wl.rounding, wl.n_ref)
+    torch.cuda.synchronize()
+    t_asm = time.perf_counter() - t0
+    S = drts.Solver(A, 1, wl.detectors, max_steps=steps + 4)
+    tab = solve.source_table(A, wl)
+    S.run(tab, 2)
+    t = _timed(lambda: S.run(tab, steps), torch)
+    S.close()
+    out = {"workload": "C2 medium with scatter order %d" % order, "nnz": A.nnz, "assembly_s": round(t_asm, 3),
+           "ms_per_step": round(t / steps * 1e3, 4), "GNNZ_per_s": round(A.nnz * steps / t / 1e9, 1)}
+    A.close()
     return out
 
 
 def structured_step(torch, A, wl, tab, steps=50):
-    """The matrix-free step (FP64 row sums) on the same 128^3 workload."""
-    from paper_1611_08536_amd import drts
+    """The matrix-free step (FP64 row sums) on the same 128^3 workload, and the
+    exact matrix-free step on its nearest-rounded twin."""
+    from paper_1611_08536_amd import drts, solve
     S = drts.Solver(A, 1, wl.detectors, max_steps=steps + 4)
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     S.set_options(kernel=drts.KERNEL_STRUCTURED_F64SUM, tiles_per_chunk=8, grid=16 * cus)
@@ -299,10 +430,30 @@ def structured_step(torch, A, wl, tab, steps=50):
     S.close()
     kern_s = k_ms / max(n_l, 1) * 1e-3
     nbytes = 4 * A.n_states + 4 * A.n_rows + A.n_states // 26
-    return {"kernel": "step_struct_dm<2> + step_struct_x<float,2> (matrix-free, FP64 row sums)",
-            "ms_per_step": round(t / steps * 1e3, 4),
-            "kernel_ms": round(kern_s * 1e3, 4), "GNNZ_equiv_per_s": round(A.nnz / kern_s / 1e9, 1),
-            "algorithmic_bytes": nbytes, "achieved_GBs": round(nbytes / kern_s / 1e9, 1)}
+    out = {"kernel": "step_struct_dm<2> + step_struct_x<float,2> (matrix-free, FP64 row sums)",
+           "precision": F64SUM_NOTE,
+           "ms_per_step": round(t / steps * 1e3, 4),
+           "kernel_ms": round(kern_s * 1e3, 4), "GNNZ_equiv_per_s": round(A.nnz / kern_s / 1e9, 1),
+           "algorithmic_bytes": nbytes, "achieved_GBs": round(nbytes / kern_s / 1e9, 1)}
+    # the exact matrix-free step (FP32 accumulation, equal to the CSR step bit
+    # for bit) on the same medium with nearest-rounded values
+    An = drts.Matrix(wl.medium, wl.value_type, "nearest", wl.n_ref)
+    Sn = drts.Solver(An, 1, wl.detectors, max_steps=steps + 4)
+    Sn.set_options(kernel=drts.KERNEL_STRUCTURED, tiles_per_chunk=8, grid=16 * cus)
+    tabn = solve.source_table(An, wl)
+    Sn.run(tabn, 2)
+    Sn.profile(True)
+    tn = _timed(lambda: Sn.run(tabn, steps), torch)
+    n_x, x_ms = Sn.profile_stats()
+    Sn.close()
+    An.close()
+    ex_s = x_ms / max(n_x, 1) * 1e-3
+    out["exact"] = {"kernel": "step_struct_dm<1> + step_struct_x<float,0> (nearest-rounded values)",
+                    "precision": "FP32 values, state and accumulation (equal to the CSR step)",
+                    "ms_per_step": round(tn / steps * 1e3, 4), "kernel_ms": round(ex_s * 1e3, 4),
+                    "GNNZ_equiv_per_s": round(A.nnz / ex_s / 1e9, 1),
+                    "achieved_GBs": round(nbytes / ex_s / 1e9, 1)}
+    return out
 
 
 def main():
@@ -320,6 +471,8 @@ def main():
                     help="of the extra measurements, run only the 64-rhs steps (for profiling)")
     ap.add_argument("--batch-only", action="store_true",
                     help="of the extra measurements, run only the uneven batch of 256 media (for profiling)")
+    ap.add_argument("--lebedev-only", action="store_true",
+                    help="of the extra measurements, run only the Lebedev-86 step (for profiling)")
     ap.add_argument("--serving-full", action="store_true",
                     help="only the serving loop on all 256 requests of C5 with their full step counts, "
                          "matrix-free server against FIFO plain runs (about 15 minutes)")
@@ -338,24 +491,27 @@ def main():
 
     import torch
     if args.serving_full:
-        print(json.dumps({"serving_full": serving_vs_fifo(torch, n_req=256, step_scale=1.0, csr_server=False)}),
-              flush=True)
+        print(json.dumps({"serving_full": serving_vs_fifo(torch, n_req=256, step_scale=1.0,
+                                                          kinds=("mf_f64sum",))}), flush=True)
         return
     import workloads as W
     from paper_1611_08536_amd import drts, solve
 
     torch.cuda.set_device(0)
-    total = args.warmup + args.steps
+    prof_steps = min(args.steps, 200)
+    total = args.warmup + args.steps + 2 * prof_steps
     wl = W.c2(n=args.n, n_steps=total)
     _log("assembling %d^3 layered medium" % args.n)
     A = drts.Matrix(wl.medium, wl.value_type, wl.rounding, wl.n_ref)
     S = drts.Solver(A, 1, wl.detectors, max_steps=total)
     tab = solve.source_table(A, wl)
+    # what ships: drts_run replaying hipGraphs of GRAPH_STEPS steps, no
+    # per-launch events
+    S.set_options(graph_steps=GRAPH_STEPS)
     S.run(tab, args.warmup)
     torch.cuda.synchronize()
 
-    _log("timing %d steps" % args.steps)
-    S.profile(True)
+    _log("timing %d steps (graph replay)" % args.steps)
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -364,13 +520,32 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     ms_total = e0.elapsed_time(e1)
+    ms_step = ms_total / args.steps
+
+    # the step kernel's own duration: a separate pass with HIP events around
+    # every launch (eager launches on the same stream)
+    _log("kernel timing pass (%d steps)" % prof_steps)
+    S.profile(True)
+    S.run(tab, prof_steps)
     launches, kernel_ms = S.profile_stats()
     S.profile(False)
-    ms_step = ms_total / args.steps
     avg_kernel_ms = kernel_ms / max(launches, 1)
+    # eager launches without events, for comparison with the graph replay
+    S.set_options(graph_steps=0)
+    e0.record(stream)
+    S.run(tab, prof_steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    eager_ms_step = e0.elapsed_time(e1) / prof_steps
 
     r = S.readout(0, total)
     assert (r["tot"][:, 0, 0] > 0).all()
+    # windowed measurement (Eq. 27 over 101 steps) of the run's two detectors
+    taps = np.exp(-0.5 * ((np.arange(101) - 50) / 12.0) ** 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.window(np.stack([taps, taps]), tap0=-50)
+    t_win = time.perf_counter() - t0
 
     nbytes = spmv_bytes(A.nnz, A.n_rows, A.n_states)
     achieved = nbytes / (avg_kernel_ms * 1e-3) / 1e9
@@ -397,13 +572,18 @@ def main():
         "data": "synthetic",
         "config": {"workload": "C2: %d^3 voxels x 26 directions, 3 Fresnel layers, FP32 CSR [A;L], "
                                "Gaussian 100 fs top-face source, 2 detectors" % args.n,
-                   "n_states": A.n_states, "n_rows": A.n_rows, "nnz": A.nnz, "parallelism": "1 GPU"},
+                   "n_states": A.n_states, "n_rows": A.n_rows, "nnz": A.nnz, "parallelism": "1 GPU",
+                   "launch": "drts_run, hipGraph replay of %d steps" % GRAPH_STEPS},
+        "eager_ms_per_step": round(eager_ms_step, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None if traffic is None else round(traffic / 1e9, 3),
                      "kernel": SPMV_KERNEL, "kernel_ms": round(avg_kernel_ms, 4),
+                     "kernel_timing": "HIP events around each of %d eager launches on the launch stream" % launches,
                      "algorithmic_bytes": nbytes, "traffic_unit": "GB per launch"},
+        "windowed_measurement": {"detectors": 2, "steps": total, "taps": 101,
+                                 "call_ms": round(t_win * 1e3, 3)},
     }
-    only = args.struct_only or args.spmm_only or args.batch_only
+    only = args.struct_only or args.spmm_only or args.batch_only or args.lebedev_only
     if not args.no_extras and args.n == 128 and (args.struct_only or not only):
         _log("structured step")
         line["structured"] = structured_step(torch, A, wl, tab)
@@ -417,6 +597,12 @@ def main():
         line["batch"] = batch_vs_sequential(torch)
     if not args.no_extras and not only:
         line["serving"] = serving_vs_fifo(torch)
+    if not args.no_extras and (args.lebedev_only or not only):
+        _log("Lebedev-86 step")
+        line["lebedev86"] = lebedev_step(torch)
+    if not args.no_extras and not only:
+        _log("scatter order 4")
+        line["higher_order"] = higher_order_step(torch)
     if not args.no_cpu:
         _log("CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline()
