@@ -51,10 +51,12 @@ class _Medium(C.Structure):
         ("sphere_c", C.c_double * 3), ("sphere_r", C.c_double),
         ("scatter_order", C.c_int32),
         ("directions", C.c_int32), ("c_dt", C.c_double),
+        ("interface_model", C.c_int32),
     ]
 
 
 DIRECTIONS = {"lattice26": 0, "lebedev86": 1}
+INTERFACE = {"origin": 0, "substep": 1}
 
 
 def _load():
@@ -202,6 +204,7 @@ def _medium_struct(medium):
     st.scatter_order = getattr(medium, "scatter_order", 1)
     st.directions = DIRECTIONS[getattr(medium, "directions", "lattice26")]
     st.c_dt = getattr(medium, "c_dt", 1.0)
+    st.interface_model = INTERFACE[getattr(medium, "interface", "origin")]
     return st, (mat, vmap)
 
 

@@ -260,6 +260,7 @@ typedef struct {
     int32_t scatter_order;       /* scatterings per step the direction block resolves */
     int32_t directions;          /* 0: the 26 lattice directions; 1: Lebedev's 86 */
     double c_dt;                 /* Lebedev: the distance c dt light travels per step, in voxels */
+    int32_t interface_model;     /* 0: the whole step in the source medium; 1: sub-step crossing */
 } or_medium_t;
 
 enum { OR_DIRS_LATTICE = 0, OR_DIRS_LEBEDEV86 = 1 };
@@ -297,6 +298,27 @@ static void or_normal(const or_medium_t *M, int x, int y, int z, const int e[3],
     N[0] = s[0];
     N[1] = s[1];
     N[2] = s[2];
+}
+
+/* Fraction of the centre-to-centre segment from voxel (x,y,z) along e that lies
+ * in the first voxel's medium: 1/2 at a planar layer boundary or a voxel map's
+ * face; on a sphere, where the segment meets the sphere's surface (the root of
+ * |X + s e - c| = r in [0, 1]: leaving the sphere when the first centre lies
+ * inside it, entering otherwise). */
+static double or_crossing_fraction(const or_medium_t *M, int x, int y, int z, const int e[3])
+{
+    if (M->geom != OR_GEOM_SPHERE) return 0.5;
+    double X[3] = {(double)x + 0.5 - M->sphere_c[0], (double)y + 0.5 - M->sphere_c[1], (double)z + 0.5 - M->sphere_c[2]};
+    double a = (double)(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+    double b = 2.0 * ((double)e[0] * X[0] + (double)e[1] * X[1] + (double)e[2] * X[2]);
+    double c = X[0] * X[0] + X[1] * X[1] + X[2] * X[2] - M->sphere_r * M->sphere_r;
+    double disc = b * b - 4.0 * a * c;
+    if (disc < 0.0) disc = 0.0;
+    double q = sqrt(disc);
+    double s = (c <= 0.0) ? (-b + q) / (2.0 * a) : (-b - q) / (2.0 * a);
+    if (s < 0.0) s = 0.0;
+    if (s > 1.0) s = 1.0;
+    return s;
 }
 
 /* ---- assembled matrix ------------------------------------------------------ */
@@ -358,9 +380,24 @@ static void or_move(const or_medium_t *M, const or_csr_t *A, int64_t v, int x, i
     double R, Tr;
     int mr[NDIR], mt[NDIR], nr, nt;
     or_fresnel(m, n1, n2, N, &R, &Tr, mr, &nr, mt, &nt);
+    /* the crossing within the step (Sec. 4.2): with the sub-step model the
+     * transmitted part is absorbed along its path in each medium, and at a
+     * planar interface the reflected part lands one voxel over along the
+     * surface (it meets the surface half way and returns for the other half) */
+    int64_t vr = v;
+    if (M->interface_model == 1) {
+        double f = or_crossing_fraction(M, x, y, z, e);
+        double mua1 = M->mat[4 * M->mat_of_voxel[v] + 1], mua2 = M->mat[4 * M->mat_of_voxel[u] + 1];
+        Tr = Tr * exp(-(mua2 - mua1) * ((1.0 - f) * M->h_mm));
+        if (M->geom == OR_GEOM_LAYERS_Z && e[2] != 0) {
+            int tx = x + e[0], ty = y + e[1];
+            if (tx >= 0 && tx < M->nx && ty >= 0 && ty < M->ny)
+                vr = (int64_t)tx + (int64_t)M->nx * ((int64_t)ty + (int64_t)M->ny * z);
+        }
+    }
     T->count = 0;
     for (int i = 0; i < nr; ++i) {
-        T->row[T->count] = NDIR * v + mr[i];
+        T->row[T->count] = NDIR * vr + mr[i];
         T->f[T->count] = R / (double)nr;
         T->count++;
     }

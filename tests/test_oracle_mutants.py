@@ -77,6 +77,17 @@ MUTANTS = [
     ("leb_generator_value", C_SRC, "0.6943540066026664", "0.6943450066026664"),
     ("leb_step_time_one_voxel", PY_SRC, 'dt = dt_seconds(med.h_mm * getattr(med, "c_dt", 1.0), workload.n_ref)',
      "dt = dt_seconds(med.h_mm, workload.n_ref)"),
+    # crossing within the step (Sec. 4.2): the fraction in the wrong medium,
+    # the absorption difference reversed, the tangential landing dropped, the
+    # sphere's other root
+    ("substep_fraction_swapped", C_SRC, "Tr = Tr * exp(-(mua2 - mua1) * ((1.0 - f) * M->h_mm));",
+     "Tr = Tr * exp(-(mua2 - mua1) * (f * M->h_mm));"),
+    ("substep_absorption_sign", C_SRC, "Tr = Tr * exp(-(mua2 - mua1) * ((1.0 - f) * M->h_mm));",
+     "Tr = Tr * exp(-(mua1 - mua2) * ((1.0 - f) * M->h_mm));"),
+    ("substep_no_tangential_landing", C_SRC,
+     "vr = (int64_t)tx + (int64_t)M->nx * ((int64_t)ty + (int64_t)M->ny * z);", "vr = v;"),
+    ("substep_sphere_root", C_SRC, "double s = (c <= 0.0) ? (-b + q) / (2.0 * a) : (-b - q) / (2.0 * a);",
+     "double s = (c <= 0.0) ? (-b - q) / (2.0 * a) : (-b + q) / (2.0 * a);"),
     # dither key with row and column swapped
     ("dither_key_swapped", C_SRC, "uint64_t key = ((uint64_t)r << 32) ^ (uint64_t)(uint32_t)A->col[j];",
      "uint64_t key = ((uint64_t)(uint32_t)A->col[j] << 32) ^ (uint64_t)r;"),

@@ -831,3 +831,85 @@ def test_outside_sensor_reads_the_delayed_escape_flux(orc):
     assert np.all(se[:gap] == 0)
     assert so[3:].max() > 0
     assert np.allclose(se[gap:], so[:T - gap], rtol=1e-12, atol=1e-300)
+
+
+# ---- crossing an interface within the step (Sec. 4.2) ------------------------------
+
+def test_substep_layers_path_absorption_and_tangential_landing(orc):
+    """Planar interface, mu_s = 0: a population in direction (1, 0, 1) meets
+    the interface half way through the step.  The transmitted part is absorbed
+    over half a step in each medium, exp(-mu_a1 h/2 - mu_a2 h/2) T; the
+    reflected part returns for the other half step along (1, 0, -1) and lands
+    in the voxel one over along the surface, (x + 1, y, z), with R (textbook
+    Fresnel at 45 degrees, the specular direction exact)."""
+    h = 0.1
+    m1, m2 = _mat(0.0, 0.3, 0.5, 1.33), _mat(0.0, 2.0, 0.5, 1.45)
+    med = W.layered(6, [m1, m2])
+    med.interface = "substep"
+    A = orc.Matrix(med).to_scipy().tocsc()
+    x, y, z = 2, 2, 2                      # layer 0 is z < 3
+    v = x + 6 * (y + 6 * z)
+    col = 26 * v + DIR[(1, 0, 1)]
+    ent = dict(zip(A.indices[A.indptr[col]:A.indptr[col + 1]].tolist(), A.data[A.indptr[col]:A.indptr[col + 1]].tolist()))
+    ti = math.pi / 4
+    tt = math.asin(1.33 / 1.45 * math.sin(ti))
+    R = 0.5 * (math.sin(ti - tt) ** 2 / math.sin(ti + tt) ** 2 + math.tan(ti - tt) ** 2 / math.tan(ti + tt) ** 2)
+    a1 = math.exp(-0.3 * h)
+    vr = (x + 1) + 6 * (y + 6 * z)
+    u = (x + 1) + 6 * (y + 6 * (z + 1))
+    assert ent[26 * vr + DIR[(1, 0, -1)]] == pytest.approx(a1 * R, rel=1e-12)
+    assert ent[26 * u + DIR[(1, 0, 1)]] == pytest.approx(math.exp(-0.3 * h / 2 - 2.0 * h / 2) * (1 - R), rel=1e-12)
+    assert len(ent) == 2
+    # normal incidence: no tangential move
+    col = 26 * v + DIR[(0, 0, 1)]
+    rows = A.indices[A.indptr[col]:A.indptr[col + 1]].tolist()
+    assert 26 * v + DIR[(0, 0, -1)] in rows
+
+
+def test_substep_sphere_crossing_point(orc):
+    """Sphere: the crossing lies where the segment between the voxel centres
+    meets the surface.  Centre and radius put it 0.3 of the way along +x from
+    voxel (3,3,3), at normal incidence: the transmitted entry is
+    exp(-0.3 mu_a1 h - 0.7 mu_a2 h) (1 - R0), R0 = ((n1 - n2)/(n1 + n2))^2."""
+    h = 0.1
+    inc, bg = _mat(0.0, 0.5, 0.5, 1.45), _mat(0.0, 0.05, 0.5, 1.33)
+    d = 1.2
+    med = W.sphere_inclusion(7, bg, inc, (3.5 - d, 3.5, 3.5), d + 0.3)
+    med.interface = "substep"
+    v = 3 + 7 * (3 + 7 * 3)
+    u = 4 + 7 * (3 + 7 * 3)
+    assert med.mat_of_voxel.reshape(-1)[v] == 1 and med.mat_of_voxel.reshape(-1)[u] == 0
+    A = orc.Matrix(med).to_scipy().tocsc()
+    col = 26 * v + DIR[(1, 0, 0)]
+    ent = dict(zip(A.indices[A.indptr[col]:A.indptr[col + 1]].tolist(), A.data[A.indptr[col]:A.indptr[col + 1]].tolist()))
+    R0 = ((1.45 - 1.33) / (1.45 + 1.33)) ** 2
+    assert ent[26 * u + DIR[(1, 0, 0)]] == pytest.approx(math.exp(-0.5 * 0.3 * h - 0.05 * 0.7 * h) * (1 - R0),
+                                                         rel=1e-12)
+    assert ent[26 * v + DIR[(-1, 0, 0)]] == pytest.approx(math.exp(-0.5 * h) * R0, rel=1e-12)
+
+
+def test_substep_conserves_without_absorption(orc):
+    """mu_a = 0 with reflecting walls: the sub-step crossing moves photons, it
+    neither creates nor destroys them (columns sum to one, the total stays)."""
+    mats = [_mat(5, 0, 0.8, 1.33), _mat(15, 0, 0.9, 1.45), _mat(10, 0, 0.85, 1.4)]
+    med = W.layered(6, mats, bc="reflect")
+    med.interface = "substep"
+    A = orc.Matrix(med)
+    colsum = np.asarray(A.to_scipy().sum(axis=0)).ravel()
+    assert np.allclose(colsum, 1.0, rtol=0, atol=30 * 1.2e-16)
+    x0 = W.seeded_state(A.n_states, 7)
+    r = A.run(40, x0=x0)
+    assert np.allclose(np.ldexp(r["tot"][:, 0], r["tot_exp"][:, 0]), x0.sum(), rtol=1e-12)
+
+
+def test_substep_equals_origin_model_without_absorption_contrast(orc):
+    """Equal absorption on both sides and normal incidence only (a 1-voxel-wide
+    column along z): the sub-step model changes nothing."""
+    m1, m2 = _mat(5.0, 0.2, 0.8, 1.33), _mat(5.0, 0.2, 0.8, 1.45)
+    med = W.layered(4, [m1, m2])
+    med = W.Medium(1, 1, 4, 0.1, med.materials, med.mat_of_voxel[:, :1, :1].copy(), "layers_z", "vacuum",
+                   layer_z0=med.layer_z0)
+    a = orc.Matrix(med).to_scipy().toarray()
+    med.interface = "substep"
+    b = orc.Matrix(med).to_scipy().toarray()
+    assert np.array_equal(a, b)

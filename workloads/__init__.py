@@ -68,6 +68,7 @@ class Medium:
     scatter_order: int = 1              # scatterings per step the direction block resolves
     directions: str = "lattice26"       # "lattice26" | "lebedev86" (Sec. 3, Eq. (18)-(19))
     c_dt: float = 1.0                   # lebedev86: light path per step, in voxels
+    interface: str = "origin"           # "origin" | "substep": crossing within the step (Sec. 4.2)
 
     @property
     def n_vox(self) -> int:
