@@ -393,13 +393,13 @@ def lebedev_step(torch, n=64, steps=20):
     return out
 
 
-def higher_order_step(torch, n=128, order=4, steps=20):
-    """Several scatterings within one step (Eq. 4): the 128^3 layered medium
-    with direction blocks of scatter order 4 (same sparsity, same kernel)."""
+def medium_variant_step(torch, label, change, n=128, steps=20):
+    """The 128^3 layered medium with one discretisation choice changed (same
+    kernel): its assembly time and step rate."""
     import workloads as W
     from paper_1611_08536_amd import drts, solve
     wl = W.c2(n=n, n_steps=steps + 4)
-    wl.medium.scatter_order = order
+    change(wl.medium)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     A = drts.Matrix(wl.medium, wl.value_type, wl.rounding, wl.n_ref)
@@ -410,7 +410,7 @@ def higher_order_step(torch, n=128, order=4, steps=20):
     S.run(tab, 2)
     t = _timed(lambda: S.run(tab, steps), torch)
     S.close()
-    out = {"workload": "C2 medium with scatter order %d" % order, "nnz": A.nnz, "assembly_s": round(t_asm, 3),
+    out = {"workload": "C2 medium, %s" % label, "nnz": A.nnz, "assembly_s": round(t_asm, 3),
            "ms_per_step": round(t / steps * 1e3, 4), "GNNZ_per_s": round(A.nnz * steps / t / 1e9, 1)}
     A.close()
     return out
@@ -602,7 +602,12 @@ def main():
         line["lebedev86"] = lebedev_step(torch)
     if not args.no_extras and not only:
         _log("scatter order 4")
-        line["higher_order"] = higher_order_step(torch)
+        line["higher_order"] = medium_variant_step(torch, "scatter order 4 (Eq. 4)",
+                                                   lambda m: setattr(m, "scatter_order", 4))
+        _log("interfaces crossed within the step")
+        line["interface_substep"] = medium_variant_step(
+            torch, "interfaces crossed within the step (path absorption, tangential landing; Sec. 4.2)",
+            lambda m: setattr(m, "interface", "substep"))
     if not args.no_cpu:
         _log("CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline()

@@ -134,7 +134,25 @@ typedef struct {
     double c_dt;           /* DRTS_DIRS_LEBEDEV86: the distance light travels
                               per step, in voxels (0 = 1); dt = c_dt h n_ref / c0.
                               Must be 0 or 1 with the lattice directions */
+    int32_t interface_model; /* DRTS_INTERFACE_*: how a move crossing into a
+                              voxel of another refractive index is treated */
 } drts_medium_t;
+
+/* Interface crossings (Sec. 4.2), lattice directions:
+ *   DRTS_INTERFACE_ORIGIN   the whole step uses the source voxel's medium; the
+ *                           reflected part stays in its voxel;
+ *   DRTS_INTERFACE_SUBSTEP  the crossing happens a fraction f of the way
+ *                           between the voxel centres (1/2 at planar layers and
+ *                           voxel faces; where the segment meets the surface
+ *                           for a sphere): the transmitted part is absorbed
+ *                           along its path in each medium,
+ *                           T exp(-mu_a1 f h - mu_a2 (1 - f) h) instead of
+ *                           T exp(-mu_a1 h); at planar layers the reflected
+ *                           part lands one voxel over along the surface,
+ *                           v + (dx, dy, 0) (in v when that voxel lies outside
+ *                           the grid).  Scattering stays at the step's origin. */
+#define DRTS_INTERFACE_ORIGIN 0
+#define DRTS_INTERFACE_SUBSTEP 1
 
 /* Angular partitions (Sec. 3 allows any):
  *   DRTS_DIRS_LATTICE26  the 26 lattice directions above: every population

@@ -206,6 +206,28 @@ void crossing_normal(const drts_geometry_t &g, int x, int y, int z, int d, doubl
     N[2] = s[2];
 }
 
+// Fraction of the centre-to-centre segment from voxel (x,y,z) along lattice
+// direction d lying in the first voxel's medium: 1/2 at a planar layer or a
+// voxel face; for a sphere, where |X + s e - c| = r for s in [0, 1] (leaving
+// the sphere when X lies inside it, entering otherwise).
+double crossing_fraction(const drts_geometry_t &g, int x, int y, int z, int d)
+{
+    if (g.kind != DRTS_GEOM_SPHERE) return 0.5;
+    const int e[3] = {dir_dx(d), dir_dy(d), dir_dz(d)};
+    const double X[3] = {(double)x + 0.5 - g.sphere_c[0], (double)y + 0.5 - g.sphere_c[1],
+                         (double)z + 0.5 - g.sphere_c[2]};
+    const double a = (double)(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+    const double b = 2.0 * ((double)e[0] * X[0] + (double)e[1] * X[1] + (double)e[2] * X[2]);
+    const double c = X[0] * X[0] + X[1] * X[1] + X[2] * X[2] - g.sphere_r * g.sphere_r;
+    double disc = b * b - 4.0 * a * c;
+    if (disc < 0.0) disc = 0.0;
+    const double q = std::sqrt(disc);
+    double s = (c <= 0.0) ? (-b + q) / (2.0 * a) : (-b - q) / (2.0 * a);
+    if (s < 0.0) s = 0.0;
+    if (s > 1.0) s = 1.0;
+    return s;
+}
+
 struct IrrMove {
     int64_t row, vox;
     int32_t dir;
@@ -479,6 +501,8 @@ int build_model(const drts_medium_t *m, Model *M)
     if (!(m->n_ref > 0.0)) return set_error(DRTS_E_INVALID, "n_ref must be positive");
     if (m->scatter_order < 0 || m->scatter_order > 16)
         return set_error(DRTS_E_INVALID, "scatter_order must be in 0..16");
+    if (m->interface_model != DRTS_INTERFACE_ORIGIN && m->interface_model != DRTS_INTERFACE_SUBSTEP)
+        return set_error(DRTS_E_INVALID, "unknown interface model %d", m->interface_model);
     for (int q = 0; q < m->n_mat; ++q) {
         const drts_material_t &mt = m->mat[q];
         if (!(mt.mu_s >= 0.0) || !(mt.mu_a >= 0.0) || !(mt.g > -1.0 && mt.g < 1.0) || !(mt.n > 0.0) ||
@@ -584,10 +608,25 @@ int build_model(const drts_medium_t *m, Model *M)
                     double N[3];
                     crossing_normal(m->geom, x, y, z, d, N);
                     const Split sp = fresnel_split(d, n1, n2, N);
+                    double T = sp.T;
+                    int64_t vr = v;   // where the reflected part lands
+                    if (m->interface_model == DRTS_INTERFACE_SUBSTEP) {
+                        // the transmitted part is absorbed along its path in
+                        // each medium; at a planar interface the reflected part
+                        // lands one voxel over along the surface
+                        const double f = crossing_fraction(m->geom, x, y, z, d);
+                        const double mua1 = m->mat[M->mat_of_voxel[v]].mu_a, mua2 = m->mat[M->mat_of_voxel[u]].mu_a;
+                        T = T * std::exp(-(mua2 - mua1) * ((1.0 - f) * g.h_mm));
+                        if (m->geom.kind == DRTS_GEOM_LAYERS_Z && dir_dz(d) != 0) {
+                            const int rx = x + dir_dx(d), ry = y + dir_dy(d);
+                            if (rx >= 0 && rx < nx && ry >= 0 && ry < ny)
+                                vr = rx + (int64_t)nx * (ry + (int64_t)ny * z);
+                        }
+                    }
                     for (int i = 0; i < sp.n_refl; ++i)
-                        irr.push_back({kDirs * v + sp.m_refl[i], v, d, sp.R / (double)sp.n_refl});
+                        irr.push_back({kDirs * vr + sp.m_refl[i], v, d, sp.R / (double)sp.n_refl});
                     for (int i = 0; i < sp.n_trans; ++i)
-                        irr.push_back({kDirs * u + sp.m_trans[i], v, d, sp.T / (double)sp.n_trans});
+                        irr.push_back({kDirs * u + sp.m_trans[i], v, d, T / (double)sp.n_trans});
                 }
             }
     M->n_escape = (int64_t)M->escape_state.size();

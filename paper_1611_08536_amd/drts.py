@@ -20,6 +20,7 @@ F64, F32 = 0, 1
 ROUND_NEAREST, ROUND_DITHER = 0, 1
 GEOM = {"voxels": 0, "homog": 0, "layers_z": 1, "sphere": 2}
 DIRECTIONS = {"lattice26": 0, "lebedev86": 1}
+INTERFACE = {"origin": 0, "substep": 1}
 BC = {"vacuum": 0, "reflect": 1}
 KERNEL_CSR, KERNEL_STRUCTURED, KERNEL_STRUCTURED_F64SUM = 0, 1, 2
 SERVE_ARRIVAL, SERVE_SHORTEST = 0, 1
@@ -72,7 +73,7 @@ class MediumT(C.Structure):
     _fields_ = [("grid", Grid), ("n_mat", i32), ("mat", C.POINTER(MaterialT)),
                 ("mat_of_voxel", C.POINTER(C.c_uint8)), ("geom", Geometry), ("bc", i32),
                 ("value_type", i32), ("rounding", i32), ("n_ref", dbl), ("scatter_order", i32),
-                ("directions", i32), ("c_dt", dbl)]
+                ("directions", i32), ("c_dt", dbl), ("interface_model", i32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(P, P, C.c_size_t, P)
@@ -270,6 +271,7 @@ def _medium_struct(medium, value_type="f32", rounding="dither", n_ref=None, use_
     m.scatter_order = getattr(medium, "scatter_order", 1)
     m.directions = DIRECTIONS[getattr(medium, "directions", "lattice26")]
     m.c_dt = getattr(medium, "c_dt", 1.0)
+    m.interface_model = INTERFACE[getattr(medium, "interface", "origin")]
     return m, (mats, vmap, z0)
 
 
