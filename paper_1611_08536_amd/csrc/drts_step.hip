@@ -722,14 +722,17 @@ __global__ void __launch_bounds__(NT, (LAY == 2 && sizeof(VT) == 4 && sizeof(IT)
 // weights of Lebedev media give): one wave per row while summing
 //
 // A workgroup takes a tile of R rows.  Each wave sums every fourth row of the
-// tile: lane l multiplies entries lo + l, lo + l + 64, ... (four loads in
-// flight per lane, each a coalesced 256-byte stream of the wave) and adds them
+// tile: lane l multiplies entries lo + l, lo + l + 64, ... -- the row's
+// columns and values are requested at once (up to 768 entries per pass, 12
+// loads in flight per lane and array), then all the gathers -- and adds them
 // in that order; a butterfly then adds the 64 lane sums in a fixed order.
 // The tile's sums go to LDS and the epilogue (rescale, sources, y store, FP64
 // totals and detectors, chunk partials) is the one of the tile kernels, a
 // thread per row.  Results are reproducible run to run; they are not the
 // tile kernels' sequential row sums bit for bit.
 // ---------------------------------------------------------------------------
+constexpr int kLongJ = 12;   // entries per lane requested at once (768 per wave)
+
 template <typename VT, typename IT>
 __global__ void __launch_bounds__(kNT) step_spmv_long(const StepInst *__restrict__ insts,
                                                        const WorkItem *__restrict__ work, int64_t n_work,
@@ -788,20 +791,27 @@ __global__ void __launch_bounds__(kNT) step_spmv_long(const StepInst *__restrict
         for (int j = 0; j < ntc; ++j) {
             const int64_t r0 = (tile0 + j) * R;
             const int nr = (int)min((int64_t)R, n_rows - r0);
-            // row sums, a wave per row
+            // row sums, a wave per row: all of a row's columns and values are
+            // requested at once (clamped into the row, so every load is in
+            // bounds), then all its gathers, then the products in entry order
             for (int rr = wave; rr < nr; rr += NW) {
                 const IT lo = rp[r0 + rr], hi = rp[r0 + rr + 1];
                 VT a = 0;
-                for (IT k = lo + lane; k < hi; k += 256) {
-                    VT p[4];
+                for (IT base = lo; base < hi; base += 64 * kLongJ) {
+                    int32_t c[kLongJ];
+                    VT v[kLongJ], xv[kLongJ];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const IT kk = k + 64 * u;
-                        p[u] = 0;
-                        if (kk < hi) p[u] = __builtin_nontemporal_load(val + kk) * x[__builtin_nontemporal_load(col + kk)];
+                    for (int u = 0; u < kLongJ; ++u) {
+                        const IT kk = base + lane + 64 * u;
+                        const IT kc = kk < hi ? kk : hi - 1;
+                        c[u] = __builtin_nontemporal_load(col + kc);
+                        v[u] = __builtin_nontemporal_load(val + kc);
                     }
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) a += p[u];
+                    for (int u = 0; u < kLongJ; ++u) xv[u] = x[c[u]];
+#pragma unroll
+                    for (int u = 0; u < kLongJ; ++u)
+                        if (base + lane + 64 * u < hi) a += v[u] * xv[u];
                 }
 #pragma unroll
                 for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
