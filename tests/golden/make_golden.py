@@ -11,7 +11,19 @@ Outputs, per workload, under tests/golden/:
   <name>_run.npz    the FP64 series of the full run (totals, detectors, with
                     exponents) and sampled entries of the final state.
 
-Usage: python tests/golden/make_golden.py c2 [--steps N]
+  c3_run.npz        the 96^3 slab with 64 right-hand sides: right-hand
+                    sides 0, 31 and 63 over all 1000 steps (series, sampled
+                    final state, its L1 norm), each also under FP64
+                    arithmetic on the FP32-rounded matrix (the same-matrix
+                    oracle, which isolates the kernels' arithmetic);
+  c4_run.npz        the first 16 of the 256 uneven-batch media over all 500
+                    steps (series), also on the same-matrix oracle;
+  c5_run.npz        the 8 smallest requests of the serving stream (sphere
+                    inclusions with Fresnel interfaces and total internal
+                    reflection) over their full step counts (series), also on
+                    the same-matrix oracle.
+
+Usage: python tests/golden/make_golden.py c2|c1|c3|c4|c5 [--steps N]
 """
 from __future__ import annotations
 
@@ -95,13 +107,101 @@ def make(name, wl, steps, out_dir):
     print("%s: run of %d steps done %.1f s" % (name, steps, time.time() - t0), flush=True)
 
 
+def _series(r, prefix, out):
+    for k in ("tot", "tot_exp", "det", "det_exp"):
+        out[prefix + k] = r[k]
+
+
+C3_RHS = (0, 31, 63)
+C3_STATE_SAMPLES = 4000
+
+
+def make_c3(out_dir, steps=None):
+    t0 = time.time()
+    wl = W.c3()
+    steps = steps or wl.n_steps
+    A = oracle.Matrix(wl.medium)
+    vals = A.round_f32(wl.rounding)
+    print("c3: assembled %d rows, %d nnz in %.1f s" % (A.n_rows, A.nnz, time.time() - t0), flush=True)
+    out = {"steps": steps, "rhs": np.array(C3_RHS)}
+    rng = np.random.default_rng([W.SEED, 33])
+    for k in C3_RHS:
+        r = oracle.run_workload(A, wl, rhs=k, n_steps=steps)
+        _series(r, "r%d_" % k, out)
+        st = rng.integers(0, A.n_states, size=C3_STATE_SAMPLES)
+        top = np.argsort(r["x"])[-200:]
+        idx = np.unique(np.concatenate([st, top]))
+        out["r%d_x_idx" % k] = idx
+        out["r%d_x_val" % k] = r["x"][idx]
+        out["r%d_x_exp" % k] = r["x_exp"]
+        out["r%d_x_l1" % k] = np.abs(r["x"]).sum()
+        s = oracle.run_workload(A, wl, rhs=k, n_steps=steps, vals32=vals)
+        _series(s, "r%d_same_" % k, out)
+        out["r%d_same_x_val" % k] = s["x"][idx]
+        out["r%d_same_x_exp" % k] = s["x_exp"]
+        print("c3: rhs %d done %.1f s" % (k, time.time() - t0), flush=True)
+    np.savez_compressed(os.path.join(out_dir, "c3_run.npz"), **out)
+
+
+C4_MEMBERS = 16
+
+
+def make_c4(out_dir, steps=None):
+    t0 = time.time()
+    wls = W.c4()[:C4_MEMBERS]
+    steps = steps or wls[0].n_steps
+    out = {"steps": steps, "members": np.arange(C4_MEMBERS)}
+    for i, wl in enumerate(wls):
+        A = oracle.Matrix(wl.medium)
+        vals = A.round_f32(wl.rounding)
+        _series(oracle.run_workload(A, wl, n_steps=steps), "m%d_" % i, out)
+        _series(oracle.run_workload(A, wl, n_steps=steps, vals32=vals), "m%d_same_" % i, out)
+        A.close()
+        print("c4: member %d (edge %d) done %.1f s" % (i, wl.medium.nx, time.time() - t0), flush=True)
+    np.savez_compressed(os.path.join(out_dir, "c4_run.npz"), **out)
+
+
+C5_REQUESTS = 8
+
+
+def c5_smallest(reqs):
+    """Indices of the C5_REQUESTS smallest requests (grid edge, then arrival)."""
+    order = sorted(range(len(reqs)), key=lambda i: (reqs[i].workload.medium.nx, i))
+    return order[:C5_REQUESTS]
+
+
+def make_c5(out_dir):
+    t0 = time.time()
+    reqs = W.c5()
+    pick = c5_smallest(reqs)
+    out = {"requests": np.array(pick)}
+    for i in pick:
+        wl = reqs[i].workload
+        A = oracle.Matrix(wl.medium)
+        vals = A.round_f32(wl.rounding)
+        _series(oracle.run_workload(A, wl), "q%d_" % i, out)
+        _series(oracle.run_workload(A, wl, vals32=vals), "q%d_same_" % i, out)
+        out["q%d_steps" % i] = wl.n_steps
+        A.close()
+        print("c5: request %d (edge %d, %d steps) done %.1f s" % (i, wl.medium.nx, wl.n_steps, time.time() - t0),
+              flush=True)
+    np.savez_compressed(os.path.join(out_dir, "c5_run.npz"), **out)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["c2", "c1"])
+    ap.add_argument("which", choices=["c2", "c1", "c3", "c4", "c5"])
     ap.add_argument("--steps", type=int, default=None)
     a = ap.parse_args()
-    wl = W.c2() if a.which == "c2" else W.c1()
-    make(a.which, wl, a.steps or wl.n_steps, HERE)
+    if a.which == "c3":
+        make_c3(HERE, a.steps)
+    elif a.which == "c4":
+        make_c4(HERE, a.steps)
+    elif a.which == "c5":
+        make_c5(HERE)
+    else:
+        wl = W.c2() if a.which == "c2" else W.c1()
+        make(a.which, wl, a.steps or wl.n_steps, HERE)
 
 
 if __name__ == "__main__":
