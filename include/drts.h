@@ -286,7 +286,8 @@ typedef struct {
                              swept in z (its x gathers stay in its L2) */
     int32_t graph_steps;  /* steps captured per hipGraph replay (0 = eager) */
     int32_t rescale;      /* 1 = power-of-two rescale every step (default) */
-    int32_t variant;      /* one rhs only: DRTS_SPMV_ROW (a thread per row,
+    int32_t variant;      /* n_rhs > 1: DRTS_SPMM_GROUPED or DRTS_SPMM_ROWS;
+                             one rhs: DRTS_SPMV_ROW (a thread per row,
                              four consecutive entries per lane), DRTS_SPMV_PIPE
                              (the next tile's entries load while the current
                              tile is reduced), DRTS_SPMV_HALF (two threads per
@@ -318,6 +319,13 @@ typedef struct {
 #define DRTS_SPMV_WAVE_PIPE 6
 #define DRTS_SPMV_LDS 7
 #define DRTS_SPMV_WAVE_LDS 8
+/* n_rhs > 1: rows whose column lists are equal (on a lattice, the rows that
+ * pull from one source voxel) share one gather of their right-hand-side rows
+ * (the default; the library takes the row-by-row step for a matrix whose
+ * rows do not group, at least two rows a group on average), or every row
+ * gathers its own.  Both give the same result bit for bit. */
+#define DRTS_SPMM_GROUPED 0
+#define DRTS_SPMM_ROWS 1
 
 /* Creates the time-stepping state for n_rhs right-hand sides sharing A: the
  * state (zero), detectors, series buffers for max_steps steps.  n_rhs > 1

@@ -71,7 +71,13 @@ void Buffer::reset()
     bytes = 0;
 }
 
-int64_t Matrix::bytes() const { return (int64_t)(row_ptr.bytes + col.bytes + val.bytes); }
+int64_t Matrix::bytes() const
+{
+    const Buffer *b[] = {&row_ptr, &col, &val, &grp_ptr, &grp_row, &grp_mat, &grp_val, &grp_voff, &grp_coff, &grp_len};
+    int64_t n = 0;
+    for (const Buffer *x : b) n += (int64_t)x->bytes;
+    return n;
+}
 int64_t Matrix::table_bytes() const
 {
     const Buffer *b[] = {&mat_of_voxel, &absorb, &index, &blocks64, &blocks32, &irr_row, &irr_vox, &irr_dir,
@@ -161,6 +167,7 @@ struct drts_solver {
 
     // profiling
     bool profile = false;
+    bool grouped = false;   // the many-rhs CSR step runs by row groups
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     int64_t prof_launches = 0;
@@ -440,6 +447,28 @@ int balanced_xcd_bounds(drts_solver *S, const std::vector<int64_t> &bounds, std:
     return DRTS_OK;
 }
 
+// Detector entries grouped by detector (stable: rows stay ascending within
+// each), uploaded; ptr and row receive the host copies.
+int upload_dets_by_detector(drts_solver *S, std::vector<int64_t> *ptr_out, std::vector<int64_t> *row_out)
+{
+    std::vector<int64_t> &ptr = *ptr_out, &row = *row_out;
+    ptr.assign((size_t)S->n_det + 1, 0);
+    row.assign(S->dets.size(), 0);
+    std::vector<double> F(S->dets.size());
+    for (const DetEntry &d : S->dets) ++ptr[(size_t)d.id + 1];
+    for (int d = 0; d < S->n_det; ++d) ptr[(size_t)d + 1] += ptr[(size_t)d];
+    std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+    for (const DetEntry &d : S->dets) {
+        const size_t at = (size_t)fill[(size_t)d.id]++;
+        row[at] = d.row;
+        F[at] = d.F;
+    }
+    int rc;
+    if ((rc = upload_vec(S->dev, S->ddet_ptr, ptr))) return rc;
+    if ((rc = upload_vec(S->dev, S->ddet_row, row))) return rc;
+    return upload_vec(S->dev, S->ddet_F, F);
+}
+
 // (Re)builds every structure that depends on the options and the sources.
 int prepare(drts_solver *S)
 {
@@ -509,20 +538,8 @@ int prepare(drts_solver *S)
         sa.n_src_entries = (int64_t)S->srcs.size();
         sa.n_det_entries = (int64_t)S->dets.size();
         {
-            // detector entries grouped by detector (stable: rows stay ascending)
-            std::vector<int64_t> ptr((size_t)S->n_det + 1, 0), row(S->dets.size());
-            std::vector<double> F(S->dets.size());
-            for (const DetEntry &d : S->dets) ++ptr[(size_t)d.id + 1];
-            for (int d = 0; d < S->n_det; ++d) ptr[(size_t)d + 1] += ptr[(size_t)d];
-            std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
-            for (const DetEntry &d : S->dets) {
-                const size_t at = (size_t)fill[(size_t)d.id]++;
-                row[at] = d.row;
-                F[at] = d.F;
-            }
-            if ((rc = upload_vec(dev, S->ddet_ptr, ptr))) return rc;
-            if ((rc = upload_vec(dev, S->ddet_row, row))) return rc;
-            if ((rc = upload_vec(dev, S->ddet_F, F))) return rc;
+            std::vector<int64_t> ptr, row;
+            if ((rc = upload_dets_by_detector(S, &ptr, &row))) return rc;
             if (!spmm_of(S)) {
                 // per work item of the second kernel (kStructXRows listed rows) and
                 // detector: the range of the detector's entries whose rows lie in
@@ -549,8 +566,16 @@ int prepare(drts_solver *S)
         S->n_tiles = (A.model.n_rows + o.rows_per_tile - 1) / o.rows_per_tile;
         S->n_xchunks = 0;
     }
+    // the many-rhs CSR step by row groups when the rows group: at least two
+    // rows a group on average
+    S->grouped = false;
+    if (spmm_of(S) && o.kernel == DRTS_KERNEL_CSR && o.variant == DRTS_SPMM_GROUPED) {
+        if ((rc = row_groups(A))) return rc;
+        S->grouped = A.n_groups > 0;
+    }
     // a work item of the many-rhs matrix-free step is one tile (kStructVoxPerChunk
-    // voxels); its kernels keep one set of partials per workgroup
+    // voxels); its kernels, and the step by row groups, keep one set of
+    // partials per workgroup
     const bool smm = structured_of(S) && spmm_of(S);
     const int64_t tpc = smm ? 1 : o.tiles_per_chunk;
     S->n_chunks = (S->n_tiles + tpc - 1) / tpc;
@@ -562,6 +587,12 @@ int prepare(drts_solver *S)
         S->sa.mm_pull_grid = (int32_t)std::max<int64_t>(1, std::min<int64_t>(S->grid, S->n_xchunks));
         S->sa.chunk_base = S->sa.mm_push_grid;
         n_part = S->sa.mm_push_grid + (S->n_xchunks > 0 ? S->sa.mm_pull_grid : 0);
+    }
+    if (S->grouped) {
+        // the workgroups launch_step starts for this work list
+        n_part = std::min<int64_t>(S->grid, (S->n_chunks + 7) / 8 * 8);
+        std::vector<int64_t> ptr, row;
+        if ((rc = upload_dets_by_detector(S, &ptr, &row))) return rc;
     }
     if (S->n_chunks > INT32_MAX) return set_error(DRTS_E_RANGE, "too many chunks");
 
@@ -579,8 +610,7 @@ int prepare(drts_solver *S)
         if ((rc = upload_vec(dev, S->src_tile, tile_offsets(S->srcs, S->n_tiles, o.rows_per_tile)))) return rc;
         if ((rc = upload_vec(dev, S->det_tile, tile_offsets(S->dets, S->n_tiles, o.rows_per_tile)))) return rc;
     }
-    const size_t slots = (size_t)(kSlotDet + S->n_det) * S->n_rhs;
-    if ((rc = S->partials.allocate(&dev, slots * (size_t)(n_part + kFinSeg) * sizeof(double)))) return rc;
+    if ((rc = S->partials.allocate(&dev, partials_bytes(S->n_det, S->n_rhs, n_part)))) return rc;
 
     StepInst &I = S->inst_h;
     memset(&I, 0, sizeof I);
@@ -621,6 +651,20 @@ int prepare(drts_solver *S)
     I.n_mat = (int32_t)A.model.mats.size();
     I.vox_mul = vox_mul_of(A.model.n_dir);
     I.max_steps = S->max_steps;
+    if (S->grouped) {
+        I.grp_ptr = A.grp_ptr.as<int32_t>();
+        I.grp_row = A.grp_row.as<int32_t>();
+        I.grp_mat = A.grp_mat.as<uint8_t>();
+        I.grp_val = A.grp_val.as<float>();
+        I.grp_voff = A.grp_voff.as<int64_t>();
+        I.grp_coff = A.grp_coff.as<int64_t>();
+        I.grp_len = A.grp_len.as<int32_t>();
+        I.n_groups = A.n_groups;
+        I.det_direct = 1;
+        I.ddet_ptr = S->ddet_ptr.as<int64_t>();
+        I.ddet_row = S->ddet_row.as<int64_t>();
+        I.ddet_F = S->ddet_F.as<double>();
+    }
     I.partials = S->partials.as<double>();
     I.n_chunks = n_part;   // the finalize reduces both kernels' chunks
     I.ser_tot = S->ser_tot.as<double>();
@@ -790,7 +834,7 @@ int launch_one(drts_solver *S, hipStream_t stream, const StepInst *inst = nullpt
     } else {
     const int variant = long_rows(A) ? kVariantLongRows : S->opt.variant;
     e = launch_step(insts, S->work_dev.as<WorkItem>(), S->n_chunks, 1, S->n_rhs,
-                               A.model.value_type == DRTS_F64, A.rp64 ? 1 : 0, spmm ? 1 : 0, S->grid,
+                               A.model.value_type == DRTS_F64, A.rp64 ? 1 : 0, spmm ? (S->grouped ? 2 : 1) : 0, S->grid,
                                (S->opt.xcd_remap ? 1 : 0) | ((variant & 15) << 1), S->xcd_bounds.as<int64_t>(),
                                S->opt.rows_per_tile, S->n_det, queue, stream);
     }
@@ -845,17 +889,18 @@ drts_options_t default_options(const drts_solver *S)
     // defaults measured on MI355X: one rhs on the 128^3 three-layer workload
     // (256-row tiles, 4 tiles per chunk, 64 workgroups per CU launched: the
     // surplus waits and gives dynamic balance; fixed walk; FP32 values go
-    // straight to LDS), 64 rhs on the 96^3 slab (64-row tiles, 16 tiles per
-    // chunk, 16 workgroups per CU, each XCD a slab of chunks: 6% faster)
+    // straight to LDS), 64 rhs on the 96^3 slab (by row groups; work items
+    // of 64-row tiles x 16, 16 workgroups per CU, round-robin walk)
     drts_options_t o{};
     o.kernel = DRTS_KERNEL_CSR;
     o.rows_per_tile = spmm_of(S) ? 64 : 256;
     o.tiles_per_chunk = spmm_of(S) ? 16 : 4;
     o.grid = device_cu_count() * (spmm_of(S) ? 16 : 64);
-    o.xcd_remap = spmm_of(S) ? 2 : 0;
+    o.xcd_remap = 0;
     o.graph_steps = 0;
     o.rescale = 1;
-    o.variant = S->A->m.model.value_type == DRTS_F64 ? DRTS_SPMV_ROW : DRTS_SPMV_LDS;
+    o.variant = spmm_of(S) ? DRTS_SPMM_GROUPED
+                           : (S->A->m.model.value_type == DRTS_F64 ? DRTS_SPMV_ROW : DRTS_SPMV_LDS);
     o.queue = 0;
     return o;
 }
@@ -886,6 +931,9 @@ int check_options(const drts_solver *S, const drts_options_t *o)
     }
     if (o->queue != 0 && o->queue != 1) return set_error(DRTS_E_INVALID, "queue must be 0 or 1");
     if (o->xcd_remap < 0 || o->xcd_remap > 2) return set_error(DRTS_E_INVALID, "xcd_remap must be 0, 1 or 2");
+    if (S->n_rhs > 1 && o->variant != DRTS_SPMM_GROUPED && o->variant != DRTS_SPMM_ROWS)
+        return set_error(DRTS_E_INVALID, "variant %d: many rhs take DRTS_SPMM_GROUPED or DRTS_SPMM_ROWS",
+                         o->variant);
     if (o->variant < DRTS_SPMV_ROW || o->variant > DRTS_SPMV_WAVE_LDS)
         return set_error(DRTS_E_INVALID, "unknown variant %d", o->variant);
     if ((o->variant == DRTS_SPMV_LDS || o->variant == DRTS_SPMV_WAVE_LDS) && S->A->m.model.value_type == DRTS_F64)
@@ -1247,8 +1295,7 @@ int drts_step_noalloc(drts_solver_t *S, const drts_source_table_t *src)
         return set_error(DRTS_E_STATE, "drts_step_noalloc: the source table is not the one staged in the solver "
                                        "(hand it to drts_step or drts_run once first)");
     const StepInst &I0 = S->inst_h;
-    const size_t slots = (size_t)(kSlotDet + S->n_det) * S->n_rhs;
-    const size_t part_bytes = slots * (size_t)(I0.n_chunks + kFinSeg) * sizeof(double);
+    const size_t part_bytes = partials_bytes(S->n_det, S->n_rhs, I0.n_chunks);
     if (part_bytes > kScratchBytes - kScratchPartOff)
         return set_error(DRTS_E_RANGE,
                          "drts_step_noalloc: the step needs %zu bytes of partials, the scratch array holds %zu "

@@ -116,13 +116,24 @@ struct Matrix {
     Buffer mat_of_voxel, absorb, index, blocks64, blocks32;
     Buffer irr_row, irr_vox, irr_dir, irr_f, irr_bits, escape_state;
     Buffer pair_ptr, pair_key, pair_w, arr_ptr, arr_key, arr_w;   // Lebedev weights
-    int64_t bytes() const;         // the CSR arrays
+    // rows with equal column lists (built on first use by a many-rhs solver):
+    // group g is grp_row[grp_ptr[g] .. grp_ptr[g+1]-1]; per member (group
+    // order) its material; the values in group order; per group the offset
+    // of its values, of its leader's columns and its entries a row.
+    // n_groups < 0 = not built, 0 = the rows do not group
+    Buffer grp_ptr, grp_row, grp_mat, grp_val, grp_voff, grp_coff, grp_len;
+    int64_t n_groups = -1;
+    int64_t bytes() const;         // the CSR arrays (and the row groups, once built)
     int64_t table_bytes() const;   // everything else on the device (tables of the model)
 };
 
 // with_csr = false builds only the tables the matrix-free steps read (and
 // counts the entries the CSR would hold).
 int assemble_on_device(Matrix *A, bool with_csr = true);
+// Builds A's row groups once (no groups: n_groups = 0, when the matrix has
+// no CSR, FP64 values, 2^31 rows or more, or fewer than two rows a group on
+// average).
+int row_groups(const Matrix &A);
 
 // ---- windowed measurement (Eq. 27 over several steps) --------------------------
 struct WindowArgs {

@@ -59,6 +59,26 @@ struct StepInst {
     int32_t n_mat;          // entries of absorb
     uint64_t vox_mul;       // vox_mul_of(directions per voxel): row -> voxel
     int64_t max_steps;
+    // many rhs: groups of rows with equal column lists (NULL = none); group
+    // g's members are grp_row[grp_ptr[g] .. grp_ptr[g+1]-1], ascending, at
+    // most kGroupMax of them, with their materials in grp_mat; its values
+    // (every member's grp_len[g] entries in turn) start at grp_val +
+    // grp_voff[g], its columns (the leader's) at col + grp_coff[g]
+    const int32_t *grp_ptr;
+    const int32_t *grp_row;
+    const uint8_t *grp_mat;
+    const float *grp_val;
+    const int64_t *grp_voff, *grp_coff;
+    const int32_t *grp_len;
+    int64_t n_groups;
+    // det_direct: the detector sums come from their own kernel (a value per
+    // detector and rhs after the finalize segments of the partials, see
+    // det_direct_sums), which takes the detector entries grouped by detector,
+    // rows ascending within each: detector d owns ddet_row/ddet_F
+    // [ddet_ptr[d], ddet_ptr[d+1])
+    int32_t det_direct;
+    const int64_t *ddet_ptr, *ddet_row;
+    const double *ddet_F;
     // partials [slot * n_rhs + rhs][n_chunks], then [slot * n_rhs + rhs][kFinSeg]
     double *partials;
     int64_t n_chunks;
@@ -68,6 +88,22 @@ struct StepInst {
     int32_t *ser_exp;       // [max_steps][n_rhs]: exponent E_{t+1} of the above
     int32_t *ser_abs_exp;   // [max_steps][n_rhs]: exponent E_t of absorbed(t)
 };
+
+// Parts of a detector's entry list whose direct sums are formed apart (and
+// added in part order by the finalize).
+constexpr int kDetParts = 64;
+// Bytes of a solver's partials buffer: [slots][n_rhs][n_chunks] chunk values,
+// [slots][n_rhs][kFinSeg] finalize segments, then [n_det][kDetParts][n_rhs]
+// direct detector sums.
+inline size_t partials_bytes(int n_det, int n_rhs, int64_t n_chunks)
+{
+    const size_t slots = (size_t)(kSlotDet + n_det) * n_rhs;
+    return (slots * (size_t)(n_chunks + kFinSeg) + (size_t)n_det * kDetParts * n_rhs) * sizeof(double);
+}
+__host__ __device__ inline double *det_direct_sums(double *partials, int n_det, int n_rhs, int64_t n_chunks)
+{
+    return partials + (size_t)(kSlotDet + n_det) * n_rhs * (size_t)(n_chunks + kFinSeg);
+}
 
 // Voxel of state row r (< 2^32): r / n_dir as the high half of r * mul with
 // mul = ceil(2^64 / n_dir), exact for every r < 2^32 (the error of mul, below
@@ -88,11 +124,16 @@ constexpr int kVariantLongRows = 9;
 // mean entries per row from which a matrix takes the wave-per-row SpMV
 constexpr int kLongRowMean = 96;
 
+// Members of one row group at most (larger sets of equal rows are split).
+constexpr int kGroupMax = 26;
+
 // Launches the SpMV (n_rhs == 1) or SpMM step over a work list.  xcd_remap
 // bit 0 selects the XCD-aware order, bit 1 the pipelined SpMV.  Returns a
 // hipError_t.
 // queue (may be NULL): a zeroed device counter from which the SpMV workgroups
 // take work items; the finalize kernel resets it.
+// spmm: 0 = one rhs, 1 = many rhs row by row, 2 = many rhs by row groups
+// (work item c takes groups c * n_groups / n_chunks onwards).
 // xcd_bounds (may be NULL): with the XCD-aware walk, XCD i takes work items
 // xcd_bounds[i] .. xcd_bounds[i+1]-1 (kXcdBounds entries), else equal counts.
 hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int64_t n_work, int n_inst,

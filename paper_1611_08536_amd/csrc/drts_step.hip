@@ -1392,6 +1392,38 @@ __global__ void __launch_bounds__(256) step_spmv_wl(const StepInst *__restrict__
 // ---------------------------------------------------------------------------
 constexpr int kSpmmUnroll = 26;   // entries of a plain row, gathered fully unrolled
 
+// A chunk's per-wave sums (lane = rhs) combined in a fixed wave order and
+// written as the chunk's partials; the workgroup's waves all call it.
+__device__ __forceinline__ void spmm_chunk_partials(const StepInst &I, int64_t c, int wave, int lane, double sN,
+                                                    double sE, double sA, float mx, double (*s_w)[4][64],
+                                                    const double *s_det)
+{
+    const int nrhs = I.n_rhs, nd = I.n_det;
+    s_w[0][wave][lane] = sN;
+    s_w[1][wave][lane] = sE;
+    s_w[2][wave][lane] = sA;
+    s_w[3][wave][lane] = (double)mx;
+    __syncthreads();
+    const int64_t nc = I.n_chunks;
+    if (wave == 0 && lane < nrhs) {
+        const double N = ((s_w[0][0][lane] + s_w[0][1][lane]) + s_w[0][2][lane]) + s_w[0][3][lane];
+        const double Es = ((s_w[1][0][lane] + s_w[1][1][lane]) + s_w[1][2][lane]) + s_w[1][3][lane];
+        const double A = ((s_w[2][0][lane] + s_w[2][1][lane]) + s_w[2][2][lane]) + s_w[2][3][lane];
+        const double M = fmax(fmax(s_w[3][0][lane], s_w[3][1][lane]), fmax(s_w[3][2][lane], s_w[3][3][lane]));
+        I.partials[((int64_t)kSlotN * nrhs + lane) * nc + c] = N;
+        I.partials[((int64_t)kSlotEsc * nrhs + lane) * nc + c] = Es;
+        I.partials[((int64_t)kSlotAbs * nrhs + lane) * nc + c] = A;
+        I.partials[((int64_t)kSlotMax * nrhs + lane) * nc + c] = M;
+        for (int d = 0; d < nd; ++d) {
+            const double D = ((s_det[(0 * nd + d) * 64 + lane] + s_det[(1 * nd + d) * 64 + lane]) +
+                              s_det[(2 * nd + d) * 64 + lane]) +
+                             s_det[(3 * nd + d) * 64 + lane];
+            I.partials[((int64_t)(kSlotDet + d) * nrhs + lane) * nc + c] = D;
+        }
+    }
+    __syncthreads();
+}
+
 template <typename IT>
 __global__ void __launch_bounds__(kNT) step_spmm(const StepInst *__restrict__ insts,
                                                   const WorkItem *__restrict__ work, int64_t n_work,
@@ -1554,30 +1586,216 @@ __global__ void __launch_bounds__(kNT) step_spmm(const StepInst *__restrict__ in
                 v_cur = v_nxt;
             }
         }
-        s_w[0][wave][lane] = sN;
-        s_w[1][wave][lane] = sE;
-        s_w[2][wave][lane] = sA;
-        s_w[3][wave][lane] = (double)mx;
-        __syncthreads();
-        const int64_t nc = I.n_chunks, c = item.chunk;
-        if (wave == 0 && active) {
-            const double N = ((s_w[0][0][lane] + s_w[0][1][lane]) + s_w[0][2][lane]) + s_w[0][3][lane];
-            const double Es = ((s_w[1][0][lane] + s_w[1][1][lane]) + s_w[1][2][lane]) + s_w[1][3][lane];
-            const double A = ((s_w[2][0][lane] + s_w[2][1][lane]) + s_w[2][2][lane]) + s_w[2][3][lane];
-            const double M = fmax(fmax(s_w[3][0][lane], s_w[3][1][lane]), fmax(s_w[3][2][lane], s_w[3][3][lane]));
-            I.partials[((int64_t)kSlotN * nrhs + lane) * nc + c] = N;
-            I.partials[((int64_t)kSlotEsc * nrhs + lane) * nc + c] = Es;
-            I.partials[((int64_t)kSlotAbs * nrhs + lane) * nc + c] = A;
-            I.partials[((int64_t)kSlotMax * nrhs + lane) * nc + c] = M;
-            for (int d = 0; d < nd; ++d) {
-                const double D = ((s_det[(0 * nd + d) * 64 + lane] + s_det[(1 * nd + d) * 64 + lane]) +
-                                  s_det[(2 * nd + d) * 64 + lane]) +
-                                 s_det[(3 * nd + d) * 64 + lane];
-                I.partials[((int64_t)(kSlotDet + d) * nrhs + lane) * nc + c] = D;
+        spmm_chunk_partials(I, item.chunk, wave, lane, sN, sE, sA, mx, s_w, s_det);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// SpMM step by row groups (n_rhs right-hand sides, FP32, one solver), lanes = rhs
+//
+// Rows whose column lists are equal form a group: in a lattice matrix, the
+// rows that pull from one source voxel (one per direction, state or escape
+// row) all hold that voxel's whole state.  The matrix keeps, beside its CSR,
+// the values in group order and each member's row and material, so every
+// array the step reads of a group is contiguous.  A wave takes a group at a
+// time: the group's offsets come through the scalar cache, lane j fetches
+// member j's row, material and whether its tile has sources; the leader's
+// columns are read once and the X rows they name are gathered once into
+// registers (one coalesced 4*n_rhs-byte row per column); every member's
+// values come with one coalesced load and are applied to those registers.
+// Each X row is then fetched about once per step instead of once per entry.  A member is formed with the same products in
+// the same column order as in the row-by-row kernel and the single-rhs step,
+// so every column of the result equals theirs bit for bit.  Groups whose rows
+// are not kSpmmUnroll long are formed row by row (windows of 64 entries).
+//
+// Work item c takes groups c * n_groups / n_work onwards; its waves take
+// every fourth group.  A workgroup sums the totals of all its work items (a
+// fixed walk) and writes one set of partials, at its own index; the detector
+// sums are left to spmm_detectors, which reads the stored rows.
+// ---------------------------------------------------------------------------
+template <typename IT>
+__global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(5, 8))) step_spmm_grouped(const StepInst *__restrict__ insts,
+                                                          const WorkItem *__restrict__ work, int64_t n_work,
+                                                          int xcd_remap, const int64_t *__restrict__ xcd_bounds)
+{
+    __shared__ double s_w[4][4][64];     // per-wave totals for the fixed-order combine
+    __shared__ double s_abs[kMatMax];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const Walk wk = walk_of(n_work, xcd_remap, xcd_bounds);
+    const StepInst &I = insts[0];
+    const int64_t t = I.t[0];
+    if (t >= *I.t_end) return;
+    const int nrhs = I.n_rhs;
+    const bool active = lane < nrhs;
+    const int xl = min(lane, nrhs - 1);   // lanes past n_rhs gather a valid element, then drop it
+    Scale sc{0, 0};
+    if (active) sc = step_scale(I, lane, t);
+    const float scale = ldexpf(1.0f, -sc.k);
+    const GLB int32_t *col = gp(I.col);
+    const GLB float *val = gp(I.grp_val);
+    const GLB float *X = gp((const float *)((t & 1) ? I.buf1 : I.buf0));
+    GLB float *Y = gpw((float *)((t & 1) ? I.buf0 : I.buf1));
+    const GLB uint8_t *gmat = gp(I.grp_mat);
+    const GLB int32_t *grow = gp(I.grp_row);
+    const GLB int32_t *src_tile = gp(I.src_tile);
+    const CST int32_t *gptr = cst(I.grp_ptr);
+    const CST int32_t *glen = cst(I.grp_len);
+    const CST int64_t *gvoff = cst(I.grp_voff);
+    const CST int64_t *gcoff = cst(I.grp_coff);
+    for (int q = threadIdx.x; q < I.n_mat; q += kNT) s_abs[q] = gp(I.absorb)[q];
+    __syncthreads();
+
+    double sN = 0.0, sE = 0.0, sA = 0.0;
+    float mx = 0.0f;
+    const int R = I.rows_per_tile;
+    const int64_t G = I.n_groups;
+    for (int64_t wi = wk.begin; wi < wk.end; wi += wk.stride) {
+        const int64_t c = work[wi].chunk;
+        const int64_t g_b = c * G / n_work, g_e = (c + 1) * G / n_work;
+        for (int64_t g = g_b + wave; g < g_e; g += 4) {
+            const int m0 = gptr[g];
+            const int nm = gptr[g + 1] - m0;
+            const int n = glen[g];
+            const int64_t voff = gvoff[g], coff = gcoff[g];
+            // lane j (< nm): member j
+            const int jl = min(lane, nm - 1);
+            const int32_t my_r = grow[m0 + jl];
+            const int my_mat = gmat[m0 + jl];
+
+            // member m's result: rescale, sources, store, totals
+            uint64_t src_mask = 0;
+            int my_tile = 0;
+            auto emit = [&](int m, float acc) {
+                const int64_t r = __builtin_amdgcn_readlane(my_r, m);
+                float v = acc * scale;
+                if ((src_mask >> m) & 1) {
+                    const int tile = __builtin_amdgcn_readlane(my_tile, m);
+                    const int sb = src_tile[tile], se = src_tile[tile + 1];
+                    int e2 = lower_bound_rows<IT>(I.src_row, sb, se, r);
+                    double s = 0.0;
+                    bool any = false;
+                    for (; e2 < se && I.src_row[e2] == r; ++e2) {
+                        if (I.src_rhs[e2] == lane) {
+                            s += I.src_w[e2] * I.amp[t * I.n_src + I.src_id[e2]];
+                            any = true;
+                        }
+                    }
+                    if (any) v += (float)ldexp(s, -sc.En);
+                }
+                if (active) {
+                    Y[r * nrhs + lane] = v;
+                    if (r < I.n_states) {
+                        sN += (double)v;
+                        sA += s_abs[__builtin_amdgcn_readlane(my_mat, m)] * (double)v;
+                        mx = fmaxf(mx, v);
+                    } else {
+                        sE += (double)v;
+                    }
+                }
+            };
+
+            if (n == kSpmmUnroll) {
+                const int32_t cl = col[coff + min(lane, kSpmmUnroll - 1)];
+                float vv[kGroupMax];
+#pragma unroll
+                for (int m = 0; m < kGroupMax; ++m)
+                    if (m < nm) vv[m] = val[voff + m * kSpmmUnroll + min(lane, kSpmmUnroll - 1)];
+                my_tile = my_r / R;
+                src_mask = __builtin_amdgcn_ballot_w64(src_tile[my_tile + 1] > src_tile[my_tile]);
+                float xv[kSpmmUnroll];
+#pragma unroll
+                for (int k = 0; k < kSpmmUnroll; ++k)
+                    xv[k] = X[(int64_t)__builtin_amdgcn_readlane(cl, k) * nrhs + xl];
+#pragma unroll
+                for (int m = 0; m < kGroupMax; ++m) {
+                    if (m < nm) {
+                        float acc = 0.0f;
+#pragma unroll
+                        for (int k = 0; k < kSpmmUnroll; ++k)
+                            acc += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vv[m]), k)) * xv[k];
+                        emit(m, acc);
+                    }
+                }
+            } else {
+                my_tile = my_r / R;
+                src_mask = __builtin_amdgcn_ballot_w64(src_tile[my_tile + 1] > src_tile[my_tile]);
+                for (int m = 0; m < nm; ++m) {
+                    const int64_t mv = voff + (int64_t)m * n;
+                    float acc = 0.0f;
+                    for (int wb = 0; wb < n; wb += 64) {
+                        int32_t cw = 0;
+                        float vw = 0.0f;
+                        if (wb + lane < n) {
+                            cw = col[coff + wb + lane];
+                            vw = val[mv + wb + lane];
+                        }
+                        const int w = min(64, n - wb);
+                        int k = 0;
+                        for (; k + 8 <= w; k += 8) {
+                            float xw[8];
+#pragma unroll
+                            for (int u = 0; u < 8; ++u)
+                                xw[u] = X[(int64_t)__builtin_amdgcn_readlane(cw, k + u) * nrhs + xl];
+#pragma unroll
+                            for (int u = 0; u < 8; ++u)
+                                acc += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vw), k + u)) * xw[u];
+                        }
+                        for (; k < w; ++k) {
+                            const float xk = X[(int64_t)__builtin_amdgcn_readlane(cw, k) * nrhs + xl];
+                            acc += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vw), k)) * xk;
+                        }
+                    }
+                    emit(m, acc);
+                }
             }
         }
-        __syncthreads();
     }
+    // the workgroup's totals, waves combined in a fixed order
+    s_w[0][wave][lane] = sN;
+    s_w[1][wave][lane] = sE;
+    s_w[2][wave][lane] = sA;
+    s_w[3][wave][lane] = (double)mx;
+    __syncthreads();
+    if (wave == 0 && active) {
+        const int64_t nc = I.n_chunks, b = blockIdx.x;
+        I.partials[((int64_t)kSlotN * nrhs + lane) * nc + b] =
+            ((s_w[0][0][lane] + s_w[0][1][lane]) + s_w[0][2][lane]) + s_w[0][3][lane];
+        I.partials[((int64_t)kSlotEsc * nrhs + lane) * nc + b] =
+            ((s_w[1][0][lane] + s_w[1][1][lane]) + s_w[1][2][lane]) + s_w[1][3][lane];
+        I.partials[((int64_t)kSlotAbs * nrhs + lane) * nc + b] =
+            ((s_w[2][0][lane] + s_w[2][1][lane]) + s_w[2][2][lane]) + s_w[2][3][lane];
+        I.partials[((int64_t)kSlotMax * nrhs + lane) * nc + b] =
+            fmax(fmax(s_w[3][0][lane], s_w[3][1][lane]), fmax(s_w[3][2][lane], s_w[3][3][lane]));
+    }
+}
+
+// Detector sums of the step by row groups (Eq. (27)): block (p, d) forms the
+// sum F * y over part p of detector d's entries (kDetParts equal parts of its
+// row-ordered list) from the stored rows of y -- lanes = rhs, the four waves
+// take every fourth entry, then combine in a fixed order -- and writes it to
+// the direct sums, which the finalize adds in part order.
+__global__ void __launch_bounds__(kNT) spmm_detectors(const StepInst *__restrict__ insts)
+{
+    __shared__ double s_d[4][64];
+    const StepInst &I = insts[0];
+    const int64_t t = I.t[0];
+    if (t >= *I.t_end) return;
+    const int p = blockIdx.x, d = blockIdx.y;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nrhs = I.n_rhs;
+    const int xl = min(lane, nrhs - 1);
+    const GLB float *Y = gp((const float *)((t & 1) ? I.buf0 : I.buf1));
+    const int64_t b = I.ddet_ptr[d], n = I.ddet_ptr[d + 1] - b;
+    const int64_t pb = b + p * n / kDetParts, pe = b + (p + 1) * n / kDetParts;
+    double acc = 0.0;
+#pragma unroll 4
+    for (int64_t k = pb + wave; k < pe; k += 4) acc += I.ddet_F[k] * (double)Y[I.ddet_row[k] * nrhs + xl];
+    s_d[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0 && lane < nrhs)
+        det_direct_sums(I.partials, I.n_det, nrhs, I.n_chunks)[((int64_t)d * kDetParts + p) * nrhs + lane] =
+            ((s_d[0][lane] + s_d[1][lane]) + s_d[2][lane]) + s_d[3][lane];
 }
 
 // ---------------------------------------------------------------------------
@@ -1609,13 +1827,22 @@ __global__ void __launch_bounds__(kNT) finalize_seg(const StepInst *__restrict__
     const GLB double *part = gp(I.partials);
     GLB double *segp = gpw(I.partials + (int64_t)nslot * nr * nc);   // [slot * n_rhs + rhs][kFinSeg]
     // up to four slots per pass, so their loads are in flight together
-    for (int k0 = 0; k0 < nslot; k0 += 4) {
+    // with direct detector sums only the totals have chunk partials
+    const int nsum = I.det_direct ? kSlotDet : nslot;
+    if (I.det_direct && tid < I.n_det) {
+        const double *ds = det_direct_sums(I.partials, I.n_det, nr, nc);
+        double v = 0.0;
+        if (seg == 0)
+            for (int p = 0; p < kDetParts; ++p) v += ds[((int64_t)tid * kDetParts + p) * nr + rhs];
+        segp[((int64_t)(kSlotDet + tid) * nr + rhs) * kFinSeg + seg] = v;
+    }
+    for (int k0 = 0; k0 < nsum; k0 += 4) {
         double a[4] = {0.0, 0.0, 0.0, 0.0};
         for (int64_t c = c0 + tid; c < c1; c += kNT) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int k = k0 + j;
-                if (k < nslot) {
+                if (k < nsum) {
                     const double v = part[((int64_t)k * nr + rhs) * nc + c];
                     a[j] = (k == kSlotMax) ? fmax(a[j], v) : a[j] + v;
                 }
@@ -1627,7 +1854,7 @@ __global__ void __launch_bounds__(kNT) finalize_seg(const StepInst *__restrict__
             if (lane == 0) s_w[j][wave] = w;
         }
         __syncthreads();
-        if (tid < 4 && k0 + tid < nslot) {
+        if (tid < 4 && k0 + tid < nsum) {
             const int k = k0 + tid;
             double r = s_w[tid][0];
             for (int w = 1; w < NW; ++w) r = (k == kSlotMax) ? fmax(r, s_w[tid][w]) : r + s_w[tid][w];
@@ -2656,7 +2883,19 @@ hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int6
     // the XCD count keeps the per-XCD walk available
     grid = (int)std::min<int64_t>(grid, (n_work + kXcds - 1) / kXcds * kXcds);
     const dim3 g((unsigned)grid), b(kNT);
-    if (spmm) {
+    if (spmm == 2) {
+        if (rp64)
+            hipLaunchKernelGGL(step_spmm_grouped<int64_t>, g, b, 0, stream, insts_dev, work_dev, n_work,
+                               xcd_remap & 1, xcd_bounds);
+        else
+            hipLaunchKernelGGL(step_spmm_grouped<int32_t>, g, b, 0, stream, insts_dev, work_dev, n_work,
+                               xcd_remap & 1, xcd_bounds);
+        if (n_det_max > 0) {
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(spmm_detectors, dim3(kDetParts, (unsigned)n_det_max), b, 0, stream, insts_dev);
+        }
+    } else if (spmm) {
         const size_t lds = (size_t)4 * n_det_max * 64 * sizeof(double);
         if (rp64)
             hipLaunchKernelGGL(step_spmm<int64_t>, g, b, lds, stream, insts_dev, work_dev, n_work, xcd_remap & 1,

@@ -23,6 +23,7 @@ DIRECTIONS = {"lattice26": 0, "lebedev86": 1}
 INTERFACE = {"origin": 0, "substep": 1}
 BC = {"vacuum": 0, "reflect": 1}
 KERNEL_CSR, KERNEL_STRUCTURED, KERNEL_STRUCTURED_F64SUM = 0, 1, 2
+SPMM_GROUPED, SPMM_ROWS = 0, 1   # variant of a many-rhs CSR solver
 SERVE_ARRIVAL, SERVE_SHORTEST = 0, 1
 
 if not os.path.exists(LIB_PATH):

@@ -1,0 +1,112 @@
+"""The many-rhs CSR step by row groups (rows with equal column lists share
+one gather of their right-hand-side rows) against the row-by-row step.
+
+Bar: bit-exact state, exponents and exponent series, FP64 series to 1e-13
+(the chunk partials are summed in another order), on media whose rows group
+in different ways: the homogeneous slab (whole groups of 26 rows), Fresnel
+layers and a sphere (interface rows that split off their voxel's group),
+reflecting walls, scattering order 3 (rows wider than one voxel), crossing
+within the step, and a Lebedev-86 medium (rows that do not group: the
+library takes the row-by-row step); with few and with 64 right-hand sides,
+sources in several rows of a group and detectors on escape and state rows.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+drts = pytest.importorskip("paper_1611_08536_amd.drts")
+from paper_1611_08536_amd import solve  # noqa: E402
+
+
+def _mat():
+    return W.Material(10.0, 0.05, 0.85, 1.4)
+
+
+def _layers(n):
+    return W.layered(n, [W.Material(5.0, 0.02, 0.8, 1.33), W.Material(15.0, 0.1, 0.9, 1.45),
+                         W.Material(10.0, 0.05, 0.85, 1.40)])
+
+
+def _sphere(n):
+    return W.sphere_inclusion(n, W.Material(10.0, 0.01, 0.9, 1.33), W.Material(10.0, 0.08, 0.9, 1.45),
+                              (n / 2 - 0.7, n / 2 + 0.1, n / 2 - 0.3), n / 3.5)
+
+
+def _order3(n):
+    m = W.homogeneous(n, _mat())
+    m.scatter_order = 3
+    return m
+
+
+def _substep(n):
+    m = _layers(n)
+    m.interface = "substep"
+    return m
+
+
+def _leb(n):
+    m = W.homogeneous(n, _mat())
+    m.directions = "lebedev86"
+    return m
+
+
+MEDIA = [("slab", lambda n: W.homogeneous(n, _mat(), nz=n - 3)),
+         ("layers", _layers),
+         ("sphere", _sphere),
+         ("reflect", lambda n: W.homogeneous(n, _mat(), bc="reflect")),
+         ("order3", _order3),
+         ("substep", _substep),
+         ("lebedev", _leb)]
+
+
+def _workload(med, k, steps, seed):
+    r = np.random.default_rng([161108536, seed])
+    srcs = []
+    for j in range(k):
+        x, y = (int(v) for v in r.integers(1, med.nx - 1, size=2))
+        kind = "gaussian" if j % 2 else "impulse"
+        srcs.append(W.point_source(x, y, 0, kind=kind, fwhm_fs=float(r.uniform(50, 300)), rhs=j))
+        if j % 3 == 0:
+            # a second source row of the same voxel (another direction) feeds the same rhs
+            srcs.append(W.point_source(x, y, 0, d=(1, 0, 1), rhs=j, w=0.5))
+    dets = []
+    if med.directions == "lattice26" and med.bc == "vacuum":
+        dets = [W.face_escape_detector(med, "top"), W.face_escape_detector(med, "bottom", 1, med.nx - 2)]
+        c = med.nx // 2
+        lv = W.lattice_vectors()
+        dets.append(W.Detector(np.array([[c, c, 1]] * 3), lv[[0, 12, 25]], np.zeros(3, dtype=bool),
+                               np.array([1.0, 2.0, 0.5]), "state"))
+    return W.Workload("grouped", med, srcs, dets, steps, k, "f32", "dither", 1.4)
+
+
+@pytest.mark.parametrize("k", [5, 64])
+@pytest.mark.parametrize("name,make", MEDIA, ids=[m[0] for m in MEDIA])
+def test_grouped_equals_row_by_row(name, make, k):
+    n = 7 if name == "lebedev" else 12
+    wl = _workload(make(n), k, 40, 7 + k)
+    print("%s %d^3, %d rhs" % (name, n, k), flush=True)
+    a = solve.run(wl, options={"variant": drts.SPMM_GROUPED})
+    b = solve.run(wl, matrix=a["matrix"], options={"variant": drts.SPMM_ROWS})
+    assert np.array_equal(a["x"].view(np.uint32), b["x"].view(np.uint32))
+    assert np.array_equal(a["x_exp"], b["x_exp"]) and np.array_equal(a["exp2"], b["exp2"])
+    assert np.allclose(a["tot"], b["tot"], rtol=1e-13, atol=0)
+    assert np.allclose(a["det"], b["det"], rtol=1e-13, atol=0)
+    assert (a["tot"][:, 0, :] > 0).any()
+    a["solver"].close()
+    b["solver"].close()
+
+
+@pytest.mark.parametrize("opts", [{"rows_per_tile": 16, "tiles_per_chunk": 1, "grid": 24, "xcd_remap": 1},
+                                  {"rows_per_tile": 256, "tiles_per_chunk": 1000, "grid": 3, "xcd_remap": 0}])
+def test_grouped_launch_shapes(opts):
+    """Many small work items (fewer groups than some items hold) and one item
+    holding every group."""
+    wl = _workload(_sphere(10), 9, 25, 3)
+    a = solve.run(wl, options={"variant": drts.SPMM_ROWS})
+    b = solve.run(wl, matrix=a["matrix"], options=dict(opts, variant=drts.SPMM_GROUPED))
+    assert np.array_equal(a["x"].view(np.uint32), b["x"].view(np.uint32))
+    assert np.array_equal(a["exp2"], b["exp2"])
+    assert np.allclose(a["det"], b["det"], rtol=1e-13, atol=0)
