@@ -305,7 +305,8 @@ typedef struct {
                              registers; FP32 values only),
                              DRTS_SPMV_WAVE_LDS (as DRTS_SPMV_WAVE with the
                              values through LDS and the chunk's tile bounds
-                             staged once; FP32 values, rows_per_tile 64) */
+                             staged once; FP32 values, rows_per_tile 64),
+                             DRTS_SPMV_GROUPED (below) */
     int32_t queue;        /* one rhs only: 1 = workgroups take chunks from a
                              device counter (dynamic balance), 0 = fixed walk */
 } drts_options_t;
@@ -319,6 +320,11 @@ typedef struct {
 #define DRTS_SPMV_WAVE_PIPE 6
 #define DRTS_SPMV_LDS 7
 #define DRTS_SPMV_WAVE_LDS 8
+/* one rhs, FP32 values: rows whose column lists are equal form groups (as
+ * for DRTS_SPMM_GROUPED); a half-wave forms a group, reading the group's
+ * columns and x once and its values from a group-order copy (the default;
+ * DRTS_SPMV_LDS for a matrix whose rows do not group). */
+#define DRTS_SPMV_GROUPED 9
 /* n_rhs > 1: rows whose column lists are equal (on a lattice, the rows that
  * pull from one source voxel) share one gather of their right-hand-side rows
  * (the default; the library takes the row-by-row step for a matrix whose

@@ -73,7 +73,7 @@ void Buffer::reset()
 
 int64_t Matrix::bytes() const
 {
-    const Buffer *b[] = {&row_ptr, &col, &val, &grp_ptr, &grp_row, &grp_mat, &grp_val, &grp_voff, &grp_coff, &grp_len};
+    const Buffer *b[] = {&row_ptr, &col, &val, &grp_desc, &grp_row, &grp_mat, &grp_val};
     int64_t n = 0;
     for (const Buffer *x : b) n += (int64_t)x->bytes;
     return n;
@@ -142,7 +142,7 @@ struct drts_solver {
 
     Buffer buf0, buf1, ctl_t, ctl_E, ctl_M, ctl_abs, t_end, partials, xcd_bounds, xrows, xirr, xsrc, xdet, zrows, xdrng,
         ddet_ptr, ddet_row,
-        ddet_F, pull_bits, esc_base;
+        ddet_F, pull_bits, esc_base, grp_src;
     Buffer ser_tot, ser_det, ser_exp, ser_abs_exp, amp, smax;
     Buffer src_tile, src_row, src_id, src_rhs, src_w;
     Buffer det_tile, det_row, det_id, det_F;
@@ -167,7 +167,9 @@ struct drts_solver {
 
     // profiling
     bool profile = false;
-    bool grouped = false;   // the many-rhs CSR step runs by row groups
+    bool grouped = false;        // the CSR step runs by row groups
+    bool group_pending = false;  // grouped step asked for, the matrix's groups not built yet
+    bool no_group = false;       // a batch member: the tiled step
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     int64_t prof_launches = 0;
@@ -447,6 +449,21 @@ int balanced_xcd_bounds(drts_solver *S, const std::vector<int64_t> &bounds, std:
     return DRTS_OK;
 }
 
+// Matrices whose rows hold several hundred entries (the multi-voxel weights of
+// Lebedev media) step with the wave-per-row SpMV.
+bool long_rows(const Matrix &A) { return A.model.n_rows > 0 && A.nnz >= (int64_t)kLongRowMean * A.model.n_rows; }
+
+int prepare(drts_solver *S);
+
+// Builds the matrix's row groups if the solver asked for the grouped step
+// and they are not built yet, then lays the solver out for them.
+int settle_groups(drts_solver *S)
+{
+    if (!S->group_pending) return DRTS_OK;
+    int rc = row_groups(S->A->m);
+    return rc ? rc : prepare(S);
+}
+
 // Detector entries grouped by detector (stable: rows stay ascending within
 // each), uploaded; ptr and row receive the host copies.
 int upload_dets_by_detector(drts_solver *S, std::vector<int64_t> *ptr_out, std::vector<int64_t> *row_out)
@@ -566,12 +583,16 @@ int prepare(drts_solver *S)
         S->n_tiles = (A.model.n_rows + o.rows_per_tile - 1) / o.rows_per_tile;
         S->n_xchunks = 0;
     }
-    // the many-rhs CSR step by row groups when the rows group: at least two
-    // rows a group on average
+    // the CSR step by row groups when the rows group (at least two rows a
+    // group on average; rows of several hundred entries take their own
+    // step).  The matrix's groups are built at the first solo step or run
+    // (settle_groups), not here: batch members never use them.
     S->grouped = false;
-    if (spmm_of(S) && o.kernel == DRTS_KERNEL_CSR && o.variant == DRTS_SPMM_GROUPED) {
-        if ((rc = row_groups(A))) return rc;
-        S->grouped = A.n_groups > 0;
+    S->group_pending = false;
+    if (!S->no_group && o.kernel == DRTS_KERNEL_CSR &&
+        (spmm_of(S) ? o.variant == DRTS_SPMM_GROUPED : o.variant == DRTS_SPMV_GROUPED) && !long_rows(A)) {
+        if (A.n_groups < 0) S->group_pending = true;
+        else S->grouped = A.n_groups > 0;
     }
     // a work item of the many-rhs matrix-free step is one tile (kStructVoxPerChunk
     // voxels); its kernels, and the step by row groups, keep one set of
@@ -589,10 +610,20 @@ int prepare(drts_solver *S)
         n_part = S->sa.mm_push_grid + (S->n_xchunks > 0 ? S->sa.mm_pull_grid : 0);
     }
     if (S->grouped) {
-        // the workgroups launch_step starts for this work list
-        n_part = std::min<int64_t>(S->grid, (S->n_chunks + 7) / 8 * 8);
+        // partials per work item and wave; detector entries by detector; the
+        // groups holding source rows
+        n_part = 4 * S->n_chunks;
         std::vector<int64_t> ptr, row;
         if ((rc = upload_dets_by_detector(S, &ptr, &row))) return rc;
+        std::vector<int64_t> srows;
+        for (const SourceEntry &e : S->srcs)
+            if (srows.empty() || srows.back() != e.row) srows.push_back(e.row);
+        Buffer sr;
+        if ((rc = upload_vec(dev, sr, srows))) return rc;
+        if ((rc = S->grp_src.allocate(&dev, (size_t)((A.n_groups + 31) / 32 + 1) * sizeof(uint32_t)))) return rc;
+        if ((rc = group_flags(A, sr.as<int64_t>(), (int64_t)srows.size(), S->grp_src.as<uint32_t>(), dev.stream)))
+            return rc;
+        DRTS_HIP(hipStreamSynchronize(dev.stream));
     }
     if (S->n_chunks > INT32_MAX) return set_error(DRTS_E_RANGE, "too many chunks");
 
@@ -652,13 +683,11 @@ int prepare(drts_solver *S)
     I.vox_mul = vox_mul_of(A.model.n_dir);
     I.max_steps = S->max_steps;
     if (S->grouped) {
-        I.grp_ptr = A.grp_ptr.as<int32_t>();
+        I.grp = A.grp_desc.as<GroupDesc>();
         I.grp_row = A.grp_row.as<int32_t>();
         I.grp_mat = A.grp_mat.as<uint8_t>();
         I.grp_val = A.grp_val.as<float>();
-        I.grp_voff = A.grp_voff.as<int64_t>();
-        I.grp_coff = A.grp_coff.as<int64_t>();
-        I.grp_len = A.grp_len.as<int32_t>();
+        I.grp_src = S->grp_src.as<uint32_t>();
         I.n_groups = A.n_groups;
         I.det_direct = 1;
         I.ddet_ptr = S->ddet_ptr.as<int64_t>();
@@ -798,9 +827,16 @@ hipEvent_t next_event(drts_solver *S)
     return S->ev_pool[S->ev_used++];
 }
 
-// Matrices whose rows hold several hundred entries (the multi-voxel weights of
-// Lebedev media) step with the wave-per-row SpMV.
-bool long_rows(const Matrix &A) { return A.model.n_rows > 0 && A.nnz >= (int64_t)kLongRowMean * A.model.n_rows; }
+
+// The single-rhs kernel a solver's CSR step takes: rows of several hundred
+// entries the wave-per-row step, rows that group (FP32) the grouped step, a
+// grouped request on rows that do not group the LDS layout.
+int spmv_variant(const drts_solver *S)
+{
+    if (long_rows(S->A->m)) return kVariantLongRows;
+    if (S->grouped) return DRTS_SPMV_GROUPED;
+    return S->opt.variant == DRTS_SPMV_GROUPED ? DRTS_SPMV_LDS : S->opt.variant;
+}
 
 // One step's launches.  inst (NULL = the solver's own) is the device copy of
 // the step descriptor the kernels read (matrix, state, partials, series);
@@ -820,7 +856,7 @@ int launch_one(drts_solver *S, hipStream_t stream, const StepInst *inst = nullpt
     }
     if (!structured_of(S) && !A.has_csr)
         return set_error(DRTS_E_STATE, "the CSR step needs the matrix's CSR arrays (built without them)");
-    int32_t *queue = (!spmm && S->opt.queue && S->opt.kernel == DRTS_KERNEL_CSR)
+    int32_t *queue = (!spmm && S->opt.queue && S->opt.kernel == DRTS_KERNEL_CSR && !S->grouped)
                          ? (inst ? queue_override : S->queue.as<int32_t>())
                          : nullptr;
     hipError_t e;
@@ -832,7 +868,7 @@ int launch_one(drts_solver *S, hipStream_t stream, const StepInst *inst = nullpt
                               A.model.value_type == DRTS_F64, structured_mode(S), S->grid,
                               S->opt.xcd_remap ? 1 : 0, S->xcd_bounds.as<int64_t>(), stream);
     } else {
-    const int variant = long_rows(A) ? kVariantLongRows : S->opt.variant;
+    const int variant = spmv_variant(S);
     e = launch_step(insts, S->work_dev.as<WorkItem>(), S->n_chunks, 1, S->n_rhs,
                                A.model.value_type == DRTS_F64, A.rp64 ? 1 : 0, spmm ? (S->grouped ? 2 : 1) : 0, S->grid,
                                (S->opt.xcd_remap ? 1 : 0) | ((variant & 15) << 1), S->xcd_bounds.as<int64_t>(),
@@ -887,20 +923,21 @@ int ensure_graph(drts_solver *S, int K)
 drts_options_t default_options(const drts_solver *S)
 {
     // defaults measured on MI355X: one rhs on the 128^3 three-layer workload
-    // (256-row tiles, 4 tiles per chunk, 64 workgroups per CU launched: the
-    // surplus waits and gives dynamic balance; fixed walk; FP32 values go
-    // straight to LDS), 64 rhs on the 96^3 slab (by row groups; work items
-    // of 64-row tiles x 16, 16 workgroups per CU, round-robin walk)
+    // (FP32: by row groups, work items of 256-row tiles x 16; FP64: the
+    // tiled step, 4 tiles per chunk; 64 workgroups per CU launched: the
+    // surplus waits and gives dynamic balance; round-robin walk), 64 rhs on
+    // the 96^3 slab (by row groups; work items of 64-row tiles x 32, 32
+    // workgroups per CU)
+    const bool f64 = S->A->m.model.value_type == DRTS_F64;
     drts_options_t o{};
     o.kernel = DRTS_KERNEL_CSR;
     o.rows_per_tile = spmm_of(S) ? 64 : 256;
-    o.tiles_per_chunk = spmm_of(S) ? 16 : 4;
-    o.grid = device_cu_count() * (spmm_of(S) ? 16 : 64);
+    o.tiles_per_chunk = spmm_of(S) ? 32 : (f64 ? 4 : 16);
+    o.grid = device_cu_count() * (spmm_of(S) ? 32 : 64);
     o.xcd_remap = 0;
     o.graph_steps = 0;
     o.rescale = 1;
-    o.variant = spmm_of(S) ? DRTS_SPMM_GROUPED
-                           : (S->A->m.model.value_type == DRTS_F64 ? DRTS_SPMV_ROW : DRTS_SPMV_LDS);
+    o.variant = spmm_of(S) ? DRTS_SPMM_GROUPED : (f64 ? DRTS_SPMV_ROW : DRTS_SPMV_GROUPED);
     o.queue = 0;
     return o;
 }
@@ -934,10 +971,11 @@ int check_options(const drts_solver *S, const drts_options_t *o)
     if (S->n_rhs > 1 && o->variant != DRTS_SPMM_GROUPED && o->variant != DRTS_SPMM_ROWS)
         return set_error(DRTS_E_INVALID, "variant %d: many rhs take DRTS_SPMM_GROUPED or DRTS_SPMM_ROWS",
                          o->variant);
-    if (o->variant < DRTS_SPMV_ROW || o->variant > DRTS_SPMV_WAVE_LDS)
+    if (o->variant < DRTS_SPMV_ROW || o->variant > DRTS_SPMV_GROUPED)
         return set_error(DRTS_E_INVALID, "unknown variant %d", o->variant);
-    if ((o->variant == DRTS_SPMV_LDS || o->variant == DRTS_SPMV_WAVE_LDS) && S->A->m.model.value_type == DRTS_F64)
-        return set_error(DRTS_E_INVALID, "the LDS variants take FP32 values");
+    if (S->n_rhs == 1 && (o->variant == DRTS_SPMV_LDS || o->variant == DRTS_SPMV_WAVE_LDS ||
+                          o->variant == DRTS_SPMV_GROUPED) && S->A->m.model.value_type == DRTS_F64)
+        return set_error(DRTS_E_INVALID, "the LDS and grouped variants take FP32 values");
     if ((o->variant == DRTS_SPMV_WAVE || o->variant == DRTS_SPMV_WAVE_PIPE || o->variant == DRTS_SPMV_WAVE_LDS) &&
         S->n_rhs == 1 && o->kernel == DRTS_KERNEL_CSR && o->rows_per_tile != 64)
         return set_error(DRTS_E_INVALID, "the wave variants take rows_per_tile = 64");
@@ -1220,6 +1258,7 @@ int drts_step(drts_solver_t *S, const drts_source_table_t *src)
     if (!S) return set_error(DRTS_E_INVALID, "solver is NULL");
     if (S->t_host + 1 > S->max_steps) return set_error(DRTS_E_RANGE, "step %lld beyond max_steps", (long long)S->t_host);
     int rc = set_sources(S, src);
+    if (!rc) rc = settle_groups(S);
     if (!rc) rc = upload_amplitudes(S, src, S->t_host, 1);
     if (!rc) rc = launch_one(S, S->dev.stream);
     if (rc) return rc;
@@ -1323,8 +1362,10 @@ int drts_run(drts_solver_t *S, const drts_source_table_t *src, int64_t n_steps)
     if (n_steps < 0 || S->t_host + n_steps > S->max_steps)
         return set_error(DRTS_E_RANGE, "steps %lld..%lld beyond max_steps %lld", (long long)S->t_host,
                          (long long)(S->t_host + n_steps), (long long)S->max_steps);
-    // a run of zero steps only stages the source table
+    // a run of zero steps only stages the source table (and lays the solver
+    // out for its step)
     int rc = set_sources(S, src);
+    if (!rc) rc = settle_groups(S);
     if (rc || n_steps == 0) return rc;
     rc = upload_amplitudes(S, src, S->t_host, n_steps);
     if (rc) return rc;
@@ -1528,7 +1569,9 @@ int batch_launch(drts_batch *B, int64_t n_work, int n_inst, int rows_per_tile, h
     else
         e = launch_step(B->inst_dev.as<StepInst>(), B->work_dev.as<WorkItem>(), n_work, n_inst, 1, 0,
                         S0->A->m.rp64 ? 1 : 0, 0, grid,
-                        ((long_rows(S0->A->m) ? kVariantLongRows : S0->opt.variant) & 15) << 1, nullptr,
+                        ((long_rows(S0->A->m) ? kVariantLongRows
+                                              : (S0->opt.variant == DRTS_SPMV_GROUPED ? DRTS_SPMV_LDS
+                                                                                      : S0->opt.variant)) & 15) << 1, nullptr,
                         rows_per_tile, 0, queue, stream);
     if (e != hipSuccess) return set_error(DRTS_E_HIP, "batch step launch failed: %s", hipGetErrorString(e));
     e = launch_finalize(B->inst_dev.as<StepInst>(), n_inst, 1, 0, queue, stream);
@@ -1553,6 +1596,15 @@ int drts_batch_create(drts_solver_t *const *solvers, int32_t n, const drts_devic
         if (S->A->m.rp64 != rp64) return set_error(DRTS_E_INVALID, "solver %d: mixed row-pointer widths", i);
         for (int j = 0; j < i; ++j)
             if (solvers[j] == S) return set_error(DRTS_E_INVALID, "solver %d appears twice", i);
+    }
+    // batch members take the tiled step (their instances share one launch)
+    for (int i = 0; i < n; ++i) {
+        drts_solver *S = solvers[i];
+        S->no_group = true;
+        if (S->grouped || S->group_pending) {
+            const int e = prepare(S);
+            if (e) return e;
+        }
     }
     drts_batch *B = new (std::nothrow) drts_batch;
     if (!B) return set_error(DRTS_E_NOMEM, "host allocation failed");
@@ -1868,7 +1920,7 @@ static std::string tune_key(const drts_solver *S)
     const int rows_cls = (int)std::lround(std::log2((double)std::max<int64_t>(A.model.n_rows, 1)));
     const int nnz_row = (int)std::lround((double)A.nnz / std::max<int64_t>(A.model.n_rows, 1));
     char buf[128];
-    snprintf(buf, sizeof buf, "drts1:rhs%d:f%d:rows2^%d:nnzrow%d:cu%d", S->n_rhs,
+    snprintf(buf, sizeof buf, "drts2:rhs%d:f%d:rows2^%d:nnzrow%d:cu%d", S->n_rhs,
              A.model.value_type == DRTS_F64 ? 64 : 32, rows_cls, nnz_row, device_cu_count());
     return buf;
 }
@@ -1877,6 +1929,11 @@ int drts_autotune(drts_solver_t *S, const char *cache_path, drts_options_t *chos
 {
     if (!S) return set_error(DRTS_E_INVALID, "solver is NULL");
     if (S->t_host != 0) return set_error(DRTS_E_STATE, "autotune before the first step");
+    // the grouped candidates need the matrix's row groups
+    if (!S->no_group && S->opt.kernel == DRTS_KERNEL_CSR && S->A->m.model.value_type == DRTS_F32) {
+        int rg = row_groups(S->A->m);
+        if (rg) return rg;
+    }
     const std::string key = tune_key(S);
     drts_options_t best = S->opt;
     if (cache_path) {
@@ -1920,7 +1977,8 @@ int drts_autotune(drts_solver_t *S, const char *cache_path, drts_options_t *chos
         for (int c : chunk_opts)
             for (int g : grid_mult)
                 for (int x = 0; x < 3; ++x)
-                    for (int pl = 0; pl <= (spmm ? 0 : DRTS_SPMV_WAVE_LDS); ++pl) {
+                    for (int pl = 0; pl <= (spmm ? 0 : DRTS_SPMV_GROUPED); ++pl) {
+                        if (pl == DRTS_SPMV_GROUPED && (A.model.value_type == DRTS_F64 || S->no_group)) continue;
                         if ((pl == DRTS_SPMV_WAVE || pl == DRTS_SPMV_WAVE_PIPE || pl == DRTS_SPMV_WAVE_LDS) && r != 64)
                             continue;
                         if ((pl == DRTS_SPMV_LDS || pl == DRTS_SPMV_WAVE_LDS) && A.model.value_type == DRTS_F64) continue;

@@ -10,10 +10,11 @@
 // a row starts a new group unless its key and whole column list equal its
 // predecessor's, and a scan numbers the groups.  Groups of more than
 // kGroupMax rows are split on the host.  When the rows group (at least two a
-// group on average) the values are copied in group order -- every member's
-// entries in turn, so a group's values are one contiguous block -- with each
-// member's row and material beside them: the step then reads every array it
-// needs of a group contiguously.
+// group on average) the values are copied in group order -- a group's values
+// one contiguous block, column-major (entry k of every member, then entry
+// k+1) -- with each member's row and material beside them: the steps then
+// read every array they need of a group contiguously, and the members' k-th
+// entries with one coalesced load.
 #include <algorithm>
 #include <vector>
 
@@ -70,29 +71,67 @@ __global__ void __launch_bounds__(256) member_info(const int32_t *grp_row, const
     gmat[i] = r < n_states ? mat[(int64_t)__umul64hi((uint64_t)r, vox_mul)] : (uint8_t)0;
 }
 
-// values in group order: member i's entries at moff[i] onwards
+// per group its descriptor: members, offset of its values (the first
+// member's offset in the scan of entry counts), its leader's columns and
+// whether they are one run
 template <typename IT>
-__global__ void __launch_bounds__(256) member_values(const int32_t *grp_row, const IT *rp, const float *val,
-                                                     const int64_t *moff, int64_t n, float *gval)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t r = grp_row[i], lo = (int64_t)rp[r], hi = (int64_t)rp[r + 1], o = moff[i];
-    for (int64_t k = lo; k < hi; ++k) gval[o + (k - lo)] = val[k];
-}
-
-// per group: offset of its values, of its leader's columns, entries a row
-template <typename IT>
-__global__ void __launch_bounds__(256) group_offsets(const int32_t *grp_ptr, const int32_t *grp_row, const IT *rp,
-                                                     const int64_t *moff, int64_t n_groups, int64_t *voff,
-                                                     int64_t *coff, int32_t *len)
+__global__ void __launch_bounds__(256) group_descs(const int32_t *grp_ptr, const int32_t *grp_row, const IT *rp,
+                                                   const int32_t *col, const int64_t *moff, int64_t n_groups,
+                                                   GroupDesc *desc)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n_groups) return;
     const int64_t r = grp_row[grp_ptr[g]];
-    voff[g] = moff[grp_ptr[g]];
-    coff[g] = (int64_t)rp[r];
-    len[g] = (int32_t)((int64_t)rp[r + 1] - (int64_t)rp[r]);
+    const int64_t lo = (int64_t)rp[r], n = (int64_t)rp[r + 1] - lo;
+    GroupDesc D;
+    D.voff = moff[grp_ptr[g]];
+    D.coff = lo;
+    D.m0 = grp_ptr[g];
+    D.nm = grp_ptr[g + 1] - grp_ptr[g];
+    D.n = (int32_t)n;
+    D.cstart = n > 0 ? col[lo] : -1;
+    for (int64_t k = 1; k < n && D.cstart >= 0; ++k)
+        if (col[lo + k] != col[lo] + k) D.cstart = -1;
+    desc[g] = D;
+}
+
+// values in group order, column-major within a group: entry k of member j of
+// group g at voff + k * nm + j
+template <typename IT>
+__global__ void __launch_bounds__(256) group_values(const GroupDesc *desc, const int32_t *grp_row, const IT *rp,
+                                                    const float *val, int64_t n_groups, float *gval)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_groups) return;
+    const GroupDesc D = desc[g];
+    for (int j = 0; j < D.nm; ++j) {
+        const int64_t lo = (int64_t)rp[grp_row[D.m0 + j]];
+        for (int k = 0; k < D.n; ++k) gval[D.voff + (int64_t)k * D.nm + j] = val[lo + k];
+    }
+}
+
+// bit g: a member of group g is in the ascending row list rows[0 .. n)
+__global__ void __launch_bounds__(256) group_flag_bits(const GroupDesc *desc, const int32_t *grp_row,
+                                                       int64_t n_groups, const int64_t *rows, int64_t n,
+                                                       uint32_t *bits)
+{
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // one word of 32 groups
+    if (w * 32 >= n_groups) return;
+    uint32_t word = 0;
+    for (int b = 0; b < 32 && w * 32 + b < n_groups; ++b) {
+        const GroupDesc D = desc[w * 32 + b];
+        for (int j = 0; j < D.nm; ++j) {
+            const int64_t r = grp_row[D.m0 + j];
+            int64_t lo = 0, hi = n;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (rows[mid] < r) lo = mid + 1;
+                else hi = mid;
+            }
+            if (lo < n && rows[lo] == r) word |= 1u << b;
+        }
+    }
+    bits[w] = word;
 }
 
 __global__ void __launch_bounds__(256) group_scatter(const int32_t *flag, const int32_t *pos, int64_t n,
@@ -174,8 +213,9 @@ int build_groups(Matrix &A)
         A.n_groups = 0;
         return DRTS_OK;
     }
-    if ((rc = A.grp_ptr.allocate(&dev, out.size() * sizeof(int32_t)))) return rc;
-    DRTS_HIP(hipMemcpyAsync(A.grp_ptr.ptr, out.data(), out.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+    Buffer gptr;
+    if ((rc = gptr.allocate(&dev, out.size() * sizeof(int32_t)))) return rc;
+    DRTS_HIP(hipMemcpyAsync(gptr.ptr, out.data(), out.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                             dev.stream));
     // members' entry counts and materials, their value offsets (a scan), the
     // values in group order and the per-group offsets
@@ -195,18 +235,16 @@ int build_groups(Matrix &A)
                                              dev.stream));
     tmp.reset();
     len.reset();
+    if ((rc = A.grp_desc.allocate(&dev, G * sizeof(GroupDesc)))) return rc;
+    const unsigned gblocks = (unsigned)((G + 255) / 256);
+    hipLaunchKernelGGL(group_descs<IT>, dim3(gblocks), dim3(256), 0, dev.stream, gptr.as<int32_t>(),
+                       A.grp_row.as<int32_t>(), rp, col, moff.as<int64_t>(), G, A.grp_desc.as<GroupDesc>());
+    DRTS_HIP(hipGetLastError());
     // (the same padding after the last entry as the CSR values)
     if ((rc = A.grp_val.allocate(&dev, A.val.bytes))) return rc;
     DRTS_HIP(hipMemsetAsync(A.grp_val.ptr, 0, A.val.bytes, dev.stream));
-    hipLaunchKernelGGL(member_values<IT>, dim3(blocks), dim3(256), 0, dev.stream, A.grp_row.as<int32_t>(), rp,
-                       A.val.as<float>(), moff.as<int64_t>(), R, A.grp_val.as<float>());
-    DRTS_HIP(hipGetLastError());
-    if ((rc = A.grp_voff.allocate(&dev, G * sizeof(int64_t)))) return rc;
-    if ((rc = A.grp_coff.allocate(&dev, G * sizeof(int64_t)))) return rc;
-    if ((rc = A.grp_len.allocate(&dev, G * sizeof(int32_t)))) return rc;
-    hipLaunchKernelGGL(group_offsets<IT>, dim3((unsigned)((G + 255) / 256)), dim3(256), 0, dev.stream,
-                       A.grp_ptr.as<int32_t>(), A.grp_row.as<int32_t>(), rp, moff.as<int64_t>(), G,
-                       A.grp_voff.as<int64_t>(), A.grp_coff.as<int64_t>(), A.grp_len.as<int32_t>());
+    hipLaunchKernelGGL(group_values<IT>, dim3(gblocks), dim3(256), 0, dev.stream, A.grp_desc.as<GroupDesc>(),
+                       A.grp_row.as<int32_t>(), rp, A.val.as<float>(), G, A.grp_val.as<float>());
     DRTS_HIP(hipGetLastError());
     DRTS_HIP(hipStreamSynchronize(dev.stream));
     A.n_groups = G;
@@ -227,11 +265,21 @@ int row_groups(const Matrix &Ac)
     }
     const int rc = A.rp64 ? build_groups<int64_t>(A) : build_groups<int32_t>(A);
     if (rc) {
-        Buffer *b[] = {&A.grp_ptr, &A.grp_row, &A.grp_mat, &A.grp_val, &A.grp_voff, &A.grp_coff, &A.grp_len};
+        Buffer *b[] = {&A.grp_desc, &A.grp_row, &A.grp_mat, &A.grp_val};
         for (Buffer *x : b) x->reset();
         A.n_groups = -1;
     }
     return rc;
+}
+
+int group_flags(const Matrix &A, const int64_t *rows, int64_t n, uint32_t *bits, hipStream_t stream)
+{
+    const int64_t words = (A.n_groups + 31) / 32;
+    if (words <= 0) return DRTS_OK;
+    hipLaunchKernelGGL(group_flag_bits, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, stream,
+                       A.grp_desc.as<GroupDesc>(), A.grp_row.as<int32_t>(), A.n_groups, rows, n, bits);
+    DRTS_HIP(hipGetLastError());
+    return DRTS_OK;
 }
 
 }  // namespace drts

@@ -116,12 +116,11 @@ struct Matrix {
     Buffer mat_of_voxel, absorb, index, blocks64, blocks32;
     Buffer irr_row, irr_vox, irr_dir, irr_f, irr_bits, escape_state;
     Buffer pair_ptr, pair_key, pair_w, arr_ptr, arr_key, arr_w;   // Lebedev weights
-    // rows with equal column lists (built on first use by a many-rhs solver):
-    // group g is grp_row[grp_ptr[g] .. grp_ptr[g+1]-1]; per member (group
-    // order) its material; the values in group order; per group the offset
-    // of its values, of its leader's columns and its entries a row.
-    // n_groups < 0 = not built, 0 = the rows do not group
-    Buffer grp_ptr, grp_row, grp_mat, grp_val, grp_voff, grp_coff, grp_len;
+    // rows with equal column lists (built on first use by a solo solver that
+    // asks for the grouped step): per group a GroupDesc; per member (group
+    // order) its row and material; the values in group order (column-major
+    // within a group).  n_groups < 0 = not built, 0 = the rows do not group
+    Buffer grp_desc, grp_row, grp_mat, grp_val;
     int64_t n_groups = -1;
     int64_t bytes() const;         // the CSR arrays (and the row groups, once built)
     int64_t table_bytes() const;   // everything else on the device (tables of the model)
@@ -134,6 +133,9 @@ int assemble_on_device(Matrix *A, bool with_csr = true);
 // no CSR, FP64 values, 2^31 rows or more, or fewer than two rows a group on
 // average).
 int row_groups(const Matrix &A);
+// Per group of A one bit (words of 32): set when a member's row is in the
+// ascending list rows[0 .. n) (device memory).
+int group_flags(const Matrix &A, const int64_t *rows, int64_t n, uint32_t *bits, hipStream_t stream);
 
 // ---- windowed measurement (Eq. 27 over several steps) --------------------------
 struct WindowArgs {

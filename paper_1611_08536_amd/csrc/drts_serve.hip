@@ -192,6 +192,16 @@ int admit(drts_server *Q, Request &q)
     det.escape = q.det_esc.data();
     det.F = q.det_F.data();
     rc = drts_solver_create(q.A, 1, q.n_det > 0 ? &det : nullptr, q.n_steps, &bdev, &q.S);
+    if (!rc && Q->kernel == DRTS_KERNEL_CSR) {
+        // requests run batched: the tiled step (LDS layout, 4 tiles per chunk)
+        drts_options_t o{};
+        rc = drts_solver_get_options(q.S, &o);
+        if (!rc) {
+            o.variant = DRTS_SPMV_LDS;
+            o.tiles_per_chunk = 4;
+            rc = drts_solver_set_options(q.S, &o);
+        }
+    }
     if (!rc && Q->kernel != DRTS_KERNEL_CSR) {
         // the matrix-free step with its measured launch shape: 8 tiles per
         // chunk, 16 workgroups per CU

@@ -59,17 +59,14 @@ struct StepInst {
     int32_t n_mat;          // entries of absorb
     uint64_t vox_mul;       // vox_mul_of(directions per voxel): row -> voxel
     int64_t max_steps;
-    // many rhs: groups of rows with equal column lists (NULL = none); group
-    // g's members are grp_row[grp_ptr[g] .. grp_ptr[g+1]-1], ascending, at
-    // most kGroupMax of them, with their materials in grp_mat; its values
-    // (every member's grp_len[g] entries in turn) start at grp_val +
-    // grp_voff[g], its columns (the leader's) at col + grp_coff[g]
-    const int32_t *grp_ptr;
+    // the step by row groups: groups of rows with equal column lists (NULL =
+    // none), described by grp[g]; the members' rows and materials and the
+    // values in group order; grp_src bit g: a member of group g has sources
+    const struct GroupDesc *grp;
     const int32_t *grp_row;
     const uint8_t *grp_mat;
     const float *grp_val;
-    const int64_t *grp_voff, *grp_coff;
-    const int32_t *grp_len;
+    const uint32_t *grp_src;
     int64_t n_groups;
     // det_direct: the detector sums come from their own kernel (a value per
     // detector and rhs after the finalize segments of the partials, see
@@ -120,12 +117,26 @@ struct WorkItem {
 // Launch variant (bits 1..4 of xcd_remap) of the wave-per-row SpMV for rows of
 // several hundred entries; chosen by the library for such matrices, not an
 // option of the caller.
-constexpr int kVariantLongRows = 9;
+constexpr int kVariantLongRows = 10;
 // mean entries per row from which a matrix takes the wave-per-row SpMV
 constexpr int kLongRowMean = 96;
 
 // Members of one row group at most (larger sets of equal rows are split).
 constexpr int kGroupMax = 26;
+
+// One row group (rows with equal column lists): its members are grp_row and
+// grp_mat [m0, m0 + nm), rows ascending; its values start at grp_val + voff,
+// column-major (entry k of member j at k * nm + j, n entries a member); its
+// columns are the leader's, col [coff, coff + n), or the run cstart,
+// cstart + 1, ... when they are one (cstart = -1 otherwise).
+struct alignas(16) GroupDesc {
+    int64_t voff;
+    int64_t coff;
+    int32_t m0;
+    int32_t nm;
+    int32_t n;
+    int32_t cstart;
+};
 
 // Launches the SpMV (n_rhs == 1) or SpMM step over a work list.  xcd_remap
 // bit 0 selects the XCD-aware order, bit 1 the pipelined SpMV.  Returns a

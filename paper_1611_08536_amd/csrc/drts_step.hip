@@ -1590,6 +1590,20 @@ __global__ void __launch_bounds__(kNT) step_spmm(const StepInst *__restrict__ in
     }
 }
 
+// A group descriptor read field by field (a struct copy from the global or
+// constant address space has no constructor)
+template <typename P> __device__ __forceinline__ GroupDesc load_desc(P p)
+{
+    GroupDesc D;
+    D.voff = p->voff;
+    D.coff = p->coff;
+    D.m0 = p->m0;
+    D.nm = p->nm;
+    D.n = p->n;
+    D.cstart = p->cstart;
+    return D;
+}
+
 // ---------------------------------------------------------------------------
 // SpMM step by row groups (n_rhs right-hand sides, FP32, one solver), lanes = rhs
 //
@@ -1597,28 +1611,30 @@ __global__ void __launch_bounds__(kNT) step_spmm(const StepInst *__restrict__ in
 // rows that pull from one source voxel (one per direction, state or escape
 // row) all hold that voxel's whole state.  The matrix keeps, beside its CSR,
 // the values in group order and each member's row and material, so every
-// array the step reads of a group is contiguous.  A wave takes a group at a
-// time: the group's offsets come through the scalar cache, lane j fetches
-// member j's row, material and whether its tile has sources; the leader's
-// columns are read once and the X rows they name are gathered once into
-// registers (one coalesced 4*n_rhs-byte row per column); every member's
-// values come with one coalesced load and are applied to those registers.
-// Each X row is then fetched about once per step instead of once per entry.  A member is formed with the same products in
-// the same column order as in the row-by-row kernel and the single-rhs step,
-// so every column of the result equals theirs bit for bit.  Groups whose rows
-// are not kSpmmUnroll long are formed row by row (windows of 64 entries).
+// array the step reads of a group is contiguous, and one descriptor per
+// group (read through the scalar cache).  A wave takes a group at a time:
+// lane j fetches member j's row and material; the X rows of the group's
+// columns are gathered once into registers (one coalesced 4*n_rhs-byte row
+// per column; a group whose columns are one run needs no column load at
+// all); lane m of load k holds member m's entry k, and member m's row is
+// formed from those registers by readlane.  Each X row is then fetched about
+// once per step instead of once per entry.  A member is formed with the same
+// products in the same column order as in the row-by-row kernel and the
+// single-rhs step, so every column of the result equals theirs bit for bit.
+// Groups whose rows are not kSpmmUnroll long are formed row by row (windows
+// of 64 entries).  Sources are looked up only in groups the solver flagged.
 //
-// Work item c takes groups c * n_groups / n_work onwards; its waves take
-// every fourth group.  A workgroup sums the totals of all its work items (a
-// fixed walk) and writes one set of partials, at its own index; the detector
-// sums are left to spmm_detectors, which reads the stored rows.
+// Work item c takes groups c * n_groups / n_work onwards, a quarter of them
+// (contiguous) to each wave; a wave's totals over its quarter are the
+// partials of index 4c + wave, so the sums do not depend on which workgroup
+// takes which item.  The detector sums are left to spmm_detectors, which
+// reads the stored rows.
 // ---------------------------------------------------------------------------
 template <typename IT>
 __global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(5, 8))) step_spmm_grouped(const StepInst *__restrict__ insts,
                                                           const WorkItem *__restrict__ work, int64_t n_work,
                                                           int xcd_remap, const int64_t *__restrict__ xcd_bounds)
 {
-    __shared__ double s_w[4][4][64];     // per-wave totals for the fixed-order combine
     __shared__ double s_abs[kMatMax];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1639,33 +1655,31 @@ __global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(5, 8))
     const GLB uint8_t *gmat = gp(I.grp_mat);
     const GLB int32_t *grow = gp(I.grp_row);
     const GLB int32_t *src_tile = gp(I.src_tile);
-    const CST int32_t *gptr = cst(I.grp_ptr);
-    const CST int32_t *glen = cst(I.grp_len);
-    const CST int64_t *gvoff = cst(I.grp_voff);
-    const CST int64_t *gcoff = cst(I.grp_coff);
+    const CST GroupDesc *grp = cst(I.grp);
+    const CST uint32_t *gsrc = cst(I.grp_src);
     for (int q = threadIdx.x; q < I.n_mat; q += kNT) s_abs[q] = gp(I.absorb)[q];
     __syncthreads();
 
-    double sN = 0.0, sE = 0.0, sA = 0.0;
-    float mx = 0.0f;
     const int R = I.rows_per_tile;
-    const int64_t G = I.n_groups;
+    const int64_t G = I.n_groups, nc = I.n_chunks;
     for (int64_t wi = wk.begin; wi < wk.end; wi += wk.stride) {
         const int64_t c = work[wi].chunk;
-        const int64_t g_b = c * G / n_work, g_e = (c + 1) * G / n_work;
-        for (int64_t g = g_b + wave; g < g_e; g += 4) {
-            const int m0 = gptr[g];
-            const int nm = gptr[g + 1] - m0;
-            const int n = glen[g];
-            const int64_t voff = gvoff[g], coff = gcoff[g];
+        const int64_t c_b = c * G / n_work, c_e = (c + 1) * G / n_work;
+        const int64_t g_b = c_b + wave * (c_e - c_b) / 4, g_e = c_b + (wave + 1) * (c_e - c_b) / 4;
+        double sN = 0.0, sE = 0.0, sA = 0.0;
+        float mx = 0.0f;
+        for (int64_t g = g_b; g < g_e; ++g) {
+            const GroupDesc D = load_desc(grp + g);
+            const bool g_src = (gsrc[g >> 5] >> (g & 31)) & 1u;
+            const int m0 = D.m0, nm = D.nm, n = D.n;
             // lane j (< nm): member j
             const int jl = min(lane, nm - 1);
             const int32_t my_r = grow[m0 + jl];
             const int my_mat = gmat[m0 + jl];
+            int my_tile = 0;
+            uint64_t src_mask = 0;
 
             // member m's result: rescale, sources, store, totals
-            uint64_t src_mask = 0;
-            int my_tile = 0;
             auto emit = [&](int m, float acc) {
                 const int64_t r = __builtin_amdgcn_readlane(my_r, m);
                 float v = acc * scale;
@@ -1694,41 +1708,58 @@ __global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(5, 8))
                     }
                 }
             };
+            auto flag_sources = [&]() {
+                if (g_src) {
+                    my_tile = my_r / R;
+                    src_mask = __builtin_amdgcn_ballot_w64(src_tile[my_tile + 1] > src_tile[my_tile]);
+                }
+            };
 
             if (n == kSpmmUnroll) {
-                const int32_t cl = col[coff + min(lane, kSpmmUnroll - 1)];
-                float vv[kGroupMax];
-#pragma unroll
-                for (int m = 0; m < kGroupMax; ++m)
-                    if (m < nm) vv[m] = val[voff + m * kSpmmUnroll + min(lane, kSpmmUnroll - 1)];
-                my_tile = my_r / R;
-                src_mask = __builtin_amdgcn_ballot_w64(src_tile[my_tile + 1] > src_tile[my_tile]);
                 float xv[kSpmmUnroll];
+                if (D.cstart >= 0) {
+                    // one run of columns: a buffer at its first X row, the
+                    // rows at scalar offsets
+                    const __amdgpu_buffer_rsrc_t rx =
+                        make_rsrc((const void *)(X + (int64_t)D.cstart * nrhs), (uint64_t)kSpmmUnroll * nrhs * 4);
+#pragma unroll
+                    for (int k = 0; k < kSpmmUnroll; ++k)
+                        xv[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rx, xl * 4, k * nrhs * 4, 0));
+                } else {
+                    const int32_t cl = col[D.coff + min(lane, kSpmmUnroll - 1)];
+#pragma unroll
+                    for (int k = 0; k < kSpmmUnroll; ++k)
+                        xv[k] = X[(int64_t)__builtin_amdgcn_readlane(cl, k) * nrhs + xl];
+                }
+                // vk[k]: lane m holds member m's entry k (a buffer at the
+                // group's values, entry k at a scalar offset)
+                const __amdgpu_buffer_rsrc_t rv =
+                    make_rsrc((const void *)(val + D.voff), (uint64_t)kSpmmUnroll * nm * 4);
+                float vk[kSpmmUnroll];
 #pragma unroll
                 for (int k = 0; k < kSpmmUnroll; ++k)
-                    xv[k] = X[(int64_t)__builtin_amdgcn_readlane(cl, k) * nrhs + xl];
+                    vk[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rv, jl * 4, k * nm * 4, kStream));
+                flag_sources();
 #pragma unroll
                 for (int m = 0; m < kGroupMax; ++m) {
                     if (m < nm) {
                         float acc = 0.0f;
 #pragma unroll
                         for (int k = 0; k < kSpmmUnroll; ++k)
-                            acc += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vv[m]), k)) * xv[k];
+                            acc += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vk[k]), m)) * xv[k];
                         emit(m, acc);
                     }
                 }
             } else {
-                my_tile = my_r / R;
-                src_mask = __builtin_amdgcn_ballot_w64(src_tile[my_tile + 1] > src_tile[my_tile]);
+                flag_sources();
                 for (int m = 0; m < nm; ++m) {
-                    const int64_t mv = voff + (int64_t)m * n;
                     float acc = 0.0f;
                     for (int wb = 0; wb < n; wb += 64) {
                         int32_t cw = 0;
                         float vw = 0.0f;
                         if (wb + lane < n) {
-                            cw = col[coff + wb + lane];
-                            vw = val[mv + wb + lane];
+                            cw = col[D.coff + wb + lane];
+                            vw = val[D.voff + (int64_t)(wb + lane) * nm + m];
                         }
                         const int w = min(64, n - wb);
                         int k = 0;
@@ -1750,23 +1781,13 @@ __global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(5, 8))
                 }
             }
         }
-    }
-    // the workgroup's totals, waves combined in a fixed order
-    s_w[0][wave][lane] = sN;
-    s_w[1][wave][lane] = sE;
-    s_w[2][wave][lane] = sA;
-    s_w[3][wave][lane] = (double)mx;
-    __syncthreads();
-    if (wave == 0 && active) {
-        const int64_t nc = I.n_chunks, b = blockIdx.x;
-        I.partials[((int64_t)kSlotN * nrhs + lane) * nc + b] =
-            ((s_w[0][0][lane] + s_w[0][1][lane]) + s_w[0][2][lane]) + s_w[0][3][lane];
-        I.partials[((int64_t)kSlotEsc * nrhs + lane) * nc + b] =
-            ((s_w[1][0][lane] + s_w[1][1][lane]) + s_w[1][2][lane]) + s_w[1][3][lane];
-        I.partials[((int64_t)kSlotAbs * nrhs + lane) * nc + b] =
-            ((s_w[2][0][lane] + s_w[2][1][lane]) + s_w[2][2][lane]) + s_w[2][3][lane];
-        I.partials[((int64_t)kSlotMax * nrhs + lane) * nc + b] =
-            fmax(fmax(s_w[3][0][lane], s_w[3][1][lane]), fmax(s_w[3][2][lane], s_w[3][3][lane]));
+        if (active) {
+            const int64_t b = 4 * c + wave;
+            I.partials[((int64_t)kSlotN * nrhs + lane) * nc + b] = sN;
+            I.partials[((int64_t)kSlotEsc * nrhs + lane) * nc + b] = sE;
+            I.partials[((int64_t)kSlotAbs * nrhs + lane) * nc + b] = sA;
+            I.partials[((int64_t)kSlotMax * nrhs + lane) * nc + b] = (double)mx;
+        }
     }
 }
 
@@ -1796,6 +1817,167 @@ __global__ void __launch_bounds__(kNT) spmm_detectors(const StepInst *__restrict
     if (wave == 0 && lane < nrhs)
         det_direct_sums(I.partials, I.n_det, nrhs, I.n_chunks)[((int64_t)d * kDetParts + p) * nrhs + lane] =
             ((s_d[0][lane] + s_d[1][lane]) + s_d[2][lane]) + s_d[3][lane];
+}
+
+// ---------------------------------------------------------------------------
+// SpMV step by row groups (one rhs, FP32, one solver)
+//
+// The row groups and the group-order arrays of the many-rhs step; here the
+// lanes are the members: each half-wave takes a group (lane m of the half is
+// member m), so a wave forms two groups at once, and the descriptors of the
+// wave's next two groups load while the current two are formed.  Lane m
+// loads x at column m (directly when the columns are one run, else through
+// the leader's column list) into LDS, then its own entries with one load per
+// k (the group's values are column-major, so a group's k-th entries are one
+// contiguous run) and adds entry * x over k in column order: the CSR step's
+// products in its order, so y equals its y bit for bit.  The matrix stream
+// is the values alone -- a group's columns are read once at most, not once
+// per row -- and x is read once per group.  Rows of other lengths than
+// kSpmmUnroll go through LDS in windows of 32 columns.  Work items are split
+// among the waves as in the many-rhs step (partials of index 4c + wave); the
+// detector sums are left to spmv_detectors.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kNT) step_spmv_grouped(const StepInst *__restrict__ insts,
+                                                          const WorkItem *__restrict__ work, int64_t n_work,
+                                                          int xcd_remap, const int64_t *__restrict__ xcd_bounds)
+{
+    __shared__ float s_x[4][2][32];   // per wave and half: x at the group's columns
+    __shared__ double s_abs[kMatMax];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int h = lane >> 5, m = lane & 31;
+    const Walk wk = walk_of(n_work, xcd_remap, xcd_bounds);
+    const StepInst &I = insts[0];
+    const int64_t t = I.t[0];
+    if (t >= *I.t_end) return;
+    const Scale sc = step_scale(I, 0, t);
+    const float scale = ldexpf(1.0f, -sc.k);
+    const GLB int32_t *col = gp(I.col);
+    const GLB float *val = gp(I.grp_val);
+    const GLB float *X = gp((const float *)((t & 1) ? I.buf1 : I.buf0));
+    GLB float *Y = gpw((float *)((t & 1) ? I.buf0 : I.buf1));
+    const GLB uint8_t *gmat = gp(I.grp_mat);
+    const GLB int32_t *grow = gp(I.grp_row);
+    const GLB int32_t *src_tile = gp(I.src_tile);
+    const CST GroupDesc *grp = cst(I.grp);
+    const CST uint32_t *gsrc = cst(I.grp_src);
+    float *sx = s_x[wave][h];
+    const int64_t nv = I.nnz + 4;   // entries of the group-order values (with the padding)
+    for (int q = threadIdx.x; q < I.n_mat; q += kNT) s_abs[q] = gp(I.absorb)[q];
+    __syncthreads();
+
+    const int R = I.rows_per_tile;
+    const int64_t G = I.n_groups;
+    for (int64_t wi = wk.begin; wi < wk.end; wi += wk.stride) {
+        const int64_t c = work[wi].chunk;
+        const int64_t c_b = c * G / n_work, c_e = (c + 1) * G / n_work;
+        const int64_t g_b = c_b + wave * (c_e - c_b) / 4, g_e = c_b + (wave + 1) * (c_e - c_b) / 4;
+        double sN = 0.0, sE = 0.0, sA = 0.0;
+        float mx = 0.0f;
+        if (g_b < g_e) {
+            // the wave's two groups (a lone last group: both halves take it),
+            // descriptors and source bits through the scalar cache; the next
+            // pair's load while this pair is formed
+            GroupDesc D0 = load_desc(grp + g_b), D1 = load_desc(grp + min(g_b + 1, g_e - 1));
+            uint32_t w0 = gsrc[g_b >> 5], w1 = gsrc[min(g_b + 1, g_e - 1) >> 5];
+            for (int64_t g2 = g_b; g2 < g_e; g2 += 2) {
+                const int64_t ga = g2, gb = min(g2 + 1, g_e - 1);
+                const GroupDesc A0 = D0, A1 = D1;
+                const uint32_t s0 = w0, s1 = w1;
+                if (g2 + 2 < g_e) {
+                    D0 = load_desc(grp + g2 + 2);
+                    D1 = load_desc(grp + min(g2 + 3, g_e - 1));
+                    w0 = gsrc[(g2 + 2) >> 5];
+                    w1 = gsrc[min(g2 + 3, g_e - 1) >> 5];
+                }
+                // this half's group
+                const int nm = h ? A1.nm : A0.nm, n = h ? A1.n : A0.n;
+                const int m0 = h ? A1.m0 : A0.m0, cstart = h ? A1.cstart : A0.cstart;
+                const int64_t voff = h ? A1.voff : A0.voff, coff = h ? A1.coff : A0.coff;
+                const bool g_src = h ? ((s1 >> (gb & 31)) & 1u) : ((s0 >> (ga & 31)) & 1u);
+                const bool mine = g2 + h < g_e && m < nm;
+                const int jm = min(m, nm - 1);
+                const int32_t r = grow[m0 + jm];
+                const int mt = gmat[m0 + jm];
+                float acc = 0.0f;
+                if (A0.n == kSpmmUnroll && A1.n == kSpmmUnroll && A0.cstart >= 0 && A1.cstart >= 0) {
+                    const float xm = X[cstart + min(m, kSpmmUnroll - 1)];
+                    // a buffer at the first group's values; each lane's
+                    // entries at 32-bit offsets from it
+                    const __amdgpu_buffer_rsrc_t rv =
+                        make_rsrc((const void *)(val + A0.voff), (uint64_t)(nv - A0.voff) * 4);
+                    const uint32_t o0 = (uint32_t)(voff - A0.voff + jm) * 4, st = (uint32_t)nm * 4;
+                    float vk[kSpmmUnroll];
+#pragma unroll
+                    for (int k = 0; k < kSpmmUnroll; ++k)
+                        vk[k] = __builtin_bit_cast(float,
+                                                   __builtin_amdgcn_raw_buffer_load_b32(rv, (int)(o0 + k * st), 0, kStream));
+                    sx[m] = xm;
+#pragma unroll
+                    for (int k = 0; k < kSpmmUnroll; ++k) acc += vk[k] * sx[k];
+                } else {
+                    for (int kb = 0; kb < n; kb += 32) {
+                        const int w = min(32, n - kb);
+                        sx[m] = X[col[coff + kb + min(m, w - 1)]];
+                        for (int k = 0; k < w; ++k) acc += val[voff + (int64_t)(kb + k) * nm + jm] * sx[k];
+                    }
+                }
+                if (mine) {
+                    float v = acc * scale;
+                    if (g_src) {
+                        const int tile = r / R;
+                        const int sb = src_tile[tile], se = src_tile[tile + 1];
+                        if (sb < se) {
+                            int e2 = lower_bound_rows<int32_t>(I.src_row, sb, se, r);
+                            double s = 0.0;
+                            bool any = false;
+                            for (; e2 < se && I.src_row[e2] == r; ++e2) {
+                                s += I.src_w[e2] * I.amp[t * I.n_src + I.src_id[e2]];
+                                any = true;
+                            }
+                            if (any) v += (float)ldexp(s, -sc.En);
+                        }
+                    }
+                    Y[r] = v;
+                    if (r < I.n_states) {
+                        sN += (double)v;
+                        sA += s_abs[mt] * (double)v;
+                        mx = fmaxf(mx, v);
+                    } else {
+                        sE += (double)v;
+                    }
+                }
+            }
+        }
+        // the wave's totals over its groups, in a fixed butterfly
+        const double wN = wave_sum(sN), wE = wave_sum(sE), wA = wave_sum(sA), wM = wave_max((double)mx);
+        if (lane == 0) {
+            const int64_t nc = I.n_chunks, b = 4 * c + wave;
+            I.partials[(int64_t)kSlotN * nc + b] = wN;
+            I.partials[(int64_t)kSlotEsc * nc + b] = wE;
+            I.partials[(int64_t)kSlotAbs * nc + b] = wA;
+            I.partials[(int64_t)kSlotMax * nc + b] = wM;
+        }
+    }
+}
+
+// Detector sums of the single-rhs step by row groups (Eq. (27)): block (p, d)
+// forms the sum F * y over part p of detector d's entries (every thread every
+// 256th entry, then a fixed-order block sum) from the stored y.
+__global__ void __launch_bounds__(kNT) spmv_detectors(const StepInst *__restrict__ insts)
+{
+    __shared__ double s_red[kNT];
+    const StepInst &I = insts[0];
+    const int64_t t = I.t[0];
+    if (t >= *I.t_end) return;
+    const int p = blockIdx.x, d = blockIdx.y;
+    const GLB float *Y = gp((const float *)((t & 1) ? I.buf0 : I.buf1));
+    const int64_t b = I.ddet_ptr[d], n = I.ddet_ptr[d + 1] - b;
+    const int64_t pb = b + p * n / kDetParts, pe = b + (p + 1) * n / kDetParts;
+    double acc = 0.0;
+    for (int64_t k = pb + threadIdx.x; k < pe; k += kNT) acc += I.ddet_F[k] * (double)Y[I.ddet_row[k]];
+    acc = block_sum<kNT>(acc, s_red);
+    if (threadIdx.x == 0) det_direct_sums(I.partials, I.n_det, 1, I.n_chunks)[(int64_t)d * kDetParts + p] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -2920,6 +3102,17 @@ hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int6
         else DRTS_SPMV1(VT, IT, RV, RV, 0, 0);                       \
     } while (0)
         const int nt = rows_per_tile <= 64 ? 64 : (rows_per_tile <= 128 ? 128 : 256);
+        if (variant == DRTS_SPMV_GROUPED) {
+            hipLaunchKernelGGL(step_spmv_grouped, g1, dim3(kNT), 0, stream, insts_dev, work_dev, n_work, remap,
+                               xcd_bounds);
+            if (n_det_max > 0) {
+                const hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return e;
+                hipLaunchKernelGGL(spmv_detectors, dim3(kDetParts, (unsigned)n_det_max), dim3(kNT), 0, stream,
+                                   insts_dev);
+            }
+            return hipGetLastError();
+        }
         if (variant == kVariantLongRows) {
             // rows of several hundred entries: a wave per row
             if (value_f64) {

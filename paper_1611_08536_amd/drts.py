@@ -24,6 +24,7 @@ INTERFACE = {"origin": 0, "substep": 1}
 BC = {"vacuum": 0, "reflect": 1}
 KERNEL_CSR, KERNEL_STRUCTURED, KERNEL_STRUCTURED_F64SUM = 0, 1, 2
 SPMM_GROUPED, SPMM_ROWS = 0, 1   # variant of a many-rhs CSR solver
+SPMV_ROW, SPMV_LDS, SPMV_GROUPED = 0, 7, 9   # variants of a single-rhs CSR solver
 SERVE_ARRIVAL, SERVE_SHORTEST = 0, 1
 
 if not os.path.exists(LIB_PATH):

@@ -105,9 +105,10 @@ def serve(requests, budget_bytes: int, quantum: int = 50, max_active: int = 256,
 
 
 def solo_options(kernel: int) -> Optional[dict]:
-    """The launch options the server gives a request run with `kernel`."""
+    """The launch options the server gives a request run with `kernel` (the
+    CSR server batches its requests: the tiled step, not the grouped one)."""
     if kernel == drts.KERNEL_CSR:
-        return None
+        return {"variant": drts.SPMV_LDS, "tiles_per_chunk": 4}
     import torch
     cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
     return {"kernel": kernel, "tiles_per_chunk": 8, "grid": 16 * cus}

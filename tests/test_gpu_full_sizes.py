@@ -106,7 +106,7 @@ def test_c4_full_batch_members_equal_solo_runs():
     B.run(tabs, [steps] * len(solvers))
     B.close()
     for i in (0, 77, 150, 255):
-        solo = solve.run(wls[i], n_steps=steps, matrix=mats[i])
+        solo = solve.run(wls[i], n_steps=steps, matrix=mats[i], options={"variant": drts.SPMV_LDS})
         x, e, t = solvers[i].state()
         assert t == steps
         assert np.array_equal(x, solo["x"]) and np.array_equal(e, solo["x_exp"]), i

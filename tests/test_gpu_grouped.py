@@ -1,5 +1,6 @@
-"""The many-rhs CSR step by row groups (rows with equal column lists share
-one gather of their right-hand-side rows) against the row-by-row step.
+"""The CSR step by row groups (rows with equal column lists share one read of
+their columns and one gather of x) against the tiled and row-by-row steps,
+for many right-hand sides and for one.
 
 Bar: bit-exact state, exponents and exponent series, FP64 series to 1e-13
 (the chunk partials are summed in another order), on media whose rows group
@@ -7,7 +8,7 @@ in different ways: the homogeneous slab (whole groups of 26 rows), Fresnel
 layers and a sphere (interface rows that split off their voxel's group),
 reflecting walls, scattering order 3 (rows wider than one voxel), crossing
 within the step, and a Lebedev-86 medium (rows that do not group: the
-library takes the row-by-row step); with few and with 64 right-hand sides,
+library takes its other step); with one, few and 64 right-hand sides,
 sources in several rows of a group and detectors on escape and state rows.
 """
 import numpy as np
@@ -107,6 +108,46 @@ def test_grouped_launch_shapes(opts):
     wl = _workload(_sphere(10), 9, 25, 3)
     a = solve.run(wl, options={"variant": drts.SPMM_ROWS})
     b = solve.run(wl, matrix=a["matrix"], options=dict(opts, variant=drts.SPMM_GROUPED))
+    assert np.array_equal(a["x"].view(np.uint32), b["x"].view(np.uint32))
+    assert np.array_equal(a["exp2"], b["exp2"])
+    assert np.allclose(a["det"], b["det"], rtol=1e-13, atol=0)
+
+
+def _single(wl):
+    import copy
+    w = copy.copy(wl)
+    w.sources = [copy.copy(x) for x in wl.sources if x.rhs == 0]
+    w.n_rhs = 1
+    return w
+
+
+@pytest.mark.parametrize("name,make", MEDIA, ids=[m[0] for m in MEDIA])
+def test_grouped_spmv_equals_tiled(name, make):
+    n = 7 if name == "lebedev" else 13
+    wl = _single(_workload(make(n), 1, 40, 5))
+    print("%s %d^3, one rhs" % (name, n), flush=True)
+    a = solve.run(wl, options={"variant": drts.SPMV_GROUPED})
+    b = solve.run(wl, matrix=a["matrix"], options={"variant": drts.SPMV_LDS})
+    c = solve.run(wl, matrix=a["matrix"], options={"variant": drts.SPMV_ROW})
+    for o in (b, c):
+        assert np.array_equal(a["x"].view(np.uint32), o["x"].view(np.uint32))
+        assert np.array_equal(a["x_exp"], o["x_exp"]) and np.array_equal(a["exp2"], o["exp2"])
+        assert np.allclose(a["tot"], o["tot"], rtol=1e-13, atol=0)
+        assert np.allclose(a["det"], o["det"], rtol=1e-13, atol=0)
+    assert (a["tot"][:, 0, :] > 0).any()
+    for o in (a, b, c):
+        o["solver"].close()
+
+
+@pytest.mark.parametrize("opts", [{"rows_per_tile": 64, "tiles_per_chunk": 1, "grid": 24, "xcd_remap": 1},
+                                  {"rows_per_tile": 256, "tiles_per_chunk": 64, "grid": 3, "xcd_remap": 0},
+                                  {"rows_per_tile": 128, "tiles_per_chunk": 2, "graph_steps": 7}])
+def test_grouped_spmv_launch_shapes(opts):
+    """Work items of a group or two, a handful of workgroups holding every
+    group, and graph replay."""
+    wl = _single(_workload(_sphere(11), 1, 25, 4))
+    a = solve.run(wl, options={"variant": drts.SPMV_LDS})
+    b = solve.run(wl, matrix=a["matrix"], options=dict(opts, variant=drts.SPMV_GROUPED))
     assert np.array_equal(a["x"].view(np.uint32), b["x"].view(np.uint32))
     assert np.array_equal(a["exp2"], b["exp2"])
     assert np.allclose(a["det"], b["det"], rtol=1e-13, atol=0)

@@ -82,7 +82,7 @@ def test_batch_members_equal_solo_runs():
     B = drts.Batch(solvers)
     B.run(tabs, steps)
     for i, (w, m, S) in enumerate(zip(wls, mats, solvers)):
-        solo = solve.run(w, n_steps=steps[i], matrix=m)
+        solo = solve.run(w, n_steps=steps[i], matrix=m, options={"variant": drts.SPMV_LDS})
         x, e, t = S.state()
         assert t == steps[i]
         assert np.array_equal(x, solo["x"]) and np.array_equal(e, solo["x_exp"]), i
