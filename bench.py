@@ -29,7 +29,7 @@ F64SUM_NOTE = ("FP32 values and state, each row summed in FP64 and rounded once:
                "FP32-accumulation precision pattern (more accurate than it)")
 STEP_SOURCES = ("paper_1611_08536_amd/csrc/drts_step.hip", "paper_1611_08536_amd/csrc/drts_step.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_spmv_c2_traffic.txt")
-SPMV_KERNEL = "step_spmv<float, int, 256, 256, 0, 2>"
+SPMV_KERNEL = "step_spmv_grouped"
 CALIB_KERNEL = "vectorized_elementwise_kernel"
 CALIB_BYTES = 2 ** 30          # the calibration kernel reads and writes 1 GiB
 GRAPH_STEPS = 50               # steps per hipGraph replay in the timed run
@@ -95,9 +95,17 @@ def load_traffic():
 
 
 def spmv_bytes(nnz, n_rows, n_states, val_bytes=4):
-    """Algorithmic bytes of one SpMV step over [A; L]: values and columns once,
-    row pointers once, x once, y once."""
+    """Algorithmic bytes of one SpMV step over [A; L] held as CSR: values and
+    columns once, row pointers once, x once, y once."""
     return val_bytes * nnz + 4 * nnz + 4 * (n_rows + 1) + val_bytes * n_states + val_bytes * n_rows
+
+
+def grouped_bytes(group_bytes, n_rows, n_states):
+    """Bytes the step by row groups must move: its group arrays once (the
+    values in group order, each member's row and material, one descriptor
+    per group), x once, y once (the columns of groups whose columns are not
+    one run are not counted: a few interface groups)."""
+    return group_bytes + 4 * n_states + 4 * n_rows
 
 
 def cpu_baseline(n=128, steps=50, steps_1=3):
@@ -179,7 +187,7 @@ def spmm_vs_plain(torch, steps=20):
            "plain_solve_steps_per_s": round(steps / t_1, 1),
            "speedup_vs_plain": round((k * steps / t_mm) / (steps / t_1), 2),
            "ms_per_step": round(t_mm / steps * 1e3, 3), "plain_ms_per_step": round(t_1 / steps * 1e3, 3),
-           "kernel": "step_spmm<int32>", "kernel_ms": round(kern_s * 1e3, 3),
+           "kernel": "step_spmm_grouped<int32> + spmm_detectors", "kernel_ms": round(kern_s * 1e3, 3),
            "achieved_GBs": round(nbytes / kern_s / 1e9, 1), "frac": round(nbytes / kern_s / 1e9 / PEAK_HBM_GBS, 4)}
     mf_s = f_ms / max(n_f, 1) * 1e-3
     mf_bytes = 4 * k * A.n_states + 4 * k * A.n_rows + A.n_states // 26
@@ -503,13 +511,15 @@ def main():
     wl = W.c2(n=args.n, n_steps=total)
     _log("assembling %d^3 layered medium" % args.n)
     A = drts.Matrix(wl.medium, wl.value_type, wl.rounding, wl.n_ref)
-    S = drts.Solver(A, 1, wl.detectors, max_steps=total)
+    S = drts.Solver(A, 1, wl.detectors, max_steps=total + prof_steps)
     tab = solve.source_table(A, wl)
-    # what ships: drts_run replaying hipGraphs of GRAPH_STEPS steps, no
-    # per-launch events
+    # what ships: the default step (by row groups: the matrix's groups are
+    # built at the first run, before the timed region), drts_run replaying
+    # hipGraphs of GRAPH_STEPS steps, no per-launch events
     S.set_options(graph_steps=GRAPH_STEPS)
     S.run(tab, args.warmup)
     torch.cuda.synchronize()
+    group_bytes = A.device_bytes() - A.bytes
 
     _log("timing %d steps (graph replay)" % args.steps)
     stream = torch.cuda.current_stream()
@@ -537,6 +547,15 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     eager_ms_step = e0.elapsed_time(e1) / prof_steps
+    # the tiled step (values straight into LDS, 4 tiles per chunk) on the same
+    # solver, for comparison
+    _log("tiled step timing pass (%d steps)" % prof_steps)
+    S.set_options(variant=drts.SPMV_LDS, tiles_per_chunk=4)
+    S.profile(True)
+    S.run(tab, prof_steps)
+    t_launches, t_ms = S.profile_stats()
+    S.profile(False)
+    tiled_kernel_ms = t_ms / max(t_launches, 1)
 
     r = S.readout(0, total)
     assert (r["tot"][:, 0, 0] > 0).all()
@@ -549,6 +568,7 @@ def main():
 
     nbytes = spmv_bytes(A.nnz, A.n_rows, A.n_states)
     achieved = nbytes / (avg_kernel_ms * 1e-3) / 1e9
+    fbytes = grouped_bytes(group_bytes, A.n_rows, A.n_states)
     traffic = load_traffic()
     if args.copy_calibration:
         a = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device="cuda")
@@ -570,16 +590,26 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "C2: %d^3 voxels x 26 directions, 3 Fresnel layers, FP32 CSR [A;L], "
+        "config": {"workload": "C2: %d^3 voxels x 26 directions, 3 Fresnel layers, FP32 [A;L], "
                                "Gaussian 100 fs top-face source, 2 detectors" % args.n,
                    "n_states": A.n_states, "n_rows": A.n_rows, "nnz": A.nnz, "parallelism": "1 GPU",
-                   "launch": "drts_run, hipGraph replay of %d steps" % GRAPH_STEPS},
+                   "launch": "drts_run, hipGraph replay of %d steps; the default step (by row groups)" % GRAPH_STEPS},
         "eager_ms_per_step": round(eager_ms_step, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None if traffic is None else round(traffic / 1e9, 3),
                      "kernel": SPMV_KERNEL, "kernel_ms": round(avg_kernel_ms, 4),
-                     "kernel_timing": "HIP events around each of %d eager launches on the launch stream" % launches,
-                     "algorithmic_bytes": nbytes, "traffic_unit": "GB per launch"},
+                     "kernel_timing": "HIP events around each of %d eager launches on the launch stream "
+                                      "(the step kernel and its detector kernel)" % launches,
+                     "algorithmic_bytes": nbytes,
+                     "algorithmic_bytes_basis": "CSR [A;L]: 8 B per entry, row pointers, x and y once",
+                     "format_bytes": fbytes,
+                     "format_frac": round(fbytes / (avg_kernel_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                     "format_bytes_basis": "what the step by row groups must move: values in group order, "
+                                           "members' rows and materials, descriptors, x and y once",
+                     "traffic_unit": "GB per launch"},
+        "tiled_step": {"kernel": "step_spmv<float, int, 256, 2> (values straight into LDS, 4 tiles per chunk)",
+                       "kernel_ms": round(tiled_kernel_ms, 4),
+                       "frac": round(nbytes / (tiled_kernel_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
         "windowed_measurement": {"detectors": 2, "steps": total, "taps": 101,
                                  "call_ms": round(t_win * 1e3, 3)},
     }

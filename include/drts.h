@@ -241,7 +241,9 @@ typedef struct drts_server drts_server_t;
 int drts_build_matrix(const drts_medium_t *medium, const drts_device_t *dev, drts_matrix_t **out);
 
 /* Sizes of an assembled matrix; any output pointer may be NULL.  bytes = device
- * bytes of the CSR (row pointers, columns, values); dt_s in seconds. */
+ * bytes of the CSR (row pointers, columns, values) and, once a solo solver
+ * has asked for the grouped step, of the row groups (descriptors, members'
+ * rows and materials, values in group order); dt_s in seconds. */
 int drts_matrix_info(const drts_matrix_t *A, int64_t *n_states, int64_t *n_escape, int64_t *nnz,
                      int64_t *bytes, double *dt_s);
 
@@ -287,44 +289,24 @@ typedef struct {
     int32_t graph_steps;  /* steps captured per hipGraph replay (0 = eager) */
     int32_t rescale;      /* 1 = power-of-two rescale every step (default) */
     int32_t variant;      /* n_rhs > 1: DRTS_SPMM_GROUPED or DRTS_SPMM_ROWS;
-                             one rhs: DRTS_SPMV_ROW (a thread per row,
-                             four consecutive entries per lane), DRTS_SPMV_PIPE
-                             (the next tile's entries load while the current
-                             tile is reduced), DRTS_SPMV_HALF (two threads per
-                             row while streaming: fewer registers, more
-                             resident waves), DRTS_SPMV_HALF_PIPE (both),
-                             DRTS_SPMV_STRIDED (a thread per row, entries in
-                             strided order: consecutive lanes load and gather
-                             consecutive entries), DRTS_SPMV_WAVE (each wave
-                             carries its own 64-row tile through every phase,
-                             no workgroup barrier per tile; rows_per_tile 64),
-                             DRTS_SPMV_WAVE_PIPE (as DRTS_SPMV_WAVE, the next
-                             tile's entries load before the current tile's
-                             gathers), DRTS_SPMV_LDS (as DRTS_SPMV_ROW, the
-                             values loaded straight into LDS, not through
-                             registers; FP32 values only),
-                             DRTS_SPMV_WAVE_LDS (as DRTS_SPMV_WAVE with the
-                             values through LDS and the chunk's tile bounds
-                             staged once; FP32 values, rows_per_tile 64),
+                             one rhs: DRTS_SPMV_ROW, DRTS_SPMV_LDS or
                              DRTS_SPMV_GROUPED (below) */
     int32_t queue;        /* one rhs only: 1 = workgroups take chunks from a
                              device counter (dynamic balance), 0 = fixed walk */
 } drts_options_t;
 
+/* One rhs: the tiled step, a thread per row and its tile's entries staged in
+ * LDS -- through registers (DRTS_SPMV_ROW, the default for FP64 values) or
+ * loaded straight into LDS (DRTS_SPMV_LDS, FP32 values) -- or the step by
+ * row groups (DRTS_SPMV_GROUPED, FP32 values, the default for them): rows
+ * whose column lists are equal form groups (as for DRTS_SPMM_GROUPED); a
+ * half-wave forms a group, reading the group's columns and x once and its
+ * values from a group-order copy the matrix keeps once a solo solver asks
+ * for it (batch members take DRTS_SPMV_LDS; a matrix whose rows do not group
+ * takes DRTS_SPMV_LDS as well).  All give the same state bit for bit. */
 #define DRTS_SPMV_ROW 0
-#define DRTS_SPMV_PIPE 1
-#define DRTS_SPMV_HALF 2
-#define DRTS_SPMV_HALF_PIPE 3
-#define DRTS_SPMV_STRIDED 4
-#define DRTS_SPMV_WAVE 5
-#define DRTS_SPMV_WAVE_PIPE 6
-#define DRTS_SPMV_LDS 7
-#define DRTS_SPMV_WAVE_LDS 8
-/* one rhs, FP32 values: rows whose column lists are equal form groups (as
- * for DRTS_SPMM_GROUPED); a half-wave forms a group, reading the group's
- * columns and x once and its values from a group-order copy (the default;
- * DRTS_SPMV_LDS for a matrix whose rows do not group). */
-#define DRTS_SPMV_GROUPED 9
+#define DRTS_SPMV_LDS 1
+#define DRTS_SPMV_GROUPED 2
 /* n_rhs > 1: rows whose column lists are equal (on a lattice, the rows that
  * pull from one source voxel) share one gather of their right-hand-side rows
  * (the default; the library takes the row-by-row step for a matrix whose

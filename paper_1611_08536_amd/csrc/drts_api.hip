@@ -73,7 +73,7 @@ void Buffer::reset()
 
 int64_t Matrix::bytes() const
 {
-    const Buffer *b[] = {&row_ptr, &col, &val, &grp_desc, &grp_row, &grp_mat, &grp_val};
+    const Buffer *b[] = {&row_ptr, &col, &val, &grp_desc, &grp_row, &grp_mat, &grp_val, &grp_fast, &slow_rows};
     int64_t n = 0;
     for (const Buffer *x : b) n += (int64_t)x->bytes;
     return n;
@@ -610,9 +610,9 @@ int prepare(drts_solver *S)
         n_part = S->sa.mm_push_grid + (S->n_xchunks > 0 ? S->sa.mm_pull_grid : 0);
     }
     if (S->grouped) {
-        // partials per work item and wave; detector entries by detector; the
-        // groups holding source rows
-        n_part = 4 * S->n_chunks;
+        // partials per work item and wave (single rhs: then per row-list item
+        // and wave); detector entries by detector; the groups holding source rows
+        n_part = 4 * S->n_chunks + (spmm_of(S) ? 0 : 4 * ((A.n_slow + kRowListItem - 1) / kRowListItem));
         std::vector<int64_t> ptr, row;
         if ((rc = upload_dets_by_detector(S, &ptr, &row))) return rc;
         std::vector<int64_t> srows;
@@ -689,6 +689,11 @@ int prepare(drts_solver *S)
         I.grp_val = A.grp_val.as<float>();
         I.grp_src = S->grp_src.as<uint32_t>();
         I.n_groups = A.n_groups;
+        I.grp_fast = A.grp_fast.as<int32_t>();
+        I.slow_rows = A.slow_rows.as<int32_t>();
+        I.n_fast = A.n_fast;
+        I.n_slow = A.n_slow;
+        I.slow_part = 4 * S->n_chunks;
         I.det_direct = 1;
         I.ddet_ptr = S->ddet_ptr.as<int64_t>();
         I.ddet_row = S->ddet_row.as<int64_t>();
@@ -872,7 +877,7 @@ int launch_one(drts_solver *S, hipStream_t stream, const StepInst *inst = nullpt
     e = launch_step(insts, S->work_dev.as<WorkItem>(), S->n_chunks, 1, S->n_rhs,
                                A.model.value_type == DRTS_F64, A.rp64 ? 1 : 0, spmm ? (S->grouped ? 2 : 1) : 0, S->grid,
                                (S->opt.xcd_remap ? 1 : 0) | ((variant & 15) << 1), S->xcd_bounds.as<int64_t>(),
-                               S->opt.rows_per_tile, S->n_det, queue, stream);
+                               S->opt.rows_per_tile, S->n_det, queue, stream, S->grouped ? A.n_slow : 0);
     }
     if (e != hipSuccess) return set_error(DRTS_E_HIP, "step launch failed: %s", hipGetErrorString(e));
     if (e1) DRTS_HIP(hipEventRecord(e1, stream));
@@ -973,12 +978,9 @@ int check_options(const drts_solver *S, const drts_options_t *o)
                          o->variant);
     if (o->variant < DRTS_SPMV_ROW || o->variant > DRTS_SPMV_GROUPED)
         return set_error(DRTS_E_INVALID, "unknown variant %d", o->variant);
-    if (S->n_rhs == 1 && (o->variant == DRTS_SPMV_LDS || o->variant == DRTS_SPMV_WAVE_LDS ||
-                          o->variant == DRTS_SPMV_GROUPED) && S->A->m.model.value_type == DRTS_F64)
+    if (S->n_rhs == 1 && (o->variant == DRTS_SPMV_LDS || o->variant == DRTS_SPMV_GROUPED) &&
+        S->A->m.model.value_type == DRTS_F64)
         return set_error(DRTS_E_INVALID, "the LDS and grouped variants take FP32 values");
-    if ((o->variant == DRTS_SPMV_WAVE || o->variant == DRTS_SPMV_WAVE_PIPE || o->variant == DRTS_SPMV_WAVE_LDS) &&
-        S->n_rhs == 1 && o->kernel == DRTS_KERNEL_CSR && o->rows_per_tile != 64)
-        return set_error(DRTS_E_INVALID, "the wave variants take rows_per_tile = 64");
     if (o->grid < 0 || o->graph_steps < 0 || o->graph_steps > 4096)
         return set_error(DRTS_E_INVALID, "bad grid or graph_steps");
     return DRTS_OK;
@@ -1803,9 +1805,8 @@ int drts_batch_autotune(drts_batch_t *B, drts_options_t *chosen)
     std::vector<Cand> cands;
     for (int r : {64, 128, 256})
         for (int c : {1, 2, 4, 8, 16})
-            for (int v : {(int)DRTS_SPMV_ROW, (int)DRTS_SPMV_LDS, (int)DRTS_SPMV_WAVE_LDS})
+            for (int v : {(int)DRTS_SPMV_ROW, (int)DRTS_SPMV_LDS})
                 for (int g : {16, 64}) {
-                    if (v == DRTS_SPMV_WAVE_LDS && r != 64) continue;
                     cands.push_back({r, c, v, cus * g});
                 }
     const std::vector<drts_options_t> orig = [&] {
@@ -1979,9 +1980,7 @@ int drts_autotune(drts_solver_t *S, const char *cache_path, drts_options_t *chos
                 for (int x = 0; x < 3; ++x)
                     for (int pl = 0; pl <= (spmm ? 0 : DRTS_SPMV_GROUPED); ++pl) {
                         if (pl == DRTS_SPMV_GROUPED && (A.model.value_type == DRTS_F64 || S->no_group)) continue;
-                        if ((pl == DRTS_SPMV_WAVE || pl == DRTS_SPMV_WAVE_PIPE || pl == DRTS_SPMV_WAVE_LDS) && r != 64)
-                            continue;
-                        if ((pl == DRTS_SPMV_LDS || pl == DRTS_SPMV_WAVE_LDS) && A.model.value_type == DRTS_F64) continue;
+                        if (pl == DRTS_SPMV_LDS && A.model.value_type == DRTS_F64) continue;
                         drts_options_t o = S->opt;
                         o.rows_per_tile = r;
                         o.tiles_per_chunk = spmm ? c * 32 : c;

@@ -134,6 +134,19 @@ __global__ void __launch_bounds__(256) group_flag_bits(const GroupDesc *desc, co
     bits[w] = word;
 }
 
+// fast groups (a full lattice row: kSpmmUnroll columns that are one run)
+// and, per member, whether its group is not one
+__global__ void __launch_bounds__(256) group_kinds(const GroupDesc *desc, int64_t n_groups, uint8_t *fast,
+                                                   uint8_t *member_slow)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_groups) return;
+    const GroupDesc D = desc[g];
+    const bool f = D.n == kSpmmUnrollHost && D.cstart >= 0;
+    fast[g] = f ? 1 : 0;
+    for (int j = 0; j < D.nm; ++j) member_slow[D.m0 + j] = f ? 0 : 1;
+}
+
 __global__ void __launch_bounds__(256) group_scatter(const int32_t *flag, const int32_t *pos, int64_t n,
                                                      int32_t *grp_ptr)
 {
@@ -246,7 +259,33 @@ int build_groups(Matrix &A)
     hipLaunchKernelGGL(group_values<IT>, dim3(gblocks), dim3(256), 0, dev.stream, A.grp_desc.as<GroupDesc>(),
                        A.grp_row.as<int32_t>(), rp, A.val.as<float>(), G, A.grp_val.as<float>());
     DRTS_HIP(hipGetLastError());
+    // the single-rhs step takes the fast groups by row groups and the rows of
+    // the others one by one: the list of fast groups and the list of those rows
+    Buffer fast, mslow, iota, cnt;
+    if ((rc = fast.allocate(&dev, G))) return rc;
+    if ((rc = mslow.allocate(&dev, R))) return rc;
+    if ((rc = cnt.allocate(&dev, 2 * sizeof(int64_t)))) return rc;
+    hipLaunchKernelGGL(group_kinds, dim3(gblocks), dim3(256), 0, dev.stream, A.grp_desc.as<GroupDesc>(), G,
+                       fast.as<uint8_t>(), mslow.as<uint8_t>());
+    DRTS_HIP(hipGetLastError());
+    if ((rc = A.grp_fast.allocate(&dev, G * sizeof(int32_t)))) return rc;
+    if ((rc = A.slow_rows.allocate(&dev, R * sizeof(int32_t)))) return rc;
+    hipcub::CountingInputIterator<int32_t> gidx(0);
+    size_t tb4 = 0, tb5 = 0;
+    DRTS_HIP(hipcub::DeviceSelect::Flagged(nullptr, tb4, gidx, fast.as<uint8_t>(), A.grp_fast.as<int32_t>(),
+                                           cnt.as<int64_t>(), (int)G, dev.stream));
+    DRTS_HIP(hipcub::DeviceSelect::Flagged(nullptr, tb5, A.grp_row.as<int32_t>(), mslow.as<uint8_t>(),
+                                           A.slow_rows.as<int32_t>(), cnt.as<int64_t>() + 1, (int)R, dev.stream));
+    if ((rc = tmp.allocate(&dev, std::max<size_t>(std::max(tb4, tb5), 16)))) return rc;
+    DRTS_HIP(hipcub::DeviceSelect::Flagged(tmp.ptr, tb4, gidx, fast.as<uint8_t>(), A.grp_fast.as<int32_t>(),
+                                           cnt.as<int64_t>(), (int)G, dev.stream));
+    DRTS_HIP(hipcub::DeviceSelect::Flagged(tmp.ptr, tb5, A.grp_row.as<int32_t>(), mslow.as<uint8_t>(),
+                                           A.slow_rows.as<int32_t>(), cnt.as<int64_t>() + 1, (int)R, dev.stream));
+    int64_t counts[2] = {0, 0};
+    DRTS_HIP(hipMemcpyAsync(counts, cnt.ptr, sizeof counts, hipMemcpyDeviceToHost, dev.stream));
     DRTS_HIP(hipStreamSynchronize(dev.stream));
+    A.n_fast = counts[0];
+    A.n_slow = counts[1];
     A.n_groups = G;
     return DRTS_OK;
 }
@@ -265,7 +304,7 @@ int row_groups(const Matrix &Ac)
     }
     const int rc = A.rp64 ? build_groups<int64_t>(A) : build_groups<int32_t>(A);
     if (rc) {
-        Buffer *b[] = {&A.grp_desc, &A.grp_row, &A.grp_mat, &A.grp_val};
+        Buffer *b[] = {&A.grp_desc, &A.grp_row, &A.grp_mat, &A.grp_val, &A.grp_fast, &A.slow_rows};
         for (Buffer *x : b) x->reset();
         A.n_groups = -1;
     }

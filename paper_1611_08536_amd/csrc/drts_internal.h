@@ -122,6 +122,10 @@ struct Matrix {
     // within a group).  n_groups < 0 = not built, 0 = the rows do not group
     Buffer grp_desc, grp_row, grp_mat, grp_val;
     int64_t n_groups = -1;
+    // for the single-rhs step: the fast groups (kSpmmUnroll columns in one
+    // run, by index) and the rows of all other groups
+    Buffer grp_fast, slow_rows;
+    int64_t n_fast = 0, n_slow = 0;
     int64_t bytes() const;         // the CSR arrays (and the row groups, once built)
     int64_t table_bytes() const;   // everything else on the device (tables of the model)
 };

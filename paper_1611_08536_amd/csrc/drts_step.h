@@ -68,6 +68,12 @@ struct StepInst {
     const float *grp_val;
     const uint32_t *grp_src;
     int64_t n_groups;
+    // the single-rhs step by row groups: the fast groups (full lattice rows,
+    // columns in one run) by index, then the rows of the other groups one by
+    // one, whose partials start at index slow_part
+    const int32_t *grp_fast;
+    const int32_t *slow_rows;
+    int64_t n_fast, n_slow, slow_part;
     // det_direct: the detector sums come from their own kernel (a value per
     // detector and rhs after the finalize segments of the partials, see
     // det_direct_sums), which takes the detector entries grouped by detector,
@@ -117,12 +123,16 @@ struct WorkItem {
 // Launch variant (bits 1..4 of xcd_remap) of the wave-per-row SpMV for rows of
 // several hundred entries; chosen by the library for such matrices, not an
 // option of the caller.
-constexpr int kVariantLongRows = 10;
+constexpr int kVariantLongRows = 3;
 // mean entries per row from which a matrix takes the wave-per-row SpMV
 constexpr int kLongRowMean = 96;
 
 // Members of one row group at most (larger sets of equal rows are split).
 constexpr int kGroupMax = 26;
+// Entries of a full lattice row (the grouped steps' fast path).
+constexpr int kSpmmUnrollHost = 26;
+// Rows a workgroup of the single-rhs row-list kernel takes per work item.
+constexpr int kRowListItem = 256;
 
 // One row group (rows with equal column lists): its members are grp_row and
 // grp_mat [m0, m0 + nm), rows ascending; its values start at grp_val + voff,
@@ -147,10 +157,11 @@ struct alignas(16) GroupDesc {
 // (work item c takes groups c * n_groups / n_chunks onwards).
 // xcd_bounds (may be NULL): with the XCD-aware walk, XCD i takes work items
 // xcd_bounds[i] .. xcd_bounds[i+1]-1 (kXcdBounds entries), else equal counts.
+// n_slow: with the grouped single-rhs step, the rows it takes one by one.
 hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int64_t n_work, int n_inst,
                        int n_rhs_max, int value_f64, int rp64, int spmm, int grid, int xcd_remap,
                        const int64_t *xcd_bounds, int rows_per_tile, int n_det_max, int32_t *queue,
-                       hipStream_t stream);
+                       hipStream_t stream, int64_t n_slow = 0);
 hipError_t launch_finalize(const StepInst *insts_dev, int n_inst, int n_rhs_max, int n_det_max, int32_t *queue,
                            hipStream_t stream);
 

@@ -396,101 +396,21 @@ __device__ __forceinline__ float finish_tile_l(const TileRegsL<IT, U> &T, __amdg
     return acc;
 }
 
-// Entries of one tile in strided order: thread t holds entries b + t + k NT,
-// so consecutive lanes hold consecutive entries.  Loads of columns and values
-// are then coalesced 4-byte loads, and so is most of the x gather: a row's
-// columns are runs of consecutive states (one voxel's 26 directions), so one
-// wave instruction gathers from the x blocks of two or three rows instead of
-// from a dozen (the address unit, not HBM, limits the quad layout).
-template <typename VT, typename IT, int S> struct TileRegsS {
-    VT v[S];
-    int32_t c[S];
-    IT b, e;
-    IT mylo, myhi;
-    int q;
-};
-
-template <typename VT, typename IT, int NT, int S, int R>
-__device__ __forceinline__ void issue_tile_s(TileRegsS<VT, IT, S> &T, const GLB IT *rp, const GLB int32_t *col,
-                                             const GLB VT *val, const GLB uint8_t *mat, IT b, IT e, int64_t r0,
-                                             int nr, int64_t n_states, uint64_t vmul, int64_t nnz)
-{
-    const int tid = threadIdx.x;
-    const int64_t r = r0 + tid;
-    T.b = b;
-    T.e = e;
-    T.mylo = 0;
-    T.myhi = 0;
-    T.q = 0;
-    if (tid < nr && tid < R) {
-        T.mylo = rp[r];
-        T.myhi = rp[r + 1];
-        if (r < n_states) T.q = mat[vox_of(r, vmul)];
-    }
-    // indices past the tile are clamped to its last entry (an empty tile reads
-    // entry b, at worst the zero padding): no branches, every load in bounds;
-    // such duplicates are not staged
-    const uint32_t last = e > b ? (uint32_t)(e - b - 1) : 0u;
-    const int64_t base = (int64_t)b;
-    const uint64_t left = (uint64_t)(nnz + 4 - base);
-    const __amdgpu_buffer_rsrc_t rc = make_rsrc((const void *)(col + base), left * 4);
-    const __amdgpu_buffer_rsrc_t rv = make_rsrc((const void *)(val + base), left * sizeof(VT));
-#pragma unroll
-    for (int k = 0; k < S; ++k) {
-        const uint32_t i = min((uint32_t)(tid + k * NT), last);
-        T.c[k] = __builtin_amdgcn_raw_buffer_load_b32(rc, (int)(i * 4), 0, kStream);
-        if constexpr (sizeof(VT) == 4)
-            T.v[k] = __builtin_bit_cast(VT, __builtin_amdgcn_raw_buffer_load_b32(rv, (int)(i * 4), 0, kStream));
-        else
-            T.v[k] = __builtin_bit_cast(VT, __builtin_amdgcn_raw_buffer_load_b64(rv, (int)(i * 8), 0, kStream));
-    }
-}
-
-template <typename VT, typename IT, int NT, int S, int R>
-__device__ __forceinline__ VT finish_tile_s(const TileRegsS<VT, IT, S> &T, __amdgpu_buffer_rsrc_t rx, VT *s_prod)
-{
-    VT xv[S];
-#pragma unroll
-    for (int k = 0; k < S; ++k) xv[k] = BufQuad<VT>::gather(rx, T.c[k]);
-    const int span = (int)(T.e - T.b);
-#pragma unroll
-    for (int k = 0; k < S; ++k) {
-        const int i = threadIdx.x + k * NT;
-        if (i < span) s_prod[i] = T.v[k] * xv[k];
-    }
-    __syncthreads();
-    VT acc = 0;
-    IT jj = T.mylo;
-    for (; jj + 4 <= T.myhi; jj += 4) {
-        const VT p0 = s_prod[jj - T.b], p1 = s_prod[jj - T.b + 1];
-        const VT p2 = s_prod[jj - T.b + 2], p3 = s_prod[jj - T.b + 3];
-        acc += p0;
-        acc += p1;
-        acc += p2;
-        acc += p3;
-    }
-    for (; jj < T.myhi; ++jj) acc += s_prod[jj - T.b];
-    return acc;
-}
-
-// NT threads stream the entries of R rows (R = NT: one row per thread and 7
-// quads per thread; R = NT/2: 4 quads per thread, so fewer registers and more
-// resident waves; the first R threads sum the rows).  PIPE = 1: the next
-// tile's entries are loaded before this tile's gathers, so the matrix stream
-// of a workgroup never stops (two register sets).  LAY = 1: the strided tile
-// layout (one row per thread, no pipelining); LAY = 2: quads with the values
-// loaded straight into LDS (FP32 values only, no pipelining); LAY = 0: quads.
-template <typename VT, typename IT, int NT, int R, int PIPE, int LAY>
-__global__ void __launch_bounds__(NT, (LAY == 2 && sizeof(VT) == 4 && sizeof(IT) == 4 && R >= 128 ? 5 : 1)) step_spmv(const StepInst *__restrict__ insts,
+// R threads stream the entries of R rows, one row per thread and 7 quads of
+// entries per thread.  LAY = 0: quads through registers; LAY = 2: the values
+// loaded straight into LDS (FP32 values only).
+template <typename VT, typename IT, int R, int LAY>
+__global__ void __launch_bounds__(R, (LAY == 2 && sizeof(VT) == 4 && sizeof(IT) == 4 && R >= 128 ? 5 : 1)) step_spmv(const StepInst *__restrict__ insts,
                                                  const WorkItem *__restrict__ work, int64_t n_work,
                                                  int xcd_remap, const int64_t *__restrict__ xcd_bounds,
                                                  int32_t *__restrict__ queue)
 {
+    constexpr int NT = R;
     constexpr int NW = NT / 64;
     __shared__ int64_t s_wi;
     __shared__ double s_wred[4][NW];
-    constexpr int U = (R == NT) ? 7 : (32 * R) / (4 * NT);   // quads of entries per thread
-    constexpr int CAP = 4 * U * NT;      // entries staged per pass (>= 28 per row)
+    constexpr int U = 7;                 // quads of entries per thread
+    constexpr int CAP = 4 * U * NT;      // entries staged per pass (28 per row)
     static_assert(U >= 1 && CAP >= 28 * R, "tile shape");
     constexpr int LAYV = (LAY == 2 && sizeof(VT) != 4) ? 0 : LAY;   // FP64 values: quads
     __shared__ __attribute__((aligned(16))) VT s_prod[CAP];
@@ -575,14 +495,8 @@ __global__ void __launch_bounds__(NT, (LAY == 2 && sizeof(VT) == 4 && sizeof(IT)
 
         double sN = 0.0, sE = 0.0, sA = 0.0, dsum = 0.0;
         VT mx = 0;
-        TileRegs<VT, IT, U> cur, nxt;
         auto fits = [&](int j) { return s_tb[j + 1] - s_tb[j] <= (IT)CAP - 3; };
         auto rows_of = [&](int j) { return (int)min((int64_t)R, n_rows - (tile0 + j) * R); };
-        bool have = false;
-        if (PIPE && ntc > 0 && fits(0)) {
-            issue_tile<VT, IT, NT, U, R>(cur, rp, col, val, mat, s_tb[0], s_tb[1], tile0 * R, rows_of(0), n_states, vmul, I.nnz);
-            have = true;
-        }
         for (int j = 0; j < ntc; ++j) {
             const int64_t r0 = (tile0 + j) * R;
             const int nr = rows_of(j);
@@ -601,25 +515,11 @@ __global__ void __launch_bounds__(NT, (LAY == 2 && sizeof(VT) == 4 && sizeof(IT)
                     acc = finish_tile_l<IT, NT, U, R>(tl, rx, (float *)s_prod, [&]() { flush(); }, mine);
                     q = tl.q;
                 }
-            } else if (LAYV == 1 && fits(j)) {
-                TileRegsS<VT, IT, CAP / NT> ts;
-                issue_tile_s<VT, IT, NT, CAP / NT, R>(ts, rp, col, val, mat, s_tb[j], s_tb[j + 1], r0, nr, n_states,
-                                                      vmul, I.nnz);
-                acc = finish_tile_s<VT, IT, NT, CAP / NT, R>(ts, rx, s_prod);
-                q = ts.q;
             } else if (fits(j)) {
-                if (!have)
-                    issue_tile<VT, IT, NT, U, R>(cur, rp, col, val, mat, s_tb[j], s_tb[j + 1], r0, nr, n_states, vmul, I.nnz);
-                bool more = false;
-                if (PIPE && j + 1 < ntc && fits(j + 1)) {
-                    issue_tile<VT, IT, NT, U, R>(nxt, rp, col, val, mat, s_tb[j + 1], s_tb[j + 2], r0 + R, rows_of(j + 1),
-                                              n_states, vmul, I.nnz);
-                    more = true;
-                }
-                acc = finish_tile<VT, IT, NT, U, R>(cur, rx, s_prod);
-                q = cur.q;
-                if (more) cur = nxt;
-                have = more;
+                TileRegs<VT, IT, U> tr;
+                issue_tile<VT, IT, NT, U, R>(tr, rp, col, val, mat, s_tb[j], s_tb[j + 1], r0, nr, n_states, vmul, I.nnz);
+                acc = finish_tile<VT, IT, NT, U, R>(tr, rx, s_prod);
+                q = tr.q;
             } else {
                 // long rows: several passes over the tile
                 const IT b = s_tb[j], e = s_tb[j + 1];
@@ -647,12 +547,6 @@ __global__ void __launch_bounds__(NT, (LAY == 2 && sizeof(VT) == 4 && sizeof(IT)
                     const IT hi = myhi < ce ? myhi : ce;
                     for (IT jj = lo; jj < hi; ++jj) acc += s_prod[jj - a];
                     __syncthreads();
-                }
-                have = false;
-                if (PIPE && j + 1 < ntc && fits(j + 1)) {
-                    issue_tile<VT, IT, NT, U, R>(cur, rp, col, val, mat, s_tb[j + 1], s_tb[j + 2], r0 + R, rows_of(j + 1),
-                                              n_states, vmul, I.nnz);
-                    have = true;
                 }
             }
 
@@ -879,501 +773,6 @@ __device__ __forceinline__ int64_t lane_i64(int64_t v, int l)
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
     return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
-// ---------------------------------------------------------------------------
-// SpMV step, one wave per tile of 64 rows
-//
-// Each wave of a workgroup takes every fourth tile of the chunk and carries it
-// through on its own: the row bounds (a lane per row), the tile's columns and
-// values as quads (lane l holds entries 4 (l + 64 k) .. + 3 of the tile), the
-// x gathers, the products staged in the wave's own LDS slice, and the row sums
-// (each lane its row, in column order).  No workgroup barrier separates these
-// phases, so every wave keeps its loads in flight independently; the waves
-// meet once per chunk to combine their FP64 partials in a fixed order.
-// ---------------------------------------------------------------------------
-constexpr int kWaveTileRows = 64;
-
-template <typename VT, typename IT, int PIPEW>
-__global__ void __launch_bounds__(256) step_spmv_wave(const StepInst *__restrict__ insts,
-                                                       const WorkItem *__restrict__ work, int64_t n_work,
-                                                       int xcd_remap, const int64_t *__restrict__ xcd_bounds)
-{
-    constexpr int NW = 4, U = 7;
-    constexpr int CAPW = 4 * U * 64;     // entries one pass of a wave stages (28 per row)
-    __shared__ VT s_prod[NW][CAPW];
-    __shared__ VT s_yw[NW][64];
-    __shared__ double s_abs[kMatMax];
-    __shared__ double s_wred[4][NW];
-    __shared__ double s_wdet[NW][kFinDetMax];
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    VT *my_prod = s_prod[wave];
-    const Walk wk = walk_of(n_work, xcd_remap, xcd_bounds);
-    for (int64_t wi = wk.begin; wi < wk.end; wi += wk.stride) {
-        const WorkItem item = work[wi];
-        const StepInst &I = insts[item.inst];
-        const int64_t t = I.t[0];
-        if (t >= *I.t_end) continue;
-        const Scale sc = step_scale(I, 0, t);
-        const VT scale = (VT)ldexp(1.0, -sc.k);
-        const GLB IT *rp = gp((const IT *)I.row_ptr);
-        const GLB int32_t *col = gp(I.col);
-        const GLB VT *val = gp((const VT *)I.val);
-        const GLB VT *x = gp((const VT *)((t & 1) ? I.buf1 : I.buf0));
-        const __amdgpu_buffer_rsrc_t rx = make_rsrc((const void *)x, (uint64_t)I.n_rows * sizeof(VT));
-        GLB VT *y = gpw((VT *)((t & 1) ? I.buf0 : I.buf1));
-        const GLB uint8_t *mat = gp(I.mat);
-        const int64_t n_rows = I.n_rows, n_states = I.n_states;
-        const uint64_t vmul = I.vox_mul;
-        const int nd = I.n_det;
-        const int64_t tile0 = (int64_t)item.chunk * I.tiles_per_chunk;
-        const int64_t tile1 = min(tile0 + (int64_t)I.tiles_per_chunk, I.n_tiles);
-        for (int q = threadIdx.x; q < I.n_mat; q += 256) s_abs[q] = gp(I.absorb)[q];
-        __syncthreads();
-        double sN = 0.0, sE = 0.0, sA = 0.0;
-        double dsum[kFinDetMax / 64] = {0.0, 0.0, 0.0, 0.0};
-        VT mx = 0;
-        // one tile's stream: bounds, then the quads of columns and values
-        struct WTile {
-            IT mylo, myhi, b, e, a0;
-            int nr;
-            uint32_t span;
-            uint32_t qo[U];
-            i4 qc[U];
-            Quad<VT> qv[U];
-        };
-        auto bounds_of = [&](WTile &T, int64_t tile) {
-            const int64_t r0 = tile * kWaveTileRows;
-            T.nr = (int)min((int64_t)kWaveTileRows, n_rows - r0);
-            const int64_t rl = r0 + min(lane, T.nr - 1);
-            T.mylo = rp[rl];
-            T.myhi = rp[rl + 1];
-            T.b = (IT)lane_i64((int64_t)T.mylo, 0);
-            T.e = (IT)lane_i64((int64_t)T.myhi, T.nr - 1);
-        };
-        auto stream_of = [&](WTile &T) {
-            T.a0 = T.b & ~(IT)3;
-            const uint32_t last = T.e > T.a0 ? (uint32_t)(((T.e - 1 - T.a0) >> 2) << 2) : 0u;
-            T.span = (uint32_t)(T.e - T.a0);
-            const int64_t base = (int64_t)T.a0;
-            const uint64_t left = (uint64_t)(I.nnz + 4 - base);
-            const __amdgpu_buffer_rsrc_t rc = make_rsrc((const void *)(col + base), left * 4);
-            const __amdgpu_buffer_rsrc_t rv = make_rsrc((const void *)(val + base), left * sizeof(VT));
-#pragma unroll
-            for (int k = 0; k < U; ++k) {
-                const uint32_t i = 4u * (uint32_t)(lane + 64 * k);
-                T.qo[k] = i < T.span ? i : last;
-            }
-#pragma unroll
-            for (int k = 0; k < U; ++k) {
-                T.qc[k] = __builtin_amdgcn_raw_buffer_load_b128(rc, (int)(T.qo[k] * 4), 0, kStream);
-                T.qv[k] = BufQuad<VT>::load(rv, T.qo[k] * (uint32_t)sizeof(VT));
-            }
-        };
-        auto fits_w = [&](const WTile &T) { return T.e - T.b <= (IT)CAPW - 3; };
-        WTile cur, nxt;
-        bool have = false;
-        if (PIPEW && tile0 + wave < tile1) {
-            bounds_of(cur, tile0 + wave);
-            if (fits_w(cur)) {
-                stream_of(cur);
-                have = true;
-            }
-        }
-        for (int64_t tile = tile0 + wave; tile < tile1; tile += NW) {
-            const int64_t r0 = tile * kWaveTileRows;
-            if (!have) bounds_of(cur, tile);
-            const int nr = cur.nr;
-            const int64_t r = r0 + lane;
-            const bool own = lane < nr;
-            const IT mylo = cur.mylo, myhi = cur.myhi, b = cur.b, e = cur.e;
-            int q = 0;
-            if (own && r < n_states) q = mat[vox_of(r, vmul)];
-            VT acc = 0;
-            if (fits_w(cur)) {
-                if (!have) stream_of(cur);
-                // the next tile's stream goes out before this tile's gathers
-                bool more = false;
-                if (PIPEW && tile + NW < tile1) {
-                    bounds_of(nxt, tile + NW);
-                    if (fits_w(nxt)) {
-                        stream_of(nxt);
-                        more = true;
-                    }
-                }
-                const IT a0 = cur.a0;
-                VT xv[U][4];
-#pragma unroll
-                for (int k = 0; k < U; ++k)
-#pragma unroll
-                    for (int jj = 0; jj < 4; ++jj) xv[k][jj] = BufQuad<VT>::gather(rx, cur.qc[k][jj]);
-#pragma unroll
-                for (int k = 0; k < U; ++k)
-#pragma unroll
-                    for (int jj = 0; jj < 4; ++jj) my_prod[cur.qo[k] + jj] = cur.qv[k][jj] * xv[k][jj];
-                // the wave's own LDS writes, then its reads: in order within the wave
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                if (own) {
-                    IT jj = mylo;
-                    for (; jj + 4 <= myhi; jj += 4) {
-                        const VT p0 = my_prod[jj - a0], p1 = my_prod[jj - a0 + 1];
-                        const VT p2 = my_prod[jj - a0 + 2], p3 = my_prod[jj - a0 + 3];
-                        acc += p0;
-                        acc += p1;
-                        acc += p2;
-                        acc += p3;
-                    }
-                    for (; jj < myhi; ++jj) acc += my_prod[jj - a0];
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                if (more) cur = nxt;
-                have = more;
-            } else {
-                // long rows: passes of CAPW entries
-                for (IT a = b & ~(IT)3; a < e; a += CAPW) {
-                    const IT cs = a < b ? b : a;
-                    const IT ce = (e - a < (IT)CAPW) ? e : a + (IT)CAPW;
-                    for (IT i = a + 4 * lane; i < ce; i += 4 * 64) {
-                        const i4 c4 = __builtin_nontemporal_load((const GLB i4 *)(col + i));
-                        Quad<VT> v4;
-                        v4.load(val + i);
-#pragma unroll
-                        for (int jj = 0; jj < 4; ++jj) {
-                            const IT idx = i + jj;
-                            if (idx >= cs && idx < ce) my_prod[idx - a] = v4[jj] * x[c4[jj]];
-                        }
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    if (own) {
-                        const IT lo = mylo > cs ? mylo : cs;
-                        const IT hi = myhi < ce ? myhi : ce;
-                        for (IT jj = lo; jj < hi; ++jj) acc += my_prod[jj - a];
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                }
-                have = false;
-                if (PIPEW && tile + NW < tile1) {
-                    bounds_of(cur, tile + NW);
-                    if (fits_w(cur)) {
-                        stream_of(cur);
-                        have = true;
-                    }
-                }
-            }
-            // epilogue: rescale, sources, store, FP64 totals
-            VT v = acc * scale;
-            const int sb = gp(I.src_tile)[tile], se = gp(I.src_tile)[tile + 1];
-            if (own && sb < se) {
-                const GLB int64_t *srow = gp(I.src_row);
-                int e2 = lower_bound_rows<IT>(I.src_row, sb, se, r);
-                double s = 0.0;
-                bool any = false;
-                for (; e2 < se && srow[e2] == r; ++e2) {
-                    s += gp(I.src_w)[e2] * gp(I.amp)[t * I.n_src + gp(I.src_id)[e2]];
-                    any = true;
-                }
-                if (any) v += (VT)ldexp(s, -sc.En);
-            }
-            if (own) {
-                y[r] = v;
-                if (r < n_states) {
-                    sN += (double)v;
-                    sA += s_abs[q] * (double)v;
-                    mx = v > mx ? v : mx;
-                } else {
-                    sE += (double)v;
-                }
-            }
-            const int db = gp(I.det_tile)[tile], de = gp(I.det_tile)[tile + 1];
-            if (db < de) {
-                s_yw[wave][lane] = v;
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                // detector d is summed by lane d % 64 in register d / 64
-                for (int e2 = db; e2 < de; ++e2) {
-                    const int d = gp(I.det_id)[e2];
-                    if ((d & 63) == lane) {
-                        const double f = gp(I.det_F)[e2] * (double)s_yw[wave][gp(I.det_row)[e2] - r0];
-#pragma unroll
-                        for (int h = 0; h < kFinDetMax / 64; ++h)
-                            if ((d >> 6) == h) dsum[h] += f;
-                    }
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            }
-        }
-        // chunk partials: wave butterflies, then the waves in order
-        const int64_t nc = I.n_chunks, c = item.chunk;
-        const double wN = wave_sum(sN), wE = wave_sum(sE), wA = wave_sum(sA), wM = wave_max((double)mx);
-        if (lane == 0) {
-            s_wred[0][wave] = wN;
-            s_wred[1][wave] = wE;
-            s_wred[2][wave] = wA;
-            s_wred[3][wave] = wM;
-        }
-#pragma unroll
-        for (int h = 0; h < kFinDetMax / 64; ++h)
-            if (h * 64 + lane < nd) s_wdet[wave][h * 64 + lane] = dsum[h];
-        __syncthreads();
-        GLB double *part = gpw(I.partials);
-        const int tid = threadIdx.x;
-        if (tid < 4) {
-            double a = s_wred[tid][0];
-            for (int w = 1; w < NW; ++w) a = (tid == 3) ? fmax(a, s_wred[tid][w]) : a + s_wred[tid][w];
-            part[(int64_t)tid * nc + c] = a;
-        }
-        for (int d = tid; d < nd; d += 256) {
-            const double a = ((s_wdet[0][d] + s_wdet[1][d]) + s_wdet[2][d]) + s_wdet[3][d];
-            part[(int64_t)(kSlotDet + d) * nc + c] = a;
-        }
-        __syncthreads();
-    }
-}
-
-// ---------------------------------------------------------------------------
-// SpMV step, one wave per 64-row tile, FP32 values straight into the wave's
-// LDS slice.  The chunk's tile bounds (row_ptr at tile starts) and its
-// per-tile source and detector offsets go to LDS once per chunk; then every
-// wave carries its own tiles (every fourth of the chunk) through all phases
-// without a workgroup barrier: its rows' bounds, the column quads into
-// registers and the value quads into its LDS slice in one round trip, the
-// gathers of x, the products in place (a lane multiplies the quads it
-// loaded), the row sums in column order, the epilogue.  The waves meet once
-// per chunk to combine their FP64 partials in a fixed order.
-// ---------------------------------------------------------------------------
-template <typename IT>
-__global__ void __launch_bounds__(256) step_spmv_wl(const StepInst *__restrict__ insts,
-                                                     const WorkItem *__restrict__ work, int64_t n_work,
-                                                     int xcd_remap, const int64_t *__restrict__ xcd_bounds)
-{
-    constexpr int NW = 4, U = 7, R = kWaveTileRows;
-    constexpr int CAPW = 4 * U * 64;     // entries one wave stages (28 per row)
-    __shared__ __attribute__((aligned(16))) float s_prod[NW][CAPW];
-    __shared__ float s_yw[NW][64];
-    __shared__ IT s_tb[kChunkMax + 1];
-    __shared__ int32_t s_src[kChunkMax + 1];
-    __shared__ int32_t s_det[kChunkMax + 1];
-    __shared__ double s_abs[kMatMax];
-    __shared__ double s_wred[4][NW];
-    // the waves' detector partials reuse the product slices once every wave
-    // has finished its tiles
-    static_assert(sizeof(double) * NW * kFinDetMax <= sizeof(float) * NW * CAPW, "detector partials fit");
-    double (*s_wdet)[kFinDetMax] = reinterpret_cast<double (*)[kFinDetMax]>(&s_prod[0][0]);
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    float *my_prod = s_prod[wave];
-    const Walk wk = walk_of(n_work, xcd_remap, xcd_bounds);
-    for (int64_t wi = wk.begin; wi < wk.end; wi += wk.stride) {
-        const WorkItem item = work[wi];
-        const StepInst &I = insts[item.inst];
-        const int64_t t = I.t[0];
-        if (t >= *I.t_end) continue;
-        const Scale sc = step_scale(I, 0, t);
-        const float scale = (float)ldexp(1.0, -sc.k);
-        const GLB IT *rp = gp((const IT *)I.row_ptr);
-        const GLB int32_t *col = gp(I.col);
-        const GLB float *val = gp((const float *)I.val);
-        const GLB float *x = gp((const float *)((t & 1) ? I.buf1 : I.buf0));
-        const __amdgpu_buffer_rsrc_t rx = make_rsrc((const void *)x, (uint64_t)I.n_rows * sizeof(float));
-        GLB float *y = gpw((float *)((t & 1) ? I.buf0 : I.buf1));
-        const GLB uint8_t *mat = gp(I.mat);
-        const int64_t n_rows = I.n_rows, n_states = I.n_states;
-        const uint64_t vmul = I.vox_mul;
-        const int nd = I.n_det;
-        const int64_t tile0 = (int64_t)item.chunk * I.tiles_per_chunk;
-        const int ntc = (int)min((int64_t)I.tiles_per_chunk, I.n_tiles - tile0);
-        for (int j = tid; j <= ntc; j += 256) {
-            s_tb[j] = rp[min((tile0 + j) * R, n_rows)];
-            s_src[j] = gp(I.src_tile)[tile0 + j];
-            s_det[j] = gp(I.det_tile)[tile0 + j];
-        }
-        for (int q = tid; q < I.n_mat; q += 256) s_abs[q] = gp(I.absorb)[q];
-        __syncthreads();
-        double sN = 0.0, sE = 0.0, sA = 0.0;
-        double dsum[kFinDetMax / 64] = {0.0, 0.0, 0.0, 0.0};
-        float mx = 0;
-        for (int j = wave; j < ntc; j += NW) {
-            const int64_t r0 = (tile0 + j) * R;
-            const int nr = (int)min((int64_t)R, n_rows - r0);
-            const int64_t r = r0 + lane;
-            const bool own = lane < nr;
-            const IT b = s_tb[j], e = s_tb[j + 1];
-            IT mylo = 0, myhi = 0;
-            int q = 0;
-            if (own) {
-                mylo = rp[r];
-                myhi = rp[r + 1];
-                if (r < n_states) q = mat[vox_of(r, vmul)];
-            }
-            float acc = 0;
-            if (e - b <= (IT)CAPW - 3) {
-                // quads past the tile re-read its last quad (an empty tile its
-                // first) into slots no row of the tile reads
-                const IT a0 = b & ~(IT)3;
-                const uint32_t last = e > a0 ? (uint32_t)(((e - 1 - a0) >> 2) << 2) : 0u;
-                const uint32_t span = (uint32_t)(e - a0);
-                const int64_t base = (int64_t)a0;
-                const uint64_t left = (uint64_t)(I.nnz + 4 - base);
-                const __amdgpu_buffer_rsrc_t rc = make_rsrc((const void *)(col + base), left * 4);
-                const __amdgpu_buffer_rsrc_t rv = make_rsrc((const void *)(val + base), left * 4);
-                i4 qc[U];
-#pragma unroll
-                for (int k = 0; k < U; ++k) {
-                    const uint32_t i = 4u * (uint32_t)(lane + 64 * k);
-                    const uint32_t o = i < span ? i : last;
-                    qc[k] = __builtin_amdgcn_raw_buffer_load_b128(rc, (int)(o * 4), 0, kStream);
-                    __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                        rv, (__attribute__((address_space(3))) void *)(my_prod + 4 * 64 * k), 16, (int)(o * 4), 0, 0,
-                        kStream);
-                }
-                float xv[U][4];
-#pragma unroll
-                for (int k = 0; k < U; ++k)
-#pragma unroll
-                    for (int jj = 0; jj < 4; ++jj) xv[k][jj] = BufQuad<float>::gather(rx, qc[k][jj]);
-                // the values of this lane's quads are in LDS once every load of
-                // the lane has completed
-                __builtin_amdgcn_s_waitcnt(0);
-#pragma unroll
-                for (int k = 0; k < U; ++k) {
-                    f4 *slot = (f4 *)(my_prod + 4 * (lane + 64 * k));
-                    f4 v = *slot;
-                    v[0] = v[0] * xv[k][0];
-                    v[1] = v[1] * xv[k][1];
-                    v[2] = v[2] * xv[k][2];
-                    v[3] = v[3] * xv[k][3];
-                    *slot = v;
-                }
-                // the wave's own LDS writes, then its reads: in order within the wave
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                if (own) {
-                    IT jj = mylo;
-                    for (; jj + 4 <= myhi; jj += 4) {
-                        const float p0 = my_prod[jj - a0], p1 = my_prod[jj - a0 + 1];
-                        const float p2 = my_prod[jj - a0 + 2], p3 = my_prod[jj - a0 + 3];
-                        acc += p0;
-                        acc += p1;
-                        acc += p2;
-                        acc += p3;
-                    }
-                    for (; jj < myhi; ++jj) acc += my_prod[jj - a0];
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            } else {
-                // long rows: passes of CAPW entries through the wave's slice
-                for (IT a = b & ~(IT)3; a < e; a += CAPW) {
-                    const IT cs = a < b ? b : a;
-                    const IT ce = (e - a < (IT)CAPW) ? e : a + (IT)CAPW;
-                    for (IT i = a + 4 * lane; i < ce; i += 4 * 64) {
-                        const i4 c4 = __builtin_nontemporal_load((const GLB i4 *)(col + i));
-                        Quad<float> v4;
-                        v4.load(val + i);
-#pragma unroll
-                        for (int jj = 0; jj < 4; ++jj) {
-                            const IT idx = i + jj;
-                            if (idx >= cs && idx < ce) my_prod[idx - a] = v4[jj] * x[c4[jj]];
-                        }
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    if (own) {
-                        const IT lo = mylo > cs ? mylo : cs;
-                        const IT hi = myhi < ce ? myhi : ce;
-                        for (IT jj = lo; jj < hi; ++jj) acc += my_prod[jj - a];
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                }
-            }
-            // epilogue: rescale, sources, store, FP64 totals
-            float v = acc * scale;
-            const int sb = s_src[j], se = s_src[j + 1];
-            if (own && sb < se) {
-                const GLB int64_t *srow = gp(I.src_row);
-                int e2 = lower_bound_rows<IT>(I.src_row, sb, se, r);
-                double s = 0.0;
-                bool any = false;
-                for (; e2 < se && srow[e2] == r; ++e2) {
-                    s += gp(I.src_w)[e2] * gp(I.amp)[t * I.n_src + gp(I.src_id)[e2]];
-                    any = true;
-                }
-                if (any) v += (float)ldexp(s, -sc.En);
-            }
-            if (own) {
-                y[r] = v;
-                if (r < n_states) {
-                    sN += (double)v;
-                    sA += s_abs[q] * (double)v;
-                    mx = v > mx ? v : mx;
-                } else {
-                    sE += (double)v;
-                }
-            }
-            const int db = s_det[j], de = s_det[j + 1];
-            if (db < de) {
-                s_yw[wave][lane] = v;
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                // detector d is summed by lane d % 64 in register d / 64
-                for (int e2 = db; e2 < de; ++e2) {
-                    const int d = gp(I.det_id)[e2];
-                    if ((d & 63) == lane) {
-                        const double f = gp(I.det_F)[e2] * (double)s_yw[wave][gp(I.det_row)[e2] - r0];
-#pragma unroll
-                        for (int h = 0; h < kFinDetMax / 64; ++h)
-                            if ((d >> 6) == h) dsum[h] += f;
-                    }
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            }
-        }
-        // chunk partials: wave butterflies, then the waves in order
-        const int64_t nc = I.n_chunks, c = item.chunk;
-        const double wN = wave_sum(sN), wE = wave_sum(sE), wA = wave_sum(sA), wM = wave_max((double)mx);
-        if (lane == 0) {
-            s_wred[0][wave] = wN;
-            s_wred[1][wave] = wE;
-            s_wred[2][wave] = wA;
-            s_wred[3][wave] = wM;
-        }
-        __syncthreads();   // every wave is done with its product slice
-#pragma unroll
-        for (int h = 0; h < kFinDetMax / 64; ++h)
-            if (h * 64 + lane < nd) s_wdet[wave][h * 64 + lane] = dsum[h];
-        __syncthreads();
-        GLB double *part = gpw(I.partials);
-        if (tid < 4) {
-            double a = s_wred[tid][0];
-            for (int w = 1; w < NW; ++w) a = (tid == 3) ? fmax(a, s_wred[tid][w]) : a + s_wred[tid][w];
-            part[(int64_t)tid * nc + c] = a;
-        }
-        for (int d = tid; d < nd; d += 256) {
-            const double a = ((s_wdet[0][d] + s_wdet[1][d]) + s_wdet[2][d]) + s_wdet[3][d];
-            part[(int64_t)(kSlotDet + d) * nc + c] = a;
-        }
-        __syncthreads();
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1822,20 +1221,22 @@ __global__ void __launch_bounds__(kNT) spmm_detectors(const StepInst *__restrict
 // ---------------------------------------------------------------------------
 // SpMV step by row groups (one rhs, FP32, one solver)
 //
-// The row groups and the group-order arrays of the many-rhs step; here the
-// lanes are the members: each half-wave takes a group (lane m of the half is
-// member m), so a wave forms two groups at once, and the descriptors of the
-// wave's next two groups load while the current two are formed.  Lane m
-// loads x at column m (directly when the columns are one run, else through
-// the leader's column list) into LDS, then its own entries with one load per
-// k (the group's values are column-major, so a group's k-th entries are one
-// contiguous run) and adds entry * x over k in column order: the CSR step's
-// products in its order, so y equals its y bit for bit.  The matrix stream
-// is the values alone -- a group's columns are read once at most, not once
-// per row -- and x is read once per group.  Rows of other lengths than
-// kSpmmUnroll go through LDS in windows of 32 columns.  Work items are split
-// among the waves as in the many-rhs step (partials of index 4c + wave); the
-// detector sums are left to spmv_detectors.
+// The row groups and the group-order arrays of the many-rhs step.  The fast
+// groups -- full lattice rows, kSpmmUnroll columns in one run, nearly every
+// group -- go to step_spmv_grouped, whose lanes are the members: each
+// half-wave takes a group (lane m of the half is member m), so a wave forms
+// two groups at once, and the descriptors of the wave's next two groups load
+// while the current two are formed.  Lane m loads x at column m of the run
+// into LDS, then its own entries with one load per k (the group's values are
+// column-major, so a group's k-th entries are one contiguous run) and adds
+// entry * x over k in column order: the CSR step's products in its order, so
+// y equals its y bit for bit.  The matrix stream is the values alone (no
+// columns) and x is read once per group.  The rows of the other groups
+// (interface rows whose entries come from two voxels, a few members each)
+// go to step_spmv_rowlist, a thread per row.  Work items of the fast groups
+// are split among the waves as in the many-rhs step (partials of index
+// 4c + wave), those of the row list follow; the detector sums are left to
+// spmv_detectors.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kNT) step_spmv_grouped(const StepInst *__restrict__ insts,
                                                           const WorkItem *__restrict__ work, int64_t n_work,
@@ -1852,7 +1253,6 @@ __global__ void __launch_bounds__(kNT) step_spmv_grouped(const StepInst *__restr
     if (t >= *I.t_end) return;
     const Scale sc = step_scale(I, 0, t);
     const float scale = ldexpf(1.0f, -sc.k);
-    const GLB int32_t *col = gp(I.col);
     const GLB float *val = gp(I.grp_val);
     const GLB float *X = gp((const float *)((t & 1) ? I.buf1 : I.buf0));
     GLB float *Y = gpw((float *)((t & 1) ? I.buf0 : I.buf1));
@@ -1860,6 +1260,7 @@ __global__ void __launch_bounds__(kNT) step_spmv_grouped(const StepInst *__restr
     const GLB int32_t *grow = gp(I.grp_row);
     const GLB int32_t *src_tile = gp(I.src_tile);
     const CST GroupDesc *grp = cst(I.grp);
+    const CST int32_t *gfast = cst(I.grp_fast);
     const CST uint32_t *gsrc = cst(I.grp_src);
     float *sx = s_x[wave][h];
     const int64_t nv = I.nnz + 4;   // entries of the group-order values (with the padding)
@@ -1867,7 +1268,7 @@ __global__ void __launch_bounds__(kNT) step_spmv_grouped(const StepInst *__restr
     __syncthreads();
 
     const int R = I.rows_per_tile;
-    const int64_t G = I.n_groups;
+    const int64_t G = I.n_fast;
     for (int64_t wi = wk.begin; wi < wk.end; wi += wk.stride) {
         const int64_t c = work[wi].chunk;
         const int64_t c_b = c * G / n_work, c_e = (c + 1) * G / n_work;
@@ -1878,50 +1279,43 @@ __global__ void __launch_bounds__(kNT) step_spmv_grouped(const StepInst *__restr
             // the wave's two groups (a lone last group: both halves take it),
             // descriptors and source bits through the scalar cache; the next
             // pair's load while this pair is formed
-            GroupDesc D0 = load_desc(grp + g_b), D1 = load_desc(grp + min(g_b + 1, g_e - 1));
-            uint32_t w0 = gsrc[g_b >> 5], w1 = gsrc[min(g_b + 1, g_e - 1) >> 5];
+            int64_t ia = gfast[g_b], ib = gfast[min(g_b + 1, g_e - 1)];
+            GroupDesc D0 = load_desc(grp + ia), D1 = load_desc(grp + ib);
+            uint32_t w0 = gsrc[ia >> 5], w1 = gsrc[ib >> 5];
             for (int64_t g2 = g_b; g2 < g_e; g2 += 2) {
-                const int64_t ga = g2, gb = min(g2 + 1, g_e - 1);
+                const int64_t ga = ia, gb = ib;
                 const GroupDesc A0 = D0, A1 = D1;
                 const uint32_t s0 = w0, s1 = w1;
                 if (g2 + 2 < g_e) {
-                    D0 = load_desc(grp + g2 + 2);
-                    D1 = load_desc(grp + min(g2 + 3, g_e - 1));
-                    w0 = gsrc[(g2 + 2) >> 5];
-                    w1 = gsrc[min(g2 + 3, g_e - 1) >> 5];
+                    ia = gfast[g2 + 2];
+                    ib = gfast[min(g2 + 3, g_e - 1)];
+                    D0 = load_desc(grp + ia);
+                    D1 = load_desc(grp + ib);
+                    w0 = gsrc[ia >> 5];
+                    w1 = gsrc[ib >> 5];
                 }
                 // this half's group
-                const int nm = h ? A1.nm : A0.nm, n = h ? A1.n : A0.n;
+                const int nm = h ? A1.nm : A0.nm;
                 const int m0 = h ? A1.m0 : A0.m0, cstart = h ? A1.cstart : A0.cstart;
-                const int64_t voff = h ? A1.voff : A0.voff, coff = h ? A1.coff : A0.coff;
+                const int64_t voff = h ? A1.voff : A0.voff;
                 const bool g_src = h ? ((s1 >> (gb & 31)) & 1u) : ((s0 >> (ga & 31)) & 1u);
                 const bool mine = g2 + h < g_e && m < nm;
                 const int jm = min(m, nm - 1);
                 const int32_t r = grow[m0 + jm];
                 const int mt = gmat[m0 + jm];
+                const float xm = X[cstart + min(m, kSpmmUnroll - 1)];
+                // a buffer at the first group's values; each lane's entries at
+                // 32-bit offsets from it
+                const __amdgpu_buffer_rsrc_t rv = make_rsrc((const void *)(val + A0.voff), (uint64_t)(nv - A0.voff) * 4);
+                const uint32_t o0 = (uint32_t)(voff - A0.voff + jm) * 4, st = (uint32_t)nm * 4;
+                float vk[kSpmmUnroll];
+#pragma unroll
+                for (int k = 0; k < kSpmmUnroll; ++k)
+                    vk[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rv, (int)(o0 + k * st), 0, kStream));
+                sx[m] = xm;
                 float acc = 0.0f;
-                if (A0.n == kSpmmUnroll && A1.n == kSpmmUnroll && A0.cstart >= 0 && A1.cstart >= 0) {
-                    const float xm = X[cstart + min(m, kSpmmUnroll - 1)];
-                    // a buffer at the first group's values; each lane's
-                    // entries at 32-bit offsets from it
-                    const __amdgpu_buffer_rsrc_t rv =
-                        make_rsrc((const void *)(val + A0.voff), (uint64_t)(nv - A0.voff) * 4);
-                    const uint32_t o0 = (uint32_t)(voff - A0.voff + jm) * 4, st = (uint32_t)nm * 4;
-                    float vk[kSpmmUnroll];
 #pragma unroll
-                    for (int k = 0; k < kSpmmUnroll; ++k)
-                        vk[k] = __builtin_bit_cast(float,
-                                                   __builtin_amdgcn_raw_buffer_load_b32(rv, (int)(o0 + k * st), 0, kStream));
-                    sx[m] = xm;
-#pragma unroll
-                    for (int k = 0; k < kSpmmUnroll; ++k) acc += vk[k] * sx[k];
-                } else {
-                    for (int kb = 0; kb < n; kb += 32) {
-                        const int w = min(32, n - kb);
-                        sx[m] = X[col[coff + kb + min(m, w - 1)]];
-                        for (int k = 0; k < w; ++k) acc += val[voff + (int64_t)(kb + k) * nm + jm] * sx[k];
-                    }
-                }
+                for (int k = 0; k < kSpmmUnroll; ++k) acc += vk[k] * sx[k];
                 if (mine) {
                     float v = acc * scale;
                     if (g_src) {
@@ -1953,6 +1347,87 @@ __global__ void __launch_bounds__(kNT) step_spmv_grouped(const StepInst *__restr
         const double wN = wave_sum(sN), wE = wave_sum(sE), wA = wave_sum(sA), wM = wave_max((double)mx);
         if (lane == 0) {
             const int64_t nc = I.n_chunks, b = 4 * c + wave;
+            I.partials[(int64_t)kSlotN * nc + b] = wN;
+            I.partials[(int64_t)kSlotEsc * nc + b] = wE;
+            I.partials[(int64_t)kSlotAbs * nc + b] = wA;
+            I.partials[(int64_t)kSlotMax * nc + b] = wM;
+        }
+    }
+}
+
+// The rows of the groups step_spmv_grouped does not take, a thread per row:
+// work item j (blockIdx.x, then every gridDim.x-th) is rows kRowListItem j
+// onwards of the list; each row's entries are added in column order (the
+// tiled step's order), eight requested at a time; its partials are those of
+// index slow_part + 4j + wave.
+constexpr int kRowListWin = 8;
+
+template <typename IT>
+__global__ void __launch_bounds__(kNT) step_spmv_rowlist(const StepInst *__restrict__ insts)
+{
+    __shared__ double s_abs[kMatMax];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const StepInst &I = insts[0];
+    const int64_t t = I.t[0];
+    if (t >= *I.t_end) return;
+    const Scale sc = step_scale(I, 0, t);
+    const float scale = ldexpf(1.0f, -sc.k);
+    const GLB IT *rp = gp((const IT *)I.row_ptr);
+    const GLB int32_t *col = gp(I.col);
+    const GLB float *val = gp((const float *)I.val);
+    const GLB float *X = gp((const float *)((t & 1) ? I.buf1 : I.buf0));
+    GLB float *Y = gpw((float *)((t & 1) ? I.buf0 : I.buf1));
+    const GLB uint8_t *mat = gp(I.mat);
+    const GLB int32_t *src_tile = gp(I.src_tile);
+    for (int q = threadIdx.x; q < I.n_mat; q += kNT) s_abs[q] = gp(I.absorb)[q];
+    __syncthreads();
+    const int R = I.rows_per_tile;
+    const int64_t n_items = (I.n_slow + kRowListItem - 1) / kRowListItem;
+    for (int64_t j = blockIdx.x; j < n_items; j += gridDim.x) {
+        const int64_t i = j * kRowListItem + threadIdx.x;
+        double sN = 0.0, sE = 0.0, sA = 0.0;
+        float mx = 0.0f;
+        if (i < I.n_slow) {
+            const int64_t r = gp(I.slow_rows)[i];
+            const int64_t lo = (int64_t)rp[r], hi = (int64_t)rp[r + 1];
+            float acc = 0.0f;
+            for (int64_t kb = lo; kb < hi; kb += kRowListWin) {
+                float vw[kRowListWin], xw[kRowListWin];
+#pragma unroll
+                for (int u = 0; u < kRowListWin; ++u) {
+                    const int64_t k = min(kb + u, hi - 1);
+                    vw[u] = val[k];
+                    xw[u] = X[col[k]];
+                }
+#pragma unroll
+                for (int u = 0; u < kRowListWin; ++u)
+                    if (kb + u < hi) acc += vw[u] * xw[u];
+            }
+            float v = acc * scale;
+            const int tile = (int)(r / R);
+            const int sb = src_tile[tile], se = src_tile[tile + 1];
+            if (sb < se) {
+                int e2 = lower_bound_rows<IT>(I.src_row, sb, se, r);
+                double s = 0.0;
+                bool any = false;
+                for (; e2 < se && I.src_row[e2] == r; ++e2) {
+                    s += I.src_w[e2] * I.amp[t * I.n_src + I.src_id[e2]];
+                    any = true;
+                }
+                if (any) v += (float)ldexp(s, -sc.En);
+            }
+            Y[r] = v;
+            if (r < I.n_states) {
+                sN += (double)v;
+                sA += s_abs[mat[vox_of(r, I.vox_mul)]] * (double)v;
+                mx = fmaxf(mx, v);
+            } else {
+                sE += (double)v;
+            }
+        }
+        const double wN = wave_sum(sN), wE = wave_sum(sE), wA = wave_sum(sA), wM = wave_max((double)mx);
+        if (lane == 0) {
+            const int64_t nc = I.n_chunks, b = I.slow_part + 4 * j + wave;
             I.partials[(int64_t)kSlotN * nc + b] = wN;
             I.partials[(int64_t)kSlotEsc * nc + b] = wE;
             I.partials[(int64_t)kSlotAbs * nc + b] = wA;
@@ -3055,7 +2530,7 @@ __global__ void __launch_bounds__(256) step_struct_mm_x(StructArgs sa, const Ste
 hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int64_t n_work, int n_inst,
                        int n_rhs_max, int value_f64, int rp64, int spmm, int grid, int xcd_remap,
                        const int64_t *xcd_bounds, int rows_per_tile, int n_det_max, int32_t *queue,
-                       hipStream_t stream)
+                       hipStream_t stream, int64_t n_slow)
 {
     (void)n_inst;
     (void)n_rhs_max;
@@ -3089,22 +2564,18 @@ hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int6
         const dim3 g1((unsigned)grid);
         const int variant = (xcd_remap >> 1) & 15;
         const int remap = xcd_remap & 1;
-#define DRTS_SPMV1(VT, IT, NTV, RV, P, L) \
-    hipLaunchKernelGGL((step_spmv<VT, IT, NTV, RV, P, L>), g1, dim3(NTV), 0, stream, insts_dev, work_dev, n_work, \
-                       remap, xcd_bounds, queue)
-#define DRTS_SPMV(VT, IT, RV)                                        \
-    do {                                                             \
-        if (variant == 1) DRTS_SPMV1(VT, IT, RV, RV, 1, 0);          \
-        else if (variant == 2) DRTS_SPMV1(VT, IT, 2 * RV, RV, 0, 0); \
-        else if (variant == 3) DRTS_SPMV1(VT, IT, 2 * RV, RV, 1, 0); \
-        else if (variant == 4) DRTS_SPMV1(VT, IT, RV, RV, 0, 1);     \
-        else if (variant == 7) DRTS_SPMV1(VT, IT, RV, RV, 0, 2);     \
-        else DRTS_SPMV1(VT, IT, RV, RV, 0, 0);                       \
-    } while (0)
-        const int nt = rows_per_tile <= 64 ? 64 : (rows_per_tile <= 128 ? 128 : 256);
         if (variant == DRTS_SPMV_GROUPED) {
+            // the fast groups, then the other groups' rows, then the detectors
             hipLaunchKernelGGL(step_spmv_grouped, g1, dim3(kNT), 0, stream, insts_dev, work_dev, n_work, remap,
                                xcd_bounds);
+            const hipError_t e0 = hipGetLastError();
+            if (e0 != hipSuccess) return e0;
+            if (n_slow > 0) {
+                const int64_t items = (n_slow + kRowListItem - 1) / kRowListItem;
+                const dim3 gr((unsigned)std::min<int64_t>(items, 2048));
+                if (rp64) hipLaunchKernelGGL(step_spmv_rowlist<int64_t>, gr, dim3(kNT), 0, stream, insts_dev);
+                else hipLaunchKernelGGL(step_spmv_rowlist<int32_t>, gr, dim3(kNT), 0, stream, insts_dev);
+            }
             if (n_det_max > 0) {
                 const hipError_t e = hipGetLastError();
                 if (e != hipSuccess) return e;
@@ -3124,37 +2595,16 @@ hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int6
             }
             return hipGetLastError();
         }
-        if (variant == 8 && !value_f64) {
-            // tiles of kWaveTileRows rows, one wave each, values through LDS
-            if (rp64)
-                hipLaunchKernelGGL((step_spmv_wl<int64_t>), g1, dim3(256), 0, stream, insts_dev, work_dev, n_work,
-                                   remap, xcd_bounds);
-            else
-                hipLaunchKernelGGL((step_spmv_wl<int32_t>), g1, dim3(256), 0, stream, insts_dev, work_dev, n_work,
-                                   remap, xcd_bounds);
-            return hipGetLastError();
-        }
-        if (variant == 5 || variant == 6) {
-            // tiles of kWaveTileRows rows, one wave each
-#define DRTS_WAVE(VT, IT)                                                                                          \
-    do {                                                                                                           \
-        if (variant == 6)                                                                                          \
-            hipLaunchKernelGGL((step_spmv_wave<VT, IT, 1>), g1, dim3(256), 0, stream, insts_dev, work_dev, n_work, \
-                               remap, xcd_bounds);                                                                 \
-        else                                                                                                       \
-            hipLaunchKernelGGL((step_spmv_wave<VT, IT, 0>), g1, dim3(256), 0, stream, insts_dev, work_dev, n_work, \
-                               remap, xcd_bounds);                                                                 \
+        // the tiled step: quads through registers, or FP32 values straight into LDS
+#define DRTS_SPMV1(VT, IT, RV, L) \
+    hipLaunchKernelGGL((step_spmv<VT, IT, RV, L>), g1, dim3(RV), 0, stream, insts_dev, work_dev, n_work, remap, \
+                       xcd_bounds, queue)
+#define DRTS_SPMV(VT, IT, RV)                                           \
+    do {                                                                \
+        if (variant == DRTS_SPMV_LDS && sizeof(VT) == 4) DRTS_SPMV1(VT, IT, RV, 2); \
+        else DRTS_SPMV1(VT, IT, RV, 0);                                 \
     } while (0)
-            if (value_f64) {
-                if (rp64) DRTS_WAVE(double, int64_t);
-                else DRTS_WAVE(double, int32_t);
-            } else {
-                if (rp64) DRTS_WAVE(float, int64_t);
-                else DRTS_WAVE(float, int32_t);
-            }
-#undef DRTS_WAVE
-            return hipGetLastError();
-        }
+        const int nt = rows_per_tile <= 64 ? 64 : (rows_per_tile <= 128 ? 128 : 256);
         if (value_f64) {
             if (rp64) {
                 if (nt == 64) DRTS_SPMV(double, int64_t, 64);

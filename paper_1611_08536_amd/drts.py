@@ -24,7 +24,7 @@ INTERFACE = {"origin": 0, "substep": 1}
 BC = {"vacuum": 0, "reflect": 1}
 KERNEL_CSR, KERNEL_STRUCTURED, KERNEL_STRUCTURED_F64SUM = 0, 1, 2
 SPMM_GROUPED, SPMM_ROWS = 0, 1   # variant of a many-rhs CSR solver
-SPMV_ROW, SPMV_LDS, SPMV_GROUPED = 0, 7, 9   # variants of a single-rhs CSR solver
+SPMV_ROW, SPMV_LDS, SPMV_GROUPED = 0, 1, 2   # variants of a single-rhs CSR solver
 SERVE_ARRIVAL, SERVE_SHORTEST = 0, 1
 
 if not os.path.exists(LIB_PATH):
@@ -313,6 +313,13 @@ class Matrix:
                "drts_matrix_info")
         self.n_states, self.n_escape, self.nnz, self.bytes, self.dt = a.value, b.value, c.value, d.value, dt.value
         self.n_rows = self.n_states + self.n_escape
+
+    def device_bytes(self) -> int:
+        """Device bytes the matrix holds now: the CSR arrays, and the row groups
+        once a solo solver has asked for the grouped step."""
+        d = i64()
+        _check(_lib.drts_matrix_info(self._h, None, None, None, C.byref(d), None), "drts_matrix_info")
+        return d.value
 
     def close(self):
         if getattr(self, "_h", None):

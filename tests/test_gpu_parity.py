@@ -180,10 +180,8 @@ def test_spmv_variants_give_identical_states(rpt):
     column order: states bit for bit; FP64 totals differ at most in the order
     of the per-wave partial sums."""
     wl = W.c2(n=18)
-    ref = _state_and_series(wl, 30, options={"rows_per_tile": rpt, "variant": 0})
-    for v in (1, 2, 3, 4, 5, 6, 7, 8):
-        if v in (5, 6, 8) and rpt != 64:
-            continue
+    ref = _state_and_series(wl, 30, options={"rows_per_tile": rpt, "variant": drts.SPMV_ROW})
+    for v in (drts.SPMV_LDS, drts.SPMV_GROUPED):
         got = _state_and_series(wl, 30, options={"rows_per_tile": rpt, "variant": v})
         assert np.array_equal(ref[0], got[0]) and np.array_equal(ref[1], got[1]), v
         assert np.array_equal(ref[3], got[3]), v
@@ -276,7 +274,7 @@ def test_reflecting_walls_conserve_in_fp64():
     assert np.all(out["tot"][:, 1, 0] == 0.0)
 
 
-@pytest.mark.parametrize("variant", [0, 7])
+@pytest.mark.parametrize("variant", [0, 1, 2], ids=["row", "lds", "grouped"])
 def test_ragged_tail_and_tiny_tiles(variant):
     """Row counts that are not a multiple of the tile, the smallest tile."""
     med = W.homogeneous(5, W.Material(3.0, 0.05, 0.6, 1.4), ny=3, nz=7)
@@ -310,12 +308,12 @@ def test_multi_pass_tiles_between_fitting_tiles(rpt, tpc):
     per_tile = [(rp[min((k + 1) * rpt, A.n_rows)] - rp[k * rpt]) / rpt for k in range((A.n_rows + rpt - 1) // rpt)]
     assert any(a > 28 for a in per_tile) and any(a <= 27 for a in per_tile)
     got = {}
-    for v in (0, 7):
+    for v in (drts.SPMV_ROW, drts.SPMV_LDS):
         got[v] = solve.run(wl, options={"rows_per_tile": rpt, "tiles_per_chunk": tpc, "grid": 16, "variant": v})
     for k in ("x", "x_exp", "tot", "exp2", "det"):
-        assert np.array_equal(got[0][k], got[7][k]), k
+        assert np.array_equal(got[drts.SPMV_ROW][k], got[drts.SPMV_LDS][k]), k
     ref = oracle.run_workload(A, wl)
-    out = got[7]
+    out = got[drts.SPMV_LDS]
     assert parity.rel_err_series(out["det"][:, 0, 0], out["exp2"][:, 0], ref["det"][:, 0],
                                  ref["det_exp"][:, 0]) <= 1e-5
     assert parity.rel_l1(out["x"][:A.n_states, 0], out["x_exp"][0], ref["x"], ref["x_exp"]) <= 1e-5
@@ -333,9 +331,11 @@ def test_errors_are_reported():
     M64 = drts.Matrix(wl.medium, "f64")
     S64 = drts.Solver(M64, 1, wl.detectors, max_steps=5)
     with pytest.raises(drts.DrtsError):
-        S64.set_options(variant=7)          # the LDS layouts take FP32 values
+        S64.set_options(variant=drts.SPMV_LDS)       # the LDS and grouped layouts take FP32 values
     with pytest.raises(drts.DrtsError):
-        S64.set_options(variant=8, rows_per_tile=64)
+        S64.set_options(variant=drts.SPMV_GROUPED)
+    with pytest.raises(drts.DrtsError):
+        S64.set_options(variant=3)                   # no such variant
     bad = W.homogeneous(4, W.Material(1.0, 0.1, 1.5, 1.4))
     with pytest.raises(drts.DrtsError) as ei:
         drts.Matrix(bad)
