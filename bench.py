@@ -28,8 +28,11 @@ PEAK_HBM_GBS = 8000.0
 F64SUM_NOTE = ("FP32 values and state, each row summed in FP64 and rounded once: outside the "
                "FP32-accumulation precision pattern (more accurate than it)")
 STEP_SOURCES = ("paper_1611_08536_amd/csrc/drts_step.hip", "paper_1611_08536_amd/csrc/drts_step.h")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_spmv_c2_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_spmv_grouped_c2_traffic.txt")
 SPMV_KERNEL = "step_spmv_grouped"
+# the kernels of one headline step launch (the finalize aside): the fast
+# groups, the row list of the other groups, the detector sums
+STEP_KERNELS = ("step_spmv_grouped", "step_spmv_rowlist", "spmv_detectors")
 CALIB_KERNEL = "vectorized_elementwise_kernel"
 CALIB_BYTES = 2 ** 30          # the calibration kernel reads and writes 1 GiB
 GRAPH_STEPS = 50               # steps per hipGraph replay in the timed run
@@ -60,22 +63,28 @@ def _counter_means(path, counter):
 
 
 def traffic_from_counters(fetch_csv, write_csv):
-    """HBM bytes per launch of the SpMV step from the FETCH_SIZE and WRITE_SIZE
-    passes, each scaled by what the same counter reads for a plain elementwise
-    kernel that reads and writes CALIB_BYTES."""
+    """HBM bytes per headline step launch (the STEP_KERNELS, per-dispatch means
+    added) from the FETCH_SIZE and WRITE_SIZE passes, each scaled by what the
+    same counter reads for a plain elementwise kernel that reads and writes
+    CALIB_BYTES."""
     out = {}
     for name, path in (("fetch", fetch_csv), ("write", write_csv)):
         m = _counter_means(path, "FETCH_SIZE" if name == "fetch" else "WRITE_SIZE")
-        spmv = [v for k, v in m.items() if SPMV_KERNEL in k]
+        per = {}
+        for kern in STEP_KERNELS:
+            hits = [v for k, v in m.items() if kern + "(" in k or kern + "<" in k]
+            if len(hits) != 1:
+                raise SystemExit("counter file %s: %d entries for %s" % (path, len(hits), kern))
+            per[kern] = hits[0]
         calib = [v for k, v in m.items() if CALIB_KERNEL in k]
-        if len(spmv) != 1 or not calib:
-            raise SystemExit("counter file %s lacks the step or the calibration kernel" % path)
+        if not calib:
+            raise SystemExit("counter file %s lacks the calibration kernel" % path)
         factor = CALIB_BYTES / (max(calib) * 1024.0)
-        out[name + "_kib"] = spmv[0]
+        out[name + "_kib"] = {k: round(v, 2) for k, v in per.items()}
         out[name + "_factor"] = round(factor, 4)
-        out[name + "_bytes"] = spmv[0] * 1024.0 * factor
+        out[name + "_bytes"] = sum(per.values()) * 1024.0 * factor
     out["bytes_per_launch"] = out["fetch_bytes"] + out["write_bytes"]
-    out["kernel"] = SPMV_KERNEL
+    out["kernel"] = " + ".join(STEP_KERNELS)
     out["source_sha256"] = step_source_hash()
     return out
 
@@ -520,6 +529,7 @@ def main():
     S.run(tab, args.warmup)
     torch.cuda.synchronize()
     group_bytes = A.device_bytes() - A.bytes
+    groups = A.groups()
 
     _log("timing %d steps (graph replay)" % args.steps)
     stream = torch.cuda.current_stream()
@@ -607,6 +617,9 @@ def main():
                      "format_bytes_basis": "what the step by row groups must move: values in group order, "
                                            "members' rows and materials, descriptors, x and y once",
                      "traffic_unit": "GB per launch"},
+        "row_groups": None if groups is None else {"groups": groups[0], "fast_groups": groups[1],
+                                                    "rows_taken_one_by_one": groups[2],
+                                                    "device_bytes": group_bytes},
         "tiled_step": {"kernel": "step_spmv<float, int, 256, 2> (values straight into LDS, 4 tiles per chunk)",
                        "kernel_ms": round(tiled_kernel_ms, 4),
                        "frac": round(nbytes / (tiled_kernel_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},

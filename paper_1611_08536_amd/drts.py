@@ -119,6 +119,7 @@ _sig("drts_direction_set", C.c_int, [i32, P, P])
 _sig("drts_matrix_info", C.c_int, [P, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64),
                                    C.POINTER(dbl)])
 _sig("drts_matrix_row_of", i64, [P, i64, i32])
+_sig("drts_matrix_groups", C.c_int, [P, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)])
 _sig("drts_matrix_export_rows", C.c_int, [P, i64, i64, P, P, P])
 _sig("drts_matrix_destroy", None, [P])
 _sig("drts_solver_create", C.c_int, [P, i32, C.POINTER(DetectorsT), i64, C.POINTER(DeviceT), C.POINTER(P)])
@@ -153,7 +154,7 @@ _sig("drts_serve_destroy", None, [P])
 _sig("drts_serve_set_step", C.c_int, [P, i32])
 
 EXPORTED = [
-    "drts_direction_set", "drts_build_matrix", "drts_matrix_info", "drts_matrix_row_of", "drts_matrix_export_rows",
+    "drts_direction_set", "drts_build_matrix", "drts_matrix_info", "drts_matrix_groups", "drts_matrix_row_of", "drts_matrix_export_rows",
     "drts_matrix_destroy", "drts_solver_create", "drts_solver_get_options", "drts_solver_set_options",
     "drts_step", "drts_step_noalloc", "drts_run", "drts_solver_time", "drts_detector_readout", "drts_detector_window", "drts_state_read",
     "drts_state_write", "drts_solver_profile", "drts_solver_profile_stats", "drts_solver_destroy",
@@ -320,6 +321,16 @@ class Matrix:
         d = i64()
         _check(_lib.drts_matrix_info(self._h, None, None, None, C.byref(d), None), "drts_matrix_info")
         return d.value
+
+    def groups(self):
+        """(groups, fast groups, rows of the other groups) of the matrix's row
+        groups, or None while they are not built."""
+        a, b, c = i64(), i64(), i64()
+        rc = _lib.drts_matrix_groups(self._h, C.byref(a), C.byref(b), C.byref(c))
+        if rc == -5:
+            return None
+        _check(rc, "drts_matrix_groups")
+        return a.value, b.value, c.value
 
     def close(self):
         if getattr(self, "_h", None):

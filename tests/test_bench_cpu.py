@@ -29,17 +29,18 @@ def _counters(path, counter, rows):
 
 
 def test_traffic_scales_each_counter_by_the_copy_kernel(bench, tmp_path):
-    step = "void drts::(anonymous namespace)::%s(args)" % bench.SPMV_KERNEL
+    k0, k1, k2 = ("void drts::(anonymous namespace)::%s(args)" % k for k in bench.STEP_KERNELS)
     calib = "void at::native::%s<...>(args)" % bench.CALIB_KERNEL
     gib_kib = bench.CALIB_BYTES / 1024.0
     # the copy kernel reads 1 GiB and writes 1 GiB; its FETCH_SIZE reads half
-    _counters(tmp_path / "f.csv", "FETCH_SIZE", [(step, 1000.0), (step, 3000.0), (calib, gib_kib / 2),
-                                                 ("other", 7.0)])
-    _counters(tmp_path / "w.csv", "WRITE_SIZE", [(step, 50.0), (step, 150.0), (calib, gib_kib)])
+    _counters(tmp_path / "f.csv", "FETCH_SIZE", [(k0, 1000.0), (k0, 3000.0), (k1, 10.0), (k2, 1.0),
+                                                 (calib, gib_kib / 2), ("other", 7.0)])
+    _counters(tmp_path / "w.csv", "WRITE_SIZE", [(k0, 50.0), (k0, 150.0), (k1, 4.0), (k2, 0.0), (calib, gib_kib)])
     t = bench.traffic_from_counters(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"))
-    assert t["fetch_kib"] == 2000.0 and t["write_kib"] == 100.0      # per-dispatch means
+    assert t["fetch_kib"] == {bench.STEP_KERNELS[0]: 2000.0, bench.STEP_KERNELS[1]: 10.0,
+                              bench.STEP_KERNELS[2]: 1.0}      # per-dispatch means
     assert t["fetch_factor"] == 2.0 and t["write_factor"] == 1.0
-    assert t["bytes_per_launch"] == 2000.0 * 1024 * 2 + 100.0 * 1024
+    assert t["bytes_per_launch"] == (2000.0 + 10.0 + 1.0) * 1024 * 2 + (100.0 + 4.0) * 1024
     assert t["source_sha256"] == bench.step_source_hash()
 
 
