@@ -109,12 +109,16 @@ def spmv_bytes(nnz, n_rows, n_states, val_bytes=4):
     return val_bytes * nnz + 4 * nnz + 4 * (n_rows + 1) + val_bytes * n_states + val_bytes * n_rows
 
 
-def grouped_bytes(group_bytes, n_rows, n_states):
-    """Bytes the step by row groups must move: its group arrays once (the
-    values in group order, each member's row and material, one descriptor
-    per group), x once, y once (the columns of groups whose columns are not
-    one run are not counted: a few interface groups)."""
-    return group_bytes + 4 * n_states + 4 * n_rows
+def grouped_bytes(n_rows, n_states, n_groups, n_fast, n_slow, slow_nnz):
+    """Bytes the step by row groups must move.  Members of fast groups
+    (26 entries a row): their values in group order (4 per entry), row id (4)
+    and material (1), per fast group its descriptor (32), list entry (4) and
+    source bit.  Rows taken one by one: their CSR entries (8 per entry), row
+    pointer (4), material (1) and list entry (4).  x once, y once."""
+    fast_rows = n_rows - n_slow
+    fast = 4 * 26 * fast_rows + 5 * fast_rows + 36 * n_fast + (n_groups + 7) // 8
+    slow = 8 * slow_nnz + 9 * n_slow
+    return fast + slow + 4 * n_states + 4 * n_rows
 
 
 def cpu_baseline(n=128, steps=50, steps_1=3):
@@ -578,7 +582,7 @@ def main():
 
     nbytes = spmv_bytes(A.nnz, A.n_rows, A.n_states)
     achieved = nbytes / (avg_kernel_ms * 1e-3) / 1e9
-    fbytes = grouped_bytes(group_bytes, A.n_rows, A.n_states)
+    fbytes = None if not groups or groups[0] == 0 else grouped_bytes(A.n_rows, A.n_states, *groups)
     traffic = load_traffic()
     if args.copy_calibration:
         a = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device="cuda")
@@ -613,12 +617,15 @@ def main():
                      "algorithmic_bytes": nbytes,
                      "algorithmic_bytes_basis": "CSR [A;L]: 8 B per entry, row pointers, x and y once",
                      "format_bytes": fbytes,
-                     "format_frac": round(fbytes / (avg_kernel_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
-                     "format_bytes_basis": "what the step by row groups must move: values in group order, "
-                                           "members' rows and materials, descriptors, x and y once",
+                     "format_frac": None if fbytes is None else
+                     round(fbytes / (avg_kernel_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                     "format_bytes_basis": "what the step by row groups must move: fast groups' values in group "
+                                           "order, members' rows and materials, descriptors; the other rows' CSR "
+                                           "entries; x and y once",
                      "traffic_unit": "GB per launch"},
         "row_groups": None if groups is None else {"groups": groups[0], "fast_groups": groups[1],
                                                     "rows_taken_one_by_one": groups[2],
+                                                    "their_entries": groups[3],
                                                     "device_bytes": group_bytes},
         "tiled_step": {"kernel": "step_spmv<float, int, 256, 2> (values straight into LDS, 4 tiles per chunk)",
                        "kernel_ms": round(tiled_kernel_ms, 4),

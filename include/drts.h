@@ -249,10 +249,12 @@ int drts_matrix_info(const drts_matrix_t *A, int64_t *n_states, int64_t *n_escap
 
 /* The row groups of an assembled matrix (rows whose column lists are equal;
  * built when a solo solver first runs a grouped step): groups, fast groups
- * (full lattice rows whose columns are one run) and rows of the other groups.
- * Any output pointer may be NULL.  Returns DRTS_E_STATE while the groups are
- * not built, and sets all three to 0 when the rows do not group. */
-int drts_matrix_groups(const drts_matrix_t *A, int64_t *n_groups, int64_t *n_fast, int64_t *n_slow_rows);
+ * (full lattice rows whose columns are one run), rows of the other groups
+ * (the step takes them one by one from the CSR) and their entries.  Any
+ * output pointer may be NULL.  Returns DRTS_E_STATE while the groups are not
+ * built, and sets all four to 0 when the rows do not group. */
+int drts_matrix_groups(const drts_matrix_t *A, int64_t *n_groups, int64_t *n_fast, int64_t *n_slow_rows,
+                       int64_t *n_slow_entries);
 
 /* Row index of state s (escape = 0 -> s itself; escape = 1 -> its escape row,
  * or -1 when the state does not leave the grid or faces reflect). */

@@ -1089,13 +1089,15 @@ int drts_matrix_info(const drts_matrix_t *A, int64_t *n_states, int64_t *n_escap
     return DRTS_OK;
 }
 
-int drts_matrix_groups(const drts_matrix_t *A, int64_t *n_groups, int64_t *n_fast, int64_t *n_slow_rows)
+int drts_matrix_groups(const drts_matrix_t *A, int64_t *n_groups, int64_t *n_fast, int64_t *n_slow_rows,
+                       int64_t *n_slow_entries)
 {
     if (!A) return set_error(DRTS_E_INVALID, "matrix is NULL");
     if (A->m.n_groups < 0) return set_error(DRTS_E_STATE, "the row groups are not built (no grouped step has run)");
     if (n_groups) *n_groups = A->m.n_groups;
     if (n_fast) *n_fast = A->m.n_groups > 0 ? A->m.n_fast : 0;
     if (n_slow_rows) *n_slow_rows = A->m.n_groups > 0 ? A->m.n_slow : 0;
+    if (n_slow_entries) *n_slow_entries = A->m.n_groups > 0 ? A->m.n_slow_nnz : 0;
     return DRTS_OK;
 }
 

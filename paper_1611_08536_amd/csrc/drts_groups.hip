@@ -134,10 +134,11 @@ __global__ void __launch_bounds__(256) group_flag_bits(const GroupDesc *desc, co
     bits[w] = word;
 }
 
-// fast groups (a full lattice row: kSpmmUnroll columns that are one run)
-// and, per member, whether its group is not one
+// fast groups (a full lattice row: kSpmmUnroll columns that are one run),
+// per member whether its group is not one, and the entries of those members
+// (an integer count: the order of the additions does not matter)
 __global__ void __launch_bounds__(256) group_kinds(const GroupDesc *desc, int64_t n_groups, uint8_t *fast,
-                                                   uint8_t *member_slow)
+                                                   uint8_t *member_slow, unsigned long long *slow_entries)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n_groups) return;
@@ -145,6 +146,7 @@ __global__ void __launch_bounds__(256) group_kinds(const GroupDesc *desc, int64_
     const bool f = D.n == kSpmmUnrollHost && D.cstart >= 0;
     fast[g] = f ? 1 : 0;
     for (int j = 0; j < D.nm; ++j) member_slow[D.m0 + j] = f ? 0 : 1;
+    if (!f) atomicAdd(slow_entries, (unsigned long long)D.n * (unsigned long long)D.nm);
 }
 
 __global__ void __launch_bounds__(256) group_scatter(const int32_t *flag, const int32_t *pos, int64_t n,
@@ -264,9 +266,10 @@ int build_groups(Matrix &A)
     Buffer fast, mslow, iota, cnt;
     if ((rc = fast.allocate(&dev, G))) return rc;
     if ((rc = mslow.allocate(&dev, R))) return rc;
-    if ((rc = cnt.allocate(&dev, 2 * sizeof(int64_t)))) return rc;
+    if ((rc = cnt.allocate(&dev, 3 * sizeof(int64_t)))) return rc;
+    DRTS_HIP(hipMemsetAsync(cnt.ptr, 0, 3 * sizeof(int64_t), dev.stream));
     hipLaunchKernelGGL(group_kinds, dim3(gblocks), dim3(256), 0, dev.stream, A.grp_desc.as<GroupDesc>(), G,
-                       fast.as<uint8_t>(), mslow.as<uint8_t>());
+                       fast.as<uint8_t>(), mslow.as<uint8_t>(), (unsigned long long *)(cnt.as<int64_t>() + 2));
     DRTS_HIP(hipGetLastError());
     if ((rc = A.grp_fast.allocate(&dev, G * sizeof(int32_t)))) return rc;
     if ((rc = A.slow_rows.allocate(&dev, R * sizeof(int32_t)))) return rc;
@@ -281,11 +284,12 @@ int build_groups(Matrix &A)
                                            cnt.as<int64_t>(), (int)G, dev.stream));
     DRTS_HIP(hipcub::DeviceSelect::Flagged(tmp.ptr, tb5, A.grp_row.as<int32_t>(), mslow.as<uint8_t>(),
                                            A.slow_rows.as<int32_t>(), cnt.as<int64_t>() + 1, (int)R, dev.stream));
-    int64_t counts[2] = {0, 0};
+    int64_t counts[3] = {0, 0, 0};
     DRTS_HIP(hipMemcpyAsync(counts, cnt.ptr, sizeof counts, hipMemcpyDeviceToHost, dev.stream));
     DRTS_HIP(hipStreamSynchronize(dev.stream));
     A.n_fast = counts[0];
     A.n_slow = counts[1];
+    A.n_slow_nnz = counts[2];
     A.n_groups = G;
     return DRTS_OK;
 }

@@ -125,7 +125,7 @@ struct Matrix {
     // for the single-rhs step: the fast groups (kSpmmUnroll columns in one
     // run, by index) and the rows of all other groups
     Buffer grp_fast, slow_rows;
-    int64_t n_fast = 0, n_slow = 0;
+    int64_t n_fast = 0, n_slow = 0, n_slow_nnz = 0;
     int64_t bytes() const;         // the CSR arrays (and the row groups, once built)
     int64_t table_bytes() const;   // everything else on the device (tables of the model)
 };

@@ -119,7 +119,7 @@ _sig("drts_direction_set", C.c_int, [i32, P, P])
 _sig("drts_matrix_info", C.c_int, [P, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64),
                                    C.POINTER(dbl)])
 _sig("drts_matrix_row_of", i64, [P, i64, i32])
-_sig("drts_matrix_groups", C.c_int, [P, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)])
+_sig("drts_matrix_groups", C.c_int, [P, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)])
 _sig("drts_matrix_export_rows", C.c_int, [P, i64, i64, P, P, P])
 _sig("drts_matrix_destroy", None, [P])
 _sig("drts_solver_create", C.c_int, [P, i32, C.POINTER(DetectorsT), i64, C.POINTER(DeviceT), C.POINTER(P)])
@@ -323,14 +323,14 @@ class Matrix:
         return d.value
 
     def groups(self):
-        """(groups, fast groups, rows of the other groups) of the matrix's row
-        groups, or None while they are not built."""
-        a, b, c = i64(), i64(), i64()
-        rc = _lib.drts_matrix_groups(self._h, C.byref(a), C.byref(b), C.byref(c))
+        """(groups, fast groups, rows of the other groups, their entries) of
+        the matrix's row groups, or None while they are not built."""
+        a, b, c, d = i64(), i64(), i64(), i64()
+        rc = _lib.drts_matrix_groups(self._h, C.byref(a), C.byref(b), C.byref(c), C.byref(d))
         if rc == -5:
             return None
         _check(rc, "drts_matrix_groups")
-        return a.value, b.value, c.value
+        return a.value, b.value, c.value, d.value
 
     def close(self):
         if getattr(self, "_h", None):

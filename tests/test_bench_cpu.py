@@ -69,3 +69,19 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_grouped_bytes_against_the_csr_count(bench):
+    """With every row in a fast group the format's bytes are the CSR count
+    minus the columns (4 per entry) and the row pointers, plus 5 per row and
+    36 (+ a bit) per group; rows taken one by one cost what the CSR costs."""
+    n_vox = 1000
+    R = 26 * n_vox + 2000            # states and escape rows
+    n_states = 26 * n_vox
+    nnz = 26 * R
+    csr = bench.spmv_bytes(nnz, R, n_states)
+    fast = bench.grouped_bytes(R, n_states, n_vox + 100, n_vox + 100, 0, 0)
+    assert fast == csr - 4 * nnz - 4 * (R + 1) + 5 * R + 36 * (n_vox + 100) + (n_vox + 100 + 7) // 8
+    # moving 10 rows of 40 entries from the groups to the row list
+    slow = bench.grouped_bytes(R + 10, n_states, n_vox + 100, n_vox + 100, 10, 400)
+    assert slow - fast == 4 * 10 + 8 * 400 + 9 * 10

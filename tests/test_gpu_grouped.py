@@ -135,6 +135,18 @@ def test_grouped_spmv_equals_tiled(name, make):
         assert np.allclose(a["tot"], o["tot"], rtol=1e-13, atol=0)
         assert np.allclose(a["det"], o["det"], rtol=1e-13, atol=0)
     assert (a["tot"][:, 0, :] > 0).any()
+    # the group counts: every row is a member of one group; a fast group's
+    # members hold 26 entries, the other rows' entries are counted apart
+    M = a["matrix"]
+    n_groups, n_fast, n_slow, slow_nnz = M.groups()
+    if name == "lebedev":
+        assert (n_groups, n_fast, n_slow, slow_nnz) == (0, 0, 0, 0)
+    else:
+        assert 0 < n_groups <= M.n_rows and 0 <= n_fast <= n_groups and 0 <= n_slow <= M.n_rows
+        assert M.nnz == 26 * (M.n_rows - n_slow) + slow_nnz
+    if name == "slab":
+        # matched index at the faces: each voxel's 26 rows (state or escape) form one fast group
+        assert n_groups == n_fast == M.n_states // 26 and n_slow == 0
     for o in (a, b, c):
         o["solver"].close()
 
