@@ -213,6 +213,28 @@ typedef struct {
     int32_t (*rhs_of)(void *ctx, int32_t src);
 } drts_source_table_t;
 
+/* Pulse shapes for amplitude() (Sec. 4.1, Eq. 26 with a time profile that
+ * varies within a step): the photons of a pulse of unit total emitted during
+ * step `step`, i.e. its time profile integrated over [step dt, (step+1) dt).
+ *   DRTS_PULSE_IMPULSE   every photon in step 0;
+ *   DRTS_PULSE_GAUSSIAN  a Gaussian of full width at half maximum fwhm_s
+ *                        seconds with its peak at three standard deviations;
+ *                        step 0 also takes the (tiny) part before t = 0, so
+ *                        the steps sum to one.  Evaluated with erfc, so the
+ *                        tails carry no cancellation. */
+#define DRTS_PULSE_IMPULSE 0
+#define DRTS_PULSE_GAUSSIAN 1
+typedef struct {
+    int32_t kind;  /* DRTS_PULSE_* */
+    double fwhm_s; /* Gaussian: full width at half maximum, seconds (> 0) */
+} drts_pulse_t;
+
+/* Photons pulse p emits during step `step` of length dt_s seconds.  Host
+ * function, no device work.  Returns NaN for a NULL or unknown pulse, a
+ * Gaussian with fwhm_s <= 0, dt_s <= 0 or step < 0 (and sets the last
+ * error). */
+double drts_pulse_step(const drts_pulse_t *p, int64_t step, double dt_s);
+
 /* ---- detectors: M_d(t) = sum F J (Eq. 27 with a one-step window) --------------- */
 typedef struct {
     int32_t n_det;

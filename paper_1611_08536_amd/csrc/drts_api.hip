@@ -2,6 +2,7 @@
 // detectors, the step loop (eager or hipGraph replay), readout, state
 // transfer, kernel timing, uneven batches and the autotuner.
 #include <algorithm>
+#include <limits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -1059,6 +1060,27 @@ int drts_build_matrix(const drts_medium_t *medium, const drts_device_t *dev, drt
     }
     *out = A;
     return DRTS_OK;
+}
+
+double drts_pulse_step(const drts_pulse_t *p, int64_t step, double dt_s)
+{
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    if (!p || step < 0 || !(dt_s > 0.0)) {
+        set_error(DRTS_E_INVALID, "drts_pulse_step: NULL pulse, step < 0 or dt_s <= 0");
+        return nan;
+    }
+    if (p->kind == DRTS_PULSE_IMPULSE) return step == 0 ? 1.0 : 0.0;
+    if (p->kind != DRTS_PULSE_GAUSSIAN || !(p->fwhm_s > 0.0)) {
+        set_error(DRTS_E_INVALID, "drts_pulse_step: unknown kind %d or fwhm_s <= 0", (int)p->kind);
+        return nan;
+    }
+    // the fraction of the pulse in [a, b) is (erfc(z(a)) - erfc(z(b))) / 2 with
+    // z(t) = (t - peak) / (sigma sqrt 2); a = -infinity for step 0 (erfc = 2)
+    const double sigma = p->fwhm_s / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+    const double peak = 3.0 * sigma, w = sigma * std::sqrt(2.0);
+    const double hi = std::erfc(((double)(step + 1) * dt_s - peak) / w);
+    const double lo = step == 0 ? 2.0 : std::erfc(((double)step * dt_s - peak) / w);
+    return 0.5 * (lo - hi);
 }
 
 int drts_direction_set(int32_t directions, double *unit, double *weight)

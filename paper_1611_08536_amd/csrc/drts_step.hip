@@ -1224,9 +1224,11 @@ __global__ void __launch_bounds__(kNT) spmm_detectors(const StepInst *__restrict
 // The row groups and the group-order arrays of the many-rhs step.  The fast
 // groups -- full lattice rows, kSpmmUnroll columns in one run, nearly every
 // group -- go to step_spmv_grouped, whose lanes are the members: each
-// half-wave takes a group (lane m of the half is member m), so a wave forms
-// two groups at once, and the descriptors of the wave's next two groups load
-// while the current two are formed.  Lane m loads x at column m of the run
+// half-wave takes a group (lane m of the half is member m), so a wave forms a
+// pair of groups per half-wave pass; it issues the loads of kGroupPairs pairs
+// before it forms the first (more bytes in flight per wave), and the
+// descriptors of its next pairs load while the current ones are formed.
+// Lane m loads x at column m of the run
 // into LDS, then its own entries with one load per k (the group's values are
 // column-major, so a group's k-th entries are one contiguous run) and adds
 // entry * x over k in column order: the CSR step's products in its order, so
@@ -1238,11 +1240,15 @@ __global__ void __launch_bounds__(kNT) spmm_detectors(const StepInst *__restrict
 // 4c + wave), those of the row list follow; the detector sums are left to
 // spmv_detectors.
 // ---------------------------------------------------------------------------
+constexpr int kGroupPairs = 2;   // pairs of groups a wave forms per iteration
+
+template <int NP>
 __global__ void __launch_bounds__(kNT) step_spmv_grouped(const StepInst *__restrict__ insts,
                                                           const WorkItem *__restrict__ work, int64_t n_work,
                                                           int xcd_remap, const int64_t *__restrict__ xcd_bounds)
 {
-    __shared__ float s_x[4][2][32];   // per wave and half: x at the group's columns
+    constexpr int NG = 2 * NP;        // groups a wave forms at once: NP pairs, a half-wave each
+    __shared__ float s_x[4][NG][32];  // per wave and group: x at the group's columns
     __shared__ double s_abs[kMatMax];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1262,7 +1268,6 @@ __global__ void __launch_bounds__(kNT) step_spmv_grouped(const StepInst *__restr
     const CST GroupDesc *grp = cst(I.grp);
     const CST int32_t *gfast = cst(I.grp_fast);
     const CST uint32_t *gsrc = cst(I.grp_src);
-    float *sx = s_x[wave][h];
     const int64_t nv = I.nnz + 4;   // entries of the group-order values (with the padding)
     for (int q = threadIdx.x; q < I.n_mat; q += kNT) s_abs[q] = gp(I.absorb)[q];
     __syncthreads();
@@ -1276,69 +1281,97 @@ __global__ void __launch_bounds__(kNT) step_spmv_grouped(const StepInst *__restr
         double sN = 0.0, sE = 0.0, sA = 0.0;
         float mx = 0.0f;
         if (g_b < g_e) {
-            // the wave's two groups (a lone last group: both halves take it),
-            // descriptors and source bits through the scalar cache; the next
-            // pair's load while this pair is formed
-            int64_t ia = gfast[g_b], ib = gfast[min(g_b + 1, g_e - 1)];
-            GroupDesc D0 = load_desc(grp + ia), D1 = load_desc(grp + ib);
-            uint32_t w0 = gsrc[ia >> 5], w1 = gsrc[ib >> 5];
-            for (int64_t g2 = g_b; g2 < g_e; g2 += 2) {
-                const int64_t ga = ia, gb = ib;
-                const GroupDesc A0 = D0, A1 = D1;
-                const uint32_t s0 = w0, s1 = w1;
-                if (g2 + 2 < g_e) {
-                    ia = gfast[g2 + 2];
-                    ib = gfast[min(g2 + 3, g_e - 1)];
-                    D0 = load_desc(grp + ia);
-                    D1 = load_desc(grp + ib);
-                    w0 = gsrc[ia >> 5];
-                    w1 = gsrc[ib >> 5];
+            // the wave's NG groups (past the end of its range: its last group
+            // again, formed but not stored), descriptors and source bits
+            // through the scalar cache; the next NG's load while these form
+            int64_t id[NG];
+            GroupDesc D[NG];
+            uint32_t w[NG];
+#pragma unroll
+            for (int q = 0; q < NG; ++q) {
+                id[q] = gfast[min(g_b + q, g_e - 1)];
+                D[q] = load_desc(grp + id[q]);
+                w[q] = gsrc[id[q] >> 5];
+            }
+            for (int64_t g2 = g_b; g2 < g_e; g2 += NG) {
+                int64_t ci[NG];
+                GroupDesc C[NG];
+                uint32_t cw[NG];
+#pragma unroll
+                for (int q = 0; q < NG; ++q) {
+                    ci[q] = id[q];
+                    C[q] = D[q];
+                    cw[q] = w[q];
                 }
-                // this half's group
-                const int nm = h ? A1.nm : A0.nm;
-                const int m0 = h ? A1.m0 : A0.m0, cstart = h ? A1.cstart : A0.cstart;
-                const int64_t voff = h ? A1.voff : A0.voff;
-                const bool g_src = h ? ((s1 >> (gb & 31)) & 1u) : ((s0 >> (ga & 31)) & 1u);
-                const bool mine = g2 + h < g_e && m < nm;
-                const int jm = min(m, nm - 1);
-                const int32_t r = grow[m0 + jm];
-                const int mt = gmat[m0 + jm];
-                const float xm = X[cstart + min(m, kSpmmUnroll - 1)];
-                // a buffer at the first group's values; each lane's entries at
-                // 32-bit offsets from it
-                const __amdgpu_buffer_rsrc_t rv = make_rsrc((const void *)(val + A0.voff), (uint64_t)(nv - A0.voff) * 4);
-                const uint32_t o0 = (uint32_t)(voff - A0.voff + jm) * 4, st = (uint32_t)nm * 4;
-                float vk[kSpmmUnroll];
+                if (g2 + NG < g_e) {
 #pragma unroll
-                for (int k = 0; k < kSpmmUnroll; ++k)
-                    vk[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rv, (int)(o0 + k * st), 0, kStream));
-                sx[m] = xm;
-                float acc = 0.0f;
-#pragma unroll
-                for (int k = 0; k < kSpmmUnroll; ++k) acc += vk[k] * sx[k];
-                if (mine) {
-                    float v = acc * scale;
-                    if (g_src) {
-                        const int tile = r / R;
-                        const int sb = src_tile[tile], se = src_tile[tile + 1];
-                        if (sb < se) {
-                            int e2 = lower_bound_rows<int32_t>(I.src_row, sb, se, r);
-                            double s = 0.0;
-                            bool any = false;
-                            for (; e2 < se && I.src_row[e2] == r; ++e2) {
-                                s += I.src_w[e2] * I.amp[t * I.n_src + I.src_id[e2]];
-                                any = true;
-                            }
-                            if (any) v += (float)ldexp(s, -sc.En);
-                        }
+                    for (int q = 0; q < NG; ++q) {
+                        id[q] = gfast[min(g2 + NG + q, g_e - 1)];
+                        D[q] = load_desc(grp + id[q]);
+                        w[q] = gsrc[id[q] >> 5];
                     }
-                    Y[r] = v;
-                    if (r < I.n_states) {
-                        sN += (double)v;
-                        sA += s_abs[mt] * (double)v;
-                        mx = fmaxf(mx, v);
-                    } else {
-                        sE += (double)v;
+                }
+                // every pair's loads first (x at the run, members' rows and
+                // materials, NP x 26 values), then the sums in pair order
+                float vk[NP][kSpmmUnroll];
+                float xm[NP];
+                int32_t r[NP];
+                int mt[NP], nmv[NP];
+                bool gsb[NP];
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    const GroupDesc &A0 = C[2 * p], &A1 = C[2 * p + 1];
+                    const int nm = h ? A1.nm : A0.nm;
+                    const int m0 = h ? A1.m0 : A0.m0, cstart = h ? A1.cstart : A0.cstart;
+                    const int64_t voff = h ? A1.voff : A0.voff;
+                    gsb[p] = h ? ((cw[2 * p + 1] >> (ci[2 * p + 1] & 31)) & 1u) : ((cw[2 * p] >> (ci[2 * p] & 31)) & 1u);
+                    nmv[p] = nm;
+                    const int jm = min(m, nm - 1);
+                    r[p] = grow[m0 + jm];
+                    mt[p] = gmat[m0 + jm];
+                    xm[p] = X[cstart + min(m, kSpmmUnroll - 1)];
+                    // a buffer at the pair's first group's values; each lane's
+                    // entries at 32-bit offsets from it
+                    const __amdgpu_buffer_rsrc_t rv =
+                        make_rsrc((const void *)(val + A0.voff), (uint64_t)(nv - A0.voff) * 4);
+                    const uint32_t o0 = (uint32_t)(voff - A0.voff + jm) * 4, st = (uint32_t)nm * 4;
+#pragma unroll
+                    for (int k = 0; k < kSpmmUnroll; ++k)
+                        vk[p][k] = __builtin_bit_cast(
+                            float, __builtin_amdgcn_raw_buffer_load_b32(rv, (int)(o0 + k * st), 0, kStream));
+                }
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    float *sx = s_x[wave][2 * p + h];
+                    sx[m] = xm[p];
+                    float acc = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < kSpmmUnroll; ++k) acc += vk[p][k] * sx[k];
+                    if (g2 + 2 * p + h < g_e && m < nmv[p]) {
+                        const int32_t rr = r[p];
+                        float v = acc * scale;
+                        if (gsb[p]) {
+                            const int tile = rr / R;
+                            const int sb = src_tile[tile], se = src_tile[tile + 1];
+                            if (sb < se) {
+                                int e2 = lower_bound_rows<int32_t>(I.src_row, sb, se, rr);
+                                double s = 0.0;
+                                bool any = false;
+                                for (; e2 < se && I.src_row[e2] == rr; ++e2) {
+                                    s += I.src_w[e2] * I.amp[t * I.n_src + I.src_id[e2]];
+                                    any = true;
+                                }
+                                if (any) v += (float)ldexp(s, -sc.En);
+                            }
+                        }
+                        Y[rr] = v;
+                        if (rr < I.n_states) {
+                            sN += (double)v;
+                            sA += s_abs[mt[p]] * (double)v;
+                            mx = fmaxf(mx, v);
+                        } else {
+                            sE += (double)v;
+                        }
                     }
                 }
             }
@@ -2566,8 +2599,8 @@ hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int6
         const int remap = xcd_remap & 1;
         if (variant == DRTS_SPMV_GROUPED) {
             // the fast groups, then the other groups' rows, then the detectors
-            hipLaunchKernelGGL(step_spmv_grouped, g1, dim3(kNT), 0, stream, insts_dev, work_dev, n_work, remap,
-                               xcd_bounds);
+            hipLaunchKernelGGL(step_spmv_grouped<kGroupPairs>, g1, dim3(kNT), 0, stream, insts_dev, work_dev, n_work,
+                               remap, xcd_bounds);
             const hipError_t e0 = hipGetLastError();
             if (e0 != hipSuccess) return e0;
             if (n_slow > 0) {

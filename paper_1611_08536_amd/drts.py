@@ -96,6 +96,13 @@ class SourceTableT(C.Structure):
                 ("rhs_of", RHS_FN)]
 
 
+PULSE_IMPULSE, PULSE_GAUSSIAN = 0, 1
+
+
+class PulseT(C.Structure):
+    _fields_ = [("kind", i32), ("fwhm_s", dbl)]
+
+
 class DetectorsT(C.Structure):
     _fields_ = [("n_det", i32), ("det_ptr", C.POINTER(i64)), ("state", C.POINTER(i64)),
                 ("escape", C.POINTER(C.c_uint8)), ("F", C.POINTER(dbl))]
@@ -119,6 +126,7 @@ _sig("drts_direction_set", C.c_int, [i32, P, P])
 _sig("drts_matrix_info", C.c_int, [P, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64),
                                    C.POINTER(dbl)])
 _sig("drts_matrix_row_of", i64, [P, i64, i32])
+_sig("drts_pulse_step", dbl, [C.POINTER(PulseT), i64, dbl])
 _sig("drts_matrix_groups", C.c_int, [P, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)])
 _sig("drts_matrix_export_rows", C.c_int, [P, i64, i64, P, P, P])
 _sig("drts_matrix_destroy", None, [P])
@@ -154,7 +162,7 @@ _sig("drts_serve_destroy", None, [P])
 _sig("drts_serve_set_step", C.c_int, [P, i32])
 
 EXPORTED = [
-    "drts_direction_set", "drts_build_matrix", "drts_matrix_info", "drts_matrix_groups", "drts_matrix_row_of", "drts_matrix_export_rows",
+    "drts_direction_set", "drts_pulse_step", "drts_build_matrix", "drts_matrix_info", "drts_matrix_groups", "drts_matrix_row_of", "drts_matrix_export_rows",
     "drts_matrix_destroy", "drts_solver_create", "drts_solver_get_options", "drts_solver_set_options",
     "drts_step", "drts_step_noalloc", "drts_run", "drts_solver_time", "drts_detector_readout", "drts_detector_window", "drts_state_read",
     "drts_state_write", "drts_solver_profile", "drts_solver_profile_stats", "drts_solver_destroy",
@@ -169,6 +177,15 @@ class DrtsError(RuntimeError):
         msg = _lib.drts_last_error().decode(errors="replace")
         super().__init__("%s failed (%d): %s" % (where, rc, msg))
         self.rc = rc
+
+
+def pulse_step(kind: int, fwhm_s: float, step: int, dt_s: float) -> float:
+    """Photons a pulse of unit total emits during step `step` (the library's
+    drts_pulse_step: its time profile integrated over the step)."""
+    v = _lib.drts_pulse_step(C.byref(PulseT(kind, fwhm_s)), step, dt_s)
+    if v != v:
+        raise DrtsError(-1, "drts_pulse_step")   # DRTS_E_INVALID
+    return v
 
 
 def _check(rc, where):

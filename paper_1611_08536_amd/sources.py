@@ -2,28 +2,30 @@
 
 The number of photons a source emits during step t is the integral of its
 time profile over [t dt, (t+1) dt): the step-integrated source the paper asks
-for when the source varies faster than a step.
+for when the source varies faster than a step.  The profiles are the
+library's (drts_pulse_step in include/drts.h), so C callers and this binding
+use one definition.
 """
 from __future__ import annotations
 
-import math
+
+def _drts():
+    from . import drts
+    return drts
 
 
 def impulse_step(t: int) -> float:
     """All photons at the first step."""
-    return 1.0 if t == 0 else 0.0
+    d = _drts()
+    return d.pulse_step(d.PULSE_IMPULSE, 0.0, t, 1.0)
 
 
 def gaussian_step(fwhm_s: float, dt_s: float, t: int) -> float:
     """Normalised Gaussian pulse (FWHM fwhm_s, peak at 3 sigma) integrated over
     step t; the first step also takes everything before t = 0, so the steps sum
-    to one.  Written with erfc to avoid cancellation in the tails."""
-    sigma = fwhm_s / (2.0 * math.sqrt(2.0 * math.log(2.0)))
-    peak = 3.0 * sigma
-    scale = sigma * math.sqrt(2.0)
-    upper = math.erfc(((t + 1) * dt_s - peak) / scale)
-    lower = 2.0 if t == 0 else math.erfc((t * dt_s - peak) / scale)
-    return 0.5 * (lower - upper)
+    to one."""
+    d = _drts()
+    return d.pulse_step(d.PULSE_GAUSSIAN, fwhm_s, t, dt_s)
 
 
 def amplitude(source, t: int, dt_s: float) -> float:

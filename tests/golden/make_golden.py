@@ -11,6 +11,9 @@ Outputs, per workload, under tests/golden/:
   <name>_run.npz    the FP64 series of the full run (totals, detectors, with
                     exponents) and sampled entries of the final state.
 
+  c2_same.npz       the 2000-step C2 run under FP64 arithmetic on the
+                    FP32-rounded matrix (the same-matrix oracle): series and
+                    the final state at the entries c2_run.npz samples;
   c3_run.npz        the 96^3 slab with 64 right-hand sides: right-hand
                     sides 0, 31 and 63 over all 1000 steps (series, sampled
                     final state, its L1 norm), each also under FP64
@@ -23,7 +26,7 @@ Outputs, per workload, under tests/golden/:
                     reflection) over their full step counts (series), also on
                     the same-matrix oracle.
 
-Usage: python tests/golden/make_golden.py c2|c1|c3|c4|c5 [--steps N]
+Usage: python tests/golden/make_golden.py c2|c1|c2same|c3|c4|c5 [--steps N]
 """
 from __future__ import annotations
 
@@ -105,6 +108,25 @@ def make(name, wl, steps, out_dir):
                         det=r["det"], det_exp=r["det_exp"], x_idx=idx, x_val=r["x"][idx], x_exp=r["x_exp"],
                         x_l1=np.abs(r["x"]).sum())
     print("%s: run of %d steps done %.1f s" % (name, steps, time.time() - t0), flush=True)
+
+
+def make_c2_same(out_dir):
+    """The same-matrix oracle of the C2 run: the FP32-rounded values under
+    FP64 arithmetic, sampled at the entries c2_run.npz holds (both files
+    come from the oracle alone)."""
+    t0 = time.time()
+    wl = W.c2()
+    g = np.load(os.path.join(out_dir, "c2_run.npz"))
+    steps = int(g["steps"])
+    A = oracle.Matrix(wl.medium)
+    vals = A.round_f32(wl.rounding)
+    print("c2same: assembled %d rows, %d nnz in %.1f s" % (A.n_rows, A.nnz, time.time() - t0), flush=True)
+    r = oracle.run_workload(A, wl, n_steps=steps, vals32=vals)
+    idx = g["x_idx"]
+    out = {"steps": steps, "x_idx": idx, "x_val": r["x"][idx], "x_exp": r["x_exp"], "x_l1": np.abs(r["x"]).sum()}
+    _series(r, "", out)
+    np.savez_compressed(os.path.join(out_dir, "c2_same.npz"), **out)
+    print("c2same: run of %d steps done %.1f s" % (steps, time.time() - t0), flush=True)
 
 
 def _series(r, prefix, out):
@@ -190,10 +212,12 @@ def make_c5(out_dir):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["c2", "c1", "c3", "c4", "c5"])
+    ap.add_argument("which", choices=["c2", "c1", "c2same", "c3", "c4", "c5"])
     ap.add_argument("--steps", type=int, default=None)
     a = ap.parse_args()
-    if a.which == "c3":
+    if a.which == "c2same":
+        make_c2_same(HERE)
+    elif a.which == "c3":
         make_c3(HERE, a.steps)
     elif a.which == "c4":
         make_c4(HERE, a.steps)

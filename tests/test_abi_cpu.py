@@ -76,3 +76,28 @@ def test_one_hip_runtime_is_mapped(lib):
     """torch's HIP runtime and the library's are the same mapped file."""
     from paper_1611_08536_amd import drts
     assert len(drts._hip_runtimes()) == 1
+
+
+def test_pulse_steps_integrate_the_profile(lib):
+    """drts_pulse_step (host function, no GPU): the Gaussian's steps sum to one
+    and each equals the density integrated over its step (numerical
+    quadrature); the impulse is one photon in step 0; bad arguments give NaN."""
+    import math
+    from scipy.integrate import quad
+    from paper_1611_08536_amd import drts
+    for fwhm, dt in ((100e-15, 467e-15), (1e-12, 0.3e-12), (50e-15, 10e-15)):
+        sig = fwhm / (2 * math.sqrt(2 * math.log(2)))
+        dens = lambda t: math.exp(-0.5 * ((t - 3 * sig) / sig) ** 2) / (sig * math.sqrt(2 * math.pi))
+        steps = [drts.pulse_step(drts.PULSE_GAUSSIAN, fwhm, t, dt) for t in range(int(12 * sig / dt) + 3)]
+        assert sum(steps) == pytest.approx(1.0, abs=1e-14)
+        for t in range(1, min(len(steps), 8)):
+            assert steps[t] == pytest.approx(quad(dens, t * dt, (t + 1) * dt, epsabs=1e-15, epsrel=1e-13)[0],
+                                             abs=1e-13)
+        assert steps[0] == pytest.approx(quad(dens, -50 * sig, dt, epsabs=1e-15, epsrel=1e-13, limit=200)[0],
+                                         abs=1e-13)
+    assert [drts.pulse_step(drts.PULSE_IMPULSE, 0.0, t, 1e-15) for t in range(3)] == [1.0, 0.0, 0.0]
+    f = drts._lib.drts_pulse_step
+    for kind, fwhm, step, dt in ((7, 1e-13, 0, 1e-15), (drts.PULSE_GAUSSIAN, 0.0, 0, 1e-15),
+                                 (drts.PULSE_GAUSSIAN, 1e-13, -1, 1e-15), (drts.PULSE_IMPULSE, 0.0, 0, 0.0)):
+        assert math.isnan(f(ctypes.byref(drts.PulseT(kind, fwhm)), step, dt))
+    assert math.isnan(f(None, 0, 1e-15))
