@@ -89,6 +89,28 @@ def traffic_from_counters(fetch_csv, write_csv):
     return out
 
 
+def traffic_by_kernel(fetch_csv, write_csv):
+    """Per-kernel HBM GB per dispatch (mean over the dispatches of each kernel
+    name) from a FETCH_SIZE and a WRITE_SIZE pass, each scaled by the
+    calibration kernel of its pass; kernels of fewer than 1 MB are left out."""
+    out, factors = {}, {}
+    for name, path in (("fetch", fetch_csv), ("write", write_csv)):
+        m = _counter_means(path, "FETCH_SIZE" if name == "fetch" else "WRITE_SIZE")
+        calib = [v for k, v in m.items() if CALIB_KERNEL in k]
+        if not calib:
+            raise SystemExit("counter file %s lacks the calibration kernel" % path)
+        factors[name] = CALIB_BYTES / (max(calib) * 1024.0)
+        for k, v in m.items():
+            if CALIB_KERNEL in k:
+                continue
+            short = k.replace("drts::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+            out.setdefault(short, {})[name + "_GB"] = round(v * 1024.0 * factors[name] / 1e9, 4)
+    out = {k: v for k, v in out.items() if v.get("fetch_GB", 0) + v.get("write_GB", 0) >= 1e-3}
+    out["_fetch_factor"] = round(factors["fetch"], 4)
+    out["_write_factor"] = round(factors["write"], 4)
+    return out
+
+
 def load_traffic():
     """Traffic of the committed counter summary, or None when it is missing or
     was taken on other kernel sources."""
@@ -501,7 +523,12 @@ def main():
                     help="after the run, launch an elementwise kernel that reads and writes 1 GiB (counter scale)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
                     help="print the traffic JSON line from two rocprofv3 --pmc counter files and exit")
+    ap.add_argument("--traffic-by-kernel", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
+                    help="print every kernel's HBM GB per dispatch from two rocprofv3 --pmc counter files and exit")
     args = ap.parse_args()
+    if args.traffic_by_kernel:
+        print(json.dumps(traffic_by_kernel(*args.traffic_by_kernel), indent=1))
+        return
     if args.traffic_from:
         print(json.dumps(traffic_from_counters(*args.traffic_from)))
         return

@@ -85,3 +85,22 @@ def test_grouped_bytes_against_the_csr_count(bench):
     # moving 10 rows of 40 entries from the groups to the row list
     slow = bench.grouped_bytes(R + 10, n_states, n_vox + 100, n_vox + 100, 10, 400)
     assert slow - fast == 4 * 10 + 8 * 400 + 9 * 10
+
+
+def test_traffic_by_kernel_names_and_scales(bench, tmp_path):
+    """Every kernel of the passes, by its short name, scaled by its pass's
+    calibration kernel; the calibration kernel itself is not listed."""
+    for counter, fn, calib in (("FETCH_SIZE", "f.csv", 0.5), ("WRITE_SIZE", "w.csv", 1.0)):
+        with open(tmp_path / fn, "w", newline="") as f:
+            w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+            w.writeheader()
+            for v in (1000000, 3000000):
+                w.writerow({"Kernel_Name": "void drts::(anonymous namespace)::step_struct_dm<2>(drts::StructArgs)",
+                            "Counter_Name": counter, "Counter_Value": str(v)})
+            w.writerow({"Kernel_Name": bench.CALIB_KERNEL + "<float>(x)", "Counter_Name": counter,
+                        "Counter_Value": str(bench.CALIB_BYTES / 1024 * calib)})
+    out = bench.traffic_by_kernel(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"))
+    assert out["_fetch_factor"] == 2.0 and out["_write_factor"] == 1.0
+    k = out["step_struct_dm<2>"]
+    assert k["fetch_GB"] == round(2e6 * 1024 * 2 / 1e9, 4) and k["write_GB"] == round(2e6 * 1024 / 1e9, 4)
+    assert set(out) == {"step_struct_dm<2>", "_fetch_factor", "_write_factor"}
