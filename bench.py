@@ -32,7 +32,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_spmv_grouped_c2_traffic.txt"
 SPMV_KERNEL = "step_spmv_grouped"
 # the kernels of one headline step launch (the finalize aside): the fast
 # groups, the row list of the other groups, the detector sums
-STEP_KERNELS = ("step_spmv_grouped", "step_spmv_rowlist", "spmv_detectors")
+STEP_KERNELS = ("step_spmv_grouped", "step_spmv_rowlist", "step_spmv_vox2", "spmv_detectors")
 CALIB_KERNEL = "vectorized_elementwise_kernel"
 CALIB_BYTES = 2 ** 30          # the calibration kernel reads and writes 1 GiB
 GRAPH_STEPS = 50               # steps per hipGraph replay in the timed run
@@ -131,16 +131,19 @@ def spmv_bytes(nnz, n_rows, n_states, val_bytes=4):
     return val_bytes * nnz + 4 * nnz + 4 * (n_rows + 1) + val_bytes * n_states + val_bytes * n_rows
 
 
-def grouped_bytes(n_rows, n_states, n_groups, n_fast, n_slow, slow_nnz):
-    """Bytes the step by row groups must move.  Members of fast groups
-    (26 entries a row): their values in group order (4 per entry), row id (4)
-    and material (1), per fast group its descriptor (32), list entry (4) and
-    source bit.  Rows taken one by one: their CSR entries (8 per entry), row
-    pointer (4), material (1) and list entry (4).  x once, y once."""
-    fast_rows = n_rows - n_slow
-    fast = 4 * 26 * fast_rows + 5 * fast_rows + 36 * n_fast + (n_groups + 7) // 8
-    slow = 8 * slow_nnz + 9 * n_slow
-    return fast + slow + 4 * n_states + 4 * n_rows
+def grouped_bytes(n_rows, n_states, g):
+    """Bytes the step by row groups must move (g: the matrix's groups info).
+    Members of fast groups (26 entries a row): their values in group order
+    (4 per entry), row id (4) and material (1), per fast group its
+    descriptor (32), list entry (4) and source bit.  Two-voxel rows: their
+    52 values (4 each) and their info (16).  Listed rows: their CSR entries
+    (8 per entry), row pointer (4), material (1) and list entry (4).  x once,
+    y once."""
+    fast_rows = n_rows - g["n_vox2_rows"] - g["n_list_rows"]
+    fast = 4 * 26 * fast_rows + 5 * fast_rows + 36 * g["n_fast"] + (g["n_groups"] + 7) // 8
+    vox2 = (4 * 52 + 16) * g["n_vox2_rows"]
+    listed = 8 * g["n_list_entries"] + 9 * g["n_list_rows"]
+    return fast + vox2 + listed + 4 * n_states + 4 * n_rows
 
 
 def cpu_baseline(n=128, steps=50, steps_1=3):
@@ -609,7 +612,7 @@ def main():
 
     nbytes = spmv_bytes(A.nnz, A.n_rows, A.n_states)
     achieved = nbytes / (avg_kernel_ms * 1e-3) / 1e9
-    fbytes = None if not groups or groups[0] == 0 else grouped_bytes(A.n_rows, A.n_states, *groups)
+    fbytes = None if not groups or groups["n_groups"] == 0 else grouped_bytes(A.n_rows, A.n_states, groups)
     traffic = load_traffic()
     if args.copy_calibration:
         a = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device="cuda")
@@ -647,13 +650,10 @@ def main():
                      "format_frac": None if fbytes is None else
                      round(fbytes / (avg_kernel_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
                      "format_bytes_basis": "what the step by row groups must move: fast groups' values in group "
-                                           "order, members' rows and materials, descriptors; the other rows' CSR "
-                                           "entries; x and y once",
+                                           "order, members' rows and materials, descriptors; two-voxel rows' "
+                                           "values and info; the listed rows' CSR entries; x and y once",
                      "traffic_unit": "GB per launch"},
-        "row_groups": None if groups is None else {"groups": groups[0], "fast_groups": groups[1],
-                                                    "rows_taken_one_by_one": groups[2],
-                                                    "their_entries": groups[3],
-                                                    "device_bytes": group_bytes},
+        "row_groups": None if groups is None else dict(groups, device_bytes=group_bytes),
         "tiled_step": {"kernel": "step_spmv<float, int, 256, 2> (values straight into LDS, 4 tiles per chunk)",
                        "kernel_ms": round(tiled_kernel_ms, 4),
                        "frac": round(nbytes / (tiled_kernel_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},

@@ -269,14 +269,26 @@ int drts_build_matrix(const drts_medium_t *medium, const drts_device_t *dev, drt
 int drts_matrix_info(const drts_matrix_t *A, int64_t *n_states, int64_t *n_escape, int64_t *nnz,
                      int64_t *bytes, double *dt_s);
 
-/* The row groups of an assembled matrix (rows whose column lists are equal;
- * built when a solo solver first runs a grouped step): groups, fast groups
- * (full lattice rows whose columns are one run), rows of the other groups
- * (the step takes them one by one from the CSR) and their entries.  Any
- * output pointer may be NULL.  Returns DRTS_E_STATE while the groups are not
- * built, and sets all four to 0 when the rows do not group. */
-int drts_matrix_groups(const drts_matrix_t *A, int64_t *n_groups, int64_t *n_fast, int64_t *n_slow_rows,
-                       int64_t *n_slow_entries);
+/* The row groups of an assembled matrix (rows whose column lists are equal),
+ * built when a solo solver first runs a grouped step, and how the single-rhs
+ * grouped step takes the rows:
+ *   n_groups        groups (of at most 26 rows);
+ *   n_fast          fast groups: full lattice rows, 26 columns that are one
+ *                   voxel's states (one run), formed by row groups;
+ *   n_vox2_rows     two-voxel rows (52 columns in two runs of 26, e.g. rows
+ *                   that take a transmitted and a reflected part at an
+ *                   interface), taken one by one from a compact copy of
+ *                   their values, x read as the two runs;
+ *   n_list_rows     all other rows (empty rows, other column patterns),
+ *                   taken one by one from the CSR;
+ *   n_list_entries  their entries. */
+typedef struct {
+    int64_t n_groups, n_fast, n_vox2_rows, n_list_rows, n_list_entries;
+} drts_groups_info_t;
+
+/* Fills *info.  DRTS_E_INVALID for a NULL argument; DRTS_E_STATE while the
+ * groups are not built; all counts 0 when the rows do not group. */
+int drts_matrix_groups(const drts_matrix_t *A, drts_groups_info_t *info);
 
 /* Row index of state s (escape = 0 -> s itself; escape = 1 -> its escape row,
  * or -1 when the state does not leave the grid or faces reflect). */
@@ -331,10 +343,13 @@ typedef struct {
  * loaded straight into LDS (DRTS_SPMV_LDS, FP32 values) -- or the step by
  * row groups (DRTS_SPMV_GROUPED, FP32 values, the default for them): rows
  * whose column lists are equal form groups (as for DRTS_SPMM_GROUPED); a
- * half-wave forms a group, reading the group's columns and x once and its
- * values from a group-order copy the matrix keeps once a solo solver asks
- * for it (batch members take DRTS_SPMV_LDS; a matrix whose rows do not group
- * takes DRTS_SPMV_LDS as well).  All give the same state bit for bit. */
+ * half-wave forms a fast group (26 columns in one run), reading x at the run
+ * once and the values from a group-order copy the matrix keeps once a solo
+ * solver asks for it; two-voxel rows (two runs) take a thread each over a
+ * compact copy of their values, every other row a thread over its CSR entries
+ * (drts_matrix_groups counts them).  Batch members take DRTS_SPMV_LDS, and so
+ * does a matrix whose rows do not group.  All give the same state bit for
+ * bit. */
 #define DRTS_SPMV_ROW 0
 #define DRTS_SPMV_LDS 1
 #define DRTS_SPMV_GROUPED 2

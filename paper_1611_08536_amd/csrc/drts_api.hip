@@ -74,7 +74,8 @@ void Buffer::reset()
 
 int64_t Matrix::bytes() const
 {
-    const Buffer *b[] = {&row_ptr, &col, &val, &grp_desc, &grp_row, &grp_mat, &grp_val, &grp_fast, &slow_rows};
+    const Buffer *b[] = {&row_ptr, &col,      &val,       &grp_desc,  &grp_row,  &grp_mat,
+                         &grp_val, &grp_fast, &slow_rows, &vox2_info, &vox2_val};
     int64_t n = 0;
     for (const Buffer *x : b) n += (int64_t)x->bytes;
     return n;
@@ -613,7 +614,9 @@ int prepare(drts_solver *S)
     if (S->grouped) {
         // partials per work item and wave (single rhs: then per row-list item
         // and wave); detector entries by detector; the groups holding source rows
-        n_part = 4 * S->n_chunks + (spmm_of(S) ? 0 : 4 * ((A.n_slow + kRowListItem - 1) / kRowListItem));
+        n_part = 4 * S->n_chunks;
+        if (!spmm_of(S))
+            n_part += 4 * ((A.n_slow + kRowListItem - 1) / kRowListItem) + 4 * ((A.n_vox2 + kVox2Item - 1) / kVox2Item);
         std::vector<int64_t> ptr, row;
         if ((rc = upload_dets_by_detector(S, &ptr, &row))) return rc;
         std::vector<int64_t> srows;
@@ -695,6 +698,10 @@ int prepare(drts_solver *S)
         I.n_fast = A.n_fast;
         I.n_slow = A.n_slow;
         I.slow_part = 4 * S->n_chunks;
+        I.vox2_info = A.vox2_info.as<int32_t>();
+        I.vox2_val = A.vox2_val.as<float>();
+        I.n_vox2 = A.n_vox2;
+        I.vox2_part = I.slow_part + 4 * ((A.n_slow + kRowListItem - 1) / kRowListItem);
         I.det_direct = 1;
         I.ddet_ptr = S->ddet_ptr.as<int64_t>();
         I.ddet_row = S->ddet_row.as<int64_t>();
@@ -878,7 +885,8 @@ int launch_one(drts_solver *S, hipStream_t stream, const StepInst *inst = nullpt
     e = launch_step(insts, S->work_dev.as<WorkItem>(), S->n_chunks, 1, S->n_rhs,
                                A.model.value_type == DRTS_F64, A.rp64 ? 1 : 0, spmm ? (S->grouped ? 2 : 1) : 0, S->grid,
                                (S->opt.xcd_remap ? 1 : 0) | ((variant & 15) << 1), S->xcd_bounds.as<int64_t>(),
-                               S->opt.rows_per_tile, S->n_det, queue, stream, S->grouped ? A.n_slow : 0);
+                               S->opt.rows_per_tile, S->n_det, queue, stream, S->grouped ? A.n_slow : 0,
+                               S->grouped && !spmm ? A.n_vox2 : 0);
     }
     if (e != hipSuccess) return set_error(DRTS_E_HIP, "step launch failed: %s", hipGetErrorString(e));
     if (e1) DRTS_HIP(hipEventRecord(e1, stream));
@@ -1111,15 +1119,16 @@ int drts_matrix_info(const drts_matrix_t *A, int64_t *n_states, int64_t *n_escap
     return DRTS_OK;
 }
 
-int drts_matrix_groups(const drts_matrix_t *A, int64_t *n_groups, int64_t *n_fast, int64_t *n_slow_rows,
-                       int64_t *n_slow_entries)
+int drts_matrix_groups(const drts_matrix_t *A, drts_groups_info_t *info)
 {
-    if (!A) return set_error(DRTS_E_INVALID, "matrix is NULL");
+    if (!A || !info) return set_error(DRTS_E_INVALID, "NULL argument");
     if (A->m.n_groups < 0) return set_error(DRTS_E_STATE, "the row groups are not built (no grouped step has run)");
-    if (n_groups) *n_groups = A->m.n_groups;
-    if (n_fast) *n_fast = A->m.n_groups > 0 ? A->m.n_fast : 0;
-    if (n_slow_rows) *n_slow_rows = A->m.n_groups > 0 ? A->m.n_slow : 0;
-    if (n_slow_entries) *n_slow_entries = A->m.n_groups > 0 ? A->m.n_slow_nnz : 0;
+    const bool g = A->m.n_groups > 0;
+    info->n_groups = A->m.n_groups;
+    info->n_fast = g ? A->m.n_fast : 0;
+    info->n_vox2_rows = g ? A->m.n_vox2 : 0;
+    info->n_list_rows = g ? A->m.n_slow : 0;
+    info->n_list_entries = g ? A->m.n_slow_nnz : 0;
     return DRTS_OK;
 }
 
@@ -1212,9 +1221,12 @@ int drts_solver_create(const drts_matrix_t *A, int32_t n_rhs, const drts_detecto
                              [](const DetEntry &a, const DetEntry &b) { return a.row < b.row; });
         }
         const size_t st = (size_t)M.n_rows * n_rhs * (M.value_type == DRTS_F64 ? 8 : 4);
+        // kStatePad entries past the state: aligned 16-byte loads of a run of
+        // x that ends near the last row stay in the buffer
+        const size_t st_alloc = st + (size_t)kStatePad * n_rhs * (M.value_type == DRTS_F64 ? 8 : 4);
         Device &dv = S->dev;
-        if (!rc) rc = S->buf0.allocate(&dv, st);
-        if (!rc) rc = S->buf1.allocate(&dv, st);
+        if (!rc) rc = S->buf0.allocate(&dv, st_alloc);
+        if (!rc) rc = S->buf1.allocate(&dv, st_alloc);
         if (!rc) rc = S->ctl_t.allocate(&dv, n_rhs * sizeof(int64_t));
         if (!rc) rc = S->ctl_E.allocate(&dv, n_rhs * sizeof(int32_t));
         if (!rc) rc = S->ctl_M.allocate(&dv, n_rhs * sizeof(double));
@@ -1249,7 +1261,8 @@ int drts_solver_create(const drts_matrix_t *A, int32_t n_rhs, const drts_detecto
         }
         if (!rc) {
             hipStream_t s = dv.stream;
-            if (hipMemsetAsync(S->buf0.ptr, 0, st, s) != hipSuccess || hipMemsetAsync(S->buf1.ptr, 0, st, s) != hipSuccess ||
+            if (hipMemsetAsync(S->buf0.ptr, 0, st_alloc, s) != hipSuccess ||
+                hipMemsetAsync(S->buf1.ptr, 0, st_alloc, s) != hipSuccess ||
                 hipMemsetAsync(S->ctl_t.ptr, 0, n_rhs * sizeof(int64_t), s) != hipSuccess ||
                 hipMemsetAsync(S->ctl_E.ptr, 0, n_rhs * sizeof(int32_t), s) != hipSuccess ||
                 hipMemsetAsync(S->ctl_M.ptr, 0, n_rhs * sizeof(double), s) != hipSuccess ||

@@ -134,19 +134,50 @@ __global__ void __launch_bounds__(256) group_flag_bits(const GroupDesc *desc, co
     bits[w] = word;
 }
 
-// fast groups (a full lattice row: kSpmmUnroll columns that are one run),
-// per member whether its group is not one, and the entries of those members
-// (an integer count: the order of the additions does not matter)
-__global__ void __launch_bounds__(256) group_kinds(const GroupDesc *desc, int64_t n_groups, uint8_t *fast,
-                                                   uint8_t *member_slow, unsigned long long *slow_entries)
+// Per group its kind -- fast (a full lattice row: kSpmmUnroll columns that
+// are one run), two-voxel (kVox2Len columns in two runs of kVox2Run: a
+// voxel's states and another voxel's) or other -- and per member whether it
+// is a two-voxel row or another group's row; the entries of the other groups'
+// members (an integer count: the order of the additions does not matter).
+__global__ void __launch_bounds__(256) group_kinds(const GroupDesc *desc, const int32_t *col, int64_t n_groups,
+                                                   uint8_t *fast, uint8_t *member_vox2, uint8_t *member_slow,
+                                                   unsigned long long *slow_entries)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n_groups) return;
     const GroupDesc D = desc[g];
     const bool f = D.n == kSpmmUnrollHost && D.cstart >= 0;
+    bool v2 = false;
+    if (!f && D.n == kVox2Len) {
+        const int32_t a = col[D.coff], b = col[D.coff + kVox2Run];
+        v2 = true;
+        for (int k = 1; k < kVox2Run && v2; ++k)
+            v2 = col[D.coff + k] == a + k && col[D.coff + kVox2Run + k] == b + k;
+    }
     fast[g] = f ? 1 : 0;
-    for (int j = 0; j < D.nm; ++j) member_slow[D.m0 + j] = f ? 0 : 1;
-    if (!f) atomicAdd(slow_entries, (unsigned long long)D.n * (unsigned long long)D.nm);
+    for (int j = 0; j < D.nm; ++j) {
+        member_vox2[D.m0 + j] = v2 ? 1 : 0;
+        member_slow[D.m0 + j] = (f || v2) ? 0 : 1;
+    }
+    if (!f && !v2) atomicAdd(slow_entries, (unsigned long long)D.n * (unsigned long long)D.nm);
+}
+
+// Two-voxel row i of the list (member position pos[i]): its info (row, the
+// two runs' first columns, material) and its values, copied in list order.
+template <typename IT>
+__global__ void __launch_bounds__(256) vox2_build(const int32_t *pos, int64_t n, const int32_t *grp_row,
+                                                  const uint8_t *grp_mat, const IT *rp, const int32_t *col,
+                                                  const float *val, int32_t *info, float *v2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t r = grp_row[pos[i]];
+    const int64_t lo = (int64_t)rp[r];
+    info[4 * i] = r;
+    info[4 * i + 1] = col[lo];
+    info[4 * i + 2] = col[lo + kVox2Run];
+    info[4 * i + 3] = grp_mat[pos[i]];
+    for (int k = 0; k < kVox2Len; ++k) v2[i * kVox2Len + k] = val[lo + k];
 }
 
 __global__ void __launch_bounds__(256) group_scatter(const int32_t *flag, const int32_t *pos, int64_t n,
@@ -263,33 +294,52 @@ int build_groups(Matrix &A)
     DRTS_HIP(hipGetLastError());
     // the single-rhs step takes the fast groups by row groups and the rows of
     // the others one by one: the list of fast groups and the list of those rows
-    Buffer fast, mslow, iota, cnt;
+    Buffer fast, mvox2, mslow, v2pos, cnt;
     if ((rc = fast.allocate(&dev, G))) return rc;
+    if ((rc = mvox2.allocate(&dev, R))) return rc;
     if ((rc = mslow.allocate(&dev, R))) return rc;
-    if ((rc = cnt.allocate(&dev, 3 * sizeof(int64_t)))) return rc;
-    DRTS_HIP(hipMemsetAsync(cnt.ptr, 0, 3 * sizeof(int64_t), dev.stream));
-    hipLaunchKernelGGL(group_kinds, dim3(gblocks), dim3(256), 0, dev.stream, A.grp_desc.as<GroupDesc>(), G,
-                       fast.as<uint8_t>(), mslow.as<uint8_t>(), (unsigned long long *)(cnt.as<int64_t>() + 2));
+    if ((rc = cnt.allocate(&dev, 4 * sizeof(int64_t)))) return rc;
+    DRTS_HIP(hipMemsetAsync(cnt.ptr, 0, 4 * sizeof(int64_t), dev.stream));
+    hipLaunchKernelGGL(group_kinds, dim3(gblocks), dim3(256), 0, dev.stream, A.grp_desc.as<GroupDesc>(), col, G,
+                       fast.as<uint8_t>(), mvox2.as<uint8_t>(), mslow.as<uint8_t>(),
+                       (unsigned long long *)(cnt.as<int64_t>() + 2));
     DRTS_HIP(hipGetLastError());
     if ((rc = A.grp_fast.allocate(&dev, G * sizeof(int32_t)))) return rc;
     if ((rc = A.slow_rows.allocate(&dev, R * sizeof(int32_t)))) return rc;
+    if ((rc = v2pos.allocate(&dev, R * sizeof(int32_t)))) return rc;
     hipcub::CountingInputIterator<int32_t> gidx(0);
-    size_t tb4 = 0, tb5 = 0;
+    size_t tb4 = 0, tb5 = 0, tb6 = 0;
     DRTS_HIP(hipcub::DeviceSelect::Flagged(nullptr, tb4, gidx, fast.as<uint8_t>(), A.grp_fast.as<int32_t>(),
                                            cnt.as<int64_t>(), (int)G, dev.stream));
     DRTS_HIP(hipcub::DeviceSelect::Flagged(nullptr, tb5, A.grp_row.as<int32_t>(), mslow.as<uint8_t>(),
                                            A.slow_rows.as<int32_t>(), cnt.as<int64_t>() + 1, (int)R, dev.stream));
-    if ((rc = tmp.allocate(&dev, std::max<size_t>(std::max(tb4, tb5), 16)))) return rc;
+    DRTS_HIP(hipcub::DeviceSelect::Flagged(nullptr, tb6, gidx, mvox2.as<uint8_t>(), v2pos.as<int32_t>(),
+                                           cnt.as<int64_t>() + 3, (int)R, dev.stream));
+    if ((rc = tmp.allocate(&dev, std::max<size_t>(std::max(std::max(tb4, tb5), tb6), 16)))) return rc;
     DRTS_HIP(hipcub::DeviceSelect::Flagged(tmp.ptr, tb4, gidx, fast.as<uint8_t>(), A.grp_fast.as<int32_t>(),
                                            cnt.as<int64_t>(), (int)G, dev.stream));
     DRTS_HIP(hipcub::DeviceSelect::Flagged(tmp.ptr, tb5, A.grp_row.as<int32_t>(), mslow.as<uint8_t>(),
                                            A.slow_rows.as<int32_t>(), cnt.as<int64_t>() + 1, (int)R, dev.stream));
-    int64_t counts[3] = {0, 0, 0};
+    DRTS_HIP(hipcub::DeviceSelect::Flagged(tmp.ptr, tb6, gidx, mvox2.as<uint8_t>(), v2pos.as<int32_t>(),
+                                           cnt.as<int64_t>() + 3, (int)R, dev.stream));
+    int64_t counts[4] = {0, 0, 0, 0};
     DRTS_HIP(hipMemcpyAsync(counts, cnt.ptr, sizeof counts, hipMemcpyDeviceToHost, dev.stream));
     DRTS_HIP(hipStreamSynchronize(dev.stream));
     A.n_fast = counts[0];
     A.n_slow = counts[1];
     A.n_slow_nnz = counts[2];
+    A.n_vox2 = counts[3];
+    // the two-voxel rows' info and values in list order
+    if ((rc = A.vox2_info.allocate(&dev, (size_t)std::max<int64_t>(A.n_vox2, 1) * 4 * sizeof(int32_t)))) return rc;
+    if ((rc = A.vox2_val.allocate(&dev, (size_t)std::max<int64_t>(A.n_vox2, 1) * kVox2Len * sizeof(float))))
+        return rc;
+    if (A.n_vox2 > 0) {
+        hipLaunchKernelGGL(vox2_build<IT>, dim3((unsigned)((A.n_vox2 + 255) / 256)), dim3(256), 0, dev.stream,
+                           v2pos.as<int32_t>(), A.n_vox2, A.grp_row.as<int32_t>(), A.grp_mat.as<uint8_t>(), rp, col,
+                           A.val.as<float>(), A.vox2_info.as<int32_t>(), A.vox2_val.as<float>());
+        DRTS_HIP(hipGetLastError());
+        DRTS_HIP(hipStreamSynchronize(dev.stream));
+    }
     A.n_groups = G;
     return DRTS_OK;
 }
@@ -308,7 +358,8 @@ int row_groups(const Matrix &Ac)
     }
     const int rc = A.rp64 ? build_groups<int64_t>(A) : build_groups<int32_t>(A);
     if (rc) {
-        Buffer *b[] = {&A.grp_desc, &A.grp_row, &A.grp_mat, &A.grp_val, &A.grp_fast, &A.slow_rows};
+        Buffer *b[] = {&A.grp_desc, &A.grp_row, &A.grp_mat, &A.grp_val, &A.grp_fast, &A.slow_rows, &A.vox2_info,
+                       &A.vox2_val};
         for (Buffer *x : b) x->reset();
         A.n_groups = -1;
     }

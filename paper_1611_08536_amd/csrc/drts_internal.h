@@ -123,9 +123,10 @@ struct Matrix {
     Buffer grp_desc, grp_row, grp_mat, grp_val;
     int64_t n_groups = -1;
     // for the single-rhs step: the fast groups (kSpmmUnroll columns in one
-    // run, by index) and the rows of all other groups
-    Buffer grp_fast, slow_rows;
-    int64_t n_fast = 0, n_slow = 0, n_slow_nnz = 0;
+    // run, by index), the two-voxel rows (two runs: info and values, see
+    // StepInst) and the rows of all other groups
+    Buffer grp_fast, slow_rows, vox2_info, vox2_val;
+    int64_t n_fast = 0, n_slow = 0, n_slow_nnz = 0, n_vox2 = 0;
     int64_t bytes() const;         // the CSR arrays (and the row groups, once built)
     int64_t table_bytes() const;   // everything else on the device (tables of the model)
 };

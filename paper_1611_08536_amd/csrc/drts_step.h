@@ -74,6 +74,13 @@ struct StepInst {
     const int32_t *grp_fast;
     const int32_t *slow_rows;
     int64_t n_fast, n_slow, slow_part;
+    // the two-voxel rows (columns two runs of a voxel's states each, kVox2Len
+    // entries), taken apart from the row list: per row {row, first column of
+    // the first run, first column of the second run, material} and its values
+    // (kVox2Len per row, list order); their partials start at index vox2_part
+    const int32_t *vox2_info;
+    const float *vox2_val;
+    int64_t n_vox2, vox2_part;
     // det_direct: the detector sums come from their own kernel (a value per
     // detector and rhs after the finalize segments of the partials, see
     // det_direct_sums), which takes the detector entries grouped by detector,
@@ -129,6 +136,10 @@ constexpr int kLongRowMean = 96;
 
 // Members of one row group at most (larger sets of equal rows are split).
 constexpr int kGroupMax = 26;
+constexpr int kVox2Run = 26;             // entries of each run of a two-voxel row
+constexpr int kVox2Len = 2 * kVox2Run;   // entries of a two-voxel row
+constexpr int kVox2Item = 256;           // two-voxel rows of one work item
+constexpr int kStatePad = 32;            // padding entries after a single-rhs state buffer
 // Entries of a full lattice row (the grouped steps' fast path).
 constexpr int kSpmmUnrollHost = 26;
 // Rows a workgroup of the single-rhs row-list kernel takes per work item.
@@ -157,11 +168,12 @@ struct alignas(16) GroupDesc {
 // (work item c takes groups c * n_groups / n_chunks onwards).
 // xcd_bounds (may be NULL): with the XCD-aware walk, XCD i takes work items
 // xcd_bounds[i] .. xcd_bounds[i+1]-1 (kXcdBounds entries), else equal counts.
-// n_slow: with the grouped single-rhs step, the rows it takes one by one.
+// n_slow, n_vox2: with the grouped single-rhs step, the rows it takes one by
+// one from the CSR and its two-voxel rows.
 hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int64_t n_work, int n_inst,
                        int n_rhs_max, int value_f64, int rp64, int spmm, int grid, int xcd_remap,
                        const int64_t *xcd_bounds, int rows_per_tile, int n_det_max, int32_t *queue,
-                       hipStream_t stream, int64_t n_slow = 0);
+                       hipStream_t stream, int64_t n_slow = 0, int64_t n_vox2 = 0);
 hipError_t launch_finalize(const StepInst *insts_dev, int n_inst, int n_rhs_max, int n_det_max, int32_t *queue,
                            hipStream_t stream);
 

@@ -1469,6 +1469,114 @@ __global__ void __launch_bounds__(kNT) step_spmv_rowlist(const StepInst *__restr
     }
 }
 
+// The two-voxel rows (columns two runs of kVox2Run: the states of two
+// voxels, e.g. the transmitted and the reflected part of an interface row),
+// a thread per row: work item j (blockIdx.x, then every gridDim.x-th) is rows
+// kVox2Item j onwards of their list.  A row's values are a 16-byte aligned
+// block of their compact copy; x at a run comes as the eight aligned quads
+// that hold it (the state buffers keep kStatePad entries past the last row,
+// so these stay inside) and is shifted into place by the run's offset in its
+// first quad, two selects per entry.  Entries are added in column order (the
+// CSR step's products and order: y is equal bit for bit).  Partials of index
+// vox2_part + 4j + wave.
+typedef float f8 __attribute__((ext_vector_type(8)));
+typedef float f16 __attribute__((ext_vector_type(16)));
+typedef float f32x32 __attribute__((ext_vector_type(32)));
+
+// x[c .. c + 32) shifted: entry k is x[c + k] (k < 29); the eight aligned
+// quads from c & ~3, then whole-vector selects by the shift (vectors, not an
+// indexed array, so that the selection stays in registers)
+__device__ __forceinline__ f32x32 x_run(const GLB float *X, int32_t c)
+{
+    const int32_t c0 = c & ~3, s = c & 3;
+    const GLB f4 *p = (const GLB f4 *)(X + c0);
+    const f8 a = __builtin_shufflevector(p[0], p[1], 0, 1, 2, 3, 4, 5, 6, 7);
+    const f8 b = __builtin_shufflevector(p[2], p[3], 0, 1, 2, 3, 4, 5, 6, 7);
+    const f8 c8 = __builtin_shufflevector(p[4], p[5], 0, 1, 2, 3, 4, 5, 6, 7);
+    const f8 d = __builtin_shufflevector(p[6], p[7], 0, 1, 2, 3, 4, 5, 6, 7);
+    const f16 ab = __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15);
+    const f16 cd = __builtin_shufflevector(c8, d, 0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15);
+    const f32x32 F = __builtin_shufflevector(ab, cd, 0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17,
+                                             18, 19, 20, 21, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31);
+    const f32x32 F1 = __builtin_shufflevector(F, F, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18,
+                                              19, 20, 21, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31, 31);
+    const f32x32 G = (s & 1) ? F1 : F;
+    const f32x32 G2 = __builtin_shufflevector(G, G, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19,
+                                              20, 21, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31, 31, 31);
+    return (s & 2) ? G2 : G;
+}
+
+__global__ void __launch_bounds__(kNT) step_spmv_vox2(const StepInst *__restrict__ insts)
+{
+    __shared__ double s_abs[kMatMax];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const StepInst &I = insts[0];
+    const int64_t t = I.t[0];
+    if (t >= *I.t_end) return;
+    const Scale sc = step_scale(I, 0, t);
+    const float scale = ldexpf(1.0f, -sc.k);
+    const GLB float *X = gp((const float *)((t & 1) ? I.buf1 : I.buf0));
+    GLB float *Y = gpw((float *)((t & 1) ? I.buf0 : I.buf1));
+    const GLB int32_t *src_tile = gp(I.src_tile);
+    const GLB int32_t *info = gp(I.vox2_info);
+    const GLB float *v2 = gp(I.vox2_val);
+    for (int q = threadIdx.x; q < I.n_mat; q += kNT) s_abs[q] = gp(I.absorb)[q];
+    __syncthreads();
+    const int R = I.rows_per_tile;
+    const int64_t n_items = (I.n_vox2 + kVox2Item - 1) / kVox2Item;
+    for (int64_t j = blockIdx.x; j < n_items; j += gridDim.x) {
+        const int64_t i = j * kVox2Item + threadIdx.x;
+        double sN = 0.0, sE = 0.0, sA = 0.0;
+        float mx = 0.0f;
+        if (i < I.n_vox2) {
+            const i4 in = *(const GLB i4 *)(info + 4 * i);
+            const int32_t r = in[0];
+            const GLB float *vr = v2 + i * kVox2Len;
+            // the row's 52 values: 13 aligned quads (entry k of the second
+            // run is value kVox2Run + k)
+            const GLB f4 *pv = (const GLB f4 *)vr;
+            f4 vq[kVox2Len / 4];
+#pragma unroll
+            for (int q = 0; q < kVox2Len / 4; ++q) vq[q] = pv[q];
+            const f32x32 wa = x_run(X, in[1]), wb = x_run(X, in[2]);
+            float acc = 0.0f;
+#pragma unroll
+            for (int k = 0; k < kVox2Run; ++k) acc += vq[k >> 2][k & 3] * wa[k];
+#pragma unroll
+            for (int k = 0; k < kVox2Run; ++k) acc += vq[(kVox2Run + k) >> 2][(kVox2Run + k) & 3] * wb[k];
+            float v = acc * scale;
+            const int tile = r / R;
+            const int sb = src_tile[tile], se = src_tile[tile + 1];
+            if (sb < se) {
+                int e2 = lower_bound_rows<int32_t>(I.src_row, sb, se, r);
+                double sacc = 0.0;
+                bool any = false;
+                for (; e2 < se && I.src_row[e2] == r; ++e2) {
+                    sacc += I.src_w[e2] * I.amp[t * I.n_src + I.src_id[e2]];
+                    any = true;
+                }
+                if (any) v += (float)ldexp(sacc, -sc.En);
+            }
+            Y[r] = v;
+            if (r < I.n_states) {
+                sN += (double)v;
+                sA += s_abs[in[3]] * (double)v;
+                mx = fmaxf(mx, v);
+            } else {
+                sE += (double)v;
+            }
+        }
+        const double wN = wave_sum(sN), wE = wave_sum(sE), wA = wave_sum(sA), wM = wave_max((double)mx);
+        if (lane == 0) {
+            const int64_t nc = I.n_chunks, b = I.vox2_part + 4 * j + wave;
+            I.partials[(int64_t)kSlotN * nc + b] = wN;
+            I.partials[(int64_t)kSlotEsc * nc + b] = wE;
+            I.partials[(int64_t)kSlotAbs * nc + b] = wA;
+            I.partials[(int64_t)kSlotMax * nc + b] = wM;
+        }
+    }
+}
+
 // Detector sums of the single-rhs step by row groups (Eq. (27)): block (p, d)
 // forms the sum F * y over part p of detector d's entries (every thread every
 // 256th entry, then a fixed-order block sum) from the stored y.
@@ -2563,7 +2671,7 @@ __global__ void __launch_bounds__(256) step_struct_mm_x(StructArgs sa, const Ste
 hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int64_t n_work, int n_inst,
                        int n_rhs_max, int value_f64, int rp64, int spmm, int grid, int xcd_remap,
                        const int64_t *xcd_bounds, int rows_per_tile, int n_det_max, int32_t *queue,
-                       hipStream_t stream, int64_t n_slow)
+                       hipStream_t stream, int64_t n_slow, int64_t n_vox2)
 {
     (void)n_inst;
     (void)n_rhs_max;
@@ -2598,7 +2706,7 @@ hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int6
         const int variant = (xcd_remap >> 1) & 15;
         const int remap = xcd_remap & 1;
         if (variant == DRTS_SPMV_GROUPED) {
-            // the fast groups, then the other groups' rows, then the detectors
+            // the fast groups, then the listed rows, the two-voxel rows, the detectors
             hipLaunchKernelGGL(step_spmv_grouped<kGroupPairs>, g1, dim3(kNT), 0, stream, insts_dev, work_dev, n_work,
                                remap, xcd_bounds);
             const hipError_t e0 = hipGetLastError();
@@ -2608,6 +2716,11 @@ hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int6
                 const dim3 gr((unsigned)std::min<int64_t>(items, 2048));
                 if (rp64) hipLaunchKernelGGL(step_spmv_rowlist<int64_t>, gr, dim3(kNT), 0, stream, insts_dev);
                 else hipLaunchKernelGGL(step_spmv_rowlist<int32_t>, gr, dim3(kNT), 0, stream, insts_dev);
+            }
+            if (n_vox2 > 0) {
+                const int64_t items = (n_vox2 + kVox2Item - 1) / kVox2Item;
+                hipLaunchKernelGGL(step_spmv_vox2, dim3((unsigned)std::min<int64_t>(items, 2048)), dim3(kNT), 0,
+                                   stream, insts_dev);
             }
             if (n_det_max > 0) {
                 const hipError_t e = hipGetLastError();

@@ -103,6 +103,11 @@ class PulseT(C.Structure):
     _fields_ = [("kind", i32), ("fwhm_s", dbl)]
 
 
+class GroupsInfoT(C.Structure):
+    _fields_ = [("n_groups", i64), ("n_fast", i64), ("n_vox2_rows", i64), ("n_list_rows", i64),
+                ("n_list_entries", i64)]
+
+
 class DetectorsT(C.Structure):
     _fields_ = [("n_det", i32), ("det_ptr", C.POINTER(i64)), ("state", C.POINTER(i64)),
                 ("escape", C.POINTER(C.c_uint8)), ("F", C.POINTER(dbl))]
@@ -127,7 +132,7 @@ _sig("drts_matrix_info", C.c_int, [P, C.POINTER(i64), C.POINTER(i64), C.POINTER(
                                    C.POINTER(dbl)])
 _sig("drts_matrix_row_of", i64, [P, i64, i32])
 _sig("drts_pulse_step", dbl, [C.POINTER(PulseT), i64, dbl])
-_sig("drts_matrix_groups", C.c_int, [P, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)])
+_sig("drts_matrix_groups", C.c_int, [P, C.POINTER(GroupsInfoT)])
 _sig("drts_matrix_export_rows", C.c_int, [P, i64, i64, P, P, P])
 _sig("drts_matrix_destroy", None, [P])
 _sig("drts_solver_create", C.c_int, [P, i32, C.POINTER(DetectorsT), i64, C.POINTER(DeviceT), C.POINTER(P)])
@@ -340,14 +345,15 @@ class Matrix:
         return d.value
 
     def groups(self):
-        """(groups, fast groups, rows of the other groups, their entries) of
-        the matrix's row groups, or None while they are not built."""
-        a, b, c, d = i64(), i64(), i64(), i64()
-        rc = _lib.drts_matrix_groups(self._h, C.byref(a), C.byref(b), C.byref(c), C.byref(d))
+        """The matrix's row groups (drts_groups_info_t as a dict: n_groups,
+        n_fast, n_vox2_rows, n_list_rows, n_list_entries), or None while they
+        are not built."""
+        g = GroupsInfoT()
+        rc = _lib.drts_matrix_groups(self._h, C.byref(g))
         if rc == -5:
             return None
         _check(rc, "drts_matrix_groups")
-        return a.value, b.value, c.value, d.value
+        return {f: getattr(g, f) for f, _ in GroupsInfoT._fields_}
 
     def close(self):
         if getattr(self, "_h", None):

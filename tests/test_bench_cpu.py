@@ -29,18 +29,23 @@ def _counters(path, counter, rows):
 
 
 def test_traffic_scales_each_counter_by_the_copy_kernel(bench, tmp_path):
-    k0, k1, k2 = ("void drts::(anonymous namespace)::%s(args)" % k for k in bench.STEP_KERNELS)
+    ks = ["void drts::(anonymous namespace)::%s(args)" % k for k in bench.STEP_KERNELS]
     calib = "void at::native::%s<...>(args)" % bench.CALIB_KERNEL
     gib_kib = bench.CALIB_BYTES / 1024.0
-    # the copy kernel reads 1 GiB and writes 1 GiB; its FETCH_SIZE reads half
-    _counters(tmp_path / "f.csv", "FETCH_SIZE", [(k0, 1000.0), (k0, 3000.0), (k1, 10.0), (k2, 1.0),
-                                                 (calib, gib_kib / 2), ("other", 7.0)])
-    _counters(tmp_path / "w.csv", "WRITE_SIZE", [(k0, 50.0), (k0, 150.0), (k1, 4.0), (k2, 0.0), (calib, gib_kib)])
+    fetch = [1000.0, 10.0, 5.0, 1.0]
+    write = [50.0, 4.0, 2.0, 0.0]
+    # the copy kernel reads 1 GiB and writes 1 GiB; its FETCH_SIZE reads half;
+    # the first kernel has two dispatches (1x and 3x its value: mean 2x)
+    frows = [(ks[0], fetch[0]), (ks[0], 3 * fetch[0])] + [(k, v) for k, v in zip(ks[1:], fetch[1:])]
+    wrows = [(ks[0], write[0]), (ks[0], 3 * write[0])] + [(k, v) for k, v in zip(ks[1:], write[1:])]
+    _counters(tmp_path / "f.csv", "FETCH_SIZE", frows + [(calib, gib_kib / 2), ("other", 7.0)])
+    _counters(tmp_path / "w.csv", "WRITE_SIZE", wrows + [(calib, gib_kib)])
     t = bench.traffic_from_counters(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"))
-    assert t["fetch_kib"] == {bench.STEP_KERNELS[0]: 2000.0, bench.STEP_KERNELS[1]: 10.0,
-                              bench.STEP_KERNELS[2]: 1.0}      # per-dispatch means
+    want_f = [2 * fetch[0]] + fetch[1:]        # per-dispatch means
+    want_w = [2 * write[0]] + write[1:]
+    assert t["fetch_kib"] == dict(zip(bench.STEP_KERNELS, want_f))
     assert t["fetch_factor"] == 2.0 and t["write_factor"] == 1.0
-    assert t["bytes_per_launch"] == (2000.0 + 10.0 + 1.0) * 1024 * 2 + (100.0 + 4.0) * 1024
+    assert t["bytes_per_launch"] == sum(want_f) * 1024 * 2 + sum(want_w) * 1024
     assert t["source_sha256"] == bench.step_source_hash()
 
 
@@ -74,17 +79,22 @@ def test_more_than_one_gpu_is_refused():
 def test_grouped_bytes_against_the_csr_count(bench):
     """With every row in a fast group the format's bytes are the CSR count
     minus the columns (4 per entry) and the row pointers, plus 5 per row and
-    36 (+ a bit) per group; rows taken one by one cost what the CSR costs."""
+    36 (+ a bit) per group; listed rows cost what the CSR costs, two-voxel
+    rows their values and 16 bytes of info."""
     n_vox = 1000
     R = 26 * n_vox + 2000            # states and escape rows
     n_states = 26 * n_vox
     nnz = 26 * R
     csr = bench.spmv_bytes(nnz, R, n_states)
-    fast = bench.grouped_bytes(R, n_states, n_vox + 100, n_vox + 100, 0, 0)
+    g = {"n_groups": n_vox + 100, "n_fast": n_vox + 100, "n_vox2_rows": 0, "n_list_rows": 0, "n_list_entries": 0}
+    fast = bench.grouped_bytes(R, n_states, g)
     assert fast == csr - 4 * nnz - 4 * (R + 1) + 5 * R + 36 * (n_vox + 100) + (n_vox + 100 + 7) // 8
-    # moving 10 rows of 40 entries from the groups to the row list
-    slow = bench.grouped_bytes(R + 10, n_states, n_vox + 100, n_vox + 100, 10, 400)
+    # 10 more rows of 40 entries in the row list
+    slow = bench.grouped_bytes(R + 10, n_states, dict(g, n_list_rows=10, n_list_entries=400))
     assert slow - fast == 4 * 10 + 8 * 400 + 9 * 10
+    # 7 more two-voxel rows
+    v2 = bench.grouped_bytes(R + 7, n_states, dict(g, n_vox2_rows=7))
+    assert v2 - fast == 4 * 7 + (4 * 52 + 16) * 7
 
 
 def test_traffic_by_kernel_names_and_scales(bench, tmp_path):

@@ -142,14 +142,20 @@ def test_grouped_spmv_equals_tiled(name, make):
         # rows of hundreds of entries take the wave-per-row step: no groups are built
         assert M.groups() is None
     else:
-        n_groups, n_fast, n_slow, slow_nnz = M.groups()
-        assert 0 < n_groups <= M.n_rows and 0 <= n_fast <= n_groups and 0 <= n_slow <= M.n_rows
-        assert M.nnz == 26 * (M.n_rows - n_slow) + slow_nnz
+        g = M.groups()
+        assert 0 < g["n_groups"] <= M.n_rows and 0 <= g["n_fast"] <= g["n_groups"]
+        n_fast_rows = M.n_rows - g["n_vox2_rows"] - g["n_list_rows"]
+        assert n_fast_rows >= 0
+        assert M.nnz == 26 * n_fast_rows + 52 * g["n_vox2_rows"] + g["n_list_entries"]
+        if name in ("layers", "sphere"):
+            # Fresnel interfaces: rows with a transmitted and a reflected part
+            assert g["n_vox2_rows"] > 0
     if name == "slab":
         # one medium, no interfaces: each voxel's 26 rows (state or escape)
         # form one fast group; the other rows are the empty rows of face
         # states that cannot be entered, as many as the escape rows
-        assert n_fast == M.n_states // 26 and slow_nnz == 0 and n_slow == M.n_escape
+        assert g["n_fast"] == M.n_states // 26 and g["n_vox2_rows"] == 0
+        assert g["n_list_entries"] == 0 and g["n_list_rows"] == M.n_escape
     for o in (a, b, c):
         o["solver"].close()
 
