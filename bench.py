@@ -29,10 +29,9 @@ F64SUM_NOTE = ("FP32 values and state, each row summed in FP64 and rounded once:
                "FP32-accumulation precision pattern (more accurate than it)")
 STEP_SOURCES = ("paper_1611_08536_amd/csrc/drts_step.hip", "paper_1611_08536_amd/csrc/drts_step.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_spmv_grouped_c2_traffic.txt")
-SPMV_KERNEL = "step_spmv_grouped"
 # the kernels of one headline step launch (the finalize aside): the fast
 # groups, the row list of the other groups, the detector sums
-STEP_KERNELS = ("step_spmv_grouped", "step_spmv_rowlist", "step_spmv_vox2", "spmv_detectors")
+STEP_KERNELS = ("step_spmv_grouped_vi", "step_spmv_rowlist", "step_spmv_vox2", "spmv_detectors")
 CALIB_KERNEL = "vectorized_elementwise_kernel"
 CALIB_BYTES = 2 ** 30          # the calibration kernel reads and writes 1 GiB
 GRAPH_STEPS = 50               # steps per hipGraph replay in the timed run
@@ -134,13 +133,17 @@ def spmv_bytes(nnz, n_rows, n_states, val_bytes=4):
 def grouped_bytes(n_rows, n_states, g):
     """Bytes the step by row groups must move (g: the matrix's groups info).
     Members of fast groups (26 entries a row): their values in group order
-    (4 per entry), row id (4) and material (1), per fast group its
+    (4 per entry; value-indexed: a 32-byte slot of one-byte indices), row id
+    (4) and material (1), per fast group its
     descriptor (32), list entry (4) and source bit.  Two-voxel rows: their
     52 values (4 each) and their info (16).  Listed rows: their CSR entries
     (8 per entry), row pointer (4), material (1) and list entry (4).  x once,
     y once."""
     fast_rows = n_rows - g["n_vox2_rows"] - g["n_list_rows"]
-    fast = 4 * 26 * fast_rows + 5 * fast_rows + 36 * g["n_fast"] + (g["n_groups"] + 7) // 8
+    # value-indexed: a 32-byte slot per member (26 one-byte indices, the
+    # dictionary's number, padding); else 26 FP32 values
+    vals = 32 * fast_rows if g.get("value_tables", 0) > 0 else 4 * 26 * fast_rows
+    fast = vals + 5 * fast_rows + 36 * g["n_fast"] + (g["n_groups"] + 7) // 8
     vox2 = (4 * 52 + 16) * g["n_vox2_rows"]
     listed = 8 * g["n_list_entries"] + 9 * g["n_list_rows"]
     return fast + vox2 + listed + 4 * n_states + 4 * n_rows
@@ -641,17 +644,22 @@ def main():
         "eager_ms_per_step": round(eager_ms_step, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None if traffic is None else round(traffic / 1e9, 3),
-                     "kernel": SPMV_KERNEL, "kernel_ms": round(avg_kernel_ms, 4),
+                     "kernel": " + ".join(STEP_KERNELS), "kernel_ms": round(avg_kernel_ms, 4),
                      "kernel_timing": "HIP events around each of %d eager launches on the launch stream "
-                                      "(the step kernel and its detector kernel)" % launches,
+                                      "(the step's kernels, without the finalize)" % launches,
                      "algorithmic_bytes": nbytes,
                      "algorithmic_bytes_basis": "CSR [A;L]: 8 B per entry, row pointers, x and y once",
                      "format_bytes": fbytes,
                      "format_frac": None if fbytes is None else
                      round(fbytes / (avg_kernel_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
-                     "format_bytes_basis": "what the step by row groups must move: fast groups' values in group "
-                                           "order, members' rows and materials, descriptors; two-voxel rows' "
-                                           "values and info; the listed rows' CSR entries; x and y once",
+                     "format_bytes_basis": "what the step by row groups must move: fast groups' values (one-byte "
+                                           "dictionary indices in a 32-byte slot per member when value-indexed, "
+                                           "else FP32 in group order), members' rows and materials, descriptors; "
+                                           "two-voxel rows' values and info; the listed rows' CSR entries; x and "
+                                           "y once",
+                     "note": "the step streams fewer bytes than the CSR count (no columns; value-indexed "
+                             "entries), so frac can exceed 1; format_frac is the fraction of peak on the "
+                             "bytes the step must move",
                      "traffic_unit": "GB per launch"},
         "row_groups": None if groups is None else dict(groups, device_bytes=group_bytes),
         "tiled_step": {"kernel": "step_spmv<float, int, 256, 2> (values straight into LDS, 4 tiles per chunk)",

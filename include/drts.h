@@ -281,9 +281,17 @@ int drts_matrix_info(const drts_matrix_t *A, int64_t *n_states, int64_t *n_escap
  *                   their values, x read as the two runs;
  *   n_list_rows     all other rows (empty rows, other column patterns),
  *                   taken one by one from the CSR;
- *   n_list_entries  their entries. */
+ *   n_list_entries  their entries;
+ *   value_tables    > 0: the fast groups' values are value-indexed, one byte
+ *                   per entry into value_tables dictionaries of at most 256
+ *                   FP32 values (one per material: the material of the voxel
+ *                   whose states are the group's columns), so the step
+ *                   streams a quarter of the bytes and takes the same values;
+ *                   0: a material's fast groups hold more than 256 distinct
+ *                   values (or there are more than 16 materials) and the
+ *                   values stream as FP32. */
 typedef struct {
-    int64_t n_groups, n_fast, n_vox2_rows, n_list_rows, n_list_entries;
+    int64_t n_groups, n_fast, n_vox2_rows, n_list_rows, n_list_entries, value_tables;
 } drts_groups_info_t;
 
 /* Fills *info.  DRTS_E_INVALID for a NULL argument; DRTS_E_STATE while the

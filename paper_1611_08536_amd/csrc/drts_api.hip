@@ -74,8 +74,8 @@ void Buffer::reset()
 
 int64_t Matrix::bytes() const
 {
-    const Buffer *b[] = {&row_ptr, &col,      &val,       &grp_desc,  &grp_row,  &grp_mat,
-                         &grp_val, &grp_fast, &slow_rows, &vox2_info, &vox2_val};
+    const Buffer *b[] = {&row_ptr,  &col,       &val,       &grp_desc, &grp_row, &grp_mat, &grp_val,
+                         &grp_fast, &slow_rows, &vox2_info, &vox2_val, &vi_idx,  &vi_dict};
     int64_t n = 0;
     for (const Buffer *x : b) n += (int64_t)x->bytes;
     return n;
@@ -702,6 +702,9 @@ int prepare(drts_solver *S)
         I.vox2_val = A.vox2_val.as<float>();
         I.n_vox2 = A.n_vox2;
         I.vox2_part = I.slow_part + 4 * ((A.n_slow + kRowListItem - 1) / kRowListItem);
+        I.vi_idx = A.vi_ntab > 0 ? A.vi_idx.as<uint8_t>() : nullptr;
+        I.vi_dict = A.vi_ntab > 0 ? A.vi_dict.as<float>() : nullptr;
+        I.vi_ntab = A.vi_ntab;
         I.det_direct = 1;
         I.ddet_ptr = S->ddet_ptr.as<int64_t>();
         I.ddet_row = S->ddet_row.as<int64_t>();
@@ -886,7 +889,7 @@ int launch_one(drts_solver *S, hipStream_t stream, const StepInst *inst = nullpt
                                A.model.value_type == DRTS_F64, A.rp64 ? 1 : 0, spmm ? (S->grouped ? 2 : 1) : 0, S->grid,
                                (S->opt.xcd_remap ? 1 : 0) | ((variant & 15) << 1), S->xcd_bounds.as<int64_t>(),
                                S->opt.rows_per_tile, S->n_det, queue, stream, S->grouped ? A.n_slow : 0,
-                               S->grouped && !spmm ? A.n_vox2 : 0);
+                               S->grouped && !spmm ? A.n_vox2 : 0, S->grouped && !spmm && A.vi_ntab > 0 ? 1 : 0);
     }
     if (e != hipSuccess) return set_error(DRTS_E_HIP, "step launch failed: %s", hipGetErrorString(e));
     if (e1) DRTS_HIP(hipEventRecord(e1, stream));
@@ -1129,6 +1132,7 @@ int drts_matrix_groups(const drts_matrix_t *A, drts_groups_info_t *info)
     info->n_vox2_rows = g ? A->m.n_vox2 : 0;
     info->n_list_rows = g ? A->m.n_slow : 0;
     info->n_list_entries = g ? A->m.n_slow_nnz : 0;
+    info->value_tables = g ? A->m.vi_ntab : 0;
     return DRTS_OK;
 }
 

@@ -20,6 +20,8 @@
 
 #include <hipcub/hipcub.hpp>
 
+#include <cstring>
+
 #include "drts_internal.h"
 #include "drts_step.h"
 
@@ -187,6 +189,155 @@ __global__ void __launch_bounds__(256) group_scatter(const int32_t *flag, const 
     if (i < n && flag[i]) grp_ptr[pos[i]] = (int32_t)i;
 }
 
+// ---- value-indexed fast groups ------------------------------------------------
+// A fast group's dictionary is the one of its source voxel's material (the
+// voxel whose states are its columns).  Any assignment would be exact; this
+// one keeps each dictionary to the few distinct values of one material's rows.
+constexpr uint32_t kViEmpty = 0xffffffffu;
+
+__device__ __forceinline__ int vi_table_of(const GroupDesc &D, const uint8_t *mat_of_voxel, int n_dir)
+{
+    return mat_of_voxel[D.cstart / n_dir];
+}
+
+// Inserts the bit pattern of every value of fast group f into its
+// dictionary's hash set (linear probing; a full set raises *overflow).
+__global__ void __launch_bounds__(256) vi_insert(const GroupDesc *desc, const int32_t *fast, int64_t n_fast,
+                                                 const float *gval, const uint8_t *mat_of_voxel, int n_dir,
+                                                 uint32_t *hs, int32_t *overflow)
+{
+    for (int64_t f = blockIdx.x; f < n_fast; f += gridDim.x) {
+        const GroupDesc D = desc[fast[f]];
+        uint32_t *set = hs + (size_t)vi_table_of(D, mat_of_voxel, n_dir) * kViHash;
+        for (int e = threadIdx.x; e < D.n * D.nm; e += blockDim.x) {
+            const uint32_t bits = __float_as_uint(gval[D.voff + e]);
+            if (bits == kViEmpty) {
+                atomicExch(overflow, 1);
+                continue;
+            }
+            uint32_t h = (bits * 2654435761u) >> 20;
+            bool done = false;
+            for (int p = 0; p < kViHash && !done; ++p, h = (h + 1) & (kViHash - 1)) {
+                const uint32_t cur = __hip_atomic_load(set + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (cur == bits) done = true;
+                else if (cur == kViEmpty) {
+                    const uint32_t old = atomicCAS(set + h, kViEmpty, bits);
+                    done = old == kViEmpty || old == bits;
+                }
+            }
+            if (!done) atomicExch(overflow, 1);
+        }
+    }
+}
+
+// Slot j of fast group f: member j's values as indices into its dictionary
+// (sorted bit patterns: an exact match by binary search), the dictionary at
+// byte kViTabByte, zeros elsewhere (and for j >= the member count).
+__global__ void __launch_bounds__(256) vi_encode(const GroupDesc *desc, const int32_t *fast, int64_t n_fast,
+                                                 const float *gval, const uint8_t *mat_of_voxel, int n_dir,
+                                                 const uint32_t *dict_bits, const int32_t *dict_n, uint8_t *idx,
+                                                 int32_t *missing)
+{
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= n_fast * 26) return;
+    const int64_t f = gid / 26;
+    const int j = (int)(gid % 26);
+    const GroupDesc D = desc[fast[f]];
+    const int tab = vi_table_of(D, mat_of_voxel, n_dir);
+    const uint32_t *dk = dict_bits + (size_t)tab * kViDict;
+    const int nd = dict_n[tab];
+    uint32_t w[kViSlot / 4] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (j < D.nm) {
+        for (int k = 0; k < D.n; ++k) {
+            const uint32_t bits = __float_as_uint(gval[D.voff + (int64_t)k * D.nm + j]);
+            int lo = 0, hi = nd;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (dk[mid] < bits) lo = mid + 1;
+                else hi = mid;
+            }
+            if (lo >= nd || dk[lo] != bits) atomicExch(missing, 1);
+            w[k >> 2] |= (uint32_t)(lo & 0xff) << (8 * (k & 3));
+        }
+    }
+    w[kViTabByte >> 2] |= (uint32_t)tab << (8 * (kViTabByte & 3));
+    uint4 *out = (uint4 *)(idx + f * kViBlock + (int64_t)j * kViSlot);
+    out[0] = make_uint4(w[0], w[1], w[2], w[3]);
+    out[1] = make_uint4(w[4], w[5], w[6], w[7]);
+}
+
+template <typename T> int upload_host(Device &dev, Buffer &b, const std::vector<T> &v)
+{
+    int rc = b.allocate(&dev, std::max<size_t>(v.size(), 1) * sizeof(T));
+    if (rc) return rc;
+    if (!v.empty()) DRTS_HIP(hipMemcpyAsync(b.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, dev.stream));
+    return DRTS_OK;
+}
+
+// Builds A.vi_idx / A.vi_dict, or leaves A.vi_ntab = 0 when a material has
+// more than kViDict distinct values among its fast groups' entries (or there
+// are more than kViTabs materials).
+int build_value_index(Matrix &A)
+{
+    Device &dev = A.dev;
+    A.vi_ntab = 0;
+    const int n_mat = (int)A.model.absorb.size();
+    if (A.n_fast <= 0 || n_mat <= 0 || n_mat > kViTabs) return DRTS_OK;
+    int rc;
+    Buffer hs, flags;
+    if ((rc = hs.allocate(&dev, (size_t)n_mat * kViHash * sizeof(uint32_t)))) return rc;
+    if ((rc = flags.allocate(&dev, 2 * sizeof(int32_t)))) return rc;
+    DRTS_HIP(hipMemsetAsync(hs.ptr, 0xff, (size_t)n_mat * kViHash * sizeof(uint32_t), dev.stream));
+    DRTS_HIP(hipMemsetAsync(flags.ptr, 0, 2 * sizeof(int32_t), dev.stream));
+    const unsigned ib = (unsigned)std::min<int64_t>(A.n_fast, 65536);
+    hipLaunchKernelGGL(vi_insert, dim3(ib), dim3(256), 0, dev.stream, A.grp_desc.as<GroupDesc>(),
+                       A.grp_fast.as<int32_t>(), A.n_fast, A.grp_val.as<float>(), A.mat_of_voxel.as<uint8_t>(),
+                       A.model.n_dir, hs.as<uint32_t>(), flags.as<int32_t>());
+    DRTS_HIP(hipGetLastError());
+    std::vector<uint32_t> h((size_t)n_mat * kViHash);
+    int32_t fl[2] = {0, 0};
+    DRTS_HIP(hipMemcpyAsync(h.data(), hs.ptr, h.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, dev.stream));
+    DRTS_HIP(hipMemcpyAsync(fl, flags.ptr, sizeof fl, hipMemcpyDeviceToHost, dev.stream));
+    DRTS_HIP(hipStreamSynchronize(dev.stream));
+    if (fl[0]) return DRTS_OK;
+    // per material: its distinct bit patterns, sorted
+    std::vector<uint32_t> dict((size_t)n_mat * kViDict, 0u);
+    std::vector<int32_t> dn((size_t)n_mat, 0);
+    std::vector<float> dval((size_t)n_mat * kViDict, 0.0f);
+    for (int q = 0; q < n_mat; ++q) {
+        std::vector<uint32_t> u;
+        for (int i = 0; i < kViHash; ++i)
+            if (h[(size_t)q * kViHash + i] != kViEmpty) u.push_back(h[(size_t)q * kViHash + i]);
+        if (u.size() > (size_t)kViDict) return DRTS_OK;
+        std::sort(u.begin(), u.end());
+        dn[(size_t)q] = (int32_t)u.size();
+        for (size_t i = 0; i < u.size(); ++i) {
+            dict[(size_t)q * kViDict + i] = u[i];
+            std::memcpy(&dval[(size_t)q * kViDict + i], &u[i], sizeof(float));
+        }
+    }
+    Buffer dbits, dcount;
+    if ((rc = upload_host(dev, dbits, dict))) return rc;
+    if ((rc = upload_host(dev, dcount, dn))) return rc;
+    if ((rc = A.vi_idx.allocate(&dev, (size_t)A.n_fast * kViBlock))) return rc;
+    if ((rc = upload_host(dev, A.vi_dict, dval))) return rc;
+    const int64_t nt = A.n_fast * 26;
+    hipLaunchKernelGGL(vi_encode, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, dev.stream,
+                       A.grp_desc.as<GroupDesc>(), A.grp_fast.as<int32_t>(), A.n_fast, A.grp_val.as<float>(),
+                       A.mat_of_voxel.as<uint8_t>(), A.model.n_dir, dbits.as<uint32_t>(), dcount.as<int32_t>(),
+                       A.vi_idx.as<uint8_t>(), flags.as<int32_t>() + 1);
+    DRTS_HIP(hipGetLastError());
+    DRTS_HIP(hipMemcpyAsync(fl, flags.ptr, sizeof fl, hipMemcpyDeviceToHost, dev.stream));
+    DRTS_HIP(hipStreamSynchronize(dev.stream));
+    if (fl[1]) {
+        A.vi_idx.reset();
+        A.vi_dict.reset();
+        return DRTS_OK;
+    }
+    A.vi_ntab = n_mat;
+    return DRTS_OK;
+}
+
 template <typename IT>
 int build_groups(Matrix &A)
 {
@@ -340,6 +491,7 @@ int build_groups(Matrix &A)
         DRTS_HIP(hipGetLastError());
         DRTS_HIP(hipStreamSynchronize(dev.stream));
     }
+    if ((rc = build_value_index(A))) return rc;
     A.n_groups = G;
     return DRTS_OK;
 }
@@ -358,8 +510,8 @@ int row_groups(const Matrix &Ac)
     }
     const int rc = A.rp64 ? build_groups<int64_t>(A) : build_groups<int32_t>(A);
     if (rc) {
-        Buffer *b[] = {&A.grp_desc, &A.grp_row, &A.grp_mat, &A.grp_val, &A.grp_fast, &A.slow_rows, &A.vox2_info,
-                       &A.vox2_val};
+        Buffer *b[] = {&A.grp_desc, &A.grp_row, &A.grp_mat, &A.grp_val,  &A.grp_fast,
+                       &A.slow_rows, &A.vox2_info, &A.vox2_val, &A.vi_idx, &A.vi_dict};
         for (Buffer *x : b) x->reset();
         A.n_groups = -1;
     }

@@ -127,6 +127,11 @@ struct Matrix {
     // StepInst) and the rows of all other groups
     Buffer grp_fast, slow_rows, vox2_info, vox2_val;
     int64_t n_fast = 0, n_slow = 0, n_slow_nnz = 0, n_vox2 = 0;
+    // the fast groups' values as one-byte indices into per-material
+    // dictionaries (vi_ntab > 0; 0 = a material has more than kViDict
+    // distinct values, or more than kViTabs materials: FP32 group values)
+    Buffer vi_idx, vi_dict;
+    int32_t vi_ntab = 0;
     int64_t bytes() const;         // the CSR arrays (and the row groups, once built)
     int64_t table_bytes() const;   // everything else on the device (tables of the model)
 };

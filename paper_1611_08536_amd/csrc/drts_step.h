@@ -81,6 +81,11 @@ struct StepInst {
     const int32_t *vox2_info;
     const float *vox2_val;
     int64_t n_vox2, vox2_part;
+    // the fast groups' values as one-byte indices (NULL = read as FP32 in
+    // group order) and the dictionaries they index ([vi_ntab][kViDict])
+    const uint8_t *vi_idx;
+    const float *vi_dict;
+    int32_t vi_ntab;
     // det_direct: the detector sums come from their own kernel (a value per
     // detector and rhs after the finalize segments of the partials, see
     // det_direct_sums), which takes the detector entries grouped by detector,
@@ -140,6 +145,16 @@ constexpr int kVox2Run = 26;             // entries of each run of a two-voxel r
 constexpr int kVox2Len = 2 * kVox2Run;   // entries of a two-voxel row
 constexpr int kVox2Item = 256;           // two-voxel rows of one work item
 constexpr int kStatePad = 32;            // padding entries after a single-rhs state buffer
+// value-indexed fast groups: each member's kSpmmUnrollHost values as one-byte
+// indices into its group's dictionary (kViDict FP32 values, at most kViTabs
+// dictionaries), in a kViSlot-byte slot whose byte kViTabByte names the
+// dictionary; a fast group's slots are kViBlock bytes in fast-list order
+constexpr int kViSlot = 32;
+constexpr int kViTabByte = 26;
+constexpr int kViBlock = 26 * kViSlot;
+constexpr int kViDict = 256;
+constexpr int kViTabs = 16;
+constexpr int kViHash = 4096;            // slots of a dictionary's build-time hash set
 // Entries of a full lattice row (the grouped steps' fast path).
 constexpr int kSpmmUnrollHost = 26;
 // Rows a workgroup of the single-rhs row-list kernel takes per work item.
@@ -169,11 +184,12 @@ struct alignas(16) GroupDesc {
 // xcd_bounds (may be NULL): with the XCD-aware walk, XCD i takes work items
 // xcd_bounds[i] .. xcd_bounds[i+1]-1 (kXcdBounds entries), else equal counts.
 // n_slow, n_vox2: with the grouped single-rhs step, the rows it takes one by
-// one from the CSR and its two-voxel rows.
+// one from the CSR and its two-voxel rows; vi: its fast groups' values are
+// value-indexed.
 hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int64_t n_work, int n_inst,
                        int n_rhs_max, int value_f64, int rp64, int spmm, int grid, int xcd_remap,
                        const int64_t *xcd_bounds, int rows_per_tile, int n_det_max, int32_t *queue,
-                       hipStream_t stream, int64_t n_slow = 0, int64_t n_vox2 = 0);
+                       hipStream_t stream, int64_t n_slow = 0, int64_t n_vox2 = 0, int vi = 0);
 hipError_t launch_finalize(const StepInst *insts_dev, int n_inst, int n_rhs_max, int n_det_max, int32_t *queue,
                            hipStream_t stream);
 

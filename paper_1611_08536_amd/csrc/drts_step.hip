@@ -1388,6 +1388,155 @@ __global__ void __launch_bounds__(kNT) step_spmv_grouped(const StepInst *__restr
     }
 }
 
+// The fast groups with value-indexed values: as step_spmv_grouped, but lane m
+// reads its member's slot (kViSlot bytes: its entries as one-byte indices and
+// the dictionary's number) with two 16-byte loads and takes each value from
+// the dictionary in LDS -- the same FP32 values, so the same products, order
+// and y bit for bit, from a quarter of the bytes.
+constexpr int kGroupPairsVi = 2;   // pairs of groups a wave forms per iteration
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <int NP>
+__global__ void __launch_bounds__(kNT) step_spmv_grouped_vi(const StepInst *__restrict__ insts,
+                                                             const WorkItem *__restrict__ work, int64_t n_work,
+                                                             int xcd_remap, const int64_t *__restrict__ xcd_bounds)
+{
+    constexpr int NG = 2 * NP;
+    __shared__ float s_x[4][NG][32];
+    __shared__ float s_tab[kViTabs * kViDict];
+    __shared__ double s_abs[kMatMax];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int h = lane >> 5, m = lane & 31;
+    const Walk wk = walk_of(n_work, xcd_remap, xcd_bounds);
+    const StepInst &I = insts[0];
+    const int64_t t = I.t[0];
+    if (t >= *I.t_end) return;
+    const Scale sc = step_scale(I, 0, t);
+    const float scale = ldexpf(1.0f, -sc.k);
+    const GLB float *X = gp((const float *)((t & 1) ? I.buf1 : I.buf0));
+    GLB float *Y = gpw((float *)((t & 1) ? I.buf0 : I.buf1));
+    const GLB uint8_t *gmat = gp(I.grp_mat);
+    const GLB int32_t *grow = gp(I.grp_row);
+    const GLB uint8_t *vidx = gp(I.vi_idx);
+    const GLB int32_t *src_tile = gp(I.src_tile);
+    const CST GroupDesc *grp = cst(I.grp);
+    const CST int32_t *gfast = cst(I.grp_fast);
+    const CST uint32_t *gsrc = cst(I.grp_src);
+    for (int q = threadIdx.x; q < I.n_mat; q += kNT) s_abs[q] = gp(I.absorb)[q];
+    for (int q = threadIdx.x; q < I.vi_ntab * kViDict; q += kNT) s_tab[q] = gp(I.vi_dict)[q];
+    __syncthreads();
+
+    const int R = I.rows_per_tile;
+    const int64_t G = I.n_fast;
+    for (int64_t wi = wk.begin; wi < wk.end; wi += wk.stride) {
+        const int64_t c = work[wi].chunk;
+        const int64_t c_b = c * G / n_work, c_e = (c + 1) * G / n_work;
+        const int64_t g_b = c_b + wave * (c_e - c_b) / 4, g_e = c_b + (wave + 1) * (c_e - c_b) / 4;
+        double sN = 0.0, sE = 0.0, sA = 0.0;
+        float mx = 0.0f;
+        if (g_b < g_e) {
+            int64_t id[NG];
+            GroupDesc D[NG];
+            uint32_t w[NG];
+#pragma unroll
+            for (int q = 0; q < NG; ++q) {
+                id[q] = gfast[min(g_b + q, g_e - 1)];
+                D[q] = load_desc(grp + id[q]);
+                w[q] = gsrc[id[q] >> 5];
+            }
+            for (int64_t g2 = g_b; g2 < g_e; g2 += NG) {
+                int64_t ci[NG];
+                GroupDesc C[NG];
+                uint32_t cw[NG];
+#pragma unroll
+                for (int q = 0; q < NG; ++q) {
+                    ci[q] = id[q];
+                    C[q] = D[q];
+                    cw[q] = w[q];
+                }
+                if (g2 + NG < g_e) {
+#pragma unroll
+                    for (int q = 0; q < NG; ++q) {
+                        id[q] = gfast[min(g2 + NG + q, g_e - 1)];
+                        D[q] = load_desc(grp + id[q]);
+                        w[q] = gsrc[id[q] >> 5];
+                    }
+                }
+                // every pair's loads first, then the sums in pair order
+                u32x4 sl[NP][2];
+                float xm[NP];
+                int32_t r[NP];
+                int mt[NP], nmv[NP];
+                bool gsb[NP];
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    const GroupDesc &A0 = C[2 * p], &A1 = C[2 * p + 1];
+                    const int nm = h ? A1.nm : A0.nm;
+                    const int m0 = h ? A1.m0 : A0.m0, cstart = h ? A1.cstart : A0.cstart;
+                    gsb[p] = h ? ((cw[2 * p + 1] >> (ci[2 * p + 1] & 31)) & 1u) : ((cw[2 * p] >> (ci[2 * p] & 31)) & 1u);
+                    nmv[p] = nm;
+                    const int jm = min(m, nm - 1);
+                    r[p] = grow[m0 + jm];
+                    mt[p] = gmat[m0 + jm];
+                    xm[p] = X[cstart + min(m, kSpmmUnroll - 1)];
+                    // this half's group is fast group g2 + 2p + h (the last
+                    // one again past the wave's range)
+                    const int64_t f = min(g2 + 2 * p + h, g_e - 1);
+                    const GLB u32x4 *slot = (const GLB u32x4 *)(vidx + f * kViBlock + (int64_t)jm * kViSlot);
+                    sl[p][0] = __builtin_nontemporal_load(slot);
+                    sl[p][1] = __builtin_nontemporal_load(slot + 1);
+                }
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    float *sx = s_x[wave][2 * p + h];
+                    sx[m] = xm[p];
+                    const uint32_t wd[8] = {sl[p][0][0], sl[p][0][1], sl[p][0][2], sl[p][0][3],
+                                            sl[p][1][0], sl[p][1][1], sl[p][1][2], sl[p][1][3]};
+                    const float *tab = s_tab + ((wd[kViTabByte >> 2] >> (8 * (kViTabByte & 3))) & 0xff) * kViDict;
+                    float acc = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < kSpmmUnroll; ++k) acc += tab[(wd[k >> 2] >> (8 * (k & 3))) & 0xff] * sx[k];
+                    if (g2 + 2 * p + h < g_e && m < nmv[p]) {
+                        const int32_t rr = r[p];
+                        float v = acc * scale;
+                        if (gsb[p]) {
+                            const int tile = rr / R;
+                            const int sb = src_tile[tile], se = src_tile[tile + 1];
+                            if (sb < se) {
+                                int e2 = lower_bound_rows<int32_t>(I.src_row, sb, se, rr);
+                                double s = 0.0;
+                                bool any = false;
+                                for (; e2 < se && I.src_row[e2] == rr; ++e2) {
+                                    s += I.src_w[e2] * I.amp[t * I.n_src + I.src_id[e2]];
+                                    any = true;
+                                }
+                                if (any) v += (float)ldexp(s, -sc.En);
+                            }
+                        }
+                        Y[rr] = v;
+                        if (rr < I.n_states) {
+                            sN += (double)v;
+                            sA += s_abs[mt[p]] * (double)v;
+                            mx = fmaxf(mx, v);
+                        } else {
+                            sE += (double)v;
+                        }
+                    }
+                }
+            }
+        }
+        const double wN = wave_sum(sN), wE = wave_sum(sE), wA = wave_sum(sA), wM = wave_max((double)mx);
+        if (lane == 0) {
+            const int64_t nc = I.n_chunks, b = 4 * c + wave;
+            I.partials[(int64_t)kSlotN * nc + b] = wN;
+            I.partials[(int64_t)kSlotEsc * nc + b] = wE;
+            I.partials[(int64_t)kSlotAbs * nc + b] = wA;
+            I.partials[(int64_t)kSlotMax * nc + b] = wM;
+        }
+    }
+}
+
 // The rows of the groups step_spmv_grouped does not take, a thread per row:
 // work item j (blockIdx.x, then every gridDim.x-th) is rows kRowListItem j
 // onwards of the list; each row's entries are added in column order (the
@@ -2671,7 +2820,7 @@ __global__ void __launch_bounds__(256) step_struct_mm_x(StructArgs sa, const Ste
 hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int64_t n_work, int n_inst,
                        int n_rhs_max, int value_f64, int rp64, int spmm, int grid, int xcd_remap,
                        const int64_t *xcd_bounds, int rows_per_tile, int n_det_max, int32_t *queue,
-                       hipStream_t stream, int64_t n_slow, int64_t n_vox2)
+                       hipStream_t stream, int64_t n_slow, int64_t n_vox2, int vi)
 {
     (void)n_inst;
     (void)n_rhs_max;
@@ -2707,8 +2856,12 @@ hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int6
         const int remap = xcd_remap & 1;
         if (variant == DRTS_SPMV_GROUPED) {
             // the fast groups, then the listed rows, the two-voxel rows, the detectors
-            hipLaunchKernelGGL(step_spmv_grouped<kGroupPairs>, g1, dim3(kNT), 0, stream, insts_dev, work_dev, n_work,
-                               remap, xcd_bounds);
+            if (vi)
+                hipLaunchKernelGGL(step_spmv_grouped_vi<kGroupPairsVi>, g1, dim3(kNT), 0, stream, insts_dev, work_dev,
+                                   n_work, remap, xcd_bounds);
+            else
+                hipLaunchKernelGGL(step_spmv_grouped<kGroupPairs>, g1, dim3(kNT), 0, stream, insts_dev, work_dev,
+                                   n_work, remap, xcd_bounds);
             const hipError_t e0 = hipGetLastError();
             if (e0 != hipSuccess) return e0;
             if (n_slow > 0) {

@@ -105,7 +105,7 @@ class PulseT(C.Structure):
 
 class GroupsInfoT(C.Structure):
     _fields_ = [("n_groups", i64), ("n_fast", i64), ("n_vox2_rows", i64), ("n_list_rows", i64),
-                ("n_list_entries", i64)]
+                ("n_list_entries", i64), ("value_tables", i64)]
 
 
 class DetectorsT(C.Structure):
@@ -346,8 +346,8 @@ class Matrix:
 
     def groups(self):
         """The matrix's row groups (drts_groups_info_t as a dict: n_groups,
-        n_fast, n_vox2_rows, n_list_rows, n_list_entries), or None while they
-        are not built."""
+        n_fast, n_vox2_rows, n_list_rows, n_list_entries, value_tables), or
+        None while they are not built."""
         g = GroupsInfoT()
         rc = _lib.drts_matrix_groups(self._h, C.byref(g))
         if rc == -5:

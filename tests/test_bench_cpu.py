@@ -95,6 +95,9 @@ def test_grouped_bytes_against_the_csr_count(bench):
     # 7 more two-voxel rows
     v2 = bench.grouped_bytes(R + 7, n_states, dict(g, n_vox2_rows=7))
     assert v2 - fast == 4 * 7 + (4 * 52 + 16) * 7
+    # value-indexed fast groups: 32 bytes a member instead of 104
+    vi = bench.grouped_bytes(R, n_states, dict(g, value_tables=3))
+    assert fast - vi == (104 - 32) * R
 
 
 def test_traffic_by_kernel_names_and_scales(bench, tmp_path):

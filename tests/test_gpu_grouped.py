@@ -54,12 +54,19 @@ def _leb(n):
     return m
 
 
+def _layers17(n):
+    # more materials than the value-indexed step has dictionaries: the fast
+    # groups' values stream as FP32
+    return W.layered(n, [W.Material(5.0 + i, 0.01 * (i + 1), 0.8, 1.4) for i in range(17)])
+
+
 MEDIA = [("slab", lambda n: W.homogeneous(n, _mat(), nz=n - 3)),
          ("layers", _layers),
          ("sphere", _sphere),
          ("reflect", lambda n: W.homogeneous(n, _mat(), bc="reflect")),
          ("order3", _order3),
          ("substep", _substep),
+         ("layers17", _layers17),
          ("lebedev", _leb)]
 
 
@@ -150,6 +157,13 @@ def test_grouped_spmv_equals_tiled(name, make):
         if name in ("layers", "sphere"):
             # Fresnel interfaces: rows with a transmitted and a reflected part
             assert g["n_vox2_rows"] > 0
+        # value-indexed fast groups: a dictionary per material, unless there
+        # are more than 16 materials; on the sphere the crossing rows' Fresnel
+        # factors vary with the normal, more than 256 values a material, and
+        # the values stream as FP32 (both paths equal the tiled step above)
+        n_mat = len(a["matrix"].medium.materials)
+        if name != "sphere":
+            assert g["value_tables"] == (0 if name == "layers17" or g["n_fast"] == 0 else n_mat), g
     if name == "slab":
         # one medium, no interfaces: each voxel's 26 rows (state or escape)
         # form one fast group; the other rows are the empty rows of face
