@@ -74,8 +74,9 @@ void Buffer::reset()
 
 int64_t Matrix::bytes() const
 {
-    const Buffer *b[] = {&row_ptr,  &col,       &val,       &grp_desc, &grp_row, &grp_mat, &grp_val,
-                         &grp_fast, &slow_rows, &vox2_info, &vox2_val, &vi_idx,  &vi_dict};
+    const Buffer *b[] = {&row_ptr,   &col,      &val,      &grp_desc, &grp_row,   &grp_mat,  &grp_val,
+                         &grp_fast,  &slow_rows, &vox2_info, &vox2_val, &vi_idx,  &vi_dict, &brick_ptr,
+                         &brick_org, &vi_fdesc};
     int64_t n = 0;
     for (const Buffer *x : b) n += (int64_t)x->bytes;
     return n;
@@ -144,7 +145,7 @@ struct drts_solver {
 
     Buffer buf0, buf1, ctl_t, ctl_E, ctl_M, ctl_abs, t_end, partials, xcd_bounds, xrows, xirr, xsrc, xdet, zrows, xdrng,
         ddet_ptr, ddet_row,
-        ddet_F, pull_bits, esc_base, grp_src;
+        ddet_F, pull_bits, esc_base, grp_src, grp_src_f;
     Buffer ser_tot, ser_det, ser_exp, ser_abs_exp, amp, smax;
     Buffer src_tile, src_row, src_id, src_rhs, src_w;
     Buffer det_tile, det_row, det_id, det_F;
@@ -627,6 +628,10 @@ int prepare(drts_solver *S)
         if ((rc = S->grp_src.allocate(&dev, (size_t)((A.n_groups + 31) / 32 + 1) * sizeof(uint32_t)))) return rc;
         if ((rc = group_flags(A, sr.as<int64_t>(), (int64_t)srows.size(), S->grp_src.as<uint32_t>(), dev.stream)))
             return rc;
+        if (A.vi_ntab > 0) {
+            if ((rc = S->grp_src_f.allocate(&dev, (size_t)((A.n_fast + 31) / 32 + 1) * sizeof(uint32_t)))) return rc;
+            if ((rc = fast_flags(A, S->grp_src.as<uint32_t>(), S->grp_src_f.as<uint32_t>(), dev.stream))) return rc;
+        }
         DRTS_HIP(hipStreamSynchronize(dev.stream));
     }
     if (S->n_chunks > INT32_MAX) return set_error(DRTS_E_RANGE, "too many chunks");
@@ -705,6 +710,13 @@ int prepare(drts_solver *S)
         I.vi_idx = A.vi_ntab > 0 ? A.vi_idx.as<uint8_t>() : nullptr;
         I.vi_dict = A.vi_ntab > 0 ? A.vi_dict.as<float>() : nullptr;
         I.vi_ntab = A.vi_ntab;
+        I.brick_ptr = A.brick_ptr.as<int32_t>();
+        I.brick_org = A.brick_org.as<int32_t>();
+        I.n_brick = A.n_brick;
+        I.grid_nx = A.model.nx;
+        I.grid_ny = A.model.ny;
+        I.vi_fdesc = A.vi_ntab > 0 ? A.vi_fdesc.as<int32_t>() : nullptr;
+        I.grp_src_f = A.vi_ntab > 0 ? S->grp_src_f.as<uint32_t>() : nullptr;
         I.det_direct = 1;
         I.ddet_ptr = S->ddet_ptr.as<int64_t>();
         I.ddet_row = S->ddet_row.as<int64_t>();
@@ -889,7 +901,7 @@ int launch_one(drts_solver *S, hipStream_t stream, const StepInst *inst = nullpt
                                A.model.value_type == DRTS_F64, A.rp64 ? 1 : 0, spmm ? (S->grouped ? 2 : 1) : 0, S->grid,
                                (S->opt.xcd_remap ? 1 : 0) | ((variant & 15) << 1), S->xcd_bounds.as<int64_t>(),
                                S->opt.rows_per_tile, S->n_det, queue, stream, S->grouped ? A.n_slow : 0,
-                               S->grouped && !spmm ? A.n_vox2 : 0, S->grouped && !spmm && A.vi_ntab > 0 ? 1 : 0);
+                               S->grouped && !spmm ? A.n_vox2 : 0, S->grouped && !spmm ? A.vi_ntab : 0);
     }
     if (e != hipSuccess) return set_error(DRTS_E_HIP, "step launch failed: %s", hipGetErrorString(e));
     if (e1) DRTS_HIP(hipEventRecord(e1, stream));

@@ -189,6 +189,104 @@ __global__ void __launch_bounds__(256) group_scatter(const int32_t *flag, const 
     if (i < n && flag[i]) grp_ptr[pos[i]] = (int32_t)i;
 }
 
+// ---- brick order of the fast groups ---------------------------------------------
+// The fast list is put in the order of bricks of kBrick^3 source voxels
+// (bricks in z, y, x order; voxels within a brick in z, y, x order, x
+// fastest), so that the value-indexed step can form a brick's groups in one
+// workgroup and stage the rows they write.  brick_key: the brick and the
+// position within it of fast group f's source voxel.
+__global__ void __launch_bounds__(256) brick_keys(const GroupDesc *desc, const int32_t *fast, int64_t n_fast,
+                                                  int n_dir, int nx, int ny, uint64_t *key)
+{
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= n_fast) return;
+    const int64_t u = desc[fast[f]].cstart / n_dir;
+    const int64_t x = u % nx, y = (u / nx) % ny, z = u / ((int64_t)nx * ny);
+    const int64_t nbx = (nx + kBrick - 1) / kBrick, nby = (ny + kBrick - 1) / kBrick;
+    const uint64_t brick = ((uint64_t)(z / kBrick) * nby + (uint64_t)(y / kBrick)) * nbx + (uint64_t)(x / kBrick);
+    const uint64_t local = ((uint64_t)(z % kBrick) * kBrick + (uint64_t)(y % kBrick)) * kBrick + (uint64_t)(x % kBrick);
+    key[f] = brick * (uint64_t)(kBrick * kBrick * kBrick) + local;
+}
+
+// first[f] = 1 where fast index f starts a brick
+__global__ void __launch_bounds__(256) brick_starts(const uint64_t *key, int64_t n, uint8_t *first)
+{
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= n) return;
+    const uint64_t b = key[f] / (uint64_t)(kBrick * kBrick * kBrick);
+    first[f] = (f == 0 || key[f - 1] / (uint64_t)(kBrick * kBrick * kBrick) != b) ? 1 : 0;
+}
+
+// brick i: its origin voxel (from the brick number of its first group's key)
+__global__ void __launch_bounds__(256) brick_origins(const int32_t *ptr, const uint64_t *key, int64_t n_brick, int nx,
+                                                     int ny, int32_t *org)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_brick) return;
+    const uint64_t b = key[ptr[i]] / (uint64_t)(kBrick * kBrick * kBrick);
+    const int64_t nbx = (nx + kBrick - 1) / kBrick, nby = (ny + kBrick - 1) / kBrick;
+    const int64_t bx = (int64_t)(b % (uint64_t)nbx), by = (int64_t)((b / (uint64_t)nbx) % (uint64_t)nby);
+    const int64_t bz = (int64_t)(b / ((uint64_t)nbx * nby));
+    org[i] = (int32_t)((bz * kBrick * ny + by * kBrick) * nx + bx * kBrick);
+}
+
+int order_fast_in_bricks(Matrix &A)
+{
+    Device &dev = A.dev;
+    const int64_t G = A.n_fast;
+    A.n_brick = 0;
+    const Model &M = A.model;
+    // consecutive fast groups of the brick order lie up to kBrick planes of
+    // source voxels apart; the FP32 step takes a pair's values at 32-bit
+    // offsets from the lower of the two, so larger planes keep the group order
+    if (G <= 0 || M.nx <= 0 || M.n_vox >= INT32_MAX ||
+        (int64_t)(kBrick + 1) * M.nx * M.ny * 26 * 26 * 4 >= (int64_t)INT32_MAX)
+        return DRTS_OK;
+    int rc;
+    Buffer key, key_s, ids, tmp, first, cnt;
+    if ((rc = key.allocate(&dev, G * sizeof(uint64_t)))) return rc;
+    if ((rc = key_s.allocate(&dev, G * sizeof(uint64_t)))) return rc;
+    if ((rc = ids.allocate(&dev, G * sizeof(int32_t)))) return rc;
+    const unsigned gb = (unsigned)((G + 255) / 256);
+    hipLaunchKernelGGL(brick_keys, dim3(gb), dim3(256), 0, dev.stream, A.grp_desc.as<GroupDesc>(),
+                       A.grp_fast.as<int32_t>(), G, M.n_dir, M.nx, M.ny, key.as<uint64_t>());
+    DRTS_HIP(hipGetLastError());
+    size_t tb = 0, tb2 = 0;
+    DRTS_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, key.as<uint64_t>(), key_s.as<uint64_t>(),
+                                                A.grp_fast.as<int32_t>(), ids.as<int32_t>(), (int)G, 0, 64,
+                                                dev.stream));
+    if ((rc = tmp.allocate(&dev, std::max<size_t>(tb, 16)))) return rc;
+    DRTS_HIP(hipcub::DeviceRadixSort::SortPairs(tmp.ptr, tb, key.as<uint64_t>(), key_s.as<uint64_t>(),
+                                                A.grp_fast.as<int32_t>(), ids.as<int32_t>(), (int)G, 0, 64,
+                                                dev.stream));
+    DRTS_HIP(hipMemcpyAsync(A.grp_fast.ptr, ids.ptr, G * sizeof(int32_t), hipMemcpyDeviceToDevice, dev.stream));
+    // brick starts and origins
+    if ((rc = first.allocate(&dev, G))) return rc;
+    if ((rc = cnt.allocate(&dev, sizeof(int64_t)))) return rc;
+    hipLaunchKernelGGL(brick_starts, dim3(gb), dim3(256), 0, dev.stream, key_s.as<uint64_t>(), G, first.as<uint8_t>());
+    DRTS_HIP(hipGetLastError());
+    if ((rc = A.brick_ptr.allocate(&dev, (G + 1) * sizeof(int32_t)))) return rc;
+    hipcub::CountingInputIterator<int32_t> fidx(0);
+    DRTS_HIP(hipcub::DeviceSelect::Flagged(nullptr, tb2, fidx, first.as<uint8_t>(), A.brick_ptr.as<int32_t>(),
+                                           cnt.as<int64_t>(), (int)G, dev.stream));
+    tmp.reset();
+    if ((rc = tmp.allocate(&dev, std::max<size_t>(tb2, 16)))) return rc;
+    DRTS_HIP(hipcub::DeviceSelect::Flagged(tmp.ptr, tb2, fidx, first.as<uint8_t>(), A.brick_ptr.as<int32_t>(),
+                                           cnt.as<int64_t>(), (int)G, dev.stream));
+    int64_t nb = 0;
+    DRTS_HIP(hipMemcpyAsync(&nb, cnt.ptr, sizeof nb, hipMemcpyDeviceToHost, dev.stream));
+    DRTS_HIP(hipStreamSynchronize(dev.stream));
+    const int32_t end = (int32_t)G;
+    DRTS_HIP(hipMemcpyAsync(A.brick_ptr.as<int32_t>() + nb, &end, sizeof end, hipMemcpyHostToDevice, dev.stream));
+    if ((rc = A.brick_org.allocate(&dev, std::max<int64_t>(nb, 1) * sizeof(int32_t)))) return rc;
+    hipLaunchKernelGGL(brick_origins, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, dev.stream,
+                       A.brick_ptr.as<int32_t>(), key_s.as<uint64_t>(), nb, M.nx, M.ny, A.brick_org.as<int32_t>());
+    DRTS_HIP(hipGetLastError());
+    DRTS_HIP(hipStreamSynchronize(dev.stream));
+    A.n_brick = nb;
+    return DRTS_OK;
+}
+
 // ---- value-indexed fast groups ------------------------------------------------
 // A fast group's dictionary is the one of its source voxel's material (the
 // voxel whose states are its columns).  Any assignment would be exact; this
@@ -234,9 +332,9 @@ __global__ void __launch_bounds__(256) vi_insert(const GroupDesc *desc, const in
 // (sorted bit patterns: an exact match by binary search), the dictionary at
 // byte kViTabByte, zeros elsewhere (and for j >= the member count).
 __global__ void __launch_bounds__(256) vi_encode(const GroupDesc *desc, const int32_t *fast, int64_t n_fast,
-                                                 const float *gval, const uint8_t *mat_of_voxel, int n_dir,
-                                                 const uint32_t *dict_bits, const int32_t *dict_n, uint8_t *idx,
-                                                 int32_t *missing)
+                                                 const float *gval, const uint8_t *mat_of_voxel, int n_dir, int nx,
+                                                 int ny, const uint32_t *dict_bits, const int32_t *dict_n,
+                                                 uint8_t *idx, int32_t *missing)
 {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= n_fast * 26) return;
@@ -261,6 +359,11 @@ __global__ void __launch_bounds__(256) vi_encode(const GroupDesc *desc, const in
         }
     }
     w[kViTabByte >> 2] |= (uint32_t)tab << (8 * (kViTabByte & 3));
+    // the source voxel's position in its brick
+    const int64_t u = D.cstart / n_dir;
+    const int64_t x = u % nx, y = (u / nx) % ny, z = u / ((int64_t)nx * ny);
+    const uint32_t pos = (uint32_t)(((z % kBrick) * kBrick + (y % kBrick)) * kBrick + (x % kBrick));
+    w[kViPosByte >> 2] |= pos << (8 * (kViPosByte & 3));
     uint4 *out = (uint4 *)(idx + f * kViBlock + (int64_t)j * kViSlot);
     out[0] = make_uint4(w[0], w[1], w[2], w[3]);
     out[1] = make_uint4(w[4], w[5], w[6], w[7]);
@@ -274,6 +377,32 @@ template <typename T> int upload_host(Device &dev, Buffer &b, const std::vector<
     return DRTS_OK;
 }
 
+__global__ void __launch_bounds__(256) fdesc_build(const GroupDesc *desc, const int32_t *fast, int64_t n_fast,
+                                                   int32_t *fd)
+{
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= n_fast) return;
+    const int32_t g = fast[f];
+    const GroupDesc D = desc[g];
+    fd[4 * f] = D.m0;
+    fd[4 * f + 1] = D.nm;
+    fd[4 * f + 2] = D.cstart;
+    fd[4 * f + 3] = g;
+}
+
+__global__ void __launch_bounds__(256) fast_flag_bits(const int32_t *fast, int64_t n_fast, const uint32_t *gbits,
+                                                      uint32_t *fbits)
+{
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w * 32 >= n_fast) return;
+    uint32_t word = 0;
+    for (int b = 0; b < 32 && w * 32 + b < n_fast; ++b) {
+        const int32_t g = fast[w * 32 + b];
+        word |= ((gbits[g >> 5] >> (g & 31)) & 1u) << b;
+    }
+    fbits[w] = word;
+}
+
 // Builds A.vi_idx / A.vi_dict, or leaves A.vi_ntab = 0 when a material has
 // more than kViDict distinct values among its fast groups' entries (or there
 // are more than kViTabs materials).
@@ -282,7 +411,7 @@ int build_value_index(Matrix &A)
     Device &dev = A.dev;
     A.vi_ntab = 0;
     const int n_mat = (int)A.model.absorb.size();
-    if (A.n_fast <= 0 || n_mat <= 0 || n_mat > kViTabs) return DRTS_OK;
+    if (A.n_fast <= 0 || n_mat <= 0 || n_mat > kViTabs || A.n_brick <= 0) return DRTS_OK;
     int rc;
     Buffer hs, flags;
     if ((rc = hs.allocate(&dev, (size_t)n_mat * kViHash * sizeof(uint32_t)))) return rc;
@@ -324,8 +453,8 @@ int build_value_index(Matrix &A)
     const int64_t nt = A.n_fast * 26;
     hipLaunchKernelGGL(vi_encode, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, dev.stream,
                        A.grp_desc.as<GroupDesc>(), A.grp_fast.as<int32_t>(), A.n_fast, A.grp_val.as<float>(),
-                       A.mat_of_voxel.as<uint8_t>(), A.model.n_dir, dbits.as<uint32_t>(), dcount.as<int32_t>(),
-                       A.vi_idx.as<uint8_t>(), flags.as<int32_t>() + 1);
+                       A.mat_of_voxel.as<uint8_t>(), A.model.n_dir, A.model.nx, A.model.ny, dbits.as<uint32_t>(),
+                       dcount.as<int32_t>(), A.vi_idx.as<uint8_t>(), flags.as<int32_t>() + 1);
     DRTS_HIP(hipGetLastError());
     DRTS_HIP(hipMemcpyAsync(fl, flags.ptr, sizeof fl, hipMemcpyDeviceToHost, dev.stream));
     DRTS_HIP(hipStreamSynchronize(dev.stream));
@@ -334,6 +463,11 @@ int build_value_index(Matrix &A)
         A.vi_dict.reset();
         return DRTS_OK;
     }
+    if ((rc = A.vi_fdesc.allocate(&dev, (size_t)A.n_fast * 4 * sizeof(int32_t)))) return rc;
+    hipLaunchKernelGGL(fdesc_build, dim3((unsigned)((A.n_fast + 255) / 256)), dim3(256), 0, dev.stream,
+                       A.grp_desc.as<GroupDesc>(), A.grp_fast.as<int32_t>(), A.n_fast, A.vi_fdesc.as<int32_t>());
+    DRTS_HIP(hipGetLastError());
+    DRTS_HIP(hipStreamSynchronize(dev.stream));
     A.vi_ntab = n_mat;
     return DRTS_OK;
 }
@@ -480,6 +614,7 @@ int build_groups(Matrix &A)
     A.n_slow = counts[1];
     A.n_slow_nnz = counts[2];
     A.n_vox2 = counts[3];
+    if ((rc = order_fast_in_bricks(A))) return rc;
     // the two-voxel rows' info and values in list order
     if ((rc = A.vox2_info.allocate(&dev, (size_t)std::max<int64_t>(A.n_vox2, 1) * 4 * sizeof(int32_t)))) return rc;
     if ((rc = A.vox2_val.allocate(&dev, (size_t)std::max<int64_t>(A.n_vox2, 1) * kVox2Len * sizeof(float))))
@@ -510,8 +645,9 @@ int row_groups(const Matrix &Ac)
     }
     const int rc = A.rp64 ? build_groups<int64_t>(A) : build_groups<int32_t>(A);
     if (rc) {
-        Buffer *b[] = {&A.grp_desc, &A.grp_row, &A.grp_mat, &A.grp_val,  &A.grp_fast,
-                       &A.slow_rows, &A.vox2_info, &A.vox2_val, &A.vi_idx, &A.vi_dict};
+        Buffer *b[] = {&A.grp_desc, &A.grp_row,   &A.grp_mat,   &A.grp_val,   &A.grp_fast,
+                       &A.slow_rows, &A.vox2_info, &A.vox2_val,  &A.vi_idx,    &A.vi_dict,
+                       &A.brick_ptr, &A.brick_org, &A.vi_fdesc};
         for (Buffer *x : b) x->reset();
         A.n_groups = -1;
     }
@@ -524,6 +660,16 @@ int group_flags(const Matrix &A, const int64_t *rows, int64_t n, uint32_t *bits,
     if (words <= 0) return DRTS_OK;
     hipLaunchKernelGGL(group_flag_bits, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, stream,
                        A.grp_desc.as<GroupDesc>(), A.grp_row.as<int32_t>(), A.n_groups, rows, n, bits);
+    DRTS_HIP(hipGetLastError());
+    return DRTS_OK;
+}
+
+int fast_flags(const Matrix &A, const uint32_t *gbits, uint32_t *fbits, hipStream_t stream)
+{
+    const int64_t words = (A.n_fast + 31) / 32;
+    if (words <= 0) return DRTS_OK;
+    hipLaunchKernelGGL(fast_flag_bits, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, stream,
+                       A.grp_fast.as<int32_t>(), A.n_fast, gbits, fbits);
     DRTS_HIP(hipGetLastError());
     return DRTS_OK;
 }

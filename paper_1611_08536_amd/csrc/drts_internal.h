@@ -132,6 +132,14 @@ struct Matrix {
     // distinct values, or more than kViTabs materials: FP32 group values)
     Buffer vi_idx, vi_dict;
     int32_t vi_ntab = 0;
+    // the fast list's bricks of kBrick^3 source voxels (the fast list is in
+    // brick order): first fast index of each brick (n_brick + 1) and its
+    // origin voxel
+    Buffer brick_ptr, brick_org;
+    int64_t n_brick = 0;
+    // per fast group (fast-list order): first member, member count, first
+    // column of its run, group index (int32 x 4), with value indexing
+    Buffer vi_fdesc;
     int64_t bytes() const;         // the CSR arrays (and the row groups, once built)
     int64_t table_bytes() const;   // everything else on the device (tables of the model)
 };
@@ -146,6 +154,8 @@ int row_groups(const Matrix &A);
 // Per group of A one bit (words of 32): set when a member's row is in the
 // ascending list rows[0 .. n) (device memory).
 int group_flags(const Matrix &A, const int64_t *rows, int64_t n, uint32_t *bits, hipStream_t stream);
+// bit f of fbits: bit gfast[f] of gbits (the source bits in fast-list order)
+int fast_flags(const Matrix &A, const uint32_t *gbits, uint32_t *fbits, hipStream_t stream);
 
 // ---- windowed measurement (Eq. 27 over several steps) --------------------------
 struct WindowArgs {

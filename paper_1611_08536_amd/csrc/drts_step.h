@@ -86,6 +86,17 @@ struct StepInst {
     const uint8_t *vi_idx;
     const float *vi_dict;
     int32_t vi_ntab;
+    // bricks of the fast list: brick b holds fast groups brick_ptr[b] ..
+    // brick_ptr[b + 1] - 1 and its window's first voxel is brick_org[b] -
+    // (1, 1, 1) (voxel index of the brick's origin in brick_org); grid extents
+    const int32_t *brick_ptr;
+    const int32_t *brick_org;
+    int64_t n_brick;
+    int32_t grid_nx, grid_ny;
+    // per fast group, in fast-list order: {first member, member count, first
+    // column of its run, group}; the source bits by fast index
+    const int32_t *vi_fdesc;
+    const uint32_t *grp_src_f;
     // det_direct: the detector sums come from their own kernel (a value per
     // detector and rhs after the finalize segments of the partials, see
     // det_direct_sums), which takes the detector entries grouped by detector,
@@ -155,6 +166,14 @@ constexpr int kViBlock = 26 * kViSlot;
 constexpr int kViDict = 256;
 constexpr int kViTabs = 16;
 constexpr int kViHash = 4096;            // slots of a dictionary's build-time hash set
+constexpr int kViPosByte = 27;           // slot byte: the group's position in its brick
+// value-indexed fast groups are ordered in bricks of kBrick^3 source voxels;
+// a workgroup forms a brick's groups and stages the rows they write into the
+// brick's window of (kBrick + 2)^3 destination voxels in LDS, then writes the
+// window out in address order
+constexpr int kBrick = 4;
+constexpr int kWin = kBrick + 2;
+constexpr int kWinSlots = kWin * kWin * kWin * 26;
 // Entries of a full lattice row (the grouped steps' fast path).
 constexpr int kSpmmUnrollHost = 26;
 // Rows a workgroup of the single-rhs row-list kernel takes per work item.
@@ -184,8 +203,8 @@ struct alignas(16) GroupDesc {
 // xcd_bounds (may be NULL): with the XCD-aware walk, XCD i takes work items
 // xcd_bounds[i] .. xcd_bounds[i+1]-1 (kXcdBounds entries), else equal counts.
 // n_slow, n_vox2: with the grouped single-rhs step, the rows it takes one by
-// one from the CSR and its two-voxel rows; vi: its fast groups' values are
-// value-indexed.
+// one from the CSR and its two-voxel rows; vi: the number of dictionaries of
+// its value-indexed fast groups (0: FP32 values).
 hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int64_t n_work, int n_inst,
                        int n_rhs_max, int value_f64, int rp64, int spmm, int grid, int xcd_remap,
                        const int64_t *xcd_bounds, int rows_per_tile, int n_det_max, int32_t *queue,

@@ -1330,11 +1330,13 @@ __global__ void __launch_bounds__(kNT) step_spmv_grouped(const StepInst *__restr
                     r[p] = grow[m0 + jm];
                     mt[p] = gmat[m0 + jm];
                     xm[p] = X[cstart + min(m, kSpmmUnroll - 1)];
-                    // a buffer at the pair's first group's values; each lane's
-                    // entries at 32-bit offsets from it
-                    const __amdgpu_buffer_rsrc_t rv =
-                        make_rsrc((const void *)(val + A0.voff), (uint64_t)(nv - A0.voff) * 4);
-                    const uint32_t o0 = (uint32_t)(voff - A0.voff + jm) * 4, st = (uint32_t)nm * 4;
+                    // a buffer at the lower of the pair's value offsets; each
+                    // lane's entries at 32-bit offsets from it (the pair's
+                    // groups are neighbours in the fast list, a few thousand
+                    // entries apart)
+                    const int64_t vb = min(A0.voff, A1.voff);
+                    const __amdgpu_buffer_rsrc_t rv = make_rsrc((const void *)(val + vb), (uint64_t)(nv - vb) * 4);
+                    const uint32_t o0 = (uint32_t)(voff - vb + jm) * 4, st = (uint32_t)nm * 4;
 #pragma unroll
                     for (int k = 0; k < kSpmmUnroll; ++k)
                         vk[p][k] = __builtin_bit_cast(
@@ -1388,22 +1390,32 @@ __global__ void __launch_bounds__(kNT) step_spmv_grouped(const StepInst *__restr
     }
 }
 
-// The fast groups with value-indexed values: as step_spmv_grouped, but lane m
-// reads its member's slot (kViSlot bytes: its entries as one-byte indices and
-// the dictionary's number) with two 16-byte loads and takes each value from
-// the dictionary in LDS -- the same FP32 values, so the same products, order
-// and y bit for bit, from a quarter of the bytes.
-constexpr int kGroupPairsVi = 2;   // pairs of groups a wave forms per iteration
+// The fast groups with value-indexed values, by bricks.  Lane m reads its
+// member's slot (kViSlot bytes: its entries as one-byte indices, the
+// dictionary's number, the group's position in its brick) with two 16-byte
+// loads and takes each value from the dictionary in LDS -- the same FP32
+// values, so the same products, order and y bit for bit, from a quarter of
+// the bytes.  A work item is a range of bricks; the workgroup forms one brick
+// at a time (its groups split among the waves, two pairs of groups issued per
+// pass) and stages every state row (u + e_m, m) of its groups -- all inside
+// the brick's window of kWin^3 voxels -- in LDS, with a presence bit; after a
+// barrier it writes the window out in address order (consecutive lanes,
+// consecutive rows: few lines per store), then the next brick.  Escape rows
+// and rows whose index is not (u + e_m, m) are stored directly.
+constexpr int kGroupPairsVi = 2;   // pairs of groups a wave forms per pass
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 template <int NP>
-__global__ void __launch_bounds__(kNT) step_spmv_grouped_vi(const StepInst *__restrict__ insts,
+__global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(5, 8))) step_spmv_grouped_vi(const StepInst *__restrict__ insts,
                                                              const WorkItem *__restrict__ work, int64_t n_work,
                                                              int xcd_remap, const int64_t *__restrict__ xcd_bounds)
 {
     constexpr int NG = 2 * NP;
+    constexpr int kHasWords = (kWinSlots + 31) / 32;
+    extern __shared__ float s_tab[];            // [vi_ntab][kViDict]
+    __shared__ float s_win[kWinSlots];          // the brick's staged rows
+    __shared__ uint32_t s_has[2][kHasWords];    // presence bits, by brick parity
     __shared__ float s_x[4][NG][32];
-    __shared__ float s_tab[kViTabs * kViDict];
     __shared__ double s_abs[kMatMax];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1420,112 +1432,156 @@ __global__ void __launch_bounds__(kNT) step_spmv_grouped_vi(const StepInst *__re
     const GLB int32_t *grow = gp(I.grp_row);
     const GLB uint8_t *vidx = gp(I.vi_idx);
     const GLB int32_t *src_tile = gp(I.src_tile);
-    const CST GroupDesc *grp = cst(I.grp);
-    const CST int32_t *gfast = cst(I.grp_fast);
-    const CST uint32_t *gsrc = cst(I.grp_src);
+    const GLB i4 *fd4 = (const GLB i4 *)gp(I.vi_fdesc);
+    const GLB uint32_t *srcf = gp(I.grp_src_f);
+    const CST int32_t *bptr = cst(I.brick_ptr);
+    const CST int32_t *borg = cst(I.brick_org);
+    const int32_t nx = I.grid_nx, ny = I.grid_ny;
+    const int64_t plane = (int64_t)nx * ny;
     for (int q = threadIdx.x; q < I.n_mat; q += kNT) s_abs[q] = gp(I.absorb)[q];
     for (int q = threadIdx.x; q < I.vi_ntab * kViDict; q += kNT) s_tab[q] = gp(I.vi_dict)[q];
+    for (int q = threadIdx.x; q < 2 * kHasWords; q += kNT) (&s_has[0][0])[q] = 0u;
     __syncthreads();
 
     const int R = I.rows_per_tile;
-    const int64_t G = I.n_fast;
+    const int64_t NB = I.n_brick;
+    int parity = 0;
     for (int64_t wi = wk.begin; wi < wk.end; wi += wk.stride) {
         const int64_t c = work[wi].chunk;
-        const int64_t c_b = c * G / n_work, c_e = (c + 1) * G / n_work;
-        const int64_t g_b = c_b + wave * (c_e - c_b) / 4, g_e = c_b + (wave + 1) * (c_e - c_b) / 4;
+        const int64_t b_b = c * NB / n_work, b_e = (c + 1) * NB / n_work;
         double sN = 0.0, sE = 0.0, sA = 0.0;
         float mx = 0.0f;
-        if (g_b < g_e) {
-            int64_t id[NG];
-            GroupDesc D[NG];
-            uint32_t w[NG];
+        for (int64_t bk = b_b; bk < b_e; ++bk) {
+            uint32_t *has = s_has[parity];
+            const int64_t f0 = bptr[bk], f1 = bptr[bk + 1];
+            const int64_t per = (f1 - f0 + 3) / 4;
+            const int64_t g_b = f0 + wave * per, g_e = min(g_b + per, f1);
+            // the window's first voxel: the brick's origin - (1, 1, 1)
+            const int64_t w0 = (int64_t)borg[bk] - 1 - nx - plane;
+            if (g_b < g_e) {
+                // per pass, the NG groups' {first member, member count, first
+                // column, group} (lane q holds group q mod NG) and the
+                // source-bit words of fast indices g2 (even lanes) and
+                // g2 + NG - 1 (odd lanes), by vector loads issued a pass
+                // ahead: no scalar loads in the loop, whose waits would also
+                // hold the LDS reads
+                i4 nd = fd4[min(g_b + (lane % NG), g_e - 1)];
+                uint32_t nsw = srcf[(g_b + ((lane & 1) ? NG - 1 : 0)) >> 5];
+                for (int64_t g2 = g_b; g2 < g_e; g2 += NG) {
+                    const i4 cd = nd;
+                    const uint32_t csw = nsw;
+                    // (unconditional: past the range it reloads the last
+                    // group, so the loads need no branch and the waits count
+                    // exactly)
+                    nd = fd4[min(g2 + NG + (lane % NG), g_e - 1)];
+                    nsw = srcf[min(g2 + NG + ((lane & 1) ? NG - 1 : 0), g_e - 1) >> 5];
+                    const uint32_t sw0 = (uint32_t)__builtin_amdgcn_readlane((int)csw, 0);
+                    const uint32_t sw1 = (uint32_t)__builtin_amdgcn_readlane((int)csw, 1);
+                    // every pair's loads first, then the sums in pair order
+                    u32x4 sl[NP][2];
+                    float xm[NP];
+                    int32_t r[NP];
+                    int mt[NP], nmv[NP], cs[NP];
+                    bool gsb[NP];
 #pragma unroll
-            for (int q = 0; q < NG; ++q) {
-                id[q] = gfast[min(g_b + q, g_e - 1)];
-                D[q] = load_desc(grp + id[q]);
-                w[q] = gsrc[id[q] >> 5];
-            }
-            for (int64_t g2 = g_b; g2 < g_e; g2 += NG) {
-                int64_t ci[NG];
-                GroupDesc C[NG];
-                uint32_t cw[NG];
-#pragma unroll
-                for (int q = 0; q < NG; ++q) {
-                    ci[q] = id[q];
-                    C[q] = D[q];
-                    cw[q] = w[q];
-                }
-                if (g2 + NG < g_e) {
-#pragma unroll
-                    for (int q = 0; q < NG; ++q) {
-                        id[q] = gfast[min(g2 + NG + q, g_e - 1)];
-                        D[q] = load_desc(grp + id[q]);
-                        w[q] = gsrc[id[q] >> 5];
+                    for (int p = 0; p < NP; ++p) {
+                        const int m0 = h ? __builtin_amdgcn_readlane(cd[0], 2 * p + 1)
+                                         : __builtin_amdgcn_readlane(cd[0], 2 * p);
+                        const int nm = h ? __builtin_amdgcn_readlane(cd[1], 2 * p + 1)
+                                         : __builtin_amdgcn_readlane(cd[1], 2 * p);
+                        const int cstart = h ? __builtin_amdgcn_readlane(cd[2], 2 * p + 1)
+                                             : __builtin_amdgcn_readlane(cd[2], 2 * p);
+                        const int64_t fi = g2 + 2 * p + h;
+                        const uint32_t swd = ((fi >> 5) == (g2 >> 5)) ? sw0 : sw1;
+                        gsb[p] = (swd >> (fi & 31)) & 1u;
+                        nmv[p] = nm;
+                        cs[p] = cstart;
+                        const int jm = min(m, nm - 1);
+                        r[p] = grow[m0 + jm];
+                        mt[p] = gmat[m0 + jm];
+                        xm[p] = X[cstart + min(m, kSpmmUnroll - 1)];
+                        // this half's group is fast group g2 + 2p + h (the
+                        // last one again past the wave's range)
+                        const int64_t f = min(g2 + 2 * p + h, g_e - 1);
+                        const GLB u32x4 *slot = (const GLB u32x4 *)(vidx + f * kViBlock + (int64_t)jm * kViSlot);
+                        sl[p][0] = __builtin_nontemporal_load(slot);
+                        sl[p][1] = __builtin_nontemporal_load(slot + 1);
                     }
-                }
-                // every pair's loads first, then the sums in pair order
-                u32x4 sl[NP][2];
-                float xm[NP];
-                int32_t r[NP];
-                int mt[NP], nmv[NP];
-                bool gsb[NP];
 #pragma unroll
-                for (int p = 0; p < NP; ++p) {
-                    const GroupDesc &A0 = C[2 * p], &A1 = C[2 * p + 1];
-                    const int nm = h ? A1.nm : A0.nm;
-                    const int m0 = h ? A1.m0 : A0.m0, cstart = h ? A1.cstart : A0.cstart;
-                    gsb[p] = h ? ((cw[2 * p + 1] >> (ci[2 * p + 1] & 31)) & 1u) : ((cw[2 * p] >> (ci[2 * p] & 31)) & 1u);
-                    nmv[p] = nm;
-                    const int jm = min(m, nm - 1);
-                    r[p] = grow[m0 + jm];
-                    mt[p] = gmat[m0 + jm];
-                    xm[p] = X[cstart + min(m, kSpmmUnroll - 1)];
-                    // this half's group is fast group g2 + 2p + h (the last
-                    // one again past the wave's range)
-                    const int64_t f = min(g2 + 2 * p + h, g_e - 1);
-                    const GLB u32x4 *slot = (const GLB u32x4 *)(vidx + f * kViBlock + (int64_t)jm * kViSlot);
-                    sl[p][0] = __builtin_nontemporal_load(slot);
-                    sl[p][1] = __builtin_nontemporal_load(slot + 1);
-                }
+                    for (int p = 0; p < NP; ++p) {
+                        float *sx = s_x[wave][2 * p + h];
+                        sx[m] = xm[p];
+                        const uint32_t wd[8] = {sl[p][0][0], sl[p][0][1], sl[p][0][2], sl[p][0][3],
+                                                sl[p][1][0], sl[p][1][1], sl[p][1][2], sl[p][1][3]};
+                        const float *tab = s_tab + ((wd[kViTabByte >> 2] >> (8 * (kViTabByte & 3))) & 0xff) * kViDict;
+                        float acc = 0.0f;
 #pragma unroll
-                for (int p = 0; p < NP; ++p) {
-                    float *sx = s_x[wave][2 * p + h];
-                    sx[m] = xm[p];
-                    const uint32_t wd[8] = {sl[p][0][0], sl[p][0][1], sl[p][0][2], sl[p][0][3],
-                                            sl[p][1][0], sl[p][1][1], sl[p][1][2], sl[p][1][3]};
-                    const float *tab = s_tab + ((wd[kViTabByte >> 2] >> (8 * (kViTabByte & 3))) & 0xff) * kViDict;
-                    float acc = 0.0f;
-#pragma unroll
-                    for (int k = 0; k < kSpmmUnroll; ++k) acc += tab[(wd[k >> 2] >> (8 * (k & 3))) & 0xff] * sx[k];
-                    if (g2 + 2 * p + h < g_e && m < nmv[p]) {
-                        const int32_t rr = r[p];
-                        float v = acc * scale;
-                        if (gsb[p]) {
-                            const int tile = rr / R;
-                            const int sb = src_tile[tile], se = src_tile[tile + 1];
-                            if (sb < se) {
-                                int e2 = lower_bound_rows<int32_t>(I.src_row, sb, se, rr);
-                                double s = 0.0;
-                                bool any = false;
-                                for (; e2 < se && I.src_row[e2] == rr; ++e2) {
-                                    s += I.src_w[e2] * I.amp[t * I.n_src + I.src_id[e2]];
-                                    any = true;
+                        for (int k = 0; k < kSpmmUnroll; ++k)
+                            acc += tab[(wd[k >> 2] >> (8 * (k & 3))) & 0xff] * sx[k];
+                        if (g2 + 2 * p + h < g_e && m < nmv[p]) {
+                            const int32_t rr = r[p];
+                            float v = acc * scale;
+                            if (gsb[p]) {
+                                const int tile = rr / R;
+                                const int sb = src_tile[tile], se = src_tile[tile + 1];
+                                if (sb < se) {
+                                    int e2 = lower_bound_rows<int32_t>(I.src_row, sb, se, rr);
+                                    double s = 0.0;
+                                    bool any = false;
+                                    for (; e2 < se && I.src_row[e2] == rr; ++e2) {
+                                        s += I.src_w[e2] * I.amp[t * I.n_src + I.src_id[e2]];
+                                        any = true;
+                                    }
+                                    if (any) v += (float)ldexp(s, -sc.En);
                                 }
-                                if (any) v += (float)ldexp(s, -sc.En);
                             }
-                        }
-                        Y[rr] = v;
-                        if (rr < I.n_states) {
-                            sN += (double)v;
-                            sA += s_abs[mt[p]] * (double)v;
-                            mx = fmaxf(mx, v);
-                        } else {
-                            sE += (double)v;
+                            bool staged = false;
+                            if (rr < I.n_states) {
+                                sN += (double)v;
+                                sA += s_abs[mt[p]] * (double)v;
+                                mx = fmaxf(mx, v);
+                                // the row (u + e_d, d) of source voxel u, d = rr mod 26:
+                                // its slot in the brick's window
+                                const int32_t vd = rr / 26, d = rr - 26 * vd;
+                                const int kk = d + (d >= 13 ? 1 : 0);
+                                const int ex = kk % 3 - 1, ey = (kk / 3) % 3 - 1, ez = kk / 9 - 1;
+                                const int32_t u = cs[p] / 26;
+                                const int pos =
+                                    (wd[kViPosByte >> 2] >> (8 * (kViPosByte & 3))) & (kBrick * kBrick * kBrick - 1);
+                                const int lx = pos % kBrick + 1 + ex, ly = (pos / kBrick) % kBrick + 1 + ey,
+                                          lz = pos / (kBrick * kBrick) + 1 + ez;
+                                if ((int64_t)vd == (int64_t)u + ex + (int64_t)ey * nx + (int64_t)ez * plane &&
+                                    w0 + lx + (int64_t)ly * nx + (int64_t)lz * plane == (int64_t)vd) {
+                                    const int slot = ((lz * kWin + ly) * kWin + lx) * 26 + d;
+                                    s_win[slot] = v;
+                                    atomicOr(&has[slot >> 5], 1u << (slot & 31));
+                                    staged = true;
+                                }
+                            } else {
+                                sE += (double)v;
+                            }
+                            if (!staged) Y[rr] = v;
                         }
                     }
                 }
             }
+            __syncthreads();
+            // the window in address order: slot s is row 26 v + d of window
+            // voxel v = s / 26; clear the other parity's bits for the next brick
+            uint32_t *nxt = s_has[parity ^ 1];
+            for (int q = threadIdx.x; q < kHasWords; q += kNT) nxt[q] = 0u;
+            for (int s = threadIdx.x; s < kWinSlots; s += kNT) {
+                if ((has[s >> 5] >> (s & 31)) & 1u) {
+                    const int vw = s / 26, d = s - 26 * vw;
+                    const int lx = vw % kWin, ly = (vw / kWin) % kWin, lz = vw / (kWin * kWin);
+                    const int64_t vd = w0 + lx + (int64_t)ly * nx + (int64_t)lz * plane;
+                    Y[vd * 26 + d] = s_win[s];
+                }
+            }
+            __syncthreads();
+            parity ^= 1;
         }
+        // the wave's totals over its groups, in a fixed butterfly
         const double wN = wave_sum(sN), wE = wave_sum(sE), wA = wave_sum(sA), wM = wave_max((double)mx);
         if (lane == 0) {
             const int64_t nc = I.n_chunks, b = 4 * c + wave;
@@ -2857,8 +2913,9 @@ hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int6
         if (variant == DRTS_SPMV_GROUPED) {
             // the fast groups, then the listed rows, the two-voxel rows, the detectors
             if (vi)
-                hipLaunchKernelGGL(step_spmv_grouped_vi<kGroupPairsVi>, g1, dim3(kNT), 0, stream, insts_dev, work_dev,
-                                   n_work, remap, xcd_bounds);
+                hipLaunchKernelGGL(step_spmv_grouped_vi<kGroupPairsVi>, g1, dim3(kNT),
+                                   (size_t)vi * kViDict * sizeof(float), stream, insts_dev, work_dev, n_work, remap,
+                                   xcd_bounds);
             else
                 hipLaunchKernelGGL(step_spmv_grouped<kGroupPairs>, g1, dim3(kNT), 0, stream, insts_dev, work_dev,
                                    n_work, remap, xcd_bounds);
