@@ -330,11 +330,14 @@ __global__ void __launch_bounds__(256) vi_insert(const GroupDesc *desc, const in
 
 // Slot j of fast group f: member j's values as indices into its dictionary
 // (sorted bit patterns: an exact match by binary search), the dictionary at
-// byte kViTabByte, zeros elsewhere (and for j >= the member count).
+// byte kViTabByte, the group's position in its brick at byte kViPosByte and
+// the member's row in word kViRowWord (for j >= the member count: no
+// indices, the last member's row).
 __global__ void __launch_bounds__(256) vi_encode(const GroupDesc *desc, const int32_t *fast, int64_t n_fast,
-                                                 const float *gval, const uint8_t *mat_of_voxel, int n_dir, int nx,
-                                                 int ny, const uint32_t *dict_bits, const int32_t *dict_n,
-                                                 uint8_t *idx, int32_t *missing)
+                                                 const float *gval, const int32_t *grp_row,
+                                                 const uint8_t *mat_of_voxel, int n_dir, int nx, int ny,
+                                                 const uint32_t *dict_bits, const int32_t *dict_n, uint8_t *idx,
+                                                 int32_t *missing)
 {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= n_fast * 26) return;
@@ -364,6 +367,7 @@ __global__ void __launch_bounds__(256) vi_encode(const GroupDesc *desc, const in
     const int64_t x = u % nx, y = (u / nx) % ny, z = u / ((int64_t)nx * ny);
     const uint32_t pos = (uint32_t)(((z % kBrick) * kBrick + (y % kBrick)) * kBrick + (x % kBrick));
     w[kViPosByte >> 2] |= pos << (8 * (kViPosByte & 3));
+    w[kViRowWord] = (uint32_t)grp_row[D.m0 + min(j, D.nm - 1)];
     uint4 *out = (uint4 *)(idx + f * kViBlock + (int64_t)j * kViSlot);
     out[0] = make_uint4(w[0], w[1], w[2], w[3]);
     out[1] = make_uint4(w[4], w[5], w[6], w[7]);
@@ -453,7 +457,8 @@ int build_value_index(Matrix &A)
     const int64_t nt = A.n_fast * 26;
     hipLaunchKernelGGL(vi_encode, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, dev.stream,
                        A.grp_desc.as<GroupDesc>(), A.grp_fast.as<int32_t>(), A.n_fast, A.grp_val.as<float>(),
-                       A.mat_of_voxel.as<uint8_t>(), A.model.n_dir, A.model.nx, A.model.ny, dbits.as<uint32_t>(),
+                       A.grp_row.as<int32_t>(), A.mat_of_voxel.as<uint8_t>(), A.model.n_dir, A.model.nx, A.model.ny,
+                       dbits.as<uint32_t>(),
                        dcount.as<int32_t>(), A.vi_idx.as<uint8_t>(), flags.as<int32_t>() + 1);
     DRTS_HIP(hipGetLastError());
     DRTS_HIP(hipMemcpyAsync(fl, flags.ptr, sizeof fl, hipMemcpyDeviceToHost, dev.stream));

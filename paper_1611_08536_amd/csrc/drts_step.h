@@ -167,6 +167,7 @@ constexpr int kViDict = 256;
 constexpr int kViTabs = 16;
 constexpr int kViHash = 4096;            // slots of a dictionary's build-time hash set
 constexpr int kViPosByte = 27;           // slot byte: the group's position in its brick
+constexpr int kViRowWord = 7;            // slot word (bytes 28..31): the member's row
 // value-indexed fast groups are ordered in bricks of kBrick^3 source voxels;
 // a workgroup forms a brick's groups and stages the rows they write into the
 // brick's window of (kBrick + 2)^3 destination voxels in LDS, then writes the

@@ -1392,8 +1392,8 @@ __global__ void __launch_bounds__(kNT) step_spmv_grouped(const StepInst *__restr
 
 // The fast groups with value-indexed values, by bricks.  Lane m reads its
 // member's slot (kViSlot bytes: its entries as one-byte indices, the
-// dictionary's number, the group's position in its brick) with two 16-byte
-// loads and takes each value from the dictionary in LDS -- the same FP32
+// dictionary's number, the group's position in its brick, its row) with two
+// 16-byte loads and takes each value from the dictionary in LDS -- the same FP32
 // values, so the same products, order and y bit for bit, from a quarter of
 // the bytes.  A work item is a range of bricks; the workgroup forms one brick
 // at a time (its groups split among the waves, two pairs of groups issued per
@@ -1429,7 +1429,6 @@ __global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(5, 8))
     const GLB float *X = gp((const float *)((t & 1) ? I.buf1 : I.buf0));
     GLB float *Y = gpw((float *)((t & 1) ? I.buf0 : I.buf1));
     const GLB uint8_t *gmat = gp(I.grp_mat);
-    const GLB int32_t *grow = gp(I.grp_row);
     const GLB uint8_t *vidx = gp(I.vi_idx);
     const GLB int32_t *src_tile = gp(I.src_tile);
     const GLB i4 *fd4 = (const GLB i4 *)gp(I.vi_fdesc);
@@ -1497,7 +1496,6 @@ __global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(5, 8))
                         nmv[p] = nm;
                         cs[p] = cstart;
                         const int jm = min(m, nm - 1);
-                        r[p] = grow[m0 + jm];
                         mt[p] = gmat[m0 + jm];
                         xm[p] = X[cstart + min(m, kSpmmUnroll - 1)];
                         // this half's group is fast group g2 + 2p + h (the
@@ -1506,6 +1504,7 @@ __global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(5, 8))
                         const GLB u32x4 *slot = (const GLB u32x4 *)(vidx + f * kViBlock + (int64_t)jm * kViSlot);
                         sl[p][0] = __builtin_nontemporal_load(slot);
                         sl[p][1] = __builtin_nontemporal_load(slot + 1);
+                        r[p] = (int32_t)sl[p][1][kViRowWord - 4];   // the member's row, from its slot
                     }
 #pragma unroll
                     for (int p = 0; p < NP; ++p) {
