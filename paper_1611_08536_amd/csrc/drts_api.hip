@@ -172,6 +172,7 @@ struct drts_solver {
     bool profile = false;
     bool grouped = false;        // the CSR step runs by row groups
     bool group_pending = false;  // grouped step asked for, the matrix's groups not built yet
+    bool fast_src = false;       // a fast group holds a source row
     bool no_group = false;       // a batch member: the tiled step
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
@@ -628,9 +629,19 @@ int prepare(drts_solver *S)
         if ((rc = S->grp_src.allocate(&dev, (size_t)((A.n_groups + 31) / 32 + 1) * sizeof(uint32_t)))) return rc;
         if ((rc = group_flags(A, sr.as<int64_t>(), (int64_t)srows.size(), S->grp_src.as<uint32_t>(), dev.stream)))
             return rc;
+        S->fast_src = false;
         if (A.vi_ntab > 0) {
-            if ((rc = S->grp_src_f.allocate(&dev, (size_t)((A.n_fast + 31) / 32 + 1) * sizeof(uint32_t)))) return rc;
+            const size_t words = (size_t)((A.n_fast + 31) / 32 + 1);
+            if ((rc = S->grp_src_f.allocate(&dev, words * sizeof(uint32_t)))) return rc;
+            DRTS_HIP(hipMemsetAsync(S->grp_src_f.ptr, 0, words * sizeof(uint32_t), dev.stream));
             if ((rc = fast_flags(A, S->grp_src.as<uint32_t>(), S->grp_src_f.as<uint32_t>(), dev.stream))) return rc;
+            // whether any fast group holds a source row (the step leaves the
+            // source code out when none does)
+            std::vector<uint32_t> fw(words);
+            DRTS_HIP(hipMemcpyAsync(fw.data(), S->grp_src_f.ptr, words * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                    dev.stream));
+            DRTS_HIP(hipStreamSynchronize(dev.stream));
+            for (uint32_t x : fw) S->fast_src = S->fast_src || x != 0u;
         }
         DRTS_HIP(hipStreamSynchronize(dev.stream));
     }
@@ -901,7 +912,8 @@ int launch_one(drts_solver *S, hipStream_t stream, const StepInst *inst = nullpt
                                A.model.value_type == DRTS_F64, A.rp64 ? 1 : 0, spmm ? (S->grouped ? 2 : 1) : 0, S->grid,
                                (S->opt.xcd_remap ? 1 : 0) | ((variant & 15) << 1), S->xcd_bounds.as<int64_t>(),
                                S->opt.rows_per_tile, S->n_det, queue, stream, S->grouped ? A.n_slow : 0,
-                               S->grouped && !spmm ? A.n_vox2 : 0, S->grouped && !spmm ? A.vi_ntab : 0);
+                               S->grouped && !spmm ? A.n_vox2 : 0,
+                               S->grouped && !spmm && A.vi_ntab > 0 ? A.vi_ntab | (S->fast_src ? 0x100 : 0) : 0);
     }
     if (e != hipSuccess) return set_error(DRTS_E_HIP, "step launch failed: %s", hipGetErrorString(e));
     if (e1) DRTS_HIP(hipEventRecord(e1, stream));

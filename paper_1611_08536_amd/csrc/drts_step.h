@@ -205,7 +205,8 @@ struct alignas(16) GroupDesc {
 // xcd_bounds[i] .. xcd_bounds[i+1]-1 (kXcdBounds entries), else equal counts.
 // n_slow, n_vox2: with the grouped single-rhs step, the rows it takes one by
 // one from the CSR and its two-voxel rows; vi: the number of dictionaries of
-// its value-indexed fast groups (0: FP32 values).
+// its value-indexed fast groups (0: FP32 values), plus 0x100 when a fast
+// group holds a source row.
 hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int64_t n_work, int n_inst,
                        int n_rhs_max, int value_f64, int rp64, int spmm, int grid, int xcd_remap,
                        const int64_t *xcd_bounds, int rows_per_tile, int n_det_max, int32_t *queue,

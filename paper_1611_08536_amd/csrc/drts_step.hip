@@ -1401,11 +1401,12 @@ __global__ void __launch_bounds__(kNT) step_spmv_grouped(const StepInst *__restr
 // the brick's window of kWin^3 voxels -- in LDS, with a presence bit; after a
 // barrier it writes the window out in address order (consecutive lanes,
 // consecutive rows: few lines per store), then the next brick.  Escape rows
-// and rows whose index is not (u + e_m, m) are stored directly.
+// and rows whose index is not (u + e_m, m) are stored directly.  SRC: some
+// fast group holds a source row (else the source code is left out).
 constexpr int kGroupPairsVi = 2;   // pairs of groups a wave forms per pass
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-template <int NP>
+template <int NP, bool SRC>
 __global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(5, 8))) step_spmv_grouped_vi(const StepInst *__restrict__ insts,
                                                              const WorkItem *__restrict__ work, int64_t n_work,
                                                              int xcd_remap, const int64_t *__restrict__ xcd_bounds)
@@ -1520,7 +1521,7 @@ __global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(5, 8))
                         if (g2 + 2 * p + h < g_e && m < nmv[p]) {
                             const int32_t rr = r[p];
                             float v = acc * scale;
-                            if (gsb[p]) {
+                            if (SRC && gsb[p]) {
                                 const int tile = rr / R;
                                 const int sb = src_tile[tile], se = src_tile[tile + 1];
                                 if (sb < se) {
@@ -2911,10 +2912,14 @@ hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int6
         const int remap = xcd_remap & 1;
         if (variant == DRTS_SPMV_GROUPED) {
             // the fast groups, then the listed rows, the two-voxel rows, the detectors
-            if (vi)
-                hipLaunchKernelGGL(step_spmv_grouped_vi<kGroupPairsVi>, g1, dim3(kNT),
-                                   (size_t)vi * kViDict * sizeof(float), stream, insts_dev, work_dev, n_work, remap,
-                                   xcd_bounds);
+            // vi: dictionaries in bits 0-7, bit 8: a fast group holds a source row
+            const size_t tab_lds = (size_t)(vi & 0xff) * kViDict * sizeof(float);
+            if (vi & 0x100)
+                hipLaunchKernelGGL((step_spmv_grouped_vi<kGroupPairsVi, true>), g1, dim3(kNT), tab_lds, stream,
+                                   insts_dev, work_dev, n_work, remap, xcd_bounds);
+            else if (vi)
+                hipLaunchKernelGGL((step_spmv_grouped_vi<kGroupPairsVi, false>), g1, dim3(kNT), tab_lds, stream,
+                                   insts_dev, work_dev, n_work, remap, xcd_bounds);
             else
                 hipLaunchKernelGGL(step_spmv_grouped<kGroupPairs>, g1, dim3(kNT), 0, stream, insts_dev, work_dev,
                                    n_work, remap, xcd_bounds);

@@ -80,6 +80,9 @@ def _workload(med, k, steps, seed):
         if j % 3 == 0:
             # a second source row of the same voxel (another direction) feeds the same rhs
             srcs.append(W.point_source(x, y, 0, d=(1, 0, 1), rhs=j, w=0.5))
+        # an interior source: its row is a member of a full lattice group
+        # (the face rows above are empty rows, taken one by one)
+        srcs.append(W.point_source(x, y, med.nz // 2, d=(0, 1, 1), rhs=j, w=0.25))
     dets = []
     if med.directions == "lattice26" and med.bc == "vacuum":
         dets = [W.face_escape_detector(med, "top"), W.face_escape_detector(med, "bottom", 1, med.nx - 2)]
