@@ -133,17 +133,21 @@ def spmv_bytes(nnz, n_rows, n_states, val_bytes=4):
 def grouped_bytes(n_rows, n_states, g):
     """Bytes the step by row groups must move (g: the matrix's groups info).
     Members of fast groups (26 entries a row): their values in group order
-    (4 per entry; value-indexed: a 32-byte slot of one-byte indices), row id
-    (4) and material (1), per fast group its
-    descriptor (32), list entry (4) and source bit.  Two-voxel rows: their
+    (4 per entry), row id (4) and material (1), per fast group its
+    descriptor (32), list entry (4) and source bit; value-indexed, a 32-byte
+    slot (indices and row) and the material (1) per member, 16 per group and
+    its source bit.  Two-voxel rows: their
     52 values (4 each) and their info (16).  Listed rows: their CSR entries
     (8 per entry), row pointer (4), material (1) and list entry (4).  x once,
     y once."""
     fast_rows = n_rows - g["n_vox2_rows"] - g["n_list_rows"]
-    # value-indexed: a 32-byte slot per member (26 one-byte indices, the
-    # dictionary's number, padding); else 26 FP32 values
-    vals = 32 * fast_rows if g.get("value_tables", 0) > 0 else 4 * 26 * fast_rows
-    fast = vals + 5 * fast_rows + 36 * g["n_fast"] + (g["n_groups"] + 7) // 8
+    if g.get("value_tables", 0) > 0:
+        # a 32-byte slot per member (26 one-byte indices, the dictionary's
+        # number, the brick position, the member's row) and its material; a
+        # 16-byte descriptor per fast group and its source bit
+        fast = 33 * fast_rows + 16 * g["n_fast"] + (g["n_fast"] + 7) // 8
+    else:
+        fast = 4 * 26 * fast_rows + 5 * fast_rows + 36 * g["n_fast"] + (g["n_groups"] + 7) // 8
     vox2 = (4 * 52 + 16) * g["n_vox2_rows"]
     listed = 8 * g["n_list_entries"] + 9 * g["n_list_rows"]
     return fast + vox2 + listed + 4 * n_states + 4 * n_rows
@@ -653,10 +657,10 @@ def main():
                      "format_frac": None if fbytes is None else
                      round(fbytes / (avg_kernel_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
                      "format_bytes_basis": "what the step by row groups must move: fast groups' values (one-byte "
-                                           "dictionary indices in a 32-byte slot per member when value-indexed, "
-                                           "else FP32 in group order), members' rows and materials, descriptors; "
-                                           "two-voxel rows' values and info; the listed rows' CSR entries; x and "
-                                           "y once",
+                                           "dictionary indices and the row in a 32-byte slot per member when "
+                                           "value-indexed, else FP32 in group order and the row), members' "
+                                           "materials, descriptors; two-voxel rows' values and info; the listed "
+                                           "rows' CSR entries; x and y once",
                      "note": "the step streams fewer bytes than the CSR count (no columns; value-indexed "
                              "entries), so frac can exceed 1; format_frac is the fraction of peak on the "
                              "bytes the step must move",

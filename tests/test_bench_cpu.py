@@ -95,9 +95,12 @@ def test_grouped_bytes_against_the_csr_count(bench):
     # 7 more two-voxel rows
     v2 = bench.grouped_bytes(R + 7, n_states, dict(g, n_vox2_rows=7))
     assert v2 - fast == 4 * 7 + (4 * 52 + 16) * 7
-    # value-indexed fast groups: 32 bytes a member instead of 104
+    # value-indexed fast groups: a 32-byte slot (indices and row) and the
+    # material a member, 16 bytes and a bit a group
     vi = bench.grouped_bytes(R, n_states, dict(g, value_tables=3))
-    assert fast - vi == (104 - 32) * R
+    n_g = n_vox + 100
+    assert fast - vi == (104 + 5 - 33) * R + (36 - 16) * n_g
+
 
 
 def test_traffic_by_kernel_names_and_scales(bench, tmp_path):
