@@ -964,7 +964,7 @@ int ensure_graph(drts_solver *S, int K)
 drts_options_t default_options(const drts_solver *S)
 {
     // defaults measured on MI355X: one rhs on the 128^3 three-layer workload
-    // (FP32: by row groups, work items of 256-row tiles x 32; FP64: the
+    // (FP32: by row groups, work items of 256-row tiles x 16; FP64: the
     // tiled step, 4 tiles per chunk; 64 workgroups per CU launched: the
     // surplus waits and gives dynamic balance; round-robin walk), 64 rhs on
     // the 96^3 slab (by row groups; work items of 64-row tiles x 32, 32
@@ -973,7 +973,7 @@ drts_options_t default_options(const drts_solver *S)
     drts_options_t o{};
     o.kernel = DRTS_KERNEL_CSR;
     o.rows_per_tile = spmm_of(S) ? 64 : 256;
-    o.tiles_per_chunk = spmm_of(S) ? 32 : (f64 ? 4 : 32);
+    o.tiles_per_chunk = spmm_of(S) ? 32 : (f64 ? 4 : 16);
     o.grid = device_cu_count() * (spmm_of(S) ? 32 : 64);
     o.xcd_remap = 0;
     o.graph_steps = 0;
