@@ -30,7 +30,7 @@ F64SUM_NOTE = ("FP32 values and state, each row summed in FP64 and rounded once:
 STEP_SOURCES = ("paper_1611_08536_amd/csrc/drts_step.hip", "paper_1611_08536_amd/csrc/drts_step.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_spmv_grouped_c2_traffic.txt")
 # the kernels of one headline step launch (the finalize aside): the fast
-# groups, the row list of the other groups, the detector sums
+# groups, the row list, the two-voxel rows, the detector sums
 STEP_KERNELS = ("step_spmv_grouped_vi", "step_spmv_rowlist", "step_spmv_vox2", "spmv_detectors")
 CALIB_KERNEL = "vectorized_elementwise_kernel"
 CALIB_BYTES = 2 ** 30          # the calibration kernel reads and writes 1 GiB
