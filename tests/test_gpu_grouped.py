@@ -189,3 +189,22 @@ def test_grouped_spmv_launch_shapes(opts):
     assert np.array_equal(a["x"].view(np.uint32), b["x"].view(np.uint32))
     assert np.array_equal(a["exp2"], b["exp2"])
     assert np.allclose(a["det"], b["det"], rtol=1e-13, atol=0)
+
+
+def test_grouped_spmv_wide_planes_keep_group_order():
+    """Planes too wide for the brick order (400 x 400 voxels: consecutive
+    fast groups of a brick would lie beyond the FP32 step's 32-bit value
+    offsets): no bricks, so no value indexing; the FP32 grouped step in group
+    order equals the tiled step bit for bit."""
+    med = W.homogeneous(400, _mat(), nz=3)
+    wl = W.Workload("wide", med, [W.point_source(200, 200, 1, d=(0, 1, 1))], [], 6, 1, "f32", "dither", 1.4)
+    a = solve.run(wl, options={"variant": drts.SPMV_GROUPED})
+    g = a["matrix"].groups()
+    print("400 x 400 x 3:", g, flush=True)
+    assert g["n_fast"] > 0 and g["value_tables"] == 0
+    b = solve.run(wl, matrix=a["matrix"], options={"variant": drts.SPMV_LDS})
+    assert np.array_equal(a["x"].view(np.uint32), b["x"].view(np.uint32))
+    assert np.array_equal(a["exp2"], b["exp2"])
+    assert np.allclose(a["tot"], b["tot"], rtol=1e-13, atol=0)
+    for o in (a, b):
+        o["solver"].close()
