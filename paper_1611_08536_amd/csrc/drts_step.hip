@@ -1223,22 +1223,22 @@ __global__ void __launch_bounds__(kNT) spmm_detectors(const StepInst *__restrict
 //
 // The row groups and the group-order arrays of the many-rhs step.  The fast
 // groups -- full lattice rows, kSpmmUnroll columns in one run, nearly every
-// group -- go to step_spmv_grouped, whose lanes are the members: each
-// half-wave takes a group (lane m of the half is member m), so a wave forms a
-// pair of groups per half-wave pass; it issues the loads of kGroupPairs pairs
-// before it forms the first (more bytes in flight per wave), and the
-// descriptors of its next pairs load while the current ones are formed.
-// Lane m loads x at column m of the run
-// into LDS, then its own entries with one load per k (the group's values are
-// column-major, so a group's k-th entries are one contiguous run) and adds
-// entry * x over k in column order: the CSR step's products in its order, so
-// y equals its y bit for bit.  The matrix stream is the values alone (no
-// columns) and x is read once per group.  The rows of the other groups
-// (interface rows whose entries come from two voxels, a few members each)
-// go to step_spmv_rowlist, a thread per row.  Work items of the fast groups
-// are split among the waves as in the many-rhs step (partials of index
-// 4c + wave), those of the row list follow; the detector sums are left to
-// spmv_detectors.
+// group -- go to step_spmv_grouped_vi when their values are value-indexed,
+// else to step_spmv_grouped, whose lanes are the members: each half-wave
+// takes a group (lane m of the half is member m), so a wave forms a pair of
+// groups per half-wave pass; it issues the loads of kGroupPairs pairs before
+// it forms the first (more bytes in flight per wave), and the descriptors of
+// its next pairs load while the current ones are formed.  Lane m loads x at
+// column m of the run into LDS, then its own entries with one load per k (the
+// group's values are column-major, so a group's k-th entries are one
+// contiguous run) and adds entry * x over k in column order: the CSR step's
+// products in its order, so y equals its y bit for bit.  The matrix stream
+// is the values alone (no columns) and x is read once per group.  Two-voxel
+// rows (interface rows whose entries come from two voxels) go to
+// step_spmv_vox2, every other row to step_spmv_rowlist, a thread per row.
+// Work items of the fast groups are split among the waves as in the many-rhs
+// step (partials of index 4c + wave), those of the row list and of the
+// two-voxel rows follow; the detector sums are left to spmv_detectors.
 // ---------------------------------------------------------------------------
 constexpr int kGroupPairs = 2;   // pairs of groups a wave forms per iteration
 
