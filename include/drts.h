@@ -265,7 +265,9 @@ int drts_build_matrix(const drts_medium_t *medium, const drts_device_t *dev, drt
 /* Sizes of an assembled matrix; any output pointer may be NULL.  bytes = device
  * bytes of the CSR (row pointers, columns, values) and, once a solo solver
  * has asked for the grouped step, of the row groups (descriptors, members'
- * rows and materials, values in group order); dt_s in seconds. */
+ * rows and materials, values in group order, the fast and listed rows, the
+ * two-voxel rows' copy, the value-indexed slots, dictionaries and bricks);
+ * dt_s in seconds. */
 int drts_matrix_info(const drts_matrix_t *A, int64_t *n_states, int64_t *n_escape, int64_t *nnz,
                      int64_t *bytes, double *dt_s);
 
