@@ -200,15 +200,21 @@ def spmm_vs_plain(torch, steps=20):
     from paper_1611_08536_amd import drts, solve
     wl = W.c3(n_steps=steps + 4)
     A = drts.Matrix(wl.medium, wl.value_type, wl.rounding, wl.n_ref)
-    S = drts.Solver(A, wl.n_rhs, wl.detectors, max_steps=2 * steps + 8)
+    S = drts.Solver(A, wl.n_rhs, wl.detectors, max_steps=3 * steps + 12)
     tab = solve.source_table(A, wl)
     S.run(tab, 2)
     S.profile(True)
     t_mm = _timed(lambda: S.run(tab, steps), torch)
     n_l, k_ms = S.profile_stats()
+    # the same step with FP64 row sums
+    S.set_options(variant=drts.SPMM_GROUPED_F64SUM)
+    S.run(tab, 2)
+    S.profile(True)
+    t_s64 = _timed(lambda: S.run(tab, steps), torch)
+    n_s, s_ms = S.profile_stats()
     # the matrix-free many-rhs step (FP64 row sums) on the same solver
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    S.set_options(kernel=drts.KERNEL_STRUCTURED_F64SUM, grid=16 * cus)
+    S.set_options(kernel=drts.KERNEL_STRUCTURED_F64SUM, variant=drts.SPMM_GROUPED, grid=16 * cus)
     S.run(tab, 2)
     S.profile(True)
     t_mf = _timed(lambda: S.run(tab, steps), torch)
@@ -237,6 +243,12 @@ def spmm_vs_plain(torch, steps=20):
     mf_s = f_ms / max(n_f, 1) * 1e-3
     mf_bytes = 4 * k * A.n_states + 4 * k * A.n_rows + A.n_states // 26
     out["precision"] = "FP32 values, state and accumulation (CSR SpMM)"
+    s64_s = s_ms / max(n_s, 1) * 1e-3
+    out["f64sum"] = {"kernel": "step_spmm_grouped<int32, FP64 row sums> + spmm_detectors",
+                     "precision": "FP32 values and state, each row summed in FP64 and rounded once",
+                     "ms_per_step": round(t_s64 / steps * 1e3, 3), "kernel_ms": round(s64_s * 1e3, 3),
+                     "achieved_GBs": round(nbytes / s64_s / 1e9, 1),
+                     "frac": round(nbytes / s64_s / 1e9 / PEAK_HBM_GBS, 4)}
     out["matrix_free"] = {"kernel": "step_struct_mm<2> + step_struct_mm_x<2> (FP64 row sums)",
                           "precision": F64SUM_NOTE,
                           "ms_per_step": round(t_mf / steps * 1e3, 3), "kernel_ms": round(mf_s * 1e3, 3),
@@ -280,8 +292,7 @@ def batch_vs_sequential(torch, steps=40):
     solvers = [drts.Solver(m, 1, [], max_steps=2 * steps + 4) for m in mats]
     tabs = [solve.source_table(m, w) for m, w in zip(mats, wls)]
     B = drts.Batch(solvers)
-    keys = ("rows_per_tile", "tiles_per_chunk", "variant", "grid", "xcd_remap")
-    defaults = [{k: S.options[k] for k in keys} for S in solvers]
+    n_own = sum(m.n_rows >= drts.BATCH_OWN_ROWS for m in mats)
     _log("C4: autotuning the batch's launch shape")
     t0 = time.perf_counter()
     chosen = B.autotune()
@@ -289,13 +300,17 @@ def batch_vs_sequential(torch, steps=40):
     B.run(tabs, [2] * len(solvers))
     t_b = _timed(lambda: B.run(tabs, [steps] * len(solvers)), torch)
     B.close()
-    # the sequential runs keep each solver's own default shape
-    for S, d in zip(solvers, defaults):
-        S.set_options(**d)
+    for S in solvers:
+        S.close()
+    # the same media stepped one after another by fresh solvers with their
+    # default step (by row groups)
+    solvers = [drts.Solver(m, 1, [], max_steps=steps + 4) for m in mats]
 
     def seq():
         for S, t in zip(solvers, tabs):
             S.run(t, steps)
+    for S, t in zip(solvers, tabs):
+        S.run(t, 2)
     t_s = _timed(seq, torch)
     nnz = sum(m.nnz for m in mats)
     for S in solvers:
@@ -341,9 +356,11 @@ def batch_vs_sequential(torch, steps=40):
             "solves_per_s": round(n * steps / t_b / 500, 3),
             "sequential_solves_per_s": round(n * steps / t_s / 500, 3),
             "GNNZ_per_s": round(nnz * steps / t_b / 1e9, 1),
-            "batch_shape": "autotuned in %.1f s: %d rows per tile, %d tiles per chunk, variant %d, %d workgroups" %
-                           (t_tune, chosen["rows_per_tile"], chosen["tiles_per_chunk"], chosen["variant"],
-                            chosen["grid"]),
+            "batch_shape": "%d members of at least %d rows on their own grouped step, %d in the shared tiled "
+                           "launch, its shape autotuned in %.1f s: %d rows per tile, %d tiles per chunk, variant %d, "
+                           "%d workgroups" % (n_own, drts.BATCH_OWN_ROWS, n - n_own, t_tune, chosen["rows_per_tile"],
+                                              chosen["tiles_per_chunk"], chosen["variant"], chosen["grid"]),
+            "sequential": "fresh solvers with their default step (by row groups), one after another",
             "precision": "FP32 values, state and accumulation (CSR)",
             "matrix_free": {"kernel": "step_struct_dm<2, true> + step_struct_x<float, 2, true> (FP64 row sums)",
                             "precision": F64SUM_NOTE,

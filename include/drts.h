@@ -341,7 +341,8 @@ typedef struct {
                              swept in z (its x gathers stay in its L2) */
     int32_t graph_steps;  /* steps captured per hipGraph replay (0 = eager) */
     int32_t rescale;      /* 1 = power-of-two rescale every step (default) */
-    int32_t variant;      /* n_rhs > 1: DRTS_SPMM_GROUPED or DRTS_SPMM_ROWS;
+    int32_t variant;      /* n_rhs > 1: DRTS_SPMM_GROUPED, DRTS_SPMM_ROWS or
+                             DRTS_SPMM_GROUPED_F64SUM;
                              one rhs: DRTS_SPMV_ROW, DRTS_SPMV_LDS or
                              DRTS_SPMV_GROUPED (below) */
     int32_t queue;        /* one rhs only: 1 = workgroups take chunks from a
@@ -357,9 +358,9 @@ typedef struct {
  * once and the values from a group-order copy the matrix keeps once a solo
  * solver asks for it; two-voxel rows (two runs) take a thread each over a
  * compact copy of their values, every other row a thread over its CSR entries
- * (drts_matrix_groups counts them).  Batch members take DRTS_SPMV_LDS, and so
- * does a matrix whose rows do not group.  All give the same state bit for
- * bit. */
+ * (drts_matrix_groups counts them).  Batch members of the shared launch
+ * take DRTS_SPMV_LDS, and so does a matrix whose rows do not group.  All give
+ * the same state bit for bit. */
 #define DRTS_SPMV_ROW 0
 #define DRTS_SPMV_LDS 1
 #define DRTS_SPMV_GROUPED 2
@@ -367,9 +368,18 @@ typedef struct {
  * pull from one source voxel) share one gather of their right-hand-side rows
  * (the default; the library takes the row-by-row step for a matrix whose
  * rows do not group, at least two rows a group on average), or every row
- * gathers its own.  Both give the same result bit for bit. */
+ * gathers its own.  Both give the same result bit for bit, and each column
+ * equals the single-rhs step's.  DRTS_SPMM_GROUPED_F64SUM is the step by row
+ * groups with each row summed in FP64 (one fma per term in column order; the
+ * product of two FP32 numbers is exact there) and rounded once to FP32: the
+ * FP32 accumulation error no longer builds up over long runs (the rounding of
+ * the stored values and of the state stays).  It needs rows that group:
+ * drts_solver_set_options builds the matrix's groups when they are not built
+ * yet, and returns DRTS_E_INVALID (options unchanged) when its rows do not
+ * group or hold several hundred entries. */
 #define DRTS_SPMM_GROUPED 0
 #define DRTS_SPMM_ROWS 1
+#define DRTS_SPMM_GROUPED_F64SUM 2
 
 /* Creates the time-stepping state for n_rhs right-hand sides sharing A: the
  * state (zero), detectors, series buffers for max_steps steps.  n_rhs > 1
@@ -465,27 +475,32 @@ void drts_solver_destroy(drts_solver_t *S);
 /* ---- uneven batch: independent solvers in one persistent launch --------------- */
 
 /* Groups n single-rhs FP32 solvers (different matrices and sizes) so that one
- * launch per step advances all of them.  Each solver keeps its own state,
- * exponent and series; results equal those of the solver run alone, bit for
- * bit.  The solvers must outlive the batch. */
+ * launch per step advances all of them.  A CSR member of at least 1536 * 1024
+ * rows whose options ask for the step by row groups (the default) fills the
+ * device by itself: it keeps that step, launched on the batch's stream in the
+ * same graph replays; the others take the tiled step and share one launch.
+ * Each solver keeps its own state, exponent and series; results equal those
+ * of the solver run alone with the same step, bit for bit.  The solvers must
+ * outlive the batch. */
 int drts_batch_create(drts_solver_t *const *solvers, int32_t n, const drts_device_t *dev,
                       drts_batch_t **out);
 
 /* Advances solver i by n_steps[i] steps (0 = idle) with source table src[i];
  * solvers that finish drop out of later launches.  Every member must use the
  * same step (DRTS_E_INVALID otherwise): the CSR step (kernel option
- * DRTS_KERNEL_CSR, the same rows_per_tile for all), or the matrix-free step
+ * DRTS_KERNEL_CSR, the same rows_per_tile for the members of the shared
+ * launch), or the matrix-free step
  * with direction-major tiles (DRTS_KERNEL_STRUCTURED on nearest-rounded
  * values, or DRTS_KERNEL_STRUCTURED_F64SUM; at most 8 materials), whose two
  * kernels then each cover every member in one launch per step. */
 int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const int64_t *n_steps);
 
-/* Chooses one launch shape for the whole batch (rows per tile, tiles per
+/* Chooses one shape for the batch's shared launch (rows per tile, tiles per
  * chunk, kernel variant, workgroups of the step launch) by timing a few
- * steps of every member at once for each candidate, then restores every
- * member's state and control words and keeps the fastest shape in all
+ * steps of its members at once for each candidate, then restores every
+ * member's state and control words and keeps the fastest shape in those
  * members' options (chosen, may be NULL, receives it; its grid is the
- * batch's).  Before the first step of every member (DRTS_E_STATE otherwise)
+ * batch's); members with their own grouped step keep their options.  Before the first step of every member (DRTS_E_STATE otherwise)
  * and for CSR members only (DRTS_E_INVALID otherwise); results stay equal to
  * solo runs with the same options, bit for bit. */
 int drts_batch_autotune(drts_batch_t *B, drts_options_t *chosen);

@@ -187,6 +187,7 @@ struct drts_batch {
     Buffer sas_dev, xwork_dev;   // matrix-free members: their arguments, their irregular-row items
     int grid = 0;                // workgroups of the step launch; 0: 16 per CU
     int mode = 0;                // 0: CSR step; 1 or 2: the matrix-free mode of every member
+    int lead = 0;                // a member of the shared launch: its options give the launch's
     // graphs of the last run, destroyed once the stream has passed them
     std::vector<hipGraphExec_t> spent;
     hipEvent_t done = nullptr;   // recorded after the last run's launches
@@ -593,11 +594,15 @@ int prepare(drts_solver *S)
     // (settle_groups), not here: batch members never use them.
     S->grouped = false;
     S->group_pending = false;
+    const bool f64sum = spmm_of(S) && o.kernel == DRTS_KERNEL_CSR && o.variant == DRTS_SPMM_GROUPED_F64SUM;
     if (!S->no_group && o.kernel == DRTS_KERNEL_CSR &&
-        (spmm_of(S) ? o.variant == DRTS_SPMM_GROUPED : o.variant == DRTS_SPMV_GROUPED) && !long_rows(A)) {
+        (spmm_of(S) ? o.variant != DRTS_SPMM_ROWS : o.variant == DRTS_SPMV_GROUPED) && !long_rows(A)) {
         if (A.n_groups < 0) S->group_pending = true;
         else S->grouped = A.n_groups > 0;
     }
+    if (f64sum && !S->grouped && !S->group_pending)
+        return set_error(DRTS_E_INVALID, "DRTS_SPMM_GROUPED_F64SUM needs rows that group (and are not several "
+                                         "hundred entries long)");
     // a work item of the many-rhs matrix-free step is one tile (kStructVoxPerChunk
     // voxels); its kernels, and the step by row groups, keep one set of
     // partials per workgroup
@@ -909,7 +914,9 @@ int launch_one(drts_solver *S, hipStream_t stream, const StepInst *inst = nullpt
     } else {
     const int variant = spmv_variant(S);
     e = launch_step(insts, S->work_dev.as<WorkItem>(), S->n_chunks, 1, S->n_rhs,
-                               A.model.value_type == DRTS_F64, A.rp64 ? 1 : 0, spmm ? (S->grouped ? 2 : 1) : 0, S->grid,
+                               A.model.value_type == DRTS_F64, A.rp64 ? 1 : 0,
+                               spmm ? (S->grouped ? (S->opt.variant == DRTS_SPMM_GROUPED_F64SUM ? 3 : 2) : 1) : 0,
+                               S->grid,
                                (S->opt.xcd_remap ? 1 : 0) | ((variant & 15) << 1), S->xcd_bounds.as<int64_t>(),
                                S->opt.rows_per_tile, S->n_det, queue, stream, S->grouped ? A.n_slow : 0,
                                S->grouped && !spmm ? A.n_vox2 : 0,
@@ -1009,8 +1016,10 @@ int check_options(const drts_solver *S, const drts_options_t *o)
     }
     if (o->queue != 0 && o->queue != 1) return set_error(DRTS_E_INVALID, "queue must be 0 or 1");
     if (o->xcd_remap < 0 || o->xcd_remap > 2) return set_error(DRTS_E_INVALID, "xcd_remap must be 0, 1 or 2");
-    if (S->n_rhs > 1 && o->variant != DRTS_SPMM_GROUPED && o->variant != DRTS_SPMM_ROWS)
-        return set_error(DRTS_E_INVALID, "variant %d: many rhs take DRTS_SPMM_GROUPED or DRTS_SPMM_ROWS",
+    if (S->n_rhs > 1 && o->variant != DRTS_SPMM_GROUPED && o->variant != DRTS_SPMM_ROWS &&
+        o->variant != DRTS_SPMM_GROUPED_F64SUM)
+        return set_error(DRTS_E_INVALID,
+                         "variant %d: many rhs take DRTS_SPMM_GROUPED, DRTS_SPMM_ROWS or DRTS_SPMM_GROUPED_F64SUM",
                          o->variant);
     if (o->variant < DRTS_SPMV_ROW || o->variant > DRTS_SPMV_GROUPED)
         return set_error(DRTS_E_INVALID, "unknown variant %d", o->variant);
@@ -1326,6 +1335,15 @@ int drts_solver_set_options(drts_solver_t *S, const drts_options_t *opt)
     if (!S || !opt) return set_error(DRTS_E_INVALID, "NULL argument");
     int rc = check_options(S, opt);
     if (rc) return rc;
+    if (S->n_rhs > 1 && opt->kernel == DRTS_KERNEL_CSR && opt->variant == DRTS_SPMM_GROUPED_F64SUM) {
+        // decided now, so that a matrix whose rows do not group leaves the
+        // options as they were
+        const Matrix &A = S->A->m;
+        if (!long_rows(A) && A.n_groups < 0 && (rc = row_groups(A))) return rc;
+        if (long_rows(A) || A.n_groups <= 0)
+            return set_error(DRTS_E_INVALID, "DRTS_SPMM_GROUPED_F64SUM needs rows that group (and are not "
+                                             "several hundred entries long)");
+    }
     S->opt = *opt;
     return prepare(S);
 }
@@ -1635,7 +1653,7 @@ void release_spent(drts_batch *B)
 int batch_launch(drts_batch *B, int64_t n_work, int n_inst, int rows_per_tile, hipStream_t stream,
                  int64_t n_xwork = 0)
 {
-    const drts_solver *S0 = B->solvers[0];
+    const drts_solver *S0 = B->solvers[(size_t)B->lead];
     const int grid = B->grid > 0 ? B->grid : device_cu_count() * 16;
     int32_t *queue = (B->mode == 0 && S0->opt.queue) ? B->queue.as<int32_t>() : nullptr;
     hipError_t e;
@@ -1656,6 +1674,21 @@ int batch_launch(drts_batch *B, int64_t n_work, int n_inst, int rows_per_tile, h
     return DRTS_OK;
 }
 
+// A CSR member of at least this many rows takes its own step by row groups
+// inside the batch instead of the shared tiled launch.  Measured on one
+// MI355X (homogeneous cubes, graph-replayed steps): a solo grouped step costs
+// about 60 us of launches plus about 10 ns per thousand rows, while in the
+// shared launch a member costs its CSR bytes at about 4.5 TB/s, some 47 ns
+// per thousand rows; the two meet near 1.5 million rows.
+constexpr int64_t kBatchOwnRows = 1536 * 1024;
+
+// A member that runs its own grouped step (its rows group and its options ask
+// for that step); the others share the batch's launch.
+bool batch_own(const drts_solver *S)
+{
+    return !S->no_group && (S->grouped || S->group_pending);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1674,11 +1707,13 @@ int drts_batch_create(drts_solver_t *const *solvers, int32_t n, const drts_devic
         for (int j = 0; j < i; ++j)
             if (solvers[j] == S) return set_error(DRTS_E_INVALID, "solver %d appears twice", i);
     }
-    // batch members take the tiled step (their instances share one launch)
+    // small members take the tiled step (their instances share one launch);
+    // members large enough to fill the device keep the step by row groups
     for (int i = 0; i < n; ++i) {
         drts_solver *S = solvers[i];
-        S->no_group = true;
-        if (S->grouped || S->group_pending) {
+        const bool no_group = S->A->m.model.n_rows < kBatchOwnRows;
+        if (S->no_group != no_group) {
+            S->no_group = no_group;
             const int e = prepare(S);
             if (e) return e;
         }
@@ -1703,9 +1738,8 @@ int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const
 {
     if (!B || !n_steps) return set_error(DRTS_E_INVALID, "NULL argument");
     const int n = (int)B->solvers.size();
-    std::vector<int> order;
+    std::vector<int> order, own;   // members of the shared launch; members with their own grouped step
     int rc;
-    const int rpt = B->solvers[0]->opt.rows_per_tile;
     // every member runs the CSR step (step -1), or every member the
     // matrix-free step in the same direction-major mode (1 or 2)
     auto step_of = [](const drts_solver *S) { return structured_of(S) ? structured_mode(S) : -1; };
@@ -1721,30 +1755,63 @@ int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const
             return set_error(DRTS_E_INVALID, "solver %d: every batch member needs the same step (kernel option)", i);
         if (mode != 0 && (S->sa.seg_len != kStructDmSeg || S->sa.n_mat > kStructMatLdsHost))
             return set_error(DRTS_E_INVALID, "solver %d: matrix-free tiles of another shape", i);
-        if (mode == 0 && S->opt.rows_per_tile != rpt)
-            return set_error(DRTS_E_INVALID, "solver %d: every batch member needs the same rows_per_tile", i);
         if (mode == 0 && !S->A->m.has_csr)
             return set_error(DRTS_E_STATE, "solver %d: the CSR step needs the matrix's CSR arrays", i);
-        if (mode == 0 && long_rows(S->A->m) != long_rows(B->solvers[0]->A->m))
-            return set_error(DRTS_E_INVALID, "solver %d: a batch takes either long-row (Lebedev) members or "
-                                             "lattice members", i);
         if (n_steps[i] < 0 || S->t_host + n_steps[i] > S->max_steps)
             return set_error(DRTS_E_RANGE, "solver %d: steps beyond max_steps", i);
+    }
+    // the members of the shared launch need one shape: the first one's
+    int lead = -1;
+    for (int i = 0; i < n; ++i) {
+        const drts_solver *S = B->solvers[i];
+        if (mode == 0 && batch_own(S)) continue;
+        if (lead < 0) {
+            lead = i;
+            continue;
+        }
+        const drts_solver *L = B->solvers[(size_t)lead];
+        if (mode == 0 && S->opt.rows_per_tile != L->opt.rows_per_tile)
+            return set_error(DRTS_E_INVALID, "solver %d: every batch member needs the same rows_per_tile", i);
+        if (mode == 0 && long_rows(S->A->m) != long_rows(L->A->m))
+            return set_error(DRTS_E_INVALID, "solver %d: a batch takes either long-row (Lebedev) members or "
+                                             "lattice members", i);
+    }
+    for (int i = 0; i < n; ++i) {
+        drts_solver *S = B->solvers[i];
         if (n_steps[i] == 0) continue;
         if ((rc = set_sources(S, src ? src[i] : nullptr))) return rc;
+        const bool mine = mode == 0 && batch_own(S);
+        if (mine && (rc = settle_groups(S))) return rc;
         if ((rc = upload_amplitudes(S, src ? src[i] : nullptr, S->t_host, n_steps[i]))) return rc;
-        order.push_back(i);
+        // a member whose rows turned out not to group joins the shared launch
+        // when it has the shared shape
+        if (mine && !S->grouped && lead >= 0 &&
+            S->opt.rows_per_tile != B->solvers[(size_t)lead]->opt.rows_per_tile)
+            return set_error(DRTS_E_INVALID, "solver %d: every batch member needs the same rows_per_tile", i);
+        (mine && S->grouped ? own : order).push_back(i);
     }
-    if (order.empty()) return DRTS_OK;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n_steps[a] > n_steps[b]; });
-    const int P = (int)order.size();
-    std::vector<StepInst> insts((size_t)P);
+    if (order.empty() && own.empty()) return DRTS_OK;
+    auto longer = [&](int a, int b) { return n_steps[a] > n_steps[b]; };
+    std::stable_sort(order.begin(), order.end(), longer);
+    std::stable_sort(own.begin(), own.end(), longer);
+    B->lead = order.empty() ? 0 : order[0];
+    const int rpt = B->solvers[(size_t)B->lead]->opt.rows_per_tile;
+    // instances: the shared launch's (0..P-1), then the own-step members'
+    // (their step limits are restored with the others')
+    const int P = (int)order.size(), Q = (int)own.size(), T = P + Q;
+    std::vector<drts_solver *> all;
+    for (int i : order) all.push_back(B->solvers[(size_t)i]);
+    for (int i : own) all.push_back(B->solvers[(size_t)i]);
+    std::vector<StepInst> insts((size_t)T);
     std::vector<StructArgs> sas;
     std::vector<WorkItem> work, xwork;
-    std::vector<int64_t> prefix((size_t)P), xprefix((size_t)P), tend((size_t)P);
-    for (int j = 0; j < P; ++j) {
-        drts_solver *S = B->solvers[(size_t)order[(size_t)j]];
+    std::vector<int64_t> prefix((size_t)P), xprefix((size_t)P), tend((size_t)T), len_of((size_t)T);
+    for (int j = 0; j < T; ++j) {
+        drts_solver *S = all[(size_t)j];
         insts[(size_t)j] = S->inst_h;
+        len_of[(size_t)j] = n_steps[j < P ? order[(size_t)j] : own[(size_t)(j - P)]];
+        tend[(size_t)j] = S->t_host + len_of[(size_t)j];
+        if (j >= P) continue;
         for (int64_t c = 0; c < S->n_chunks; ++c) work.push_back({j, (int32_t)c});
         if (mode != 0) {
             sas.push_back(S->sa);
@@ -1753,13 +1820,12 @@ int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const
         }
         prefix[(size_t)j] = (int64_t)work.size();
         xprefix[(size_t)j] = (int64_t)xwork.size();
-        tend[(size_t)j] = S->t_host + n_steps[order[(size_t)j]];
     }
     B->mode = mode;
     Device &dev = B->dev;
     hipStream_t s = dev.stream;
-    for (int j = 0; j < P; ++j) {
-        drts_solver *S = B->solvers[(size_t)order[(size_t)j]];
+    for (int j = 0; j < T; ++j) {
+        drts_solver *S = all[(size_t)j];
         // every solver's own stream work (uploads) must be done before the batch stream uses it
         DRTS_HIP(hipStreamSynchronize(S->dev.stream));
         DRTS_HIP(hipMemcpyAsync(S->t_end.ptr, &tend[(size_t)j], sizeof(int64_t), hipMemcpyHostToDevice, s));
@@ -1773,24 +1839,34 @@ int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const
     DRTS_HIP(hipStreamSynchronize(s));
     release_spent(B);   // the previous run's graphs are done
 
-    // launches: while step < n of the j-th longest, the first j+1 solvers are active
+    // launches: while step < the length of the j-th longest, the first j+1
+    // members of each list are active
     const int K = 25;
     hipStream_t cap = nullptr;
     int64_t step = 0;
-    const int64_t n_max = n_steps[order[0]];
+    const int64_t n_max = std::max(P ? len_of[0] : 0, Q ? len_of[(size_t)P] : 0);
     while (step < n_max) {
-        int active = 0;
-        while (active < P && n_steps[order[(size_t)active]] > step) ++active;
-        const int64_t seg_end = n_steps[order[(size_t)active - 1]];   // active set constant until here
-        const int64_t n_work = prefix[(size_t)active - 1];
-        const int64_t n_xwork = xprefix[(size_t)active - 1];
+        int active = 0, active_own = 0;
+        while (active < P && len_of[(size_t)active] > step) ++active;
+        while (active_own < Q && len_of[(size_t)(P + active_own)] > step) ++active_own;
+        // both active sets stay constant until the first of their members ends
+        int64_t seg_end = n_max;
+        if (active) seg_end = std::min(seg_end, len_of[(size_t)active - 1]);
+        if (active_own) seg_end = std::min(seg_end, len_of[(size_t)(P + active_own - 1)]);
+        const int64_t n_work = active ? prefix[(size_t)active - 1] : 0;
+        const int64_t n_xwork = active ? xprefix[(size_t)active - 1] : 0;
+        auto one_step = [&](hipStream_t st) {
+            int r = active ? batch_launch(B, n_work, active, rpt, st, n_xwork) : DRTS_OK;
+            for (int j = 0; j < active_own && r == DRTS_OK; ++j) r = launch_one(all[(size_t)(P + j)], st);
+            return r;
+        };
         int64_t len = seg_end - step;
         if (len >= 2 * K) {
             if (!cap) DRTS_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
             hipGraph_t g = nullptr;
             hipGraphExec_t ge = nullptr;
             DRTS_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-            for (int k = 0; k < K && rc == DRTS_OK; ++k) rc = batch_launch(B, n_work, active, rpt, cap, n_xwork);
+            for (int k = 0; k < K && rc == DRTS_OK; ++k) rc = one_step(cap);
             hipError_t e = hipStreamEndCapture(cap, &g);
             if (rc == DRTS_OK && e != hipSuccess) rc = set_error(DRTS_E_HIP, "capture: %s", hipGetErrorString(e));
             if (rc == DRTS_OK && hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess)
@@ -1803,7 +1879,7 @@ int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const
             if (rc) break;
         }
         for (; len > 0; --len, ++step)
-            if ((rc = batch_launch(B, n_work, active, rpt, s, n_xwork))) break;
+            if ((rc = one_step(s))) break;
         if (rc) break;
     }
     if (cap) (void)hipStreamDestroy(cap);
@@ -1812,30 +1888,24 @@ int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const
         // own step limit, its step count as the device has it)
         (void)hipStreamSynchronize(s);
         release_spent(B);
-        for (int j = 0; j < P; ++j) {
-            drts_solver *S = B->solvers[(size_t)order[(size_t)j]];
+        for (drts_solver *S : all) {
             int64_t tt = S->t_host;
             (void)hipMemcpy(S->t_end.ptr, &S->max_steps, sizeof(int64_t), hipMemcpyHostToDevice);
             if (hipMemcpy(&tt, S->ctl_t.ptr, sizeof(int64_t), hipMemcpyDeviceToHost) == hipSuccess) S->t_host = tt;
         }
         return rc;
     }
-    for (int j = 0; j < P; ++j) {
-        drts_solver *S = B->solvers[(size_t)order[(size_t)j]];
-        S->t_host += n_steps[order[(size_t)j]];
-    }
+    for (int j = 0; j < T; ++j) all[(size_t)j]->t_host += len_of[(size_t)j];
     // the solvers' own step limits come back after the batch's launches, in
     // stream order: the call returns without waiting for the steps
-    hipLaunchKernelGGL(restore_t_end, dim3((unsigned)((P + 63) / 64)), dim3(64), 0, s, B->inst_dev.as<StepInst>(), P);
+    hipLaunchKernelGGL(restore_t_end, dim3((unsigned)((T + 63) / 64)), dim3(64), 0, s, B->inst_dev.as<StepInst>(), T);
     DRTS_HIP(hipGetLastError());
     // work a member's own stream takes later (readout, its own steps) waits for
     // the batch
     if (!B->done) DRTS_HIP(hipEventCreateWithFlags(&B->done, hipEventDisableTiming));
     DRTS_HIP(hipEventRecord(B->done, s));
-    for (int j = 0; j < P; ++j) {
-        drts_solver *S = B->solvers[(size_t)order[(size_t)j]];
+    for (drts_solver *S : all)
         if (S->dev.stream != s) DRTS_HIP(hipStreamWaitEvent(S->dev.stream, B->done, 0));
-    }
     return DRTS_OK;
 }
 
@@ -1851,12 +1921,29 @@ int drts_batch_autotune(drts_batch_t *B, drts_options_t *chosen)
     B->mode = 0;
     Device &dev = B->dev;
     hipStream_t s = dev.stream;
+    // members with their own grouped step keep their options: the shape is
+    // chosen for the shared launch (groups built now, so that the split is
+    // final)
+    int rc = DRTS_OK;
+    std::vector<int> shared;
+    for (int i = 0; i < n; ++i) {
+        drts_solver *S = B->solvers[(size_t)i];
+        if (batch_own(S) && (rc = settle_groups(S))) return rc;
+        if (!(batch_own(S) && S->grouped)) shared.push_back(i);
+    }
+    const int cus = device_cu_count();
+    if (shared.empty()) {
+        if (chosen) {
+            *chosen = B->solvers[0]->opt;
+            chosen->grid = B->grid > 0 ? B->grid : cus * 16;
+        }
+        return DRTS_OK;
+    }
     // every member's state and control words (exponent, maximum, absorbed
     // sum at t = 0), restored afterwards
     std::vector<Buffer> save((size_t)n);
     std::vector<int32_t> save_E((size_t)n);
     std::vector<double> save_M((size_t)n), save_abs((size_t)n);
-    int rc = DRTS_OK;
     for (int i = 0; i < n && !rc; ++i) {
         drts_solver *S = B->solvers[(size_t)i];
         DRTS_HIP(hipStreamSynchronize(S->dev.stream));
@@ -1869,8 +1956,8 @@ int drts_batch_autotune(drts_batch_t *B, drts_options_t *chosen)
     }
     if (rc) return rc;
     DRTS_HIP(hipStreamSynchronize(s));
-    const int cus = device_cu_count();
-    const drts_solver *S0 = B->solvers[0];
+    B->lead = shared[0];
+    const drts_solver *S0 = B->solvers[(size_t)B->lead];
     int64_t min_steps = INT64_MAX;
     for (const drts_solver *S : B->solvers) min_steps = std::min(min_steps, S->max_steps);
     const int steps = (int)std::max<int64_t>(1, std::min<int64_t>(3, min_steps - 1));
@@ -1889,12 +1976,14 @@ int drts_batch_autotune(drts_batch_t *B, drts_options_t *chosen)
         for (const drts_solver *S : B->solvers) o.push_back(S->opt);
         return o;
     }();
-    // one candidate's options on every member, the batch lists for all members
-    std::vector<StepInst> insts((size_t)n);
+    // one candidate's options on every member of the shared launch, its lists
+    const int n_sh = (int)shared.size();
+    std::vector<StepInst> insts((size_t)n_sh);
     std::vector<WorkItem> work;
     auto apply = [&](const Cand &c) -> int {
         work.clear();
-        for (int i = 0; i < n; ++i) {
+        for (int j = 0; j < n_sh; ++j) {
+            const int i = shared[(size_t)j];
             drts_solver *S = B->solvers[(size_t)i];
             drts_options_t o = orig[(size_t)i];
             o.rows_per_tile = c.rpt;
@@ -1905,8 +1994,8 @@ int drts_batch_autotune(drts_batch_t *B, drts_options_t *chosen)
             if (e) return e;
             S->opt = o;
             if ((e = prepare(S))) return e;
-            insts[(size_t)i] = S->inst_h;
-            for (int64_t k = 0; k < S->n_chunks; ++k) work.push_back({i, (int32_t)k});
+            insts[(size_t)j] = S->inst_h;
+            for (int64_t k = 0; k < S->n_chunks; ++k) work.push_back({j, (int32_t)k});
         }
         B->grid = c.grid;
         int e = upload_vec(dev, B->inst_dev, insts);
@@ -1915,7 +2004,7 @@ int drts_batch_autotune(drts_batch_t *B, drts_options_t *chosen)
     };
     std::vector<int64_t> zero_t((size_t)n, 0);
     auto reset_t = [&]() -> int {
-        for (int i = 0; i < n; ++i)
+        for (int i : shared)
             DRTS_HIP(hipMemcpyAsync(B->solvers[(size_t)i]->ctl_t.ptr, &zero_t[(size_t)i], sizeof(int64_t),
                                     hipMemcpyHostToDevice, s));
         return DRTS_OK;
@@ -1929,13 +2018,13 @@ int drts_batch_autotune(drts_batch_t *B, drts_options_t *chosen)
         if ((rc = apply(c))) break;
         const int64_t n_work = (int64_t)work.size();
         if ((rc = reset_t())) break;
-        if ((rc = batch_launch(B, n_work, n, c.rpt, s))) break;   // warm-up
+        if ((rc = batch_launch(B, n_work, n_sh, c.rpt, s))) break;   // warm-up
         if ((rc = reset_t())) break;
         if (hipEventRecord(e0, s) != hipSuccess) {
             rc = set_error(DRTS_E_HIP, "hipEventRecord failed");
             break;
         }
-        for (int k = 0; k < steps && !rc; ++k) rc = batch_launch(B, n_work, n, c.rpt, s);
+        for (int k = 0; k < steps && !rc; ++k) rc = batch_launch(B, n_work, n_sh, c.rpt, s);
         if (rc) break;
         float ms = 0.f;
         if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -1963,7 +2052,7 @@ int drts_batch_autotune(drts_batch_t *B, drts_options_t *chosen)
     DRTS_HIP(hipStreamSynchronize(s));
     if (rc) {
         // leave the members as they were
-        for (int i = 0; i < n; ++i) {
+        for (int i : shared) {
             B->solvers[(size_t)i]->opt = orig[(size_t)i];
             (void)prepare(B->solvers[(size_t)i]);
         }
@@ -1973,7 +2062,7 @@ int drts_batch_autotune(drts_batch_t *B, drts_options_t *chosen)
     if ((rc = apply(best))) return rc;
     DRTS_HIP(hipStreamSynchronize(s));
     if (chosen) {
-        *chosen = B->solvers[0]->opt;
+        *chosen = B->solvers[(size_t)B->lead]->opt;
         chosen->grid = best.grid;
     }
     return DRTS_OK;
@@ -1990,14 +2079,21 @@ void drts_batch_destroy(drts_batch_t *B)
 
 // ---- autotuning ----------------------------------------------------------------------
 
+static bool f64sum_spmm(const drts_solver *S)
+{
+    return S->n_rhs > 1 && S->opt.kernel == DRTS_KERNEL_CSR && S->opt.variant == DRTS_SPMM_GROUPED_F64SUM;
+}
+
 static std::string tune_key(const drts_solver *S)
 {
     const Matrix &A = S->A->m;
     const int rows_cls = (int)std::lround(std::log2((double)std::max<int64_t>(A.model.n_rows, 1)));
     const int nnz_row = (int)std::lround((double)A.nnz / std::max<int64_t>(A.model.n_rows, 1));
     char buf[128];
-    snprintf(buf, sizeof buf, "drts2:rhs%d:f%d:rows2^%d:nnzrow%d:cu%d", S->n_rhs,
-             A.model.value_type == DRTS_F64 ? 64 : 32, rows_cls, nnz_row, device_cu_count());
+    // the FP64-sum SpMM gives other results: its shapes are cached apart
+    snprintf(buf, sizeof buf, "drts2:rhs%d:f%d%s:rows2^%d:nnzrow%d:cu%d", S->n_rhs,
+             A.model.value_type == DRTS_F64 ? 64 : 32, f64sum_spmm(S) ? "s64" : "", rows_cls, nnz_row,
+             device_cu_count());
     return buf;
 }
 
@@ -2023,7 +2119,7 @@ int drts_autotune(drts_solver_t *S, const char *cache_path, drts_options_t *chos
                     best.tiles_per_chunk = c;
                     best.grid = g;
                     best.xcd_remap = x;
-                    best.variant = pl;
+                    best.variant = f64sum_spmm(S) ? DRTS_SPMM_GROUPED_F64SUM : pl;
                     hit = true;
                 }
             }
@@ -2061,7 +2157,7 @@ int drts_autotune(drts_solver_t *S, const char *cache_path, drts_options_t *chos
                         o.tiles_per_chunk = spmm ? c * 32 : c;
                         o.grid = cus * (spmm ? g / 2 : g);
                         o.xcd_remap = x;
-                        o.variant = pl;
+                        o.variant = f64sum_spmm(S) ? DRTS_SPMM_GROUPED_F64SUM : pl;
                         cands.push_back(o);
                     }
     const int steps = (int)std::min<int64_t>(4, S->max_steps);

@@ -200,7 +200,8 @@ struct alignas(16) GroupDesc {
 // queue (may be NULL): a zeroed device counter from which the SpMV workgroups
 // take work items; the finalize kernel resets it.
 // spmm: 0 = one rhs, 1 = many rhs row by row, 2 = many rhs by row groups
-// (work item c takes groups c * n_groups / n_chunks onwards).
+// (work item c takes groups c * n_groups / n_chunks onwards), 3 = as 2 with
+// each row summed in FP64 and rounded once to FP32.
 // xcd_bounds (may be NULL): with the XCD-aware walk, XCD i takes work items
 // xcd_bounds[i] .. xcd_bounds[i+1]-1 (kXcdBounds entries), else equal counts.
 // n_slow, n_vox2: with the grouped single-rhs step, the rows it takes one by

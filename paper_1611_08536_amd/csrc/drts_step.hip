@@ -21,6 +21,8 @@
 // XCD-aware order: with xcd_remap the work list is cut into 8 contiguous
 // ranges and the workgroups dispatched to one XCD (round robin by workgroup
 // id) walk one range, so each XCD's L2 holds one moving window of x.
+#include <type_traits>
+
 #include "drts_internal.h"
 #include "drts_step.h"
 
@@ -1020,6 +1022,10 @@ template <typename P> __device__ __forceinline__ GroupDesc load_desc(P p)
 // once per step instead of once per entry.  A member is formed with the same
 // products in the same column order as in the row-by-row kernel and the
 // single-rhs step, so every column of the result equals theirs bit for bit.
+// With F64S each member's row is instead summed in FP64 (one fma per term, in
+// column order: the products of two FP32 numbers are exact in FP64) and
+// rounded once to FP32, which keeps the FP32 accumulation error from building
+// up over long runs.
 // Groups whose rows are not kSpmmUnroll long are formed row by row (windows
 // of 64 entries).  Sources are looked up only in groups the solver flagged.
 //
@@ -1029,8 +1035,8 @@ template <typename P> __device__ __forceinline__ GroupDesc load_desc(P p)
 // takes which item.  The detector sums are left to spmm_detectors, which
 // reads the stored rows.
 // ---------------------------------------------------------------------------
-template <typename IT>
-__global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(5, 8))) step_spmm_grouped(const StepInst *__restrict__ insts,
+template <typename IT, bool F64S>
+__global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(F64S ? 4 : 5, 8))) step_spmm_grouped(const StepInst *__restrict__ insts,
                                                           const WorkItem *__restrict__ work, int64_t n_work,
                                                           int xcd_remap, const int64_t *__restrict__ xcd_bounds)
 {
@@ -1139,20 +1145,38 @@ __global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(5, 8))
                 for (int k = 0; k < kSpmmUnroll; ++k)
                     vk[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rv, jl * 4, k * nm * 4, kStream));
                 flag_sources();
+                if constexpr (F64S) {
+                    double xd[kSpmmUnroll];
 #pragma unroll
-                for (int m = 0; m < kGroupMax; ++m) {
-                    if (m < nm) {
-                        float acc = 0.0f;
+                    for (int k = 0; k < kSpmmUnroll; ++k) xd[k] = (double)xv[k];
 #pragma unroll
-                        for (int k = 0; k < kSpmmUnroll; ++k)
-                            acc += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vk[k]), m)) * xv[k];
-                        emit(m, acc);
+                    for (int m = 0; m < kGroupMax; ++m) {
+                        if (m < nm) {
+                            double acc = 0.0;
+#pragma unroll
+                            for (int k = 0; k < kSpmmUnroll; ++k)
+                                acc = __builtin_fma(
+                                    (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(vk[k]), m)), xd[k],
+                                    acc);
+                            emit(m, (float)acc);
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int m = 0; m < kGroupMax; ++m) {
+                        if (m < nm) {
+                            float acc = 0.0f;
+#pragma unroll
+                            for (int k = 0; k < kSpmmUnroll; ++k)
+                                acc += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vk[k]), m)) * xv[k];
+                            emit(m, acc);
+                        }
                     }
                 }
             } else {
                 flag_sources();
                 for (int m = 0; m < nm; ++m) {
-                    float acc = 0.0f;
+                    std::conditional_t<F64S, double, float> acc = 0;
                     for (int wb = 0; wb < n; wb += 64) {
                         int32_t cw = 0;
                         float vw = 0.0f;
@@ -1168,15 +1192,20 @@ __global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(5, 8))
                             for (int u = 0; u < 8; ++u)
                                 xw[u] = X[(int64_t)__builtin_amdgcn_readlane(cw, k + u) * nrhs + xl];
 #pragma unroll
-                            for (int u = 0; u < 8; ++u)
-                                acc += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vw), k + u)) * xw[u];
+                            for (int u = 0; u < 8; ++u) {
+                                const float vu = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vw), k + u));
+                                if constexpr (F64S) acc = __builtin_fma((double)vu, (double)xw[u], acc);
+                                else acc += vu * xw[u];
+                            }
                         }
                         for (; k < w; ++k) {
                             const float xk = X[(int64_t)__builtin_amdgcn_readlane(cw, k) * nrhs + xl];
-                            acc += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vw), k)) * xk;
+                            const float vu = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vw), k));
+                            if constexpr (F64S) acc = __builtin_fma((double)vu, (double)xk, acc);
+                            else acc += vu * xk;
                         }
                     }
-                    emit(m, acc);
+                    emit(m, (float)acc);
                 }
             }
         }
@@ -2886,13 +2915,19 @@ hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int6
     // the XCD count keeps the per-XCD walk available
     grid = (int)std::min<int64_t>(grid, (n_work + kXcds - 1) / kXcds * kXcds);
     const dim3 g((unsigned)grid), b(kNT);
-    if (spmm == 2) {
-        if (rp64)
-            hipLaunchKernelGGL(step_spmm_grouped<int64_t>, g, b, 0, stream, insts_dev, work_dev, n_work,
-                               xcd_remap & 1, xcd_bounds);
+    if (spmm == 2 || spmm == 3) {
+        if (rp64 && spmm == 3)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(step_spmm_grouped<int64_t, true>), g, b, 0, stream, insts_dev,
+                               work_dev, n_work, xcd_remap & 1, xcd_bounds);
+        else if (rp64)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(step_spmm_grouped<int64_t, false>), g, b, 0, stream, insts_dev,
+                               work_dev, n_work, xcd_remap & 1, xcd_bounds);
+        else if (spmm == 3)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(step_spmm_grouped<int32_t, true>), g, b, 0, stream, insts_dev,
+                               work_dev, n_work, xcd_remap & 1, xcd_bounds);
         else
-            hipLaunchKernelGGL(step_spmm_grouped<int32_t>, g, b, 0, stream, insts_dev, work_dev, n_work,
-                               xcd_remap & 1, xcd_bounds);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(step_spmm_grouped<int32_t, false>), g, b, 0, stream, insts_dev,
+                               work_dev, n_work, xcd_remap & 1, xcd_bounds);
         if (n_det_max > 0) {
             const hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;

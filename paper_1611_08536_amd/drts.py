@@ -23,8 +23,9 @@ DIRECTIONS = {"lattice26": 0, "lebedev86": 1}
 INTERFACE = {"origin": 0, "substep": 1}
 BC = {"vacuum": 0, "reflect": 1}
 KERNEL_CSR, KERNEL_STRUCTURED, KERNEL_STRUCTURED_F64SUM = 0, 1, 2
-SPMM_GROUPED, SPMM_ROWS = 0, 1   # variant of a many-rhs CSR solver
+SPMM_GROUPED, SPMM_ROWS, SPMM_GROUPED_F64SUM = 0, 1, 2   # variant of a many-rhs CSR solver
 SPMV_ROW, SPMV_LDS, SPMV_GROUPED = 0, 1, 2   # variants of a single-rhs CSR solver
+BATCH_OWN_ROWS = 1536 * 1024   # a CSR batch member this large keeps its own grouped step
 SERVE_ARRIVAL, SERVE_SHORTEST = 0, 1
 
 if not os.path.exists(LIB_PATH):
@@ -530,8 +531,10 @@ class Solver:
 
 class Batch:
     """Uneven batch of single-rhs FP32 solvers advanced by one launch per step
-    (per kernel): all members on the CSR step, or all on the matrix-free step
-    in a direction-major mode (drts_batch_*)."""
+    (per kernel): all members on the CSR step (members of BATCH_OWN_ROWS rows
+    or more keep their own step by row groups, the others share one tiled
+    launch), or all on the matrix-free step in a direction-major mode
+    (drts_batch_*)."""
 
     def __init__(self, solvers: List[Solver], device: Optional[TorchDevice] = None):
         self.solvers = list(solvers)

@@ -3,8 +3,8 @@ step counts against stored FP64 oracle values (tests/golden/, written by
 tests/golden/make_golden.py, which calls only the oracle).
 
   - 96^3 slab, 64 right-hand sides, 1000 steps: right-hand sides 0, 31 and 63
-    through the CSR SpMM step and the matrix-free many-rhs step (FP64 row
-    sums);
+    through the CSR SpMM step (FP32 and FP64 row sums) and the matrix-free
+    many-rhs step (FP64 row sums);
   - 256 uneven media, 500 steps, one batch (shape chosen by the batch
     autotuner, as the benchmark does): the first 16 members, on the CSR batch
     and on the matrix-free batch (FP64 row sums);
@@ -83,16 +83,17 @@ C3_CSR_MISS = ("measured: the FP32 CSR SpMM misses the 1e-5 series gate at its s
                "error is as large, so it is the FP32 accumulation, not the value rounding); state L1 2.7e-6")
 
 
-@pytest.mark.parametrize("kernel", [pytest.param(drts.KERNEL_CSR, marks=pytest.mark.xfail(reason=C3_CSR_MISS,
-                                                                                       strict=False)),
-                                    drts.KERNEL_STRUCTURED_F64SUM], ids=["csr_spmm", "mf_f64sum"])
-def test_c3_full_against_oracle(c3, kernel):
+@pytest.mark.parametrize("kernel,variant", [
+    pytest.param(drts.KERNEL_CSR, drts.SPMM_GROUPED, marks=pytest.mark.xfail(reason=C3_CSR_MISS, strict=False)),
+    (drts.KERNEL_CSR, drts.SPMM_GROUPED_F64SUM), (drts.KERNEL_STRUCTURED_F64SUM, drts.SPMM_GROUPED)],
+    ids=["csr_spmm", "csr_spmm_f64sum", "mf_f64sum"])
+def test_c3_full_against_oracle(c3, kernel, variant):
     import torch
     wl, M = c3
     g = _load("c3_run.npz")
     steps = int(g["steps"])
-    print("C3 96^3 x 64 rhs, %d steps, kernel %d" % (steps, kernel), flush=True)
-    opts = None
+    print("C3 96^3 x 64 rhs, %d steps, kernel %d, variant %d" % (steps, kernel, variant), flush=True)
+    opts = {"variant": variant}
     if kernel != drts.KERNEL_CSR:
         opts = {"kernel": kernel, "grid": 16 * torch.cuda.get_device_properties(0).multi_processor_count}
     out = solve.run(wl, n_steps=steps, matrix=M, options=opts)

@@ -1,10 +1,13 @@
 """Many right-hand sides (SpMM), uneven batches and the autotuner, through the C ABI.
 
 Bars: each right-hand side against the FP64 oracle run of its own sources
-(1e-5); each SpMM column against the single-rhs SpMV run of the same source
-(bit-exact state: the per-row sums are the same operations in the same order);
+(1e-5), with FP32 and with FP64 row sums; each SpMM column against the
+single-rhs SpMV run of the same source (bit-exact state: the per-row sums are
+the same operations in the same order); one step of either sum bit-exact
+against its sum written out over the oracle's FP32 values;
 each batch member against the same solver run alone (bit-exact state and
-series), with the CSR step and with the matrix-free step; autotuned launch
+series), with the CSR step (small members in the shared tiled launch, a large
+one on its own grouped step) and with the matrix-free step; autotuned launch
 shapes against the defaults (bit-exact state).
 """
 import numpy as np
@@ -43,9 +46,65 @@ def test_spmm_columns_equal_spmv_runs():
         assert np.allclose(out["det"][:, :, j], one["det"][:, :, 0], rtol=1e-13, atol=0)
 
 
-def test_spmm_64_rhs_against_oracle():
+def _rows_summed(A, v32, x, f64):
+    """[A; L] x with each row summed in column order from the oracle's FP32
+    values: in FP32 (every product and every sum rounded) or in FP64 (the
+    products of two FP32 numbers are exact there) and rounded once to FP32."""
+    rp, col = A.row_ptr, A.col
+    lens = np.diff(rp)
+    dt = np.float64 if f64 else np.float32
+    acc = np.zeros((A.n_rows, x.shape[1]), dtype=dt)
+    for j in range(int(lens.max())):
+        rows = np.flatnonzero(lens > j)
+        e = rp[rows] + j
+        acc[rows] = acc[rows] + v32[e].astype(dt)[:, None] * x[col[e]].astype(dt)
+    return acc.astype(np.float32)
+
+
+@pytest.mark.parametrize("variant", [drts.SPMM_GROUPED, drts.SPMM_GROUPED_F64SUM], ids=["f32sum", "f64sum"])
+def test_spmm_one_step_rows_bitexact(variant):
+    """A three-layer medium (fast groups, two-voxel Fresnel rows, face and
+    escape rows), 8 seeded right-hand sides, one step."""
+    wl = W.c2(n=14, n_steps=2)
+    A = oracle.Matrix(wl.medium)
+    v32 = A.round_f32(wl.rounding)
+    k = 8
+    x = np.stack([W.seeded_state(A.n_rows, 40 + j) for j in range(k)], axis=1).astype(np.float32)
+    M = drts.Matrix(wl.medium, wl.value_type, wl.rounding, wl.n_ref)
+    S = drts.Solver(M, k, [], max_steps=2)
+    S.set_options(variant=variant)
+    assert S.options["variant"] == variant
+    e0 = np.zeros(k, dtype=np.int32)
+    S.set_state(x, e0, 0)
+    S.step(None)
+    y, e1, t = S.state()
+    assert t == 1
+    want = _rows_summed(A, v32, x, variant == drts.SPMM_GROUPED_F64SUM).astype(np.float64)
+    got = np.ldexp(y.astype(np.float64), (e1 - e0)[None, :])
+    bad = np.argwhere(got != want)
+    assert bad.size == 0, (bad.shape[0], bad[:5].tolist())
+    S.close()
+    M.close()
+
+
+def test_spmm_f64sum_needs_rows_that_group():
+    """Rows of several hundred entries (Lebedev-86) take no FP64-sum SpMM; the
+    options stay as they were."""
+    med = W.homogeneous(5, W.Material(10.0, 0.02, 0.85, 1.4))
+    med.directions = "lebedev86"
+    M = drts.Matrix(med, "f32", "dither", 1.4)
+    S = drts.Solver(M, 2, [], max_steps=2)
+    with pytest.raises(drts.DrtsError):
+        S.set_options(variant=drts.SPMM_GROUPED_F64SUM)
+    assert S.options["variant"] == drts.SPMM_GROUPED
+    S.close()
+    M.close()
+
+
+@pytest.mark.parametrize("variant", [drts.SPMM_GROUPED, drts.SPMM_GROUPED_F64SUM], ids=["f32sum", "f64sum"])
+def test_spmm_64_rhs_against_oracle(variant):
     wl = W.c3(n=24, k=64, n_steps=60)
-    out = solve.run(wl)
+    out = solve.run(wl, options={"variant": variant})
     A = oracle.Matrix(wl.medium)
     for j in (0, 17, 40, 63):
         ref = oracle.run_workload(A, wl, rhs=j)
@@ -88,6 +147,45 @@ def test_batch_members_equal_solo_runs():
         assert np.array_equal(x, solo["x"]) and np.array_equal(e, solo["x_exp"]), i
         r = S.readout(0, steps[i])
         assert np.array_equal(r["tot"], solo["tot"]) and np.array_equal(r["exp2"], solo["exp2"]), i
+
+
+def test_batch_large_member_takes_its_own_grouped_step():
+    """A member of at least BATCH_OWN_ROWS rows (a 40^3 cube) keeps the step by
+    row groups inside the batch while the small members share the tiled
+    launch: after the batch autotuner, through graph-replayed segments (more
+    than 50 steps) and members dropping out on both sides, every member equals
+    its solo run with the same step, bit for bit (state, exponent, series)."""
+    big = W.c4(n_inst=1, n_steps=80, edge=(40, 40))[0]
+    small = _c4_small(n_inst=3)
+    wls = [small[0], big, small[1], small[2]]
+    steps = [80, 60, 7, 80]
+    mats = [drts.Matrix(w.medium, w.value_type, w.rounding, w.n_ref) for w in wls]
+    assert mats[1].n_rows >= drts.BATCH_OWN_ROWS
+    assert all(mats[i].n_rows < drts.BATCH_OWN_ROWS for i in (0, 2, 3))
+    solvers = [drts.Solver(m, 1, w.detectors, max_steps=80) for m, w in zip(mats, wls)]
+    tabs = [solve.source_table(m, w) for m, w in zip(mats, wls)]
+    B = drts.Batch(solvers)
+    chosen = B.autotune()
+    keys = ("rows_per_tile", "tiles_per_chunk", "variant")
+    assert solvers[1].options["variant"] == drts.SPMV_GROUPED
+    for i in (0, 2, 3):
+        assert {k: solvers[i].options[k] for k in keys} == {k: chosen[k] for k in keys}
+    B.run(tabs, steps)
+    B.close()
+    assert mats[1].groups() is not None
+    for i, (w, m, S) in enumerate(zip(wls, mats, solvers)):
+        opts = None if i == 1 else {k: chosen[k] for k in keys}
+        solo = solve.run(w, n_steps=steps[i], matrix=m, options=opts)
+        x, e, t = S.state()
+        assert t == steps[i]
+        assert np.array_equal(x, solo["x"]) and np.array_equal(e, solo["x_exp"]), i
+        r = S.readout(0, steps[i])
+        assert np.array_equal(r["tot"], solo["tot"]) and np.array_equal(r["exp2"], solo["exp2"]), i
+        solo["solver"].close()
+    for S in solvers:
+        S.close()
+    for m in mats:
+        m.close()
 
 
 def test_batch_autotune_keeps_results():
