@@ -180,6 +180,9 @@ struct drts_solver {
     double prof_ms = 0.0;
 };
 
+// streams that carry the batch members with their own grouped step
+constexpr int kBatchAuxStreams = 7;
+
 struct drts_batch {
     Device dev;
     std::vector<drts_solver *> solvers;
@@ -188,6 +191,10 @@ struct drts_batch {
     int grid = 0;                // workgroups of the step launch; 0: 16 per CU
     int mode = 0;                // 0: CSR step; 1 or 2: the matrix-free mode of every member
     int lead = 0;                // a member of the shared launch: its options give the launch's
+    // streams of the members with their own grouped step (forked from the
+    // batch's stream and joined back around each run of steps)
+    hipStream_t aux[kBatchAuxStreams] = {};
+    hipEvent_t fork = nullptr, join[kBatchAuxStreams] = {};
     // graphs of the last run, destroyed once the stream has passed them
     std::vector<hipGraphExec_t> spent;
     hipEvent_t done = nullptr;   // recorded after the last run's launches
@@ -1045,6 +1052,8 @@ namespace drts {
 
 int64_t matrix_device_bytes(const drts_matrix_t *A) { return A->m.bytes() + A->m.table_bytes(); }
 
+int matrix_row_groups(const drts_matrix_t *A) { return row_groups(A->m); }
+
 int solver_set_stream(drts_solver_t *S, hipStream_t stream)
 {
     DRTS_HIP(hipStreamSynchronize(S->dev.stream));
@@ -1674,14 +1683,6 @@ int batch_launch(drts_batch *B, int64_t n_work, int n_inst, int rows_per_tile, h
     return DRTS_OK;
 }
 
-// A CSR member of at least this many rows takes its own step by row groups
-// inside the batch instead of the shared tiled launch.  Measured on one
-// MI355X (homogeneous cubes, graph-replayed steps): a solo grouped step costs
-// about 60 us of launches plus about 10 ns per thousand rows, while in the
-// shared launch a member costs its CSR bytes at about 4.5 TB/s, some 47 ns
-// per thousand rows; the two meet near 1.5 million rows.
-constexpr int64_t kBatchOwnRows = 1536 * 1024;
-
 // A member that runs its own grouped step (its rows group and its options ask
 // for that step); the others share the batch's launch.
 bool batch_own(const drts_solver *S)
@@ -1838,6 +1839,13 @@ int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const
     }
     DRTS_HIP(hipStreamSynchronize(s));
     release_spent(B);   // the previous run's graphs are done
+    if (Q > 0 && !B->fork) {
+        DRTS_HIP(hipEventCreateWithFlags(&B->fork, hipEventDisableTiming));
+        for (int a = 0; a < kBatchAuxStreams; ++a) {
+            DRTS_HIP(hipStreamCreateWithFlags(&B->aux[a], hipStreamNonBlocking));
+            DRTS_HIP(hipEventCreateWithFlags(&B->join[a], hipEventDisableTiming));
+        }
+    }
 
     // launches: while step < the length of the j-th longest, the first j+1
     // members of each list are active
@@ -1855,9 +1863,27 @@ int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const
         if (active_own) seg_end = std::min(seg_end, len_of[(size_t)(P + active_own - 1)]);
         const int64_t n_work = active ? prefix[(size_t)active - 1] : 0;
         const int64_t n_xwork = active ? xprefix[(size_t)active - 1] : 0;
-        auto one_step = [&](hipStream_t st) {
-            int r = active ? batch_launch(B, n_work, active, rpt, st, n_xwork) : DRTS_OK;
-            for (int j = 0; j < active_own && r == DRTS_OK; ++j) r = launch_one(all[(size_t)(P + j)], st);
+        // count steps: the shared launches on st, each large member's steps
+        // on an auxiliary stream forked from st and joined back (member j on
+        // stream j mod kBatchAuxStreams), so their launch gaps overlap
+        const int n_aux = std::min(active_own, kBatchAuxStreams);
+        auto steps_on = [&](hipStream_t st, int64_t count) {
+            int r = DRTS_OK;
+            if (n_aux > 0 && hipEventRecord(B->fork, st) != hipSuccess)
+                return set_error(DRTS_E_HIP, "hipEventRecord failed");
+            for (int a = 0; a < n_aux; ++a)
+                if (hipStreamWaitEvent(B->aux[a], B->fork, 0) != hipSuccess)
+                    return set_error(DRTS_E_HIP, "hipStreamWaitEvent failed");
+            for (int64_t k = 0; k < count && r == DRTS_OK; ++k) {
+                if (active) r = batch_launch(B, n_work, active, rpt, st, n_xwork);
+                for (int j = 0; j < active_own && r == DRTS_OK; ++j)
+                    r = launch_one(all[(size_t)(P + j)], B->aux[j % kBatchAuxStreams]);
+            }
+            // joined also after a failed launch: a capture ends only joined
+            for (int a = 0; a < n_aux; ++a)
+                if (hipEventRecord(B->join[a], B->aux[a]) != hipSuccess ||
+                    hipStreamWaitEvent(st, B->join[a], 0) != hipSuccess)
+                    if (r == DRTS_OK) r = set_error(DRTS_E_HIP, "stream join failed");
             return r;
         };
         int64_t len = seg_end - step;
@@ -1866,7 +1892,7 @@ int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const
             hipGraph_t g = nullptr;
             hipGraphExec_t ge = nullptr;
             DRTS_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-            for (int k = 0; k < K && rc == DRTS_OK; ++k) rc = one_step(cap);
+            rc = steps_on(cap, K);
             hipError_t e = hipStreamEndCapture(cap, &g);
             if (rc == DRTS_OK && e != hipSuccess) rc = set_error(DRTS_E_HIP, "capture: %s", hipGetErrorString(e));
             if (rc == DRTS_OK && hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess)
@@ -1878,8 +1904,10 @@ int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const
             if (ge) B->spent.push_back(ge);
             if (rc) break;
         }
-        for (; len > 0; --len, ++step)
-            if ((rc = one_step(s))) break;
+        if (len > 0) {
+            rc = steps_on(s, len);
+            step += len;
+        }
         if (rc) break;
     }
     if (cap) (void)hipStreamDestroy(cap);
@@ -2074,6 +2102,11 @@ void drts_batch_destroy(drts_batch_t *B)
     (void)hipStreamSynchronize(B->dev.stream);
     release_spent(B);
     if (B->done) (void)hipEventDestroy(B->done);
+    if (B->fork) (void)hipEventDestroy(B->fork);
+    for (int a = 0; a < kBatchAuxStreams; ++a) {
+        if (B->aux[a]) (void)hipStreamDestroy(B->aux[a]);
+        if (B->join[a]) (void)hipEventDestroy(B->join[a]);
+    }
     delete B;
 }
 

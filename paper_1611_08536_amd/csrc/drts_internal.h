@@ -174,6 +174,18 @@ hipError_t launch_detector_window(const WindowArgs &a, hipStream_t stream);
 int build_matrix_from_model(Model &&model, const drts_device_t *dev, drts_matrix_t **out, bool with_csr = true);
 // device bytes a matrix holds (CSR arrays and tables)
 int64_t matrix_device_bytes(const drts_matrix_t *A);
+// builds A's row groups now (row_groups) on A's stream
+int matrix_row_groups(const drts_matrix_t *A);
+// A CSR batch member (or served request) of at least this many rows takes its
+// own step by row groups instead of the batch's shared tiled launch.  On one
+// MI355X a solo grouped step costs about 60 us of launches plus about 10 ns
+// per thousand rows, while in the shared launch a member costs its CSR bytes
+// at about 4.5 TB/s, some 47 ns per thousand rows.  With the own steps spread
+// over the batch's auxiliary streams their launch gaps overlap, which moves
+// the break-even down: on 256 cubes of edge 16..64 thresholds of 256K to 768K
+// rows with 7 or 15 streams all gave 26.6-27.0 thousand instance-steps/s
+// (1.5M rows with 3 streams: 23.5 thousand).
+constexpr int64_t kBatchOwnRows = 512 * 1024;
 // moves a solver's work to another stream (after finishing what its current
 // stream holds)
 int solver_set_stream(drts_solver_t *S, hipStream_t stream);

@@ -43,6 +43,7 @@ struct Request {
     const drts_source_table_t *src = nullptr;
     int64_t est_base = 0;    // footprint bound before assembly, without the CSR arrays
     int64_t est_csr = 0;     // bound of the CSR arrays (built for the CSR step only)
+    int64_t est_grp = 0;     // bound of the row groups (CSR step, requests of kBatchOwnRows rows or more)
     int64_t bytes = 0;       // footprint held while admitted
     double work = 0;         // entries of [A; L] (bound) x steps: the shortest-first key
     Model model;             // host model, built once at submission, moved into the matrix
@@ -145,7 +146,13 @@ int copy_request(Request &q, const drts_medium_t *m, const drts_detectors_t *det
 // plus the row pointers.  The tables every step reads or the assembly needs:
 // the material map, the direction blocks (FP64 and FP32), the irregular-move
 // and escape lists with the row bitmap, and the matrix-free solver's row lists
-// (about 32 bytes per irregular or escape row, one bit per row).
+// (about 32 bytes per irregular or escape row, one bit per row).  A request
+// of kBatchOwnRows rows or more takes the CSR step by row groups, whose
+// arrays hold the values once more in group order and the two-voxel rows'
+// copy (at most 8 bytes per entry in all) and per row at most 117 bytes of
+// descriptors, members' rows and materials, row lists, value-indexed slots
+// and bricks; the bound adds 64 bytes per row for the sort buffers of their
+// construction.
 int estimate_bytes(Request &q, int32_t kernel = DRTS_KERNEL_CSR)
 {
     Model &M = q.model;
@@ -154,6 +161,7 @@ int estimate_bytes(Request &q, int32_t kernel = DRTS_KERNEL_CSR)
     const int64_t n_irr = (int64_t)M.irr_row.size();
     const int64_t nnz_ub = (int64_t)kDirs * (M.n_rows + n_irr);
     q.est_csr = 8 * (nnz_ub + 4) + 8 * (M.n_rows + 1);
+    q.est_grp = M.n_rows >= kBatchOwnRows ? 8 * nnz_ub + (117 + 64) * M.n_rows + (1 << 20) : 0;
     const int64_t tables = M.n_vox + (int64_t)M.mats.size() * kDirs * kDirs * 12 + 28 * n_irr + 8 * M.n_escape +
                            M.n_states / 8 + 32 * (n_irr + M.n_escape) + M.n_rows / 8 + (1 << 20);
     const int32_t n_src = q.src ? q.src->n_src : 0;
@@ -166,7 +174,7 @@ int estimate_bytes(Request &q, int32_t kernel = DRTS_KERNEL_CSR)
 // The footprint bound of a request admitted with `kernel` as its step.
 int64_t bound_for(const Request &q, int32_t kernel)
 {
-    return q.est_base + (kernel == DRTS_KERNEL_CSR ? q.est_csr : 0);
+    return q.est_base + (kernel == DRTS_KERNEL_CSR ? q.est_csr + q.est_grp : 0);
 }
 
 // Assembles an admitted request's matrix (only the tables the matrix-free
@@ -191,9 +199,16 @@ int admit(drts_server *Q, Request &q)
     det.state = q.det_state.data();
     det.escape = q.det_esc.data();
     det.F = q.det_F.data();
-    rc = drts_solver_create(q.A, 1, q.n_det > 0 ? &det : nullptr, q.n_steps, &bdev, &q.S);
-    if (!rc && Q->kernel == DRTS_KERNEL_CSR) {
-        // requests run batched: the tiled step (LDS layout, 4 tiles per chunk)
+    // a large request keeps the step by row groups (on its own in the batch):
+    // its groups are built now, so that its footprint counts them
+    int64_t n_st = 0, n_esc = 0;
+    drts_matrix_info(q.A, &n_st, &n_esc, nullptr, nullptr, nullptr);
+    const bool own = Q->kernel == DRTS_KERNEL_CSR && n_st + n_esc >= kBatchOwnRows;
+    if (own) rc = matrix_row_groups(q.A);
+    if (!rc) rc = drts_solver_create(q.A, 1, q.n_det > 0 ? &det : nullptr, q.n_steps, &bdev, &q.S);
+    if (!rc && Q->kernel == DRTS_KERNEL_CSR && !own) {
+        // small requests share the batch's launch: the tiled step (LDS
+        // layout, 4 tiles per chunk)
         drts_options_t o{};
         rc = drts_solver_get_options(q.S, &o);
         if (!rc) {

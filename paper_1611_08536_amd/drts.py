@@ -25,7 +25,7 @@ BC = {"vacuum": 0, "reflect": 1}
 KERNEL_CSR, KERNEL_STRUCTURED, KERNEL_STRUCTURED_F64SUM = 0, 1, 2
 SPMM_GROUPED, SPMM_ROWS, SPMM_GROUPED_F64SUM = 0, 1, 2   # variant of a many-rhs CSR solver
 SPMV_ROW, SPMV_LDS, SPMV_GROUPED = 0, 1, 2   # variants of a single-rhs CSR solver
-BATCH_OWN_ROWS = 1536 * 1024   # a CSR batch member this large keeps its own grouped step
+BATCH_OWN_ROWS = 512 * 1024   # a CSR batch member this large keeps its own grouped step
 SERVE_ARRIVAL, SERVE_SHORTEST = 0, 1
 
 if not os.path.exists(LIB_PATH):

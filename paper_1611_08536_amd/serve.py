@@ -104,10 +104,14 @@ def serve(requests, budget_bytes: int, quantum: int = 50, max_active: int = 256,
     return out
 
 
-def solo_options(kernel: int) -> Optional[dict]:
-    """The launch options the server gives a request run with `kernel` (the
-    CSR server batches its requests: the tiled step, not the grouped one)."""
+def solo_options(kernel: int, n_rows: int = 0) -> Optional[dict]:
+    """The launch options the server gives a request of n_rows rows run with
+    `kernel` (the CSR server batches its small requests on the tiled step and
+    leaves the large ones, drts.BATCH_OWN_ROWS rows or more, their default
+    step by row groups)."""
     if kernel == drts.KERNEL_CSR:
+        if n_rows >= drts.BATCH_OWN_ROWS:
+            return None
         return {"variant": drts.SPMV_LDS, "tiles_per_chunk": 4}
     import torch
     cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
@@ -117,7 +121,6 @@ def solo_options(kernel: int) -> Optional[dict]:
 def fifo_plain(requests, keep_results: bool = False, log=None, kernel: int = drts.KERNEL_CSR) -> dict:
     """The same requests, one at a time in arrival order, each solved alone
     (with the options the server gives a request run with `kernel`)."""
-    opts = solo_options(kernel)
     order = sorted(range(len(requests)), key=lambda i: requests[i].arrival_s)
     lat, results = [], {}
     t0 = time.perf_counter()
@@ -129,6 +132,7 @@ def fifo_plain(requests, keep_results: bool = False, log=None, kernel: int = drt
         wl = req.workload
         A = drts.Matrix(wl.medium, wl.value_type, wl.rounding, wl.n_ref)
         Sv = drts.Solver(A, 1, wl.detectors, max_steps=wl.n_steps)
+        opts = solo_options(kernel, A.n_rows)
         if opts:
             Sv.set_options(**opts)
         Sv.run(_table(wl), wl.n_steps)

@@ -106,7 +106,10 @@ def test_c4_full_batch_members_equal_solo_runs():
     B.run(tabs, [steps] * len(solvers))
     B.close()
     for i in (0, 77, 150, 255):
-        solo = solve.run(wls[i], n_steps=steps, matrix=mats[i], options={"variant": drts.SPMV_LDS})
+        # the same step as in the batch: its own grouped step for a large
+        # member, the tiled step for one of the shared launch
+        opts = None if mats[i].n_rows >= drts.BATCH_OWN_ROWS else {"variant": drts.SPMV_LDS}
+        solo = solve.run(wls[i], n_steps=steps, matrix=mats[i], options=opts)
         x, e, t = solvers[i].state()
         assert t == steps
         assert np.array_equal(x, solo["x"]) and np.array_equal(e, solo["x_exp"]), i

@@ -65,6 +65,38 @@ def test_strict_fifo_and_single_slot_give_the_same_results():
         assert _same(a["results"][i], b["results"][i]), i
 
 
+def test_large_request_keeps_the_grouped_step():
+    """A request of at least BATCH_OWN_ROWS rows (a 40^3 sphere medium) served
+    beside small ones keeps its step by row groups, its groups built and
+    counted at admission (its footprint bound covers them): every result
+    equals the solo run with the server's options, bit for bit, and the large
+    one is within 1e-5 of the oracle."""
+    big = W.c5(n_req=1, rate=1e6, edge=(40, 40), steps=(40, 40))
+    reqs = big + _requests(3, steps=(20, 50))
+    for q in reqs:
+        q.arrival_s = 0.0
+    fps = _footprints(reqs)
+    out = serve.serve(reqs, 2 * sum(fps), quantum=16, max_active=4, keep_results=True, submit_threads=0)
+    assert out["peak_active"] == len(reqs), out["peak_active"]
+    solo = serve.fifo_plain(reqs, keep_results=True)
+    for i in range(len(reqs)):
+        assert _same(out["results"][i], solo["results"][i]), i
+    wl = reqs[0].workload
+    A = drts.Matrix(wl.medium, wl.value_type, wl.rounding, wl.n_ref)
+    assert A.n_rows >= drts.BATCH_OWN_ROWS
+    S = drts.Solver(A, 1, wl.detectors, max_steps=1)
+    S.run(serve._table(wl), 1)                # builds the groups, as admission does
+    assert A.groups() is not None
+    assert A.device_bytes() <= fps[0], (A.device_bytes(), fps[0])
+    S.close()
+    A.close()
+    ref = oracle.run_workload(oracle.Matrix(wl.medium), wl)
+    r = out["results"][0]
+    for c in range(3):
+        err = parity.rel_err_series(r["tot"][:, c], r["exp2"], ref["tot"][:, c], ref["tot_exp"][:, c])
+        assert err <= 1e-5, (c, err)
+
+
 def test_served_results_against_oracle():
     reqs = _requests(4)
     out = serve.serve(reqs, 1 << 34, quantum=25, keep_results=True)
