@@ -245,7 +245,7 @@ def spmm_vs_plain(torch, steps=20):
     out["precision"] = "FP32 values, state and accumulation (CSR SpMM)"
     s64_s = s_ms / max(n_s, 1) * 1e-3
     out["f64sum"] = {"kernel": "step_spmm_grouped<int32, FP64 row sums> + spmm_detectors",
-                     "precision": "FP32 values and state, each row summed in FP64 and rounded once",
+                     "precision": F64SUM_NOTE,
                      "ms_per_step": round(t_s64 / steps * 1e3, 3), "kernel_ms": round(s64_s * 1e3, 3),
                      "achieved_GBs": round(nbytes / s64_s / 1e9, 1),
                      "frac": round(nbytes / s64_s / 1e9 / PEAK_HBM_GBS, 4)}
