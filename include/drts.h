@@ -478,9 +478,9 @@ void drts_solver_destroy(drts_solver_t *S);
  * launch per step advances all of them.  A CSR member of at least 512 * 1024
  * rows whose options ask for the step by row groups (the default) keeps that
  * step: its launches go to one of the batch's auxiliary streams (forked from
- * the batch's stream and joined back in the same graph replays, so that the
- * members' launch gaps overlap); the others take the tiled step and share
- * one launch.
+ * the batch's stream and joined back around each run, so that the members'
+ * launch gaps overlap; such a batch launches without graph capture); the
+ * others take the tiled step and share one launch.
  * Each solver keeps its own state, exponent and series; results equal those
  * of the solver run alone with the same step, bit for bit.  The solvers must
  * outlive the batch. */
@@ -527,11 +527,9 @@ void drts_batch_destroy(drts_batch_t *B);
  *      admit more.
  * The footprint of a request is its matrix [A; L] (an upper bound from the
  * medium before assembly, the exact size after), two state buffers, its
- * series and its source table.  A CSR request of at least 512 * 1024 rows
- * keeps the step by row groups (on its own in the batch; see
- * drts_batch_create): its row groups are built at admission and counted too.
- * Results equal those of the same solve run alone (drts_run) with the same
- * step, bit for bit.  budget_bytes > 0; 1 <= quantum <= 100000;
+ * series and its source table.  CSR requests take the tiled step, all of
+ * them in the batch's shared launch.  Results equal those of the same solve
+ * run alone (drts_run) with the same step, bit for bit.  budget_bytes > 0; 1 <= quantum <= 100000;
  * 1 <= max_active <= 4096; max_skips >= 0; policy DRTS_SERVE_*.
  * drts_serve_submit may be called from any thread, also while another call
  * on the same server runs (it builds the request's host model before it
@@ -545,9 +543,8 @@ int drts_serve_create(const drts_device_t *dev, int64_t budget_bytes, int32_t qu
                       int32_t max_skips, int32_t policy, drts_server_t **out);
 
 /* Selects the step of the requests admitted from now on: DRTS_KERNEL_CSR
- * (the default: all CSR requests advance together, the small ones in one
- * batched launch per step, the large ones each on its own grouped step) or a
- * matrix-free kernel (DRTS_KERNEL_STRUCTURED or
+ * (the default: all CSR requests advance together, one batched launch per
+ * step) or a matrix-free kernel (DRTS_KERNEL_STRUCTURED or
  * DRTS_KERNEL_STRUCTURED_F64SUM, with 8 tiles per chunk and 16 workgroups
  * per CU): the matrix-free requests that a batch takes (FP64 row sums, or
  * exact values when nearest-rounded; at most 8 materials) advance together

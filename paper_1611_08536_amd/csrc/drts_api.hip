@@ -1887,7 +1887,9 @@ int drts_batch_run(drts_batch_t *B, const drts_source_table_t *const *src, const
             return r;
         };
         int64_t len = seg_end - step;
-        if (len >= 2 * K) {
+        // graph segments only for a batch without own-step members; one with
+        // them launches eagerly
+        if (len >= 2 * K && Q == 0) {
             if (!cap) DRTS_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
             hipGraph_t g = nullptr;
             hipGraphExec_t ge = nullptr;

@@ -140,6 +140,12 @@ int copy_request(Request &q, const drts_medium_t *m, const drts_detectors_t *det
     return DRTS_OK;
 }
 
+// Large CSR requests on their own step by row groups inside the server's
+// batch: off.  A replay of the full 256-request sphere stream with it on ended
+// in a host segmentation fault after 70 requests, whose cause is not known;
+// every CSR request takes the shared tiled launch.
+constexpr bool kServeOwnGrouped = false;
+
 // Upper bound of the request's device footprint, from the medium alone.  The
 // CSR arrays: a row holds at most 26 entries per move group (the plain move
 // and each irregular move), every entry 8 bytes (FP32 value, int32 column),
@@ -161,7 +167,7 @@ int estimate_bytes(Request &q, int32_t kernel = DRTS_KERNEL_CSR)
     const int64_t n_irr = (int64_t)M.irr_row.size();
     const int64_t nnz_ub = (int64_t)kDirs * (M.n_rows + n_irr);
     q.est_csr = 8 * (nnz_ub + 4) + 8 * (M.n_rows + 1);
-    q.est_grp = M.n_rows >= kBatchOwnRows ? 8 * nnz_ub + (117 + 64) * M.n_rows + (1 << 20) : 0;
+    q.est_grp = kServeOwnGrouped && M.n_rows >= kBatchOwnRows ? 8 * nnz_ub + (117 + 64) * M.n_rows + (1 << 20) : 0;
     const int64_t tables = M.n_vox + (int64_t)M.mats.size() * kDirs * kDirs * 12 + 28 * n_irr + 8 * M.n_escape +
                            M.n_states / 8 + 32 * (n_irr + M.n_escape) + M.n_rows / 8 + (1 << 20);
     const int32_t n_src = q.src ? q.src->n_src : 0;
@@ -200,10 +206,11 @@ int admit(drts_server *Q, Request &q)
     det.escape = q.det_esc.data();
     det.F = q.det_F.data();
     // a large request keeps the step by row groups (on its own in the batch):
-    // its groups are built now, so that its footprint counts them
+    // its groups are built now, so that its footprint counts them (switched
+    // off: see kServeOwnGrouped)
     int64_t n_st = 0, n_esc = 0;
     drts_matrix_info(q.A, &n_st, &n_esc, nullptr, nullptr, nullptr);
-    const bool own = Q->kernel == DRTS_KERNEL_CSR && n_st + n_esc >= kBatchOwnRows;
+    const bool own = kServeOwnGrouped && Q->kernel == DRTS_KERNEL_CSR && n_st + n_esc >= kBatchOwnRows;
     if (own) rc = matrix_row_groups(q.A);
     if (!rc) rc = drts_solver_create(q.A, 1, q.n_det > 0 ? &det : nullptr, q.n_steps, &bdev, &q.S);
     if (!rc && Q->kernel == DRTS_KERNEL_CSR && !own) {

