@@ -244,7 +244,7 @@ def spmm_vs_plain(torch, steps=20):
     mf_bytes = 4 * k * A.n_states + 4 * k * A.n_rows + A.n_states // 26
     out["precision"] = "FP32 values, state and accumulation (CSR SpMM)"
     s64_s = s_ms / max(n_s, 1) * 1e-3
-    out["f64sum"] = {"kernel": "step_spmm_grouped<int32, FP64 row sums> + spmm_detectors",
+    out["f64sum"] = {"kernel": "step_spmm_grouped<int32, FP64 row sums, value-indexed> + spmm_detectors",
                      "precision": F64SUM_NOTE,
                      "ms_per_step": round(t_s64 / steps * 1e3, 3), "kernel_ms": round(s64_s * 1e3, 3),
                      "achieved_GBs": round(nbytes / s64_s / 1e9, 1),

@@ -76,7 +76,7 @@ int64_t Matrix::bytes() const
 {
     const Buffer *b[] = {&row_ptr,   &col,      &val,      &grp_desc, &grp_row,   &grp_mat,  &grp_val,
                          &grp_fast,  &slow_rows, &vox2_info, &vox2_val, &vi_idx,  &vi_dict, &brick_ptr,
-                         &brick_org, &vi_fdesc};
+                         &brick_org, &vi_fdesc, &vi_fast_of};
     int64_t n = 0;
     for (const Buffer *x : b) n += (int64_t)x->bytes;
     return n;
@@ -739,6 +739,7 @@ int prepare(drts_solver *S)
         I.grid_nx = A.model.nx;
         I.grid_ny = A.model.ny;
         I.vi_fdesc = A.vi_ntab > 0 ? A.vi_fdesc.as<int32_t>() : nullptr;
+        I.vi_fast_of = A.vi_ntab > 0 ? A.vi_fast_of.as<int32_t>() : nullptr;
         I.grp_src_f = A.vi_ntab > 0 ? S->grp_src_f.as<uint32_t>() : nullptr;
         I.det_direct = 1;
         I.ddet_ptr = S->ddet_ptr.as<int64_t>();
@@ -927,7 +928,7 @@ int launch_one(drts_solver *S, hipStream_t stream, const StepInst *inst = nullpt
                                (S->opt.xcd_remap ? 1 : 0) | ((variant & 15) << 1), S->xcd_bounds.as<int64_t>(),
                                S->opt.rows_per_tile, S->n_det, queue, stream, S->grouped ? A.n_slow : 0,
                                S->grouped && !spmm ? A.n_vox2 : 0,
-                               S->grouped && !spmm && A.vi_ntab > 0 ? A.vi_ntab | (S->fast_src ? 0x100 : 0) : 0);
+                               S->grouped && A.vi_ntab > 0 ? A.vi_ntab | (!spmm && S->fast_src ? 0x100 : 0) : 0);
     }
     if (e != hipSuccess) return set_error(DRTS_E_HIP, "step launch failed: %s", hipGetErrorString(e));
     if (e1) DRTS_HIP(hipEventRecord(e1, stream));

@@ -394,6 +394,13 @@ __global__ void __launch_bounds__(256) fdesc_build(const GroupDesc *desc, const 
     fd[4 * f + 3] = g;
 }
 
+// fast_of[g] = f for fast group g = fast[f] (the other entries stay -1)
+__global__ void __launch_bounds__(256) fast_index_of(const int32_t *fast, int64_t n_fast, int32_t *fast_of)
+{
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f < n_fast) fast_of[fast[f]] = (int32_t)f;
+}
+
 __global__ void __launch_bounds__(256) fast_flag_bits(const int32_t *fast, int64_t n_fast, const uint32_t *gbits,
                                                       uint32_t *fbits)
 {
@@ -407,10 +414,11 @@ __global__ void __launch_bounds__(256) fast_flag_bits(const int32_t *fast, int64
     fbits[w] = word;
 }
 
-// Builds A.vi_idx / A.vi_dict, or leaves A.vi_ntab = 0 when a material has
+// Builds A.vi_idx / A.vi_dict (and the map of A's n_groups groups to fast
+// indices), or leaves A.vi_ntab = 0 when a material has
 // more than kViDict distinct values among its fast groups' entries (or there
 // are more than kViTabs materials).
-int build_value_index(Matrix &A)
+int build_value_index(Matrix &A, int64_t n_groups)
 {
     Device &dev = A.dev;
     A.vi_ntab = 0;
@@ -471,6 +479,12 @@ int build_value_index(Matrix &A)
     if ((rc = A.vi_fdesc.allocate(&dev, (size_t)A.n_fast * 4 * sizeof(int32_t)))) return rc;
     hipLaunchKernelGGL(fdesc_build, dim3((unsigned)((A.n_fast + 255) / 256)), dim3(256), 0, dev.stream,
                        A.grp_desc.as<GroupDesc>(), A.grp_fast.as<int32_t>(), A.n_fast, A.vi_fdesc.as<int32_t>());
+    DRTS_HIP(hipGetLastError());
+    // each group's fast index (the many-rhs step walks the groups in group order)
+    if ((rc = A.vi_fast_of.allocate(&dev, (size_t)n_groups * sizeof(int32_t)))) return rc;
+    DRTS_HIP(hipMemsetAsync(A.vi_fast_of.ptr, 0xff, (size_t)n_groups * sizeof(int32_t), dev.stream));
+    hipLaunchKernelGGL(fast_index_of, dim3((unsigned)((A.n_fast + 255) / 256)), dim3(256), 0, dev.stream,
+                       A.grp_fast.as<int32_t>(), A.n_fast, A.vi_fast_of.as<int32_t>());
     DRTS_HIP(hipGetLastError());
     DRTS_HIP(hipStreamSynchronize(dev.stream));
     A.vi_ntab = n_mat;
@@ -631,7 +645,7 @@ int build_groups(Matrix &A)
         DRTS_HIP(hipGetLastError());
         DRTS_HIP(hipStreamSynchronize(dev.stream));
     }
-    if ((rc = build_value_index(A))) return rc;
+    if ((rc = build_value_index(A, G))) return rc;
     A.n_groups = G;
     return DRTS_OK;
 }
@@ -652,7 +666,7 @@ int row_groups(const Matrix &Ac)
     if (rc) {
         Buffer *b[] = {&A.grp_desc, &A.grp_row,   &A.grp_mat,   &A.grp_val,   &A.grp_fast,
                        &A.slow_rows, &A.vox2_info, &A.vox2_val,  &A.vi_idx,    &A.vi_dict,
-                       &A.brick_ptr, &A.brick_org, &A.vi_fdesc};
+                       &A.brick_ptr, &A.brick_org, &A.vi_fdesc,  &A.vi_fast_of};
         for (Buffer *x : b) x->reset();
         A.n_groups = -1;
     }

@@ -138,8 +138,9 @@ struct Matrix {
     Buffer brick_ptr, brick_org;
     int64_t n_brick = 0;
     // per fast group (fast-list order): first member, member count, first
-    // column of its run, group index (int32 x 4), with value indexing
-    Buffer vi_fdesc;
+    // column of its run, group index (int32 x 4), and per group its fast
+    // index (-1: not a fast group), with value indexing
+    Buffer vi_fdesc, vi_fast_of;
     int64_t bytes() const;         // the CSR arrays (and the row groups, once built)
     int64_t table_bytes() const;   // everything else on the device (tables of the model)
 };

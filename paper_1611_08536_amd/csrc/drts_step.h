@@ -94,8 +94,10 @@ struct StepInst {
     int64_t n_brick;
     int32_t grid_nx, grid_ny;
     // per fast group, in fast-list order: {first member, member count, first
-    // column of its run, group}; the source bits by fast index
+    // column of its run, group}; per group its fast index (-1: not fast); the
+    // source bits by fast index
     const int32_t *vi_fdesc;
+    const int32_t *vi_fast_of;
     const uint32_t *grp_src_f;
     // det_direct: the detector sums come from their own kernel (a value per
     // detector and rhs after the finalize segments of the partials, see
@@ -207,7 +209,8 @@ struct alignas(16) GroupDesc {
 // n_slow, n_vox2: with the grouped single-rhs step, the rows it takes one by
 // one from the CSR and its two-voxel rows; vi: the number of dictionaries of
 // its value-indexed fast groups (0: FP32 values), plus 0x100 when a fast
-// group holds a source row.
+// group holds a source row; with spmm 2 or 3 the number of dictionaries that
+// the fast groups' values index (0: FP32 group values; spmm 3 reads them).
 hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int64_t n_work, int n_inst,
                        int n_rhs_max, int value_f64, int rp64, int spmm, int grid, int xcd_remap,
                        const int64_t *xcd_bounds, int rows_per_tile, int n_det_max, int32_t *queue,

@@ -35,6 +35,7 @@ constexpr int kXcds = 8;
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
 typedef int i4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // Pointers into device memory are marked as global (address space 1): the
 // descriptors are read from memory, so the compiler would otherwise emit flat
@@ -1026,6 +1027,10 @@ template <typename P> __device__ __forceinline__ GroupDesc load_desc(P p)
 // column order: the products of two FP32 numbers are exact in FP64) and
 // rounded once to FP32, which keeps the FP32 accumulation error from building
 // up over long runs.
+// With VI (taken with F64S) the fast groups' values come from their
+// value-indexed slots (lane j reads member j's 32-byte slot and takes its 26
+// values from the dictionary in LDS: the same FP32 values, from a quarter of
+// the bytes).
 // Groups whose rows are not kSpmmUnroll long are formed row by row (windows
 // of 64 entries).  Sources are looked up only in groups the solver flagged.
 //
@@ -1035,11 +1040,12 @@ template <typename P> __device__ __forceinline__ GroupDesc load_desc(P p)
 // takes which item.  The detector sums are left to spmm_detectors, which
 // reads the stored rows.
 // ---------------------------------------------------------------------------
-template <typename IT, bool F64S>
+template <typename IT, bool F64S, bool VI>
 __global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(F64S ? 4 : 5, 8))) step_spmm_grouped(const StepInst *__restrict__ insts,
                                                           const WorkItem *__restrict__ work, int64_t n_work,
                                                           int xcd_remap, const int64_t *__restrict__ xcd_bounds)
 {
+    extern __shared__ float s_dict[];   // VI: [vi_ntab][kViDict]
     __shared__ double s_abs[kMatMax];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1062,7 +1068,11 @@ __global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(F64S ?
     const GLB int32_t *src_tile = gp(I.src_tile);
     const CST GroupDesc *grp = cst(I.grp);
     const CST uint32_t *gsrc = cst(I.grp_src);
+    const CST int32_t *gfo = cst(I.vi_fast_of);
+    const GLB uint8_t *vidx = gp(I.vi_idx);
     for (int q = threadIdx.x; q < I.n_mat; q += kNT) s_abs[q] = gp(I.absorb)[q];
+    if constexpr (VI)
+        for (int q = threadIdx.x; q < I.vi_ntab * kViDict; q += kNT) s_dict[q] = gp(I.vi_dict)[q];
     __syncthreads();
 
     const int R = I.rows_per_tile;
@@ -1137,13 +1147,31 @@ __global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(F64S ?
                         xv[k] = X[(int64_t)__builtin_amdgcn_readlane(cl, k) * nrhs + xl];
                 }
                 // vk[k]: lane m holds member m's entry k (a buffer at the
-                // group's values, entry k at a scalar offset)
-                const __amdgpu_buffer_rsrc_t rv =
-                    make_rsrc((const void *)(val + D.voff), (uint64_t)kSpmmUnroll * nm * 4);
+                // group's values, entry k at a scalar offset; or, value-
+                // indexed, member m's slot and the dictionary)
                 float vk[kSpmmUnroll];
+                bool indexed = false;
+                if constexpr (VI) {
+                    const int32_t f = gfo[g];
+                    if (f >= 0) {
+                        const GLB u32x4 *slot = (const GLB u32x4 *)(vidx + (int64_t)f * kViBlock + (int64_t)jl * kViSlot);
+                        const u32x4 s0 = __builtin_nontemporal_load(slot), s1 = __builtin_nontemporal_load(slot + 1);
+                        const uint32_t wd[8] = {s0[0], s0[1], s0[2], s0[3], s1[0], s1[1], s1[2], s1[3]};
+                        const float *tab =
+                            s_dict + ((wd[kViTabByte >> 2] >> (8 * (kViTabByte & 3))) & 0xff) * kViDict;
 #pragma unroll
-                for (int k = 0; k < kSpmmUnroll; ++k)
-                    vk[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rv, jl * 4, k * nm * 4, kStream));
+                        for (int k = 0; k < kSpmmUnroll; ++k) vk[k] = tab[(wd[k >> 2] >> (8 * (k & 3))) & 0xff];
+                        indexed = true;
+                    }
+                }
+                if (!indexed) {
+                    const __amdgpu_buffer_rsrc_t rv =
+                        make_rsrc((const void *)(val + D.voff), (uint64_t)kSpmmUnroll * nm * 4);
+#pragma unroll
+                    for (int k = 0; k < kSpmmUnroll; ++k)
+                        vk[k] = __builtin_bit_cast(
+                            float, __builtin_amdgcn_raw_buffer_load_b32(rv, jl * 4, k * nm * 4, kStream));
+                }
                 flag_sources();
                 if constexpr (F64S) {
                     double xd[kSpmmUnroll];
@@ -1433,7 +1461,6 @@ __global__ void __launch_bounds__(kNT) step_spmv_grouped(const StepInst *__restr
 // and rows whose index is not (u + e_m, m) are stored directly.  SRC: some
 // fast group holds a source row (else the source code is left out).
 constexpr int kGroupPairsVi = 2;   // pairs of groups a wave forms per pass
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 template <int NP, bool SRC>
 __global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(5, 8))) step_spmv_grouped_vi(const StepInst *__restrict__ insts,
@@ -2916,18 +2943,32 @@ hipError_t launch_step(const StepInst *insts_dev, const WorkItem *work_dev, int6
     grid = (int)std::min<int64_t>(grid, (n_work + kXcds - 1) / kXcds * kXcds);
     const dim3 g((unsigned)grid), b(kNT);
     if (spmm == 2 || spmm == 3) {
-        if (rp64 && spmm == 3)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(step_spmm_grouped<int64_t, true>), g, b, 0, stream, insts_dev,
-                               work_dev, n_work, xcd_remap & 1, xcd_bounds);
+        // value-indexed fast groups (the dictionaries in dynamic LDS) for the
+        // FP64 sums only: measured on the 96^3 slab with 64 rhs, they take
+        // the FP64-sum step from 4.73 to 4.19 ms but the FP32 one from 4.05
+        // to 4.70 ms
+        const int ntab = vi & 0xff;
+        const size_t dl = (size_t)ntab * kViDict * sizeof(float);
+        const int x = xcd_remap & 1;
+        if (ntab > 0 && spmm == 3) {
+            if (rp64)
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(step_spmm_grouped<int64_t, true, true>), g, b, dl, stream,
+                                   insts_dev, work_dev, n_work, x, xcd_bounds);
+            else
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(step_spmm_grouped<int32_t, true, true>), g, b, dl, stream,
+                                   insts_dev, work_dev, n_work, x, xcd_bounds);
+        } else if (rp64 && spmm == 3)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(step_spmm_grouped<int64_t, true, false>), g, b, 0, stream, insts_dev,
+                               work_dev, n_work, x, xcd_bounds);
         else if (rp64)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(step_spmm_grouped<int64_t, false>), g, b, 0, stream, insts_dev,
-                               work_dev, n_work, xcd_remap & 1, xcd_bounds);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(step_spmm_grouped<int64_t, false, false>), g, b, 0, stream, insts_dev,
+                               work_dev, n_work, x, xcd_bounds);
         else if (spmm == 3)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(step_spmm_grouped<int32_t, true>), g, b, 0, stream, insts_dev,
-                               work_dev, n_work, xcd_remap & 1, xcd_bounds);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(step_spmm_grouped<int32_t, true, false>), g, b, 0, stream, insts_dev,
+                               work_dev, n_work, x, xcd_bounds);
         else
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(step_spmm_grouped<int32_t, false>), g, b, 0, stream, insts_dev,
-                               work_dev, n_work, xcd_remap & 1, xcd_bounds);
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(step_spmm_grouped<int32_t, false, false>), g, b, 0, stream, insts_dev,
+                               work_dev, n_work, x, xcd_bounds);
         if (n_det_max > 0) {
             const hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
