@@ -1473,7 +1473,11 @@ __global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(5, 8))
     __shared__ float s_win[kWinSlots];          // the brick's staged rows
     __shared__ uint32_t s_has[2][kHasWords];    // presence bits, by brick parity
     __shared__ float s_x[4][NG][32];
-    __shared__ double s_abs[kMatMax];
+    __shared__ double s_abs[kViTabs];           // value indexing: at most kViTabs materials
+    // index tables: per direction d its voxel offset in the grid and in the
+    // window; per position in the brick its voxel in the window; per window
+    // voxel its offset in the grid from the window's first voxel
+    __shared__ int32_t s_goff[26], s_doff[26], s_pb[kBrick * kBrick * kBrick], s_woff[kWin * kWin * kWin];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int h = lane >> 5, m = lane & 31;
@@ -1497,6 +1501,19 @@ __global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(5, 8))
     for (int q = threadIdx.x; q < I.n_mat; q += kNT) s_abs[q] = gp(I.absorb)[q];
     for (int q = threadIdx.x; q < I.vi_ntab * kViDict; q += kNT) s_tab[q] = gp(I.vi_dict)[q];
     for (int q = threadIdx.x; q < 2 * kHasWords; q += kNT) (&s_has[0][0])[q] = 0u;
+    // (the bricks' guard keeps a plane, and so every offset here, within int32)
+    for (int q = threadIdx.x; q < 26; q += kNT) {
+        const int kk = q + (q >= 13 ? 1 : 0);
+        const int ex = kk % 3 - 1, ey = (kk / 3) % 3 - 1, ez = kk / 9 - 1;
+        s_goff[q] = ex + ey * nx + ez * (int32_t)plane;
+        s_doff[q] = (ez * kWin + ey) * kWin + ex;
+    }
+    for (int q = threadIdx.x; q < kBrick * kBrick * kBrick; q += kNT)
+        s_pb[q] = ((q / (kBrick * kBrick) + 1) * kWin + (q / kBrick) % kBrick + 1) * kWin + q % kBrick + 1;
+    for (int q = threadIdx.x; q < kWin * kWin * kWin; q += kNT)
+        s_woff[q] = q % kWin + ((q / kWin) % kWin) * nx + (q / (kWin * kWin)) * (int32_t)plane;
+    // this thread's first window slot s = threadIdx.x as (window voxel, direction)
+    const int vw0 = threadIdx.x / 26, dd0 = threadIdx.x - 26 * (threadIdx.x / 26);
     __syncthreads();
 
     const int R = I.rows_per_tile;
@@ -1597,18 +1614,14 @@ __global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(5, 8))
                                 sA += s_abs[mt[p]] * (double)v;
                                 mx = fmaxf(mx, v);
                                 // the row (u + e_d, d) of source voxel u, d = rr mod 26:
-                                // its slot in the brick's window
+                                // its slot in the brick's window (u at position pos of
+                                // the brick, so the slot is in the window for any d)
                                 const int32_t vd = rr / 26, d = rr - 26 * vd;
-                                const int kk = d + (d >= 13 ? 1 : 0);
-                                const int ex = kk % 3 - 1, ey = (kk / 3) % 3 - 1, ez = kk / 9 - 1;
                                 const int32_t u = cs[p] / 26;
-                                const int pos =
-                                    (wd[kViPosByte >> 2] >> (8 * (kViPosByte & 3))) & (kBrick * kBrick * kBrick - 1);
-                                const int lx = pos % kBrick + 1 + ex, ly = (pos / kBrick) % kBrick + 1 + ey,
-                                          lz = pos / (kBrick * kBrick) + 1 + ez;
-                                if ((int64_t)vd == (int64_t)u + ex + (int64_t)ey * nx + (int64_t)ez * plane &&
-                                    w0 + lx + (int64_t)ly * nx + (int64_t)lz * plane == (int64_t)vd) {
-                                    const int slot = ((lz * kWin + ly) * kWin + lx) * 26 + d;
+                                if (vd == u + s_goff[d]) {
+                                    const int pos = (wd[kViPosByte >> 2] >> (8 * (kViPosByte & 3))) &
+                                                    (kBrick * kBrick * kBrick - 1);
+                                    const int slot = (s_pb[pos] + s_doff[d]) * 26 + d;
                                     s_win[slot] = v;
                                     atomicOr(&has[slot >> 5], 1u << (slot & 31));
                                     staged = true;
@@ -1623,15 +1636,19 @@ __global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(5, 8))
             }
             __syncthreads();
             // the window in address order: slot s is row 26 v + d of window
-            // voxel v = s / 26; clear the other parity's bits for the next brick
+            // voxel v (s = 26 v + d, stepped by kNT = 9 * 26 + 22 per pass);
+            // clear the other parity's bits for the next brick
             uint32_t *nxt = s_has[parity ^ 1];
             for (int q = threadIdx.x; q < kHasWords; q += kNT) nxt[q] = 0u;
+            GLB float *Yw = Y + w0 * 26;
+            int vw = vw0, dd = dd0;
             for (int s = threadIdx.x; s < kWinSlots; s += kNT) {
-                if ((has[s >> 5] >> (s & 31)) & 1u) {
-                    const int vw = s / 26, d = s - 26 * vw;
-                    const int lx = vw % kWin, ly = (vw / kWin) % kWin, lz = vw / (kWin * kWin);
-                    const int64_t vd = w0 + lx + (int64_t)ly * nx + (int64_t)lz * plane;
-                    Y[vd * 26 + d] = s_win[s];
+                if ((has[s >> 5] >> (s & 31)) & 1u) Yw[s_woff[vw] * 26 + dd] = s_win[s];
+                vw += kNT / 26;
+                dd += kNT % 26;
+                if (dd >= 26) {
+                    dd -= 26;
+                    ++vw;
                 }
             }
             __syncthreads();
