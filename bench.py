@@ -680,7 +680,9 @@ def main():
                                            "rows' CSR entries; x and y once",
                      "note": "the step streams fewer bytes than the CSR count (no columns; value-indexed "
                              "entries), so frac can exceed 1; format_frac is the fraction of peak on the "
-                             "bytes the step must move",
+                             "bytes the step must move; instruction counters show the fast-group kernel "
+                             "bound by VALU issue rather than by HBM (profiles/"
+                             "step_spmv_grouped_c2_instructions.md)",
                      "traffic_unit": "GB per launch"},
         "row_groups": None if groups is None else dict(groups, device_bytes=group_bytes),
         "tiled_step": {"kernel": "step_spmv<float, int, 256, 2> (values straight into LDS, 4 tiles per chunk)",
